@@ -1,0 +1,136 @@
+/*
+ * dp.h - C ABI of the MI355X (gfx950) Deep Potential smooth-edition library (libdp.so).
+ *
+ * The library evaluates a DP-SE model (arXiv 2004.11658, Section 2) for energy,
+ * forces and virial of periodic systems, entirely in hand-written HIP kernels:
+ * neighbour search and formatting (Alg. 1), environment matrix (Eq. 5, Alg. 2),
+ * embedding net (Eq. 6-9), descriptor (Eq. 4), fitting net (Eq. 1-3) and the adjoint
+ * for forces (Eq. 10) and virial, plus velocity-Verlet MD (Section 4).
+ *
+ * Conventions (all calls):
+ *   - Units: Angstrom, eV, fs, amu ("metal" units).
+ *   - Boxes: 3x3 row-major double, rows are the cell vectors a, b, c (right handed);
+ *     fractional coordinates f satisfy x = f . B (row vectors).
+ *   - Device pointers are HIP device memory owned by the caller (e.g. torch tensors);
+ *     host pointers are ordinary host memory.  The library owns only its handle and the
+ *     model weights it uploads at dp_init.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Compute calls
+ *     only enqueue work on it and return after host-side validation; they never
+ *     synchronise.  Conditions found on the device are written to a status word in
+ *     the workspace and read back by dp_status (which synchronises the stream).
+ *   - Return codes: DP_OK (0); > 0 warnings (results valid); < 0 errors (outputs
+ *     undefined).  dp_last_error gives a readable reason for the last failing call.
+ *   - A handle may be used from one host thread at a time.  Calls on different
+ *     workspaces may run concurrently on different streams.
+ */
+#ifndef DP_H
+#define DP_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dp_handle_s* dp_handle;
+
+enum {
+  DP_OK = 0,
+  DP_WARN_SEL_OVERFLOW = 1,  /* a neighbour-type block held more than sel atoms; the
+                                nearest sel were kept (Alg. 1 padding width exceeded) */
+  DP_ERR_ARG = -1,           /* null pointer, bad size or bad option */
+  DP_ERR_MODEL = -2,         /* unreadable model file or unsupported architecture */
+  DP_ERR_BOX = -3,           /* singular or left-handed box */
+  DP_ERR_TYPE = -4,          /* atom type outside [0, ntypes) (found on the device) */
+  DP_ERR_CAPACITY = -5,      /* more than DP_MAX_CANDIDATES atoms within rc of one atom,
+                                or more ghost images than the workspace plan allowed */
+  DP_ERR_WORKSPACE = -6,     /* workspace smaller than dp_workspace_size reported */
+  DP_ERR_HIP = -7,           /* a HIP runtime call failed */
+  DP_ERR_NONFINITE = -8,     /* non-finite coordinate (found on the device) */
+  DP_ERR_OVERLAP = -9        /* two atoms closer than 1e-6 A (found on the device) */
+};
+
+#define DP_MAX_CANDIDATES 1024
+
+enum { DP_PREC_FP64 = 0, DP_PREC_FP32 = 1, DP_PREC_BF16 = 2, DP_PREC_BF16X3 = 3 };
+
+typedef struct {
+  int32_t precision;  /* DP_PREC_*: operand precision of the embedding and fitting
+                         GEMMs.  FP64: everything in double.  FP32 / BF16: GEMM
+                         operands in that type with FP32 accumulation; BF16X3: BF16
+                         operands split as hi + lo (three MFMAs per product).
+                         Coordinates, distances, the environment matrix, force and
+                         virial accumulation, energy sums and integration stay FP64. */
+  int32_t reserved0;
+  double skin;        /* MD neighbour skin (A); 0 = rebuild cell lists every step */
+} dp_options;
+
+/* Read a model file ("DPSEMDL1" format: architecture + FP64 parameters in the
+ * documented flat order) and upload its weights to the current HIP device.
+ * Supported architecture: 1..8 species, embedding nets of three layers
+ * 1 -> s0 -> 2 s0 -> 4 s0 = M with s0 <= 32 (Section 2, Eq. 7-9), square hidden
+ * fitting layers after the first (Eq. 3), M< <= M, N_m = sum(sel) <= 1024.
+ * opt may be NULL (FP64, skin 0).  On error *out is NULL. */
+int dp_init(const char* model_path, const dp_options* opt, dp_handle* out);
+void dp_free(dp_handle h);
+
+/* Architecture summary. Any output pointer may be NULL. */
+int dp_model_info(dp_handle h, int32_t* ntypes, int32_t* nm, int32_t* M, int32_t* m2,
+                  double* rc, int64_t* nparams);
+
+/* Bytes of device workspace needed for a batch of nframes frames with the given host
+ * arrays atom_offsets [nframes+1] (frame f owns atoms [atom_offsets[f], atom_offsets[f+1]))
+ * and boxes [nframes][9].  The workspace carries the neighbour list, ghost images,
+ * per-atom descriptors and status words; one workspace serves calls of at most that
+ * size and equal or smaller ghost shells. */
+int dp_workspace_size(dp_handle h, int32_t nframes, const int64_t* atom_offsets,
+                      const double* boxes, size_t* bytes);
+
+/* Energy, forces and virial of one periodic frame (Eq. 1 and 10).
+ *   coords [natoms][3] device, types [natoms] device int32 in [0, ntypes),
+ *   box [9] host, energy [1] device, forces [natoms][3] device (overwritten),
+ *   virial [9] device or NULL (W_ab = -sum_pairs d_a dE/dd_b),
+ *   atom_energy [natoms] device or NULL (E_i). */
+int dp_compute(dp_handle h, int64_t natoms, const double* coords, const int32_t* types,
+               const double* box, double* energy, double* forces, double* virial,
+               double* atom_energy, void* workspace, size_t ws_bytes, void* stream);
+
+/* The same for a batch of independent frames of uneven size, in one launch per kernel.
+ *   atom_offsets [nframes+1] host, coords/types/forces/atom_energy concatenated over
+ *   frames, boxes [nframes][9] host, energies [nframes] and virials [nframes][9] device
+ *   (virials may be NULL). */
+int dp_compute_batch(dp_handle h, int32_t nframes, const int64_t* atom_offsets,
+                     const double* coords, const int32_t* types, const double* boxes,
+                     double* energies, double* forces, double* virials, double* atom_energy,
+                     void* workspace, size_t ws_bytes, void* stream);
+
+/* Formatted neighbour list of one frame (Alg. 1): nlist [natoms][N_m] device int32,
+ * type blocks of width sel in species order, each sorted by (r, owner index, image
+ * code) with -1 pads; img [natoms][N_m] device int32 image codes
+ * ((n0+K0)(2K1+1) + n1+K1)(2K2+1) + n2+K2 with K_k = ceil(rc / width_k); nnei
+ * [natoms][ntypes] device int32 real counts. img and nnei may be NULL. */
+int dp_nlist(dp_handle h, int64_t natoms, const double* coords, const int32_t* types,
+             const double* box, int32_t* nlist, int32_t* img, int32_t* nnei,
+             void* workspace, size_t ws_bytes, void* stream);
+
+/* Descriptor intermediates of one frame, for parity checks: T [natoms][M][4]
+ * (= G^T R / N_m, Eq. 4), and dE_i/dT [natoms][M][4], device doubles; either may
+ * be NULL.  Runs the same kernels as dp_compute. */
+int dp_descriptor(dp_handle h, int64_t natoms, const double* coords, const int32_t* types,
+                  const double* box, double* T, double* gT, void* workspace,
+                  size_t ws_bytes, void* stream);
+
+/* Synchronise stream and read the status word of the last call that used workspace.
+ * flags (may be NULL) receives the raw flag bits; detail (may be NULL) the count
+ * attached to the first condition.  Returns DP_OK, DP_WARN_SEL_OVERFLOW or a
+ * negative DP_ERR_* for device-detected conditions. */
+int dp_status(dp_handle h, const void* workspace, void* stream, int32_t* flags,
+              int64_t* detail);
+
+const char* dp_strerror(int code);
+const char* dp_last_error(dp_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

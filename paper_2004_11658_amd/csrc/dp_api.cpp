@@ -1,0 +1,724 @@
+// C ABI of libdp: model loading, validation, workspace planning and the launch
+// sequence of one DP-SE evaluation (arXiv 2004.11658, Sections 2 and 3).
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dp.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace dp;
+
+struct dp_handle_s {
+  // architecture
+  int ntypes = 0, n_emb = 0, n_fit = 0, m2 = 0, switch_kind = 0, desc_norm = 0;
+  double rc = 0, rcs = 0;
+  std::vector<int> emb_w, fit_w, sel;
+  std::vector<double> params;
+  int nm = 0, M = 0, s0 = 0;
+  int64_t nparams = 0;
+  dp_options opt{};
+  int device = 0;
+  // device weights
+  void* d_nets = nullptr;          // ntypes^2 embedding net blocks
+  void* d_fit = nullptr;           // fitting weights (storage type)
+  double* d_bo = nullptr;          // output biases [ntypes]
+  void** d_ptrs = nullptr;         // device pointer tables for the fitting kernel
+  // pinned staging for per-call frame tables
+  Frame* h_frames = nullptr;
+  int h_frames_cap = 0;
+  hipEvent_t frames_done = nullptr;
+  bool frames_pending = false;
+  std::string err;
+};
+
+static thread_local std::string g_init_err;
+
+static int fail(dp_handle h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_init_err = msg;
+  return code;
+}
+
+#define HIPCHECK(h, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(h, DP_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// ------------------------------------------------------------------------------------
+// model file
+// ------------------------------------------------------------------------------------
+static int parse_model(dp_handle h, const char* path) {
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(h, DP_ERR_MODEL, std::string("cannot open model file ") + path);
+  std::vector<unsigned char> buf;
+  fseek(f, 0, SEEK_END);
+  long sz = ftell(f);
+  fseek(f, 0, SEEK_SET);
+  if (sz < 64) {
+    fclose(f);
+    return fail(h, DP_ERR_MODEL, "model file too short");
+  }
+  buf.resize(sz);
+  size_t got = fread(buf.data(), 1, sz, f);
+  fclose(f);
+  if ((long)got != sz) return fail(h, DP_ERR_MODEL, "short read of model file");
+  auto i32 = [&](size_t o) { int32_t v; memcpy(&v, &buf[o], 4); return v; };
+  auto i64 = [&](size_t o) { int64_t v; memcpy(&v, &buf[o], 8); return v; };
+  auto f64 = [&](size_t o) { double v; memcpy(&v, &buf[o], 8); return v; };
+  if (memcmp(buf.data(), "DPSEMDL1", 8) != 0) return fail(h, DP_ERR_MODEL, "bad magic");
+  if (i32(8) != 1) return fail(h, DP_ERR_MODEL, "unsupported model version");
+  int hb = i32(12);
+  int64_t np = i64(16);
+  h->ntypes = i32(24);
+  h->n_emb = i32(28);
+  h->n_fit = i32(32);
+  h->m2 = i32(36);
+  h->switch_kind = i32(40);
+  h->desc_norm = i32(44);
+  h->rc = f64(48);
+  h->rcs = f64(56);
+  if (h->ntypes < 1 || h->ntypes > kMaxTypes) return fail(h, DP_ERR_MODEL, "ntypes must be 1..8");
+  if (h->n_emb != 3) return fail(h, DP_ERR_MODEL, "embedding net must have 3 layers");
+  if (h->n_fit < 1 || h->n_fit > 8) return fail(h, DP_ERR_MODEL, "fitting net must have 1..8 hidden layers");
+  size_t nint = h->n_emb + h->n_fit + h->ntypes;
+  if (64 + 4 * nint > (size_t)hb || hb > sz) return fail(h, DP_ERR_MODEL, "bad header size");
+  for (int k = 0; k < h->n_emb; k++) h->emb_w.push_back(i32(64 + 4 * k));
+  for (int k = 0; k < h->n_fit; k++) h->fit_w.push_back(i32(64 + 4 * (h->n_emb + k)));
+  h->nm = 0;
+  for (int t = 0; t < h->ntypes; t++) {
+    h->sel.push_back(i32(64 + 4 * (h->n_emb + h->n_fit + t)));
+    if (h->sel.back() < 0) return fail(h, DP_ERR_MODEL, "negative sel");
+    h->nm += h->sel.back();
+  }
+  h->s0 = h->emb_w[0];
+  h->M = h->emb_w[2];
+  if (h->s0 < 1 || h->s0 > 32 || h->emb_w[1] != 2 * h->s0 || h->emb_w[2] != 2 * h->emb_w[1])
+    return fail(h, DP_ERR_MODEL, "embedding widths must be s0, 2 s0, 4 s0 with s0 <= 32");
+  for (int k = 1; k < h->n_fit; k++)
+    if (h->fit_w[k] != h->fit_w[0]) return fail(h, DP_ERR_MODEL, "hidden fitting layers must be square");
+  if (h->fit_w[0] < 1 || h->fit_w[0] > 1024) return fail(h, DP_ERR_MODEL, "fitting width out of range");
+  if (h->m2 < 1 || h->m2 > h->M) return fail(h, DP_ERR_MODEL, "M< out of range");
+  if (h->nm < 1 || h->nm > kMaxNm) return fail(h, DP_ERR_MODEL, "N_m must be 1..1024");
+  if (!(h->rc > h->rcs) || h->rcs < 0 || !(h->rc < 64)) return fail(h, DP_ERR_MODEL, "bad cutoffs");
+  if (h->switch_kind < 0 || h->switch_kind > 1 || h->desc_norm < 0 || h->desc_norm > 1)
+    return fail(h, DP_ERR_MODEL, "bad switch/normalisation flag");
+  // parameter count
+  int64_t cnt = 0;
+  for (int a = 0; a < h->ntypes * h->ntypes; a++) {
+    int nin = 1;
+    for (int k = 0; k < 3; k++) { cnt += (int64_t)nin * h->emb_w[k] + h->emb_w[k]; nin = h->emb_w[k]; }
+  }
+  for (int a = 0; a < h->ntypes; a++) {
+    int nin = h->M * h->m2;
+    for (int k = 0; k < h->n_fit; k++) { cnt += (int64_t)nin * h->fit_w[k] + h->fit_w[k]; nin = h->fit_w[k]; }
+    cnt += nin + 1;
+  }
+  if (cnt != np || hb + 8 * np != sz) return fail(h, DP_ERR_MODEL, "parameter count mismatch");
+  h->nparams = np;
+  h->params.resize(np);
+  memcpy(h->params.data(), &buf[hb], 8 * np);
+  return DP_OK;
+}
+
+// offsets of each block in the flat parameter vector
+struct ParamIndex {
+  std::vector<int64_t> eW, eB;   // [net*3 + layer]
+  std::vector<int64_t> fW, fB;   // [type*(nfit+1) + layer], layer nfit = output
+};
+static ParamIndex index_params(dp_handle h) {
+  ParamIndex P;
+  int64_t off = 0;
+  for (int a = 0; a < h->ntypes * h->ntypes; a++) {
+    int nin = 1;
+    for (int k = 0; k < 3; k++) {
+      P.eW.push_back(off); off += (int64_t)nin * h->emb_w[k];
+      P.eB.push_back(off); off += h->emb_w[k];
+      nin = h->emb_w[k];
+    }
+  }
+  for (int a = 0; a < h->ntypes; a++) {
+    int nin = h->M * h->m2;
+    for (int k = 0; k <= h->n_fit; k++) {
+      int nout = k < h->n_fit ? h->fit_w[k] : 1;
+      P.fW.push_back(off); off += (int64_t)nin * nout;
+      P.fB.push_back(off); off += nout;
+      nin = nout;
+    }
+  }
+  return P;
+}
+
+static int storage_bytes(int prec) { return prec == PREC_FP64 ? 8 : 4; }
+
+// position p of a padded layer <-> feature index (p / 32) * s0 + p % 32, pad if p % 32 >= s0
+static int pos_feature(int p, int s0) { return (p % kP0) < s0 ? (p / kP0) * s0 + (p % kP0) : -1; }
+
+template <class S>
+static void fill_net_block(dp_handle h, const ParamIndex& P, int net, S* blk) {
+  const double* p = h->params.data();
+  int s0 = h->s0, s1 = 2 * s0, s2 = 4 * s0;
+  for (int q = 0; q < kNetElems; q++) blk[q] = (S)0;
+  for (int pp = 0; pp < kP0; pp++) {
+    int f = pos_feature(pp, s0);
+    if (f < 0) continue;
+    blk[kOffW0 + pp] = (S)p[P.eW[net * 3 + 0] + f];
+    blk[kOffB0 + pp] = (S)p[P.eB[net * 3 + 0] + f];
+  }
+  for (int pp = 0; pp < kP1; pp++) {
+    int f = pos_feature(pp, s0);
+    if (f >= 0) blk[kOffB1 + pp] = (S)p[P.eB[net * 3 + 1] + f];
+  }
+  for (int pp = 0; pp < kP2; pp++) {
+    int f = pos_feature(pp, s0);
+    if (f >= 0) blk[kOffB2 + pp] = (S)p[P.eB[net * 3 + 2] + f];
+  }
+  for (int pi = 0; pi < kP0; pi++) {
+    int fi = pos_feature(pi, s0);
+    if (fi < 0) continue;
+    for (int po = 0; po < kP1; po++) {
+      int fo = pos_feature(po, s0);
+      if (fo < 0) continue;
+      blk[kOffW1 + pi * kW1Stride + po] = (S)p[P.eW[net * 3 + 1] + (int64_t)fi * s1 + fo];
+    }
+  }
+  for (int pi = 0; pi < kP1; pi++) {
+    int fi = pos_feature(pi, s0);
+    if (fi < 0) continue;
+    for (int po = 0; po < kP2; po++) {
+      int fo = pos_feature(po, s0);
+      if (fo < 0) continue;
+      blk[kOffW2 + pi * kW2Stride + po] = (S)p[P.eW[net * 3 + 2] + (int64_t)fi * s2 + fo];
+    }
+  }
+}
+
+template <class S>
+static int upload_weights_t(dp_handle h) {
+  ParamIndex P = index_params(h);
+  int nnet = h->ntypes * h->ntypes;
+  std::vector<S> nets((size_t)nnet * kNetElems);
+  for (int net = 0; net < nnet; net++) fill_net_block<S>(h, P, net, nets.data() + (size_t)net * kNetElems);
+  HIPCHECK(h, hipMalloc(&h->d_nets, nets.size() * sizeof(S)));
+  HIPCHECK(h, hipMemcpy(h->d_nets, nets.data(), nets.size() * sizeof(S), hipMemcpyHostToDevice));
+  // fitting weights, per species: W_k, b_k for k < nfit, then wo
+  std::vector<S> fit;
+  std::vector<size_t> offW, offB, offO;
+  std::vector<double> bo(h->ntypes);
+  for (int a = 0; a < h->ntypes; a++) {
+    int nin = h->M * h->m2;
+    for (int k = 0; k < h->n_fit; k++) {
+      int nout = h->fit_w[k];
+      offW.push_back(fit.size());
+      for (int64_t q = 0; q < (int64_t)nin * nout; q++) fit.push_back((S)h->params[P.fW[a * (h->n_fit + 1) + k] + q]);
+      offB.push_back(fit.size());
+      for (int q = 0; q < nout; q++) fit.push_back((S)h->params[P.fB[a * (h->n_fit + 1) + k] + q]);
+      nin = nout;
+    }
+    offO.push_back(fit.size());
+    for (int q = 0; q < nin; q++) fit.push_back((S)h->params[P.fW[a * (h->n_fit + 1) + h->n_fit] + q]);
+    bo[a] = h->params[P.fB[a * (h->n_fit + 1) + h->n_fit]];
+    while (fit.size() % 64) fit.push_back((S)0);
+  }
+  HIPCHECK(h, hipMalloc(&h->d_fit, fit.size() * sizeof(S)));
+  HIPCHECK(h, hipMemcpy(h->d_fit, fit.data(), fit.size() * sizeof(S), hipMemcpyHostToDevice));
+  HIPCHECK(h, hipMalloc(&h->d_bo, h->ntypes * sizeof(double)));
+  HIPCHECK(h, hipMemcpy(h->d_bo, bo.data(), h->ntypes * sizeof(double), hipMemcpyHostToDevice));
+  // pointer tables: W [ntypes*nfit], b [ntypes*nfit], wo [ntypes]
+  std::vector<void*> ptrs;
+  S* base = (S*)h->d_fit;
+  for (size_t q = 0; q < offW.size(); q++) ptrs.push_back(base + offW[q]);
+  for (size_t q = 0; q < offB.size(); q++) ptrs.push_back(base + offB[q]);
+  for (size_t q = 0; q < offO.size(); q++) ptrs.push_back(base + offO[q]);
+  HIPCHECK(h, hipMalloc(&h->d_ptrs, ptrs.size() * sizeof(void*)));
+  HIPCHECK(h, hipMemcpy(h->d_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice));
+  return DP_OK;
+}
+
+static int upload_weights(dp_handle h) {
+  if (h->opt.precision == PREC_FP64) return upload_weights_t<double>(h);
+  return upload_weights_t<float>(h);
+}
+
+static void release_weights(dp_handle h) {
+  if (h->d_nets) (void)hipFree(h->d_nets);
+  if (h->d_fit) (void)hipFree(h->d_fit);
+  if (h->d_bo) (void)hipFree(h->d_bo);
+  if (h->d_ptrs) (void)hipFree(h->d_ptrs);
+  h->d_nets = h->d_fit = nullptr;
+  h->d_bo = nullptr;
+  h->d_ptrs = nullptr;
+}
+
+// ------------------------------------------------------------------------------------
+// boxes and frames
+// ------------------------------------------------------------------------------------
+// B^-1 as the adjugate over the determinant, evaluated in a fixed order with
+// contraction off (integer decisions downstream depend on these bits).
+static int box_setup(const double* b9, double rc, Frame& F) {
+#pragma clang fp contract(off)
+  const double* B = b9;
+  double det = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
+               B[2] * (B[3] * B[7] - B[4] * B[6]);
+  if (!(det > 0) || !std::isfinite(det)) return -1;
+  double C[9];
+  C[0] = B[4] * B[8] - B[5] * B[7];
+  C[1] = B[5] * B[6] - B[3] * B[8];
+  C[2] = B[3] * B[7] - B[4] * B[6];
+  C[3] = B[2] * B[7] - B[1] * B[8];
+  C[4] = B[0] * B[8] - B[2] * B[6];
+  C[5] = B[1] * B[6] - B[0] * B[7];
+  C[6] = B[1] * B[5] - B[2] * B[4];
+  C[7] = B[2] * B[3] - B[0] * B[5];
+  C[8] = B[0] * B[4] - B[1] * B[3];
+  for (int r = 0; r < 3; r++)
+    for (int c = 0; c < 3; c++) F.Bi[3 * r + c] = C[3 * c + r] / det;
+  memcpy(F.B, B, sizeof(F.B));
+  int nimg = 1;
+  for (int k = 0; k < 3; k++) {
+    double n2 = (F.Bi[0 + k] * F.Bi[0 + k] + F.Bi[3 + k] * F.Bi[3 + k]) + F.Bi[6 + k] * F.Bi[6 + k];
+    double width = 1.0 / std::sqrt(n2);
+    F.K[k] = (int)std::ceil(rc / width);
+    double g = rc / width * (1.0 + 1e-9) + 1e-9;
+    F.g[k] = g;
+    F.Kg[k] = (int)std::ceil(g);
+    int nc = (int)std::floor((1.0 + 2.0 * g) * width / rc);
+    if (nc < 1) nc = 1;
+    F.nc[k] = nc;
+    F.cw[k] = (1.0 + 2.0 * g) / nc;
+    nimg *= 2 * F.K[k] + 1;
+  }
+  F.nimg = nimg;
+  return 0;
+}
+
+struct Plan {
+  size_t total = 0;
+  size_t o_status, o_frames, o_frame_of, o_xw, o_fw, o_gcount, o_goff, o_small, o_scan;
+  size_t o_xe, o_eown, o_eimg, o_etype, o_ecell, o_ccount, o_cstart, o_cfill, o_catoms;
+  size_t o_nlist, o_nnei, o_tpos, o_rowof, o_rowatom, o_T, o_gT, o_D, o_Dg, o_act, o_xs, o_g0,
+      o_g1, o_Ei, o_vir, o_tmpj, o_tmpi;
+  int n, nframes, ncell, ghost_cap, nrows;
+};
+
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int make_plan(dp_handle h, int nframes, const int64_t* off, const double* boxes,
+                     std::vector<Frame>* frames, Plan& P) {
+  if (nframes < 1) return fail(h, DP_ERR_ARG, "nframes must be >= 1");
+  if (off[0] != 0) return fail(h, DP_ERR_ARG, "atom_offsets[0] must be 0");
+  int64_t n = off[nframes];
+  if (n < 1 || n > (1 << 26)) return fail(h, DP_ERR_ARG, "natoms out of range");
+  int64_t ghost_cap = 0, ncell = 0;
+  if (frames) frames->resize(nframes);
+  for (int f = 0; f < nframes; f++) {
+    int64_t na = off[f + 1] - off[f];
+    if (na < 1) return fail(h, DP_ERR_ARG, "every frame needs at least one atom");
+    Frame F{};
+    if (box_setup(boxes + 9 * f, h->rc, F)) return fail(h, DP_ERR_BOX, "singular or left-handed box");
+    double vol_ext = (1 + 2 * F.g[0]) * (1 + 2 * F.g[1]) * (1 + 2 * F.g[2]);
+    double expect = na * (vol_ext - 1.0);
+    int64_t maxg = na * ((int64_t)(2 * F.Kg[0] + 1) * (2 * F.Kg[1] + 1) * (2 * F.Kg[2] + 1) - 1);
+    int64_t cap = std::min<int64_t>(maxg, (int64_t)std::ceil(1.3 * expect) + 2048);
+    F.atom0 = (int)off[f];
+    F.natoms = (int)na;
+    F.cell0 = (int)ncell;
+    ncell += (int64_t)F.nc[0] * F.nc[1] * F.nc[2];
+    ghost_cap += cap;
+    if (frames) (*frames)[f] = F;
+  }
+  if (ncell > (1 << 28) || ghost_cap + n > (1LL << 30)) return fail(h, DP_ERR_ARG, "system too large");
+  P.n = (int)n;
+  P.nframes = nframes;
+  P.ncell = (int)ncell;
+  P.ghost_cap = (int)ghost_cap;
+  P.nrows = (int)(n + (int64_t)h->ntypes * kRowPad);
+  int W = h->ntypes == 1 ? 1 : h->ntypes == 2 ? 2 : h->ntypes <= 4 ? 4 : 8;
+  int64_t ne = n + ghost_cap;
+  int sb = storage_bytes(h->opt.precision);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = al(o + bytes); return r; };
+  P.o_status = take(sizeof(int) * STW_N);
+  P.o_frames = take(sizeof(Frame) * nframes);
+  P.o_frame_of = take(sizeof(int) * n);
+  P.o_xw = take(sizeof(double) * 3 * n);
+  P.o_fw = take(sizeof(double) * 3 * n);
+  P.o_gcount = take(sizeof(int) * n);
+  P.o_goff = take(sizeof(int) * (n + 1));
+  P.o_small = take(sizeof(int) * 64);
+  size_t ns = std::max(scan_sums_ints((int)std::max<int64_t>(n, ncell + 1), 1),
+                       scan_sums_ints((int)n, W));
+  P.o_scan = take(sizeof(int) * ns);
+  P.o_xe = take(sizeof(double) * 3 * ne);
+  P.o_eown = take(sizeof(int) * ne);
+  P.o_eimg = take(sizeof(int) * ne);
+  P.o_etype = take(sizeof(int) * ne);
+  P.o_ecell = take(sizeof(int) * ne);
+  P.o_ccount = take(sizeof(int) * (ncell + 1));
+  P.o_cstart = take(sizeof(int) * (ncell + 1));
+  P.o_cfill = take(sizeof(int) * ncell);
+  P.o_catoms = take(sizeof(int) * ne);
+  P.o_nlist = take(sizeof(int) * n * h->nm);
+  P.o_nnei = take(sizeof(int) * n * h->ntypes);
+  P.o_tpos = take(sizeof(int) * n * W);
+  P.o_rowof = take(sizeof(int) * n);
+  P.o_rowatom = take(sizeof(int) * P.nrows);
+  size_t rows = P.nrows;
+  P.o_T = take((size_t)sb * rows * h->M * 4);
+  P.o_gT = take((size_t)sb * rows * h->M * 4);
+  int K1 = h->M * h->m2, fw = h->fit_w[0];
+  P.o_D = take((size_t)sb * rows * K1);
+  P.o_Dg = take((size_t)sb * rows * K1);
+  P.o_act = take((size_t)sb * rows * fw * h->n_fit);
+  P.o_xs = take((size_t)sb * rows * fw * h->n_fit);
+  P.o_g0 = take((size_t)sb * rows * fw);
+  P.o_g1 = take((size_t)sb * rows * fw);
+  P.o_Ei = take(sizeof(double) * rows);
+  P.o_vir = take(sizeof(double) * rows * 9);
+  P.o_tmpj = take(sizeof(double) * nframes * 10);
+  P.o_tmpi = take(sizeof(int) * 16);
+  P.total = o;
+  return DP_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// public API
+// ------------------------------------------------------------------------------------
+static ModelC model_consts(dp_handle h) {
+  ModelC m{};
+  m.ntypes = h->ntypes;
+  m.nm = h->nm;
+  m.M = h->M;
+  m.m2 = h->m2;
+  m.s0 = h->s0;
+  int o = 0;
+  for (int t = 0; t < kMaxTypes; t++) {
+    m.sel[t] = t < h->ntypes ? h->sel[t] : 0;
+    m.sel_off[t] = o;
+    o += m.sel[t];
+  }
+  m.sel_off[kMaxTypes] = o;
+  m.rc = h->rc;
+  m.rcs = h->rcs;
+  m.rc2 = h->rc * h->rc;
+  m.switch_kind = h->switch_kind;
+  m.desc_norm = h->desc_norm;
+  m.inv_norm = h->desc_norm == 0 ? 1.0 / (double)h->nm : 1.0;
+  return m;
+}
+
+struct Ws {
+  char* base;
+  const Plan* P;
+  template <class T>
+  T* at(size_t off) const { return (T*)(base + off); }
+};
+
+// runs the neighbour stage; returns DP_OK or an error code
+static int stage_frames_and_nlist(dp_handle h, int nframes, const int64_t* off, const double* boxes,
+                                  const double* coords, const int32_t* types, void* ws,
+                                  size_t ws_bytes, hipStream_t st, Plan& P, NlistArgs& A) {
+  std::vector<Frame> frames;
+  int rc = make_plan(h, nframes, off, boxes, &frames, P);
+  if (rc != DP_OK) return rc;
+  if (!ws || ws_bytes < P.total)
+    return fail(h, DP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(P.total) + " bytes");
+  if (!coords || !types) return fail(h, DP_ERR_ARG, "null coordinates or types");
+  HIPCHECK(h, hipSetDevice(h->device));
+  // pinned staging of the frame table (previous copy must have completed)
+  if (h->frames_pending) {
+    HIPCHECK(h, hipEventSynchronize(h->frames_done));
+    h->frames_pending = false;
+  }
+  if (h->h_frames_cap < nframes) {
+    if (h->h_frames) (void)hipHostFree(h->h_frames);
+    h->h_frames = nullptr;
+    HIPCHECK(h, hipHostMalloc((void**)&h->h_frames, sizeof(Frame) * nframes, 0));
+    h->h_frames_cap = nframes;
+  }
+  memcpy(h->h_frames, frames.data(), sizeof(Frame) * nframes);
+  Ws W{(char*)ws, &P};
+  HIPCHECK(h, hipMemcpyAsync(W.at<Frame>(P.o_frames), h->h_frames, sizeof(Frame) * nframes,
+                             hipMemcpyHostToDevice, st));
+  HIPCHECK(h, hipEventRecord(h->frames_done, st));
+  h->frames_pending = true;
+  A.n = P.n;
+  A.nframes = nframes;
+  A.ncell = P.ncell;
+  A.ghost_cap = P.ghost_cap;
+  A.nrows = P.nrows;
+  A.m = model_consts(h);
+  A.frames = W.at<Frame>(P.o_frames);
+  A.x = coords;
+  A.types = types;
+  A.status = W.at<int>(P.o_status);
+  A.frame_of = W.at<int>(P.o_frame_of);
+  A.xw = W.at<double>(P.o_xw);
+  A.fw = W.at<double>(P.o_fw);
+  A.gcount = W.at<int>(P.o_gcount);
+  A.goff = W.at<int>(P.o_goff);
+  int* small = W.at<int>(P.o_small);
+  A.gtotal = small + 0;
+  A.ctotal = small + 1;
+  A.n_ext = small + 2;
+  A.tcount = small + 8;        // up to 8 counters
+  A.type_row0 = small + 16;    // up to 9 values
+  A.scan_sums = W.at<int>(P.o_scan);
+  A.xe = W.at<double>(P.o_xe);
+  A.eown = W.at<int>(P.o_eown);
+  A.eimg = W.at<int>(P.o_eimg);
+  A.etype = W.at<int>(P.o_etype);
+  A.ecell = W.at<int>(P.o_ecell);
+  A.cell_count = W.at<int>(P.o_ccount);
+  A.cell_start = W.at<int>(P.o_cstart);
+  A.cell_fill = W.at<int>(P.o_cfill);
+  A.cell_atoms = W.at<int>(P.o_catoms);
+  A.nlist = W.at<int>(P.o_nlist);
+  A.nnei = W.at<int>(P.o_nnei);
+  A.tpos = W.at<int>(P.o_tpos);
+  A.row_of = W.at<int>(P.o_rowof);
+  A.row_atom = W.at<int>(P.o_rowatom);
+  launch_nlist(A, st);
+  HIPCHECK(h, hipGetLastError());
+  return DP_OK;
+}
+
+static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, hipStream_t st,
+                     double* energies, double* forces, double* virials, double* atom_energy,
+                     bool want_forces, double* T_out, double* gT_out) {
+  Ws W{(char*)ws, &P};
+  EmbedArgs E{};
+  E.prec = h->opt.precision;
+  E.nrows = P.nrows;
+  E.n = P.n;
+  E.m = A.m;
+  E.nets = h->d_nets;
+  E.xe = A.xe;
+  E.nlist = A.nlist;
+  E.nnei = A.nnei;
+  E.row_atom = A.row_atom;
+  E.type_row0 = A.type_row0;
+  E.eown = A.eown;
+  E.T = W.at<void>(P.o_T);
+  E.gT = W.at<void>(P.o_gT);
+  E.forces = forces;
+  E.vir_part = W.at<double>(P.o_vir);
+  E.frame_of = A.frame_of;
+  E.nframes = P.nframes;
+  launch_embed_fwd(E, st);
+  HIPCHECK(h, hipGetLastError());
+  FitArgs F{};
+  F.prec = h->opt.precision;
+  F.nrows = P.nrows;
+  F.n = P.n;
+  F.m = A.m;
+  F.nfit = h->n_fit;
+  F.fw = h->fit_w[0];
+  F.type_row0 = A.type_row0;
+  F.row_atom = A.row_atom;
+  F.T = E.T;
+  F.gT = W.at<void>(P.o_gT);
+  F.W = (const void* const*)h->d_ptrs;
+  F.b = (const void* const*)h->d_ptrs + h->ntypes * h->n_fit;
+  F.wo = (const void* const*)h->d_ptrs + 2 * h->ntypes * h->n_fit;
+  F.bo = h->d_bo;
+  F.D = W.at<void>(P.o_D);
+  F.Dg = W.at<void>(P.o_Dg);
+  F.act = W.at<void>(P.o_act);
+  F.xs = W.at<void>(P.o_xs);
+  F.g0 = W.at<void>(P.o_g0);
+  F.g1 = W.at<void>(P.o_g1);
+  F.Ei = W.at<double>(P.o_Ei);
+  launch_fit(F, st);
+  HIPCHECK(h, hipGetLastError());
+  if (T_out || gT_out) {
+    launch_export_T(h->opt.precision, P.n, h->M, A.row_of, E.T, F.gT, T_out, gT_out, st);
+    HIPCHECK(h, hipGetLastError());
+  }
+  if (want_forces) {
+    launch_zero(forces, (size_t)P.n * 3, st);
+    launch_embed_bwd(E, st);
+    HIPCHECK(h, hipGetLastError());
+  }
+  launch_frame_reduce(P.nframes, A.frames, A.row_of, F.Ei, want_forces ? E.vir_part : nullptr,
+                      energies, virials, atom_energy, st);
+  HIPCHECK(h, hipGetLastError());
+  return DP_OK;
+}
+
+
+extern "C" {
+
+const char* dp_strerror(int code) {
+  switch (code) {
+    case DP_OK: return "ok";
+    case DP_WARN_SEL_OVERFLOW: return "a neighbour-type block exceeded sel; nearest kept";
+    case DP_ERR_ARG: return "invalid argument";
+    case DP_ERR_MODEL: return "invalid or unsupported model";
+    case DP_ERR_BOX: return "singular or left-handed box";
+    case DP_ERR_TYPE: return "atom type out of range";
+    case DP_ERR_CAPACITY: return "neighbour or ghost capacity exceeded";
+    case DP_ERR_WORKSPACE: return "workspace too small";
+    case DP_ERR_HIP: return "HIP runtime error";
+    case DP_ERR_NONFINITE: return "non-finite coordinate";
+    case DP_ERR_OVERLAP: return "two atoms closer than 1e-6 A";
+    default: return "unknown status";
+  }
+}
+
+const char* dp_last_error(dp_handle h) { return h ? h->err.c_str() : g_init_err.c_str(); }
+
+int dp_init(const char* model_path, const dp_options* opt, dp_handle* out) {
+  if (!out) return fail(nullptr, DP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!model_path) return fail(nullptr, DP_ERR_ARG, "model_path is NULL");
+  dp_handle h = new dp_handle_s();
+  if (opt) h->opt = *opt;
+  if (h->opt.precision < 0 || h->opt.precision > 3 || !(h->opt.skin >= 0)) {
+    delete h;
+    return fail(nullptr, DP_ERR_ARG, "bad options");
+  }
+  int rc = parse_model(h, model_path);
+  if (rc != DP_OK) {
+    g_init_err = h->err;
+    delete h;
+    return rc;
+  }
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(nullptr, DP_ERR_HIP, "no HIP device");
+  }
+  rc = upload_weights(h);
+  if (rc == DP_OK && hipEventCreateWithFlags(&h->frames_done, hipEventDisableTiming) != hipSuccess)
+    rc = fail(h, DP_ERR_HIP, "hipEventCreate failed");
+  if (rc != DP_OK) {
+    g_init_err = h->err;
+    release_weights(h);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return DP_OK;
+}
+
+void dp_free(dp_handle h) {
+  if (!h) return;
+  if (h->frames_pending) (void)hipEventSynchronize(h->frames_done);
+  release_weights(h);
+  if (h->h_frames) (void)hipHostFree(h->h_frames);
+  if (h->frames_done) (void)hipEventDestroy(h->frames_done);
+  delete h;
+}
+
+int dp_model_info(dp_handle h, int32_t* ntypes, int32_t* nm, int32_t* M, int32_t* m2, double* rc,
+                  int64_t* nparams) {
+  if (!h) return DP_ERR_ARG;
+  if (ntypes) *ntypes = h->ntypes;
+  if (nm) *nm = h->nm;
+  if (M) *M = h->M;
+  if (m2) *m2 = h->m2;
+  if (rc) *rc = h->rc;
+  if (nparams) *nparams = h->nparams;
+  return DP_OK;
+}
+
+int dp_workspace_size(dp_handle h, int32_t nframes, const int64_t* atom_offsets, const double* boxes,
+                      size_t* bytes) {
+  if (!h || !atom_offsets || !boxes || !bytes) return fail(h, DP_ERR_ARG, "null argument");
+  Plan P;
+  int rc = make_plan(h, nframes, atom_offsets, boxes, nullptr, P);
+  if (rc != DP_OK) return rc;
+  *bytes = P.total;
+  return DP_OK;
+}
+
+int dp_compute_batch(dp_handle h, int32_t nframes, const int64_t* atom_offsets, const double* coords,
+                     const int32_t* types, const double* boxes, double* energies, double* forces,
+                     double* virials, double* atom_energy, void* workspace, size_t ws_bytes,
+                     void* stream) {
+  if (!h) return DP_ERR_ARG;
+  if (!atom_offsets || !boxes || !energies || !forces)
+    return fail(h, DP_ERR_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  Plan P;
+  NlistArgs A{};
+  int rc = stage_frames_and_nlist(h, nframes, atom_offsets, boxes, coords, types, workspace, ws_bytes,
+                                  st, P, A);
+  if (rc != DP_OK) return rc;
+  return run_model(h, P, A, workspace, st, energies, forces, virials, atom_energy, true, nullptr,
+                   nullptr);
+}
+
+int dp_compute(dp_handle h, int64_t natoms, const double* coords, const int32_t* types,
+               const double* box, double* energy, double* forces, double* virial,
+               double* atom_energy, void* workspace, size_t ws_bytes, void* stream) {
+  int64_t off[2] = {0, natoms};
+  return dp_compute_batch(h, 1, off, coords, types, box, energy, forces, virial, atom_energy,
+                          workspace, ws_bytes, stream);
+}
+
+int dp_nlist(dp_handle h, int64_t natoms, const double* coords, const int32_t* types,
+             const double* box, int32_t* nlist, int32_t* img, int32_t* nnei, void* workspace,
+             size_t ws_bytes, void* stream) {
+  if (!h) return DP_ERR_ARG;
+  if (!box || !nlist) return fail(h, DP_ERR_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  int64_t off[2] = {0, natoms};
+  Plan P;
+  NlistArgs A{};
+  int rc = stage_frames_and_nlist(h, 1, off, box, coords, types, workspace, ws_bytes, st, P, A);
+  if (rc != DP_OK) return rc;
+  launch_nlist_export(P.n, h->nm, A.nlist, A.eown, A.eimg, A.frame_of, A.frames, nlist, img, st);
+  if (nnei)
+    HIPCHECK(h, hipMemcpyAsync(nnei, A.nnei, sizeof(int) * P.n * h->ntypes, hipMemcpyDeviceToDevice, st));
+  HIPCHECK(h, hipGetLastError());
+  return DP_OK;
+}
+
+int dp_descriptor(dp_handle h, int64_t natoms, const double* coords, const int32_t* types,
+                  const double* box, double* T, double* gT, void* workspace, size_t ws_bytes,
+                  void* stream) {
+  if (!h) return DP_ERR_ARG;
+  if (!box) return fail(h, DP_ERR_ARG, "null box");
+  hipStream_t st = (hipStream_t)stream;
+  int64_t off[2] = {0, natoms};
+  Plan P;
+  NlistArgs A{};
+  int rc = stage_frames_and_nlist(h, 1, off, box, coords, types, workspace, ws_bytes, st, P, A);
+  if (rc != DP_OK) return rc;
+  Ws W{(char*)workspace, &P};
+  double* e = W.at<double>(P.o_tmpj);
+  return run_model(h, P, A, workspace, st, e, nullptr, nullptr, nullptr, false, T, gT);
+}
+
+int dp_status(dp_handle h, const void* workspace, void* stream, int32_t* flags, int64_t* detail) {
+  if (!h || !workspace) return DP_ERR_ARG;
+  int st_host[STW_N];
+  HIPCHECK(h, hipMemcpyAsync(st_host, workspace, sizeof(st_host), hipMemcpyDeviceToHost,
+                             (hipStream_t)stream));
+  HIPCHECK(h, hipStreamSynchronize((hipStream_t)stream));
+  int f = st_host[STW_FLAGS];
+  if (flags) *flags = f;
+  int code = DP_OK;
+  int64_t det = 0;
+  if (f & ST_BAD_TYPE) code = DP_ERR_TYPE;
+  else if (f & ST_NONFINITE) code = DP_ERR_NONFINITE;
+  else if (f & ST_OVERLAP) code = DP_ERR_OVERLAP;
+  else if (f & ST_GHOST_CAP) { code = DP_ERR_CAPACITY; det = st_host[STW_GHOSTS]; }
+  else if (f & ST_CAPACITY) { code = DP_ERR_CAPACITY; det = st_host[STW_MAX_CAND]; }
+  else if (f & ST_SEL_OVERFLOW) { code = DP_WARN_SEL_OVERFLOW; det = st_host[STW_SEL_ROWS]; }
+  if (detail) *detail = det;
+  if (code < 0) fail(h, code, dp_strerror(code));
+  return code;
+}
+
+}  // extern "C"

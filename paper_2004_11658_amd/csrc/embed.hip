@@ -1,0 +1,440 @@
+// Embedding net, descriptor contraction and its adjoint (paper Section 2, Eq. 4-10;
+// Section 3.2.3 for the fused bias / tanh / tanh-gradient epilogues).
+//
+// Work layout.  Rows (centre atoms) are grouped by species and padded (kRowPad); a
+// workgroup of WPB waves handles WPB centres of one species alpha, one wave per centre.
+// For each neighbour species beta the workgroup stages the position-padded net
+// (alpha, beta) in LDS and every wave walks its centre's real neighbours of species
+// beta in chunks of 16 (padded slots hold no atom and are skipped: their R rows are 0).
+//
+// Transposed MFMA chain.  A layer y = x W + b is evaluated as y^T = W^T x^T on the
+// 16x16x4 MFMA: the weights are the A operand (read from LDS), the activations the B
+// operand, so the 16 neighbour rows run along lane % 16 and the features along
+// (lane / 16, accumulator register).  Layer outputs come out in exactly the layout the
+// next layer needs as its B operand (the k order of each MFMA step is permuted to
+// match), so activations never leave registers.  Features are placed at "positions":
+// feature f of a width-s0 block sits at position (f / s0) * 32 + f % s0; with this
+// placement the concatenation skip (x, x) of Eq. 9 adds values held by the same lane
+// and register, and the pads (position % 32 >= s0) carry zero weights and stay zero.
+//
+// The contraction T = G^T R / N_m (Eq. 4) reduces over the 16 rows of a chunk with a
+// lane reduce-scatter (16 lanes -> 8 values per lane), accumulated over chunks.
+//
+// The adjoint recomputes G (no per-neighbour activations are stored) and runs the
+// chain backwards with the transposed weight access, fusing 1 - tanh^2 into the MFMA
+// operand preparation; g_ij = dR^T dE/dR, F_i += g, F_j -= g (FP64 atomics), and the
+// per-centre virial -d (x) g.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace dp {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <class T> struct Acc4;
+template <> struct Acc4<double> { typedef d4v type; };
+template <> struct Acc4<float> { typedef f4v type; };
+
+__device__ __forceinline__ d4v mfma4(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// tanh: double uses the HIP math library; float uses tanh x = 1 - 2 / (exp(2x) + 1)
+// with the hardware exp2 and a correctly rounded division.
+__device__ __forceinline__ double tanh_t(double x) { return tanh(x); }
+__device__ __forceinline__ float tanh_t(float x) {
+  float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);  // exp(2x) = 2^(2x log2 e)
+  return 1.0f - 2.0f / (e + 1.0f);
+}
+
+// Accumulator row held by lane group g in register q of a 16x16 MFMA result:
+// FP64 16x16x4 returns rows g + 4q, FP32 16x16x4 (and BF16 16x16x32) rows 4g + q.
+__device__ __forceinline__ int lpos(double, int g, int q) { return g + 4 * q; }
+__device__ __forceinline__ int lpos(float, int g, int q) { return 4 * g + q; }
+#define LP(g, q) lpos(T(), g, q)
+
+template <class T>
+__device__ __forceinline__ T shfl_x(T v, int mask) {
+  return __shfl_xor(v, mask);
+}
+
+// species of the rows starting at r0 (rows of one block never straddle species)
+__device__ __forceinline__ int species_of(int r0, int ntypes, const int* __restrict__ type_row0) {
+  for (int t = 0; t < ntypes; t++)
+    if (r0 >= type_row0[t] && r0 < type_row0[t + 1]) return t;
+  return -1;
+}
+
+template <class T>
+__device__ __forceinline__ void stage_net(T* __restrict__ dst, const T* __restrict__ src) {
+  for (int q = threadIdx.x; q < kNetElems; q += blockDim.x) dst[q] = src[q];
+}
+
+// Environment row of one neighbour (Eq. 5) and its derivative with respect to d.
+struct Env {
+  double d[3], r, s, ds, R[4];
+};
+__device__ __forceinline__ void env_row(const ModelC& m, const double* __restrict__ xe, int e,
+                                        const double xi[3], Env& v) {
+  v.d[0] = xe[3 * e] - xi[0];
+  v.d[1] = xe[3 * e + 1] - xi[1];
+  v.d[2] = xe[3 * e + 2] - xi[2];
+  double r2 = v.d[0] * v.d[0] + v.d[1] * v.d[1] + v.d[2] * v.d[2];
+  v.r = sqrt(r2);
+  smooth_fn(m, v.r, v.s, v.ds);
+  double sr = v.s / v.r;
+  v.R[0] = v.s;
+  v.R[1] = sr * v.d[0];
+  v.R[2] = sr * v.d[1];
+  v.R[3] = sr * v.d[2];
+}
+
+// forward chain of one 16-row chunk: t0 (L0 = tanh), t1, t2 (tanh parts of L1, L2)
+template <class T>
+__device__ __forceinline__ void chain_fwd(const T* __restrict__ net, T s, int g, int rb,
+                                          T (&t0)[2][4], T (&t1)[4][4], T (&t2)[8][4]) {
+  typedef typename Acc4<T>::type A4;
+#pragma unroll
+  for (int n = 0; n < 2; n++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      int p = 16 * n + LP(g, q);
+      t0[n][q] = tanh_t(s * net[kOffW0 + p] + net[kOffB0 + p]);
+    }
+#pragma unroll
+  for (int mt = 0; mt < 4; mt++) {
+    A4 c = {0, 0, 0, 0};
+#pragma unroll
+    for (int n = 0; n < 2; n++)
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        c = mfma4(net[kOffW1 + (16 * n + LP(g, q)) * kW1Stride + 16 * mt + rb], t0[n][q], c);
+#pragma unroll
+    for (int q = 0; q < 4; q++) t1[mt][q] = tanh_t(c[q] + net[kOffB1 + 16 * mt + LP(g, q)]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // h1 = (h0, h0) + t1, h0 = t0
+  T h1[4][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) h1[mt][q] = t0[mt & 1][q] + t1[mt][q];
+#pragma unroll
+  for (int mt = 0; mt < 8; mt++) {
+    A4 c = {0, 0, 0, 0};
+#pragma unroll
+    for (int n = 0; n < 4; n++)
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        c = mfma4(net[kOffW2 + (16 * n + LP(g, q)) * kW2Stride + 16 * mt + rb], h1[n][q], c);
+#pragma unroll
+    for (int q = 0; q < 4; q++) t2[mt][q] = tanh_t(c[q] + net[kOffB2 + 16 * mt + LP(g, q)]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// G = (h1, h1) + t2 with h1 = (t0, t0) + t1, at position 16 mt + lpos(g, q)
+template <class T>
+__device__ __forceinline__ T g_at(const T (&t0)[2][4], const T (&t1)[4][4], const T (&t2)[8][4],
+                                  int mt, int q) {
+  return t0[mt & 1][q] + t1[mt & 3][q] + t2[mt][q];
+}
+
+// one reduce-scatter step over lane bit B on an array of S values
+template <class T, int S, int B>
+__device__ __forceinline__ void rs_step(T (&v)[64], bool up) {
+#pragma unroll
+  for (int k = 0; k < S / 2; k++) {
+    T a = v[k], b = v[k + S / 2];
+    T send = up ? a : b;
+    T keep = up ? b : a;
+    v[k] = keep + shfl_x(send, B);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// forward: T_i = (1/N_m) sum_j G_j^T R_j
+// ------------------------------------------------------------------------------------
+template <class T, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_embed_fwd(EmbedArgs A) {
+  extern __shared__ __align__(16) char smem_raw[];
+  T* net = (T*)smem_raw;
+  const ModelC& m = A.m;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, rb = lane & 15, g = lane >> 4;
+  const int r0 = blockIdx.x * WPB;
+  const int alpha = species_of(r0, m.ntypes, A.type_row0);
+  if (alpha < 0) return;  // uniform over the block
+  const int row = r0 + wv;
+  const int atom = A.row_atom[row];
+  double xi[3] = {0, 0, 0};
+  if (atom >= 0) {
+    xi[0] = A.xe[3 * atom];
+    xi[1] = A.xe[3 * atom + 1];
+    xi[2] = A.xe[3 * atom + 2];
+  }
+  T acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) acc[j] = (T)0;
+  for (int beta = 0; beta < m.ntypes; beta++) {
+    __syncthreads();
+    stage_net<T>(net, (const T*)A.nets + (size_t)(alpha * m.ntypes + beta) * kNetElems);
+    __syncthreads();
+    if (atom < 0) continue;
+    const int nn = A.nnei[atom * m.ntypes + beta];
+    const int* nl = A.nlist + (size_t)atom * m.nm + m.sel_off[beta];
+    for (int c0 = 0; c0 < nn; c0 += 16) {
+      const int k = c0 + rb;
+      Env v;
+      T s = (T)0;
+      T R[4] = {(T)0, (T)0, (T)0, (T)0};
+      if (k < nn) {
+        env_row(m, A.xe, nl[k], xi, v);
+        s = (T)v.s;
+#pragma unroll
+        for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
+      }
+      T t0[2][4], t1[4][4], t2[8][4];
+      chain_fwd<T>(net, s, g, rb, t0, t1, t2);
+      // reduce-scatter of the 128 products G[mt][q] R[c] over the 16 rows
+      const bool b3 = rb & 8, b2 = rb & 4, b1 = rb & 2, b0 = rb & 1;
+      T vv[64];
+#pragma unroll
+      for (int kk = 0; kk < 64; kk++) {
+        int mt = kk >> 4, q = (kk >> 2) & 3, c = kk & 3;
+        T a = g_at(t0, t1, t2, mt, q) * R[c];
+        T b = g_at(t0, t1, t2, mt + 4, q) * R[c];
+        T send = b3 ? a : b;
+        T keep = b3 ? b : a;
+        vv[kk] = keep + shfl_x(send, 8);
+        if ((kk & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+      }
+      rs_step<T, 64, 4>(vv, b2);
+      rs_step<T, 32, 2>(vv, b1);
+      rs_step<T, 16, 1>(vv, b0);
+#pragma unroll
+      for (int j = 0; j < 8; j++) acc[j] += vv[j];
+    }
+  }
+  if (atom < 0) return;
+  // lane holds tile mt = 4 b3 + 2 b2 + b1, register q = 2 b0 + j / 4, c = j % 4
+  const int mt = 4 * ((rb >> 3) & 1) + 2 * ((rb >> 2) & 1) + ((rb >> 1) & 1);
+  T* Tout = (T*)A.T + (size_t)row * m.M * 4;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    int q = 2 * (rb & 1) + (j >> 2), c = j & 3;
+    int p = 16 * mt + LP(g, q);
+    int f = (p % kP0) < m.s0 ? (p / kP0) * m.s0 + (p % kP0) : -1;
+    if (f >= 0) Tout[f * 4 + c] = acc[j] * (T)m.inv_norm;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// adjoint: forces and per-centre virial
+// ------------------------------------------------------------------------------------
+template <class T, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_embed_bwd(EmbedArgs A) {
+  extern __shared__ __align__(16) char smem_raw[];
+  T* net = (T*)smem_raw;
+  T* gts = net + kNetElems + 64;           // per wave: dE/dT at positions [kP2][4]
+  const ModelC& m = A.m;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, rb = lane & 15, g = lane >> 4;
+  const int r0 = blockIdx.x * WPB;
+  const int alpha = species_of(r0, m.ntypes, A.type_row0);
+  if (alpha < 0) return;
+  const int row = r0 + wv;
+  const int atom = A.row_atom[row];
+  T* gt = gts + wv * kP2 * 4;
+  double xi[3] = {0, 0, 0};
+  if (atom >= 0) {
+    xi[0] = A.xe[3 * atom];
+    xi[1] = A.xe[3 * atom + 1];
+    xi[2] = A.xe[3 * atom + 2];
+    const T* src = (const T*)A.gT + (size_t)row * m.M * 4;
+    for (int q = lane; q < kP2 * 4; q += 64) {
+      int p = q >> 2, c = q & 3;
+      int f = (p % kP0) < m.s0 ? (p / kP0) * m.s0 + (p % kP0) : -1;
+      gt[q] = f >= 0 ? src[f * 4 + c] : (T)0;
+    }
+  }
+  double fi[3] = {0, 0, 0};
+  double vir[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const T inorm = (T)m.inv_norm;
+  typedef typename Acc4<T>::type A4;
+  for (int beta = 0; beta < m.ntypes; beta++) {
+    __syncthreads();
+    stage_net<T>(net, (const T*)A.nets + (size_t)(alpha * m.ntypes + beta) * kNetElems);
+    __syncthreads();
+    if (atom < 0) continue;
+    const int nn = A.nnei[atom * m.ntypes + beta];
+    const int* nl = A.nlist + (size_t)atom * m.nm + m.sel_off[beta];
+    for (int c0 = 0; c0 < nn; c0 += 16) {
+      const int k = c0 + rb;
+      const bool valid = k < nn;
+      Env v;
+      int e = -1;
+      T s = (T)0;
+      T R[4] = {(T)0, (T)0, (T)0, (T)0};
+      if (valid) {
+        e = nl[k];
+        env_row(m, A.xe, e, xi, v);
+        s = (T)v.s;
+#pragma unroll
+        for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
+      }
+      T t0[2][4], t1[4][4], t2[8][4];
+      chain_fwd<T>(net, s, g, rb, t0, t1, t2);
+      // dE/dG (Eq. 4 adjoint) and the G.dE/dT part of dE/dR
+      T gR[4] = {(T)0, (T)0, (T)0, (T)0};
+      T res1[4][4];   // dE/dG[p] + dE/dG[p + 64]: the concat skip of the last layer
+#pragma unroll
+      for (int mt = 0; mt < 8; mt++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const T* gp = gt + (16 * mt + LP(g, q)) * 4;
+          T G = g_at(t0, t1, t2, mt, q);
+          T gG = (gp[0] * R[0] + gp[1] * R[1] + gp[2] * R[2] + gp[3] * R[3]) * inorm;
+#pragma unroll
+          for (int c = 0; c < 4; c++) gR[c] += G * gp[c];
+          if (mt < 4) res1[mt][q] = gG;
+          else res1[mt - 4][q] += gG;
+          t2[mt][q] = gG * ((T)1 - t2[mt][q] * t2[mt][q]);  // becomes d(pre-activation)
+        }
+      // layer 2 adjoint: dh1 = res1 + W2 . d2; the concat skip of layer 1 passes the
+      // undamped dh1 on (dh1[p] + dh1[p + 32]); then dh1 is damped by 1 - t1^2
+      T dh1[4][4];
+#pragma unroll
+      for (int nt = 0; nt < 4; nt++) {
+        A4 c = {0, 0, 0, 0};
+#pragma unroll
+        for (int mt = 0; mt < 8; mt++)
+#pragma unroll
+          for (int q = 0; q < 4; q++)
+            c = mfma4(net[kOffW2 + (16 * nt + rb) * kW2Stride + 16 * mt + LP(g, q)], t2[mt][q], c);
+#pragma unroll
+        for (int q = 0; q < 4; q++) dh1[nt][q] = res1[nt][q] + c[q];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      T dh0[2][4];
+#pragma unroll
+      for (int nt = 0; nt < 2; nt++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) dh0[nt][q] = dh1[nt][q] + dh1[nt + 2][q];
+#pragma unroll
+      for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) dh1[nt][q] *= ((T)1 - t1[nt][q] * t1[nt][q]);
+      // layer 1 adjoint: dh0 += W1 . d1
+#pragma unroll
+      for (int nt = 0; nt < 2; nt++) {
+        A4 c = {0, 0, 0, 0};
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+          for (int q = 0; q < 4; q++)
+            c = mfma4(net[kOffW1 + (16 * nt + rb) * kW1Stride + 16 * mt + LP(g, q)], dh1[mt][q], c);
+#pragma unroll
+        for (int q = 0; q < 4; q++) dh0[nt][q] += c[q];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // layer 0: ds = sum_p dh0 (1 - t0^2) W0
+      T dsl = (T)0;
+#pragma unroll
+      for (int nt = 0; nt < 2; nt++)
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          dsl += dh0[nt][q] * ((T)1 - t0[nt][q] * t0[nt][q]) * net[kOffW0 + 16 * nt + LP(g, q)];
+      // sum over the 4 lane groups holding the same row
+      dsl += shfl_x(dsl, 16);
+      dsl += shfl_x(dsl, 32);
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        gR[c] += shfl_x(gR[c], 16);
+        gR[c] += shfl_x(gR[c], 32);
+      }
+      if (valid && g == 0) {
+        double gRd[4] = {(double)gR[0] * m.inv_norm + (double)dsl, (double)gR[1] * m.inv_norm,
+                         (double)gR[2] * m.inv_norm, (double)gR[3] * m.inv_norm};
+        // g_b = sum_c dE/dR_c dR_c/dd_b (Eq. 5 differentiated)
+        double ir = 1.0 / v.r;
+        double sr = v.s * ir;
+        double qf = (v.ds * ir - v.s * ir * ir) * ir;
+        double dot = gRd[1] * v.d[0] + gRd[2] * v.d[1] + gRd[3] * v.d[2];
+        double gv[3];
+#pragma unroll
+        for (int b = 0; b < 3; b++) gv[b] = gRd[0] * v.ds * v.d[b] * ir + qf * dot * v.d[b] + sr * gRd[1 + b];
+        int own = A.eown[e];
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+          fi[b] += gv[b];
+          unsafeAtomicAdd(&A.forces[3 * own + b], -gv[b]);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+          for (int b = 0; b < 3; b++) vir[3 * a + b] -= v.d[a] * gv[b];
+      }
+    }
+  }
+  if (atom < 0) return;
+  // reduce over the 16 rows (lanes 0..15 hold the sums; other lane groups hold zeros)
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+    for (int b = 0; b < 3; b++) fi[b] += __shfl_xor(fi[b], o);
+#pragma unroll
+    for (int q = 0; q < 9; q++) vir[q] += __shfl_xor(vir[q], o);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int b = 0; b < 3; b++) unsafeAtomicAdd(&A.forces[3 * atom + b], fi[b]);
+  }
+  if (lane < 9) {
+    double val = 0;
+#pragma unroll
+    for (int q = 0; q < 9; q++) val = (lane == q) ? vir[q] : val;
+    A.vir_part[(size_t)row * 9 + lane] = val;
+  }
+}
+
+constexpr int kEmbWaves = 8;
+
+static int embed_grid(int nrows) { return (nrows + kEmbWaves - 1) / kEmbWaves; }
+int embed_bwd_blocks(int nrows) { return embed_grid(nrows); }
+
+void launch_embed_fwd(const EmbedArgs& a, hipStream_t st) {
+  if (a.prec == PREC_FP64) {
+    size_t sh = sizeof(double) * kNetElems;
+    (void)hipFuncSetAttribute((const void*)k_embed_fwd<double, kEmbWaves>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((k_embed_fwd<double, kEmbWaves>), dim3(embed_grid(a.nrows)), dim3(64 * kEmbWaves),
+                       sh, st, a);
+  } else {
+    size_t sh = sizeof(float) * kNetElems;
+    hipLaunchKernelGGL((k_embed_fwd<float, kEmbWaves>), dim3(embed_grid(a.nrows)), dim3(64 * kEmbWaves),
+                       sh, st, a);
+  }
+}
+
+void launch_embed_bwd(const EmbedArgs& a, hipStream_t st) {
+  if (a.prec == PREC_FP64) {
+    size_t sh = sizeof(double) * (kNetElems + 64 + kEmbWaves * kP2 * 4);
+    (void)hipFuncSetAttribute((const void*)k_embed_bwd<double, kEmbWaves>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((k_embed_bwd<double, kEmbWaves>), dim3(embed_grid(a.nrows)), dim3(64 * kEmbWaves),
+                       sh, st, a);
+  } else {
+    size_t sh = sizeof(float) * (kNetElems + 64 + kEmbWaves * kP2 * 4);
+    (void)hipFuncSetAttribute((const void*)k_embed_bwd<float, kEmbWaves>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((k_embed_bwd<float, kEmbWaves>), dim3(embed_grid(a.nrows)), dim3(64 * kEmbWaves),
+                       sh, st, a);
+  }
+}
+
+}  // namespace dp

@@ -1,0 +1,377 @@
+// Descriptor and fitting net (paper Section 2, Eq. 1-4) with their adjoint.
+//
+// Rows are centre atoms grouped by species (row groups padded to 64, so a 64-row GEMM
+// tile never mixes species and every tile uses one fitting net).  Per species:
+//   D   = T T<^T flattened a * M< + b                       (Eq. 4)
+//   x1  = tanh(D W1 + b1)                                    first layer, no skip
+//   xk  = x_{k-1} + tanh(x_{k-1} Wk + bk)                    Eq. 3
+//   E_i = x_last . w_o + b_o
+// and back: g_last = w_o; g_{k-1} = g_k + (g_k * (1 - t_k^2)) Wk^T; dD = (g_1 (1 - t_1^2)) W1^T;
+// dE/dT from dD.  GEMMs run on the 16x16x4 MFMA (FP64 or FP32 operands), 64x64 output
+// tiles per workgroup, with the bias, tanh and skip fused into the epilogue and the
+// 1 - tanh^2 factor fused into operand staging (the paper's fused TANH / TANHGrad,
+// Section 3.2.3).
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace dp {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <class T> struct FAcc4;
+template <> struct FAcc4<double> { typedef d4v type; };
+template <> struct FAcc4<float> { typedef f4v type; };
+
+__device__ __forceinline__ d4v fmfma4(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v fmfma4(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ double ftanh(double x) { return tanh(x); }
+__device__ __forceinline__ float ftanh(float x) {
+  float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);
+  return 1.0f - 2.0f / (e + 1.0f);
+}
+
+enum Epi { EPI_FWD1 = 0, EPI_FWDRES = 1, EPI_BWD = 2, EPI_BWD1 = 3 };
+
+constexpr int GT = 64;   // output tile
+constexpr int KT = 16;   // k tile
+
+struct GemmArgs {
+  int nrows, K, N;
+  int species_rows[kMaxTypes + 1];  // unused on device; rows read from type_row0
+  const int* type_row0;
+  int ntypes;
+  const void* A;        // [nrows][K]
+  const void* Aaux;     // BWD: t of this layer [nrows][K] (A staged as A * (1 - t^2))
+  const void* const* W;  // per species weight pointer table (row major [K_w][N_w])
+  int wsel;             // index offset into the table: species * wstride + wsel
+  int wstride;
+  const void* const* bias;
+  const void* Xprev;    // FWDRES: x_{k-1} [nrows][N]; BWD: skip source g_k [nrows][N]
+  void* out;            // [nrows][N]
+  void* out2;           // FWD*: tanh part [nrows][N]
+};
+
+template <class T, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
+  __shared__ T As[GT][KT + 1];
+  __shared__ T Bs[KT][GT + 1];
+  const int r0 = blockIdx.x * GT;
+  const int n0 = blockIdx.y * GT;
+  int sp = -1;
+  for (int t = 0; t < G.ntypes; t++)
+    if (r0 >= G.type_row0[t] && r0 < G.type_row0[t + 1]) sp = t;
+  if (sp < 0) return;
+  const T* A = (const T*)G.A;
+  const T* At = (const T*)G.Aaux;
+  const T* W = (const T*)G.W[sp * G.wstride + G.wsel];
+  const bool transW = (EPI == EPI_BWD || EPI == EPI_BWD1);
+  const int K = G.K, N = G.N;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, rb = lane & 15, g = lane >> 4;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+  typedef typename FAcc4<T>::type A4;
+  A4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) acc[a][b] = A4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += KT) {
+    // stage A (64 x 16) and B (16 x 64)
+    for (int q = tid; q < GT * KT; q += 256) {
+      int r = q / KT, k = q % KT;
+      int gr = r0 + r, gk = k0 + k;
+      T v = (T)0;
+      if (gk < K) {
+        v = A[(size_t)gr * K + gk];
+        if (EPI == EPI_BWD || EPI == EPI_BWD1) {
+          T t = At[(size_t)gr * K + gk];
+          v = v * ((T)1 - t * t);
+        }
+      }
+      As[r][k] = v;
+    }
+    for (int q = tid; q < GT * KT; q += 256) {
+      int k = q / GT, c = q % GT;
+      int gk = k0 + k, gc = n0 + c;
+      T v = (T)0;
+      if (gk < K && gc < N) v = transW ? W[(size_t)gc * K + gk] : W[(size_t)gk * N + gc];
+      Bs[k][c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KT; ks += 4) {
+      T a0 = As[wr + rb][ks + g], a1 = As[wr + 16 + rb][ks + g];
+      T b0 = Bs[ks + g][wc + rb], b1 = Bs[ks + g][wc + 16 + rb];
+      acc[0][0] = fmfma4(a0, b0, acc[0][0]);
+      acc[0][1] = fmfma4(a0, b1, acc[0][1]);
+      acc[1][0] = fmfma4(a1, b0, acc[1][0]);
+      acc[1][1] = fmfma4(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+  // epilogue: lane holds column (wc + 16 b + rb) and four rows of the 16-row tile
+  T* out = (T*)G.out;
+  T* out2 = (T*)G.out2;
+  const T* X = (const T*)G.Xprev;
+  const T* bias = (EPI == EPI_FWD1 || EPI == EPI_FWDRES) ? (const T*)G.bias[sp * G.wstride + G.wsel] : nullptr;
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      int col = n0 + wc + 16 * b + rb;
+      if (col >= N) continue;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        // FP64 16x16x4 results hold rows g + 4q, FP32 rows 4g + q
+        int row = r0 + wr + 16 * a + (sizeof(T) == 8 ? g + 4 * q : 4 * g + q);
+        size_t o = (size_t)row * N + col;
+        T v = acc[a][b][q];
+        if (EPI == EPI_FWD1) {
+          T t = ftanh(v + bias[col]);
+          out[o] = t;
+          out2[o] = t;
+        } else if (EPI == EPI_FWDRES) {
+          T t = ftanh(v + bias[col]);
+          out[o] = X[o] + t;
+          out2[o] = t;
+        } else if (EPI == EPI_BWD) {
+          out[o] = X[o] + v;
+        } else {
+          out[o] = v;
+        }
+      }
+    }
+}
+
+// D[row][a m2 + b] = sum_c T[row][a][c] T[row][b][c]; pad rows get zeros
+template <class T>
+__global__ void k_desc(int nrows, int M, int m2, const int* __restrict__ row_atom,
+                       const T* __restrict__ Tm, T* __restrict__ D) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t tot = (size_t)nrows * M * m2;
+  if (q >= tot) return;
+  int row = (int)(q / (M * m2));
+  int ab = (int)(q % (M * m2));
+  int a = ab / m2, b = ab % m2;
+  T v = (T)0;
+  if (row_atom[row] >= 0) {
+    const T* t = Tm + (size_t)row * M * 4;
+    v = t[a * 4] * t[b * 4] + t[a * 4 + 1] * t[b * 4 + 1] + t[a * 4 + 2] * t[b * 4 + 2] +
+        t[a * 4 + 3] * t[b * 4 + 3];
+  }
+  D[q] = v;
+}
+
+// dE/dT[p][c] = sum_b dD[p][b] T[b][c] + [p < m2] sum_a dD[a][p] T[a][c]
+template <class T>
+__global__ void k_desc_bwd(int nrows, int M, int m2, const int* __restrict__ row_atom,
+                           const T* __restrict__ Tm, const T* __restrict__ Dg, T* __restrict__ gT) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t tot = (size_t)nrows * M;
+  if (q >= tot) return;
+  int row = (int)(q / M), p = (int)(q % M);
+  T* o = gT + (size_t)row * M * 4 + p * 4;
+  if (row_atom[row] < 0) {
+    o[0] = o[1] = o[2] = o[3] = (T)0;
+    return;
+  }
+  const T* t = Tm + (size_t)row * M * 4;
+  const T* dg = Dg + (size_t)row * M * m2;
+  T v[4] = {(T)0, (T)0, (T)0, (T)0};
+  for (int b = 0; b < m2; b++) {
+    T w = dg[p * m2 + b];
+#pragma unroll
+    for (int c = 0; c < 4; c++) v[c] += w * t[b * 4 + c];
+  }
+  if (p < m2)
+    for (int a = 0; a < M; a++) {
+      T w = dg[a * m2 + p];
+#pragma unroll
+      for (int c = 0; c < 4; c++) v[c] += w * t[a * 4 + c];
+    }
+#pragma unroll
+  for (int c = 0; c < 4; c++) o[c] = v[c];
+}
+
+// E_i = x . w_o + b_o (FP64 accumulation) and the backward seed g = w_o; one wave per row
+template <class T>
+__global__ void k_fit_out(int nrows, int N, int ntypes, const int* __restrict__ type_row0,
+                          const int* __restrict__ row_atom, const T* __restrict__ X,
+                          const void* const* __restrict__ wo, const double* __restrict__ bo,
+                          double* __restrict__ Ei, T* __restrict__ gseed) {
+  int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (row >= nrows) return;
+  int sp = -1;
+  for (int t = 0; t < ntypes; t++)
+    if (row >= type_row0[t] && row < type_row0[t + 1]) sp = t;
+  if (sp < 0) return;
+  const T* w = (const T*)wo[sp];
+  double acc = 0.0;
+  bool real = row_atom[row] >= 0;
+  for (int c = lane; c < N; c += 64) {
+    if (real) acc += (double)X[(size_t)row * N + c] * (double)w[c];
+    gseed[(size_t)row * N + c] = w[c];
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) Ei[row] = real ? acc + bo[sp] : 0.0;
+}
+
+template <class T, int EPI>
+static void gemm(const GemmArgs& G, hipStream_t st) {
+  dim3 grid((G.nrows + GT - 1) / GT, (G.N + GT - 1) / GT);
+  hipLaunchKernelGGL((k_gemm<T, EPI>), grid, dim3(256), 0, st, G);
+}
+
+template <class T>
+static void fit_t(const FitArgs& F, hipStream_t st) {
+  const int rows = F.nrows, M = F.m.M, m2 = F.m.m2, K1 = M * m2, fw = F.fw;
+  {
+    size_t tot = (size_t)rows * K1;
+    hipLaunchKernelGGL(k_desc<T>, dim3((tot + 255) / 256), dim3(256), 0, st, rows, M, m2, F.row_atom,
+                       (const T*)F.T, (T*)F.D);
+  }
+  T* act = (T*)F.act;
+  T* xs = (T*)F.xs;
+  size_t L = (size_t)rows * fw;
+  GemmArgs G{};
+  G.nrows = rows;
+  G.type_row0 = F.type_row0;
+  G.ntypes = F.m.ntypes;
+  G.W = F.W;
+  G.bias = F.b;
+  G.wstride = F.nfit;
+  for (int k = 0; k < F.nfit; k++) {
+    G.K = k == 0 ? K1 : fw;
+    G.N = fw;
+    G.wsel = k;
+    G.A = k == 0 ? F.D : (const void*)(xs + (k - 1) * L);
+    G.Xprev = k == 0 ? nullptr : (const void*)(xs + (k - 1) * L);
+    G.out = xs + k * L;
+    G.out2 = act + k * L;
+    if (k == 0) gemm<T, EPI_FWD1>(G, st);
+    else gemm<T, EPI_FWDRES>(G, st);
+  }
+  hipLaunchKernelGGL(k_fit_out<T>, dim3((rows + 3) / 4), dim3(256), 0, st, rows, fw, F.m.ntypes,
+                     F.type_row0, F.row_atom, (const T*)(xs + (F.nfit - 1) * L), F.wo, F.bo, F.Ei,
+                     (T*)F.g0);
+  T* gcur = (T*)F.g0;
+  T* gnext = (T*)F.g1;
+  for (int k = F.nfit - 1; k >= 1; k--) {
+    G.K = fw;
+    G.N = fw;
+    G.wsel = k;
+    G.A = gcur;
+    G.Aaux = act + k * L;
+    G.Xprev = gcur;
+    G.out = gnext;
+    gemm<T, EPI_BWD>(G, st);
+    T* tmp = gcur;
+    gcur = gnext;
+    gnext = tmp;
+  }
+  G.K = fw;
+  G.N = K1;
+  G.wsel = 0;
+  G.A = gcur;
+  G.Aaux = act;
+  G.Xprev = nullptr;
+  G.out = F.Dg;
+  gemm<T, EPI_BWD1>(G, st);
+  {
+    size_t tot = (size_t)rows * M;
+    hipLaunchKernelGGL(k_desc_bwd<T>, dim3((tot + 255) / 256), dim3(256), 0, st, rows, M, m2, F.row_atom,
+                       (const T*)F.T, (const T*)F.Dg, (T*)F.gT);
+  }
+}
+
+void launch_fit(const FitArgs& F, hipStream_t st) {
+  if (F.prec == PREC_FP64) fit_t<double>(F, st);
+  else fit_t<float>(F, st);
+}
+
+// ------------------------------------------------------------------------------------
+// reductions and small helpers
+// ------------------------------------------------------------------------------------
+__global__ void k_zero(size_t n, double* __restrict__ p) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+void launch_zero(double* p, size_t n, hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, st, n, p);
+}
+
+// per frame, fixed-order sums of E_i and the per-centre virials (one block per frame)
+__global__ __launch_bounds__(256) void k_frame_reduce(const Frame* __restrict__ frames,
+                                                      const int* __restrict__ row_of,
+                                                      const double* __restrict__ Ei,
+                                                      const double* __restrict__ vir,
+                                                      double* __restrict__ energies,
+                                                      double* __restrict__ virials,
+                                                      double* __restrict__ atom_energy) {
+  __shared__ double sh[256][10];
+  const Frame& F = frames[blockIdx.x];
+  double acc[10];
+#pragma unroll
+  for (int q = 0; q < 10; q++) acc[q] = 0.0;
+  for (int i = F.atom0 + threadIdx.x; i < F.atom0 + F.natoms; i += 256) {
+    int r = row_of[i];
+    double e = Ei[r];
+    acc[0] += e;
+    if (atom_energy) atom_energy[i] = e;
+    if (vir)
+#pragma unroll
+      for (int q = 0; q < 9; q++) acc[1 + q] += vir[(size_t)r * 9 + q];
+  }
+#pragma unroll
+  for (int q = 0; q < 10; q++) sh[threadIdx.x][q] = acc[q];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+#pragma unroll
+      for (int q = 0; q < 10; q++) sh[threadIdx.x][q] += sh[threadIdx.x + s][q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    energies[blockIdx.x] = sh[0][0];
+    if (virials && vir)
+#pragma unroll
+      for (int q = 0; q < 9; q++) virials[blockIdx.x * 9 + q] = sh[0][1 + q];
+  }
+}
+
+void launch_frame_reduce(int nframes, const Frame* frames, const int* row_of, const double* Ei,
+                         const double* vir_rows, double* energies, double* virials,
+                         double* atom_energy, hipStream_t st) {
+  hipLaunchKernelGGL(k_frame_reduce, dim3(nframes), dim3(256), 0, st, frames, row_of, Ei, vir_rows,
+                     energies, virials, atom_energy);
+}
+
+template <class T>
+__global__ void k_export_T(int n, int M, const int* __restrict__ row_of, const T* __restrict__ Tm,
+                           const T* __restrict__ gT, double* __restrict__ To, double* __restrict__ gTo) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (size_t)n * M * 4) return;
+  int i = (int)(q / (M * 4));
+  size_t src = (size_t)row_of[i] * M * 4 + q % (M * 4);
+  if (To) To[q] = (double)Tm[src];
+  if (gTo) gTo[q] = (double)gT[src];
+}
+
+void launch_export_T(int prec, int n, int M, const int* row_of, const void* Tm, const void* gT,
+                     double* To, double* gTo, hipStream_t st) {
+  size_t tot = (size_t)n * M * 4;
+  if (prec == PREC_FP64)
+    hipLaunchKernelGGL(k_export_T<double>, dim3((tot + 255) / 256), dim3(256), 0, st, n, M, row_of,
+                       (const double*)Tm, (const double*)gT, To, gTo);
+  else
+    hipLaunchKernelGGL(k_export_T<float>, dim3((tot + 255) / 256), dim3(256), 0, st, n, M, row_of,
+                       (const float*)Tm, (const float*)gT, To, gTo);
+}
+
+}  // namespace dp

@@ -1,0 +1,104 @@
+// Host-side launch interfaces between the C ABI layer and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace dp {
+
+constexpr int kRowPad = 64;   // species row groups are padded to this many rows
+
+// ---------------------------------------------------------------- neighbour list
+struct NlistArgs {
+  int n, nframes, ncell, ghost_cap, nrows;
+  ModelC m;
+  const Frame* frames;
+  const double* x;
+  const int* types;
+  int* status;
+  int* frame_of;
+  double *xw, *fw;
+  int *gcount, *goff, *gtotal, *ctotal, *n_ext, *scan_sums;
+  double* xe;
+  int *eown, *eimg, *etype, *ecell;
+  int *cell_count, *cell_start, *cell_fill, *cell_atoms;
+  int *nlist, *nnei;
+  int *tpos, *tcount, *row_of, *type_row0, *row_atom;
+};
+size_t scan_sums_ints(int n, int W);
+void launch_nlist(const NlistArgs& a, hipStream_t st);
+void launch_nlist_export(int n, int nm, const int* nlist, const int* eown, const int* eimg,
+                         const int* frame_of, const Frame* frames, int* out_j, int* out_img,
+                         hipStream_t st);
+
+// ---------------------------------------------------------------- embedding nets
+// Position-padded per-net weight block (see embed.hip): P0 = 32, P1 = 64, P2 = 128.
+constexpr int kP0 = 32, kP1 = 64, kP2 = 128;
+constexpr int kW1Stride = kP1 + 1, kW2Stride = kP2 + 1;
+// element offsets inside one net block (same for every storage type)
+constexpr int kOffW0 = 0, kOffB0 = kP0, kOffB1 = 2 * kP0, kOffB2 = 2 * kP0 + kP1;
+constexpr int kOffW1 = 2 * kP0 + kP1 + kP2;
+constexpr int kOffW2 = kOffW1 + kP0 * kW1Stride;
+constexpr int kNetElems = kOffW2 + kP1 * kW2Stride;
+
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2, PREC_BF16X3 = 3 };
+
+struct EmbedArgs {
+  int prec;
+  int nrows;           // padded species-grouped rows
+  int n;               // local atoms
+  ModelC m;
+  const void* nets;    // [ntypes*ntypes] net blocks in the precision's storage layout
+  const double* xe;
+  const int* nlist;
+  const int* nnei;
+  const int* row_atom;
+  const int* type_row0;
+  const int* eown;
+  void* T;             // [nrows][M][4] (double for FP64, float otherwise)
+  const void* gT;      // backward: dE/dT, same layout
+  double* forces;      // backward: [n][3] accumulated with atomics
+  double* vir_part;    // backward: per-centre virial [nrows][9]
+  const int* frame_of;
+  int nframes;
+};
+void launch_embed_fwd(const EmbedArgs& a, hipStream_t st);
+void launch_embed_bwd(const EmbedArgs& a, hipStream_t st);
+int embed_bwd_blocks(int nrows);
+
+// ---------------------------------------------------------------- fitting net
+struct FitArgs {
+  int prec;
+  int nrows, n;
+  ModelC m;
+  int nfit;            // hidden layers
+  int fw;              // hidden width (square layers after the first)
+  const int* type_row0;
+  const int* row_atom;
+  const void* T;       // [nrows][M][4]
+  void* gT;            // out: dE/dT [nrows][M][4]
+  // per species weights in storage type (double for FP64, float otherwise):
+  // W1 [M*m2][fw], b1, W2.., wo [fw], bo [1]
+  const void* const* W;  // [ntypes][nfit] device pointers (row major [in][out])
+  const void* const* b;  // [ntypes][nfit]
+  const void* const* wo; // [ntypes]
+  const double* bo;      // [ntypes] device
+  void *D, *Dg;        // [nrows][M*m2]
+  void* act;           // [nfit][nrows][fw]  tanh outputs
+  void* xs;            // [nfit][nrows][fw]  layer outputs
+  void *g0, *g1;       // [nrows][fw] gradient ping-pong
+  double* Ei;          // [nrows]
+};
+void launch_fit(const FitArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------------- reductions, MD
+void launch_zero(double* p, size_t n, hipStream_t st);
+void launch_frame_reduce(int nframes, const Frame* frames, const int* row_of, const double* Ei,
+                         const double* vir_rows, double* energies, double* virials,
+                         double* atom_energy, hipStream_t st);
+void launch_export_T(int prec, int n, int M, const int* row_of, const void* Tm, const void* gT,
+                     double* To, double* gTo, hipStream_t st);
+
+}  // namespace dp

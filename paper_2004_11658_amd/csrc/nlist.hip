@@ -1,0 +1,554 @@
+// Neighbour search and formatting on the GPU (paper Section 3.2.2, Alg. 1).
+//
+// Layout: the local atoms of all frames are followed by their periodic images
+// ("ghosts", Section 3.1: a ghost shell at least rc thick around each frame's box).
+// Every extended atom e has coordinates xe[e], owner index, species and image code.
+// A cell list over the extended region of each frame (cells at least rc wide in
+// perpendicular distance) limits the search to 27 cells; each local atom's
+// candidates within rc are then ranked by (species, r^2, owner, image) and written
+// into per-species blocks of fixed width sel with -1 pads (Alg. 1, Fig. 2a).
+//
+// Positions that decide integers (inside rc, neighbour order) are computed with
+// floating-point contraction off, in a fixed operation order:
+//   x_w = x - (m0 B0 + m1 B1) + m2 B2   (m = floor(x . B^-1)),
+//   ghost = x_w + (n0 B0 + n1 B1) + n2 B2,  d = ghost - x_w,i,  r^2 = (dx dx + dy dy) + dz dz.
+#include "common.h"
+#include "kernels.h"
+
+namespace dp {
+
+// ------------------------------------------------------------------------------------
+// device-wide exclusive scan of int vectors of width W (W counters per element)
+// ------------------------------------------------------------------------------------
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+template <int W>
+struct IV {
+  int v[W];
+};
+
+template <int W>
+__device__ __forceinline__ IV<W> iv_add(const IV<W>& a, const IV<W>& b) {
+  IV<W> c;
+#pragma unroll
+  for (int q = 0; q < W; q++) c.v[q] = a.v[q] + b.v[q];
+  return c;
+}
+
+// in: W ints per element produced by a loader; out: exclusive prefix (W ints per
+// element); sums: per-block totals.
+template <int W, class Load>
+__global__ __launch_bounds__(kScanBlock) void k_scan_up(int n, Load load, int* __restrict__ out,
+                                                       int* __restrict__ sums) {
+  __shared__ IV<W> sh[kScanBlock];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  IV<W> it[kScanItems];
+  IV<W> tot;
+#pragma unroll
+  for (int q = 0; q < W; q++) tot.v[q] = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; k++) {
+    int i = base + k;
+    IV<W> x;
+    if (i < n) x = load(i);
+    else {
+#pragma unroll
+      for (int q = 0; q < W; q++) x.v[q] = 0;
+    }
+    it[k] = tot;  // exclusive within thread
+    tot = iv_add<W>(tot, x);
+  }
+  sh[threadIdx.x] = tot;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of thread totals
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    IV<W> v = sh[threadIdx.x];
+    IV<W> add;
+    bool has = threadIdx.x >= off;
+    if (has) add = sh[threadIdx.x - off];
+    __syncthreads();
+    if (has) sh[threadIdx.x] = iv_add<W>(v, add);
+    __syncthreads();
+  }
+  IV<W> excl;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < W; q++) excl.v[q] = 0;
+  } else {
+    excl = sh[threadIdx.x - 1];
+  }
+#pragma unroll
+  for (int k = 0; k < kScanItems; k++) {
+    int i = base + k;
+    if (i < n) {
+      IV<W> v = iv_add<W>(excl, it[k]);
+#pragma unroll
+      for (int q = 0; q < W; q++) out[(size_t)i * W + q] = v.v[q];
+    }
+  }
+  if (threadIdx.x == kScanBlock - 1) {
+#pragma unroll
+    for (int q = 0; q < W; q++) sums[blockIdx.x * W + q] = sh[threadIdx.x].v[q];
+  }
+}
+
+// exclusive scan of nb block sums in place by a single block (looping over chunks);
+// total[W] receives the grand total.
+template <int W>
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int nb, int* __restrict__ sums,
+                                                         int* __restrict__ total) {
+  __shared__ IV<W> sh[kScanBlock];
+  IV<W> carry;
+#pragma unroll
+  for (int q = 0; q < W; q++) carry.v[q] = 0;
+  for (int c0 = 0; c0 < nb; c0 += kScanBlock) {
+    int i = c0 + threadIdx.x;
+    IV<W> x;
+#pragma unroll
+    for (int q = 0; q < W; q++) x.v[q] = i < nb ? sums[i * W + q] : 0;
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+      IV<W> v = sh[threadIdx.x];
+      IV<W> add;
+      bool has = threadIdx.x >= off;
+      if (has) add = sh[threadIdx.x - off];
+      __syncthreads();
+      if (has) sh[threadIdx.x] = iv_add<W>(v, add);
+      __syncthreads();
+    }
+    IV<W> incl = sh[threadIdx.x];
+    if (i < nb) {
+#pragma unroll
+      for (int q = 0; q < W; q++) sums[i * W + q] = carry.v[q] + incl.v[q] - x.v[q];
+    }
+    IV<W> last = sh[kScanBlock - 1];
+    __syncthreads();
+    carry = iv_add<W>(carry, last);
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < W; q++) total[q] = carry.v[q];
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(kScanBlock) void k_scan_add(int n, int* __restrict__ out,
+                                                        const int* __restrict__ sums) {
+  int i = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+#pragma unroll
+  for (int k = 0; k < kScanItems; k++) {
+    if (i + k < n) {
+#pragma unroll
+      for (int q = 0; q < W; q++) out[(size_t)(i + k) * W + q] += sums[blockIdx.x * W + q];
+    }
+  }
+}
+
+struct LoadInt {
+  const int* p;
+  __device__ IV<1> operator()(int i) const { IV<1> r; r.v[0] = p[i]; return r; }
+};
+
+template <int W>
+struct LoadTypeOneHot {
+  const int* types;
+  int ntypes;
+  __device__ IV<W> operator()(int i) const {
+    IV<W> r;
+    int t = types[i];
+#pragma unroll
+    for (int q = 0; q < W; q++) r.v[q] = (q == t) ? 1 : 0;
+    return r;
+  }
+};
+
+// scan scratch: sums[nblocks * W]
+template <int W, class Load>
+static void scan_launch(int n, Load load, int* out, int* sums, int* total, hipStream_t st) {
+  int nb = (n + kScanTile - 1) / kScanTile;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL((k_scan_up<W, Load>), dim3(nb), dim3(kScanBlock), 0, st, n, load, out, sums);
+  hipLaunchKernelGGL((k_scan_sums<W>), dim3(1), dim3(kScanBlock), 0, st, nb, sums, total);
+  hipLaunchKernelGGL((k_scan_add<W>), dim3(nb), dim3(kScanBlock), 0, st, n, out, sums);
+}
+
+size_t scan_sums_ints(int n, int W) {
+  int nb = (n + kScanTile - 1) / kScanTile;
+  if (nb < 1) nb = 1;
+  return (size_t)nb * W;
+}
+
+// ------------------------------------------------------------------------------------
+// position arithmetic with contraction off
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ void frac_of(const Frame& F, const double x[3], double f[3]) {
+#pragma clang fp contract(off)
+  for (int k = 0; k < 3; k++) f[k] = (x[0] * F.Bi[0 + k] + x[1] * F.Bi[3 + k]) + x[2] * F.Bi[6 + k];
+}
+
+__device__ __forceinline__ void shift_of(const Frame& F, int n0, int n1, int n2, double s[3]) {
+#pragma clang fp contract(off)
+  for (int c = 0; c < 3; c++)
+    s[c] = ((double)n0 * F.B[0 + c] + (double)n1 * F.B[3 + c]) + (double)n2 * F.B[6 + c];
+}
+
+__device__ __forceinline__ bool in_shell(const Frame& F, const double fw[3], int n0, int n1, int n2) {
+  double a = fw[0] + n0, b = fw[1] + n1, c = fw[2] + n2;
+  return a >= -F.g[0] && a < 1.0 + F.g[0] && b >= -F.g[1] && b < 1.0 + F.g[1] && c >= -F.g[2] &&
+         c < 1.0 + F.g[2];
+}
+
+__device__ __forceinline__ int cell_of(const Frame& F, const double f[3]) {
+  int c[3];
+  for (int k = 0; k < 3; k++) {
+    int v = (int)floor((f[k] + F.g[k]) / F.cw[k]);
+    c[k] = v < 0 ? 0 : (v >= F.nc[k] ? F.nc[k] - 1 : v);
+  }
+  return F.cell0 + (c[0] * F.nc[1] + c[1]) * F.nc[2] + c[2];
+}
+
+__device__ __forceinline__ int find_frame(const Frame* __restrict__ fr, int nframes, int i) {
+  int lo = 0, hi = nframes - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (fr[mid].atom0 <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------------------------
+// 1. wrap local atoms, validate, count their ghost images
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_wrap(int n, int nframes, const Frame* __restrict__ frames,
+                                              int ntypes, const double* __restrict__ x,
+                                              const int* __restrict__ types,
+                                              int* __restrict__ frame_of,
+                                              double* __restrict__ xw, double* __restrict__ fw,
+                                              int* __restrict__ gcount, int* __restrict__ status) {
+#pragma clang fp contract(off)
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int fi = find_frame(frames, nframes, i);
+  frame_of[i] = fi;
+  const Frame& F = frames[fi];
+  double xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+  int t = types[i];
+  int bad = 0;
+  if (t < 0 || t >= ntypes) bad |= ST_BAD_TYPE;
+  if (!isfinite(xi[0]) || !isfinite(xi[1]) || !isfinite(xi[2])) bad |= ST_NONFINITE;
+  if (bad) {
+    atomicOr(&status[STW_FLAGS], bad);
+    xi[0] = xi[1] = xi[2] = 0.0;
+  }
+  double f[3], s[3], w[3], ff[3];
+  frac_of(F, xi, f);
+  shift_of(F, (int)floor(f[0]), (int)floor(f[1]), (int)floor(f[2]), s);
+  for (int c = 0; c < 3; c++) w[c] = xi[c] - s[c];
+  frac_of(F, w, ff);
+  for (int c = 0; c < 3; c++) {
+    xw[3 * i + c] = w[c];
+    fw[3 * i + c] = ff[c];
+  }
+  int cnt = 0;
+  for (int a = -F.Kg[0]; a <= F.Kg[0]; a++)
+    for (int b = -F.Kg[1]; b <= F.Kg[1]; b++)
+      for (int c = -F.Kg[2]; c <= F.Kg[2]; c++)
+        if ((a | b | c) != 0 && in_shell(F, ff, a, b, c)) cnt++;
+  gcount[i] = cnt;
+}
+
+// ------------------------------------------------------------------------------------
+// 2. write the extended arrays (locals then ghosts) and count cell occupancy
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ghost_emit(
+    int n, int ntypes, int ghost_cap, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
+    const int* __restrict__ types, const double* __restrict__ xw, const double* __restrict__ fw,
+    const int* __restrict__ goff, const int* __restrict__ gtotal, double* __restrict__ xe,
+    int* __restrict__ eown, int* __restrict__ eimg, int* __restrict__ etype,
+    int* __restrict__ ecell, int* __restrict__ cell_count, int* __restrict__ status) {
+#pragma clang fp contract(off)
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (i == 0 && gtotal[0] > ghost_cap) {
+    atomicOr(&status[STW_FLAGS], ST_GHOST_CAP);
+    atomicMax(&status[STW_GHOSTS], gtotal[0]);
+  }
+  const Frame& F = frames[frame_of[i]];
+  double w[3] = {xw[3 * i], xw[3 * i + 1], xw[3 * i + 2]};
+  double f[3] = {fw[3 * i], fw[3 * i + 1], fw[3 * i + 2]};
+  int t = types[i];
+  if (t < 0 || t >= ntypes) t = 0;  // already flagged as an error by k_wrap
+  for (int c = 0; c < 3; c++) xe[3 * i + c] = w[c];
+  eown[i] = i;
+  eimg[i] = ((F.K[0]) * (2 * F.K[1] + 1) + F.K[1]) * (2 * F.K[2] + 1) + F.K[2];
+  etype[i] = t;
+  int cl = cell_of(F, f);
+  ecell[i] = cl;
+  atomicAdd(&cell_count[cl], 1);
+  int q = goff[i];
+  for (int a = -F.Kg[0]; a <= F.Kg[0]; a++)
+    for (int b = -F.Kg[1]; b <= F.Kg[1]; b++)
+      for (int c = -F.Kg[2]; c <= F.Kg[2]; c++) {
+        if ((a | b | c) == 0 || !in_shell(F, f, a, b, c)) continue;
+        if (q < ghost_cap) {
+          int e = n + q;
+          double s[3];
+          shift_of(F, a, b, c, s);
+          for (int k = 0; k < 3; k++) xe[3 * e + k] = w[k] + s[k];
+          eown[e] = i;
+          bool codeok = a >= -F.K[0] && a <= F.K[0] && b >= -F.K[1] && b <= F.K[1] &&
+                        c >= -F.K[2] && c <= F.K[2];
+          eimg[e] = codeok ? ((a + F.K[0]) * (2 * F.K[1] + 1) + (b + F.K[1])) * (2 * F.K[2] + 1) +
+                                 (c + F.K[2])
+                           : -1;
+          etype[e] = t;
+          double fg[3] = {f[0] + a, f[1] + b, f[2] + c};
+          int cg = cell_of(F, fg);
+          ecell[e] = cg;
+          atomicAdd(&cell_count[cg], 1);
+        }
+        q++;
+      }
+}
+
+__global__ __launch_bounds__(256) void k_cell_place(int ne_cap, const int* __restrict__ n_ext,
+                                                    const int* __restrict__ ecell,
+                                                    const int* __restrict__ cell_start,
+                                                    int* __restrict__ cell_fill,
+                                                    int* __restrict__ cell_atoms) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne_cap || e >= n_ext[0]) return;
+  int c = ecell[e];
+  int p = atomicAdd(&cell_fill[c], 1);
+  cell_atoms[cell_start[c] + p] = e;
+}
+
+__global__ void k_ext_count(int n, int ghost_cap, const int* __restrict__ gtotal,
+                            int* __restrict__ n_ext) {
+  int g = gtotal[0];
+  n_ext[0] = n + (g < ghost_cap ? g : ghost_cap);
+}
+
+// ------------------------------------------------------------------------------------
+// 3. formatted neighbour list: one wave per local atom
+// ------------------------------------------------------------------------------------
+constexpr int kNlWaves = 4;
+
+__global__ __launch_bounds__(64 * kNlWaves) void k_nlist(
+    int n, ModelC m, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
+    const double* __restrict__ xe, const int* __restrict__ eown, const int* __restrict__ eimg,
+    const int* __restrict__ etype, const int* __restrict__ ecell,
+    const int* __restrict__ cell_start, const int* __restrict__ cell_atoms,
+    int* __restrict__ nlist, int* __restrict__ nnei, int* __restrict__ status) {
+#pragma clang fp contract(off)
+  __shared__ double s_r2[kNlWaves][kMaxCand];
+  __shared__ unsigned long long s_key[kNlWaves][kMaxCand];
+  __shared__ int s_e[kNlWaves][kMaxCand];
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kNlWaves + wv;
+  if (i >= n) return;
+  const Frame& F = frames[frame_of[i]];
+  const double xi0 = xe[3 * i], xi1 = xe[3 * i + 1], xi2 = xe[3 * i + 2];
+  int ci = ecell[i] - F.cell0;
+  int c2 = ci % F.nc[2], c1 = (ci / F.nc[2]) % F.nc[1], c0 = ci / (F.nc[2] * F.nc[1]);
+  int ncand = 0;
+  int too_close = 0;
+  for (int a = c0 - 1; a <= c0 + 1; a++) {
+    if (a < 0 || a >= F.nc[0]) continue;
+    for (int b = c1 - 1; b <= c1 + 1; b++) {
+      if (b < 0 || b >= F.nc[1]) continue;
+      for (int c = c2 - 1; c <= c2 + 1; c++) {
+        if (c < 0 || c >= F.nc[2]) continue;
+        int cell = F.cell0 + (a * F.nc[1] + b) * F.nc[2] + c;
+        int beg = cell_start[cell], end = cell_start[cell + 1];
+        for (int p0 = beg; p0 < end; p0 += 64) {
+          int p = p0 + lane;
+          bool keep = false;
+          double r2 = 0.0;
+          int e = -1;
+          if (p < end) {
+            e = cell_atoms[p];
+            double d0 = xe[3 * e] - xi0, d1 = xe[3 * e + 1] - xi1, d2 = xe[3 * e + 2] - xi2;
+            r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+            keep = (r2 < m.rc2) && (e != i);
+            if (keep && r2 < 1e-12) too_close = 1;
+          }
+          unsigned long long bal = __ballot(keep);
+          int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
+          if (keep && pos < kMaxCand) {
+            int own = eown[e];
+            s_r2[wv][pos] = r2;
+            s_key[wv][pos] = ((unsigned long long)etype[e] << 56) |
+                             ((unsigned long long)(own - F.atom0) * (unsigned)F.nimg +
+                              (unsigned)eimg[e]);
+            s_e[wv][pos] = e;
+          }
+          ncand += __popcll(bal);
+        }
+      }
+    }
+  }
+  if (too_close) atomicOr(&status[STW_FLAGS], ST_OVERLAP);
+  if (ncand > kMaxCand) {
+    if (lane == 0) {
+      atomicOr(&status[STW_FLAGS], ST_CAPACITY);
+      atomicMax(&status[STW_MAX_CAND], ncand);
+    }
+    ncand = kMaxCand;
+  }
+  // the LDS rows are private to this wave: order its writes before its reads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // per-type counts
+  int tcnt[kMaxTypes];
+#pragma unroll
+  for (int t = 0; t < kMaxTypes; t++) tcnt[t] = 0;
+  for (int q = lane; q < ncand; q += 64) {
+    int ty = (int)(s_key[wv][q] >> 56);
+#pragma unroll
+    for (int t = 0; t < kMaxTypes; t++) tcnt[t] += (ty == t);
+  }
+#pragma unroll
+  for (int t = 0; t < kMaxTypes; t++) {
+    int v = tcnt[t];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    tcnt[t] = v;
+  }
+  // rank sort: position of each candidate in (type, r2, owner, image) order within
+  // its species block
+  int* nl = nlist + (size_t)i * m.nm;
+  int ovf = 0;
+  for (int q = lane; q < ncand; q += 64) {
+    double r2 = s_r2[wv][q];
+    unsigned long long key = s_key[wv][q];
+    unsigned t = (unsigned)(key >> 56);
+    int rank = 0;
+    for (int u = 0; u < ncand; u++) {
+      unsigned long long k2 = s_key[wv][u];
+      double r2u = s_r2[wv][u];
+      rank += ((unsigned)(k2 >> 56) == t) && ((r2u < r2) || (r2u == r2 && k2 < key));
+    }
+    if (rank < m.sel[t]) nl[m.sel_off[t] + rank] = s_e[wv][q];
+    else ovf = 1;
+  }
+  // pads
+  for (int k = lane; k < m.nm; k += 64) {
+    int t = 0;
+    while (t + 1 < m.ntypes && k >= m.sel_off[t + 1]) t++;
+    int pos = k - m.sel_off[t];
+    int cnt = 0;
+#pragma unroll
+    for (int u = 0; u < kMaxTypes; u++) cnt = (u == t) ? tcnt[u] : cnt;
+    int real = cnt < m.sel[t] ? cnt : m.sel[t];
+    if (pos >= real) nl[k] = -1;
+  }
+#pragma unroll
+  for (int t = 0; t < kMaxTypes; t++)
+    if (lane == t && t < m.ntypes)
+      nnei[(size_t)i * m.ntypes + t] = tcnt[t] < m.sel[t] ? tcnt[t] : m.sel[t];
+  unsigned long long anyovf = __ballot(ovf);
+  if (anyovf && lane == 0) {
+    atomicOr(&status[STW_FLAGS], ST_SEL_OVERFLOW);
+    atomicAdd(&status[STW_SEL_ROWS], 1);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// 4. species-grouped row order for the embedding / fitting kernels
+// ------------------------------------------------------------------------------------
+// rows: for each species t, its atoms in index order, padded to a multiple of kRowPad.
+__global__ void k_type_rows(int n, int ntypes, int W, const int* __restrict__ types,
+                            const int* __restrict__ tpos, const int* __restrict__ tcount,
+                            int* __restrict__ row_of, int* __restrict__ type_row0) {
+  // type_row0[t] = sum_{t'<t} roundup(count[t'], kRowPad); computed by every thread
+  int r0[kMaxTypes + 1];
+  r0[0] = 0;
+  for (int t = 0; t < ntypes; t++) r0[t + 1] = r0[t] + (tcount[t] + kRowPad - 1) / kRowPad * kRowPad;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0)
+    for (int t = 0; t <= ntypes; t++) type_row0[t] = r0[t];
+  if (i >= n) return;
+  int t = types[i];
+  if (t < 0 || t >= ntypes) t = 0;
+  row_of[i] = r0[t] + tpos[(size_t)i * W + t];
+}
+
+__global__ void k_fill_int(int n, int* __restrict__ p, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_row_atoms(int n, const int* __restrict__ row_of, int* __restrict__ row_atom) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) row_atom[row_of[i]] = i;
+}
+
+// debug export of the list as (frame-local owner index, image code)
+__global__ void k_nlist_export(int n, int nm, const int* __restrict__ nlist,
+                               const int* __restrict__ eown, const int* __restrict__ eimg,
+                               const int* __restrict__ frame_of, const Frame* __restrict__ frames,
+                               int* __restrict__ out_j, int* __restrict__ out_img) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n * nm) return;
+  int i = q / nm;
+  int e = nlist[q];
+  int a0 = frames[frame_of[i]].atom0;
+  out_j[q] = e < 0 ? -1 : eown[e] - a0;
+  if (out_img) out_img[q] = e < 0 ? -1 : eimg[e];
+}
+
+// ------------------------------------------------------------------------------------
+// host launch sequence
+// ------------------------------------------------------------------------------------
+void launch_nlist(const NlistArgs& A, hipStream_t st) {
+  const int n = A.n;
+  const int nb = (n + 255) / 256;
+  hipMemsetAsync(A.status, 0, sizeof(int) * STW_N, st);
+  hipMemsetAsync(A.cell_count, 0, sizeof(int) * (A.ncell + 1), st);
+  hipMemsetAsync(A.cell_fill, 0, sizeof(int) * A.ncell, st);
+  hipLaunchKernelGGL(k_wrap, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes, A.x,
+                     A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status);
+  scan_launch<1>(n, LoadInt{A.gcount}, A.goff, A.scan_sums, A.gtotal, st);
+  hipLaunchKernelGGL(k_ghost_emit, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, A.ghost_cap, A.frames, A.frame_of,
+                     A.types, A.xw, A.fw, A.goff, A.gtotal, A.xe, A.eown, A.eimg, A.etype, A.ecell,
+                     A.cell_count, A.status);
+  hipLaunchKernelGGL(k_ext_count, dim3(1), dim3(1), 0, st, n, A.ghost_cap, A.gtotal, A.n_ext);
+  scan_launch<1>(A.ncell + 1, LoadInt{A.cell_count}, A.cell_start, A.scan_sums, A.ctotal, st);
+  int ne_cap = n + A.ghost_cap;
+  hipLaunchKernelGGL(k_cell_place, dim3((ne_cap + 255) / 256), dim3(256), 0, st, ne_cap, A.n_ext,
+                     A.ecell, A.cell_start, A.cell_fill, A.cell_atoms);
+  hipLaunchKernelGGL(k_nlist, dim3((n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, n,
+                     A.m, A.frames, A.frame_of, A.xe, A.eown, A.eimg, A.etype, A.ecell,
+                     A.cell_start, A.cell_atoms, A.nlist, A.nnei, A.status);
+  // species-grouped rows
+  if (A.m.ntypes == 1) {
+    scan_launch<1>(n, LoadTypeOneHot<1>{A.types, 1}, A.tpos, A.scan_sums, A.tcount, st);
+  } else if (A.m.ntypes == 2) {
+    scan_launch<2>(n, LoadTypeOneHot<2>{A.types, 2}, A.tpos, A.scan_sums, A.tcount, st);
+  } else if (A.m.ntypes <= 4) {
+    scan_launch<4>(n, LoadTypeOneHot<4>{A.types, 4}, A.tpos, A.scan_sums, A.tcount, st);
+  } else {
+    scan_launch<8>(n, LoadTypeOneHot<8>{A.types, 8}, A.tpos, A.scan_sums, A.tcount, st);
+  }
+  int W = A.m.ntypes == 1 ? 1 : A.m.ntypes == 2 ? 2 : A.m.ntypes <= 4 ? 4 : 8;
+  hipLaunchKernelGGL(k_fill_int, dim3((A.nrows + 255) / 256), dim3(256), 0, st, A.nrows, A.row_atom, -1);
+  hipLaunchKernelGGL(k_type_rows, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, W, A.types, A.tpos,
+                     A.tcount, A.row_of, A.type_row0);
+  hipLaunchKernelGGL(k_row_atoms, dim3(nb), dim3(256), 0, st, n, A.row_of, A.row_atom);
+}
+
+void launch_nlist_export(int n, int nm, const int* nlist, const int* eown, const int* eimg,
+                         const int* frame_of, const Frame* frames, int* out_j, int* out_img,
+                         hipStream_t st) {
+  long tot = (long)n * nm;
+  hipLaunchKernelGGL(k_nlist_export, dim3((tot + 255) / 256), dim3(256), 0, st, n, nm, nlist, eown,
+                     eimg, frame_of, frames, out_j, out_img);
+}
+
+}  // namespace dp

@@ -1,0 +1,202 @@
+"""Thin Python binding of libdp.so (the C ABI in include/dp.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP stream;
+every step of the computation runs in the library's HIP kernels.  Importing this
+module raises if the library has not been built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdp.so")
+
+DP_OK = 0
+DP_WARN_SEL_OVERFLOW = 1
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
+
+
+class DPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libdp error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("reserved0", C.c_int32), ("skin", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libdp.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2004_11658_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, D, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    sig = {
+        "dp_init": ([C.c_char_p, P, P], C.c_int),
+        "dp_free": ([P], None),
+        "dp_model_info": ([P, P, P, P, P, P, P], C.c_int),
+        "dp_workspace_size": ([P, I32, P, P, P], C.c_int),
+        "dp_compute": ([P, I64, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
+        "dp_compute_batch": ([P, I32, P, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
+        "dp_nlist": ([P, I64, P, P, P, P, P, P, P, SZ, P], C.c_int),
+        "dp_descriptor": ([P, I64, P, P, P, P, P, P, SZ, P], C.c_int),
+        "dp_status": ([P, P, P, P, P], C.c_int),
+        "dp_strerror": ([C.c_int], C.c_char_p),
+        "dp_last_error": ([P], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _box9(box) -> np.ndarray:
+    b = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(-1, 9))
+    return b
+
+
+class DPModel:
+    """A DP-SE model on the current HIP device."""
+
+    def __init__(self, model_path: str, precision: str = "fp64", skin: float = 0.0):
+        opt = _Options(PRECISIONS[precision], 0, float(skin))
+        h = C.c_void_p()
+        rc = _lib.dp_init(model_path.encode(), C.byref(opt), C.byref(h))
+        if rc != DP_OK:
+            raise DPError(rc, _lib.dp_last_error(None).decode())
+        self.h = h
+        self.precision = precision
+        nt, nm, M, m2 = (C.c_int32() for _ in range(4))
+        rcut, npar = C.c_double(), C.c_int64()
+        _lib.dp_model_info(h, C.byref(nt), C.byref(nm), C.byref(M), C.byref(m2), C.byref(rcut),
+                           C.byref(npar))
+        self.ntypes, self.nm, self.M, self.m2 = nt.value, nm.value, M.value, m2.value
+        self.rc, self.nparams = rcut.value, npar.value
+        self._ws = None
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            _lib.dp_free(h)
+            self.h = None
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, rc: int):
+        if rc < 0:
+            raise DPError(rc, _lib.dp_last_error(self.h).decode())
+        return rc
+
+    def workspace(self, offsets: np.ndarray, boxes: np.ndarray) -> torch.Tensor:
+        nb = C.c_size_t()
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        boxes = _box9(boxes)
+        self._check(_lib.dp_workspace_size(self.h, len(offsets) - 1, offsets.ctypes.data_as(C.c_void_p),
+                                           boxes.ctypes.data_as(C.c_void_p), C.byref(nb)))
+        if self._ws is None or self._ws.numel() < nb.value:
+            self._ws = torch.empty(int(nb.value * 1.1) + 4096, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def status(self) -> int:
+        flags, det = C.c_int32(), C.c_int64()
+        rc = _lib.dp_status(self.h, _ptr(self._ws), _stream(), C.byref(flags), C.byref(det))
+        self._check(rc)
+        return rc
+
+    @staticmethod
+    def _dev(x, dtype):
+        t = torch.as_tensor(x)
+        if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous():
+            t = t.to(device="cuda", dtype=dtype).contiguous()
+        return t
+
+    # ------------------------------------------------------------------ compute
+    def compute(self, coords, types, box, atom_energy: bool = False, check: bool = True):
+        """E [1], F [N][3], W [3][3] (and E_i [N]) of one frame; device tensors."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        n = x.shape[0]
+        b = _box9(box)
+        ws = self.workspace(np.array([0, n]), b)
+        E = torch.empty(1, dtype=torch.float64, device=x.device)
+        F = torch.empty(n, 3, dtype=torch.float64, device=x.device)
+        W = torch.empty(9, dtype=torch.float64, device=x.device)
+        Ei = torch.empty(n, dtype=torch.float64, device=x.device) if atom_energy else None
+        self._check(_lib.dp_compute(self.h, n, _ptr(x), _ptr(t), b.ctypes.data_as(C.c_void_p), _ptr(E),
+                                    _ptr(F), _ptr(W), _ptr(Ei), _ptr(ws), ws.numel(), _stream()))
+        if check:
+            self.status()
+        return (E, F, W.view(3, 3), Ei) if atom_energy else (E, F, W.view(3, 3))
+
+    def compute_batch(self, coords, types, offsets: Sequence[int], boxes, atom_energy: bool = False,
+                      check: bool = True):
+        """Energies [nf], forces [N][3], virials [nf][3][3] of a ragged batch."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        nf = len(off) - 1
+        b = _box9(boxes)
+        assert b.shape[0] == nf and off[-1] == x.shape[0]
+        ws = self.workspace(off, b)
+        E = torch.empty(nf, dtype=torch.float64, device=x.device)
+        F = torch.empty(x.shape[0], 3, dtype=torch.float64, device=x.device)
+        W = torch.empty(nf, 9, dtype=torch.float64, device=x.device)
+        Ei = torch.empty(x.shape[0], dtype=torch.float64, device=x.device) if atom_energy else None
+        self._check(_lib.dp_compute_batch(self.h, nf, off.ctypes.data_as(C.c_void_p), _ptr(x), _ptr(t),
+                                          b.ctypes.data_as(C.c_void_p), _ptr(E), _ptr(F), _ptr(W),
+                                          _ptr(Ei), _ptr(ws), ws.numel(), _stream()))
+        if check:
+            self.status()
+        return (E, F, W.view(nf, 3, 3), Ei) if atom_energy else (E, F, W.view(nf, 3, 3))
+
+    def nlist(self, coords, types, box, check: bool = True):
+        """Formatted neighbour list (owner index, image code) and per-type counts."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        n = x.shape[0]
+        b = _box9(box)
+        ws = self.workspace(np.array([0, n]), b)
+        nl = torch.empty(n, self.nm, dtype=torch.int32, device=x.device)
+        img = torch.empty(n, self.nm, dtype=torch.int32, device=x.device)
+        nn = torch.empty(n, self.ntypes, dtype=torch.int32, device=x.device)
+        self._check(_lib.dp_nlist(self.h, n, _ptr(x), _ptr(t), b.ctypes.data_as(C.c_void_p), _ptr(nl),
+                                  _ptr(img), _ptr(nn), _ptr(ws), ws.numel(), _stream()))
+        rc = self.status() if check else 0
+        return nl, img, nn, rc
+
+    def descriptor(self, coords, types, box, check: bool = True):
+        """T = G^T R / N_m and dE/dT per atom, [N][M][4] doubles."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        n = x.shape[0]
+        b = _box9(box)
+        ws = self.workspace(np.array([0, n]), b)
+        T = torch.empty(n, self.M, 4, dtype=torch.float64, device=x.device)
+        gT = torch.empty(n, self.M, 4, dtype=torch.float64, device=x.device)
+        self._check(_lib.dp_descriptor(self.h, n, _ptr(x), _ptr(t), b.ctypes.data_as(C.c_void_p),
+                                       _ptr(T), _ptr(gT), _ptr(ws), ws.numel(), _stream()))
+        if check:
+            self.status()
+        return T, gT

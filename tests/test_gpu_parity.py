@@ -1,0 +1,94 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Bars: neighbour lists bit-exact (integer work); FP64 energies within 1e-10 relative and
+forces within 1e-9 relative (normwise: max_i |dF_i| / max_i |F_i|), virial 1e-9 relative;
+descriptor intermediates T and dE/dT within 1e-12 relative (normwise) - these are sums of
+O(100) FP64 terms, so the expected error is ~100 ulp of the largest entry.
+"""
+import numpy as np
+import pytest
+
+from paper_2004_11658_amd import inputs as I
+from oracle.oracle import Oracle, set_threads
+from conftest import TINY, model_file, tiny_water
+
+pytestmark = pytest.mark.gpu
+set_threads(8)
+
+
+@pytest.fixture(scope="module")
+def dp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_11658_amd import dp as D
+    return D
+
+
+def _cases():
+    c1, t1, b1 = tiny_water(11, 2, 6.3)
+    c2, t2, b2 = I.water_lattice(1, 3.2, 5)
+    c3, t3, b3 = tiny_water(12, 2, 6.6)
+    tric = np.array([[6.6, 0.0, 0.0], [1.3, 6.4, 0.0], [-0.9, 0.7, 6.5]])
+    c3 = c3 @ np.linalg.inv(b3) @ tric
+    return {"two_images": (c1, t1, b1), "self_images": (c2, t2, b2), "triclinic": (c3, t3, tric)}
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _frel(F, Fo):
+    return np.linalg.norm(F - Fo, axis=1).max() / np.linalg.norm(Fo, axis=1).max()
+
+
+@pytest.mark.parametrize("case", ["two_images", "self_images", "triclinic"])
+def test_nlist_small_boxes_bit_exact(dp, tiny_model, case):
+    c, t, b = _cases()[case]
+    print("case", case, len(t), flush=True)
+    m = dp.DPModel(tiny_model)
+    nl, img, nn, rc = m.nlist(c, t, b)
+    o = Oracle(tiny_model)
+    onl, oimg, onn, ovf = o.nlist(c, t, b)
+    assert np.array_equal(nl.cpu().numpy(), onl)
+    assert np.array_equal(img.cpu().numpy(), oimg)
+    assert np.array_equal(nn.cpu().numpy(), onn)
+    assert (rc == 1) == ovf
+
+
+def test_nlist_water192_bit_exact(dp, water_model, water192):
+    c, t, b = water192
+    m = dp.DPModel(water_model)
+    nl, img, nn, rc = m.nlist(c, t, b)
+    onl, oimg, onn, _ = Oracle(water_model).nlist(c, t, b)
+    assert rc == 0
+    assert np.array_equal(nl.cpu().numpy(), onl)
+    assert np.array_equal(img.cpu().numpy(), oimg)
+    assert np.array_equal(nn.cpu().numpy(), onn)
+
+
+def test_descriptor_water192(dp, water_model, water192):
+    c, t, b = water192
+    m = dp.DPModel(water_model)
+    T, gT = m.descriptor(c, t, b)
+    r = Oracle(water_model).eval(c, t, b, dumps=True)
+    assert _rel(T.cpu().numpy(), r["T"]) < 1e-12
+    assert _rel(gT.cpu().numpy(), r["gT"]) < 1e-11
+
+
+@pytest.mark.parametrize("which", ["water192", "tiny_two_images", "tiny_self_images", "tiny_triclinic"])
+def test_energy_forces_virial_fp64(dp, water_model, tiny_model, water192, which):
+    if which == "water192":
+        path, (c, t, b) = water_model, water192
+    else:
+        path, (c, t, b) = tiny_model, _cases()[which[5:]]
+    print("case", which, flush=True)
+    m = dp.DPModel(path)
+    E, F, W, Ei = m.compute(c, t, b, atom_energy=True)
+    r = Oracle(path).eval(c, t, b)
+    E = float(E.cpu()[0])
+    assert abs(E - r["E"]) <= 1e-10 * abs(r["E"])
+    assert _frel(F.cpu().numpy(), r["F"]) < 1e-9
+    assert _rel(W.cpu().numpy(), r["W"]) < 1e-9
+    assert _rel(Ei.cpu().numpy(), r["Ei"]) < 1e-10
