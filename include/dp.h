@@ -120,6 +120,31 @@ int dp_descriptor(dp_handle h, int64_t natoms, const double* coords, const int32
                   const double* box, double* T, double* gT, void* workspace,
                   size_t ws_bytes, void* stream);
 
+/* Velocity-Verlet molecular dynamics of one frame (paper Section 4), nsteps steps of
+ * dt_fs femtoseconds with a fresh force evaluation per step:
+ *   v += dt/2 F/m;  x += dt v;  F = F(x);  v += dt/2 F/m
+ * x [natoms][3] and v [natoms][3] (A/fs) are device arrays updated in place (x is not
+ * wrapped into the box); masses [ntypes] host (amu).  thermo (device, may be NULL)
+ * receives rows [step, E_pot, E_kin, T(K), E_tot, P(bar)] at step 0 and every
+ * thermo_every steps: 1 + nsteps / thermo_every rows of 6 doubles.  forces [natoms][3]
+ * (device, may be NULL) receives the forces of the final positions.  The workspace is
+ * the one dp_workspace_size reports for this frame. */
+int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* types,
+              const double* masses, const double* box, double dt_fs, int32_t nsteps,
+              int32_t thermo_every, double* thermo, double* forces, void* workspace,
+              size_t ws_bytes, void* stream);
+
+/* Stage timing with HIP events recorded on the call's stream around each stage
+ * (neighbour list, embedding forward, fitting net, embedding adjoint, reductions,
+ * integration).  dp_profile(h, 1) clears the records and enables timing,
+ * dp_profile(h, 0) stops recording and keeps the records for dp_profile_read.
+ * dp_profile_read synchronises the events and returns the summed milliseconds and the
+ * number of launches of one stage (DP_STAGE_*). */
+enum { DP_STAGE_NLIST = 0, DP_STAGE_EMBED_FWD = 1, DP_STAGE_FIT = 2, DP_STAGE_EMBED_BWD = 3,
+       DP_STAGE_REDUCE = 4, DP_STAGE_MD = 5, DP_NSTAGES = 6 };
+int dp_profile(dp_handle h, int32_t enable);
+int dp_profile_read(dp_handle h, int32_t stage, double* total_ms, int64_t* launches);
+
 /* Synchronise stream and read the status word of the last call that used workspace.
  * flags (may be NULL) receives the raw flag bits; detail (may be NULL) the count
  * attached to the first condition.  Returns DP_OK, DP_WARN_SEL_OVERFLOW or a

@@ -31,12 +31,49 @@ struct dp_handle_s {
   void* d_fit = nullptr;           // fitting weights (storage type)
   double* d_bo = nullptr;          // output biases [ntypes]
   void** d_ptrs = nullptr;         // device pointer tables for the fitting kernel
-  // pinned staging for per-call frame tables
-  Frame* h_frames = nullptr;
-  int h_frames_cap = 0;
-  hipEvent_t frames_done = nullptr;
-  bool frames_pending = false;
+  // pinned staging for per-call frame tables: a ring of slots, each reused only
+  // after the copy that last read it has completed
+  static constexpr int kSlots = 8;
+  Frame* h_frames[kSlots] = {};
+  int h_frames_cap[kSlots] = {};
+  hipEvent_t frames_done[kSlots] = {};
+  bool frames_pending[kSlots] = {};
+  int slot = 0;
+  // stage timing
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_pool;
+  size_t prof_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_rec;
   std::string err;
+};
+
+static hipEvent_t prof_event(dp_handle h) {
+  if (h->prof_used == h->prof_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->prof_pool.push_back(e);
+  }
+  return h->prof_pool[h->prof_used++];
+}
+
+// records an event pair around a stage when timing is enabled
+struct StageTimer {
+  dp_handle h;
+  int stage;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr;
+  StageTimer(dp_handle h_, int stage_, hipStream_t st_) : h(h_), stage(stage_), st(st_) {
+    if (h->prof_on && (e0 = prof_event(h))) (void)hipEventRecord(e0, st);
+  }
+  ~StageTimer() {
+    if (h->prof_on && e0) {
+      hipEvent_t e1 = prof_event(h);
+      if (e1) {
+        (void)hipEventRecord(e1, st);
+        h->prof_rec.push_back({stage, {e0, e1}});
+      }
+    }
+  }
 };
 
 static thread_local std::string g_init_err;
@@ -306,7 +343,7 @@ struct Plan {
   size_t o_status, o_frames, o_frame_of, o_xw, o_fw, o_gcount, o_goff, o_small, o_scan;
   size_t o_xe, o_eown, o_eimg, o_etype, o_ecell, o_ccount, o_cstart, o_cfill, o_catoms;
   size_t o_nlist, o_nnei, o_tpos, o_rowof, o_rowatom, o_T, o_gT, o_D, o_Dg, o_act, o_xs, o_g0,
-      o_g1, o_Ei, o_vir, o_tmpj, o_tmpi;
+      o_g1, o_Ei, o_vir, o_tmpj, o_tmpi, o_mdF, o_mdE, o_mdW;
   int n, nframes, ncell, ghost_cap, nrows;
 };
 
@@ -386,6 +423,9 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
   P.o_vir = take(sizeof(double) * rows * 9);
   P.o_tmpj = take(sizeof(double) * nframes * 10);
   P.o_tmpi = take(sizeof(int) * 16);
+  P.o_mdF = take(sizeof(double) * 3 * n);
+  P.o_mdE = take(sizeof(double) * nframes);
+  P.o_mdW = take(sizeof(double) * 9 * nframes);
   P.total = o;
   return DP_OK;
 }
@@ -423,10 +463,10 @@ struct Ws {
   T* at(size_t off) const { return (T*)(base + off); }
 };
 
-// runs the neighbour stage; returns DP_OK or an error code
-static int stage_frames_and_nlist(dp_handle h, int nframes, const int64_t* off, const double* boxes,
-                                  const double* coords, const int32_t* types, void* ws,
-                                  size_t ws_bytes, hipStream_t st, Plan& P, NlistArgs& A) {
+// plans the call, validates the workspace and copies the frame table to the device
+static int stage_frames(dp_handle h, int nframes, const int64_t* off, const double* boxes,
+                        const double* coords, const int32_t* types, void* ws, size_t ws_bytes,
+                        hipStream_t st, Plan& P, NlistArgs& A) {
   std::vector<Frame> frames;
   int rc = make_plan(h, nframes, off, boxes, &frames, P);
   if (rc != DP_OK) return rc;
@@ -434,23 +474,25 @@ static int stage_frames_and_nlist(dp_handle h, int nframes, const int64_t* off, 
     return fail(h, DP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(P.total) + " bytes");
   if (!coords || !types) return fail(h, DP_ERR_ARG, "null coordinates or types");
   HIPCHECK(h, hipSetDevice(h->device));
-  // pinned staging of the frame table (previous copy must have completed)
-  if (h->frames_pending) {
-    HIPCHECK(h, hipEventSynchronize(h->frames_done));
-    h->frames_pending = false;
+  int s = h->slot;
+  h->slot = (h->slot + 1) % dp_handle_s::kSlots;
+  if (h->frames_pending[s]) {
+    HIPCHECK(h, hipEventSynchronize(h->frames_done[s]));
+    h->frames_pending[s] = false;
   }
-  if (h->h_frames_cap < nframes) {
-    if (h->h_frames) (void)hipHostFree(h->h_frames);
-    h->h_frames = nullptr;
-    HIPCHECK(h, hipHostMalloc((void**)&h->h_frames, sizeof(Frame) * nframes, 0));
-    h->h_frames_cap = nframes;
+  if (!h->frames_done[s]) HIPCHECK(h, hipEventCreateWithFlags(&h->frames_done[s], hipEventDisableTiming));
+  if (h->h_frames_cap[s] < nframes) {
+    if (h->h_frames[s]) (void)hipHostFree(h->h_frames[s]);
+    h->h_frames[s] = nullptr;
+    HIPCHECK(h, hipHostMalloc((void**)&h->h_frames[s], sizeof(Frame) * nframes, 0));
+    h->h_frames_cap[s] = nframes;
   }
-  memcpy(h->h_frames, frames.data(), sizeof(Frame) * nframes);
+  memcpy(h->h_frames[s], frames.data(), sizeof(Frame) * nframes);
   Ws W{(char*)ws, &P};
-  HIPCHECK(h, hipMemcpyAsync(W.at<Frame>(P.o_frames), h->h_frames, sizeof(Frame) * nframes,
+  HIPCHECK(h, hipMemcpyAsync(W.at<Frame>(P.o_frames), h->h_frames[s], sizeof(Frame) * nframes,
                              hipMemcpyHostToDevice, st));
-  HIPCHECK(h, hipEventRecord(h->frames_done, st));
-  h->frames_pending = true;
+  HIPCHECK(h, hipEventRecord(h->frames_done[s], st));
+  h->frames_pending[s] = true;
   A.n = P.n;
   A.nframes = nframes;
   A.ncell = P.ncell;
@@ -487,9 +529,22 @@ static int stage_frames_and_nlist(dp_handle h, int nframes, const int64_t* off, 
   A.tpos = W.at<int>(P.o_tpos);
   A.row_of = W.at<int>(P.o_rowof);
   A.row_atom = W.at<int>(P.o_rowatom);
+  return DP_OK;
+}
+
+static int stage_nlist(dp_handle h, const NlistArgs& A, hipStream_t st) {
+  StageTimer tm(h, DP_STAGE_NLIST, st);
   launch_nlist(A, st);
   HIPCHECK(h, hipGetLastError());
   return DP_OK;
+}
+
+static int stage_frames_and_nlist(dp_handle h, int nframes, const int64_t* off, const double* boxes,
+                                  const double* coords, const int32_t* types, void* ws,
+                                  size_t ws_bytes, hipStream_t st, Plan& P, NlistArgs& A) {
+  int rc = stage_frames(h, nframes, off, boxes, coords, types, ws, ws_bytes, st, P, A);
+  if (rc != DP_OK) return rc;
+  return stage_nlist(h, A, st);
 }
 
 static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, hipStream_t st,
@@ -514,7 +569,10 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
   E.vir_part = W.at<double>(P.o_vir);
   E.frame_of = A.frame_of;
   E.nframes = P.nframes;
-  launch_embed_fwd(E, st);
+  {
+    StageTimer tm(h, DP_STAGE_EMBED_FWD, st);
+    launch_embed_fwd(E, st);
+  }
   HIPCHECK(h, hipGetLastError());
   FitArgs F{};
   F.prec = h->opt.precision;
@@ -538,7 +596,10 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
   F.g0 = W.at<void>(P.o_g0);
   F.g1 = W.at<void>(P.o_g1);
   F.Ei = W.at<double>(P.o_Ei);
-  launch_fit(F, st);
+  {
+    StageTimer tm(h, DP_STAGE_FIT, st);
+    launch_fit(F, st);
+  }
   HIPCHECK(h, hipGetLastError());
   if (T_out || gT_out) {
     launch_export_T(h->opt.precision, P.n, h->M, A.row_of, E.T, F.gT, T_out, gT_out, st);
@@ -546,11 +607,15 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
   }
   if (want_forces) {
     launch_zero(forces, (size_t)P.n * 3, st);
+    StageTimer tm(h, DP_STAGE_EMBED_BWD, st);
     launch_embed_bwd(E, st);
-    HIPCHECK(h, hipGetLastError());
   }
-  launch_frame_reduce(P.nframes, A.frames, A.row_of, F.Ei, want_forces ? E.vir_part : nullptr,
-                      energies, virials, atom_energy, st);
+  HIPCHECK(h, hipGetLastError());
+  {
+    StageTimer tm(h, DP_STAGE_REDUCE, st);
+    launch_frame_reduce(P.nframes, A.frames, A.row_of, F.Ei, want_forces ? E.vir_part : nullptr,
+                        energies, virials, atom_energy, st);
+  }
   HIPCHECK(h, hipGetLastError());
   return DP_OK;
 }
@@ -598,8 +663,6 @@ int dp_init(const char* model_path, const dp_options* opt, dp_handle* out) {
     return fail(nullptr, DP_ERR_HIP, "no HIP device");
   }
   rc = upload_weights(h);
-  if (rc == DP_OK && hipEventCreateWithFlags(&h->frames_done, hipEventDisableTiming) != hipSuccess)
-    rc = fail(h, DP_ERR_HIP, "hipEventCreate failed");
   if (rc != DP_OK) {
     g_init_err = h->err;
     release_weights(h);
@@ -612,10 +675,16 @@ int dp_init(const char* model_path, const dp_options* opt, dp_handle* out) {
 
 void dp_free(dp_handle h) {
   if (!h) return;
-  if (h->frames_pending) (void)hipEventSynchronize(h->frames_done);
+  for (int s = 0; s < dp_handle_s::kSlots; s++) {
+    if (h->frames_pending[s]) (void)hipEventSynchronize(h->frames_done[s]);
+    if (h->h_frames[s]) (void)hipHostFree(h->h_frames[s]);
+    if (h->frames_done[s]) (void)hipEventDestroy(h->frames_done[s]);
+  }
+  for (hipEvent_t e : h->prof_pool) {
+    (void)hipEventSynchronize(e);
+    (void)hipEventDestroy(e);
+  }
   release_weights(h);
-  if (h->h_frames) (void)hipHostFree(h->h_frames);
-  if (h->frames_done) (void)hipEventDestroy(h->frames_done);
   delete h;
 }
 
@@ -698,6 +767,90 @@ int dp_descriptor(dp_handle h, int64_t natoms, const double* coords, const int32
   Ws W{(char*)workspace, &P};
   double* e = W.at<double>(P.o_tmpj);
   return run_model(h, P, A, workspace, st, e, nullptr, nullptr, nullptr, false, T, gT);
+}
+
+int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* types,
+              const double* masses, const double* box, double dt_fs, int32_t nsteps,
+              int32_t thermo_every, double* thermo, double* forces, void* workspace,
+              size_t ws_bytes, void* stream) {
+  if (!h) return DP_ERR_ARG;
+  if (!x || !v || !types || !masses || !box) return fail(h, DP_ERR_ARG, "null argument");
+  if (nsteps < 0 || thermo_every < 0 || !(dt_fs > 0) || !std::isfinite(dt_fs))
+    return fail(h, DP_ERR_ARG, "bad step count or time step");
+  MDMass mm{};
+  for (int t = 0; t < h->ntypes; t++) {
+    if (!(masses[t] > 0) || !std::isfinite(masses[t])) return fail(h, DP_ERR_ARG, "masses must be > 0");
+    mm.m[t] = masses[t];
+    mm.inv[t] = 1.0 / masses[t];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int64_t off[2] = {0, natoms};
+  Plan P;
+  NlistArgs A{};
+  int rc = stage_frames(h, 1, off, box, x, types, workspace, ws_bytes, st, P, A);
+  if (rc != DP_OK) return rc;
+  Ws W{(char*)workspace, &P};
+  double* F = forces ? forces : W.at<double>(P.o_mdF);
+  double* E = W.at<double>(P.o_mdE);
+  double* Wv = W.at<double>(P.o_mdW);
+  const double* B = box;
+  double vol = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
+               B[2] * (B[3] * B[7] - B[4] * B[6]);
+  const int n = (int)natoms;
+  auto force = [&]() -> int {
+    int r = stage_nlist(h, A, st);
+    if (r != DP_OK) return r;
+    return run_model(h, P, A, workspace, st, E, F, Wv, nullptr, true, nullptr, nullptr);
+  };
+  rc = force();
+  if (rc != DP_OK) return rc;
+  int row = 0;
+  if (thermo) launch_thermo(n, types, mm, vol, 0, v, E, Wv, thermo + 6 * row++, st);
+  for (int s = 1; s <= nsteps; s++) {
+    {
+      StageTimer tm(h, DP_STAGE_MD, st);
+      launch_vv(n, types, mm, dt_fs, F, v, x, true, st);
+    }
+    rc = force();
+    if (rc != DP_OK) return rc;
+    {
+      StageTimer tm(h, DP_STAGE_MD, st);
+      launch_vv(n, types, mm, dt_fs, F, v, x, false, st);
+      if (thermo && thermo_every > 0 && s % thermo_every == 0)
+        launch_thermo(n, types, mm, vol, s, v, E, Wv, thermo + 6 * row++, st);
+    }
+  }
+  HIPCHECK(h, hipGetLastError());
+  return DP_OK;
+}
+
+int dp_profile(dp_handle h, int32_t enable) {
+  if (!h) return DP_ERR_ARG;
+  if (enable) {
+    // the pooled events are reused: wait for the ones still in flight
+    for (auto& r : h->prof_rec) (void)hipEventSynchronize(r.second.second);
+    h->prof_rec.clear();
+    h->prof_used = 0;
+  }
+  h->prof_on = enable != 0;
+  return DP_OK;
+}
+
+int dp_profile_read(dp_handle h, int32_t stage, double* total_ms, int64_t* launches) {
+  if (!h || stage < 0 || stage >= DP_NSTAGES) return DP_ERR_ARG;
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto& r : h->prof_rec) {
+    if (r.first != stage) continue;
+    HIPCHECK(h, hipEventSynchronize(r.second.second));
+    float ms = 0.f;
+    HIPCHECK(h, hipEventElapsedTime(&ms, r.second.first, r.second.second));
+    tot += ms;
+    cnt++;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  return DP_OK;
 }
 
 int dp_status(dp_handle h, const void* workspace, void* stream, int32_t* flags, int64_t* detail) {

@@ -101,4 +101,13 @@ void launch_frame_reduce(int nframes, const Frame* frames, const int* row_of, co
 void launch_export_T(int prec, int n, int M, const int* row_of, const void* Tm, const void* gT,
                      double* To, double* gTo, hipStream_t st);
 
+struct MDMass {
+  double m[kMaxTypes];
+  double inv[kMaxTypes];
+};
+void launch_vv(int n, const int* types, const MDMass& mass, double dt, const double* F, double* v,
+               double* x, bool drift, hipStream_t st);
+void launch_thermo(int n, const int* types, const MDMass& mass, double volume, int step,
+                   const double* v, const double* E, const double* W, double* row, hipStream_t st);
+
 }  // namespace dp

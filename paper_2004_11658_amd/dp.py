@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdp.so")
 DP_OK = 0
 DP_WARN_SEL_OVERFLOW = 1
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
+STAGES = {"nlist": 0, "embed_fwd": 1, "fit": 2, "embed_bwd": 3, "reduce": 4, "md": 5}
 
 
 class DPError(RuntimeError):
@@ -47,6 +48,9 @@ def _load():
         "dp_nlist": ([P, I64, P, P, P, P, P, P, P, SZ, P], C.c_int),
         "dp_descriptor": ([P, I64, P, P, P, P, P, P, SZ, P], C.c_int),
         "dp_status": ([P, P, P, P, P], C.c_int),
+        "dp_md_run": ([P, I64, P, P, P, P, P, D, I32, I32, P, P, P, SZ, P], C.c_int),
+        "dp_profile": ([P, I32], C.c_int),
+        "dp_profile_read": ([P, I32, P, P], C.c_int),
         "dp_strerror": ([C.c_int], C.c_char_p),
         "dp_last_error": ([P], C.c_char_p),
     }
@@ -200,3 +204,32 @@ class DPModel:
         if check:
             self.status()
         return T, gT
+
+    def md_run(self, x: torch.Tensor, v: torch.Tensor, types, masses, box, dt: float, nsteps: int,
+               thermo_every: int = 0, forces: Optional[torch.Tensor] = None, check: bool = True):
+        """Velocity Verlet in place on device tensors x, v; returns the thermo rows tensor."""
+        assert x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()
+        assert v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+        t = self._dev(types, torch.int32)
+        n = x.shape[0]
+        b = _box9(box)
+        ms = np.ascontiguousarray(masses, dtype=np.float64)
+        ws = self.workspace(np.array([0, n]), b)
+        nrow = 1 + (nsteps // thermo_every if thermo_every > 0 else 0)
+        th = torch.zeros(nrow, 6, dtype=torch.float64, device=x.device)
+        self._check(_lib.dp_md_run(self.h, n, _ptr(x), _ptr(v), _ptr(t), ms.ctypes.data_as(C.c_void_p),
+                                   b.ctypes.data_as(C.c_void_p), float(dt), int(nsteps),
+                                   int(thermo_every), _ptr(th), _ptr(forces), _ptr(ws), ws.numel(),
+                                   _stream()))
+        if check:
+            self.status()
+        return th
+
+    def profile(self, enable: bool):
+        self._check(_lib.dp_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self, stage: str):
+        """(total milliseconds, launches) of one stage since profile(True)."""
+        ms, cnt = C.c_double(), C.c_int64()
+        self._check(_lib.dp_profile_read(self.h, STAGES[stage], C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value

@@ -92,3 +92,73 @@ def test_energy_forces_virial_fp64(dp, water_model, tiny_model, water192, which)
     assert _frel(F.cpu().numpy(), r["F"]) < 1e-9
     assert _rel(W.cpu().numpy(), r["W"]) < 1e-9
     assert _rel(Ei.cpu().numpy(), r["Ei"]) < 1e-10
+
+
+def test_md_water192_fp64_matches_oracle(dp, water_model, water192):
+    """20 velocity-Verlet steps: positions, velocities and thermo rows (Section 4)."""
+    import torch
+    c, t, b = water192
+    masses = [I.MASS["O"], I.MASS["H"]]
+    v = I.maxwell_velocities(t, masses, 300.0, 302)
+    m = dp.DPModel(water_model)
+    x_d = torch.as_tensor(c, device="cuda").clone()
+    v_d = torch.as_tensor(v, device="cuda").clone()
+    th = m.md_run(x_d, v_d, t, masses, b, 0.5, 20, 5).cpu().numpy()
+    xo, vo, tho = Oracle(water_model).md(c, v, t, masses, b, 0.5, 20, 5)
+    assert np.abs(x_d.cpu().numpy() - xo).max() < 1e-10
+    assert _rel(v_d.cpu().numpy(), vo) < 1e-8
+    assert np.abs(th[:, 0] - tho[:, 0]).max() == 0
+    assert _rel(th[:, 1:], tho[:, 1:]) < 1e-10
+
+
+def test_water12k_full_frame_fp64(dp, water_model):
+    """The benchmark's 12,288-atom frame, every atom against the oracle."""
+    c, t, b = I.config_water12k(202)
+    m = dp.DPModel(water_model)
+    nl, img, nn, rc = m.nlist(c, t, b)
+    assert rc == 0
+    o = Oracle(water_model)
+    onl, oimg, onn, _ = o.nlist(c, t, b)
+    assert np.array_equal(nl.cpu().numpy(), onl) and np.array_equal(img.cpu().numpy(), oimg)
+    E, F, W, Ei = m.compute(c, t, b, atom_energy=True)
+    r = o.eval(c, t, b)
+    assert abs(float(E.cpu()[0]) - r["E"]) <= 1e-10 * abs(r["E"])
+    assert _frel(F.cpu().numpy(), r["F"]) < 1e-9
+    assert _rel(W.cpu().numpy(), r["W"]) < 1e-9
+    assert _rel(Ei.cpu().numpy(), r["Ei"]) < 1e-10
+
+
+def test_copper131k_sampled_fp64(dp, copper_model):
+    """131,072-atom copper (one GPU's share of the paper's weak-scaling run): E_i and F_i of
+    sampled atoms, each computed exactly by the oracle from the centres that see it."""
+    c, t, b = I.config_copper131k(203)
+    m = dp.DPModel(copper_model)
+    E, F, W, Ei = m.compute(c, t, b, atom_energy=True)
+    idx = np.random.default_rng(7).choice(len(t), 24, replace=False)
+    oEi, oF = Oracle(copper_model).eval_sampled(c, t, b, idx)
+    Fg = F.cpu().numpy()[idx]
+    assert _rel(Ei.cpu().numpy()[idx], oEi) < 1e-10
+    assert np.linalg.norm(Fg - oF, axis=1).max() <= 1e-9 * np.linalg.norm(oF, axis=1).max()
+    # momentum: sum of all forces vanishes
+    Fa = F.cpu().numpy()
+    assert np.abs(Fa.sum(0)).max() <= 1e-9 * np.abs(Fa).max()
+
+
+def test_ragged_batch_fp64(dp, water_model):
+    """Frames of uneven size (96..3,072 atoms, small boxes down to 9.9 A) in one call."""
+    frames = I.ragged_water_batch(64, 204)
+    pick = [0, 1, 2, 3, 5, 8]
+    sel = [frames[k] for k in pick]
+    coords = np.concatenate([f[0] for f in sel])
+    types = np.concatenate([f[1] for f in sel])
+    boxes = np.stack([f[2] for f in sel])
+    off = np.concatenate([[0], np.cumsum([len(f[1]) for f in sel])])
+    m = dp.DPModel(water_model)
+    E, F, W = m.compute_batch(coords, types, off, boxes)
+    E, F, W = E.cpu().numpy(), F.cpu().numpy(), W.cpu().numpy()
+    o = Oracle(water_model)
+    for k, (c, t, b) in enumerate(sel):
+        r = o.eval(c, t, b)
+        assert abs(E[k] - r["E"]) <= 1e-10 * abs(r["E"])
+        assert _frel(F[off[k]:off[k + 1]], r["F"]) < 1e-9
+        assert _rel(W[k], r["W"]) < 1e-9
