@@ -28,6 +28,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "devmath.h"
 
 namespace dp {
 
@@ -45,13 +46,8 @@ __device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// tanh: double uses the HIP math library; float uses tanh x = 1 - 2 / (exp(2x) + 1)
-// with the hardware exp2 and a correctly rounded division.
-__device__ __forceinline__ double tanh_t(double x) { return tanh(x); }
-__device__ __forceinline__ float tanh_t(float x) {
-  float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);  // exp(2x) = 2^(2x log2 e)
-  return 1.0f - 2.0f / (e + 1.0f);
-}
+template <class T>
+__device__ __forceinline__ T tanh_t(T x) { return dp_tanh(x); }
 
 // Accumulator row held by lane group g in register q of a 16x16 MFMA result:
 // FP64 16x16x4 returns rows g + 4q, FP32 16x16x4 (and BF16 16x16x32) rows 4g + q.
@@ -62,6 +58,22 @@ __device__ __forceinline__ int lpos(float, int g, int q) { return 4 * g + q; }
 template <class T>
 __device__ __forceinline__ T shfl_x(T v, int mask) {
   return __shfl_xor(v, mask);
+}
+
+// Cross-lane moves inside a 16-lane row with DPP (VALU, no LDS traffic).  The
+// reduce-scatter over the 16 rows of a chunk pairs lanes by xor 8 (row_ror:8), xor 7
+// (row_half_mirror), xor 2 and xor 1 (quad_perm); these partner offsets span the row.
+enum { DPP_ROR8 = 0x128, DPP_HALF_MIRROR = 0x141, DPP_XOR2 = 0x4E, DPP_XOR1 = 0xB1 };
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  long long x = __builtin_bit_cast(long long, v);
+  int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // species of the rows starting at r0 (rows of one block never straddle species)
@@ -146,15 +158,16 @@ __device__ __forceinline__ T g_at(const T (&t0)[2][4], const T (&t1)[4][4], cons
   return t0[mt & 1][q] + t1[mt & 3][q] + t2[mt][q];
 }
 
-// one reduce-scatter step over lane bit B on an array of S values
-template <class T, int S, int B>
+// one reduce-scatter step on an array of S values: the lane whose "up" bit is set
+// keeps the upper half, its DPP partner (which has the bit clear) the lower half
+template <class T, int S, int CTRL>
 __device__ __forceinline__ void rs_step(T (&v)[64], bool up) {
 #pragma unroll
   for (int k = 0; k < S / 2; k++) {
     T a = v[k], b = v[k + S / 2];
     T send = up ? a : b;
     T keep = up ? b : a;
-    v[k] = keep + shfl_x(send, B);
+    v[k] = keep + dpp_mov<CTRL>(send);
   }
 }
 
@@ -211,12 +224,12 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd(EmbedArgs A) {
         T b = g_at(t0, t1, t2, mt + 4, q) * R[c];
         T send = b3 ? a : b;
         T keep = b3 ? b : a;
-        vv[kk] = keep + shfl_x(send, 8);
+        vv[kk] = keep + dpp_mov<DPP_ROR8>(send);
         if ((kk & 15) == 15) __builtin_amdgcn_sched_barrier(0);
       }
-      rs_step<T, 64, 4>(vv, b2);
-      rs_step<T, 32, 2>(vv, b1);
-      rs_step<T, 16, 1>(vv, b0);
+      rs_step<T, 64, DPP_HALF_MIRROR>(vv, b2);
+      rs_step<T, 32, DPP_XOR2>(vv, b1);
+      rs_step<T, 16, DPP_XOR1>(vv, b0);
 #pragma unroll
       for (int j = 0; j < 8; j++) acc[j] += vv[j];
     }

@@ -15,6 +15,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "devmath.h"
 
 namespace dp {
 
@@ -30,20 +31,16 @@ __device__ __forceinline__ d4v fmfma4(double a, double b, d4v c) {
 __device__ __forceinline__ f4v fmfma4(float a, float b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ double ftanh(double x) { return tanh(x); }
-__device__ __forceinline__ float ftanh(float x) {
-  float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);
-  return 1.0f - 2.0f / (e + 1.0f);
-}
+template <class T>
+__device__ __forceinline__ T ftanh(T x) { return dp_tanh(x); }
 
 enum Epi { EPI_FWD1 = 0, EPI_FWDRES = 1, EPI_BWD = 2, EPI_BWD1 = 3 };
 
-constexpr int GT = 64;   // output tile
-constexpr int KT = 16;   // k tile
+constexpr int BM = 64;    // output tile rows (one species per tile)
+constexpr int BN = 128;   // output tile columns
 
 struct GemmArgs {
   int nrows, K, N;
-  int species_rows[kMaxTypes + 1];  // unused on device; rows read from type_row0
   const int* type_row0;
   int ntypes;
   const void* A;        // [nrows][K]
@@ -57,86 +54,123 @@ struct GemmArgs {
   void* out2;           // FWD*: tanh part [nrows][N]
 };
 
+// 64 x 128 output tile per workgroup of 4 waves; wave w owns columns [32 w, 32 w + 32)
+// as 4 x 2 MFMA tiles.  K is consumed in tiles of KT (16 doubles / 32 floats) staged
+// in LDS; the next tile is prefetched into registers while the current one is used.
 template <class T, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
-  __shared__ T As[GT][KT + 1];
-  __shared__ T Bs[KT][GT + 1];
-  const int r0 = blockIdx.x * GT;
-  const int n0 = blockIdx.y * GT;
+  constexpr int KT = sizeof(T) == 8 ? 16 : 32;
+  constexpr int APT = BM * KT / 256;     // A elements per thread per tile
+  constexpr int BPT = KT * BN / 256;     // B elements per thread per tile
+  __shared__ T As[BM][KT + 1];
+  __shared__ T Bs[KT][BN + 1];
+  const int r0 = blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
   int sp = -1;
   for (int t = 0; t < G.ntypes; t++)
     if (r0 >= G.type_row0[t] && r0 < G.type_row0[t + 1]) sp = t;
   if (sp < 0) return;
-  const T* A = (const T*)G.A;
-  const T* At = (const T*)G.Aaux;
-  const T* W = (const T*)G.W[sp * G.wstride + G.wsel];
-  const bool transW = (EPI == EPI_BWD || EPI == EPI_BWD1);
+  const T* __restrict__ A = (const T*)G.A;
+  const T* __restrict__ At = (const T*)G.Aaux;
+  const T* __restrict__ W = (const T*)G.W[sp * G.wstride + G.wsel];
+  constexpr bool transW = (EPI == EPI_BWD || EPI == EPI_BWD1);
   const int K = G.K, N = G.N;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, rb = lane & 15, g = lane >> 4;
-  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+  const int wc = wv * 32;
   typedef typename FAcc4<T>::type A4;
-  A4 acc[2][2];
+  A4 acc[4][2];
 #pragma unroll
-  for (int a = 0; a < 2; a++)
+  for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 2; b++) acc[a][b] = A4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < K; k0 += KT) {
-    // stage A (64 x 16) and B (16 x 64)
-    for (int q = tid; q < GT * KT; q += 256) {
-      int r = q / KT, k = q % KT;
-      int gr = r0 + r, gk = k0 + k;
+  T ra[APT], rbv[BPT];
+  // A tile element e = tid + 256 j: row e / KT, k e % KT (consecutive threads along k)
+  // B tile (not transposed) element e: k e / BN, col e % BN (consecutive along columns)
+  // B tile (transposed W): element e: col e / KT, k e % KT (consecutive along k of W rows)
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < APT; j++) {
+      int e = tid + 256 * j, r = e / KT, k = e % KT;
+      int gk = k0 + k;
       T v = (T)0;
       if (gk < K) {
-        v = A[(size_t)gr * K + gk];
+        size_t o = (size_t)(r0 + r) * K + gk;
+        v = A[o];
         if (EPI == EPI_BWD || EPI == EPI_BWD1) {
-          T t = At[(size_t)gr * K + gk];
+          T t = At[o];
           v = v * ((T)1 - t * t);
         }
       }
-      As[r][k] = v;
+      ra[j] = v;
     }
-    for (int q = tid; q < GT * KT; q += 256) {
-      int k = q / GT, c = q % GT;
+#pragma unroll
+    for (int j = 0; j < BPT; j++) {
+      int e = tid + 256 * j;
+      int k, c;
+      if (transW) { c = e / KT; k = e % KT; }
+      else { k = e / BN; c = e % BN; }
       int gk = k0 + k, gc = n0 + c;
       T v = (T)0;
       if (gk < K && gc < N) v = transW ? W[(size_t)gc * K + gk] : W[(size_t)gk * N + gc];
-      Bs[k][c] = v;
+      rbv[j] = v;
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int j = 0; j < APT; j++) {
+      int e = tid + 256 * j;
+      As[e / KT][e % KT] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < BPT; j++) {
+      int e = tid + 256 * j;
+      if (transW) Bs[e % KT][e / KT] = rbv[j];
+      else Bs[e / BN][e % BN] = rbv[j];
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += KT) {
     __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + KT < K) load(k0 + KT);
 #pragma unroll
     for (int ks = 0; ks < KT; ks += 4) {
-      T a0 = As[wr + rb][ks + g], a1 = As[wr + 16 + rb][ks + g];
-      T b0 = Bs[ks + g][wc + rb], b1 = Bs[ks + g][wc + 16 + rb];
-      acc[0][0] = fmfma4(a0, b0, acc[0][0]);
-      acc[0][1] = fmfma4(a0, b1, acc[0][1]);
-      acc[1][0] = fmfma4(a1, b0, acc[1][0]);
-      acc[1][1] = fmfma4(a1, b1, acc[1][1]);
+      T av[4], bv[2];
+#pragma unroll
+      for (int a = 0; a < 4; a++) av[a] = As[16 * a + rb][ks + g];
+#pragma unroll
+      for (int b = 0; b < 2; b++) bv[b] = Bs[ks + g][wc + 16 * b + rb];
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) acc[a][b] = fmfma4(av[a], bv[b], acc[a][b]);
     }
-    __syncthreads();
   }
-  // epilogue: lane holds column (wc + 16 b + rb) and four rows of the 16-row tile
+  // epilogue: lane holds column (wc + 16 b + rb) and four rows of each 16-row tile
   T* out = (T*)G.out;
   T* out2 = (T*)G.out2;
   const T* X = (const T*)G.Xprev;
   const T* bias = (EPI == EPI_FWD1 || EPI == EPI_FWDRES) ? (const T*)G.bias[sp * G.wstride + G.wsel] : nullptr;
 #pragma unroll
-  for (int a = 0; a < 2; a++)
+  for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       int col = n0 + wc + 16 * b + rb;
       if (col >= N) continue;
+      T bc = bias ? bias[col] : (T)0;
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         // FP64 16x16x4 results hold rows g + 4q, FP32 rows 4g + q
-        int row = r0 + wr + 16 * a + (sizeof(T) == 8 ? g + 4 * q : 4 * g + q);
+        int row = r0 + 16 * a + (sizeof(T) == 8 ? g + 4 * q : 4 * g + q);
         size_t o = (size_t)row * N + col;
         T v = acc[a][b][q];
         if (EPI == EPI_FWD1) {
-          T t = ftanh(v + bias[col]);
+          T t = ftanh(v + bc);
           out[o] = t;
           out2[o] = t;
         } else if (EPI == EPI_FWDRES) {
-          T t = ftanh(v + bias[col]);
+          T t = ftanh(v + bc);
           out[o] = X[o] + t;
           out2[o] = t;
         } else if (EPI == EPI_BWD) {
@@ -168,34 +202,33 @@ __global__ void k_desc(int nrows, int M, int m2, const int* __restrict__ row_ato
 }
 
 // dE/dT[p][c] = sum_b dD[p][b] T[b][c] + [p < m2] sum_a dD[a][p] T[a][c]
+// one workgroup per row: T and dD of the row staged in LDS
 template <class T>
-__global__ void k_desc_bwd(int nrows, int M, int m2, const int* __restrict__ row_atom,
-                           const T* __restrict__ Tm, const T* __restrict__ Dg, T* __restrict__ gT) {
-  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t tot = (size_t)nrows * M;
-  if (q >= tot) return;
-  int row = (int)(q / M), p = (int)(q % M);
-  T* o = gT + (size_t)row * M * 4 + p * 4;
+__global__ __launch_bounds__(256) void k_desc_bwd(int nrows, int M, int m2, const int* __restrict__ row_atom,
+                                                 const T* __restrict__ Tm, const T* __restrict__ Dg,
+                                                 T* __restrict__ gT) {
+  extern __shared__ __align__(16) char sm[];
+  T* st = (T*)sm;               // [M][4]
+  T* sd = st + M * 4;           // [M][m2]
+  const int row = blockIdx.x;
+  T* o = gT + (size_t)row * M * 4;
   if (row_atom[row] < 0) {
-    o[0] = o[1] = o[2] = o[3] = (T)0;
+    for (int q = threadIdx.x; q < M * 4; q += blockDim.x) o[q] = (T)0;
     return;
   }
   const T* t = Tm + (size_t)row * M * 4;
   const T* dg = Dg + (size_t)row * M * m2;
-  T v[4] = {(T)0, (T)0, (T)0, (T)0};
-  for (int b = 0; b < m2; b++) {
-    T w = dg[p * m2 + b];
-#pragma unroll
-    for (int c = 0; c < 4; c++) v[c] += w * t[b * 4 + c];
+  for (int q = threadIdx.x; q < M * 4; q += blockDim.x) st[q] = t[q];
+  for (int q = threadIdx.x; q < M * m2; q += blockDim.x) sd[q] = dg[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < M * 4; q += blockDim.x) {
+    int p = q >> 2, c = q & 3;
+    T v = (T)0;
+    for (int b = 0; b < m2; b++) v += sd[p * m2 + b] * st[b * 4 + c];
+    if (p < m2)
+      for (int a = 0; a < M; a++) v += sd[a * m2 + p] * st[a * 4 + c];
+    o[q] = v;
   }
-  if (p < m2)
-    for (int a = 0; a < M; a++) {
-      T w = dg[a * m2 + p];
-#pragma unroll
-      for (int c = 0; c < 4; c++) v[c] += w * t[a * 4 + c];
-    }
-#pragma unroll
-  for (int c = 0; c < 4; c++) o[c] = v[c];
 }
 
 // E_i = x . w_o + b_o (FP64 accumulation) and the backward seed g = w_o; one wave per row
@@ -224,7 +257,7 @@ __global__ void k_fit_out(int nrows, int N, int ntypes, const int* __restrict__ 
 
 template <class T, int EPI>
 static void gemm(const GemmArgs& G, hipStream_t st) {
-  dim3 grid((G.nrows + GT - 1) / GT, (G.N + GT - 1) / GT);
+  dim3 grid((G.nrows + BM - 1) / BM, (G.N + BN - 1) / BN);
   hipLaunchKernelGGL((k_gemm<T, EPI>), grid, dim3(256), 0, st, G);
 }
 
@@ -283,11 +316,8 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
   G.Xprev = nullptr;
   G.out = F.Dg;
   gemm<T, EPI_BWD1>(G, st);
-  {
-    size_t tot = (size_t)rows * M;
-    hipLaunchKernelGGL(k_desc_bwd<T>, dim3((tot + 255) / 256), dim3(256), 0, st, rows, M, m2, F.row_atom,
-                       (const T*)F.T, (const T*)F.Dg, (T*)F.gT);
-  }
+  hipLaunchKernelGGL(k_desc_bwd<T>, dim3(rows), dim3(256), sizeof(T) * (M * 4 + M * m2), st, rows, M, m2,
+                     F.row_atom, (const T*)F.T, (const T*)F.Dg, (T*)F.gT);
 }
 
 void launch_fit(const FitArgs& F, hipStream_t st) {
