@@ -134,6 +134,26 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
               int32_t thermo_every, double* thermo, double* forces, void* workspace,
               size_t ws_bytes, void* stream);
 
+/* Replace the model parameters by theta (device, FP64, nparams values in the model
+ * file's flat order) and rebuild the kernels' weight layouts on stream.  Later calls
+ * on the handle use the new parameters.  dp_get_params copies the current ones out. */
+int dp_set_params(dp_handle h, const double* theta, void* stream);
+int dp_get_params(dp_handle h, double* theta, void* stream);
+
+/* Parameter gradient of an energy + force loss for a batch of frames (training):
+ *   gtheta += sum_f gE[f] dE_f/dtheta + sum_i gF[i] . dF_i/dtheta      (F = -dE/dr, Eq. 10)
+ * with gE [nframes] and gF [natoms][3] device doubles (the loss gradients with respect
+ * to the energies and forces) and gtheta [nparams] device doubles (accumulated: zero
+ * it first).  Computed exactly (forward-over-reverse, FP64, any precision option).
+ * Batch arguments as dp_compute_batch.  The workspace must hold
+ * dp_param_grad_workspace_size bytes (roughly 8 KB per neighbour pair: split large
+ * batches into several calls).  Synchronises the stream once. */
+int dp_param_grad_workspace_size(dp_handle h, int32_t nframes, const int64_t* atom_offsets,
+                                 const double* boxes, size_t* bytes);
+int dp_param_grad(dp_handle h, int32_t nframes, const int64_t* atom_offsets, const double* coords,
+                  const int32_t* types, const double* boxes, const double* gE, const double* gF,
+                  double* gtheta, void* workspace, size_t ws_bytes, void* stream);
+
 /* Stage timing with HIP events recorded on the call's stream around each stage
  * (neighbour list, embedding forward, fitting net, embedding adjoint, reductions,
  * integration).  dp_profile(h, 1) clears the records and enables timing,

@@ -31,6 +31,11 @@ struct dp_handle_s {
   void* d_fit = nullptr;           // fitting weights (storage type)
   double* d_bo = nullptr;          // output biases [ntypes]
   void** d_ptrs = nullptr;         // device pointer tables for the fitting kernel
+  double* d_theta = nullptr;       // flat FP64 parameters (model-file order)
+  int* d_net_map = nullptr;        // net blocks <- theta index (-1: zero)
+  int* d_fit_map = nullptr;        // fitting buffer <- theta index
+  int* d_bo_map = nullptr;         // output biases <- theta index
+  size_t net_elems = 0, fit_elems = 0;
   // pinned staging for per-call frame tables: a ring of slots, each reused only
   // after the copy that last read it has completed
   static constexpr int kSlots = 8;
@@ -200,32 +205,30 @@ static int storage_bytes(int prec) { return prec == PREC_FP64 ? 8 : 4; }
 // position p of a padded layer <-> feature index (p / 32) * s0 + p % 32, pad if p % 32 >= s0
 static int pos_feature(int p, int s0) { return (p % kP0) < s0 ? (p / kP0) * s0 + (p % kP0) : -1; }
 
-template <class S>
-static void fill_net_block(dp_handle h, const ParamIndex& P, int net, S* blk) {
-  const double* p = h->params.data();
+// index map of one position-padded net block: element -> parameter index (-1 = zero)
+static void net_block_map(dp_handle h, const ParamIndex& P, int net, int* blk) {
   int s0 = h->s0, s1 = 2 * s0, s2 = 4 * s0;
-  for (int q = 0; q < kNetElems; q++) blk[q] = (S)0;
+  for (int q = 0; q < kNetElems; q++) blk[q] = -1;
   for (int pp = 0; pp < kP0; pp++) {
     int f = pos_feature(pp, s0);
     if (f < 0) continue;
-    blk[kOffW0 + pp] = (S)p[P.eW[net * 3 + 0] + f];
-    blk[kOffB0 + pp] = (S)p[P.eB[net * 3 + 0] + f];
+    blk[kOffW0 + pp] = (int)(P.eW[net * 3 + 0] + f);
+    blk[kOffB0 + pp] = (int)(P.eB[net * 3 + 0] + f);
   }
   for (int pp = 0; pp < kP1; pp++) {
     int f = pos_feature(pp, s0);
-    if (f >= 0) blk[kOffB1 + pp] = (S)p[P.eB[net * 3 + 1] + f];
+    if (f >= 0) blk[kOffB1 + pp] = (int)(P.eB[net * 3 + 1] + f);
   }
   for (int pp = 0; pp < kP2; pp++) {
     int f = pos_feature(pp, s0);
-    if (f >= 0) blk[kOffB2 + pp] = (S)p[P.eB[net * 3 + 2] + f];
+    if (f >= 0) blk[kOffB2 + pp] = (int)(P.eB[net * 3 + 2] + f);
   }
   for (int pi = 0; pi < kP0; pi++) {
     int fi = pos_feature(pi, s0);
     if (fi < 0) continue;
     for (int po = 0; po < kP1; po++) {
       int fo = pos_feature(po, s0);
-      if (fo < 0) continue;
-      blk[kOffW1 + pi * kW1Stride + po] = (S)p[P.eW[net * 3 + 1] + (int64_t)fi * s1 + fo];
+      if (fo >= 0) blk[kOffW1 + pi * kW1Stride + po] = (int)(P.eW[net * 3 + 1] + (int64_t)fi * s1 + fo);
     }
   }
   for (int pi = 0; pi < kP1; pi++) {
@@ -233,60 +236,81 @@ static void fill_net_block(dp_handle h, const ParamIndex& P, int net, S* blk) {
     if (fi < 0) continue;
     for (int po = 0; po < kP2; po++) {
       int fo = pos_feature(po, s0);
-      if (fo < 0) continue;
-      blk[kOffW2 + pi * kW2Stride + po] = (S)p[P.eW[net * 3 + 2] + (int64_t)fi * s2 + fo];
+      if (fo >= 0) blk[kOffW2 + pi * kW2Stride + po] = (int)(P.eW[net * 3 + 2] + (int64_t)fi * s2 + fo);
     }
   }
 }
 
-template <class S>
-static int upload_weights_t(dp_handle h) {
-  ParamIndex P = index_params(h);
-  int nnet = h->ntypes * h->ntypes;
-  std::vector<S> nets((size_t)nnet * kNetElems);
-  for (int net = 0; net < nnet; net++) fill_net_block<S>(h, P, net, nets.data() + (size_t)net * kNetElems);
-  HIPCHECK(h, hipMalloc(&h->d_nets, nets.size() * sizeof(S)));
-  HIPCHECK(h, hipMemcpy(h->d_nets, nets.data(), nets.size() * sizeof(S), hipMemcpyHostToDevice));
-  // fitting weights, per species: W_k, b_k for k < nfit, then wo
-  std::vector<S> fit;
-  std::vector<size_t> offW, offB, offO;
-  std::vector<double> bo(h->ntypes);
-  for (int a = 0; a < h->ntypes; a++) {
-    int nin = h->M * h->m2;
-    for (int k = 0; k < h->n_fit; k++) {
-      int nout = h->fit_w[k];
-      offW.push_back(fit.size());
-      for (int64_t q = 0; q < (int64_t)nin * nout; q++) fit.push_back((S)h->params[P.fW[a * (h->n_fit + 1) + k] + q]);
-      offB.push_back(fit.size());
-      for (int q = 0; q < nout; q++) fit.push_back((S)h->params[P.fB[a * (h->n_fit + 1) + k] + q]);
-      nin = nout;
-    }
-    offO.push_back(fit.size());
-    for (int q = 0; q < nin; q++) fit.push_back((S)h->params[P.fW[a * (h->n_fit + 1) + h->n_fit] + q]);
-    bo[a] = h->params[P.fB[a * (h->n_fit + 1) + h->n_fit]];
-    while (fit.size() % 64) fit.push_back((S)0);
-  }
-  HIPCHECK(h, hipMalloc(&h->d_fit, fit.size() * sizeof(S)));
-  HIPCHECK(h, hipMemcpy(h->d_fit, fit.data(), fit.size() * sizeof(S), hipMemcpyHostToDevice));
-  HIPCHECK(h, hipMalloc(&h->d_bo, h->ntypes * sizeof(double)));
-  HIPCHECK(h, hipMemcpy(h->d_bo, bo.data(), h->ntypes * sizeof(double), hipMemcpyHostToDevice));
-  // pointer tables: W [ntypes*nfit], b [ntypes*nfit], wo [ntypes]
-  std::vector<void*> ptrs;
-  S* base = (S*)h->d_fit;
-  for (size_t q = 0; q < offW.size(); q++) ptrs.push_back(base + offW[q]);
-  for (size_t q = 0; q < offB.size(); q++) ptrs.push_back(base + offB[q]);
-  for (size_t q = 0; q < offO.size(); q++) ptrs.push_back(base + offO[q]);
-  HIPCHECK(h, hipMalloc(&h->d_ptrs, ptrs.size() * sizeof(void*)));
-  HIPCHECK(h, hipMemcpy(h->d_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice));
+// device layouts of the weights, rebuilt from d_theta by index maps
+static int refresh_weights(dp_handle h, hipStream_t st) {
+  launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, h->net_elems, h->d_net_map, h->d_theta,
+                        h->d_nets, st);
+  launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, h->fit_elems, h->d_fit_map, h->d_theta,
+                        h->d_fit, st);
+  launch_scatter_params(0, h->ntypes, h->d_bo_map, h->d_theta, h->d_bo, st);
+  HIPCHECK(h, hipGetLastError());
   return DP_OK;
 }
 
 static int upload_weights(dp_handle h) {
-  if (h->opt.precision == PREC_FP64) return upload_weights_t<double>(h);
-  return upload_weights_t<float>(h);
+  ParamIndex P = index_params(h);
+  const int sb = storage_bytes(h->opt.precision);
+  int nnet = h->ntypes * h->ntypes;
+  std::vector<int> nmap((size_t)nnet * kNetElems);
+  for (int net = 0; net < nnet; net++) net_block_map(h, P, net, nmap.data() + (size_t)net * kNetElems);
+  // fitting weights, per species: W_k, b_k for k < nfit, then wo (rows padded to 64)
+  std::vector<int> fmap;
+  std::vector<size_t> offW, offB, offO;
+  std::vector<int> bomap(h->ntypes);
+  for (int a = 0; a < h->ntypes; a++) {
+    int nin = h->M * h->m2;
+    for (int k = 0; k < h->n_fit; k++) {
+      int nout = h->fit_w[k];
+      offW.push_back(fmap.size());
+      for (int64_t q = 0; q < (int64_t)nin * nout; q++) fmap.push_back((int)(P.fW[a * (h->n_fit + 1) + k] + q));
+      offB.push_back(fmap.size());
+      for (int q = 0; q < nout; q++) fmap.push_back((int)(P.fB[a * (h->n_fit + 1) + k] + q));
+      nin = nout;
+    }
+    offO.push_back(fmap.size());
+    for (int q = 0; q < nin; q++) fmap.push_back((int)(P.fW[a * (h->n_fit + 1) + h->n_fit] + q));
+    bomap[a] = (int)P.fB[a * (h->n_fit + 1) + h->n_fit];
+    while (fmap.size() % 64) fmap.push_back(-1);
+  }
+  h->net_elems = nmap.size();
+  h->fit_elems = fmap.size();
+  HIPCHECK(h, hipMalloc(&h->d_theta, sizeof(double) * h->nparams));
+  HIPCHECK(h, hipMemcpy(h->d_theta, h->params.data(), sizeof(double) * h->nparams, hipMemcpyHostToDevice));
+  HIPCHECK(h, hipMalloc(&h->d_net_map, sizeof(int) * nmap.size()));
+  HIPCHECK(h, hipMemcpy(h->d_net_map, nmap.data(), sizeof(int) * nmap.size(), hipMemcpyHostToDevice));
+  HIPCHECK(h, hipMalloc(&h->d_fit_map, sizeof(int) * fmap.size()));
+  HIPCHECK(h, hipMemcpy(h->d_fit_map, fmap.data(), sizeof(int) * fmap.size(), hipMemcpyHostToDevice));
+  HIPCHECK(h, hipMalloc(&h->d_bo_map, sizeof(int) * bomap.size()));
+  HIPCHECK(h, hipMemcpy(h->d_bo_map, bomap.data(), sizeof(int) * bomap.size(), hipMemcpyHostToDevice));
+  HIPCHECK(h, hipMalloc(&h->d_nets, nmap.size() * sb));
+  HIPCHECK(h, hipMalloc(&h->d_fit, fmap.size() * sb));
+  HIPCHECK(h, hipMalloc(&h->d_bo, h->ntypes * sizeof(double)));
+  // pointer tables: W [ntypes*nfit], b [ntypes*nfit], wo [ntypes]
+  std::vector<void*> ptrs;
+  char* base = (char*)h->d_fit;
+  for (size_t q = 0; q < offW.size(); q++) ptrs.push_back(base + offW[q] * sb);
+  for (size_t q = 0; q < offB.size(); q++) ptrs.push_back(base + offB[q] * sb);
+  for (size_t q = 0; q < offO.size(); q++) ptrs.push_back(base + offO[q] * sb);
+  HIPCHECK(h, hipMalloc(&h->d_ptrs, ptrs.size() * sizeof(void*)));
+  HIPCHECK(h, hipMemcpy(h->d_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice));
+  int rc = refresh_weights(h, nullptr);
+  if (rc != DP_OK) return rc;
+  HIPCHECK(h, hipDeviceSynchronize());
+  return DP_OK;
 }
 
 static void release_weights(dp_handle h) {
+  if (h->d_theta) (void)hipFree(h->d_theta);
+  if (h->d_net_map) (void)hipFree(h->d_net_map);
+  if (h->d_fit_map) (void)hipFree(h->d_fit_map);
+  if (h->d_bo_map) (void)hipFree(h->d_bo_map);
+  h->d_theta = nullptr;
+  h->d_net_map = h->d_fit_map = h->d_bo_map = nullptr;
   if (h->d_nets) (void)hipFree(h->d_nets);
   if (h->d_fit) (void)hipFree(h->d_fit);
   if (h->d_bo) (void)hipFree(h->d_bo);
@@ -820,6 +844,136 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
         launch_thermo(n, types, mm, vol, s, v, E, Wv, thermo + 6 * row++, st);
     }
   }
+  HIPCHECK(h, hipGetLastError());
+  return DP_OK;
+}
+
+int dp_set_params(dp_handle h, const double* theta, void* stream) {
+  if (!h || !theta) return fail(h, DP_ERR_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHECK(h, hipMemcpyAsync(h->d_theta, theta, sizeof(double) * h->nparams, hipMemcpyDeviceToDevice, st));
+  return refresh_weights(h, st);
+}
+
+int dp_get_params(dp_handle h, double* theta, void* stream) {
+  if (!h || !theta) return fail(h, DP_ERR_ARG, "null argument");
+  HIPCHECK(h, hipMemcpyAsync(theta, h->d_theta, sizeof(double) * h->nparams, hipMemcpyDeviceToDevice,
+                             (hipStream_t)stream));
+  return DP_OK;
+}
+
+struct PGLayout {
+  size_t o_base, o_sums, o_ptrs, o_gtan, o_scr, scr_bytes, total;
+  long np_max;
+};
+
+static PGLayout pg_layout(dp_handle h, const Plan& P) {
+  PGLayout L{};
+  size_t o = P.total;
+  auto take = [&](size_t bytes) { size_t r = o; o = al(o + bytes); return r; };
+  L.o_base = take(sizeof(int) * (size_t)h->ntypes * (P.nrows + 1));
+  L.o_sums = take(sizeof(int) * (scan_sums_ints(P.nrows + 1, 1) + 16));
+  L.o_ptrs = take(sizeof(void*) * kMaxTypes + sizeof(int) * kMaxTypes);
+  L.o_gtan = take(sizeof(double) * h->nparams);
+  L.np_max = (long)P.n * h->nm;
+  L.scr_bytes = param_grad_scratch_bytes(P.nrows, L.np_max, h->M, h->m2, h->s0, h->fit_w[0], h->n_fit);
+  L.o_scr = take(L.scr_bytes);
+  L.total = o;
+  return L;
+}
+
+int dp_param_grad_workspace_size(dp_handle h, int32_t nframes, const int64_t* atom_offsets,
+                                 const double* boxes, size_t* bytes) {
+  if (!h || !atom_offsets || !boxes || !bytes) return fail(h, DP_ERR_ARG, "null argument");
+  Plan P;
+  int rc = make_plan(h, nframes, atom_offsets, boxes, nullptr, P);
+  if (rc != DP_OK) return rc;
+  *bytes = pg_layout(h, P).total;
+  return DP_OK;
+}
+
+int dp_param_grad(dp_handle h, int32_t nframes, const int64_t* atom_offsets, const double* coords,
+                  const int32_t* types, const double* boxes, const double* gE, const double* gF,
+                  double* gtheta, void* workspace, size_t ws_bytes, void* stream) {
+  if (!h) return DP_ERR_ARG;
+  if (!atom_offsets || !boxes || !gE || !gF || !gtheta) return fail(h, DP_ERR_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  Plan P;
+  NlistArgs A{};
+  {
+    Plan Q;
+    int rc = make_plan(h, nframes, atom_offsets, boxes, nullptr, Q);
+    if (rc != DP_OK) return rc;
+    if (!workspace || ws_bytes < pg_layout(h, Q).total)
+      return fail(h, DP_ERR_WORKSPACE, "workspace too small for dp_param_grad");
+  }
+  int rc = stage_frames_and_nlist(h, nframes, atom_offsets, boxes, coords, types, workspace, ws_bytes, st,
+                                  P, A);
+  if (rc != DP_OK) return rc;
+  PGLayout L = pg_layout(h, P);
+  Ws W{(char*)workspace, &P};
+  const int nt = h->ntypes, nrows = P.nrows;
+  int* base = W.at<int>(L.o_base);
+  int* sums = W.at<int>(L.o_sums);
+  for (int b = 0; b < nt; b++)
+    launch_pair_scan(nrows, nt, b, A.row_atom, A.nnei, base + (size_t)b * (nrows + 1), sums, sums + 8 + b, st);
+  HIPCHECK(h, hipGetLastError());
+  // the pair-row groups size the GEMMs: read them back (one synchronisation)
+  std::vector<int> hb((size_t)nt * (nrows + 1)), tr0(nt + 1);
+  HIPCHECK(h, hipMemcpyAsync(hb.data(), base, sizeof(int) * hb.size(), hipMemcpyDeviceToHost, st));
+  HIPCHECK(h, hipMemcpyAsync(tr0.data(), A.type_row0, sizeof(int) * (nt + 1), hipMemcpyDeviceToHost, st));
+  HIPCHECK(h, hipStreamSynchronize(st));
+  int32_t stw[STW_N];
+  HIPCHECK(h, hipMemcpy(stw, A.status, sizeof(stw), hipMemcpyDeviceToHost));
+  if (stw[STW_FLAGS] & (ST_BAD_TYPE | ST_NONFINITE | ST_OVERLAP | ST_GHOST_CAP | ST_CAPACITY))
+    return dp_status(h, workspace, stream, nullptr, nullptr);
+  PGradArgs G{};
+  G.m = A.m;
+  G.nrows = nrows;
+  G.fw = h->fit_w[0];
+  G.nfit = h->n_fit;
+  long np = 0;
+  for (int b = 0; b < nt; b++) {
+    G.base[b] = base + (size_t)b * (nrows + 1);
+    G.boff[b] = (int)np;
+    np += hb[(size_t)b * (nrows + 1) + nrows];
+  }
+  if (np > L.np_max) return fail(h, DP_ERR_CAPACITY, "pair rows exceed the workspace plan");
+  G.np = (int)np;
+  for (int a = 0; a < nt; a++)
+    for (int b = 0; b < nt; b++) {
+      const int* bb = hb.data() + (size_t)b * (nrows + 1);
+      G.group[(a * nt + b) * 2] = G.boff[b] + bb[tr0[a]];
+      G.group[(a * nt + b) * 2 + 1] = bb[tr0[a + 1]] - bb[tr0[a]];
+    }
+  for (int t = 0; t <= nt; t++) G.type_row0_h[t] = tr0[t];
+  // device copies of the base pointers and offsets
+  char* pt = W.at<char>(L.o_ptrs);
+  HIPCHECK(h, hipMemcpy(pt, G.base, sizeof(void*) * kMaxTypes, hipMemcpyHostToDevice));
+  HIPCHECK(h, hipMemcpy(pt + sizeof(void*) * kMaxTypes, G.boff, sizeof(int) * kMaxTypes, hipMemcpyHostToDevice));
+  G.base_dev = (const int* const*)pt;
+  G.boff_dev = (const int*)(pt + sizeof(void*) * kMaxTypes);
+  ParamIndex PI = index_params(h);
+  G.eW = PI.eW.data();
+  G.eB = PI.eB.data();
+  G.fW = PI.fW.data();
+  G.fB = PI.fB.data();
+  G.theta = h->d_theta;
+  double* gtan = W.at<double>(L.o_gtan);
+  launch_zero(gtan, h->nparams, st);
+  G.gtheta_tan = gtan;
+  G.row_atom = A.row_atom;
+  G.nnei = A.nnei;
+  G.nlist = A.nlist;
+  G.eown = A.eown;
+  G.xe = A.xe;
+  G.vdir = gF;
+  G.gE = gE;
+  G.frame_of = A.frame_of;
+  G.scratch = W.at<void>(L.o_scr);
+  G.scratch_bytes = L.scr_bytes;
+  if (launch_param_grad(G, st) != 0) return fail(h, DP_ERR_WORKSPACE, "param-grad scratch too small");
+  launch_axpy(h->nparams, -1.0, gtan, gtheta, st);
   HIPCHECK(h, hipGetLastError());
   return DP_OK;
 }

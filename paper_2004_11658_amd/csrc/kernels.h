@@ -101,6 +101,37 @@ void launch_frame_reduce(int nframes, const Frame* frames, const int* row_of, co
 void launch_export_T(int prec, int n, int M, const int* row_of, const void* Tm, const void* gT,
                      double* To, double* gTo, hipStream_t st);
 
+// ---------------------------------------------------------------- parameter gradient
+struct PGradArgs {
+  ModelC m;
+  int nrows, np, fw, nfit;
+  const double* theta;       // flat FP64 parameters (model-file order)
+  double* gtheta_tan;        // tangent part of the parameter adjoint (accumulated)
+  const int* row_atom;
+  const int* nnei;
+  const int* nlist;
+  const int* eown;
+  const double* xe;
+  const double* vdir;        // gF [n][3]: tangent direction of the coordinates
+  const double* gE;          // [nframes]
+  const int* frame_of;
+  const int* base[kMaxTypes];  // per neighbour species: exclusive scan over rows [nrows+1]
+  int boff[kMaxTypes];         // first pair row of each neighbour-species block
+  const int* const* base_dev;  // device copies of base[] and boff[]
+  const int* boff_dev;
+  int group[2 * kMaxTypes * kMaxTypes];  // (first pair row, count) per species pair
+  int type_row0_h[kMaxTypes + 1];
+  const int64_t *eW, *eB, *fW, *fB;      // parameter offsets (host)
+  void* scratch;
+  size_t scratch_bytes;
+};
+size_t param_grad_scratch_bytes(int nrows, long np_max, int M, int m2, int s0, int fw, int nfit);
+int launch_param_grad(const PGradArgs& a, hipStream_t st);
+void launch_pair_scan(int nrows, int ntypes, int beta, const int* row_atom, const int* nnei, int* base,
+                      int* sums, int* total, hipStream_t st);
+void launch_scatter_params(int prec, size_t n, const int* map, const double* theta, void* dst, hipStream_t st);
+void launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t st);
+
 struct MDMass {
   double m[kMaxTypes];
   double inv[kMaxTypes];

@@ -543,6 +543,52 @@ void launch_nlist(const NlistArgs& A, hipStream_t st) {
   hipLaunchKernelGGL(k_row_atoms, dim3(nb), dim3(256), 0, st, n, A.row_of, A.row_atom);
 }
 
+struct LoadPairCount {
+  const int* row_atom;
+  const int* nnei;
+  int ntypes, beta, nrows;
+  __device__ IV<1> operator()(int r) const {
+    IV<1> v;
+    int a = r < nrows ? row_atom[r] : -1;
+    v.v[0] = a >= 0 ? nnei[a * ntypes + beta] : 0;
+    return v;
+  }
+};
+
+// exclusive scan over species-grouped rows of each centre's real neighbours of
+// species beta: base [nrows + 1] (base[nrows] = total)
+void launch_pair_scan(int nrows, int ntypes, int beta, const int* row_atom, const int* nnei, int* base,
+                      int* sums, int* total, hipStream_t st) {
+  scan_launch<1>(nrows + 1, LoadPairCount{row_atom, nnei, ntypes, beta, nrows}, base, sums, total, st);
+}
+
+__global__ void k_scatter_params_d(size_t n, const int* __restrict__ map, const double* __restrict__ th,
+                                   double* __restrict__ dst) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) dst[q] = map[q] >= 0 ? th[map[q]] : 0.0;
+}
+__global__ void k_scatter_params_f(size_t n, const int* __restrict__ map, const double* __restrict__ th,
+                                   float* __restrict__ dst) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) dst[q] = map[q] >= 0 ? (float)th[map[q]] : 0.0f;
+}
+// weights in the kernels' layouts from the flat parameter vector via an index map
+void launch_scatter_params(int prec, size_t n, const int* map, const double* theta, void* dst, hipStream_t st) {
+  if (!n) return;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_scatter_params_d, dim3((n + 255) / 256), dim3(256), 0, st, n, map, theta, (double*)dst);
+  else
+    hipLaunchKernelGGL(k_scatter_params_f, dim3((n + 255) / 256), dim3(256), 0, st, n, map, theta, (float*)dst);
+}
+
+__global__ void k_axpy(size_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) y[q] += a * x[q];
+}
+void launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_axpy, dim3((n + 255) / 256), dim3(256), 0, st, n, a, x, y);
+}
+
 void launch_nlist_export(int n, int nm, const int* nlist, const int* eown, const int* eimg,
                          const int* frame_of, const Frame* frames, int* out_j, int* out_img,
                          hipStream_t st) {

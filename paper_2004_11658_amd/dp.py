@@ -50,6 +50,10 @@ def _load():
         "dp_status": ([P, P, P, P, P], C.c_int),
         "dp_md_run": ([P, I64, P, P, P, P, P, D, I32, I32, P, P, P, SZ, P], C.c_int),
         "dp_profile": ([P, I32], C.c_int),
+        "dp_set_params": ([P, P, P], C.c_int),
+        "dp_get_params": ([P, P, P], C.c_int),
+        "dp_param_grad_workspace_size": ([P, I32, P, P, P], C.c_int),
+        "dp_param_grad": ([P, I32, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
         "dp_profile_read": ([P, I32, P, P], C.c_int),
         "dp_strerror": ([C.c_int], C.c_char_p),
         "dp_last_error": ([P], C.c_char_p),
@@ -233,3 +237,75 @@ class DPModel:
         ms, cnt = C.c_double(), C.c_int64()
         self._check(_lib.dp_profile_read(self.h, STAGES[stage], C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
+
+    # ------------------------------------------------------------------ parameters
+    def get_params(self) -> torch.Tensor:
+        th = torch.empty(self.nparams, dtype=torch.float64, device=self.device)
+        self._check(_lib.dp_get_params(self.h, _ptr(th), _stream()))
+        return th
+
+    def set_params(self, theta: torch.Tensor):
+        th = self._dev(theta.detach(), torch.float64)
+        assert th.numel() == self.nparams
+        self._check(_lib.dp_set_params(self.h, _ptr(th), _stream()))
+
+    def param_grad(self, coords, types, offsets, boxes, gE, gF, max_atoms: int = 8192) -> torch.Tensor:
+        """sum_f gE_f dE_f/dtheta + sum_i gF_i . dF_i/dtheta for a ragged batch (FP64)."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        b = _box9(boxes)
+        nf = len(off) - 1
+        gE = self._dev(gE, torch.float64).reshape(nf)
+        gF = self._dev(gF, torch.float64).reshape(-1, 3)
+        gt = torch.zeros(self.nparams, dtype=torch.float64, device=x.device)
+        f0 = 0
+        while f0 < nf:                      # frames in chunks of at most max_atoms atoms
+            f1 = f0 + 1
+            while f1 < nf and off[f1 + 1] - off[f0] <= max_atoms:
+                f1 += 1
+            sub = np.ascontiguousarray(off[f0:f1 + 1] - off[f0])
+            a0, a1 = int(off[f0]), int(off[f1])
+            bb = np.ascontiguousarray(b[f0:f1])
+            nb = C.c_size_t()
+            self._check(_lib.dp_param_grad_workspace_size(self.h, f1 - f0, sub.ctypes.data_as(C.c_void_p),
+                                                          bb.ctypes.data_as(C.c_void_p), C.byref(nb)))
+            ws = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
+            xs, ts = x[a0:a1].contiguous(), t[a0:a1].contiguous()
+            gEs, gFs = gE[f0:f1].contiguous(), gF[a0:a1].contiguous()
+            self._check(_lib.dp_param_grad(self.h, f1 - f0, sub.ctypes.data_as(C.c_void_p), _ptr(xs), _ptr(ts),
+                                           bb.ctypes.data_as(C.c_void_p), _ptr(gEs), _ptr(gFs), _ptr(gt),
+                                           _ptr(ws), ws.numel(), _stream()))
+            f0 = f1
+        return gt
+
+
+class DPEnergyForce(torch.autograd.Function):
+    """(E [nframes], F [natoms][3]) = DP-SE(theta; batch), differentiable in theta.
+
+    forward runs dp_compute_batch with theta installed; backward runs dp_param_grad,
+    which returns sum_f gE_f dE_f/dtheta + sum_i gF_i . dF_i/dtheta exactly.
+    Coordinates, types and boxes receive no gradient."""
+
+    @staticmethod
+    def forward(ctx, theta, model: DPModel, coords, types, offsets, boxes):
+        model.set_params(theta)
+        E, F, _ = model.compute_batch(coords, types, offsets, boxes)
+        ctx.model = model
+        ctx.batch = (coords, types, offsets, boxes)
+        ctx.save_for_backward(theta)
+        return E, F
+
+    @staticmethod
+    def backward(ctx, gE, gF):
+        (theta,) = ctx.saved_tensors
+        model = ctx.model
+        coords, types, offsets, boxes = ctx.batch
+        nf = len(offsets) - 1
+        if gE is None:
+            gE = torch.zeros(nf, dtype=torch.float64, device=theta.device)
+        if gF is None:
+            gF = torch.zeros(int(offsets[-1]), 3, dtype=torch.float64, device=theta.device)
+        model.set_params(theta)
+        g = model.param_grad(coords, types, offsets, boxes, gE.contiguous(), gF.contiguous())
+        return g.to(theta.dtype), None, None, None, None, None

@@ -1,0 +1,119 @@
+"""GPU parameter gradient of the energy + force loss (dp_param_grad and the
+torch.autograd.Function) against the oracle's double back propagation (PyTorch-CPU
+FP64) and against central finite differences of GPU energies and forces.
+
+Bar: max |g_gpu - g_oracle| <= 1e-9 max |g_oracle| (both exact FP64 derivatives; the
+difference is summation order over ~1e5 terms).  Finite differences: h = 1e-6 on
+sampled parameters, tolerance 1e-5 relative (truncation O(h^2) and cancellation).
+"""
+import numpy as np
+import pytest
+
+from paper_2004_11658_amd import inputs as I
+from oracle.oracle import Oracle, set_threads
+from oracle import torch_ref as TR
+from conftest import TINY, model_file, tiny_water
+
+pytestmark = pytest.mark.gpu
+set_threads(8)
+
+
+@pytest.fixture(scope="module")
+def dp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_11658_amd import dp as D
+    return D
+
+
+def _frames(which):
+    if which == "tiny":
+        fr = [I.water_lattice(1, 3.2, 31), tiny_water(32, 2, 6.3), tiny_water(33, 2, 6.6)]
+    else:
+        allf = I.ragged_water_batch(64, 204)
+        sizes = np.argsort([len(f[1]) for f in allf])
+        fr = [allf[k] for k in sizes[:3]]
+    return fr
+
+
+def _targets(o, frames, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for (c, t, b) in frames:
+        r = o.eval(c, t, b)
+        out.append((r["E"] + rng.normal(0, 0.5), r["F"] + rng.normal(0, 0.02, r["F"].shape)))
+    return out
+
+
+@pytest.mark.parametrize("which", ["tiny", "water"])
+def test_param_grad_matches_oracle(dp, which, tiny_model, water_model):
+    import torch
+    path = tiny_model if which == "tiny" else water_model
+    frames = _frames(which)
+    print("case", which, [len(f[1]) for f in frames], flush=True)
+    o = Oracle(path)
+    tg = _targets(o, frames, 5)
+    lam = 1.0
+    arch = TR.Arch(path)
+    ofr = []
+    for (c, t, b), (Et, Ft) in zip(frames, tg):
+        nl, img, _, _ = o.nlist(c, t, b)
+        ofr.append((c, t, b, nl, img, Et, Ft))
+    L_ref, g_ref = TR.loss_and_grad(arch, arch.params, ofr, lam)
+    # GPU: loss through the autograd.Function, gradient by backward()
+    m = dp.DPModel(path)
+    coords = np.concatenate([f[0] for f in frames])
+    types = np.concatenate([f[1] for f in frames])
+    boxes = np.stack([f[2] for f in frames])
+    off = np.concatenate([[0], np.cumsum([len(f[1]) for f in frames])])
+    theta = torch.as_tensor(arch.params, device="cuda").clone().requires_grad_(True)
+    E, F = dp.DPEnergyForce.apply(theta, m, coords, types, off, boxes)
+    Et = torch.as_tensor([x[0] for x in tg], device="cuda")
+    Ft = torch.as_tensor(np.concatenate([x[1] for x in tg]), device="cuda")
+    nat = torch.as_tensor(np.diff(off), device="cuda", dtype=torch.float64)
+    L = (((E - Et) ** 2) / nat).sum() + lam * ((F - Ft) ** 2).sum()
+    L.backward()
+    g = theta.grad.cpu().numpy()
+    assert abs(float(L) - L_ref) <= 1e-10 * abs(L_ref)
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print("grad rel err", err, flush=True)
+    assert err < 1e-9
+
+
+def test_param_grad_finite_differences(dp, tiny_model):
+    """Central differences of the GPU loss on sampled parameters of every tensor."""
+    import torch
+    frames = _frames("tiny")
+    o = Oracle(tiny_model)
+    tg = _targets(o, frames, 6)
+    arch = TR.Arch(tiny_model)
+    m = dp.DPModel(tiny_model)
+    coords = np.concatenate([f[0] for f in frames])
+    types = np.concatenate([f[1] for f in frames])
+    boxes = np.stack([f[2] for f in frames])
+    off = np.concatenate([[0], np.cumsum([len(f[1]) for f in frames])])
+    Et = torch.as_tensor([x[0] for x in tg], device="cuda")
+    Ft = torch.as_tensor(np.concatenate([x[1] for x in tg]), device="cuda")
+    nat = torch.as_tensor(np.diff(off), device="cuda", dtype=torch.float64)
+
+    def loss(th):
+        E, F = dp.DPEnergyForce.apply(th, m, coords, types, off, boxes)
+        return (((E - Et) ** 2) / nat).sum() + ((F - Ft) ** 2).sum()
+
+    th0 = torch.as_tensor(arch.params, device="cuda").clone().requires_grad_(True)
+    loss(th0).backward()
+    g = th0.grad.cpu().numpy()
+    rng = np.random.default_rng(3)
+    picks = []
+    for lay in list(arch.emb.values()) + list(arch.fit.values()):
+        for (woff, (ni, no), boff) in lay:
+            picks += [woff + int(rng.integers(0, ni * no)), boff + int(rng.integers(0, no))]
+    h = 1e-6
+    base = th0.detach().clone()
+    for q in picks:
+        tp, tm = base.clone(), base.clone()
+        tp[q] += h
+        tm[q] -= h
+        fd = (float(loss(tp)) - float(loss(tm))) / (2 * h)
+        assert abs(fd - g[q]) <= 1e-5 * max(abs(g[q]), 1e-3 * np.abs(g).max()), (q, fd, g[q])
