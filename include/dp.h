@@ -154,6 +154,57 @@ int dp_param_grad(dp_handle h, int32_t nframes, const int64_t* atom_offsets, con
                   const int32_t* types, const double* boxes, const double* gE, const double* gF,
                   double* gtheta, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- student embedding net (a narrower G_s(s) = tanh(s W1 + b1) W2 + b2, 1 -> H -> M,
+ * trained to reproduce the full embedding net on the s range the model visits) ---- */
+
+/* s values of the real neighbours of species beta around centres of species alpha in
+ * one frame, each kept when its uniform number (uniforms [natoms][N_m] device floats,
+ * one per neighbour slot) is below keep_prob, written to s_out [cap] (device) in slot
+ * order.  *count (host) receives the number kept (may exceed cap: the rest are
+ * dropped).  Synchronises the stream.  The workspace must hold
+ * dp_student_samples_workspace_size bytes. */
+int dp_student_samples_workspace_size(dp_handle h, int64_t natoms, const double* box, size_t* bytes);
+int dp_student_samples(dp_handle h, int32_t alpha, int32_t beta, int64_t natoms, const double* coords,
+                       const int32_t* types, const double* box, const float* uniforms, double keep_prob,
+                       double* s_out, int64_t cap, int64_t* count, void* workspace, size_t ws_bytes,
+                       void* stream);
+
+/* The full embedding net G^{alpha,beta} (Eq. 7-9) at n given s (device), in FP64 with the
+ * current parameters: G [n][M] device. */
+int dp_embed_eval(dp_handle h, int32_t alpha, int32_t beta, int64_t n, const double* s, double* G,
+                  void* stream);
+
+/* Student MSE loss L = mean over samples and outputs of (G_s(s) - G)^2 and its gradient:
+ * theta_s [2H + H M + M] device (W1 [H], b1 [H], W2 [H][M] row major, b2 [M]),
+ * s [n], G [n][M] device; loss [1] device is ADDED to; grad device is overwritten.
+ * scratch: dp_student_scratch_size bytes of device memory. */
+int dp_student_scratch_size(int32_t hidden, int32_t M, int64_t n, size_t* bytes);
+int dp_student_loss_grad(int32_t hidden, int32_t M, int64_t n, const double* s, const double* G,
+                         const double* theta_s, double* loss, double* grad, void* scratch,
+                         size_t scratch_bytes, void* stream);
+
+/* Least-squares output layer of a student: with W1, b1 of theta_s fixed, sets W2, b2 to
+ * the minimiser of sum (G_s(s) - G)^2 by the normal equations with a ridge of
+ * ridge * max diag (Cholesky on the device); hidden <= 32.  scratch:
+ * dp_student_lsq_scratch_size bytes of device memory. */
+int dp_student_lsq_scratch_size(int32_t hidden, int32_t M, int64_t n, size_t* bytes);
+int dp_student_lsq(int32_t hidden, int32_t M, int64_t n, const double* s, const double* G, double* theta_s,
+                   double ridge, void* scratch, size_t scratch_bytes, void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) on n device doubles: theta, moments m, v. */
+int dp_adam(int64_t n, double* theta, double* m, double* v, const double* g, int32_t step, double lr,
+            double beta1, double beta2, double eps, void* stream);
+
+/* Install (enable = 1) or remove (enable = 0) student embedding nets for inference.
+ * theta_s (device, FP64): ntypes^2 consecutive student parameter blocks, species pair
+ * (alpha, beta) at index alpha * ntypes + beta, each laid out as for
+ * dp_student_loss_grad with hidden width 1..32.  s_lo, s_hi (host [ntypes^2]): the s
+ * range each student was trained on.  While enabled, every compute, MD and descriptor
+ * call uses the student for neighbours with s in [s_lo, s_hi] and the full net (FP64)
+ * for the others.  Workspaces must be sized after this call. */
+int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const double* s_lo,
+                   const double* s_hi, int32_t enable, void* stream);
+
 /* Stage timing with HIP events recorded on the call's stream around each stage
  * (neighbour list, embedding forward, fitting net, embedding adjoint, reductions,
  * integration).  dp_profile(h, 1) clears the records and enables timing,

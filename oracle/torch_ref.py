@@ -124,8 +124,12 @@ def decode_img(img: np.ndarray, K):
 
 
 def energy(arch: Arch, theta: torch.Tensor, x: torch.Tensor, types: np.ndarray,
-           box: np.ndarray, nlist: np.ndarray, img: np.ndarray):
-    """E and E_i of one frame (Eq. 1) for a formatted neighbour list (Alg. 1)."""
+           box: np.ndarray, nlist: np.ndarray, img: np.ndarray, student=None):
+    """E and E_i of one frame (Eq. 1) for a formatted neighbour list (Alg. 1).
+
+    student: optional {(a, b): (theta_s, H, s_lo, s_hi)}: for those species pairs G(s)
+    is the student net 1 -> H tanh -> M affine where s_lo <= s <= s_hi and the full
+    net elsewhere."""
     n = len(types)
     B = torch.as_tensor(box)
     K = box_K(arch, box)
@@ -150,7 +154,13 @@ def energy(arch: Arch, theta: torch.Tensor, x: torch.Tensor, types: np.ndarray,
         for b in range(arch.ntypes):
             m = np.nonzero((ti == a) & (st == b))[0]
             if m.size:
-                G = G.index_copy(0, torch.as_tensor(m), embed(arch, theta, a, b, s[m]))
+                g = embed(arch, theta, a, b, s[m])
+                if student is not None and (a, b) in student:
+                    ths, H, lo, hi = student[(a, b)]
+                    gs = student_forward(torch.as_tensor(ths), H, arch.M, s[m])
+                    inr = ((s[m] >= lo) & (s[m] <= hi))[:, None]
+                    g = torch.where(inr, gs, g)
+                G = G.index_copy(0, torch.as_tensor(m), g)
     norm = float(arch.nm) if arch.desc_norm == 0 else 1.0
     T = torch.zeros(n, arch.M, 4).index_add(0, torch.as_tensor(ii),
                                             G[:, :, None] * R[:, None, :]) / norm
@@ -163,9 +173,9 @@ def energy(arch: Arch, theta: torch.Tensor, x: torch.Tensor, types: np.ndarray,
     return Ei.sum(), Ei
 
 
-def energy_forces(arch: Arch, theta, coords, types, box, nlist, img, create_graph=False):
+def energy_forces(arch: Arch, theta, coords, types, box, nlist, img, create_graph=False, student=None):
     x = torch.as_tensor(np.asarray(coords, np.float64)).clone().requires_grad_(True)
-    E, Ei = energy(arch, theta, x, np.asarray(types), np.asarray(box), nlist, img)
+    E, Ei = energy(arch, theta, x, np.asarray(types), np.asarray(box), nlist, img, student)
     (gx,) = torch.autograd.grad(E, x, create_graph=create_graph)
     return E, -gx, Ei
 

@@ -36,6 +36,13 @@ struct dp_handle_s {
   int* d_fit_map = nullptr;        // fitting buffer <- theta index
   int* d_bo_map = nullptr;         // output biases <- theta index
   size_t net_elems = 0, fit_elems = 0;
+  // student embedding nets
+  bool student_on = false;
+  int student_hidden = 0;
+  void* d_student = nullptr;       // [nnet][kStuElems] storage type
+  int* d_student_map = nullptr;
+  double st_lo[kMaxTypes * kMaxTypes] = {}, st_hi[kMaxTypes * kMaxTypes] = {};
+  int64_t* d_net_off = nullptr;    // [nnet][6] parameter offsets of the full nets
   // pinned staging for per-call frame tables: a ring of slots, each reused only
   // after the copy that last read it has completed
   static constexpr int kSlots = 8;
@@ -298,6 +305,14 @@ static int upload_weights(dp_handle h) {
   for (size_t q = 0; q < offO.size(); q++) ptrs.push_back(base + offO[q] * sb);
   HIPCHECK(h, hipMalloc(&h->d_ptrs, ptrs.size() * sizeof(void*)));
   HIPCHECK(h, hipMemcpy(h->d_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice));
+  std::vector<int64_t> noff((size_t)nnet * 6);
+  for (int net = 0; net < nnet; net++)
+    for (int k = 0; k < 3; k++) {
+      noff[net * 6 + 2 * k] = P.eW[net * 3 + k];
+      noff[net * 6 + 2 * k + 1] = P.eB[net * 3 + k];
+    }
+  HIPCHECK(h, hipMalloc(&h->d_net_off, sizeof(int64_t) * noff.size()));
+  HIPCHECK(h, hipMemcpy(h->d_net_off, noff.data(), sizeof(int64_t) * noff.size(), hipMemcpyHostToDevice));
   int rc = refresh_weights(h, nullptr);
   if (rc != DP_OK) return rc;
   HIPCHECK(h, hipDeviceSynchronize());
@@ -305,6 +320,12 @@ static int upload_weights(dp_handle h) {
 }
 
 static void release_weights(dp_handle h) {
+  if (h->d_student) (void)hipFree(h->d_student);
+  if (h->d_student_map) (void)hipFree(h->d_student_map);
+  if (h->d_net_off) (void)hipFree(h->d_net_off);
+  h->d_student = nullptr;
+  h->d_student_map = nullptr;
+  h->d_net_off = nullptr;
   if (h->d_theta) (void)hipFree(h->d_theta);
   if (h->d_net_map) (void)hipFree(h->d_net_map);
   if (h->d_fit_map) (void)hipFree(h->d_fit_map);
@@ -367,7 +388,7 @@ struct Plan {
   size_t o_status, o_frames, o_frame_of, o_xw, o_fw, o_gcount, o_goff, o_small, o_scan;
   size_t o_xe, o_eown, o_eimg, o_etype, o_ecell, o_ccount, o_cstart, o_cfill, o_catoms;
   size_t o_nlist, o_nnei, o_tpos, o_rowof, o_rowatom, o_T, o_gT, o_D, o_Dg, o_act, o_xs, o_g0,
-      o_g1, o_Ei, o_vir, o_tmpj, o_tmpi, o_mdF, o_mdE, o_mdW;
+      o_g1, o_Ei, o_vir, o_tmpj, o_tmpi, o_mdF, o_mdE, o_mdW, o_fb, o_fbcnt;
   int n, nframes, ncell, ghost_cap, nrows;
 };
 
@@ -450,6 +471,8 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
   P.o_mdF = take(sizeof(double) * 3 * n);
   P.o_mdE = take(sizeof(double) * nframes);
   P.o_mdW = take(sizeof(double) * 9 * nframes);
+  P.o_fb = h->student_on ? take(sizeof(int2) * n * h->nm) : 0;
+  P.o_fbcnt = take(sizeof(int) * 64);
   P.total = o;
   return DP_OK;
 }
@@ -593,9 +616,22 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
   E.vir_part = W.at<double>(P.o_vir);
   E.frame_of = A.frame_of;
   E.nframes = P.nframes;
+  if (h->student_on) {
+    E.snets = h->d_student;
+    memcpy(E.st_lo, h->st_lo, sizeof(E.st_lo));
+    memcpy(E.st_hi, h->st_hi, sizeof(E.st_hi));
+    E.fb_list = W.at<int2>(P.o_fb);
+    E.fb_count = W.at<int>(P.o_fbcnt);
+    E.fb_cap = P.n * h->nm;
+    E.theta = h->d_theta;
+    E.net_off = h->d_net_off;
+    E.etype = A.etype;
+    launch_zero_int(E.fb_count, 1, st);
+  }
   {
     StageTimer tm(h, DP_STAGE_EMBED_FWD, st);
-    launch_embed_fwd(E, st);
+    if (h->student_on) launch_student_fwd(E, st);
+    else launch_embed_fwd(E, st);
   }
   HIPCHECK(h, hipGetLastError());
   FitArgs F{};
@@ -632,7 +668,8 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
   if (want_forces) {
     launch_zero(forces, (size_t)P.n * 3, st);
     StageTimer tm(h, DP_STAGE_EMBED_BWD, st);
-    launch_embed_bwd(E, st);
+    if (h->student_on) launch_student_bwd(E, st);
+    else launch_embed_bwd(E, st);
   }
   HIPCHECK(h, hipGetLastError());
   {
@@ -976,6 +1013,153 @@ int dp_param_grad(dp_handle h, int32_t nframes, const int64_t* atom_offsets, con
   launch_axpy(h->nparams, -1.0, gtan, gtheta, st);
   HIPCHECK(h, hipGetLastError());
   return DP_OK;
+}
+
+int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const double* s_lo,
+                   const double* s_hi, int32_t enable, void* stream) {
+  if (!h) return DP_ERR_ARG;
+  if (!enable) {
+    h->student_on = false;
+    return DP_OK;
+  }
+  if (!theta_s || !s_lo || !s_hi || hidden < 1 || hidden > kP0)
+    return fail(h, DP_ERR_ARG, "student: bad arguments (hidden must be 1..32)");
+  const int nnet = h->ntypes * h->ntypes, M = h->M;
+  const size_t size = 2 * (size_t)hidden + (size_t)hidden * M + M;
+  if (h->d_student && h->student_hidden != hidden) {
+    (void)hipFree(h->d_student);
+    (void)hipFree(h->d_student_map);
+    h->d_student = nullptr;
+    h->d_student_map = nullptr;
+  }
+  if (!h->d_student) {
+    std::vector<int> map((size_t)nnet * kStuElems, -1);
+    for (int net = 0; net < nnet; net++) {
+      int* b = map.data() + (size_t)net * kStuElems;
+      size_t o = net * size;
+      for (int j = 0; j < hidden; j++) {
+        b[kSW1 + j] = (int)(o + j);
+        b[kSB1 + j] = (int)(o + hidden + j);
+      }
+      for (int p = 0; p < kP2; p++) {
+        int f = pos_feature(p, h->s0);
+        if (f < 0) continue;
+        b[kSB2 + p] = (int)(o + 2 * hidden + (size_t)hidden * M + f);
+        for (int j = 0; j < hidden; j++) b[kSW2 + j * kSW2Stride + p] = (int)(o + 2 * hidden + (size_t)j * M + f);
+      }
+    }
+    HIPCHECK(h, hipMalloc(&h->d_student_map, sizeof(int) * map.size()));
+    HIPCHECK(h, hipMemcpy(h->d_student_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMalloc(&h->d_student, map.size() * storage_bytes(h->opt.precision)));
+    h->student_hidden = hidden;
+  }
+  launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, (size_t)nnet * kStuElems, h->d_student_map,
+                        theta_s, h->d_student, (hipStream_t)stream);
+  HIPCHECK(h, hipGetLastError());
+  for (int q = 0; q < nnet; q++) {
+    h->st_lo[q] = s_lo[q];
+    h->st_hi[q] = s_hi[q];
+  }
+  h->student_on = true;
+  return DP_OK;
+}
+
+int dp_student_samples(dp_handle h, int32_t alpha, int32_t beta, int64_t natoms, const double* coords,
+                       const int32_t* types, const double* box, const float* uniforms, double keep_prob,
+                       double* s_out, int64_t cap, int64_t* count, void* workspace, size_t ws_bytes,
+                       void* stream) {
+  if (!h) return DP_ERR_ARG;
+  if (!box || !uniforms || !s_out || !count || cap < 0) return fail(h, DP_ERR_ARG, "null argument");
+  if (alpha < 0 || alpha >= h->ntypes || beta < 0 || beta >= h->ntypes) return fail(h, DP_ERR_ARG, "bad species");
+  hipStream_t st = (hipStream_t)stream;
+  int64_t off[2] = {0, natoms};
+  Plan P;
+  NlistArgs A{};
+  size_t extra = al(sizeof(int) * (size_t)natoms * h->nm) * 2 + al(sizeof(int) * (scan_sums_ints((int)(natoms * h->nm), 1) + 16));
+  {
+    Plan Q;
+    int rc = make_plan(h, 1, off, box, nullptr, Q);
+    if (rc != DP_OK) return rc;
+    if (!workspace || ws_bytes < Q.total + extra) return fail(h, DP_ERR_WORKSPACE, "workspace too small");
+  }
+  int rc = stage_frames_and_nlist(h, 1, off, box, coords, types, workspace, ws_bytes, st, P, A);
+  if (rc != DP_OK) return rc;
+  char* base = (char*)workspace + P.total;
+  int* flag = (int*)base;
+  int* pos = (int*)(base + al(sizeof(int) * (size_t)natoms * h->nm));
+  int* sums = (int*)(base + 2 * al(sizeof(int) * (size_t)natoms * h->nm));
+  int* total = sums + scan_sums_ints((int)(natoms * h->nm), 1) + 8;
+  launch_student_gather((int)natoms, A.m, alpha, beta, types, A.nnei, A.nlist, A.xe, uniforms, (float)keep_prob,
+                        flag, pos, sums, total, (long)cap, s_out, st);
+  HIPCHECK(h, hipGetLastError());
+  int tot = 0;
+  HIPCHECK(h, hipMemcpyAsync(&tot, total, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHECK(h, hipStreamSynchronize(st));
+  *count = tot;
+  return dp_status(h, workspace, stream, nullptr, nullptr);
+}
+
+int dp_student_samples_workspace_size(dp_handle h, int64_t natoms, const double* box, size_t* bytes) {
+  if (!h || !box || !bytes) return DP_ERR_ARG;
+  int64_t off[2] = {0, natoms};
+  Plan P;
+  int rc = make_plan(h, 1, off, box, nullptr, P);
+  if (rc != DP_OK) return rc;
+  *bytes = P.total + al(sizeof(int) * (size_t)natoms * h->nm) * 2 +
+           al(sizeof(int) * (scan_sums_ints((int)(natoms * h->nm), 1) + 16));
+  return DP_OK;
+}
+
+int dp_embed_eval(dp_handle h, int32_t alpha, int32_t beta, int64_t n, const double* s, double* G, void* stream) {
+  if (!h || !s || !G || n < 0) return fail(h, DP_ERR_ARG, "bad argument");
+  if (alpha < 0 || alpha >= h->ntypes || beta < 0 || beta >= h->ntypes) return fail(h, DP_ERR_ARG, "bad species");
+  ParamIndex PI = index_params(h);
+  int net = alpha * h->ntypes + beta;
+  const double* th[6];
+  for (int k = 0; k < 3; k++) {
+    th[2 * k] = h->d_theta + PI.eW[net * 3 + k];
+    th[2 * k + 1] = h->d_theta + PI.eB[net * 3 + k];
+  }
+  launch_full_eval((long)n, h->s0, th, s, G, (hipStream_t)stream);
+  HIPCHECK(h, hipGetLastError());
+  return DP_OK;
+}
+
+int dp_student_scratch_size(int32_t hidden, int32_t M, int64_t n, size_t* bytes) {
+  if (!bytes || hidden < 1 || M < 1 || n < 0) return DP_ERR_ARG;
+  *bytes = student_scratch_bytes((long)n, hidden, M);
+  return DP_OK;
+}
+
+int dp_student_loss_grad(int32_t hidden, int32_t M, int64_t n, const double* s, const double* G,
+                         const double* theta_s, double* loss, double* grad, void* scratch,
+                         size_t scratch_bytes, void* stream) {
+  if (!s || !G || !theta_s || !loss || !grad || !scratch || hidden < 1 || M < 1 || n < 1) return DP_ERR_ARG;
+  if (scratch_bytes < student_scratch_bytes((long)n, hidden, M)) return DP_ERR_WORKSPACE;
+  launch_student_loss_grad((long)n, hidden, M, s, G, theta_s, loss, grad, scratch, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? DP_OK : DP_ERR_HIP;
+}
+
+int dp_student_lsq_scratch_size(int32_t hidden, int32_t M, int64_t n, size_t* bytes) {
+  if (!bytes || hidden < 1 || hidden > 32 || M < 1 || n < 0) return DP_ERR_ARG;
+  *bytes = student_lsq_scratch_bytes((long)n, hidden, M);
+  return DP_OK;
+}
+
+int dp_student_lsq(int32_t hidden, int32_t M, int64_t n, const double* s, const double* G, double* theta_s,
+                   double ridge, void* scratch, size_t scratch_bytes, void* stream) {
+  if (!s || !G || !theta_s || !scratch || hidden < 1 || hidden > 32 || M < 1 || n < 1 || !(ridge >= 0))
+    return DP_ERR_ARG;
+  if (scratch_bytes < student_lsq_scratch_bytes((long)n, hidden, M)) return DP_ERR_WORKSPACE;
+  launch_student_lsq((long)n, hidden, M, s, G, theta_s, ridge, scratch, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? DP_OK : DP_ERR_HIP;
+}
+
+int dp_adam(int64_t n, double* theta, double* m, double* v, const double* g, int32_t step, double lr,
+            double beta1, double beta2, double eps, void* stream) {
+  if (!theta || !m || !v || !g || n < 0 || step < 1) return DP_ERR_ARG;
+  launch_adam((size_t)n, theta, m, v, g, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? DP_OK : DP_ERR_HIP;
 }
 
 int dp_profile(dp_handle h, int32_t enable) {

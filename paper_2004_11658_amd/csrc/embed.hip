@@ -27,85 +27,9 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
-#include "kernels.h"
-#include "devmath.h"
+#include "embed_common.h"
 
 namespace dp {
-
-typedef double d4v __attribute__((ext_vector_type(4)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-
-template <class T> struct Acc4;
-template <> struct Acc4<double> { typedef d4v type; };
-template <> struct Acc4<float> { typedef f4v type; };
-
-__device__ __forceinline__ d4v mfma4(double a, double b, d4v c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-template <class T>
-__device__ __forceinline__ T tanh_t(T x) { return dp_tanh(x); }
-
-// Accumulator row held by lane group g in register q of a 16x16 MFMA result:
-// FP64 16x16x4 returns rows g + 4q, FP32 16x16x4 (and BF16 16x16x32) rows 4g + q.
-__device__ __forceinline__ int lpos(double, int g, int q) { return g + 4 * q; }
-__device__ __forceinline__ int lpos(float, int g, int q) { return 4 * g + q; }
-#define LP(g, q) lpos(T(), g, q)
-
-template <class T>
-__device__ __forceinline__ T shfl_x(T v, int mask) {
-  return __shfl_xor(v, mask);
-}
-
-// Cross-lane moves inside a 16-lane row with DPP (VALU, no LDS traffic).  The
-// reduce-scatter over the 16 rows of a chunk pairs lanes by xor 8 (row_ror:8), xor 7
-// (row_half_mirror), xor 2 and xor 1 (quad_perm); these partner offsets span the row.
-enum { DPP_ROR8 = 0x128, DPP_HALF_MIRROR = 0x141, DPP_XOR2 = 0x4E, DPP_XOR1 = 0xB1 };
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-  long long x = __builtin_bit_cast(long long, v);
-  int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
-  int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// species of the rows starting at r0 (rows of one block never straddle species)
-__device__ __forceinline__ int species_of(int r0, int ntypes, const int* __restrict__ type_row0) {
-  for (int t = 0; t < ntypes; t++)
-    if (r0 >= type_row0[t] && r0 < type_row0[t + 1]) return t;
-  return -1;
-}
-
-template <class T>
-__device__ __forceinline__ void stage_net(T* __restrict__ dst, const T* __restrict__ src) {
-  for (int q = threadIdx.x; q < kNetElems; q += blockDim.x) dst[q] = src[q];
-}
-
-// Environment row of one neighbour (Eq. 5) and its derivative with respect to d.
-struct Env {
-  double d[3], r, s, ds, R[4];
-};
-__device__ __forceinline__ void env_row(const ModelC& m, const double* __restrict__ xe, int e,
-                                        const double xi[3], Env& v) {
-  v.d[0] = xe[3 * e] - xi[0];
-  v.d[1] = xe[3 * e + 1] - xi[1];
-  v.d[2] = xe[3 * e + 2] - xi[2];
-  double r2 = v.d[0] * v.d[0] + v.d[1] * v.d[1] + v.d[2] * v.d[2];
-  v.r = sqrt(r2);
-  smooth_fn(m, v.r, v.s, v.ds);
-  double sr = v.s / v.r;
-  v.R[0] = v.s;
-  v.R[1] = sr * v.d[0];
-  v.R[2] = sr * v.d[1];
-  v.R[3] = sr * v.d[2];
-}
 
 // forward chain of one 16-row chunk: t0 (L0 = tanh), t1, t2 (tanh parts of L1, L2)
 template <class T>
@@ -156,19 +80,6 @@ template <class T>
 __device__ __forceinline__ T g_at(const T (&t0)[2][4], const T (&t1)[4][4], const T (&t2)[8][4],
                                   int mt, int q) {
   return t0[mt & 1][q] + t1[mt & 3][q] + t2[mt][q];
-}
-
-// one reduce-scatter step on an array of S values: the lane whose "up" bit is set
-// keeps the upper half, its DPP partner (which has the bit clear) the lower half
-template <class T, int S, int CTRL>
-__device__ __forceinline__ void rs_step(T (&v)[64], bool up) {
-#pragma unroll
-  for (int k = 0; k < S / 2; k++) {
-    T a = v[k], b = v[k + S / 2];
-    T send = up ? a : b;
-    T keep = up ? b : a;
-    v[k] = keep + dpp_mov<CTRL>(send);
-  }
 }
 
 // ------------------------------------------------------------------------------------

@@ -45,6 +45,12 @@ constexpr int kNetElems = kOffW2 + kP1 * kW2Stride;
 
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2, PREC_BF16X3 = 3 };
 
+// Position-padded student block (1 -> H <= 32 tanh -> M affine): W1, b1 at hidden
+// positions 0..31, b2 at the output positions of G, W2 [32][kP2 + 1].
+constexpr int kSW1 = 0, kSB1 = kP0, kSB2 = 2 * kP0, kSW2 = 2 * kP0 + kP2;
+constexpr int kSW2Stride = kP2 + 1;
+constexpr int kStuElems = kSW2 + kP0 * kSW2Stride;
+
 struct EmbedArgs {
   int prec;
   int nrows;           // padded species-grouped rows
@@ -63,8 +69,19 @@ struct EmbedArgs {
   double* vir_part;    // backward: per-centre virial [nrows][9]
   const int* frame_of;
   int nframes;
+  // student inference
+  const void* snets;         // [ntypes*ntypes] student blocks (storage type)
+  double st_lo[kMaxTypes * kMaxTypes], st_hi[kMaxTypes * kMaxTypes];
+  int2* fb_list;             // fallback rows (species row, extended neighbour index)
+  int* fb_count;
+  int fb_cap;
+  const double* theta;       // flat FP64 parameters (fallback rows use the full net)
+  const int64_t* net_off;    // [ntypes*ntypes][6] offsets of W0, b0, W1, b1, W2, b2
+  const int* etype;
 };
 void launch_embed_fwd(const EmbedArgs& a, hipStream_t st);
+void launch_student_fwd(const EmbedArgs& a, hipStream_t st);
+void launch_student_bwd(const EmbedArgs& a, hipStream_t st);
 void launch_embed_bwd(const EmbedArgs& a, hipStream_t st);
 int embed_bwd_blocks(int nrows);
 
@@ -131,6 +148,22 @@ void launch_pair_scan(int nrows, int ntypes, int beta, const int* row_atom, cons
                       int* sums, int* total, hipStream_t st);
 void launch_scatter_params(int prec, size_t n, const int* map, const double* theta, void* dst, hipStream_t st);
 void launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t st);
+void launch_zero_int(int* p, int n, hipStream_t st);
+
+// ---------------------------------------------------------------- student net
+void launch_student_gather(int n, const ModelC& m, int alpha, int beta, const int* types, const int* nnei,
+                           const int* nlist, const double* xe, const float* u, float keep, int* flag,
+                           int* pos, int* sums, int* total, long cap, double* out, hipStream_t st);
+void launch_full_eval(long n, int s0, const double* th_net[6], const double* s, double* G, hipStream_t st);
+size_t student_scratch_bytes(long n, int H, int M);
+void launch_student_loss_grad(long n, int H, int M, const double* s, const double* G, const double* th,
+                              double* loss, double* grad, void* scratch, hipStream_t st);
+size_t student_lsq_scratch_bytes(long n, int H, int M);
+void launch_student_lsq(long n, int H, int M, const double* s, const double* G, double* th, double ridge,
+                        void* scratch, hipStream_t st);
+void launch_adam(size_t n, double* th, double* m, double* v, const double* g, double lr, double b1, double b2,
+                 double eps, int t, hipStream_t st);
+size_t scan_sums_ints(int n, int W);
 
 struct MDMass {
   double m[kMaxTypes];

@@ -543,6 +543,11 @@ void launch_nlist(const NlistArgs& A, hipStream_t st) {
   hipLaunchKernelGGL(k_row_atoms, dim3(nb), dim3(256), 0, st, n, A.row_of, A.row_atom);
 }
 
+// exclusive scan of n ints (out [n], total [1])
+void launch_scan_int(int n, const int* in, int* out, int* sums, int* total, hipStream_t st) {
+  scan_launch<1>(n, LoadInt{in}, out, sums, total, st);
+}
+
 struct LoadPairCount {
   const int* row_atom;
   const int* nnei;
@@ -585,6 +590,10 @@ __global__ void k_axpy(size_t n, double a, const double* __restrict__ x, double*
   size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < n) y[q] += a * x[q];
 }
+void launch_zero_int(int* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, n, p, 0);
+}
+
 void launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_axpy, dim3((n + 255) / 256), dim3(256), 0, st, n, a, x, y);
 }

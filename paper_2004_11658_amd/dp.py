@@ -54,6 +54,15 @@ def _load():
         "dp_get_params": ([P, P, P], C.c_int),
         "dp_param_grad_workspace_size": ([P, I32, P, P, P], C.c_int),
         "dp_param_grad": ([P, I32, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
+        "dp_student_samples_workspace_size": ([P, I64, P, P], C.c_int),
+        "dp_student_samples": ([P, I32, I32, I64, P, P, P, P, D, P, I64, P, P, SZ, P], C.c_int),
+        "dp_embed_eval": ([P, I32, I32, I64, P, P, P], C.c_int),
+        "dp_student_scratch_size": ([I32, I32, I64, P], C.c_int),
+        "dp_student_loss_grad": ([I32, I32, I64, P, P, P, P, P, P, SZ, P], C.c_int),
+        "dp_adam": ([I64, P, P, P, P, I32, D, D, D, D, P], C.c_int),
+        "dp_student_lsq_scratch_size": ([I32, I32, I64, P], C.c_int),
+        "dp_student_lsq": ([I32, I32, I64, P, P, P, D, P, SZ, P], C.c_int),
+        "dp_set_student": ([P, I32, P, P, P, I32, P], C.c_int),
         "dp_profile_read": ([P, I32, P, P], C.c_int),
         "dp_strerror": ([C.c_int], C.c_char_p),
         "dp_last_error": ([P], C.c_char_p),
@@ -238,6 +247,46 @@ class DPModel:
         self._check(_lib.dp_profile_read(self.h, STAGES[stage], C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
 
+    # ------------------------------------------------------------------ student
+    def student_samples(self, alpha: int, beta: int, coords, types, box, uniforms: torch.Tensor,
+                        keep: float, cap: int):
+        """s of real (alpha, beta) neighbours kept where uniforms < keep (slot order)."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        n = x.shape[0]
+        b = _box9(box)
+        nb = C.c_size_t()
+        self._check(_lib.dp_student_samples_workspace_size(self.h, n, b.ctypes.data_as(C.c_void_p), C.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
+        out = torch.empty(max(cap, 1), dtype=torch.float64, device=x.device)
+        cnt = C.c_int64()
+        u = uniforms.to(device=x.device, dtype=torch.float32).contiguous()
+        assert u.numel() == n * self.nm
+        self._check(_lib.dp_student_samples(self.h, alpha, beta, n, _ptr(x), _ptr(t), b.ctypes.data_as(C.c_void_p),
+                                            _ptr(u), float(keep), _ptr(out), cap, C.byref(cnt), _ptr(ws),
+                                            ws.numel(), _stream()))
+        return out[:min(cnt.value, cap)], cnt.value
+
+    def embed_eval(self, alpha: int, beta: int, s: torch.Tensor) -> torch.Tensor:
+        """The full embedding net G^{alpha,beta}(s) in FP64: [n][M]."""
+        s = self._dev(s, torch.float64)
+        G = torch.empty(s.numel(), self.M, dtype=torch.float64, device=s.device)
+        self._check(_lib.dp_embed_eval(self.h, alpha, beta, s.numel(), _ptr(s), _ptr(G), _stream()))
+        return G
+
+    def set_student(self, hidden: int, theta_s: Optional[torch.Tensor], s_lo=None, s_hi=None, enable: bool = True):
+        if not enable:
+            self._check(_lib.dp_set_student(self.h, hidden, None, None, None, 0, _stream()))
+            self._ws = None
+            return
+        th = self._dev(theta_s, torch.float64)
+        assert th.numel() == self.ntypes ** 2 * student_size(hidden, self.M)
+        lo = np.ascontiguousarray(s_lo, dtype=np.float64)
+        hi = np.ascontiguousarray(s_hi, dtype=np.float64)
+        self._check(_lib.dp_set_student(self.h, hidden, _ptr(th), lo.ctypes.data_as(C.c_void_p),
+                                        hi.ctypes.data_as(C.c_void_p), 1, _stream()))
+        self._ws = None       # workspace layout changes with the student's fallback list
+
     # ------------------------------------------------------------------ parameters
     def get_params(self) -> torch.Tensor:
         th = torch.empty(self.nparams, dtype=torch.float64, device=self.device)
@@ -278,6 +327,47 @@ class DPModel:
                                            _ptr(ws), ws.numel(), _stream()))
             f0 = f1
         return gt
+
+
+def student_size(hidden: int, M: int) -> int:
+    return 2 * hidden + hidden * M + M
+
+
+def student_loss_grad(hidden: int, M: int, s: torch.Tensor, G: torch.Tensor, theta_s: torch.Tensor,
+                      scratch: Optional[torch.Tensor] = None):
+    """Student MSE loss and gradient on the GPU (loss [1], grad [size] device tensors)."""
+    n = s.numel()
+    nb = C.c_size_t()
+    _lib.dp_student_scratch_size(hidden, M, n, C.byref(nb))
+    if scratch is None or scratch.numel() < nb.value:
+        scratch = torch.empty(nb.value, dtype=torch.uint8, device=s.device)
+    loss = torch.zeros(1, dtype=torch.float64, device=s.device)
+    grad = torch.empty(student_size(hidden, M), dtype=torch.float64, device=s.device)
+    rc = _lib.dp_student_loss_grad(hidden, M, n, _ptr(s), _ptr(G), _ptr(theta_s), _ptr(loss), _ptr(grad),
+                                   _ptr(scratch), scratch.numel(), _stream())
+    if rc != DP_OK:
+        raise DPError(rc, "dp_student_loss_grad failed")
+    return loss, grad, scratch
+
+
+def student_lsq(hidden: int, M: int, s: torch.Tensor, G: torch.Tensor, theta_s: torch.Tensor,
+                ridge: float = 1e-13):
+    """Least-squares output layer (W2, b2 of theta_s) for the given hidden layer."""
+    nb = C.c_size_t()
+    _lib.dp_student_lsq_scratch_size(hidden, M, s.numel(), C.byref(nb))
+    scratch = torch.empty(nb.value, dtype=torch.uint8, device=s.device)
+    rc = _lib.dp_student_lsq(hidden, M, s.numel(), _ptr(s), _ptr(G), _ptr(theta_s), float(ridge),
+                             _ptr(scratch), scratch.numel(), _stream())
+    if rc != DP_OK:
+        raise DPError(rc, "dp_student_lsq failed")
+
+
+def adam_step(theta: torch.Tensor, m: torch.Tensor, v: torch.Tensor, g: torch.Tensor, step: int, lr: float,
+              b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    rc = _lib.dp_adam(theta.numel(), _ptr(theta), _ptr(m), _ptr(v), _ptr(g), int(step), float(lr), b1, b2, eps,
+                      _stream())
+    if rc != DP_OK:
+        raise DPError(rc, "dp_adam failed")
 
 
 class DPEnergyForce(torch.autograd.Function):

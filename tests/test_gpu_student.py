@@ -1,0 +1,187 @@
+"""Student embedding net on the GPU: training kernels against the oracle, inference
+(student inside [s_lo, s_hi], full net outside) against the oracle's energy with the
+same substitution, and the gain of the trained student over the full net.
+
+Bars: loss / gradient / Adam / full-net evaluation / gathered s: 1e-12 relative (FP64,
+reduction order only); FP64 inference E 1e-10, F 1e-9 (as the force path); the trained
+student's forces: RMSE <= 1e-3 relative to the FP64 full model (the metric's bar).
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from paper_2004_11658_amd import inputs as I
+from oracle.oracle import Oracle, set_threads
+from oracle import torch_ref as TR
+
+pytestmark = pytest.mark.gpu
+set_threads(8)
+
+
+@pytest.fixture(scope="module")
+def dp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_11658_amd import dp as D
+    return D
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def test_student_loss_grad_and_adam(dp):
+    import torch
+    H, M, n = 32, 100, 777
+    rng = np.random.default_rng(1)
+    th = rng.normal(0, 0.5, dp.student_size(H, M))
+    s = rng.uniform(0, 1.2, n)
+    G = rng.normal(0, 1, (n, M))
+    L_ref, g_ref = TR.student_loss_grad(th, H, M, s, G)
+    d = lambda a: torch.as_tensor(a, device="cuda")
+    loss, g, _ = dp.student_loss_grad(H, M, d(s), d(G), d(th))
+    assert abs(float(loss.item()) - L_ref) <= 1e-12 * L_ref
+    assert _rel(g.cpu().numpy(), g_ref) < 1e-12
+    m0 = rng.normal(0, 0.1, th.size)
+    v0 = rng.uniform(0, 0.1, th.size)
+    t_ref, m_ref, v_ref = TR.adam_step(th, m0, v0, g_ref, 7, 1e-3)
+    tt, mm, vv = d(th).clone(), d(m0).clone(), d(v0).clone()
+    dp.adam_step(tt, mm, vv, d(g_ref), 7, 1e-3)
+    assert _rel(tt.cpu().numpy(), t_ref) < 1e-14
+    assert _rel(mm.cpu().numpy(), m_ref) < 1e-14 and _rel(vv.cpu().numpy(), v_ref) < 1e-14
+
+
+def test_student_learns_a_student_shaped_teacher(dp):
+    """Learnability: targets from a net of the student's own shape.  With the teacher's
+    hidden layer, the least-squares kernel recovers the output layer exactly; from a
+    perturbed output layer, Adam with the gradient kernel drives the loss to ~0."""
+    import torch
+    H, M, n = 32, 100, 20000
+    rng = np.random.default_rng(2)
+    teacher = rng.normal(0, 0.5, dp.student_size(H, M))
+    teacher[:H] *= 3.0
+    s = rng.uniform(0, 1.2, n)
+    G = TR.student_forward(torch.as_tensor(teacher), H, M, torch.as_tensor(s)).numpy()
+    d = lambda a: torch.as_tensor(a, device="cuda")
+    sd, Gd = d(s), d(G)
+    th = d(np.concatenate([teacher[:2 * H], np.zeros(H * M + M)]))
+    dp.student_lsq(H, M, sd, Gd, th, ridge=1e-13)
+    loss, _, _ = dp.student_loss_grad(H, M, sd, Gd, th)
+    rms2 = float((G ** 2).mean())
+    print("least-squares loss / mean G^2", float(loss.item()) / rms2, flush=True)
+    assert float(loss.item()) < 1e-12 * rms2
+    pert = teacher.copy()
+    pert[2 * H:] += rng.normal(0, 0.05, pert.size - 2 * H)
+    th = d(pert)
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    loss, g, sc = dp.student_loss_grad(H, M, sd, Gd, th)
+    L0 = float(loss.item())
+    for step in range(1, 3001):
+        lr = 3e-3 * (0.001 + 0.999 * 0.5 * (1 + math.cos(math.pi * (step - 1) / 3000)))
+        dp.adam_step(th, m, v, g, step, lr)
+        loss, g, sc = dp.student_loss_grad(H, M, sd, Gd, th, sc)
+    print("student loss", L0, "->", float(loss.item()), flush=True)
+    assert float(loss.item()) < 1e-6 * L0
+
+
+def test_full_net_eval_and_sample_gather(dp, water_model, water192):
+    import torch
+    c, t, b = water192
+    m = dp.DPModel(water_model)
+    arch = TR.Arch(water_model)
+    o = Oracle(water_model)
+    nl, img, nnei, _ = o.nlist(c, t, b)
+    for (a, bb) in [(0, 1), (1, 1)]:
+        u = torch.zeros(len(t) * m.nm, dtype=torch.float32)
+        s, cnt = m.student_samples(a, bb, c, t, b, u, 1.0, 10 ** 6)
+        # oracle: s of every real (a, bb) neighbour
+        off = sum(I.WATER.sel[:bb])
+        rows = [(i, k) for i in range(len(t)) if t[i] == a for k in range(off, off + I.WATER.sel[bb])
+                if nl[i, k] >= 0]
+        K = TR.box_K(arch, b)
+        wrap = np.floor(c @ np.linalg.inv(b))
+        d = []
+        for i, k in rows:
+            j = nl[i, k]
+            n = TR.decode_img(np.array([img[i, k]]), K)[0]
+            d.append(c[j] - c[i] + (n - wrap[j] + wrap[i]) @ b)
+        r = np.linalg.norm(np.array(d), axis=1)
+        so, _ = o.smooth(r)
+        assert cnt == len(rows)
+        assert _rel(np.sort(s.cpu().numpy()), np.sort(so)) < 1e-13
+        G = m.embed_eval(a, bb, s).cpu().numpy()
+        Gr = TR.embed(arch, torch.as_tensor(arch.params), a, bb, torch.as_tensor(s.cpu().numpy())).numpy()
+        assert _rel(G, Gr) < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_student_inference_matches_oracle(dp, water_model, water192, prec):
+    """Untrained random students with a narrow range, so that part of the neighbours
+    falls back to the full net: E and F against the oracle's substituted model."""
+    import torch
+    c, t, b = water192
+    H, M = 32, 100
+    rng = np.random.default_rng(4)
+    ths = [rng.normal(0, 0.3, dp.student_size(H, M)) for _ in range(4)]
+    lo = np.array([0.05, 0.1, 0.1, 0.05])
+    hi = np.array([0.6, 0.5, 0.55, 0.7])
+    m = dp.DPModel(water_model, prec)
+    m.set_student(H, torch.as_tensor(np.concatenate(ths), device="cuda"), lo, hi)
+    E, F, W = m.compute(c, t, b)
+    arch = TR.Arch(water_model)
+    o = Oracle(water_model)
+    nl, img, _, _ = o.nlist(c, t, b)
+    st = {(a, bb): (ths[2 * a + bb], H, lo[2 * a + bb], hi[2 * a + bb]) for a in range(2) for bb in range(2)}
+    Er, Fr, _ = TR.energy_forces(arch, torch.as_tensor(arch.params), c, t, b, nl, img, student=st)
+    Er, Fr = float(Er.detach()), Fr.numpy()
+    tolE, tolF = (1e-10, 1e-9) if prec == "fp64" else (1e-5, 1e-3)
+    dE = abs(float(E.cpu()[0]) - Er) / abs(Er)
+    dF = np.linalg.norm(F.cpu().numpy() - Fr, axis=1).max() / np.linalg.norm(Fr, axis=1).max()
+    print(prec, "student inference dE", dE, "dF", dF, flush=True)
+    assert dE < tolE and dF < tolF
+
+
+def test_student_gain_over_full_net(dp, water_model):
+    """Trained on frames of the full model's own FP64 MD, the FP32 student meets the force
+    bar against the FP64 full model and makes the MD step faster than the FP32 full net."""
+    import torch
+    from paper_2004_11658_amd import student as S
+    c, t, b = I.config_water12k(202)
+    masses = [I.MASS["O"], I.MASS["H"]]
+    v = I.maxwell_velocities(t, masses, 300.0, 302)
+    full64 = dp.DPModel(water_model, "fp64")
+    x = torch.as_tensor(c, device="cuda").clone()
+    vd = torch.as_tensor(v, device="cuda").clone()
+    frames = []
+    for k in range(4):
+        frames.append((x.clone(), t, b))
+        full64.md_run(x, vd, t, masses, b, 0.5, 10, 0)
+    th, lo, hi, rep = S.train_students(full64, frames, hidden=32, n_samples=400000)
+    print("student training", rep, flush=True)
+    # force error at a later frame of the trajectory, identical coordinates
+    full64.md_run(x, vd, t, masses, b, 0.5, 10, 0)
+    _, F64, _ = full64.compute(x, t, b)
+    stu = dp.DPModel(water_model, "fp32")
+    stu.set_student(32, th, lo, hi)
+    _, Fs, _ = stu.compute(x, t, b)
+    rmse = float(torch.sqrt(((Fs - F64) ** 2).mean()) / torch.sqrt((F64 ** 2).mean()))
+    full32 = dp.DPModel(water_model, "fp32")
+
+    def step_time(model):
+        xx, vv = x.clone(), vd.clone()
+        model.md_run(xx, vv, t, masses, b, 0.5, 3, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        model.md_run(xx, vv, t, masses, b, 0.5, 30, 0)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / 30
+
+    t_full, t_stu = step_time(full32), step_time(stu)
+    print("student force RMSE rel %.3e, step %.3f ms (full fp32 %.3f ms), gain %.2fx"
+          % (rmse, 1e3 * t_stu, 1e3 * t_full, t_full / t_stu), flush=True)
+    assert rmse <= 1e-3
+    assert t_stu < t_full
