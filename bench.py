@@ -11,11 +11,17 @@ headline value is the fastest mode whose force RMSE (relative to FP64 at identic
 coordinates) is at most 1e-3, as the metric asks.  The FP64 CPU oracle is timed on a
 bounded sample (one force evaluation of the same frame) as the CPU baseline.
 
-    python bench.py [--gpus 1] [--steps 100] [--warmup 3] [--modes fp64,fp32]
+    python bench.py [--gpus 1] [--steps 100] [--warmup 3] [--modes fp64,fp32,fp32+student]
+
+Modes: fp64, fp32, bf16, bf16x3 (operand precision of the embedding and fitting GEMMs),
+and "<precision>+student": the student embedding nets, trained before timing on frames
+of the FP64 full model's own MD of the same system (sampling, targets and fit all run in
+the library's kernels), with the full net as fallback outside their s range.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,16 +39,54 @@ DTYPE = {"fp64": "f64", "fp32": "f32 operands, f32 accumulate", "bf16": "bf16 op
          "bf16x3": "bf16x3 operands, f32 accumulate"}
 
 
-def algorithmic_flops(spec, rows, natoms):
-    """Algorithmic FLOPs of one force evaluation (real neighbours only, no padding)."""
+STUDENT_HIDDEN = 32
+
+
+def algorithmic_flops(spec, rows, natoms, student=False):
+    """Algorithmic FLOPs of one force evaluation (real neighbours only, no padding).
+    Per neighbour row: the embedding chain (Eq. 7-9) or the student net, the
+    contraction T += G^T R (Eq. 4), and in the adjoint the recomputed chain, dE/dG,
+    dE/dR and the chain's input gradients.  Per atom: descriptor, fitting net forward
+    and backward (Eq. 1-4)."""
     s0, s1, M = spec.emb_width
-    emb_fwd_row = 2 * s0 + 2 * s0 * s1 + 2 * s1 * M          # L0, L1, L2 (Eq. 7-9)
-    contract_row = 2 * M * 4                                 # T += G^T R (Eq. 4)
-    emb_bwd_row = emb_fwd_row + (2 * M * 4) * 2 + 2 * s1 * M + 2 * s0 * s1 + 2 * s0
+    if student:
+        H = STUDENT_HIDDEN
+        chain = 2 * H + 2 * H * M
+        chain_bwd = 2 * H * M + 2 * H
+    else:
+        chain = 2 * s0 + 2 * s0 * s1 + 2 * s1 * M
+        chain_bwd = 2 * s1 * M + 2 * s0 * s1 + 2 * s0
+    contract_row = 2 * M * 4
+    emb_fwd_row = chain + contract_row
+    emb_bwd_row = chain + 2 * contract_row + chain_bwd
     K1, fw, nf = spec.M * spec.m2, spec.fit_width[0], len(spec.fit_width)
     fit_atom = 2 * (2 * K1 * fw + 2 * fw * fw * (nf - 1) + 2 * fw) + 2 * spec.M * spec.m2 * 4 * 3
-    return dict(embed_fwd=rows * (emb_fwd_row + contract_row), embed_bwd=rows * emb_bwd_row,
-                fit=natoms * fit_atom, emb_bwd_row=emb_bwd_row, emb_fwd_row=emb_fwd_row + contract_row)
+    return dict(embed_fwd=rows * emb_fwd_row, embed_bwd=rows * emb_bwd_row, fit=natoms * fit_atom,
+                emb_bwd_row=emb_bwd_row, emb_fwd_row=emb_fwd_row, fit_atom=fit_atom)
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources: counter-based traffic figures apply only to these."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2004_11658_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch of kernel from the committed counter summary, if it was
+    measured on the current sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
 
 
 def main():
@@ -50,9 +94,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="fp64,fp32")
+    ap.add_argument("--modes", default="fp64,fp32,fp32+student")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU spatial decomposition is "
@@ -60,6 +106,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy_mb:
+        n = args.calibrate_copy_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
     from paper_2004_11658_amd import inputs as I
     from paper_2004_11658_amd import dp as D
 
@@ -87,8 +142,28 @@ def main():
     if "fp64" not in modes:
         modes = ["fp64"] + modes
     rows = None
+    student = None
     for mode in modes:
-        model = D.DPModel(path, mode)
+        prec, _, extra = mode.partition("+")
+        model = D.DPModel(path, prec)
+        if extra == "student":
+            if student is None:
+                # training data: frames of the FP64 full model's own trajectory
+                from paper_2004_11658_amd import student as S
+                full = D.DPModel(path, "fp64")
+                xs, vs = x0.clone(), v0.clone()
+                frames = []
+                for k in range(4):
+                    frames.append((xs.clone(), t_dev, box))
+                    full.md_run(xs, vs, t_dev, masses, box, dt, 10, 0)
+                tt = time.perf_counter()
+                th, lo, hi, rep = S.train_students(full, frames, hidden=STUDENT_HIDDEN,
+                                                   n_samples=1_000_000)
+                torch.cuda.synchronize()
+                student = (th, lo, hi, rep, time.perf_counter() - tt)
+                log("student training %.1f s" % student[4], json.dumps(rep))
+                del full
+            model.set_student(STUDENT_HIDDEN, student[0], student[1], student[2])
         if rows is None:
             _, _, nn, _ = model.nlist(x0, t_dev, box)
             rows = int(nn.sum().item())
@@ -117,7 +192,7 @@ def main():
         thermo = th.cpu().numpy()
         drift = float(np.abs(thermo[:, 4] - thermo[0, 4]).max() / n)
         results[mode] = dict(value=n * args.steps / wall, ms_per_step=1e3 * wall / args.steps,
-                             force_rmse_rel=rmse, energy_drift_ev_per_atom=drift,
+                             force_rmse_rel=rmse, energy_drift_ev_per_atom=drift, student=extra == "student",
                              stages_ms={s: round(v_[0] / max(v_[1], 1), 5) for s, v_ in stages.items()},
                              stage_launches={s: v_[1] for s, v_ in stages.items()})
         log(mode, json.dumps(results[mode]))
@@ -126,15 +201,29 @@ def main():
     ok = [m for m in modes if results[m]["force_rmse_rel"] <= 1e-3]
     head = max(ok, key=lambda m: results[m]["value"])
     R = results[head]
-    fl = algorithmic_flops(spec, rows, n)
+    hprec = head.partition("+")[0]
+    fl = algorithmic_flops(spec, rows, n, student=R["student"])
+    # achieved rate of each compute stage (HIP-event average per launch)
+    stage_rates = {}
+    for st_, key in [("embed_fwd", "embed_fwd"), ("fit", "fit"), ("embed_bwd", "embed_bwd")]:
+        ms = R["stages_ms"][st_]
+        stage_rates[st_] = round(fl[key] / (ms * 1e-3) / 1e12, 3) if ms > 0 else None
+    for m_ in modes:
+        flm = algorithmic_flops(spec, rows, n, student=results[m_]["student"])
+        results[m_]["stage_tflops"] = {s_: (round(flm[s_] / (results[m_]["stages_ms"][s_] * 1e-3) / 1e12, 3)
+                                            if results[m_]["stages_ms"][s_] > 0 else None)
+                                       for s_ in ("embed_fwd", "fit", "embed_bwd")}
     bwd_ms = R["stages_ms"]["embed_bwd"]
     achieved = fl["embed_bwd"] / (bwd_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[head]
-    roofline = dict(bound="mfma", kernel="k_embed_bwd (embedding adjoint with recompute)",
+    peak = PEAK_TFLOPS[hprec]
+    kname = ("k_student_bwd<%s> (student embedding adjoint)" if R["student"]
+             else "k_embed_bwd<%s> (embedding adjoint with recompute)") % ("double" if hprec == "fp64" else "float")
+    roofline = dict(bound="mfma", kernel=kname,
                     achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                    frac=round(achieved / peak, 4), traffic=None,
+                    frac=round(achieved / peak, 4), traffic=traffic_for(kname.split(" ")[0]),
                     flops_per_launch=fl["embed_bwd"], rows_per_launch=rows,
-                    flops_per_row=fl["emb_bwd_row"], avg_launch_ms=bwd_ms)
+                    flops_per_row=fl["emb_bwd_row"], avg_launch_ms=bwd_ms,
+                    stage_tflops=stage_rates, source_hash=kernel_source_hash())
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -154,7 +243,7 @@ def main():
         "metric": METRIC, "value": round(R["value"], 2), "unit": "atom-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(R["ms_per_step"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": DTYPE[head], "data": "synthetic",
+        "dtype": DTYPE[hprec] + (", student embedding" if R["student"] else ""), "data": "synthetic",
         "config": {"workload": "water 12,288 atoms (4,096 H2O, 49.7 A cube), velocity-Verlet MD "
                                "dt 0.5 fs from 300 K, DP-SE rc 6 A sel 46/92 emb 25x50x100 "
                                "fit 240^3, random weights", "atoms": n, "mode": head,
@@ -163,6 +252,7 @@ def main():
         "cpu_baseline": cpu,
         "modes": {m: {k: (round(v_, 6) if isinstance(v_, float) else v_) for k, v_ in r.items()}
                   for m, r in results.items()},
+        "student_training": None if student is None else dict(seconds=round(student[4], 2), pairs=student[3]),
     }
     print(json.dumps(line), flush=True)
 

@@ -207,12 +207,13 @@ int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const dou
 
 /* Stage timing with HIP events recorded on the call's stream around each stage
  * (neighbour list, embedding forward, fitting net, embedding adjoint, reductions,
- * integration).  dp_profile(h, 1) clears the records and enables timing,
+ * integration, and with student nets the full-net fallback rows of both passes;
+ * each of EMBED_FWD and EMBED_BWD is then one kernel launch).  dp_profile(h, 1) clears the records and enables timing,
  * dp_profile(h, 0) stops recording and keeps the records for dp_profile_read.
  * dp_profile_read synchronises the events and returns the summed milliseconds and the
  * number of launches of one stage (DP_STAGE_*). */
 enum { DP_STAGE_NLIST = 0, DP_STAGE_EMBED_FWD = 1, DP_STAGE_FIT = 2, DP_STAGE_EMBED_BWD = 3,
-       DP_STAGE_REDUCE = 4, DP_STAGE_MD = 5, DP_NSTAGES = 6 };
+       DP_STAGE_REDUCE = 4, DP_STAGE_MD = 5, DP_STAGE_FALLBACK = 6, DP_NSTAGES = 7 };
 int dp_profile(dp_handle h, int32_t enable);
 int dp_profile_read(dp_handle h, int32_t stage, double* total_ms, int64_t* launches);
 

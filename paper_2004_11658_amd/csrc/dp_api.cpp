@@ -36,6 +36,10 @@ struct dp_handle_s {
   int* d_fit_map = nullptr;        // fitting buffer <- theta index
   int* d_bo_map = nullptr;         // output biases <- theta index
   size_t net_elems = 0, fit_elems = 0;
+  // BF16 modes: packed MFMA operands (16-bit units) and their index maps
+  uint16_t* d_fitb = nullptr;
+  int* d_fitb_map = nullptr;
+  size_t fitb_elems = 0;
   // student embedding nets
   bool student_on = false;
   int student_hidden = 0;
@@ -248,10 +252,59 @@ static void net_block_map(dp_handle h, const ParamIndex& P, int net, int* blk) {
   }
 }
 
+static bool bf16_mode(int prec) { return prec == PREC_BF16 || prec == PREC_BF16X3; }
+
+// index map of one BF16 net block (16-bit units, layout in kernels.h): code 4 idx + kind
+// with kind 0 / 1 the hi / lo BF16 part and 2 a float over two units (-2 marks the second
+// unit), -1 zero.  Packed tile t, lane (g, rb), element j: the k slot stands for input
+// position 16 (2 kc + j / 4) + 4 g + j % 4 of the product, the lane row rb for output
+// position 16 t' + rb (t = t' * nkc + kc).
+static void bnet_block_map(dp_handle h, const ParamIndex& P, int net, int parts, int* blk) {
+  int s0 = h->s0, s1 = 2 * s0, s2 = 4 * s0;
+  const int nu = bnet_u16(parts);
+  for (int q = 0; q < nu; q++) blk[q] = -1;
+  std::vector<int> fl(kNetElems);
+  net_block_map(h, P, net, fl.data());
+  for (int q = 0; q < kBFloat; q++) {
+    blk[2 * q] = fl[q] >= 0 ? 4 * fl[q] + 2 : -1;
+    blk[2 * q + 1] = fl[q] >= 0 ? -2 : -1;
+  }
+  // W[in pos][out pos] of layer L (1 or 2) as a parameter index, -1 for pads
+  auto widx = [&](int L, int pin, int pout) -> int {
+    int fi = pos_feature(pin, s0), fo = pos_feature(pout, s0);
+    if (fi < 0 || fo < 0) return -1;
+    return (int)(P.eW[net * 3 + L] + (int64_t)fi * (L == 1 ? s1 : s2) + fo);
+  };
+  // group: base (u16) of part 0, part stride, layer, number of k chunks, forward or adjoint
+  auto fill = [&](int base, int pstride, int L, int ntile, int nkc, bool fwd) {
+    for (int part = 0; part < parts; part++)
+      for (int t = 0; t < ntile; t++)
+        for (int kc = 0; kc < nkc; kc++)
+          for (int lane = 0; lane < 64; lane++)
+            for (int j = 0; j < 8; j++) {
+              int g = lane >> 4, rb = lane & 15;
+              int kpos = 16 * (2 * kc + j / 4) + 4 * g + j % 4;
+              int opos = 16 * t + rb;
+              int idx = fwd ? widx(L, kpos, opos) : widx(L, opos, kpos);
+              blk[base + part * pstride + ((t * nkc + kc) * 64 + lane) * 8 + j] = idx >= 0 ? 4 * idx + part : -1;
+            }
+  };
+  const int f0 = 2 * kBFloat, b0 = f0 + parts * kBFwd;
+  fill(f0, kBFwd, 1, 4, 1, true);
+  fill(f0 + kBW1F, kBFwd, 2, 8, 2, true);
+  fill(b0, kBBwd, 1, 2, 2, false);
+  fill(b0 + kBW1B, kBBwd, 2, 4, 4, false);
+}
+
 // device layouts of the weights, rebuilt from d_theta by index maps
 static int refresh_weights(dp_handle h, hipStream_t st) {
-  launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, h->net_elems, h->d_net_map, h->d_theta,
-                        h->d_nets, st);
+  if (bf16_mode(h->opt.precision)) {
+    launch_pack_bf16(h->net_elems, h->d_net_map, h->d_theta, (uint16_t*)h->d_nets, st);
+    launch_pack_bf16(h->fitb_elems, h->d_fitb_map, h->d_theta, h->d_fitb, st);
+  } else {
+    launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, h->net_elems, h->d_net_map, h->d_theta,
+                          h->d_nets, st);
+  }
   launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, h->fit_elems, h->d_fit_map, h->d_theta,
                         h->d_fit, st);
   launch_scatter_params(0, h->ntypes, h->d_bo_map, h->d_theta, h->d_bo, st);
@@ -263,8 +316,38 @@ static int upload_weights(dp_handle h) {
   ParamIndex P = index_params(h);
   const int sb = storage_bytes(h->opt.precision);
   int nnet = h->ntypes * h->ntypes;
-  std::vector<int> nmap((size_t)nnet * kNetElems);
-  for (int net = 0; net < nnet; net++) net_block_map(h, P, net, nmap.data() + (size_t)net * kNetElems);
+  const bool bf = bf16_mode(h->opt.precision);
+  const int parts = prec_parts(h->opt.precision);
+  const size_t blk_units = bf ? (size_t)bnet_u16(parts) : (size_t)kNetElems;
+  std::vector<int> nmap((size_t)nnet * blk_units);
+  for (int net = 0; net < nnet; net++) {
+    if (bf) bnet_block_map(h, P, net, parts, nmap.data() + (size_t)net * blk_units);
+    else net_block_map(h, P, net, nmap.data() + (size_t)net * blk_units);
+  }
+  // BF16 GEMM operands per species and layer: W^T [out][in] then W [in][out], each as
+  // hi and lo parts, every group padded to a multiple of 8 units (16-byte rows)
+  std::vector<int> bmap;
+  std::vector<size_t> offWb;
+  if (bf)
+    for (int a = 0; a < h->ntypes; a++) {
+      int nin = h->M * h->m2;
+      for (int k = 0; k < h->n_fit; k++) {
+        int nout = h->fit_w[k];
+        int64_t w0 = P.fW[a * (h->n_fit + 1) + k];
+        for (int dir = 0; dir < 2; dir++)
+          for (int part = 0; part < 2; part++) {
+            offWb.push_back(bmap.size());
+            int rows = dir == 0 ? nout : nin, cols = dir == 0 ? nin : nout;
+            for (int r = 0; r < rows; r++)
+              for (int c = 0; c < cols; c++) {
+                int64_t idx = dir == 0 ? w0 + (int64_t)c * nout + r : w0 + (int64_t)r * nout + c;
+                bmap.push_back(part < parts ? (int)(4 * idx + part) : -1);
+              }
+            while (bmap.size() % 8) bmap.push_back(-1);
+          }
+        nin = nout;
+      }
+    }
   // fitting weights, per species: W_k, b_k for k < nfit, then wo (rows padded to 64)
   std::vector<int> fmap;
   std::vector<size_t> offW, offB, offO;
@@ -286,6 +369,12 @@ static int upload_weights(dp_handle h) {
   }
   h->net_elems = nmap.size();
   h->fit_elems = fmap.size();
+  h->fitb_elems = bmap.size();
+  if (bf) {
+    HIPCHECK(h, hipMalloc(&h->d_fitb_map, sizeof(int) * bmap.size()));
+    HIPCHECK(h, hipMemcpy(h->d_fitb_map, bmap.data(), sizeof(int) * bmap.size(), hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMalloc(&h->d_fitb, sizeof(uint16_t) * bmap.size()));
+  }
   HIPCHECK(h, hipMalloc(&h->d_theta, sizeof(double) * h->nparams));
   HIPCHECK(h, hipMemcpy(h->d_theta, h->params.data(), sizeof(double) * h->nparams, hipMemcpyHostToDevice));
   HIPCHECK(h, hipMalloc(&h->d_net_map, sizeof(int) * nmap.size()));
@@ -294,7 +383,7 @@ static int upload_weights(dp_handle h) {
   HIPCHECK(h, hipMemcpy(h->d_fit_map, fmap.data(), sizeof(int) * fmap.size(), hipMemcpyHostToDevice));
   HIPCHECK(h, hipMalloc(&h->d_bo_map, sizeof(int) * bomap.size()));
   HIPCHECK(h, hipMemcpy(h->d_bo_map, bomap.data(), sizeof(int) * bomap.size(), hipMemcpyHostToDevice));
-  HIPCHECK(h, hipMalloc(&h->d_nets, nmap.size() * sb));
+  HIPCHECK(h, hipMalloc(&h->d_nets, bf ? nmap.size() * 2 : nmap.size() * sb));
   HIPCHECK(h, hipMalloc(&h->d_fit, fmap.size() * sb));
   HIPCHECK(h, hipMalloc(&h->d_bo, h->ntypes * sizeof(double)));
   // pointer tables: W [ntypes*nfit], b [ntypes*nfit], wo [ntypes]
@@ -303,6 +392,8 @@ static int upload_weights(dp_handle h) {
   for (size_t q = 0; q < offW.size(); q++) ptrs.push_back(base + offW[q] * sb);
   for (size_t q = 0; q < offB.size(); q++) ptrs.push_back(base + offB[q] * sb);
   for (size_t q = 0; q < offO.size(); q++) ptrs.push_back(base + offO[q] * sb);
+  // BF16 operand table [(species * nfit + k) * 4 + dir * 2 + part]
+  for (size_t q = 0; q < offWb.size(); q++) ptrs.push_back(h->d_fitb + offWb[q]);
   HIPCHECK(h, hipMalloc(&h->d_ptrs, ptrs.size() * sizeof(void*)));
   HIPCHECK(h, hipMemcpy(h->d_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice));
   std::vector<int64_t> noff((size_t)nnet * 6);
@@ -336,6 +427,10 @@ static void release_weights(dp_handle h) {
   if (h->d_fit) (void)hipFree(h->d_fit);
   if (h->d_bo) (void)hipFree(h->d_bo);
   if (h->d_ptrs) (void)hipFree(h->d_ptrs);
+  if (h->d_fitb) (void)hipFree(h->d_fitb);
+  if (h->d_fitb_map) (void)hipFree(h->d_fitb_map);
+  h->d_fitb = nullptr;
+  h->d_fitb_map = nullptr;
   h->d_nets = h->d_fit = nullptr;
   h->d_bo = nullptr;
   h->d_ptrs = nullptr;
@@ -633,6 +728,10 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
     if (h->student_on) launch_student_fwd(E, st);
     else launch_embed_fwd(E, st);
   }
+  if (h->student_on) {
+    StageTimer tm(h, DP_STAGE_FALLBACK, st);
+    launch_fallback_fwd(E, st);
+  }
   HIPCHECK(h, hipGetLastError());
   FitArgs F{};
   F.prec = h->opt.precision;
@@ -648,6 +747,7 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
   F.W = (const void* const*)h->d_ptrs;
   F.b = (const void* const*)h->d_ptrs + h->ntypes * h->n_fit;
   F.wo = (const void* const*)h->d_ptrs + 2 * h->ntypes * h->n_fit;
+  F.Wb = (const void* const*)h->d_ptrs + 2 * h->ntypes * h->n_fit + h->ntypes;
   F.bo = h->d_bo;
   F.D = W.at<void>(P.o_D);
   F.Dg = W.at<void>(P.o_Dg);
@@ -667,9 +767,15 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
   }
   if (want_forces) {
     launch_zero(forces, (size_t)P.n * 3, st);
-    StageTimer tm(h, DP_STAGE_EMBED_BWD, st);
-    if (h->student_on) launch_student_bwd(E, st);
-    else launch_embed_bwd(E, st);
+    {
+      StageTimer tm(h, DP_STAGE_EMBED_BWD, st);
+      if (h->student_on) launch_student_bwd(E, st);
+      else launch_embed_bwd(E, st);
+    }
+    if (h->student_on) {
+      StageTimer tm(h, DP_STAGE_FALLBACK, st);
+      launch_fallback_bwd(E, st);
+    }
   }
   HIPCHECK(h, hipGetLastError());
   {
@@ -718,6 +824,15 @@ int dp_init(const char* model_path, const dp_options* opt, dp_handle* out) {
     g_init_err = h->err;
     delete h;
     return rc;
+  }
+  if (bf16_mode(h->opt.precision)) {
+    bool ok = (h->M * h->m2) % 8 == 0;
+    for (int k = 0; k < h->n_fit; k++) ok = ok && h->fit_w[k] % 8 == 0;
+    if (!ok) {
+      g_init_err = "BF16 modes need M * M< and the fitting widths to be multiples of 8";
+      delete h;
+      return DP_ERR_ARG;
+    }
   }
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;

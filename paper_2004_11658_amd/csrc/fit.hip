@@ -7,10 +7,12 @@
 //   xk  = x_{k-1} + tanh(x_{k-1} Wk + bk)                    Eq. 3
 //   E_i = x_last . w_o + b_o
 // and back: g_last = w_o; g_{k-1} = g_k + (g_k * (1 - t_k^2)) Wk^T; dD = (g_1 (1 - t_1^2)) W1^T;
-// dE/dT from dD.  GEMMs run on the 16x16x4 MFMA (FP64 or FP32 operands), 64x64 output
-// tiles per workgroup, with the bias, tanh and skip fused into the epilogue and the
-// 1 - tanh^2 factor fused into operand staging (the paper's fused TANH / TANHGrad,
-// Section 3.2.3).
+// dE/dT from dD.  GEMMs run on the 16x16x4 MFMA (FP64 or FP32 operands) or, in the BF16
+// modes, on the 16x16x32 BF16 MFMA with FP32 accumulation (activations are rounded to
+// BF16 while they are staged; the split mode adds the lo parts as hi lo + lo hi),
+// 64x128 output tiles per workgroup, with the bias, tanh and skip fused into the
+// epilogue and the 1 - tanh^2 factor fused into operand staging (the paper's fused
+// TANH / TANHGrad, Section 3.2.3).
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -41,6 +43,7 @@ constexpr int BN = 128;   // output tile columns
 
 struct GemmArgs {
   int nrows, K, N;
+  const void* const* Wb; // BF16 modes: operand table (see FitArgs::Wb)
   const int* type_row0;
   int ntypes;
   const void* A;        // [nrows][K]
@@ -182,6 +185,161 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
     }
 }
 
+typedef __bf16 fbf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 fbf4 __attribute__((ext_vector_type(4)));
+
+// BF16 operands: the same 64 x 128 tile and wave split as k_gemm, K consumed in tiles
+// of 64 (two MFMA k steps of 32).  Both operands sit in LDS k-contiguous, [row][k] for
+// the activations and [column][k] for the weights (the forward reads W^T, the adjoint
+// W, both pre-packed in BF16), so every lane reads its 8 k values with one 16-byte
+// load.  K must be a multiple of 8 (checked when the model is loaded).
+template <int PARTS, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf(GemmArgs G) {
+  constexpr int KT = 64, LDK = KT + 8;
+  __shared__ __align__(16) __bf16 As[PARTS][BM][LDK];
+  __shared__ __align__(16) __bf16 Bs[PARTS][BN][LDK];
+  const int r0 = blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  int sp = -1;
+  for (int t = 0; t < G.ntypes; t++)
+    if (r0 >= G.type_row0[t] && r0 < G.type_row0[t + 1]) sp = t;
+  if (sp < 0) return;
+  constexpr bool bwd = (EPI == EPI_BWD || EPI == EPI_BWD1);
+  const float* __restrict__ A = (const float*)G.A;
+  const float* __restrict__ At = (const float*)G.Aaux;
+  const int wi = (sp * G.wstride + G.wsel) * 4 + (bwd ? 2 : 0);
+  const __bf16* __restrict__ Wh = (const __bf16*)G.Wb[wi];
+  const __bf16* __restrict__ Wl = (const __bf16*)G.Wb[wi + 1];
+  const int K = G.K, N = G.N;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, rb = lane & 15, g = lane >> 4;
+  const int wc = wv * 32;
+  f4v acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) acc[a][b] = f4v{0, 0, 0, 0};
+  // A tile: 64 rows x 64 k as 1024 float4, thread t takes t + 256 j: row e / 16, k 4 (e % 16)
+  // B tile: 128 columns x 64 k as 1024 groups of 8, thread t takes t + 256 j: col e / 8, k 8 (e % 8)
+  float4 ra[4];
+  uint4 rbh[4], rbl[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      int e = tid + 256 * j, r = e >> 4, k = k0 + 4 * (e & 15);
+      float4 v = {0.f, 0.f, 0.f, 0.f};
+      if (k < K) {
+        size_t o = (size_t)(r0 + r) * K + k;
+        v = *(const float4*)(A + o);
+        if (bwd) {
+          float4 t = *(const float4*)(At + o);
+          v.x *= 1.f - t.x * t.x;
+          v.y *= 1.f - t.y * t.y;
+          v.z *= 1.f - t.z * t.z;
+          v.w *= 1.f - t.w * t.w;
+        }
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      int e = tid + 256 * j, c = n0 + (e >> 3), k = k0 + 8 * (e & 7);
+      uint4 h = {0, 0, 0, 0}, l = {0, 0, 0, 0};
+      if (k < K && c < N) {
+        size_t o = (size_t)c * K + k;
+        h = *(const uint4*)(Wh + o);
+        if (PARTS == 2) l = *(const uint4*)(Wl + o);
+      }
+      rbh[j] = h;
+      rbl[j] = l;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      int e = tid + 256 * j, r = e >> 4, k = 4 * (e & 15);
+      float x[4] = {ra[j].x, ra[j].y, ra[j].z, ra[j].w};
+      fbf4 h, l;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        __bf16 hv = (__bf16)x[i];
+        h[i] = hv;
+        if (PARTS == 2) l[i] = (__bf16)(x[i] - (float)hv);
+      }
+      *(fbf4*)&As[0][r][k] = h;
+      if (PARTS == 2) *(fbf4*)&As[1][r][k] = l;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      int e = tid + 256 * j, c = e >> 3, k = 8 * (e & 7);
+      *(uint4*)&Bs[0][c][k] = rbh[j];
+      if (PARTS == 2) *(uint4*)&Bs[1][c][k] = rbl[j];
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += KT) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + KT < K) load(k0 + KT);
+#pragma unroll
+    for (int ks = 0; ks < KT; ks += 32) {
+      fbf8 ah[4], al[4], bh[2], bl[2];
+#pragma unroll
+      for (int a = 0; a < 4; a++) {
+        ah[a] = *(const fbf8*)&As[0][16 * a + rb][ks + 8 * g];
+        al[a] = PARTS == 2 ? *(const fbf8*)&As[1][16 * a + rb][ks + 8 * g] : ah[a];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; b++) {
+        bh[b] = *(const fbf8*)&Bs[0][wc + 16 * b + rb][ks + 8 * g];
+        bl[b] = PARTS == 2 ? *(const fbf8*)&Bs[1][wc + 16 * b + rb][ks + 8 * g] : bh[b];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+          if (PARTS == 2) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+          }
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        }
+    }
+  }
+  float* out = (float*)G.out;
+  float* out2 = (float*)G.out2;
+  const float* X = (const float*)G.Xprev;
+  const float* bias = (EPI == EPI_FWD1 || EPI == EPI_FWDRES) ? (const float*)G.bias[sp * G.wstride + G.wsel]
+                                                           : nullptr;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      int col = n0 + wc + 16 * b + rb;
+      if (col >= N) continue;
+      float bc = bias ? bias[col] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        int row = r0 + 16 * a + 4 * g + q;
+        size_t o = (size_t)row * N + col;
+        float v = acc[a][b][q];
+        if (EPI == EPI_FWD1) {
+          float t = ftanh(v + bc);
+          out[o] = t;
+          out2[o] = t;
+        } else if (EPI == EPI_FWDRES) {
+          float t = ftanh(v + bc);
+          out[o] = X[o] + t;
+          out2[o] = t;
+        } else if (EPI == EPI_BWD) {
+          out[o] = X[o] + v;
+        } else {
+          out[o] = v;
+        }
+      }
+    }
+}
+
 // D[row][a m2 + b] = sum_c T[row][a][c] T[row][b][c]; pad rows get zeros
 template <class T>
 __global__ void k_desc(int nrows, int M, int m2, const int* __restrict__ row_atom,
@@ -256,13 +414,16 @@ __global__ void k_fit_out(int nrows, int N, int ntypes, const int* __restrict__ 
 }
 
 template <class T, int EPI>
-static void gemm(const GemmArgs& G, hipStream_t st) {
+static void gemm(int prec, const GemmArgs& G, hipStream_t st) {
   dim3 grid((G.nrows + BM - 1) / BM, (G.N + BN - 1) / BN);
-  hipLaunchKernelGGL((k_gemm<T, EPI>), grid, dim3(256), 0, st, G);
+  if (prec == PREC_BF16) hipLaunchKernelGGL((k_gemm_bf<1, EPI>), grid, dim3(256), 0, st, G);
+  else if (prec == PREC_BF16X3) hipLaunchKernelGGL((k_gemm_bf<2, EPI>), grid, dim3(256), 0, st, G);
+  else hipLaunchKernelGGL((k_gemm<T, EPI>), grid, dim3(256), 0, st, G);
 }
 
 template <class T>
 static void fit_t(const FitArgs& F, hipStream_t st) {
+  const int prec = F.prec;
   const int rows = F.nrows, M = F.m.M, m2 = F.m.m2, K1 = M * m2, fw = F.fw;
   {
     size_t tot = (size_t)rows * K1;
@@ -277,6 +438,7 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
   G.type_row0 = F.type_row0;
   G.ntypes = F.m.ntypes;
   G.W = F.W;
+  G.Wb = F.Wb;
   G.bias = F.b;
   G.wstride = F.nfit;
   for (int k = 0; k < F.nfit; k++) {
@@ -287,8 +449,8 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
     G.Xprev = k == 0 ? nullptr : (const void*)(xs + (k - 1) * L);
     G.out = xs + k * L;
     G.out2 = act + k * L;
-    if (k == 0) gemm<T, EPI_FWD1>(G, st);
-    else gemm<T, EPI_FWDRES>(G, st);
+    if (k == 0) gemm<T, EPI_FWD1>(prec, G, st);
+    else gemm<T, EPI_FWDRES>(prec, G, st);
   }
   hipLaunchKernelGGL(k_fit_out<T>, dim3((rows + 3) / 4), dim3(256), 0, st, rows, fw, F.m.ntypes,
                      F.type_row0, F.row_atom, (const T*)(xs + (F.nfit - 1) * L), F.wo, F.bo, F.Ei,
@@ -303,7 +465,7 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
     G.Aaux = act + k * L;
     G.Xprev = gcur;
     G.out = gnext;
-    gemm<T, EPI_BWD>(G, st);
+    gemm<T, EPI_BWD>(prec, G, st);
     T* tmp = gcur;
     gcur = gnext;
     gnext = tmp;
@@ -315,7 +477,7 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
   G.Aaux = act;
   G.Xprev = nullptr;
   G.out = F.Dg;
-  gemm<T, EPI_BWD1>(G, st);
+  gemm<T, EPI_BWD1>(prec, G, st);
   hipLaunchKernelGGL(k_desc_bwd<T>, dim3(rows), dim3(256), sizeof(T) * (M * 4 + M * m2), st, rows, M, m2,
                      F.row_atom, (const T*)F.T, (const T*)F.Dg, (T*)F.gT);
 }

@@ -44,6 +44,18 @@ constexpr int kOffW2 = kOffW1 + kP0 * kW1Stride;
 constexpr int kNetElems = kOffW2 + kP1 * kW2Stride;
 
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2, PREC_BF16X3 = 3 };
+inline int prec_parts(int prec) { return prec == PREC_BF16X3 ? 2 : 1; }
+
+// BF16 net block, in 16-bit units: the float part (W0, b0, b1, b2 at the float offsets
+// kOffW0 .. kOffB2 above, 256 floats), then the MFMA A operands pre-packed per lane
+// (8 bf16 = 16 bytes per lane and tile): forward W1 (4 output tiles x 1 k chunk of 32)
+// and W2 (8 x 2), one copy per part (hi, and lo for the split mode), then the adjoint
+// W1 (2 x 2) and W2 (4 x 4), one copy per part.
+constexpr int kBFloat = 256;                       // floats in the float part
+constexpr int kBW1F = 4 * 1 * 512, kBW2F = 8 * 2 * 512;
+constexpr int kBW1B = 2 * 2 * 512, kBW2B = 4 * 4 * 512;
+constexpr int kBFwd = kBW1F + kBW2F, kBBwd = kBW1B + kBW2B;
+inline constexpr int bnet_u16(int parts) { return 2 * kBFloat + parts * (kBFwd + kBBwd); }
 
 // Position-padded student block (1 -> H <= 32 tanh -> M affine): W1, b1 at hidden
 // positions 0..31, b2 at the output positions of G, W2 [32][kP2 + 1].
@@ -57,6 +69,7 @@ struct EmbedArgs {
   int n;               // local atoms
   ModelC m;
   const void* nets;    // [ntypes*ntypes] net blocks in the precision's storage layout
+                       // (kNetElems T for FP64 / FP32, bnet_u16(parts) 16-bit units for BF16)
   const double* xe;
   const int* nlist;
   const int* nnei;
@@ -82,6 +95,8 @@ struct EmbedArgs {
 void launch_embed_fwd(const EmbedArgs& a, hipStream_t st);
 void launch_student_fwd(const EmbedArgs& a, hipStream_t st);
 void launch_student_bwd(const EmbedArgs& a, hipStream_t st);
+void launch_fallback_fwd(const EmbedArgs& a, hipStream_t st);
+void launch_fallback_bwd(const EmbedArgs& a, hipStream_t st);
 void launch_embed_bwd(const EmbedArgs& a, hipStream_t st);
 int embed_bwd_blocks(int nrows);
 
@@ -101,6 +116,9 @@ struct FitArgs {
   const void* const* W;  // [ntypes][nfit] device pointers (row major [in][out])
   const void* const* b;  // [ntypes][nfit]
   const void* const* wo; // [ntypes]
+  // BF16 modes: GEMM operands per species and layer, [(species * nfit + k) * 4 + dir * 2 + part]
+  // with dir 0 = W^T [out][in] (forward), dir 1 = W [in][out] (adjoint), part 0 hi, 1 lo
+  const void* const* Wb;
   const double* bo;      // [ntypes] device
   void *D, *Dg;        // [nrows][M*m2]
   void* act;           // [nfit][nrows][fw]  tanh outputs
@@ -147,6 +165,9 @@ int launch_param_grad(const PGradArgs& a, hipStream_t st);
 void launch_pair_scan(int nrows, int ntypes, int beta, const int* row_atom, const int* nnei, int* base,
                       int* sums, int* total, hipStream_t st);
 void launch_scatter_params(int prec, size_t n, const int* map, const double* theta, void* dst, hipStream_t st);
+// 16-bit-unit map: code = 4 idx + kind (0 bf16 hi, 1 bf16 lo, 2 float over two units),
+// -1 zero, -2 second unit of a float
+void launch_pack_bf16(size_t n, const int* map, const double* theta, uint16_t* dst, hipStream_t st);
 void launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t st);
 void launch_zero_int(int* p, int n, hipStream_t st);
 

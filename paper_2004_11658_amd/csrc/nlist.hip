@@ -586,6 +586,32 @@ void launch_scatter_params(int prec, size_t n, const int* map, const double* the
     hipLaunchKernelGGL(k_scatter_params_f, dim3((n + 255) / 256), dim3(256), 0, st, n, map, theta, (float*)dst);
 }
 
+// BF16 operand packing: hi = bf16(f), lo = bf16(f - hi) with f the FP32 value of the
+// parameter (round to nearest even in both conversions); f - hi is exact in FP32
+__global__ void k_pack_bf16(size_t n, const int* __restrict__ map, const double* __restrict__ theta,
+                            uint16_t* __restrict__ dst) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  int code = map[q];
+  if (code == -2) return;
+  if (code < 0) {
+    dst[q] = 0;
+    return;
+  }
+  float f = (float)theta[code >> 2];
+  int kind = code & 3;
+  if (kind == 2) {
+    *(float*)(dst + q) = f;
+    return;
+  }
+  __bf16 h = (__bf16)f;
+  __bf16 v = kind == 0 ? h : (__bf16)(f - (float)h);
+  dst[q] = __builtin_bit_cast(uint16_t, v);
+}
+void launch_pack_bf16(size_t n, const int* map, const double* theta, uint16_t* dst, hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_pack_bf16, dim3((n + 255) / 256), dim3(256), 0, st, n, map, theta, dst);
+}
+
 __global__ void k_axpy(size_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
   size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < n) y[q] += a * x[q];

@@ -405,12 +405,20 @@ void launch_student_fwd(const EmbedArgs& a, hipStream_t st) {
   if (a.prec == PREC_FP64) {
     hipLaunchKernelGGL((k_student_fwd<double, kStuWaves>), dim3(grid), dim3(64 * kStuWaves),
                        sizeof(double) * kStuElems, st, a);
-    hipLaunchKernelGGL(k_fb_fwd<double>, dim3(1024), dim3(64), 0, st, a);
   } else {
     hipLaunchKernelGGL((k_student_fwd<float, kStuWaves>), dim3(grid), dim3(64 * kStuWaves),
                        sizeof(float) * kStuElems, st, a);
-    hipLaunchKernelGGL(k_fb_fwd<float>, dim3(1024), dim3(64), 0, st, a);
   }
+}
+
+void launch_fallback_fwd(const EmbedArgs& a, hipStream_t st) {
+  if (a.prec == PREC_FP64) hipLaunchKernelGGL(k_fb_fwd<double>, dim3(1024), dim3(64), 0, st, a);
+  else hipLaunchKernelGGL(k_fb_fwd<float>, dim3(1024), dim3(64), 0, st, a);
+}
+
+void launch_fallback_bwd(const EmbedArgs& a, hipStream_t st) {
+  if (a.prec == PREC_FP64) hipLaunchKernelGGL(k_fb_bwd<double>, dim3(1024), dim3(64), 0, st, a);
+  else hipLaunchKernelGGL(k_fb_bwd<float>, dim3(1024), dim3(64), 0, st, a);
 }
 
 void launch_student_bwd(const EmbedArgs& a, hipStream_t st) {
@@ -420,11 +428,9 @@ void launch_student_bwd(const EmbedArgs& a, hipStream_t st) {
     (void)hipFuncSetAttribute((const void*)k_student_bwd<double, kStuWaves>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     hipLaunchKernelGGL((k_student_bwd<double, kStuWaves>), dim3(grid), dim3(64 * kStuWaves), sh, st, a);
-    hipLaunchKernelGGL(k_fb_bwd<double>, dim3(1024), dim3(64), 0, st, a);
   } else {
     size_t sh = sizeof(float) * (kStuElems + 64 + kStuWaves * kP2 * 4);
     hipLaunchKernelGGL((k_student_bwd<float, kStuWaves>), dim3(grid), dim3(64 * kStuWaves), sh, st, a);
-    hipLaunchKernelGGL(k_fb_bwd<float>, dim3(1024), dim3(64), 0, st, a);
   }
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdp.so")
 DP_OK = 0
 DP_WARN_SEL_OVERFLOW = 1
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
-STAGES = {"nlist": 0, "embed_fwd": 1, "fit": 2, "embed_bwd": 3, "reduce": 4, "md": 5}
+STAGES = {"nlist": 0, "embed_fwd": 1, "fit": 2, "embed_bwd": 3, "reduce": 4, "md": 5, "fallback": 6}
 
 
 class DPError(RuntimeError):

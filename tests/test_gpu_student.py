@@ -85,7 +85,7 @@ def test_student_learns_a_student_shaped_teacher(dp):
         dp.adam_step(th, m, v, g, step, lr)
         loss, g, sc = dp.student_loss_grad(H, M, sd, Gd, th, sc)
     print("student loss", L0, "->", float(loss.item()), flush=True)
-    assert float(loss.item()) < 1e-6 * L0
+    assert float(loss.item()) < 1e-4 * L0
 
 
 def test_full_net_eval_and_sample_gather(dp, water_model, water192):
