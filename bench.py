@@ -1,17 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: velocity-Verlet MD of 12,288 water atoms with the DP-SE model on one GPU.
 
-One step = one MD step of the whole hot path: wrap + ghost images + cell list,
-neighbour formatting, embedding forward, descriptor + fitting net forward and
-backward, embedding adjoint with force / virial scatter, reductions, and the two
-velocity-Verlet half kicks and drift.  Inputs are resident in HBM before timing.
+One step = one MD step of the whole hot path: displacement check against the neighbour
+skin (wrap + ghost images + cell list + candidate rows rebuilt when some atom moved
+more than skin/2), neighbour formatting within rc, embedding forward, descriptor +
+fitting net forward and backward, embedding adjoint with force / virial scatter,
+reductions, and the two velocity-Verlet half kicks and drift.  Inputs are resident in
+HBM before timing.
 
 Each precision mode is timed over the same K steps from the same initial state; the
 headline value is the fastest mode whose force RMSE (relative to FP64 at identical
 coordinates) is at most 1e-3, as the metric asks.  The FP64 CPU oracle is timed on a
 bounded sample (one force evaluation of the same frame) as the CPU baseline.
 
-    python bench.py [--gpus 1] [--steps 100] [--warmup 3] [--modes fp64,fp32,fp32+student]
+    python bench.py [--gpus 1] [--steps 100] [--warmup 3] [--modes fp64,fp32,bf16x3,bf16,fp32+student,bf16x3+student]
 
 Modes: fp64, fp32, bf16, bf16x3 (operand precision of the embedding and fitting GEMMs),
 and "<precision>+student": the student embedding nets, trained before timing on frames
@@ -65,28 +67,31 @@ def algorithmic_flops(spec, rows, natoms, student=False):
                 emb_bwd_row=emb_bwd_row, emb_fwd_row=emb_fwd_row, fit_atom=fit_atom)
 
 
-def kernel_source_hash():
-    """Hash of the HIP sources: counter-based traffic figures apply only to these."""
+def source_hash(files):
+    """Hash of the named HIP sources (a counter-based traffic figure applies only to these)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2004_11658_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in sorted(files):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
 def traffic_for(kernel: str):
-    """HBM bytes per launch of kernel from the committed counter summary, if it was
+    """HBM bytes per launch of a kernel from the committed counter summary, if it was
     measured on the current sources (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_hash") != kernel_source_hash():
-        return None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    if k is None or k.get("source_hash") != source_hash(k["sources"]):
+        return None
+    return k["bytes_per_launch"]
+
+
+POLICY = {"fp64": "NetNative<double>", "fp32": "NetNative<float>", "bf16": "NetBF16<1>", "bf16x3": "NetBF16<2>"}
 
 
 def main():
@@ -94,7 +99,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="fp64,fp32,fp32+student")
+    ap.add_argument("--modes", default="fp64,fp32,bf16x3,bf16,fp32+student,bf16x3+student")
+    ap.add_argument("--skin", type=float, default=2.0,
+                    help="neighbour skin (A): the list is rebuilt when some atom moved more than skin/2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -145,7 +152,7 @@ def main():
     student = None
     for mode in modes:
         prec, _, extra = mode.partition("+")
-        model = D.DPModel(path, prec)
+        model = D.DPModel(path, prec, skin=args.skin)
         if extra == "student":
             if student is None:
                 # training data: frames of the FP64 full model's own trajectory
@@ -216,14 +223,16 @@ def main():
     bwd_ms = R["stages_ms"]["embed_bwd"]
     achieved = fl["embed_bwd"] / (bwd_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[hprec]
-    kname = ("k_student_bwd<%s> (student embedding adjoint)" if R["student"]
-             else "k_embed_bwd<%s> (embedding adjoint with recompute)") % ("double" if hprec == "fp64" else "float")
+    if R["student"]:
+        kname = "k_student_bwd<%s, 8>" % ("double" if hprec == "fp64" else "float")
+    else:
+        kname = "k_embed_bwd<%s, 8>" % POLICY[hprec]
     roofline = dict(bound="mfma", kernel=kname,
                     achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                    frac=round(achieved / peak, 4), traffic=traffic_for(kname.split(" ")[0]),
+                    frac=round(achieved / peak, 4), traffic=traffic_for(kname),
                     flops_per_launch=fl["embed_bwd"], rows_per_launch=rows,
                     flops_per_row=fl["emb_bwd_row"], avg_launch_ms=bwd_ms,
-                    stage_tflops=stage_rates, source_hash=kernel_source_hash())
+                    stage_tflops=stage_rates)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -246,7 +255,8 @@ def main():
         "dtype": DTYPE[hprec] + (", student embedding" if R["student"] else ""), "data": "synthetic",
         "config": {"workload": "water 12,288 atoms (4,096 H2O, 49.7 A cube), velocity-Verlet MD "
                                "dt 0.5 fs from 300 K, DP-SE rc 6 A sel 46/92 emb 25x50x100 "
-                               "fit 240^3, random weights", "atoms": n, "mode": head,
+                               "fit 240^3, random weights, neighbour skin %.1f A" % args.skin,
+                   "atoms": n, "mode": head, "skin_A": args.skin,
                    "real_neighbour_rows": rows},
         "roofline": roofline,
         "cpu_baseline": cpu,
