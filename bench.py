@@ -92,6 +92,8 @@ def traffic_for(kernel: str):
 
 
 POLICY = {"fp64": "NetNative<double>", "fp32": "NetNative<float>", "bf16": "NetBF16<1>", "bf16x3": "NetBF16<2>"}
+STUDENT_POLICY = {"fp64": "StuNative<double>", "fp32": "StuNative<float>", "bf16": "StuBF16<1>",
+                  "bf16x3": "StuBF16<2>"}
 
 
 def main():
@@ -223,10 +225,7 @@ def main():
     bwd_ms = R["stages_ms"]["embed_bwd"]
     achieved = fl["embed_bwd"] / (bwd_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[hprec]
-    if R["student"]:
-        kname = "k_student_bwd<%s, 8>" % ("double" if hprec == "fp64" else "float")
-    else:
-        kname = "k_embed_bwd<%s, 8>" % POLICY[hprec]
+    kname = "k_embed_bwd<%s, 8>" % (STUDENT_POLICY if R["student"] else POLICY)[hprec]
     roofline = dict(bound="mfma", kernel=kname,
                     achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4), traffic=traffic_for(kname),

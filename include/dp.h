@@ -61,8 +61,14 @@ typedef struct {
                          operands split as hi + lo (three MFMAs per product).
                          Coordinates, distances, the environment matrix, force and
                          virial accumulation, energy sums and integration stay FP64. */
-  int32_t reserved0;
-  double skin;        /* MD neighbour skin (A); 0 = rebuild cell lists every step */
+  int32_t deterministic; /* 1: forces independent of kernel scheduling (each pair force
+                         is stored in its list slot and gathered per atom in slot
+                         order, Remark 4's reverse sum) instead of FP64 atomics;
+                         not combinable with student nets.  0: atomics. */
+  double skin;        /* MD neighbour skin (A): dp_md_run rebuilds the list of pairs
+                         within rc + skin only when some atom moved more than skin/2
+                         (checked on the device every step) and formats it within rc
+                         at every step; 0 = rebuild everything every step */
 } dp_options;
 
 /* Read a model file ("DPSEMDL1" format: architecture + FP64 parameters in the
@@ -70,7 +76,7 @@ typedef struct {
  * Supported architecture: 1..8 species, embedding nets of three layers
  * 1 -> s0 -> 2 s0 -> 4 s0 = M with s0 <= 32 (Section 2, Eq. 7-9), square hidden
  * fitting layers after the first (Eq. 3), M< <= M, N_m = sum(sel) <= 1024.
- * opt may be NULL (FP64, skin 0).  On error *out is NULL. */
+ * opt may be NULL (FP64, atomics, skin 0).  On error *out is NULL. */
 int dp_init(const char* model_path, const dp_options* opt, dp_handle* out);
 void dp_free(dp_handle h);
 
@@ -201,7 +207,8 @@ int dp_adam(int64_t n, double* theta, double* m, double* v, const double* g, int
  * dp_student_loss_grad with hidden width 1..32.  s_lo, s_hi (host [ntypes^2]): the s
  * range each student was trained on.  While enabled, every compute, MD and descriptor
  * call uses the student for neighbours with s in [s_lo, s_hi] and the full net (FP64)
- * for the others.  Workspaces must be sized after this call. */
+ * for the others.  Workspaces must be sized after this call.  DP_ERR_ARG on a handle
+ * made with deterministic = 1. */
 int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const double* s_lo,
                    const double* s_hi, int32_t enable, void* stream);
 

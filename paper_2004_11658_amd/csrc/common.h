@@ -44,35 +44,38 @@ struct ModelC {
   double rc, rcs, rc2;
   int switch_kind, desc_norm;
   double inv_norm;  // 1/N_m or 1
+  double inv_h;     // 1 / (rc - rcs)
 };
 
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
 
-// s(r) = w(r)/r and ds/dr for the C2 quintic (or cosine) switch between rcs and rc.
-__device__ __forceinline__ void smooth_fn(const ModelC& m, double r, double& s, double& ds) {
+// s(r) = w(r)/r and ds/dr for the C2 quintic (or cosine) switch between rcs and rc,
+// given ir = 1/r.
+__device__ __forceinline__ void smooth_fn_ir(const ModelC& m, double r, double ir, double& s, double& ds) {
   double w, dw;
   if (r < m.rcs) {
     w = 1.0;
     dw = 0.0;
   } else if (r < m.rc) {
-    double h = m.rc - m.rcs;
-    double u = (r - m.rcs) / h;
+    double u = (r - m.rcs) * m.inv_h;
     if (m.switch_kind == 1) {
       double sp, cp;
       sincos(M_PI * u, &sp, &cp);
       w = 0.5 * cp + 0.5;
-      dw = -0.5 * M_PI * sp / h;
+      dw = -0.5 * M_PI * sp * m.inv_h;
     } else {
       w = u * u * u * (-6.0 * u * u + 15.0 * u - 10.0) + 1.0;
-      dw = -30.0 * u * u * (u - 1.0) * (u - 1.0) / h;
+      dw = -30.0 * u * u * (u - 1.0) * (u - 1.0) * m.inv_h;
     }
   } else {
     w = 0.0;
     dw = 0.0;
   }
-  double ir = 1.0 / r;
   s = w * ir;
   ds = (dw - w * ir) * ir;
+}
+__device__ __forceinline__ void smooth_fn(const ModelC& m, double r, double& s, double& ds) {
+  smooth_fn_ir(m, r, 1.0 / r, s, ds);
 }
 
 }  // namespace dp

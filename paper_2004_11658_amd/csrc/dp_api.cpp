@@ -484,24 +484,41 @@ struct Plan {
   size_t o_xe, o_eown, o_eimg, o_etype, o_ecell, o_ccount, o_cstart, o_cfill, o_catoms;
   size_t o_nlist, o_nnei, o_tpos, o_rowof, o_rowatom, o_T, o_gT, o_D, o_Dg, o_act, o_xs, o_g0,
       o_g1, o_Ei, o_vir, o_tmpj, o_tmpi, o_mdF, o_mdE, o_mdW, o_fb, o_fbcnt;
-  int n, nframes, ncell, ghost_cap, nrows;
+  // Verlet reuse (MD with a skin)
+  bool verlet = false;
+  size_t o_wk, o_xref, o_eabc, o_vlist, o_vcnt, o_vflag;
+  int n, nframes, ncell, ghost_cap, nrows, vcap, max_frame_atoms;
+  size_t o_redpart;
+  size_t o_gbuf = 0, o_rev = 0;   // deterministic force gather
+  size_t o_big = 0;
 };
 
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// verlet: lay out the MD Verlet reuse as well (ghost shell and cells for rc + skin,
+// image codes over the whole ghost range)
 static int make_plan(dp_handle h, int nframes, const int64_t* off, const double* boxes,
-                     std::vector<Frame>* frames, Plan& P) {
+                     std::vector<Frame>* frames, Plan& P, bool verlet = false) {
   if (nframes < 1) return fail(h, DP_ERR_ARG, "nframes must be >= 1");
   if (off[0] != 0) return fail(h, DP_ERR_ARG, "atom_offsets[0] must be 0");
   int64_t n = off[nframes];
   if (n < 1 || n > (1 << 26)) return fail(h, DP_ERR_ARG, "natoms out of range");
-  int64_t ghost_cap = 0, ncell = 0;
+  int64_t ghost_cap = 0, ncell = 0, maxna = 0;
   if (frames) frames->resize(nframes);
   for (int f = 0; f < nframes; f++) {
     int64_t na = off[f + 1] - off[f];
     if (na < 1) return fail(h, DP_ERR_ARG, "every frame needs at least one atom");
+    maxna = std::max(maxna, na);
     Frame F{};
-    if (box_setup(boxes + 9 * f, h->rc, F)) return fail(h, DP_ERR_BOX, "singular or left-handed box");
+    if (box_setup(boxes + 9 * f, verlet ? h->rc + h->opt.skin : h->rc, F))
+      return fail(h, DP_ERR_BOX, "singular or left-handed box");
+    if (verlet) {
+      F.nimg = 1;
+      for (int k = 0; k < 3; k++) {
+        F.K[k] = F.Kg[k];
+        F.nimg *= 2 * F.K[k] + 1;
+      }
+    }
     double vol_ext = (1 + 2 * F.g[0]) * (1 + 2 * F.g[1]) * (1 + 2 * F.g[2]);
     double expect = na * (vol_ext - 1.0);
     int64_t maxg = na * ((int64_t)(2 * F.Kg[0] + 1) * (2 * F.Kg[1] + 1) * (2 * F.Kg[2] + 1) - 1);
@@ -546,6 +563,7 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
   P.o_catoms = take(sizeof(int) * ne);
   P.o_nlist = take(sizeof(int) * n * h->nm);
   P.o_nnei = take(sizeof(int) * n * h->ntypes);
+  P.o_big = take(sizeof(int) * n);
   P.o_tpos = take(sizeof(int) * n * W);
   P.o_rowof = take(sizeof(int) * n);
   P.o_rowatom = take(sizeof(int) * P.nrows);
@@ -562,12 +580,31 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
   P.o_Ei = take(sizeof(double) * rows);
   P.o_vir = take(sizeof(double) * rows * 9);
   P.o_tmpj = take(sizeof(double) * nframes * 10);
+  P.max_frame_atoms = (int)maxna;
+  P.o_redpart = take(sizeof(double) * 10 * (size_t)nframes * frame_reduce_chunks((int)maxna));
   P.o_tmpi = take(sizeof(int) * 16);
   P.o_mdF = take(sizeof(double) * 3 * n);
   P.o_mdE = take(sizeof(double) * nframes);
   P.o_mdW = take(sizeof(double) * 9 * nframes);
   P.o_fb = h->student_on ? take(sizeof(int2) * n * h->nm) : 0;
   P.o_fbcnt = take(sizeof(int) * 64);
+  if (h->opt.deterministic) {
+    P.o_gbuf = take(sizeof(double) * 3 * (size_t)n * h->nm);
+    P.o_rev = take(sizeof(int) * (rev_scratch_ints((int)n, h->nm) + 16));
+  }
+  P.verlet = verlet;
+  P.vcap = 0;
+  if (verlet) {
+    // candidates within rc + skin: the rc capacity scaled by the volume ratio
+    double q = (h->rc + h->opt.skin) / h->rc;
+    P.vcap = (int)std::min<double>(4.0 * kMaxCand, std::ceil(kMaxCand * q * q * q / 64.0) * 64.0);
+    P.o_wk = take(sizeof(int) * 3 * n);
+    P.o_xref = take(sizeof(double) * 3 * n);
+    P.o_eabc = take(sizeof(int) * 3 * ne);
+    P.o_vlist = take(sizeof(int) * (size_t)n * P.vcap);
+    P.o_vcnt = take(sizeof(int) * n);
+    P.o_vflag = take(sizeof(int) * 64);
+  }
   P.total = o;
   return DP_OK;
 }
@@ -595,6 +632,7 @@ static ModelC model_consts(dp_handle h) {
   m.switch_kind = h->switch_kind;
   m.desc_norm = h->desc_norm;
   m.inv_norm = h->desc_norm == 0 ? 1.0 / (double)h->nm : 1.0;
+  m.inv_h = 1.0 / (h->rc - h->rcs);
   return m;
 }
 
@@ -608,9 +646,9 @@ struct Ws {
 // plans the call, validates the workspace and copies the frame table to the device
 static int stage_frames(dp_handle h, int nframes, const int64_t* off, const double* boxes,
                         const double* coords, const int32_t* types, void* ws, size_t ws_bytes,
-                        hipStream_t st, Plan& P, NlistArgs& A) {
+                        hipStream_t st, Plan& P, NlistArgs& A, bool verlet = false) {
   std::vector<Frame> frames;
-  int rc = make_plan(h, nframes, off, boxes, &frames, P);
+  int rc = make_plan(h, nframes, off, boxes, &frames, P, verlet);
   if (rc != DP_OK) return rc;
   if (!ws || ws_bytes < P.total)
     return fail(h, DP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(P.total) + " bytes");
@@ -671,6 +709,24 @@ static int stage_frames(dp_handle h, int nframes, const int64_t* off, const doub
   A.tpos = W.at<int>(P.o_tpos);
   A.row_of = W.at<int>(P.o_rowof);
   A.row_atom = W.at<int>(P.o_rowatom);
+  A.big = W.at<int>(P.o_big);
+  A.nbig = small + 32;
+  A.skip_rows = false;
+  A.gate = nullptr;
+  if (P.verlet) {
+    A.wk = W.at<int>(P.o_wk);
+    A.xref = W.at<double>(P.o_xref);
+    A.eabc = W.at<int>(P.o_eabc);
+    A.vlist = W.at<int>(P.o_vlist);
+    A.vcnt = W.at<int>(P.o_vcnt);
+    A.vcap = P.vcap;
+    double rl = h->rc + h->opt.skin;
+    A.rl2 = rl * rl;
+    A.gate = W.at<int>(P.o_vflag);
+    launch_zero_int((int*)A.gate, 1, st);
+  }
+  // the status word covers the whole call
+  launch_zero_int(A.status, STW_N, st);
   return DP_OK;
 }
 
@@ -708,6 +764,7 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
   E.T = W.at<void>(P.o_T);
   E.gT = W.at<void>(P.o_gT);
   E.forces = forces;
+  E.gbuf = h->opt.deterministic ? W.at<double>(P.o_gbuf) : nullptr;
   E.vir_part = W.at<double>(P.o_vir);
   E.frame_of = A.frame_of;
   E.nframes = P.nframes;
@@ -776,12 +833,18 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
       StageTimer tm(h, DP_STAGE_FALLBACK, st);
       launch_fallback_bwd(E, st);
     }
+    if (E.gbuf) {
+      StageTimer tm(h, DP_STAGE_REDUCE, st);
+      int* rs = W.at<int>(P.o_rev);
+      launch_rev_gather(P.n, h->nm, A.nlist, A.eown, E.gbuf, forces, rs,
+                        A.scan_sums, rs + rev_scratch_ints(P.n, h->nm), A.status, st);
+    }
   }
   HIPCHECK(h, hipGetLastError());
   {
     StageTimer tm(h, DP_STAGE_REDUCE, st);
-    launch_frame_reduce(P.nframes, A.frames, A.row_of, F.Ei, want_forces ? E.vir_part : nullptr,
-                        energies, virials, atom_energy, st);
+    launch_frame_reduce(P.nframes, P.max_frame_atoms, A.frames, A.row_of, F.Ei, want_forces ? E.vir_part : nullptr,
+                        energies, virials, atom_energy, W.at<double>(P.o_redpart), st);
   }
   HIPCHECK(h, hipGetLastError());
   return DP_OK;
@@ -815,7 +878,8 @@ int dp_init(const char* model_path, const dp_options* opt, dp_handle* out) {
   if (!model_path) return fail(nullptr, DP_ERR_ARG, "model_path is NULL");
   dp_handle h = new dp_handle_s();
   if (opt) h->opt = *opt;
-  if (h->opt.precision < 0 || h->opt.precision > 3 || !(h->opt.skin >= 0)) {
+  if (h->opt.precision < 0 || h->opt.precision > 3 || !(h->opt.skin >= 0) ||
+      (h->opt.deterministic != 0 && h->opt.deterministic != 1)) {
     delete h;
     return fail(nullptr, DP_ERR_ARG, "bad options");
   }
@@ -883,6 +947,12 @@ int dp_workspace_size(dp_handle h, int32_t nframes, const int64_t* atom_offsets,
   int rc = make_plan(h, nframes, atom_offsets, boxes, nullptr, P);
   if (rc != DP_OK) return rc;
   *bytes = P.total;
+  if (h->opt.skin > 0 && nframes == 1) {
+    Plan V;
+    rc = make_plan(h, nframes, atom_offsets, boxes, nullptr, V, true);
+    if (rc != DP_OK) return rc;
+    *bytes = std::max(*bytes, V.total);
+  }
   return DP_OK;
 }
 
@@ -963,8 +1033,10 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
   int64_t off[2] = {0, natoms};
   Plan P;
   NlistArgs A{};
-  int rc = stage_frames(h, 1, off, box, x, types, workspace, ws_bytes, st, P, A);
+  const bool verlet = h->opt.skin > 0;
+  int rc = stage_frames(h, 1, off, box, x, types, workspace, ws_bytes, st, P, A, verlet);
   if (rc != DP_OK) return rc;
+  if (verlet) launch_fill_int((int*)A.gate, 1, 1, st);  // build at the first step
   Ws W{(char*)workspace, &P};
   double* F = forces ? forces : W.at<double>(P.o_mdF);
   double* E = W.at<double>(P.o_mdE);
@@ -974,8 +1046,15 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
                B[2] * (B[3] * B[7] - B[4] * B[6]);
   const int n = (int)natoms;
   auto force = [&]() -> int {
-    int r = stage_nlist(h, A, st);
-    if (r != DP_OK) return r;
+    if (verlet) {
+      StageTimer tm(h, DP_STAGE_NLIST, st);
+      launch_nlist_verlet(A, 0.5 * h->opt.skin, st);
+      A.skip_rows = true;   // the species row order is fixed after the first build
+      HIPCHECK(h, hipGetLastError());
+    } else {
+      int r = stage_nlist(h, A, st);
+      if (r != DP_OK) return r;
+    }
     return run_model(h, P, A, workspace, st, E, F, Wv, nullptr, true, nullptr, nullptr);
   };
   rc = force();
@@ -1139,6 +1218,7 @@ int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const dou
   }
   if (!theta_s || !s_lo || !s_hi || hidden < 1 || hidden > kP0)
     return fail(h, DP_ERR_ARG, "student: bad arguments (hidden must be 1..32)");
+  if (h->opt.deterministic) return fail(h, DP_ERR_ARG, "student nets are not available in deterministic mode");
   const int nnet = h->ntypes * h->ntypes, M = h->M;
   const size_t size = 2 * (size_t)hidden + (size_t)hidden * M + M;
   if (h->d_student && h->student_hidden != hidden) {
@@ -1147,10 +1227,15 @@ int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const dou
     h->d_student = nullptr;
     h->d_student_map = nullptr;
   }
+  const bool bf = bf16_mode(h->opt.precision);
+  const int parts = prec_parts(h->opt.precision);
+  const size_t blk = bf ? (size_t)snet_u16(parts) : (size_t)kStuElems;
   if (!h->d_student) {
-    std::vector<int> map((size_t)nnet * kStuElems, -1);
+    std::vector<int> map((size_t)nnet * blk, -1);
+    std::vector<int> nat(kStuElems);
     for (int net = 0; net < nnet; net++) {
-      int* b = map.data() + (size_t)net * kStuElems;
+      int* b = bf ? nat.data() : map.data() + (size_t)net * blk;
+      for (int q = 0; q < kStuElems; q++) b[q] = -1;
       size_t o = net * size;
       for (int j = 0; j < hidden; j++) {
         b[kSW1 + j] = (int)(o + j);
@@ -1162,14 +1247,45 @@ int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const dou
         b[kSB2 + p] = (int)(o + 2 * hidden + (size_t)hidden * M + f);
         for (int j = 0; j < hidden; j++) b[kSW2 + j * kSW2Stride + p] = (int)(o + 2 * hidden + (size_t)j * M + f);
       }
+      if (!bf) continue;
+      // BF16 block (layout in kernels.h): float part, then W2 packed like the full
+      // net's layers (k slot (g, j) = position 16 (2 kc + j / 4) + 4 g + j % 4)
+      int* u = map.data() + (size_t)net * blk;
+      for (int q = 0; q < kSBFloat; q++) {
+        u[2 * q] = nat[q] >= 0 ? 4 * nat[q] + 2 : -1;
+        u[2 * q + 1] = nat[q] >= 0 ? -2 : -1;
+      }
+      auto w2 = [&](int hid, int gpos) -> int {
+        int f = pos_feature(gpos, h->s0);
+        if (hid >= hidden || f < 0) return -1;
+        return (int)(o + 2 * hidden + (size_t)hid * M + f);
+      };
+      const int f0 = 2 * kSBFloat, b0 = f0 + parts * kSW2F;
+      for (int part = 0; part < parts; part++)
+        for (int lane = 0; lane < 64; lane++)
+          for (int j = 0; j < 8; j++) {
+            const int g = lane >> 4, rb = lane & 15;
+            for (int mt = 0; mt < 8; mt++) {
+              int idx = w2(16 * (j / 4) + 4 * g + j % 4, 16 * mt + rb);
+              u[f0 + part * kSW2F + (mt * 64 + lane) * 8 + j] = idx >= 0 ? 4 * idx + part : -1;
+            }
+            for (int nt = 0; nt < 2; nt++)
+              for (int kc = 0; kc < 4; kc++) {
+                int idx = w2(16 * nt + rb, 16 * (2 * kc + j / 4) + 4 * g + j % 4);
+                u[b0 + part * kSW2B + ((nt * 4 + kc) * 64 + lane) * 8 + j] = idx >= 0 ? 4 * idx + part : -1;
+              }
+          }
     }
     HIPCHECK(h, hipMalloc(&h->d_student_map, sizeof(int) * map.size()));
     HIPCHECK(h, hipMemcpy(h->d_student_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
-    HIPCHECK(h, hipMalloc(&h->d_student, map.size() * storage_bytes(h->opt.precision)));
+    HIPCHECK(h, hipMalloc(&h->d_student, map.size() * (bf ? 2 : storage_bytes(h->opt.precision))));
     h->student_hidden = hidden;
   }
-  launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, (size_t)nnet * kStuElems, h->d_student_map,
-                        theta_s, h->d_student, (hipStream_t)stream);
+  if (bf)
+    launch_pack_bf16((size_t)nnet * blk, h->d_student_map, theta_s, (uint16_t*)h->d_student, (hipStream_t)stream);
+  else
+    launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, (size_t)nnet * kStuElems, h->d_student_map,
+                          theta_s, h->d_student, (hipStream_t)stream);
   HIPCHECK(h, hipGetLastError());
   for (int q = 0; q < nnet; q++) {
     h->st_lo[q] = s_lo[q];

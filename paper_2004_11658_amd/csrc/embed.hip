@@ -25,12 +25,15 @@
 // operand preparation; g_ij = dR^T dE/dR, F_i += g, F_j -= g (FP64 atomics), and the
 // per-centre virial -d (x) g.
 //
-// Operand precision is a policy of the kernels: NetNative<T> runs the layers on the
-// 16x16x4 MFMA in T (FP64 or FP32); NetBF16<PARTS> rounds the layer inputs to BF16 and
-// runs v_mfma_f32_16x16x32_bf16 with FP32 accumulation, one k chunk of 32 positions per
-// instruction, against weights pre-packed per lane (PARTS = 2 splits both operands
-// into hi + lo BF16 and sums hi hi + hi lo + lo hi).  Everything outside the layer
-// products (s, L0, biases, tanh, the skips, the contraction) stays in FP32.
+// The per-neighbour net is a policy of the kernels: the full embedding net or the
+// student net G_s(s) = tanh(s W1 + b1) W2 + b2 (1 -> H <= 32 -> M; its rows outside the
+// student's trained s range go to a fallback list handled by the FP64 full net, see
+// student_infer.hip), each with native operands (NetNative / StuNative: 16x16x4 MFMA in
+// T, FP64 or FP32) or BF16 operands (NetBF16 / StuBF16: layer inputs rounded to BF16 on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation, one k chunk of 32 positions per
+// instruction, against weights pre-packed per lane; PARTS = 2 splits both operands into
+// hi + lo BF16 and sums hi hi + hi lo + lo hi).  Everything outside the layer products
+// (s, layer 0, biases, tanh, the skips, the contraction) stays in FP32 or FP64.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -90,20 +93,46 @@ __device__ __forceinline__ T g_at(const T (&t0)[2][4], const T (&t1)[4][4], cons
 }
 
 
+template <class NP, class T>
+__device__ __forceinline__ T chain_back(const char* sm, typename NP::State& st, T (&res1)[4][4], const T* fn,
+                                        int g, int rb, int lane);
+
+// The full chain receives dE/dG element by element: the concat skip of the last layer
+// sums dE/dG[p] + dE/dG[p + 64] (res1), and t2 is overwritten by dE/dG (1 - t2^2), the
+// gradient of layer 2's pre-activation.
+template <class T>
+__device__ __forceinline__ void chain_take_dG(T (&t2)[8][4], T (&res1)[4][4], int mt, int q, T gG) {
+  if (mt < 4) res1[mt][q] = gG;
+  else res1[mt - 4][q] += gG;
+  t2[mt][q] = gG * ((T)1 - t2[mt][q] * t2[mt][q]);
+}
+
 // ------------------------------------------------------------------------------------
-// operand policies
+// net policies: State holds one chunk's activations; fwd() evaluates the net, G() reads
+// G at (tile mt, register q), take_dG() receives dE/dG at (mt, q) once G there has been
+// read, back() returns this lane's part of dE/ds (summed over the lane groups by the
+// caller)
 // ------------------------------------------------------------------------------------
 template <class T>
 struct NetNative {
   typedef T Tv;
+  static constexpr bool kStudent = false;
+  struct State {
+    T t0[2][4], t1[4][4], t2[8][4];
+  };
+  struct Aux {
+    T res1[4][4];
+  };
   static constexpr int kFwdBytes = sizeof(T) * kNetElems;   // staged by the forward kernel
   static constexpr int kBwdBytes = sizeof(T) * kNetElems;   // staged by the adjoint kernel
   static constexpr int kBlockBytes = sizeof(T) * kNetElems; // stride of the net blocks
-  __device__ static const T* fpart(const char* sm) { return (const T*)sm; }
-  __device__ static void fwd(const char* sm, T s, int g, int rb, int lane, T (&t0)[2][4], T (&t1)[4][4],
-                             T (&t2)[8][4]) {
-    chain_fwd<T>((const T*)sm, s, g, rb, t0, t1, t2);
+  __device__ static const char* block(const EmbedArgs& A, int pair) {
+    return (const char*)A.nets + (size_t)pair * kBlockBytes;
   }
+  __device__ static void fwd(const char* sm, T s, int g, int rb, int lane, State& st) {
+    chain_fwd<T>((const T*)sm, s, g, rb, st.t0, st.t1, st.t2);
+  }
+  __device__ static T G(const State& st, int mt, int q) { return g_at(st.t0, st.t1, st.t2, mt, q); }
   // out[nt] = (W2 d2)[nt] at layer-1 output positions 16 nt + lpos(g, q)
   __device__ static void adj2(const char* sm, const T (&d2)[8][4], int g, int rb, int lane, T (&out)[4][4]) {
     typedef typename Acc4<T>::type A4;
@@ -138,33 +167,82 @@ struct NetNative {
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  __device__ static void take_dG(State& st, Aux& ax, int mt, int q, T gG) { chain_take_dG(st.t2, ax.res1, mt, q, gG); }
+  __device__ static T back(const char* sm, State& st, Aux& ax, int g, int rb, int lane) {
+    return chain_back<NetNative<T>, T>(sm, st, ax.res1, (const T*)sm, g, rb, lane);
+  }
 };
+
+// Adjoint of the full chain (shared by both operand policies), after chain_take_dG:
+// layer 2's adjoint on t2 (now d2), plus the concat skip res1; the concat skip of layer
+// 1 passes the undamped dh1 on (dh1[p] + dh1[p + 32]); then dh1 is damped by 1 - t1^2;
+// layer 1's adjoint; ds = sum_p dh0 (1 - t0^2) W0.  fn: the float / double part holding
+// W0 at kOffW0.
+template <class NP, class T>
+__device__ __forceinline__ T chain_back(const char* sm, typename NP::State& st, T (&res1)[4][4], const T* fn,
+                                        int g, int rb, int lane) {
+  T dh1[4][4];
+  NP::adj2(sm, st.t2, g, rb, lane, dh1);
+  T dh0[2][4];
+#pragma unroll
+  for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) dh1[nt][q] += res1[nt][q];
+#pragma unroll
+  for (int nt = 0; nt < 2; nt++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) dh0[nt][q] = dh1[nt][q] + dh1[nt + 2][q];
+#pragma unroll
+  for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) dh1[nt][q] *= ((T)1 - st.t1[nt][q] * st.t1[nt][q]);
+  {
+    T w1d[2][4];
+    NP::adj1(sm, dh1, g, rb, lane, w1d);
+#pragma unroll
+    for (int nt = 0; nt < 2; nt++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) dh0[nt][q] += w1d[nt][q];
+  }
+  T dsl = (T)0;
+#pragma unroll
+  for (int nt = 0; nt < 2; nt++)
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+      dsl += dh0[nt][q] * ((T)1 - st.t0[nt][q] * st.t0[nt][q]) * fn[kOffW0 + 16 * nt + LP(g, q)];
+  return dsl;
+}
 
 // BF16 operands.  In the packed tiles, lane (g, rb) element j of k chunk kc stands for
 // the position 16 (2 kc + j / 4) + 4 g + j % 4 of the layer input: exactly the value the
 // lane holds in register j % 4 of tile 2 kc + j / 4, so a chunk of the B operand is two
 // accumulator tiles rounded to BF16 in place.
 template <int PARTS>
+__device__ __forceinline__ bf8 bf_tile(const char* sm, int off, int part, int gs, int t, int lane) {
+  return ((const bf8*)(sm + off + part * 2 * gs))[t * 64 + lane];
+}
+template <int PARTS, int NT>
+__device__ __forceinline__ void bf_pack(const float (&v)[NT][4], int kc, bf8& hi, bf8& lo) {
+  float x[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) x[j] = v[2 * kc + j / 4][j % 4];
+  split8<PARTS>(x, hi, lo);
+}
+
+template <int PARTS>
 struct NetBF16 {
   typedef float Tv;
+  static constexpr bool kStudent = false;
+  typedef typename NetNative<float>::State State;
+  typedef typename NetNative<float>::Aux Aux;
   static constexpr int kFloatBytes = 4 * kBFloat;
   static constexpr int kFwdBytes = kFloatBytes + PARTS * 2 * kBFwd;
   static constexpr int kBwdBytes = kFwdBytes + PARTS * 2 * kBBwd;
   static constexpr int kBlockBytes = 2 * bnet_u16(PARTS);
-  __device__ static const float* fpart(const char* sm) { return (const float*)sm; }
-  // tile t of a packed group starting at byte offset off, part (0 hi, 1 lo), group size gs (u16)
-  __device__ static bf8 tile(const char* sm, int off, int part, int gs, int t, int lane) {
-    return ((const bf8*)(sm + off + part * 2 * gs))[t * 64 + lane];
+  __device__ static const char* block(const EmbedArgs& A, int pair) {
+    return (const char*)A.nets + (size_t)pair * kBlockBytes;
   }
-  template <int NT>
-  __device__ static void pack(const float (&v)[NT][4], int kc, bf8& hi, bf8& lo) {
-    float x[8];
-#pragma unroll
-    for (int j = 0; j < 8; j++) x[j] = v[2 * kc + j / 4][j % 4];
-    split8<PARTS>(x, hi, lo);
-  }
-  __device__ static void fwd(const char* sm, float s, int g, int rb, int lane, float (&t0)[2][4],
-                             float (&t1)[4][4], float (&t2)[8][4]) {
+  __device__ static void fwd(const char* sm, float s, int g, int rb, int lane, State& st) {
     const float* fn = (const float*)sm;
     const int oF = kFloatBytes;
 #pragma unroll
@@ -172,55 +250,56 @@ struct NetBF16 {
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         int p = 16 * n + 4 * g + q;
-        t0[n][q] = tanh_t(s * fn[kOffW0 + p] + fn[kOffB0 + p]);
+        st.t0[n][q] = tanh_t(s * fn[kOffW0 + p] + fn[kOffB0 + p]);
       }
     bf8 xh, xl;
-    pack<2>(t0, 0, xh, xl);
+    bf_pack<PARTS, 2>(st.t0, 0, xh, xl);
 #pragma unroll
     for (int mt = 0; mt < 4; mt++) {
       f4v c = {0, 0, 0, 0};
-      bf8 wh = tile(sm, oF, 0, kBFwd, mt, lane);
-      bf8 wl = PARTS == 2 ? tile(sm, oF, 1, kBFwd, mt, lane) : wh;
+      bf8 wh = bf_tile<PARTS>(sm, oF, 0, kBFwd, mt, lane);
+      bf8 wl = PARTS == 2 ? bf_tile<PARTS>(sm, oF, 1, kBFwd, mt, lane) : wh;
       c = mfma_split<PARTS>(wh, wl, xh, xl, c);
 #pragma unroll
-      for (int q = 0; q < 4; q++) t1[mt][q] = tanh_t(c[q] + fn[kOffB1 + 16 * mt + 4 * g + q]);
+      for (int q = 0; q < 4; q++) st.t1[mt][q] = tanh_t(c[q] + fn[kOffB1 + 16 * mt + 4 * g + q]);
     }
     __builtin_amdgcn_sched_barrier(0);
     float h1[4][4];
 #pragma unroll
     for (int mt = 0; mt < 4; mt++)
 #pragma unroll
-      for (int q = 0; q < 4; q++) h1[mt][q] = t0[mt & 1][q] + t1[mt][q];
+      for (int q = 0; q < 4; q++) h1[mt][q] = st.t0[mt & 1][q] + st.t1[mt][q];
     bf8 hh[2], hl[2];
-    pack<4>(h1, 0, hh[0], hl[0]);
-    pack<4>(h1, 1, hh[1], hl[1]);
+    bf_pack<PARTS, 4>(h1, 0, hh[0], hl[0]);
+    bf_pack<PARTS, 4>(h1, 1, hh[1], hl[1]);
 #pragma unroll
     for (int mt = 0; mt < 8; mt++) {
       f4v c = {0, 0, 0, 0};
 #pragma unroll
       for (int kc = 0; kc < 2; kc++) {
-        bf8 wh = tile(sm, oF + 2 * kBW1F, 0, kBFwd, 2 * mt + kc, lane);
-        bf8 wl = PARTS == 2 ? tile(sm, oF + 2 * kBW1F, 1, kBFwd, 2 * mt + kc, lane) : wh;
+        bf8 wh = bf_tile<PARTS>(sm, oF + 2 * kBW1F, 0, kBFwd, 2 * mt + kc, lane);
+        bf8 wl = PARTS == 2 ? bf_tile<PARTS>(sm, oF + 2 * kBW1F, 1, kBFwd, 2 * mt + kc, lane) : wh;
         c = mfma_split<PARTS>(wh, wl, hh[kc], hl[kc], c);
       }
 #pragma unroll
-      for (int q = 0; q < 4; q++) t2[mt][q] = tanh_t(c[q] + fn[kOffB2 + 16 * mt + 4 * g + q]);
+      for (int q = 0; q < 4; q++) st.t2[mt][q] = tanh_t(c[q] + fn[kOffB2 + 16 * mt + 4 * g + q]);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  __device__ static float G(const State& st, int mt, int q) { return g_at(st.t0, st.t1, st.t2, mt, q); }
   __device__ static void adj2(const char* sm, const float (&d2)[8][4], int g, int rb, int lane,
                               float (&out)[4][4]) {
     const int oB = kFwdBytes + 2 * kBW1B;
     bf8 xh[4], xl[4];
 #pragma unroll
-    for (int kc = 0; kc < 4; kc++) pack<8>(d2, kc, xh[kc], xl[kc]);
+    for (int kc = 0; kc < 4; kc++) bf_pack<PARTS, 8>(d2, kc, xh[kc], xl[kc]);
 #pragma unroll
     for (int nt = 0; nt < 4; nt++) {
       f4v c = {0, 0, 0, 0};
 #pragma unroll
       for (int kc = 0; kc < 4; kc++) {
-        bf8 wh = tile(sm, oB, 0, kBBwd, 4 * nt + kc, lane);
-        bf8 wl = PARTS == 2 ? tile(sm, oB, 1, kBBwd, 4 * nt + kc, lane) : wh;
+        bf8 wh = bf_tile<PARTS>(sm, oB, 0, kBBwd, 4 * nt + kc, lane);
+        bf8 wl = PARTS == 2 ? bf_tile<PARTS>(sm, oB, 1, kBBwd, 4 * nt + kc, lane) : wh;
         c = mfma_split<PARTS>(wh, wl, xh[kc], xl[kc], c);
       }
 #pragma unroll
@@ -233,14 +312,14 @@ struct NetBF16 {
     const int oB = kFwdBytes;
     bf8 xh[2], xl[2];
 #pragma unroll
-    for (int kc = 0; kc < 2; kc++) pack<4>(d1, kc, xh[kc], xl[kc]);
+    for (int kc = 0; kc < 2; kc++) bf_pack<PARTS, 4>(d1, kc, xh[kc], xl[kc]);
 #pragma unroll
     for (int nt = 0; nt < 2; nt++) {
       f4v c = {0, 0, 0, 0};
 #pragma unroll
       for (int kc = 0; kc < 2; kc++) {
-        bf8 wh = tile(sm, oB, 0, kBBwd, 2 * nt + kc, lane);
-        bf8 wl = PARTS == 2 ? tile(sm, oB, 1, kBBwd, 2 * nt + kc, lane) : wh;
+        bf8 wh = bf_tile<PARTS>(sm, oB, 0, kBBwd, 2 * nt + kc, lane);
+        bf8 wl = PARTS == 2 ? bf_tile<PARTS>(sm, oB, 1, kBBwd, 2 * nt + kc, lane) : wh;
         c = mfma_split<PARTS>(wh, wl, xh[kc], xl[kc], c);
       }
 #pragma unroll
@@ -248,7 +327,143 @@ struct NetBF16 {
     }
     __builtin_amdgcn_sched_barrier(0);
   }
+  __device__ static void take_dG(State& st, Aux& ax, int mt, int q, float gG) {
+    chain_take_dG(st.t2, ax.res1, mt, q, gG);
+  }
+  __device__ static float back(const char* sm, State& st, Aux& ax, int g, int rb, int lane) {
+    return chain_back<NetBF16<PARTS>, float>(sm, st, ax.res1, (const float*)sm, g, rb, lane);
+  }
 };
+
+// Student net, native operands: block of kStuElems T (W1, b1 at hidden positions 0..31,
+// b2 at G positions, W2 [32][kSW2Stride]).
+template <class T>
+struct StuNative {
+  typedef T Tv;
+  static constexpr bool kStudent = true;
+  struct State {
+    T h[2][4], G[8][4];   // G is overwritten by dE/dG in the adjoint
+  };
+  struct Aux {};
+  static constexpr int kFwdBytes = sizeof(T) * kStuElems;
+  static constexpr int kBwdBytes = sizeof(T) * kStuElems;
+  static constexpr int kBlockBytes = sizeof(T) * kStuElems;
+  __device__ static const char* block(const EmbedArgs& A, int pair) {
+    return (const char*)A.snets + (size_t)pair * kBlockBytes;
+  }
+  __device__ static void fwd(const char* sm, T s, int g, int rb, int lane, State& st) {
+    typedef typename Acc4<T>::type A4;
+    const T* sn = (const T*)sm;
+#pragma unroll
+    for (int n = 0; n < 2; n++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        int p = 16 * n + LP(g, q);
+        st.h[n][q] = tanh_t(s * sn[kSW1 + p] + sn[kSB1 + p]);
+      }
+#pragma unroll
+    for (int mt = 0; mt < 8; mt++) {
+      A4 c = {0, 0, 0, 0};
+#pragma unroll
+      for (int n = 0; n < 2; n++)
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          c = mfma4(sn[kSW2 + (16 * n + LP(g, q)) * kSW2Stride + 16 * mt + rb], st.h[n][q], c);
+#pragma unroll
+      for (int q = 0; q < 4; q++) st.G[mt][q] = c[q] + sn[kSB2 + 16 * mt + LP(g, q)];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  __device__ static T G(const State& st, int mt, int q) { return st.G[mt][q]; }
+  __device__ static void take_dG(State& st, Aux&, int mt, int q, T gG) { st.G[mt][q] = gG; }
+  __device__ static T back(const char* sm, State& st, Aux&, int g, int rb, int lane) {
+    typedef typename Acc4<T>::type A4;
+    const T (&dG)[8][4] = st.G;
+    const T* sn = (const T*)sm;
+    T dsl = (T)0;
+#pragma unroll
+    for (int nt = 0; nt < 2; nt++) {
+      A4 c = {0, 0, 0, 0};
+#pragma unroll
+      for (int mt = 0; mt < 8; mt++)
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          c = mfma4(sn[kSW2 + (16 * nt + rb) * kSW2Stride + 16 * mt + LP(g, q)], dG[mt][q], c);
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        dsl += c[q] * ((T)1 - st.h[nt][q] * st.h[nt][q]) * sn[kSW1 + 16 * nt + LP(g, q)];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    return dsl;
+  }
+};
+
+// Student net, BF16 operands: float part (W1, b1, b2 at the kStuElems offsets), then W2
+// packed per lane for the forward (8 output tiles x 1 k chunk) and the adjoint (2 x 4).
+template <int PARTS>
+struct StuBF16 {
+  typedef float Tv;
+  static constexpr bool kStudent = true;
+  typedef typename StuNative<float>::State State;
+  typedef typename StuNative<float>::Aux Aux;
+  static constexpr int kFloatBytes = 4 * kSBFloat;
+  static constexpr int kFwdBytes = kFloatBytes + PARTS * 2 * kSW2F;
+  static constexpr int kBwdBytes = kFwdBytes + PARTS * 2 * kSW2B;
+  static constexpr int kBlockBytes = 2 * snet_u16(PARTS);
+  __device__ static const char* block(const EmbedArgs& A, int pair) {
+    return (const char*)A.snets + (size_t)pair * kBlockBytes;
+  }
+  __device__ static void fwd(const char* sm, float s, int g, int rb, int lane, State& st) {
+    const float* fn = (const float*)sm;
+#pragma unroll
+    for (int n = 0; n < 2; n++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        int p = 16 * n + 4 * g + q;
+        st.h[n][q] = tanh_t(s * fn[kSW1 + p] + fn[kSB1 + p]);
+      }
+    bf8 xh, xl;
+    bf_pack<PARTS, 2>(st.h, 0, xh, xl);
+#pragma unroll
+    for (int mt = 0; mt < 8; mt++) {
+      f4v c = {0, 0, 0, 0};
+      bf8 wh = bf_tile<PARTS>(sm, kFloatBytes, 0, kSW2F, mt, lane);
+      bf8 wl = PARTS == 2 ? bf_tile<PARTS>(sm, kFloatBytes, 1, kSW2F, mt, lane) : wh;
+      c = mfma_split<PARTS>(wh, wl, xh, xl, c);
+#pragma unroll
+      for (int q = 0; q < 4; q++) st.G[mt][q] = c[q] + fn[kSB2 + 16 * mt + 4 * g + q];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __device__ static float G(const State& st, int mt, int q) { return st.G[mt][q]; }
+  __device__ static void take_dG(State& st, Aux&, int mt, int q, float gG) { st.G[mt][q] = gG; }
+  __device__ static float back(const char* sm, State& st, Aux&, int g, int rb, int lane) {
+    const float* fn = (const float*)sm;
+    const float (&dG)[8][4] = st.G;
+    bf8 xh[4], xl[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; kc++) bf_pack<PARTS, 8>(dG, kc, xh[kc], xl[kc]);
+    float dsl = 0.f;
+#pragma unroll
+    for (int nt = 0; nt < 2; nt++) {
+      f4v c = {0, 0, 0, 0};
+#pragma unroll
+      for (int kc = 0; kc < 4; kc++) {
+        bf8 wh = bf_tile<PARTS>(sm, kFwdBytes, 0, kSW2B, 4 * nt + kc, lane);
+        bf8 wl = PARTS == 2 ? bf_tile<PARTS>(sm, kFwdBytes, 1, kSW2B, 4 * nt + kc, lane) : wh;
+        c = mfma_split<PARTS>(wh, wl, xh[kc], xl[kc], c);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; q++) dsl += c[q] * (1.f - st.h[nt][q] * st.h[nt][q]) * fn[kSW1 + 16 * nt + 4 * g + q];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    return dsl;
+  }
+};
+
+__device__ __forceinline__ bool out_of_range(const EmbedArgs& A, int pair, double s) {
+  return s < A.st_lo[pair] || s > A.st_hi[pair];
+}
 
 // ------------------------------------------------------------------------------------
 // forward: T_i = (1/N_m) sum_j G_j^T R_j
@@ -270,13 +485,19 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd(EmbedArgs A) {
     xi[1] = A.xe[3 * atom + 1];
     xi[2] = A.xe[3 * atom + 2];
   }
+  // FP32: each lane sums G R over its own rows of every chunk and the 16-row reduction
+  // runs once per centre; FP64 (register budget) reduces per chunk
+  constexpr bool kLaneAcc = sizeof(T) == 4;
   T acc[8];
 #pragma unroll
   for (int j = 0; j < 8; j++) acc[j] = (T)0;
+  T part[kLaneAcc ? 128 : 1];
+#pragma unroll
+  for (int j = 0; j < (kLaneAcc ? 128 : 1); j++) part[j] = (T)0;
   for (int beta = 0; beta < m.ntypes; beta++) {
+    const int pair = alpha * m.ntypes + beta;
     __syncthreads();
-    stage_bytes(smem_raw, (const char*)A.nets + (size_t)(alpha * m.ntypes + beta) * NP::kBlockBytes,
-                NP::kFwdBytes);
+    stage_bytes(smem_raw, NP::block(A, pair), NP::kFwdBytes);
     __syncthreads();
     if (atom < 0) continue;
     const int nn = A.nnei[atom * m.ntypes + beta];
@@ -287,44 +508,70 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd(EmbedArgs A) {
       T s = (T)0;
       T R[4] = {(T)0, (T)0, (T)0, (T)0};
       if (k < nn) {
-        env_row(m, A.xe, nl[k], xi, v);
-        s = (T)v.s;
+        const int e = nl[k];
+        env_row(m, A.xe, e, xi, v);
+        if (NP::kStudent && out_of_range(A, pair, v.s)) {
+          // left to the full net (fallback list); contributes nothing here
+          if (g == 0) {
+            int p = atomicAdd(A.fb_count, 1);
+            if (p < A.fb_cap) A.fb_list[p] = make_int2(row, e);
+          }
+        } else {
+          s = (T)v.s;
 #pragma unroll
-        for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
+          for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
+        }
       }
-      T t0[2][4], t1[4][4], t2[8][4];
-      NP::fwd(smem_raw, s, g, rb, lane, t0, t1, t2);
-      // reduce-scatter of the 128 products G[mt][q] R[c] over the 16 rows
-      const bool b3 = rb & 8, b2 = rb & 4, b1 = rb & 2, b0 = rb & 1;
-      T vv[64];
+      typename NP::State st;
+      NP::fwd(smem_raw, s, g, rb, lane, st);
+      if constexpr (kLaneAcc) {
+        // per-lane partial sums over this lane's rows of all chunks
 #pragma unroll
-      for (int kk = 0; kk < 64; kk++) {
-        int mt = kk >> 4, q = (kk >> 2) & 3, c = kk & 3;
-        T a = g_at(t0, t1, t2, mt, q) * R[c];
-        T b = g_at(t0, t1, t2, mt + 4, q) * R[c];
-        T send = b3 ? a : b;
-        T keep = b3 ? b : a;
-        vv[kk] = keep + dpp_mov<DPP_ROR8>(send);
-        if ((kk & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+        for (int kk = 0; kk < 128; kk++) {
+          int mt = kk >> 4, q = (kk >> 2) & 3, c = kk & 3;
+          part[kk] += NP::G(st, mt, q) * R[c];
+        }
+      } else {
+        // reduce-scatter of the 128 products G[mt][q] R[c] over the 16 rows
+        const bool b3 = rb & 8, b2 = rb & 4, b1 = rb & 2, b0 = rb & 1;
+        T vv[64];
+#pragma unroll
+        for (int kk = 0; kk < 64; kk++) {
+          int mt = kk >> 4, q = (kk >> 2) & 3, c = kk & 3;
+          T a = NP::G(st, mt, q) * R[c];
+          T b = NP::G(st, mt + 4, q) * R[c];
+          T send = b3 ? a : b;
+          T keep = b3 ? b : a;
+          vv[kk] = keep + dpp_mov<DPP_ROR8>(send);
+          if ((kk & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+        }
+        rs_step<T, 64, DPP_HALF_MIRROR>(vv, b2);
+        rs_step<T, 32, DPP_XOR2>(vv, b1);
+        rs_step<T, 16, DPP_XOR1>(vv, b0);
+#pragma unroll
+        for (int j = 0; j < 8; j++) acc[j] += vv[j];
       }
-      rs_step<T, 64, DPP_HALF_MIRROR>(vv, b2);
-      rs_step<T, 32, DPP_XOR2>(vv, b1);
-      rs_step<T, 16, DPP_XOR1>(vv, b0);
-#pragma unroll
-      for (int j = 0; j < 8; j++) acc[j] += vv[j];
     }
   }
-  if (atom < 0) return;
-  // lane holds tile mt = 4 b3 + 2 b2 + b1, register q = 2 b0 + j / 4, c = j % 4
-  const int mt = 4 * ((rb >> 3) & 1) + 2 * ((rb >> 2) & 1) + ((rb >> 1) & 1);
-  T* Tout = (T*)A.T + (size_t)row * m.M * 4;
+  if constexpr (kLaneAcc) {
+    // one reduce-scatter of the lane partials over the 16 rows of the wave
+    const bool b3 = rb & 8, b2 = rb & 4, b1 = rb & 2, b0 = rb & 1;
+    T vv[64];
 #pragma unroll
-  for (int j = 0; j < 8; j++) {
-    int q = 2 * (rb & 1) + (j >> 2), c = j & 3;
-    int p = 16 * mt + LP(g, q);
-    int f = (p % kP0) < m.s0 ? (p / kP0) * m.s0 + (p % kP0) : -1;
-    if (f >= 0) Tout[f * 4 + c] = acc[j] * (T)m.inv_norm;
+    for (int kk = 0; kk < 64; kk++) {
+      T a = part[kk], b = part[kk + 64];
+      T send = b3 ? a : b;
+      T keep = b3 ? b : a;
+      vv[kk] = keep + dpp_mov<DPP_ROR8>(send);
+    }
+    rs_step<T, 64, DPP_HALF_MIRROR>(vv, b2);
+    rs_step<T, 32, DPP_XOR2>(vv, b1);
+    rs_step<T, 16, DPP_XOR1>(vv, b0);
+#pragma unroll
+    for (int j = 0; j < 8; j++) acc[j] = vv[j];
   }
+  if (atom < 0) return;
+  write_T<T>((T*)A.T + (size_t)row * m.M * 4, acc, rb, g, m.s0, (T)m.inv_norm);
 }
 
 // ------------------------------------------------------------------------------------
@@ -355,20 +602,25 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd(EmbedArgs A) {
       gt[q] = f >= 0 ? src[f * 4 + c] : (T)0;
     }
   }
-  double fi[3] = {0, 0, 0};
-  double vir[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double fi = 0;                  // force component g on the centre (lane groups 0..2)
+  double vir[3] = {0, 0, 0};      // virial column g: W[a][g]
   const T inorm = (T)m.inv_norm;
+  constexpr bool kMfmaGG = sizeof(T) == 4;
+  T ga[kMfmaGG ? 8 : 1];   // MFMA A operand of dE/dG: dE/dT[16 mt + rb][g] / N_m
   for (int beta = 0; beta < m.ntypes; beta++) {
+    const int pair = alpha * m.ntypes + beta;
     __syncthreads();
-    stage_bytes(smem_raw, (const char*)A.nets + (size_t)(alpha * m.ntypes + beta) * NP::kBlockBytes,
-                NP::kBwdBytes);
+    stage_bytes(smem_raw, NP::block(A, pair), NP::kBwdBytes);
     __syncthreads();
     if (atom < 0) continue;
+    if (kMfmaGG && beta == 0)
+#pragma unroll
+      for (int mt = 0; mt < (kMfmaGG ? 8 : 1); mt++) ga[mt] = gt[(16 * mt + rb) * 4 + g] * inorm;
     const int nn = A.nnei[atom * m.ntypes + beta];
     const int* nl = A.nlist + (size_t)atom * m.nm + m.sel_off[beta];
     for (int c0 = 0; c0 < nn; c0 += 16) {
       const int k = c0 + rb;
-      const bool valid = k < nn;
+      bool valid = k < nn;
       Env v;
       int e = -1;
       T s = (T)0;
@@ -376,61 +628,42 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd(EmbedArgs A) {
       if (valid) {
         e = nl[k];
         env_row(m, A.xe, e, xi, v);
-        s = (T)v.s;
+        if (NP::kStudent && out_of_range(A, pair, v.s)) {
+          valid = false;  // handled by the fallback kernel
+        } else {
+          s = (T)v.s;
 #pragma unroll
-        for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
+          for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
+        }
       }
-      T t0[2][4], t1[4][4], t2[8][4];
-      NP::fwd(smem_raw, s, g, rb, lane, t0, t1, t2);
-      // dE/dG (Eq. 4 adjoint) and the G.dE/dT part of dE/dR
+      typename NP::State st;
+      NP::fwd(smem_raw, s, g, rb, lane, st);
+      // dE/dG (Eq. 4 adjoint) and the G.dE/dT part of dE/dR.  dE/dG[p][row] =
+      // sum_c (dE/dT[p][c] / N_m) R[row][c] is one 16x16x4 MFMA per position tile: A =
+      // dE/dT of the tile (lane (g, i) holds position 16 mt + i, component g), B = R
+      // (lane (g, row) holds component g of its row); the result lands in the layout
+      // of G itself.  (FP64 keeps the VALU form: its register budget has no room for
+      // the operand.)
       T gR[4] = {(T)0, (T)0, (T)0, (T)0};
-      T res1[4][4];   // dE/dG[p] + dE/dG[p + 64]: the concat skip of the last layer
+      typename NP::Aux ax;
+      const T Rg = g == 0 ? R[0] : g == 1 ? R[1] : g == 2 ? R[2] : R[3];
 #pragma unroll
-      for (int mt = 0; mt < 8; mt++)
+      for (int mt = 0; mt < 8; mt++) {
+        typename Acc4<T>::type gGt = {0, 0, 0, 0};
+        if constexpr (kMfmaGG) gGt = mfma4(ga[mt], Rg, gGt);
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           const T* gp = gt + (16 * mt + LP(g, q)) * 4;
-          T G = g_at(t0, t1, t2, mt, q);
-          T gG = (gp[0] * R[0] + gp[1] * R[1] + gp[2] * R[2] + gp[3] * R[3]) * inorm;
+          const T G = NP::G(st, mt, q);
 #pragma unroll
           for (int c = 0; c < 4; c++) gR[c] += G * gp[c];
-          if (mt < 4) res1[mt][q] = gG;
-          else res1[mt - 4][q] += gG;
-          t2[mt][q] = gG * ((T)1 - t2[mt][q] * t2[mt][q]);  // becomes d(pre-activation)
+          T gG;
+          if constexpr (kMfmaGG) gG = gGt[q];
+          else gG = (gp[0] * R[0] + gp[1] * R[1] + gp[2] * R[2] + gp[3] * R[3]) * inorm;
+          NP::take_dG(st, ax, mt, q, gG);
         }
-      // layer 2 adjoint: dh1 = res1 + W2 . d2; the concat skip of layer 1 passes the
-      // undamped dh1 on (dh1[p] + dh1[p + 32]); then dh1 is damped by 1 - t1^2
-      T dh1[4][4];
-      NP::adj2(smem_raw, t2, g, rb, lane, dh1);
-#pragma unroll
-      for (int nt = 0; nt < 4; nt++)
-#pragma unroll
-        for (int q = 0; q < 4; q++) dh1[nt][q] += res1[nt][q];
-      T dh0[2][4];
-#pragma unroll
-      for (int nt = 0; nt < 2; nt++)
-#pragma unroll
-        for (int q = 0; q < 4; q++) dh0[nt][q] = dh1[nt][q] + dh1[nt + 2][q];
-#pragma unroll
-      for (int nt = 0; nt < 4; nt++)
-#pragma unroll
-        for (int q = 0; q < 4; q++) dh1[nt][q] *= ((T)1 - t1[nt][q] * t1[nt][q]);
-      // layer 1 adjoint: dh0 += W1 . d1
-      {
-        T w1d[2][4];
-        NP::adj1(smem_raw, dh1, g, rb, lane, w1d);
-#pragma unroll
-        for (int nt = 0; nt < 2; nt++)
-#pragma unroll
-          for (int q = 0; q < 4; q++) dh0[nt][q] += w1d[nt][q];
       }
-      // layer 0: ds = sum_p dh0 (1 - t0^2) W0
-      T dsl = (T)0;
-#pragma unroll
-      for (int nt = 0; nt < 2; nt++)
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-          dsl += dh0[nt][q] * ((T)1 - t0[nt][q] * t0[nt][q]) * NP::fpart(smem_raw)[kOffW0 + 16 * nt + LP(g, q)];
+      T dsl = NP::back(smem_raw, st, ax, g, rb, lane);
       // sum over the 4 lane groups holding the same row
       dsl += shfl_x(dsl, 16);
       dsl += shfl_x(dsl, 32);
@@ -439,48 +672,38 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd(EmbedArgs A) {
         gR[c] += shfl_x(gR[c], 16);
         gR[c] += shfl_x(gR[c], 32);
       }
-      if (valid && g == 0) {
+      // g_ij = dR^T dE/dR (Eq. 5 differentiated): lane group g < 3 computes component g
+      if (valid && g < 3) {
         double gRd[4] = {(double)gR[0] * m.inv_norm + (double)dsl, (double)gR[1] * m.inv_norm,
                          (double)gR[2] * m.inv_norm, (double)gR[3] * m.inv_norm};
-        // g_b = sum_c dE/dR_c dR_c/dd_b (Eq. 5 differentiated)
-        double ir = 1.0 / v.r;
+        double ir = v.ir;
         double sr = v.s * ir;
         double qf = (v.ds * ir - v.s * ir * ir) * ir;
         double dot = gRd[1] * v.d[0] + gRd[2] * v.d[1] + gRd[3] * v.d[2];
-        double gv[3];
+        const double db = g == 0 ? v.d[0] : g == 1 ? v.d[1] : v.d[2];
+        const double gRb = g == 0 ? gRd[1] : g == 1 ? gRd[2] : gRd[3];
+        const double gv = gRd[0] * v.ds * db * ir + qf * dot * db + sr * gRb;
+        fi += gv;
+        if (A.gbuf) A.gbuf[((size_t)atom * m.nm + m.sel_off[beta] + k) * 3 + g] = gv;
+        else unsafeAtomicAdd(&A.forces[3 * A.eown[e] + g], -gv);
 #pragma unroll
-        for (int b = 0; b < 3; b++) gv[b] = gRd[0] * v.ds * v.d[b] * ir + qf * dot * v.d[b] + sr * gRd[1 + b];
-        int own = A.eown[e];
-#pragma unroll
-        for (int b = 0; b < 3; b++) {
-          fi[b] += gv[b];
-          unsafeAtomicAdd(&A.forces[3 * own + b], -gv[b]);
-        }
-#pragma unroll
-        for (int a = 0; a < 3; a++)
-#pragma unroll
-          for (int b = 0; b < 3; b++) vir[3 * a + b] -= v.d[a] * gv[b];
+        for (int a = 0; a < 3; a++) vir[a] -= v.d[a] * gv;   // W[a][g]
       }
     }
   }
   if (atom < 0) return;
-  // reduce over the 16 rows (lanes 0..15 hold the sums; other lane groups hold zeros)
+  // reduce over the 16 rows of each lane group (group g < 3 holds component g)
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
+  for (int o = 1; o < 16; o <<= 1) {
+    fi += __shfl_xor(fi, o);
 #pragma unroll
-    for (int b = 0; b < 3; b++) fi[b] += __shfl_xor(fi[b], o);
-#pragma unroll
-    for (int q = 0; q < 9; q++) vir[q] += __shfl_xor(vir[q], o);
+    for (int a = 0; a < 3; a++) vir[a] += __shfl_xor(vir[a], o);
   }
-  if (lane == 0) {
+  if (rb == 0 && g < 3) {
+    if (A.gbuf) A.forces[3 * atom + g] = fi;   // the -g_ij of other centres are gathered later
+    else unsafeAtomicAdd(&A.forces[3 * atom + g], fi);
 #pragma unroll
-    for (int b = 0; b < 3; b++) unsafeAtomicAdd(&A.forces[3 * atom + b], fi[b]);
-  }
-  if (lane < 9) {
-    double val = 0;
-#pragma unroll
-    for (int q = 0; q < 9; q++) val = (lane == q) ? vir[q] : val;
-    A.vir_part[(size_t)row * 9 + lane] = val;
+    for (int a = 0; a < 3; a++) A.vir_part[(size_t)row * 9 + 3 * a + g] = vir[a];
   }
 }
 
@@ -520,6 +743,24 @@ void launch_embed_bwd(const EmbedArgs& a, hipStream_t st) {
     case PREC_FP32: embed_bwd_t<NetNative<float>>(a, st); break;
     case PREC_BF16: embed_bwd_t<NetBF16<1>>(a, st); break;
     default: embed_bwd_t<NetBF16<2>>(a, st); break;
+  }
+}
+
+void launch_student_fwd(const EmbedArgs& a, hipStream_t st) {
+  switch (a.prec) {
+    case PREC_FP64: embed_fwd_t<StuNative<double>>(a, st); break;
+    case PREC_FP32: embed_fwd_t<StuNative<float>>(a, st); break;
+    case PREC_BF16: embed_fwd_t<StuBF16<1>>(a, st); break;
+    default: embed_fwd_t<StuBF16<2>>(a, st); break;
+  }
+}
+
+void launch_student_bwd(const EmbedArgs& a, hipStream_t st) {
+  switch (a.prec) {
+    case PREC_FP64: embed_bwd_t<StuNative<double>>(a, st); break;
+    case PREC_FP32: embed_bwd_t<StuNative<float>>(a, st); break;
+    case PREC_BF16: embed_bwd_t<StuBF16<1>>(a, st); break;
+    default: embed_bwd_t<StuBF16<2>>(a, st); break;
   }
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
+#include "bf16ops.h"
 #include "devmath.h"
 #include "kernels.h"
 
@@ -71,36 +72,11 @@ __device__ __forceinline__ void stage_bytes(void* __restrict__ dst, const void* 
   for (int q = threadIdx.x; q < nbytes / 16; q += blockDim.x) d[q] = s[q];
 }
 
-// BF16 MFMA operands: 8 bf16 per lane for v_mfma_f32_16x16x32_bf16.  The k slot (lane
-// group, element) is the same for the A and the B operand, so a product sums over any
-// bijection of positions onto slots that both operands follow.
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-__device__ __forceinline__ f4v mfma_bf(bf8 a, bf8 b, f4v c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-// round 8 floats to bf16 (nearest even) and, for the split mode, the residuals
-template <int PARTS>
-__device__ __forceinline__ void split8(const float (&v)[8], bf8& hi, bf8& lo) {
-#pragma unroll
-  for (int j = 0; j < 8; j++) {
-    __bf16 h = (__bf16)v[j];
-    hi[j] = h;
-    if (PARTS == 2) lo[j] = (__bf16)(v[j] - (float)h);
-  }
-}
-// c += A B with A, B given as hi (+ lo): hi hi (+ hi lo + lo hi)
-template <int PARTS>
-__device__ __forceinline__ f4v mfma_split(bf8 ah, bf8 al, bf8 bh, bf8 bl, f4v c) {
-  if (PARTS == 2) {
-    c = mfma_bf(al, bh, c);
-    c = mfma_bf(ah, bl, c);
-  }
-  return mfma_bf(ah, bh, c);
-}
+
 
 // Environment row of one neighbour (Eq. 5) and its derivative with respect to d.
 struct Env {
-  double d[3], r, s, ds, R[4];
+  double d[3], r, ir, s, ds, R[4];
 };
 __device__ __forceinline__ void env_row(const ModelC& m, const double* __restrict__ xe, int e,
                                         const double xi[3], Env& v) {
@@ -109,8 +85,9 @@ __device__ __forceinline__ void env_row(const ModelC& m, const double* __restric
   v.d[2] = xe[3 * e + 2] - xi[2];
   double r2 = v.d[0] * v.d[0] + v.d[1] * v.d[1] + v.d[2] * v.d[2];
   v.r = sqrt(r2);
-  smooth_fn(m, v.r, v.s, v.ds);
-  double sr = v.s / v.r;
+  v.ir = 1.0 / v.r;
+  smooth_fn_ir(m, v.r, v.ir, v.s, v.ds);
+  double sr = v.s * v.ir;
   v.R[0] = v.s;
   v.R[1] = sr * v.d[0];
   v.R[2] = sr * v.d[1];

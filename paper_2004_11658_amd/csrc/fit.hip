@@ -15,6 +15,7 @@
 // TANH / TANHGrad, Section 3.2.3).
 #include <hip/hip_runtime.h>
 
+#include "bf16ops.h"
 #include "common.h"
 #include "kernels.h"
 #include "devmath.h"
@@ -41,9 +42,22 @@ enum Epi { EPI_FWD1 = 0, EPI_FWDRES = 1, EPI_BWD = 2, EPI_BWD1 = 3 };
 constexpr int BM = 64;    // output tile rows (one species per tile)
 constexpr int BN = 128;   // output tile columns
 
+// Output tile of this workgroup.  Workgroups are dealt to the 8 XCDs round robin
+// (block b runs on XCD b % 8), each XCD with its own L2; the mapping gives every XCD a
+// contiguous range of tiles, columns fastest, so the column tiles of one row tile
+// (which read the same activation rows) run on one XCD and share its L2.
+__device__ __forceinline__ void gemm_tile(int nct, int& r0, int& n0) {
+  const int nb = gridDim.x, b = blockIdx.x, x = b & 7;
+  const int q = nb >> 3, r = nb & 7;
+  const int L = x * q + (x < r ? x : r) + (b >> 3);
+  r0 = (L / nct) * BM;
+  n0 = (L % nct) * BN;
+}
+
 struct GemmArgs {
   int nrows, K, N;
   const void* const* Wb; // BF16 modes: operand table (see FitArgs::Wb)
+
   const int* type_row0;
   int ntypes;
   const void* A;        // [nrows][K]
@@ -67,8 +81,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs G) {
   constexpr int BPT = KT * BN / 256;     // B elements per thread per tile
   __shared__ T As[BM][KT + 1];
   __shared__ T Bs[KT][BN + 1];
-  const int r0 = blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
+  int r0, n0;
+  gemm_tile((G.N + BN - 1) / BN, r0, n0);
   int sp = -1;
   for (int t = 0; t < G.ntypes; t++)
     if (r0 >= G.type_row0[t] && r0 < G.type_row0[t + 1]) sp = t;
@@ -198,8 +212,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf(GemmArgs G) {
   constexpr int KT = 64, LDK = KT + 8;
   __shared__ __align__(16) __bf16 As[PARTS][BM][LDK];
   __shared__ __align__(16) __bf16 Bs[PARTS][BN][LDK];
-  const int r0 = blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
+  int r0, n0;
+  gemm_tile((G.N + BN - 1) / BN, r0, n0);
   int sp = -1;
   for (int t = 0; t < G.ntypes; t++)
     if (r0 >= G.type_row0[t] && r0 < G.type_row0[t + 1]) sp = t;
@@ -340,6 +354,143 @@ __global__ __launch_bounds__(256) void k_gemm_bf(GemmArgs G) {
     }
 }
 
+// ------------------------------------------------------------------------------------
+// BF16 first fitting layer with the descriptor fused in (forward).
+//
+// A workgroup takes 32 rows (one species) and stages their T rows in LDS (pad rows as
+// zeros); x1 = tanh(D W1 + b1) over all N columns, with D = T T<^T (Eq. 4) formed stage
+// by stage (64 k at a time, double-buffered) straight into BF16 MFMA operands in LDS,
+// so D never reaches HBM; wave w owns the column tiles w, w + 4, ...; W1^T is read
+// from L2/HBM per lane (16 bytes per MFMA tile), one k chunk ahead.
+// ------------------------------------------------------------------------------------
+constexpr int F1R = 32;     // rows per workgroup
+constexpr int F1KC = 64;    // k per A stage (two MFMA k chunks)
+constexpr int F1LDA = F1KC + 8;
+
+struct Fit1Args {
+  int M, N, nfit;              // embedding width, hidden width (multiple of 16, <= 256), layers
+  const int* type_row0;
+  int ntypes;
+  const int* row_atom;
+  const float* T;              // [nrows][M][4]
+  const void* const* Wb;       // operand table: [(species * nfit + k) * 4 + dir * 2 + part]
+  const void* const* bias;     // [species * nfit + k]
+  float *out, *out2;           // x1 and t1 [nrows][N]
+};
+
+__device__ __forceinline__ int fit1_species(const Fit1Args& P, int r0) {
+  for (int t = 0; t < P.ntypes; t++)
+    if (r0 >= P.type_row0[t] && r0 < P.type_row0[t + 1]) return t;
+  return -1;
+}
+
+__device__ __forceinline__ void fit1_stage_T(const Fit1Args& P, int r0, float* Ts) {
+  for (int q = threadIdx.x; q < F1R * P.M; q += blockDim.x) {
+    int r = q / P.M, a = q - r * P.M;
+    float4 v = {0.f, 0.f, 0.f, 0.f};
+    if (P.row_atom[r0 + r] >= 0) v = *(const float4*)(P.T + ((size_t)(r0 + r) * P.M + a) * 4);
+    *(float4*)(Ts + (r * P.M + a) * 4) = v;
+  }
+}
+
+template <int PARTS>
+__global__ __launch_bounds__(256) void k_fit1_fwd_bf(Fit1Args P) {
+  extern __shared__ __align__(16) char sm[];
+  float* Ts = (float*)sm;                                   // [F1R][M][4]
+  __bf16* As = (__bf16*)(sm + (size_t)F1R * P.M * 16);       // [2][PARTS][F1R][F1LDA]
+  const int r0 = blockIdx.x * F1R;
+  const int sp = fit1_species(P, r0);
+  if (sp < 0) return;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, rb = lane & 15, g = lane >> 4;
+  const int M = P.M, K = 16 * M, N = P.N, ntile = N / 16;
+  fit1_stage_T(P, r0, Ts);
+  __syncthreads();
+  // A stage s: thread t forms D[row t / 8][s * 64 + 8 (t % 8) + i], i < 8 (one a, 8 b)
+  auto make_A = [&](int s, int buf) {
+    const int r = tid >> 3, kq = (tid & 7) * 8;
+    const int k = s * F1KC + kq, a = k >> 4, b0 = k & 15;
+    const float* tr = Ts + r * M * 4;
+    const float4 ta = *(const float4*)(tr + 4 * a);
+    float d[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      const float4 tb = *(const float4*)(tr + 4 * (b0 + i));
+      d[i] = ta.x * tb.x + ta.y * tb.y + ta.z * tb.z + ta.w * tb.w;
+    }
+    bf8 hi, lo;
+    split8<PARTS>(d, hi, lo);
+    *(bf8*)(As + ((size_t)(buf * PARTS + 0) * F1R + r) * F1LDA + kq) = hi;
+    if (PARTS == 2) *(bf8*)(As + ((size_t)(buf * PARTS + 1) * F1R + r) * F1LDA + kq) = lo;
+  };
+  const int wi = (sp * P.nfit + 0) * 4 + 0;   // W1^T [N][K]
+  const __bf16* __restrict__ Wh = (const __bf16*)P.Wb[wi];
+  const __bf16* __restrict__ Wl = (const __bf16*)P.Wb[wi + 1];
+  f4v acc[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+    for (int u = 0; u < 4; u++) acc[rt][u] = f4v{0, 0, 0, 0};
+  // B operand of k chunk c (global k = 32 c): lane (g, rb) holds W1^T[col][32 c + 8 g .. + 7]
+  bf8 bh[4], bl[4], nh[4], nl[4];
+  auto load_B = [&](int c, bf8 (&h)[4], bf8 (&l)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int ct = wv + 4 * u;
+      if (ct < ntile) {
+        const size_t o = (size_t)(16 * ct + rb) * K + 32 * c + 8 * g;
+        h[u] = *(const bf8*)(Wh + o);
+        l[u] = PARTS == 2 ? *(const bf8*)(Wl + o) : h[u];
+      }
+    }
+  };
+  const int S = K / F1KC, C = K / 32;
+  make_A(0, 0);
+  load_B(0, bh, bl);
+  __syncthreads();
+  for (int c = 0; c < C; c++) {
+    const int s = c >> 1, kc = c & 1, buf = s & 1;
+    if (kc == 0 && s + 1 < S) make_A(s + 1, (s + 1) & 1);
+    if (c + 1 < C) load_B(c + 1, nh, nl);
+    bf8 ah[2], al[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; rt++) {
+      ah[rt] = *(const bf8*)(As + ((size_t)(buf * PARTS + 0) * F1R + 16 * rt + rb) * F1LDA + 32 * kc + 8 * g);
+      al[rt] = PARTS == 2 ? *(const bf8*)(As + ((size_t)(buf * PARTS + 1) * F1R + 16 * rt + rb) * F1LDA + 32 * kc + 8 * g)
+                          : ah[rt];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (wv + 4 * u < ntile)
+#pragma unroll
+        for (int rt = 0; rt < 2; rt++) acc[rt][u] = mfma_split<PARTS>(ah[rt], al[rt], bh[u], bl[u], acc[rt][u]);
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      bh[u] = nh[u];
+      bl[u] = nl[u];
+    }
+    if (kc == 1) __syncthreads();
+  }
+  const float* bias = (const float*)P.bias[sp * P.nfit + 0];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int ct = wv + 4 * u;
+    if (ct >= ntile) continue;
+    const int col = 16 * ct + rb;
+    const float bc = bias[col];
+#pragma unroll
+    for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const size_t o = (size_t)(r0 + 16 * rt + 4 * g + q) * N + col;
+        const float t = dp_tanh(acc[rt][u][q] + bc);
+        P.out[o] = t;
+        P.out2[o] = t;
+      }
+  }
+}
+
+size_t fit1_fwd_lds(int M, int parts) { return (size_t)F1R * M * 16 + (size_t)2 * parts * F1R * F1LDA * 2; }
+
 // D[row][a m2 + b] = sum_c T[row][a][c] T[row][b][c]; pad rows get zeros
 template <class T>
 __global__ void k_desc(int nrows, int M, int m2, const int* __restrict__ row_atom,
@@ -415,7 +566,7 @@ __global__ void k_fit_out(int nrows, int N, int ntypes, const int* __restrict__ 
 
 template <class T, int EPI>
 static void gemm(int prec, const GemmArgs& G, hipStream_t st) {
-  dim3 grid((G.nrows + BM - 1) / BM, (G.N + BN - 1) / BN);
+  dim3 grid(((G.nrows + BM - 1) / BM) * ((G.N + BN - 1) / BN));
   if (prec == PREC_BF16) hipLaunchKernelGGL((k_gemm_bf<1, EPI>), grid, dim3(256), 0, st, G);
   else if (prec == PREC_BF16X3) hipLaunchKernelGGL((k_gemm_bf<2, EPI>), grid, dim3(256), 0, st, G);
   else hipLaunchKernelGGL((k_gemm<T, EPI>), grid, dim3(256), 0, st, G);
@@ -425,7 +576,22 @@ template <class T>
 static void fit_t(const FitArgs& F, hipStream_t st) {
   const int prec = F.prec;
   const int rows = F.nrows, M = F.m.M, m2 = F.m.m2, K1 = M * m2, fw = F.fw;
-  {
+  // BF16 modes run the first layer (forward and adjoint) with the descriptor fused in
+  const bool bf = prec == PREC_BF16 || prec == PREC_BF16X3;
+  const int parts = prec == PREC_BF16X3 ? 2 : 1;
+  const bool fuse_desc = bf && m2 == 16 && M % 4 == 0 && M >= 16 && fw % 16 == 0 && fw <= 256 &&
+                         rows % F1R == 0;
+  Fit1Args P1{};
+  P1.M = M;
+  P1.N = fw;
+  P1.nfit = F.nfit;
+  P1.type_row0 = F.type_row0;
+  P1.ntypes = F.m.ntypes;
+  P1.row_atom = F.row_atom;
+  P1.T = (const float*)F.T;
+  P1.Wb = F.Wb;
+  P1.bias = F.b;
+  if (!fuse_desc) {
     size_t tot = (size_t)rows * K1;
     hipLaunchKernelGGL(k_desc<T>, dim3((tot + 255) / 256), dim3(256), 0, st, rows, M, m2, F.row_atom,
                        (const T*)F.T, (T*)F.D);
@@ -449,8 +615,22 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
     G.Xprev = k == 0 ? nullptr : (const void*)(xs + (k - 1) * L);
     G.out = xs + k * L;
     G.out2 = act + k * L;
-    if (k == 0) gemm<T, EPI_FWD1>(prec, G, st);
-    else gemm<T, EPI_FWDRES>(prec, G, st);
+    if (k == 0 && fuse_desc) {
+      P1.out = (float*)(xs + k * L);
+      P1.out2 = (float*)(act + k * L);
+      const size_t sh = fit1_fwd_lds(M, parts);
+      if (parts == 2) {
+        (void)hipFuncSetAttribute((const void*)k_fit1_fwd_bf<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        hipLaunchKernelGGL(k_fit1_fwd_bf<2>, dim3(rows / F1R), dim3(256), sh, st, P1);
+      } else {
+        (void)hipFuncSetAttribute((const void*)k_fit1_fwd_bf<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        hipLaunchKernelGGL(k_fit1_fwd_bf<1>, dim3(rows / F1R), dim3(256), sh, st, P1);
+      }
+    } else if (k == 0) {
+      gemm<T, EPI_FWD1>(prec, G, st);
+    } else {
+      gemm<T, EPI_FWDRES>(prec, G, st);
+    }
   }
   hipLaunchKernelGGL(k_fit_out<T>, dim3((rows + 3) / 4), dim3(256), 0, st, rows, fw, F.m.ntypes,
                      F.type_row0, F.row_atom, (const T*)(xs + (F.nfit - 1) * L), F.wo, F.bo, F.Ei,
@@ -498,20 +678,25 @@ void launch_zero(double* p, size_t n, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, st, n, p);
 }
 
-// per frame, fixed-order sums of E_i and the per-centre virials (one block per frame)
-__global__ __launch_bounds__(256) void k_frame_reduce(const Frame* __restrict__ frames,
-                                                      const int* __restrict__ row_of,
-                                                      const double* __restrict__ Ei,
-                                                      const double* __restrict__ vir,
-                                                      double* __restrict__ energies,
-                                                      double* __restrict__ virials,
-                                                      double* __restrict__ atom_energy) {
+// Per frame, fixed-order sums of E_i and the per-centre virials in two passes: block
+// (c, f) sums the atoms [c * kRedChunk, (c + 1) * kRedChunk) of frame f into partial
+// row (f, c); then one block per frame adds its partial rows in order.
+constexpr int kRedChunk = 1024;
+
+__global__ __launch_bounds__(256) void k_frame_partial(const Frame* __restrict__ frames,
+                                                       const int* __restrict__ row_of,
+                                                       const double* __restrict__ Ei,
+                                                       const double* __restrict__ vir,
+                                                       double* __restrict__ atom_energy,
+                                                       double* __restrict__ part) {
   __shared__ double sh[256][10];
-  const Frame& F = frames[blockIdx.x];
+  const Frame& F = frames[blockIdx.y];
+  const int beg = F.atom0 + blockIdx.x * kRedChunk;
+  const int end = min(F.atom0 + F.natoms, beg + kRedChunk);
   double acc[10];
 #pragma unroll
   for (int q = 0; q < 10; q++) acc[q] = 0.0;
-  for (int i = F.atom0 + threadIdx.x; i < F.atom0 + F.natoms; i += 256) {
+  for (int i = beg + threadIdx.x; i < end; i += 256) {
     int r = row_of[i];
     double e = Ei[r];
     acc[0] += e;
@@ -529,19 +714,29 @@ __global__ __launch_bounds__(256) void k_frame_reduce(const Frame* __restrict__ 
       for (int q = 0; q < 10; q++) sh[threadIdx.x][q] += sh[threadIdx.x + s][q];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    energies[blockIdx.x] = sh[0][0];
-    if (virials && vir)
-#pragma unroll
-      for (int q = 0; q < 9; q++) virials[blockIdx.x * 9 + q] = sh[0][1 + q];
-  }
+  if (threadIdx.x < 10) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 10 + threadIdx.x] = sh[0][threadIdx.x];
 }
 
-void launch_frame_reduce(int nframes, const Frame* frames, const int* row_of, const double* Ei,
-                         const double* vir_rows, double* energies, double* virials,
-                         double* atom_energy, hipStream_t st) {
-  hipLaunchKernelGGL(k_frame_reduce, dim3(nframes), dim3(256), 0, st, frames, row_of, Ei, vir_rows,
-                     energies, virials, atom_energy);
+__global__ __launch_bounds__(64) void k_frame_final(int nchunk, const double* __restrict__ part,
+                                                    const double* __restrict__ vir, double* __restrict__ energies,
+                                                    double* __restrict__ virials) {
+  const int f = blockIdx.x, q = threadIdx.x;
+  if (q >= 10) return;
+  double acc = 0.0;
+  for (int c = 0; c < nchunk; c++) acc += part[((size_t)f * nchunk + c) * 10 + q];
+  if (q == 0) energies[f] = acc;
+  else if (virials && vir) virials[f * 9 + q - 1] = acc;
+}
+
+int frame_reduce_chunks(int max_frame_atoms) { return (max_frame_atoms + kRedChunk - 1) / kRedChunk; }
+
+void launch_frame_reduce(int nframes, int max_frame_atoms, const Frame* frames, const int* row_of,
+                         const double* Ei, const double* vir_rows, double* energies, double* virials,
+                         double* atom_energy, double* part, hipStream_t st) {
+  const int nchunk = frame_reduce_chunks(max_frame_atoms);
+  hipLaunchKernelGGL(k_frame_partial, dim3(nchunk, nframes), dim3(256), 0, st, frames, row_of, Ei, vir_rows,
+                     atom_energy, part);
+  hipLaunchKernelGGL(k_frame_final, dim3(nframes), dim3(64), 0, st, nchunk, part, vir_rows, energies, virials);
 }
 
 template <class T>

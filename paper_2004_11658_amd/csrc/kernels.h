@@ -26,9 +26,23 @@ struct NlistArgs {
   int *cell_count, *cell_start, *cell_fill, *cell_atoms;
   int *nlist, *nnei;
   int *tpos, *tcount, *row_of, *type_row0, *row_atom;
+  // build kernels are skipped while *gate == 0 (NULL: always build)
+  const int* gate;
+  // Verlet reuse (NULL vlist: format directly within rc): wrap integers [n][3] and
+  // reference positions [n][3] of the last build, image offsets [ne][3], candidate rows
+  // within rl = rc + skin [n][vcap] with their counts
+  int* wk;
+  double* xref;
+  int* eabc;
+  int *vlist, *vcnt;
+  int vcap;
+  double rl2;
+  bool skip_rows;   // leave the species-grouped row order as it is (MD after its first step)
+  int *big, *nbig;  // atoms with more candidates within rc than the first formatting pass holds
 };
 size_t scan_sums_ints(int n, int W);
 void launch_nlist(const NlistArgs& a, hipStream_t st);
+void launch_nlist_verlet(const NlistArgs& a, double half_skin, hipStream_t st);
 void launch_nlist_export(int n, int nm, const int* nlist, const int* eown, const int* eimg,
                          const int* frame_of, const Frame* frames, int* out_j, int* out_img,
                          hipStream_t st);
@@ -62,6 +76,12 @@ inline constexpr int bnet_u16(int parts) { return 2 * kBFloat + parts * (kBFwd +
 constexpr int kSW1 = 0, kSB1 = kP0, kSB2 = 2 * kP0, kSW2 = 2 * kP0 + kP2;
 constexpr int kSW2Stride = kP2 + 1;
 constexpr int kStuElems = kSW2 + kP0 * kSW2Stride;
+// BF16 student block, in 16-bit units: the float part (W1, b1, b2 at the offsets above,
+// 192 floats), then W2 packed per lane for the forward (8 output tiles x 1 k chunk) and
+// for the adjoint (2 x 4), each once per part.
+constexpr int kSBFloat = kSW2;
+constexpr int kSW2F = 8 * 1 * 512, kSW2B = 2 * 4 * 512;
+inline constexpr int snet_u16(int parts) { return 2 * kSBFloat + parts * (kSW2F + kSW2B); }
 
 struct EmbedArgs {
   int prec;
@@ -79,6 +99,7 @@ struct EmbedArgs {
   void* T;             // [nrows][M][4] (double for FP64, float otherwise)
   const void* gT;      // backward: dE/dT, same layout
   double* forces;      // backward: [n][3] accumulated with atomics
+  double* gbuf;        // deterministic mode (else NULL): g_ij per list slot [n][N_m][3]
   double* vir_part;    // backward: per-centre virial [nrows][9]
   const int* frame_of;
   int nframes;
@@ -99,6 +120,13 @@ void launch_fallback_fwd(const EmbedArgs& a, hipStream_t st);
 void launch_fallback_bwd(const EmbedArgs& a, hipStream_t st);
 void launch_embed_bwd(const EmbedArgs& a, hipStream_t st);
 int embed_bwd_blocks(int nrows);
+
+void launch_scan_int(int n, const int* in, int* out, int* sums, int* total, hipStream_t st);
+// deterministic force gather: F_j -= sum of g over the list slots whose neighbour is an
+// image of j, in slot order.  scratch: rev_scratch_ints(n, N_m) ints
+size_t rev_scratch_ints(int n, int nm);
+void launch_rev_gather(int n, int nm, const int* nlist, const int* eown, const double* gbuf, double* forces,
+                       int* scratch, int* scan_sums, int* scan_total, int* status, hipStream_t st);
 
 // ---------------------------------------------------------------- fitting net
 struct FitArgs {
@@ -130,9 +158,11 @@ void launch_fit(const FitArgs& a, hipStream_t st);
 
 // ---------------------------------------------------------------- reductions, MD
 void launch_zero(double* p, size_t n, hipStream_t st);
-void launch_frame_reduce(int nframes, const Frame* frames, const int* row_of, const double* Ei,
-                         const double* vir_rows, double* energies, double* virials,
-                         double* atom_energy, hipStream_t st);
+// part: frame_reduce_chunks(max atoms of a frame) * nframes * 10 doubles of scratch
+int frame_reduce_chunks(int max_frame_atoms);
+void launch_frame_reduce(int nframes, int max_frame_atoms, const Frame* frames, const int* row_of,
+                         const double* Ei, const double* vir_rows, double* energies, double* virials,
+                         double* atom_energy, double* part, hipStream_t st);
 void launch_export_T(int prec, int n, int M, const int* row_of, const void* Tm, const void* gT,
                      double* To, double* gTo, hipStream_t st);
 
@@ -170,6 +200,7 @@ void launch_scatter_params(int prec, size_t n, const int* map, const double* the
 void launch_pack_bf16(size_t n, const int* map, const double* theta, uint16_t* dst, hipStream_t st);
 void launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t st);
 void launch_zero_int(int* p, int n, hipStream_t st);
+void launch_fill_int(int* p, int n, int v, hipStream_t st);
 
 // ---------------------------------------------------------------- student net
 void launch_student_gather(int n, const ModelC& m, int alpha, int beta, const int* types, const int* nnei,

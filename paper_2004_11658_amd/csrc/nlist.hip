@@ -41,7 +41,8 @@ __device__ __forceinline__ IV<W> iv_add(const IV<W>& a, const IV<W>& b) {
 // element); sums: per-block totals.
 template <int W, class Load>
 __global__ __launch_bounds__(kScanBlock) void k_scan_up(int n, Load load, int* __restrict__ out,
-                                                       int* __restrict__ sums) {
+                                                       int* __restrict__ sums, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ IV<W> sh[kScanBlock];
   const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   IV<W> it[kScanItems];
@@ -98,7 +99,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_up(int n, Load load, int* _
 // total[W] receives the grand total.
 template <int W>
 __global__ __launch_bounds__(kScanBlock) void k_scan_sums(int nb, int* __restrict__ sums,
-                                                         int* __restrict__ total) {
+                                                         int* __restrict__ total, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ IV<W> sh[kScanBlock];
   IV<W> carry;
 #pragma unroll
@@ -136,7 +138,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_sums(int nb, int* __restric
 
 template <int W>
 __global__ __launch_bounds__(kScanBlock) void k_scan_add(int n, int* __restrict__ out,
-                                                        const int* __restrict__ sums) {
+                                                        const int* __restrict__ sums, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   int i = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
 #pragma unroll
   for (int k = 0; k < kScanItems; k++) {
@@ -165,14 +168,15 @@ struct LoadTypeOneHot {
   }
 };
 
-// scan scratch: sums[nblocks * W]
+// scan scratch: sums[nblocks * W]; gate (may be NULL): skip the scan when *gate == 0
 template <int W, class Load>
-static void scan_launch(int n, Load load, int* out, int* sums, int* total, hipStream_t st) {
+static void scan_launch(int n, Load load, int* out, int* sums, int* total, hipStream_t st,
+                        const int* gate = nullptr) {
   int nb = (n + kScanTile - 1) / kScanTile;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL((k_scan_up<W, Load>), dim3(nb), dim3(kScanBlock), 0, st, n, load, out, sums);
-  hipLaunchKernelGGL((k_scan_sums<W>), dim3(1), dim3(kScanBlock), 0, st, nb, sums, total);
-  hipLaunchKernelGGL((k_scan_add<W>), dim3(nb), dim3(kScanBlock), 0, st, n, out, sums);
+  hipLaunchKernelGGL((k_scan_up<W, Load>), dim3(nb), dim3(kScanBlock), 0, st, n, load, out, sums, gate);
+  hipLaunchKernelGGL((k_scan_sums<W>), dim3(1), dim3(kScanBlock), 0, st, nb, sums, total, gate);
+  hipLaunchKernelGGL((k_scan_add<W>), dim3(nb), dim3(kScanBlock), 0, st, n, out, sums, gate);
 }
 
 size_t scan_sums_ints(int n, int W) {
@@ -228,10 +232,12 @@ __global__ __launch_bounds__(256) void k_wrap(int n, int nframes, const Frame* _
                                               const int* __restrict__ types,
                                               int* __restrict__ frame_of,
                                               double* __restrict__ xw, double* __restrict__ fw,
-                                              int* __restrict__ gcount, int* __restrict__ status) {
+                                              int* __restrict__ gcount, int* __restrict__ status,
+                                              const int* __restrict__ gate, int* __restrict__ wk,
+                                              double* __restrict__ xref) {
 #pragma clang fp contract(off)
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || (gate && *gate == 0)) return;
   int fi = find_frame(frames, nframes, i);
   frame_of[i] = fi;
   const Frame& F = frames[fi];
@@ -246,7 +252,14 @@ __global__ __launch_bounds__(256) void k_wrap(int n, int nframes, const Frame* _
   }
   double f[3], s[3], w[3], ff[3];
   frac_of(F, xi, f);
-  shift_of(F, (int)floor(f[0]), (int)floor(f[1]), (int)floor(f[2]), s);
+  const int m0 = (int)floor(f[0]), m1 = (int)floor(f[1]), m2 = (int)floor(f[2]);
+  shift_of(F, m0, m1, m2, s);
+  if (wk) {
+    wk[3 * i] = m0;
+    wk[3 * i + 1] = m1;
+    wk[3 * i + 2] = m2;
+    for (int c = 0; c < 3; c++) xref[3 * i + c] = xi[c];
+  }
   for (int c = 0; c < 3; c++) w[c] = xi[c] - s[c];
   frac_of(F, w, ff);
   for (int c = 0; c < 3; c++) {
@@ -269,10 +282,11 @@ __global__ __launch_bounds__(256) void k_ghost_emit(
     const int* __restrict__ types, const double* __restrict__ xw, const double* __restrict__ fw,
     const int* __restrict__ goff, const int* __restrict__ gtotal, double* __restrict__ xe,
     int* __restrict__ eown, int* __restrict__ eimg, int* __restrict__ etype,
-    int* __restrict__ ecell, int* __restrict__ cell_count, int* __restrict__ status) {
+    int* __restrict__ ecell, int* __restrict__ cell_count, int* __restrict__ status,
+    const int* __restrict__ gate, int* __restrict__ eabc) {
 #pragma clang fp contract(off)
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || (gate && *gate == 0)) return;
   if (i == 0 && gtotal[0] > ghost_cap) {
     atomicOr(&status[STW_FLAGS], ST_GHOST_CAP);
     atomicMax(&status[STW_GHOSTS], gtotal[0]);
@@ -289,6 +303,7 @@ __global__ __launch_bounds__(256) void k_ghost_emit(
   int cl = cell_of(F, f);
   ecell[i] = cl;
   atomicAdd(&cell_count[cl], 1);
+  if (eabc) eabc[3 * i] = eabc[3 * i + 1] = eabc[3 * i + 2] = 0;
   int q = goff[i];
   for (int a = -F.Kg[0]; a <= F.Kg[0]; a++)
     for (int b = -F.Kg[1]; b <= F.Kg[1]; b++)
@@ -306,6 +321,11 @@ __global__ __launch_bounds__(256) void k_ghost_emit(
                                  (c + F.K[2])
                            : -1;
           etype[e] = t;
+          if (eabc) {
+            eabc[3 * e] = a;
+            eabc[3 * e + 1] = b;
+            eabc[3 * e + 2] = c;
+          }
           double fg[3] = {f[0] + a, f[1] + b, f[2] + c};
           int cg = cell_of(F, fg);
           ecell[e] = cg;
@@ -319,16 +339,18 @@ __global__ __launch_bounds__(256) void k_cell_place(int ne_cap, const int* __res
                                                     const int* __restrict__ ecell,
                                                     const int* __restrict__ cell_start,
                                                     int* __restrict__ cell_fill,
-                                                    int* __restrict__ cell_atoms) {
+                                                    int* __restrict__ cell_atoms,
+                                                    const int* __restrict__ gate) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne_cap || e >= n_ext[0]) return;
+  if (e >= ne_cap || (gate && *gate == 0) || e >= n_ext[0]) return;
   int c = ecell[e];
   int p = atomicAdd(&cell_fill[c], 1);
   cell_atoms[cell_start[c] + p] = e;
 }
 
 __global__ void k_ext_count(int n, int ghost_cap, const int* __restrict__ gtotal,
-                            int* __restrict__ n_ext) {
+                            int* __restrict__ n_ext, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   int g = gtotal[0];
   n_ext[0] = n + (g < ghost_cap ? g : ghost_cap);
 }
@@ -336,64 +358,53 @@ __global__ void k_ext_count(int n, int ghost_cap, const int* __restrict__ gtotal
 // ------------------------------------------------------------------------------------
 // 3. formatted neighbour list: one wave per local atom
 // ------------------------------------------------------------------------------------
-constexpr int kNlWaves = 4;
+__global__ void k_fill_int(int n, int* __restrict__ p, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
 
-__global__ __launch_bounds__(64 * kNlWaves) void k_nlist(
-    int n, ModelC m, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
-    const double* __restrict__ xe, const int* __restrict__ eown, const int* __restrict__ eimg,
-    const int* __restrict__ etype, const int* __restrict__ ecell,
-    const int* __restrict__ cell_start, const int* __restrict__ cell_atoms,
-    int* __restrict__ nlist, int* __restrict__ nnei, int* __restrict__ status) {
-#pragma clang fp contract(off)
-  __shared__ double s_r2[kNlWaves][kMaxCand];
-  __shared__ unsigned long long s_key[kNlWaves][kMaxCand];
-  __shared__ int s_e[kNlWaves][kMaxCand];
-  const int wv = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * kNlWaves + wv;
-  if (i >= n) return;
-  const Frame& F = frames[frame_of[i]];
-  const double xi0 = xe[3 * i], xi1 = xe[3 * i + 1], xi2 = xe[3 * i + 2];
-  int ci = ecell[i] - F.cell0;
-  int c2 = ci % F.nc[2], c1 = (ci / F.nc[2]) % F.nc[1], c0 = ci / (F.nc[2] * F.nc[1]);
-  int ncand = 0;
-  int too_close = 0;
-  for (int a = c0 - 1; a <= c0 + 1; a++) {
-    if (a < 0 || a >= F.nc[0]) continue;
-    for (int b = c1 - 1; b <= c1 + 1; b++) {
-      if (b < 0 || b >= F.nc[1]) continue;
-      for (int c = c2 - 1; c <= c2 + 1; c++) {
-        if (c < 0 || c >= F.nc[2]) continue;
-        int cell = F.cell0 + (a * F.nc[1] + b) * F.nc[2] + c;
-        int beg = cell_start[cell], end = cell_start[cell + 1];
-        for (int p0 = beg; p0 < end; p0 += 64) {
-          int p = p0 + lane;
-          bool keep = false;
-          double r2 = 0.0;
-          int e = -1;
-          if (p < end) {
-            e = cell_atoms[p];
-            double d0 = xe[3 * e] - xi0, d1 = xe[3 * e + 1] - xi1, d2 = xe[3 * e + 2] - xi2;
-            r2 = (d0 * d0 + d1 * d1) + d2 * d2;
-            keep = (r2 < m.rc2) && (e != i);
-            if (keep && r2 < 1e-12) too_close = 1;
-          }
-          unsigned long long bal = __ballot(keep);
-          int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
-          if (keep && pos < kMaxCand) {
-            int own = eown[e];
-            s_r2[wv][pos] = r2;
-            s_key[wv][pos] = ((unsigned long long)etype[e] << 56) |
-                             ((unsigned long long)(own - F.atom0) * (unsigned)F.nimg +
-                              (unsigned)eimg[e]);
-            s_e[wv][pos] = e;
-          }
-          ncand += __popcll(bal);
-        }
-      }
-    }
+constexpr int kNlWaves = 4;
+constexpr int kNlCap = 256;    // candidates within rc staged in LDS by the main kernels
+
+// one candidate in LDS: r^2 and the sort key (species << 56 | owner * nimg + image)
+struct NlEnt {
+  double r2;
+  unsigned long long key;
+};
+
+// LDS rows of one wave
+struct NlRows {
+  NlEnt* ent;
+  int* e;
+};
+
+// Append the candidates of one 64-wide batch that lie within the cutoff to the wave's
+// LDS rows (up to cap); returns the new candidate count (which may exceed cap).
+__device__ __forceinline__ int nl_append(bool keep, double r2, int e, int ncand, int lane, const Frame& F,
+                                         const int* __restrict__ eown, const int* __restrict__ eimg,
+                                         const int* __restrict__ etype, NlRows rows, int cap) {
+  unsigned long long bal = __ballot(keep);
+  int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
+  if (keep && pos < cap) {
+    int own = eown[e];
+    rows.ent[pos].r2 = r2;
+    rows.ent[pos].key = ((unsigned long long)etype[e] << 56) |
+                        ((unsigned long long)(own - F.atom0) * (unsigned)F.nimg + (unsigned)eimg[e]);
+    rows.e[pos] = e;
   }
-  if (too_close) atomicOr(&status[STW_FLAGS], ST_OVERLAP);
+  return ncand + __popcll(bal);
+}
+
+// x precedes y in (species, r^2, owner, image) order, given y's species ty
+__device__ __forceinline__ int nl_before(const NlEnt& x, const NlEnt& y, unsigned ty) {
+  return ((unsigned)(x.key >> 56) == ty) && ((x.r2 < y.r2) || (x.r2 == y.r2 && x.key < y.key));
+}
+
+// Rank the staged candidates of atom i by (species, r^2, owner, image) and write its
+// formatted row: per-species blocks of width sel, nearest first, -1 pads (Alg. 1).
+__device__ __forceinline__ void nl_format(int i, int ncand, const ModelC& m, NlRows rows, int lane,
+                                          int* __restrict__ nlist, int* __restrict__ nnei,
+                                          int* __restrict__ status) {
   if (ncand > kMaxCand) {
     if (lane == 0) {
       atomicOr(&status[STW_FLAGS], ST_CAPACITY);
@@ -405,12 +416,11 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // per-type counts
   int tcnt[kMaxTypes];
 #pragma unroll
   for (int t = 0; t < kMaxTypes; t++) tcnt[t] = 0;
   for (int q = lane; q < ncand; q += 64) {
-    int ty = (int)(s_key[wv][q] >> 56);
+    int ty = (int)(rows.ent[q].key >> 56);
 #pragma unroll
     for (int t = 0; t < kMaxTypes; t++) tcnt[t] += (ty == t);
   }
@@ -421,20 +431,19 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(
     tcnt[t] = v;
   }
   // rank sort: position of each candidate in (type, r2, owner, image) order within
-  // its species block
+  // its species block (every lane reads the same entry: LDS broadcast)
   int* nl = nlist + (size_t)i * m.nm;
   int ovf = 0;
   for (int q = lane; q < ncand; q += 64) {
-    double r2 = s_r2[wv][q];
-    unsigned long long key = s_key[wv][q];
-    unsigned t = (unsigned)(key >> 56);
-    int rank = 0;
-    for (int u = 0; u < ncand; u++) {
-      unsigned long long k2 = s_key[wv][u];
-      double r2u = s_r2[wv][u];
-      rank += ((unsigned)(k2 >> 56) == t) && ((r2u < r2) || (r2u == r2 && k2 < key));
+    const NlEnt me = rows.ent[q];
+    const unsigned t = (unsigned)(me.key >> 56);
+    int rank = 0, u = 0;
+    for (; u + 4 <= ncand; u += 4) {
+      const NlEnt x0 = rows.ent[u], x1 = rows.ent[u + 1], x2 = rows.ent[u + 2], x3 = rows.ent[u + 3];
+      rank += nl_before(x0, me, t) + nl_before(x1, me, t) + nl_before(x2, me, t) + nl_before(x3, me, t);
     }
-    if (rank < m.sel[t]) nl[m.sel_off[t] + rank] = s_e[wv][q];
+    for (; u < ncand; u++) rank += nl_before(rows.ent[u], me, t);
+    if (rank < m.sel[t]) nl[m.sel_off[t] + rank] = rows.e[q];
     else ovf = 1;
   }
   // pads
@@ -459,13 +468,205 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(
   }
 }
 
+// Candidates of atom i in the 27 cells around its own: those with r^2 < rcut2 are
+// appended to the LDS rows (LIST = false) or written to the Verlet row vrow (LIST = true).
+template <bool LIST>
+__device__ __forceinline__ int nl_gather_cells(int i, const Frame& F, double rcut2, const double* __restrict__ xe,
+                                               const int* __restrict__ eown, const int* __restrict__ eimg,
+                                               const int* __restrict__ etype, const int* __restrict__ ecell,
+                                               const int* __restrict__ cell_start,
+                                               const int* __restrict__ cell_atoms, int lane, NlRows rows, int cap,
+                                               int* vrow, int vcap, int& too_close) {
+#pragma clang fp contract(off)
+  const double xi0 = xe[3 * i], xi1 = xe[3 * i + 1], xi2 = xe[3 * i + 2];
+  int ci = ecell[i] - F.cell0;
+  int c2 = ci % F.nc[2], c1 = (ci / F.nc[2]) % F.nc[1], c0 = ci / (F.nc[2] * F.nc[1]);
+  int ncand = 0;
+  for (int a = c0 - 1; a <= c0 + 1; a++) {
+    if (a < 0 || a >= F.nc[0]) continue;
+    for (int b = c1 - 1; b <= c1 + 1; b++) {
+      if (b < 0 || b >= F.nc[1]) continue;
+      for (int c = c2 - 1; c <= c2 + 1; c++) {
+        if (c < 0 || c >= F.nc[2]) continue;
+        int cell = F.cell0 + (a * F.nc[1] + b) * F.nc[2] + c;
+        int beg = cell_start[cell], end = cell_start[cell + 1];
+        for (int p0 = beg; p0 < end; p0 += 64) {
+          int p = p0 + lane;
+          bool keep = false;
+          double r2 = 0.0;
+          int e = -1;
+          if (p < end) {
+            e = cell_atoms[p];
+            double d0 = xe[3 * e] - xi0, d1 = xe[3 * e + 1] - xi1, d2 = xe[3 * e + 2] - xi2;
+            r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+            keep = (r2 < rcut2) && (e != i);
+            if (keep && r2 < 1e-12) too_close = 1;
+          }
+          if constexpr (LIST) {
+            unsigned long long bal = __ballot(keep);
+            int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
+            if (keep && pos < vcap) vrow[pos] = e;
+            ncand += __popcll(bal);
+          } else {
+            ncand = nl_append(keep, r2, e, ncand, lane, F, eown, eimg, etype, rows, cap);
+          }
+        }
+      }
+    }
+  }
+  return ncand;
+}
+
+// Candidates of atom i from its Verlet row (pairs within rc + skin at the last build),
+// at the current coordinates.
+__device__ __forceinline__ int nl_gather_verlet(int i, const Frame& F, double rc2, const double* __restrict__ xe,
+                                                const int* __restrict__ eown, const int* __restrict__ eimg,
+                                                const int* __restrict__ etype, const int* __restrict__ vrow,
+                                                int cnt, int lane, NlRows rows, int cap) {
+#pragma clang fp contract(off)
+  const double xi0 = xe[3 * i], xi1 = xe[3 * i + 1], xi2 = xe[3 * i + 2];
+  int ncand = 0;
+  for (int p0 = 0; p0 < cnt; p0 += 64) {
+    int p = p0 + lane;
+    bool keep = false;
+    double r2 = 0.0;
+    int e = -1;
+    if (p < cnt) {
+      e = vrow[p];
+      double d0 = xe[3 * e] - xi0, d1 = xe[3 * e + 1] - xi1, d2 = xe[3 * e + 2] - xi2;
+      r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+      keep = r2 < rc2;
+    }
+    ncand = nl_append(keep, r2, e, ncand, lane, F, eown, eimg, etype, rows, cap);
+  }
+  return ncand;
+}
+
+struct NlKArgs {
+  int n;
+  ModelC m;
+  const Frame* frames;
+  const int* frame_of;
+  const double* xe;
+  const int *eown, *eimg, *etype, *ecell, *cell_start, *cell_atoms;
+  const int *vlist, *vcnt;   // Verlet rows (NULL: search the cells)
+  int vcap;
+  int *nlist, *nnei, *status;
+  int *big, *nbig;           // atoms with more than kNlCap candidates, for the second pass
+};
+
+// Formatted list, one wave per atom.  CAP = kNlCap: the main pass (atoms with more
+// candidates are deferred to the list big); CAP = kMaxCand: the second pass over that
+// list (a fixed grid striding over *nbig entries).
+template <int CAP>
+__global__ __launch_bounds__(64 * kNlWaves) void k_nlist(NlKArgs A) {
+  __shared__ NlEnt s_ent[kNlWaves][CAP];
+  __shared__ int s_e[kNlWaves][CAP];
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const NlRows rows{s_ent[wv], s_e[wv]};
+  const bool second = CAP > kNlCap;
+  const int nwork = second ? *A.nbig : A.n;
+  const int stride = second ? gridDim.x * kNlWaves : nwork;
+  for (int w = blockIdx.x * kNlWaves + wv; w < nwork; w += stride) {
+    const int i = second ? A.big[w] : w;
+    const Frame& F = A.frames[A.frame_of[i]];
+    int too_close = 0, ncand;
+    if (A.vlist)
+      ncand = nl_gather_verlet(i, F, A.m.rc2, A.xe, A.eown, A.eimg, A.etype, A.vlist + (size_t)i * A.vcap,
+                               A.vcnt[i], lane, rows, CAP);
+    else
+      ncand = nl_gather_cells<false>(i, F, A.m.rc2, A.xe, A.eown, A.eimg, A.etype, A.ecell, A.cell_start,
+                                     A.cell_atoms, lane, rows, CAP, nullptr, 0, too_close);
+    if (too_close) atomicOr(&A.status[STW_FLAGS], ST_OVERLAP);
+    if (!second && ncand > CAP) {
+      if (lane == 0) A.big[atomicAdd(A.nbig, 1)] = i;
+      continue;
+    }
+    nl_format(i, ncand, A.m, rows, lane, A.nlist, A.nnei, A.status);
+  }
+}
+
+// Verlet candidate rows: every extended atom within rl of atom i (rl = rc + skin),
+// in cell order; rebuilt only when *gate != 0.
+__global__ __launch_bounds__(64 * kNlWaves) void k_vbuild(
+    int n, double rl2, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
+    const double* __restrict__ xe, const int* __restrict__ ecell, const int* __restrict__ cell_start,
+    const int* __restrict__ cell_atoms, int* __restrict__ vlist, int* __restrict__ vcnt, int vcap,
+    int* __restrict__ status, const int* __restrict__ gate) {
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kNlWaves + wv;
+  if (i >= n || (gate && *gate == 0)) return;
+  const Frame& F = frames[frame_of[i]];
+  int too_close = 0;
+  int cnt = nl_gather_cells<true>(i, F, rl2, xe, nullptr, nullptr, nullptr, ecell, cell_start, cell_atoms, lane,
+                                  NlRows{nullptr, nullptr}, 0, vlist + (size_t)i * vcap, vcap, too_close);
+  if (too_close) atomicOr(&status[STW_FLAGS], ST_OVERLAP);
+  if (lane == 0) {
+    vcnt[i] = cnt < vcap ? cnt : vcap;
+    if (cnt > vcap) {
+      atomicOr(&status[STW_FLAGS], ST_CAPACITY);
+      atomicMax(&status[STW_MAX_CAND], cnt);
+    }
+  }
+}
+
+// both passes of the formatted list
+static void launch_format(const NlKArgs& K, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, K.nbig, 0);
+  hipLaunchKernelGGL((k_nlist<kNlCap>), dim3((K.n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, K);
+  hipLaunchKernelGGL((k_nlist<kMaxCand>), dim3(64), dim3(64 * kNlWaves), 0, st, K);
+}
+
+// Extended coordinates at the current positions with the wrap and image integers of
+// the last rebuild (the same arithmetic as k_wrap / k_ghost_emit).
+__global__ __launch_bounds__(256) void k_update_ext(int n, int ne_cap, const int* __restrict__ n_ext,
+                                                    const Frame* __restrict__ frames,
+                                                    const int* __restrict__ frame_of,
+                                                    const double* __restrict__ x, const int* __restrict__ wk,
+                                                    const int* __restrict__ eown, const int* __restrict__ eabc,
+                                                    double* __restrict__ xe) {
+#pragma clang fp contract(off)
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne_cap || e >= n_ext[0]) return;
+  int i = eown[e];
+  const Frame& F = frames[frame_of[i]];
+  double s[3], w[3];
+  shift_of(F, wk[3 * i], wk[3 * i + 1], wk[3 * i + 2], s);
+  for (int c = 0; c < 3; c++) w[c] = x[3 * i + c] - s[c];
+  if (e < n) {
+    for (int c = 0; c < 3; c++) xe[3 * e + c] = w[c];
+    return;
+  }
+  double g[3];
+  shift_of(F, eabc[3 * e], eabc[3 * e + 1], eabc[3 * e + 2], g);
+  for (int c = 0; c < 3; c++) xe[3 * e + c] = w[c] + g[c];
+}
+
+// *flag |= 1 when some atom moved more than half the skin since the last rebuild
+// (or has a non-finite coordinate)
+__global__ __launch_bounds__(256) void k_disp(int n, const double* __restrict__ x, const double* __restrict__ xref,
+                                              double lim2, int* __restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool moved = false;
+  if (i < n) {
+    double d0 = x[3 * i] - xref[3 * i], d1 = x[3 * i + 1] - xref[3 * i + 1], d2 = x[3 * i + 2] - xref[3 * i + 2];
+    double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    moved = !(r2 <= lim2);
+  }
+  if (__ballot(moved) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
 // ------------------------------------------------------------------------------------
 // 4. species-grouped row order for the embedding / fitting kernels
 // ------------------------------------------------------------------------------------
 // rows: for each species t, its atoms in index order, padded to a multiple of kRowPad.
 __global__ void k_type_rows(int n, int ntypes, int W, const int* __restrict__ types,
                             const int* __restrict__ tpos, const int* __restrict__ tcount,
-                            int* __restrict__ row_of, int* __restrict__ type_row0) {
+                            int* __restrict__ row_of, int* __restrict__ type_row0,
+                            const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   // type_row0[t] = sum_{t'<t} roundup(count[t'], kRowPad); computed by every thread
   int r0[kMaxTypes + 1];
   r0[0] = 0;
@@ -479,14 +680,16 @@ __global__ void k_type_rows(int n, int ntypes, int W, const int* __restrict__ ty
   row_of[i] = r0[t] + tpos[(size_t)i * W + t];
 }
 
-__global__ void k_fill_int(int n, int* __restrict__ p, int v) {
+
+__global__ void k_fill_int_gated(int n, int* __restrict__ p, int v, const int* __restrict__ gate) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  if (i < n && (!gate || *gate != 0)) p[i] = v;
 }
 
-__global__ void k_row_atoms(int n, const int* __restrict__ row_of, int* __restrict__ row_atom) {
+__global__ void k_row_atoms(int n, const int* __restrict__ row_of, int* __restrict__ row_atom,
+                            const int* __restrict__ gate) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) row_atom[row_of[i]] = i;
+  if (i < n && (!gate || *gate != 0)) row_atom[row_of[i]] = i;
 }
 
 // debug export of the list as (frame-local owner index, image code)
@@ -506,41 +709,100 @@ __global__ void k_nlist_export(int n, int nm, const int* __restrict__ nlist,
 // ------------------------------------------------------------------------------------
 // host launch sequence
 // ------------------------------------------------------------------------------------
+static void fill_int(int n, int* p, int v, const int* gate, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_int_gated, dim3((n + 255) / 256), dim3(256), 0, st, n, p, v, gate);
+}
+
+// Full build (every kernel skipped when A.gate points at 0): wrap, ghost images, cell
+// list, then either the formatted list (k_nlist) or, with A.vlist, the Verlet rows
+// within rc + skin (k_vbuild), and the species-grouped row order.
+static NlKArgs format_args(const NlistArgs& A) {
+  NlKArgs K{};
+  K.n = A.n;
+  K.m = A.m;
+  K.frames = A.frames;
+  K.frame_of = A.frame_of;
+  K.xe = A.xe;
+  K.eown = A.eown;
+  K.eimg = A.eimg;
+  K.etype = A.etype;
+  K.ecell = A.ecell;
+  K.cell_start = A.cell_start;
+  K.cell_atoms = A.cell_atoms;
+  K.vlist = A.vlist;
+  K.vcnt = A.vcnt;
+  K.vcap = A.vcap;
+  K.nlist = A.nlist;
+  K.nnei = A.nnei;
+  K.status = A.status;
+  K.big = A.big;
+  K.nbig = A.nbig;
+  return K;
+}
+
+// zero two int arrays (cell counts and fill pointers) in one launch
+__global__ void k_zero2_gated(int n1, int* __restrict__ p1, int n2, int* __restrict__ p2,
+                              const int* __restrict__ gate) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gate && *gate == 0) return;
+  if (i < n1) p1[i] = 0;
+  if (i < n2) p2[i] = 0;
+}
+
 void launch_nlist(const NlistArgs& A, hipStream_t st) {
   const int n = A.n;
   const int nb = (n + 255) / 256;
-  hipMemsetAsync(A.status, 0, sizeof(int) * STW_N, st);
-  hipMemsetAsync(A.cell_count, 0, sizeof(int) * (A.ncell + 1), st);
-  hipMemsetAsync(A.cell_fill, 0, sizeof(int) * A.ncell, st);
+  const int* G = A.gate;
+  hipLaunchKernelGGL(k_zero2_gated, dim3((A.ncell + 1 + 255) / 256), dim3(256), 0, st, A.ncell + 1, A.cell_count,
+                     A.ncell, A.cell_fill, G);
   hipLaunchKernelGGL(k_wrap, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes, A.x,
-                     A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status);
-  scan_launch<1>(n, LoadInt{A.gcount}, A.goff, A.scan_sums, A.gtotal, st);
+                     A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status, G, A.wk, A.xref);
+  scan_launch<1>(n, LoadInt{A.gcount}, A.goff, A.scan_sums, A.gtotal, st, G);
   hipLaunchKernelGGL(k_ghost_emit, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, A.ghost_cap, A.frames, A.frame_of,
                      A.types, A.xw, A.fw, A.goff, A.gtotal, A.xe, A.eown, A.eimg, A.etype, A.ecell,
-                     A.cell_count, A.status);
-  hipLaunchKernelGGL(k_ext_count, dim3(1), dim3(1), 0, st, n, A.ghost_cap, A.gtotal, A.n_ext);
-  scan_launch<1>(A.ncell + 1, LoadInt{A.cell_count}, A.cell_start, A.scan_sums, A.ctotal, st);
+                     A.cell_count, A.status, G, A.eabc);
+  hipLaunchKernelGGL(k_ext_count, dim3(1), dim3(1), 0, st, n, A.ghost_cap, A.gtotal, A.n_ext, G);
+  scan_launch<1>(A.ncell + 1, LoadInt{A.cell_count}, A.cell_start, A.scan_sums, A.ctotal, st, G);
   int ne_cap = n + A.ghost_cap;
   hipLaunchKernelGGL(k_cell_place, dim3((ne_cap + 255) / 256), dim3(256), 0, st, ne_cap, A.n_ext,
-                     A.ecell, A.cell_start, A.cell_fill, A.cell_atoms);
-  hipLaunchKernelGGL(k_nlist, dim3((n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, n,
-                     A.m, A.frames, A.frame_of, A.xe, A.eown, A.eimg, A.etype, A.ecell,
-                     A.cell_start, A.cell_atoms, A.nlist, A.nnei, A.status);
-  // species-grouped rows
+                     A.ecell, A.cell_start, A.cell_fill, A.cell_atoms, G);
+  if (A.vlist)
+    hipLaunchKernelGGL(k_vbuild, dim3((n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, n, A.rl2,
+                       A.frames, A.frame_of, A.xe, A.ecell, A.cell_start, A.cell_atoms, A.vlist, A.vcnt,
+                       A.vcap, A.status, G);
+  else
+    launch_format(format_args(A), st);
+  // species-grouped rows (species do not change during MD: built once there)
+  if (A.skip_rows) return;
   if (A.m.ntypes == 1) {
-    scan_launch<1>(n, LoadTypeOneHot<1>{A.types, 1}, A.tpos, A.scan_sums, A.tcount, st);
+    scan_launch<1>(n, LoadTypeOneHot<1>{A.types, 1}, A.tpos, A.scan_sums, A.tcount, st, G);
   } else if (A.m.ntypes == 2) {
-    scan_launch<2>(n, LoadTypeOneHot<2>{A.types, 2}, A.tpos, A.scan_sums, A.tcount, st);
+    scan_launch<2>(n, LoadTypeOneHot<2>{A.types, 2}, A.tpos, A.scan_sums, A.tcount, st, G);
   } else if (A.m.ntypes <= 4) {
-    scan_launch<4>(n, LoadTypeOneHot<4>{A.types, 4}, A.tpos, A.scan_sums, A.tcount, st);
+    scan_launch<4>(n, LoadTypeOneHot<4>{A.types, 4}, A.tpos, A.scan_sums, A.tcount, st, G);
   } else {
-    scan_launch<8>(n, LoadTypeOneHot<8>{A.types, 8}, A.tpos, A.scan_sums, A.tcount, st);
+    scan_launch<8>(n, LoadTypeOneHot<8>{A.types, 8}, A.tpos, A.scan_sums, A.tcount, st, G);
   }
   int W = A.m.ntypes == 1 ? 1 : A.m.ntypes == 2 ? 2 : A.m.ntypes <= 4 ? 4 : 8;
-  hipLaunchKernelGGL(k_fill_int, dim3((A.nrows + 255) / 256), dim3(256), 0, st, A.nrows, A.row_atom, -1);
+  fill_int(A.nrows, A.row_atom, -1, G, st);
   hipLaunchKernelGGL(k_type_rows, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, W, A.types, A.tpos,
-                     A.tcount, A.row_of, A.type_row0);
-  hipLaunchKernelGGL(k_row_atoms, dim3(nb), dim3(256), 0, st, n, A.row_of, A.row_atom);
+                     A.tcount, A.row_of, A.type_row0, G);
+  hipLaunchKernelGGL(k_row_atoms, dim3(nb), dim3(256), 0, st, n, A.row_of, A.row_atom, G);
+}
+
+// One MD step's list with Verlet reuse: flag a rebuild when some atom moved more
+// than half the skin (A.gate is the flag), rebuild if flagged, then refresh the
+// extended coordinates and format the list within rc from the Verlet rows.
+void launch_nlist_verlet(const NlistArgs& A, double half_skin, hipStream_t st) {
+  const int n = A.n;
+  hipLaunchKernelGGL(k_disp, dim3((n + 255) / 256), dim3(256), 0, st, n, A.x, A.xref, half_skin * half_skin,
+                     (int*)A.gate);
+  launch_nlist(A, st);
+  fill_int(1, (int*)A.gate, 0, nullptr, st);
+  int ne_cap = n + A.ghost_cap;
+  hipLaunchKernelGGL(k_update_ext, dim3((ne_cap + 255) / 256), dim3(256), 0, st, n, ne_cap, A.n_ext, A.frames,
+                     A.frame_of, A.x, A.wk, A.eown, A.eabc, A.xe);
+  launch_format(format_args(A), st);
 }
 
 // exclusive scan of n ints (out [n], total [1])
@@ -615,6 +877,9 @@ void launch_pack_bf16(size_t n, const int* map, const double* theta, uint16_t* d
 __global__ void k_axpy(size_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
   size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < n) y[q] += a * x[q];
+}
+void launch_fill_int(int* p, int n, int v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, n, p, v);
 }
 void launch_zero_int(int* p, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, n, p, 0);

@@ -29,7 +29,7 @@ class DPError(RuntimeError):
 
 
 class _Options(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("reserved0", C.c_int32), ("skin", C.c_double)]
+    _fields_ = [("precision", C.c_int32), ("deterministic", C.c_int32), ("skin", C.c_double)]
 
 
 def _load():
@@ -97,8 +97,9 @@ def _box9(box) -> np.ndarray:
 class DPModel:
     """A DP-SE model on the current HIP device."""
 
-    def __init__(self, model_path: str, precision: str = "fp64", skin: float = 0.0):
-        opt = _Options(PRECISIONS[precision], 0, float(skin))
+    def __init__(self, model_path: str, precision: str = "fp64", skin: float = 0.0,
+                 deterministic: bool = False):
+        opt = _Options(PRECISIONS[precision], 1 if deterministic else 0, float(skin))
         h = C.c_void_p()
         rc = _lib.dp_init(model_path.encode(), C.byref(opt), C.byref(h))
         if rc != DP_OK:

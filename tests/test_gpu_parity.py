@@ -57,6 +57,25 @@ def test_nlist_small_boxes_bit_exact(dp, tiny_model, case):
     assert (rc == 1) == ovf
 
 
+def test_nlist_dense_second_pass_bit_exact(dp, copper_model):
+    """Compressed copper (a = 3.0 A, ~320 neighbours within rc = 8 A): every atom has more
+    candidates than the first formatting pass stages, so the whole list comes from the
+    second pass; bit-exact against the oracle, and E / F as well."""
+    c, t, b = I.copper_fcc(6, 3.0, 17)
+    m = dp.DPModel(copper_model)
+    nl, img, nn, rc = m.nlist(c, t, b)
+    o = Oracle(copper_model)
+    onl, oimg, onn, ovf = o.nlist(c, t, b)
+    assert onn.min() > 256
+    assert np.array_equal(nl.cpu().numpy(), onl)
+    assert np.array_equal(img.cpu().numpy(), oimg)
+    assert np.array_equal(nn.cpu().numpy(), onn)
+    E, F, W = m.compute(c, t, b)
+    r = o.eval(c, t, b)
+    assert abs(float(E.cpu()[0]) - r["E"]) <= 1e-10 * abs(r["E"])
+    assert _frel(F.cpu().numpy(), r["F"]) < 1e-9
+
+
 def test_nlist_water192_bit_exact(dp, water_model, water192):
     c, t, b = water192
     m = dp.DPModel(water_model)
@@ -162,3 +181,82 @@ def test_ragged_batch_fp64(dp, water_model):
         assert abs(E[k] - r["E"]) <= 1e-10 * abs(r["E"])
         assert _frel(F[off[k]:off[k + 1]], r["F"]) < 1e-9
         assert _rel(W[k], r["W"]) < 1e-9
+
+
+@pytest.mark.parametrize("skin", [0.05, 2.0])
+def test_md_verlet_skin_matches_oracle(dp, water_model, water192, skin):
+    """Velocity Verlet with neighbour reuse (a8: rebuild when some atom moved more than
+    skin / 2; skin 0.05 A rebuilds many times in 20 steps, 2 A never): the same
+    trajectory as the oracle, which builds a fresh list at every step."""
+    import torch
+    c, t, b = water192
+    print("skin", skin, flush=True)
+    masses = [I.MASS["O"], I.MASS["H"]]
+    v = I.maxwell_velocities(t, masses, 300.0, 302)
+    m = dp.DPModel(water_model, skin=skin)
+    x_d = torch.as_tensor(c, device="cuda").clone()
+    v_d = torch.as_tensor(v, device="cuda").clone()
+    th = m.md_run(x_d, v_d, t, masses, b, 0.5, 20, 5).cpu().numpy()
+    xo, vo, tho = Oracle(water_model).md(c, v, t, masses, b, 0.5, 20, 5)
+    assert np.abs(x_d.cpu().numpy() - xo).max() < 1e-10
+    assert _rel(v_d.cpu().numpy(), vo) < 1e-8
+    assert _rel(th[:, 1:], tho[:, 1:]) < 1e-10
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_md_verlet_forces_equal_fresh_list(dp, water_model, mode):
+    """After 60 steps of the 12,288-atom water MD with a 0.3 A skin (several rebuilds),
+    the forces of the last step (reused list) equal a fresh evaluation at the same
+    coordinates."""
+    import torch
+    c, t, b = I.config_water12k(202)
+    masses = [I.MASS["O"], I.MASS["H"]]
+    v = I.maxwell_velocities(t, masses, 300.0, 302)
+    m = dp.DPModel(water_model, mode, skin=0.3)
+    x_d = torch.as_tensor(c, device="cuda").clone()
+    v_d = torch.as_tensor(v, device="cuda").clone()
+    F_md = torch.empty_like(x_d)
+    m.md_run(x_d, v_d, t, masses, b, 0.5, 60, 0, forces=F_md)
+    E, F, W = dp.DPModel(water_model, mode).compute(x_d, t, b)
+    F_md, F = F_md.cpu().numpy(), F.cpu().numpy()
+    tol = 1e-12 if mode == "fp64" else 1e-6
+    assert np.abs(F_md - F).max() <= tol * np.abs(F).max()
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_deterministic_forces(dp, water_model, mode):
+    """Deterministic mode (pair forces stored per list slot and gathered per atom in slot
+    order) gives bit-identical forces on repeated calls, and the atomic mode's forces
+    up to summation order; FP64 also against the oracle on the 12,288-atom frame."""
+    c, t, b = I.config_water12k(202)
+    md = dp.DPModel(water_model, mode, deterministic=True)
+    E1, F1, W1 = md.compute(c, t, b)
+    E2, F2, W2 = md.compute(c, t, b)
+    F1, F2 = F1.cpu().numpy(), F2.cpu().numpy()
+    assert np.array_equal(F1, F2)
+    assert np.array_equal(W1.cpu().numpy(), W2.cpu().numpy())
+    Ea, Fa, Wa = dp.DPModel(water_model, mode).compute(c, t, b)
+    Fa = Fa.cpu().numpy()
+    assert np.abs(F1 - Fa).max() <= 1e-12 * np.abs(Fa).max()
+    assert float(E1.cpu()[0]) == float(Ea.cpu()[0])
+    if mode == "fp64":
+        r = Oracle(water_model).eval(c, t, b)
+        assert _frel(F1, r["F"]) < 1e-9
+
+
+def test_deterministic_small_box_self_images(dp, tiny_model):
+    """Self-images (box < 2 rc): the gather sees several slots of one owner per centre."""
+    c, t, b = _cases()["self_images"]
+    md = dp.DPModel(tiny_model, deterministic=True)
+    E, F, W = md.compute(c, t, b)
+    r = Oracle(tiny_model).eval(c, t, b)
+    assert _frel(F.cpu().numpy(), r["F"]) < 1e-9
+    assert abs(float(E.cpu()[0]) - r["E"]) <= 1e-10 * abs(r["E"])
+
+
+def test_deterministic_rejects_student(dp, water_model):
+    import torch
+    md = dp.DPModel(water_model, deterministic=True)
+    th = torch.zeros(4 * dp.student_size(32, 100), dtype=torch.float64, device="cuda")
+    with pytest.raises(Exception):
+        md.set_student(32, th, np.zeros(4), np.ones(4))

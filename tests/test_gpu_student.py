@@ -118,7 +118,7 @@ def test_full_net_eval_and_sample_gather(dp, water_model, water192):
         assert _rel(G, Gr) < 1e-13
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16"])
 def test_student_inference_matches_oracle(dp, water_model, water192, prec):
     """Untrained random students with a narrow range, so that part of the neighbours
     falls back to the full net: E and F against the oracle's substituted model."""
@@ -138,16 +138,21 @@ def test_student_inference_matches_oracle(dp, water_model, water192, prec):
     st = {(a, bb): (ths[2 * a + bb], H, lo[2 * a + bb], hi[2 * a + bb]) for a in range(2) for bb in range(2)}
     Er, Fr, _ = TR.energy_forces(arch, torch.as_tensor(arch.params), c, t, b, nl, img, student=st)
     Er, Fr = float(Er.detach()), Fr.numpy()
-    tolE, tolF = (1e-10, 1e-9) if prec == "fp64" else (1e-5, 1e-3)
+    # FP32: operands to 2^-24; split BF16: hi + lo holds an operand to about 2^-16, held to
+    # 4 x 2^-16 in energy; BF16: u = 2^-8 per operand, held to 4u in energy and 16u in the
+    # largest force error
+    tolE, tolF = {"fp64": (1e-10, 1e-9), "fp32": (1e-5, 1e-3), "bf16x3": (6.1e-5, 1e-3),
+                  "bf16": (1.6e-2, 6.25e-2)}[prec]
     dE = abs(float(E.cpu()[0]) - Er) / abs(Er)
     dF = np.linalg.norm(F.cpu().numpy() - Fr, axis=1).max() / np.linalg.norm(Fr, axis=1).max()
     print(prec, "student inference dE", dE, "dF", dF, flush=True)
     assert dE < tolE and dF < tolF
 
 
-def test_student_gain_over_full_net(dp, water_model):
-    """Trained on frames of the full model's own FP64 MD, the FP32 student meets the force
-    bar against the FP64 full model and makes the MD step faster than the FP32 full net."""
+@pytest.fixture(scope="module")
+def trained_students(dp, water_model):
+    """Students trained on frames of the full model's own FP64 MD of the 12,288-atom water
+    system, and a later frame of that trajectory (positions, velocities)."""
     import torch
     from paper_2004_11658_amd import student as S
     c, t, b = I.config_water12k(202)
@@ -162,14 +167,24 @@ def test_student_gain_over_full_net(dp, water_model):
         full64.md_run(x, vd, t, masses, b, 0.5, 10, 0)
     th, lo, hi, rep = S.train_students(full64, frames, hidden=32, n_samples=400000)
     print("student training", rep, flush=True)
-    # force error at a later frame of the trajectory, identical coordinates
     full64.md_run(x, vd, t, masses, b, 0.5, 10, 0)
-    _, F64, _ = full64.compute(x, t, b)
-    stu = dp.DPModel(water_model, "fp32")
-    stu.set_student(32, th, lo, hi)
+    return dict(th=th, lo=lo, hi=hi, x=x, v=vd, t=t, b=b, masses=masses, full64=full64)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_student_gain_over_full_net(dp, water_model, trained_students, prec):
+    """Trained on frames of the full model's own FP64 MD, the student meets the force bar
+    against the FP64 full model (identical coordinates, a later frame of the trajectory)
+    and makes the MD step faster than the full net of the same operand precision."""
+    import torch
+    d = trained_students
+    x, vd, t, b, masses = d["x"], d["v"], d["t"], d["b"], d["masses"]
+    _, F64, _ = d["full64"].compute(x, t, b)
+    stu = dp.DPModel(water_model, prec)
+    stu.set_student(32, d["th"], d["lo"], d["hi"])
     _, Fs, _ = stu.compute(x, t, b)
     rmse = float(torch.sqrt(((Fs - F64) ** 2).mean()) / torch.sqrt((F64 ** 2).mean()))
-    full32 = dp.DPModel(water_model, "fp32")
+    full = dp.DPModel(water_model, prec)
 
     def step_time(model):
         xx, vv = x.clone(), vd.clone()
@@ -180,8 +195,8 @@ def test_student_gain_over_full_net(dp, water_model):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / 30
 
-    t_full, t_stu = step_time(full32), step_time(stu)
-    print("student force RMSE rel %.3e, step %.3f ms (full fp32 %.3f ms), gain %.2fx"
-          % (rmse, 1e3 * t_stu, 1e3 * t_full, t_full / t_stu), flush=True)
+    t_full, t_stu = step_time(full), step_time(stu)
+    print("%s student force RMSE rel %.3e, step %.3f ms (full %.3f ms), gain %.2fx"
+          % (prec, rmse, 1e3 * t_stu, 1e3 * t_full, t_full / t_stu), flush=True)
     assert rmse <= 1e-3
     assert t_stu < t_full
