@@ -63,8 +63,19 @@ def algorithmic_flops(spec, rows, natoms, student=False):
     emb_bwd_row = chain + 2 * contract_row + chain_bwd
     K1, fw, nf = spec.M * spec.m2, spec.fit_width[0], len(spec.fit_width)
     fit_atom = 2 * (2 * K1 * fw + 2 * fw * fw * (nf - 1) + 2 * fw) + 2 * spec.M * spec.m2 * 4 * 3
+    # the part of the adjoint's work that is not a layer product (vector ALU): layer-0
+    # affine map, tanh (counted as 5 operations: scale, exp, add, reciprocal, fma), bias
+    # and skip adds, the recompute's 1 - tanh^2 factors, dE/dR = G . dE/dT (8 M), dE/ds
+    # and the FP64 force / virial assembly (~30)
+    if student:
+        H = STUDENT_HIDDEN
+        alu_bwd_row = 2 * H + 5 * H + M + 8 * M + 4 * H + 30
+    else:
+        ntanh = s0 + s1 + M
+        alu_bwd_row = 2 * s0 + 5 * ntanh + 2 * (s1 + M) + 8 * M + 3 * ntanh + (s1 + M) + 3 * s0 + 30
     return dict(embed_fwd=rows * emb_fwd_row, embed_bwd=rows * emb_bwd_row, fit=natoms * fit_atom,
-                emb_bwd_row=emb_bwd_row, emb_fwd_row=emb_fwd_row, fit_atom=fit_atom)
+                emb_bwd_row=emb_bwd_row, emb_fwd_row=emb_fwd_row, fit_atom=fit_atom,
+                alu_bwd_row=alu_bwd_row, alu_bwd=rows * alu_bwd_row)
 
 
 def source_hash(files):
@@ -231,7 +242,12 @@ def main():
                     frac=round(achieved / peak, 4), traffic=traffic_for(kname),
                     flops_per_launch=fl["embed_bwd"], rows_per_launch=rows,
                     flops_per_row=fl["emb_bwd_row"], avg_launch_ms=bwd_ms,
-                    stage_tflops=stage_rates)
+                    stage_tflops=stage_rates,
+                    # the same kernel against the vector-ALU ceiling (its non-product work)
+                    alu=dict(flops_per_row=fl["alu_bwd_row"],
+                             achieved=round(fl["alu_bwd"] / (bwd_ms * 1e-3) / 1e12, 3),
+                             peak=PEAK_TFLOPS["fp32"], unit="TFLOP/s",
+                             frac=round(fl["alu_bwd"] / (bwd_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4)))
 
     cpu = None
     if not args.no_cpu_baseline:
