@@ -17,6 +17,7 @@
 
 #include "bf16ops.h"
 #include "common.h"
+#include "embed_common.h"
 #include "kernels.h"
 #include "devmath.h"
 
@@ -357,15 +358,17 @@ __global__ __launch_bounds__(256) void k_gemm_bf(GemmArgs G) {
 // ------------------------------------------------------------------------------------
 // BF16 first fitting layer with the descriptor fused in (forward).
 //
-// A workgroup takes 32 rows (one species) and stages their T rows in LDS (pad rows as
-// zeros); x1 = tanh(D W1 + b1) over all N columns, with D = T T<^T (Eq. 4) formed stage
-// by stage (64 k at a time, double-buffered) straight into BF16 MFMA operands in LDS,
-// so D never reaches HBM; wave w owns the column tiles w, w + 4, ...; W1^T is read
-// from L2/HBM per lane (16 bytes per MFMA tile), one k chunk ahead.
+// x1 = tanh(D W1 + b1) with D = T T<^T (Eq. 4) formed in the operand staging, so D never
+// reaches HBM.  A workgroup takes 64 rows (one species) and all N columns; wave w owns
+// the column tiles w, w + 4, ... for the 4 row tiles.  K is consumed 32 at a time: each
+// thread forms 8 entries of D from T< (staged once in LDS) and its row's T[a] (read one
+// stage ahead), and the W1^T slice of the stage is loaded cooperatively one stage ahead
+// into registers, then both go to LDS as BF16 (hi, lo) MFMA operands.
 // ------------------------------------------------------------------------------------
-constexpr int F1R = 32;     // rows per workgroup
-constexpr int F1KC = 64;    // k per A stage (two MFMA k chunks)
-constexpr int F1LDA = F1KC + 8;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int F1R = 64;     // rows per workgroup
+constexpr int F1KC = 32;    // k per stage (one MFMA k chunk)
+constexpr int F1LD = F1KC + 8;
 
 struct Fit1Args {
   int M, N, nfit;              // embedding width, hidden width (multiple of 16, <= 256), layers
@@ -375,101 +378,113 @@ struct Fit1Args {
   const float* T;              // [nrows][M][4]
   const void* const* Wb;       // operand table: [(species * nfit + k) * 4 + dir * 2 + part]
   const void* const* bias;     // [species * nfit + k]
-  float *out, *out2;           // x1 and t1 [nrows][N]
+  float *out, *out2;           // forward: x1 and t1 [nrows][N]
+  const float *g, *act;        // adjoint: g1 and t1 [nrows][N]
+  float* gT;                   // adjoint: dE/dT [nrows][M][4]
 };
-
-__device__ __forceinline__ int fit1_species(const Fit1Args& P, int r0) {
-  for (int t = 0; t < P.ntypes; t++)
-    if (r0 >= P.type_row0[t] && r0 < P.type_row0[t + 1]) return t;
-  return -1;
-}
-
-__device__ __forceinline__ void fit1_stage_T(const Fit1Args& P, int r0, float* Ts) {
-  for (int q = threadIdx.x; q < F1R * P.M; q += blockDim.x) {
-    int r = q / P.M, a = q - r * P.M;
-    float4 v = {0.f, 0.f, 0.f, 0.f};
-    if (P.row_atom[r0 + r] >= 0) v = *(const float4*)(P.T + ((size_t)(r0 + r) * P.M + a) * 4);
-    *(float4*)(Ts + (r * P.M + a) * 4) = v;
-  }
-}
 
 template <int PARTS>
 __global__ __launch_bounds__(256) void k_fit1_fwd_bf(Fit1Args P) {
   extern __shared__ __align__(16) char sm[];
-  float* Ts = (float*)sm;                                   // [F1R][M][4]
-  __bf16* As = (__bf16*)(sm + (size_t)F1R * P.M * 16);       // [2][PARTS][F1R][F1LDA]
+  const int M = P.M, K = 16 * M, N = P.N, ntile = N / 16;
+  float* Tl = (float*)sm;                                          // [F1R][16][4]: T<
+  __bf16* As = (__bf16*)(sm + F1R * 16 * 16);                      // [PARTS][F1R][F1LD]
+  __bf16* Bs = As + (size_t)PARTS * F1R * F1LD;                    // [PARTS][N][F1LD]
   const int r0 = blockIdx.x * F1R;
-  const int sp = fit1_species(P, r0);
+  int sp = -1;
+  for (int t = 0; t < P.ntypes; t++)
+    if (r0 >= P.type_row0[t] && r0 < P.type_row0[t + 1]) sp = t;
   if (sp < 0) return;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, rb = lane & 15, g = lane >> 4;
-  const int M = P.M, K = 16 * M, N = P.N, ntile = N / 16;
-  fit1_stage_T(P, r0, Ts);
-  __syncthreads();
-  // A stage s: thread t forms D[row t / 8][s * 64 + 8 (t % 8) + i], i < 8 (one a, 8 b)
-  auto make_A = [&](int s, int buf) {
-    const int r = tid >> 3, kq = (tid & 7) * 8;
-    const int k = s * F1KC + kq, a = k >> 4, b0 = k & 15;
-    const float* tr = Ts + r * M * 4;
-    const float4 ta = *(const float4*)(tr + 4 * a);
-    float d[8];
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-      const float4 tb = *(const float4*)(tr + 4 * (b0 + i));
-      d[i] = ta.x * tb.x + ta.y * tb.y + ta.z * tb.z + ta.w * tb.w;
-    }
-    bf8 hi, lo;
-    split8<PARTS>(d, hi, lo);
-    *(bf8*)(As + ((size_t)(buf * PARTS + 0) * F1R + r) * F1LDA + kq) = hi;
-    if (PARTS == 2) *(bf8*)(As + ((size_t)(buf * PARTS + 1) * F1R + r) * F1LDA + kq) = lo;
-  };
+  // T< of the 64 rows (pad rows: zeros)
+  for (int q = tid; q < F1R * 16; q += 256) {
+    const int r = q >> 4, b = q & 15;
+    float4 v = {0.f, 0.f, 0.f, 0.f};
+    if (P.row_atom[r0 + r] >= 0) v = *(const float4*)(P.T + ((size_t)(r0 + r) * M + b) * 4);
+    *(float4*)(Tl + q * 4) = v;
+  }
   const int wi = (sp * P.nfit + 0) * 4 + 0;   // W1^T [N][K]
   const __bf16* __restrict__ Wh = (const __bf16*)P.Wb[wi];
   const __bf16* __restrict__ Wl = (const __bf16*)P.Wb[wi + 1];
-  f4v acc[2][4];
+  // this thread's D entries: row tid / 4, k = 32 s + 8 (tid % 4) + i, i < 8 (one a, 8 b)
+  const int drow = tid >> 2, dkq = (tid & 3) * 8;
+  const bool dreal = P.row_atom[r0 + drow] >= 0;
+  const float* trow = P.T + (size_t)(r0 + drow) * M * 4;
+  // this thread's W1^T pieces: e = tid + 256 j < 4 N: column e / 4, k offset 8 (e % 4)
+  const int nB = 4 * N;
+  f4v tv;
+  u32x4 bq0[4], bq1[4];
+#define FIT1_FETCH_B(S_, J)                                                                     \
+  do {                                                                                          \
+    const int e = tid + 256 * (J);                                                              \
+    if (e < nB) {                                                                               \
+      const size_t o = (size_t)(e >> 2) * K + 32 * (S_) + 8 * (e & 3);                          \
+      bq0[J] = *(const u32x4*)(Wh + o);                                                         \
+      if (PARTS == 2) bq1[J] = *(const u32x4*)(Wl + o);                                         \
+    }                                                                                           \
+  } while (0)
+#define FIT1_FETCH(S_)                                                                          \
+  do {                                                                                          \
+    const int a_ = (32 * (S_) + dkq) >> 4;                                                      \
+    tv = dreal ? *(const f4v*)(trow + 4 * a_) : f4v{0.f, 0.f, 0.f, 0.f};                       \
+    FIT1_FETCH_B(S_, 0);                                                                        \
+    FIT1_FETCH_B(S_, 1);                                                                        \
+    FIT1_FETCH_B(S_, 2);                                                                        \
+    FIT1_FETCH_B(S_, 3);                                                                        \
+  } while (0)
+  f4v acc[4][4];
 #pragma unroll
-  for (int rt = 0; rt < 2; rt++)
+  for (int rt = 0; rt < 4; rt++)
 #pragma unroll
     for (int u = 0; u < 4; u++) acc[rt][u] = f4v{0, 0, 0, 0};
-  // B operand of k chunk c (global k = 32 c): lane (g, rb) holds W1^T[col][32 c + 8 g .. + 7]
-  bf8 bh[4], bl[4], nh[4], nl[4];
-  auto load_B = [&](int c, bf8 (&h)[4], bf8 (&l)[4]) {
+  const int S = K / F1KC;
+  FIT1_FETCH(0);
+  __syncthreads();   // T< staged
+  for (int s = 0; s < S; s++) {
+    // operands of stage s from the registers into LDS
+    {
+      const int b0 = (32 * s + dkq) & 15;
+      const float* tl = Tl + (drow * 16 + b0) * 4;
+      float d[8];
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const float4 tb = *(const float4*)(tl + 4 * i);
+        d[i] = tv[0] * tb.x + tv[1] * tb.y + tv[2] * tb.z + tv[3] * tb.w;
+      }
+      bf8 hi, lo;
+      split8<PARTS>(d, hi, lo);
+      if (s > 0) __syncthreads();   // the previous stage's operands have been read
+      *(bf8*)(As + (size_t)drow * F1LD + dkq) = hi;
+      if (PARTS == 2) *(bf8*)(As + ((size_t)F1R + drow) * F1LD + dkq) = lo;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int e = tid + 256 * j;
+        if (e < nB) {
+          *(u32x4*)(Bs + (size_t)(e >> 2) * F1LD + 8 * (e & 3)) = bq0[j];
+          if (PARTS == 2) *(u32x4*)(Bs + ((size_t)N + (e >> 2)) * F1LD + 8 * (e & 3)) = bq1[j];
+        }
+      }
+    }
+    __syncthreads();
+    if (s + 1 < S) FIT1_FETCH(s + 1);
+    bf8 ah[4], al[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) {
+      ah[rt] = *(const bf8*)(As + (size_t)(16 * rt + rb) * F1LD + 8 * g);
+      al[rt] = PARTS == 2 ? *(const bf8*)(As + ((size_t)F1R + 16 * rt + rb) * F1LD + 8 * g) : ah[rt];
+    }
 #pragma unroll
     for (int u = 0; u < 4; u++) {
       const int ct = wv + 4 * u;
-      if (ct < ntile) {
-        const size_t o = (size_t)(16 * ct + rb) * K + 32 * c + 8 * g;
-        h[u] = *(const bf8*)(Wh + o);
-        l[u] = PARTS == 2 ? *(const bf8*)(Wl + o) : h[u];
-      }
+      if (ct >= ntile) continue;
+      const bf8 bh = *(const bf8*)(Bs + (size_t)(16 * ct + rb) * F1LD + 8 * g);
+      const bf8 bl = PARTS == 2 ? *(const bf8*)(Bs + ((size_t)N + 16 * ct + rb) * F1LD + 8 * g) : bh;
+#pragma unroll
+      for (int rt = 0; rt < 4; rt++) acc[rt][u] = mfma_split<PARTS>(ah[rt], al[rt], bh, bl, acc[rt][u]);
     }
-  };
-  const int S = K / F1KC, C = K / 32;
-  make_A(0, 0);
-  load_B(0, bh, bl);
-  __syncthreads();
-  for (int c = 0; c < C; c++) {
-    const int s = c >> 1, kc = c & 1, buf = s & 1;
-    if (kc == 0 && s + 1 < S) make_A(s + 1, (s + 1) & 1);
-    if (c + 1 < C) load_B(c + 1, nh, nl);
-    bf8 ah[2], al[2];
-#pragma unroll
-    for (int rt = 0; rt < 2; rt++) {
-      ah[rt] = *(const bf8*)(As + ((size_t)(buf * PARTS + 0) * F1R + 16 * rt + rb) * F1LDA + 32 * kc + 8 * g);
-      al[rt] = PARTS == 2 ? *(const bf8*)(As + ((size_t)(buf * PARTS + 1) * F1R + 16 * rt + rb) * F1LDA + 32 * kc + 8 * g)
-                          : ah[rt];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; u++)
-      if (wv + 4 * u < ntile)
-#pragma unroll
-        for (int rt = 0; rt < 2; rt++) acc[rt][u] = mfma_split<PARTS>(ah[rt], al[rt], bh[u], bl[u], acc[rt][u]);
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      bh[u] = nh[u];
-      bl[u] = nl[u];
-    }
-    if (kc == 1) __syncthreads();
   }
+#undef FIT1_FETCH
+#undef FIT1_FETCH_B
   const float* bias = (const float*)P.bias[sp * P.nfit + 0];
 #pragma unroll
   for (int u = 0; u < 4; u++) {
@@ -478,7 +493,7 @@ __global__ __launch_bounds__(256) void k_fit1_fwd_bf(Fit1Args P) {
     const int col = 16 * ct + rb;
     const float bc = bias[col];
 #pragma unroll
-    for (int rt = 0; rt < 2; rt++)
+    for (int rt = 0; rt < 4; rt++)
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         const size_t o = (size_t)(r0 + 16 * rt + 4 * g + q) * N + col;
@@ -489,7 +504,195 @@ __global__ __launch_bounds__(256) void k_fit1_fwd_bf(Fit1Args P) {
   }
 }
 
-size_t fit1_fwd_lds(int M, int parts) { return (size_t)F1R * M * 16 + (size_t)2 * parts * F1R * F1LDA * 2; }
+// Adjoint of the first layer with the descriptor's adjoint fused in: dD = (g1 (1 - t1^2))
+// W1^T is produced 16 columns (one a, b = 0..15) at a time and folded at once into
+// dE/dT (Eq. 4 differentiated): dE/dT[a] += sum_b dD[a][b] T[b] and, for b < M<,
+// dE/dT[b] += dD[a][b] T[a]; dD never reaches HBM.  A workgroup takes 64 rows and wave
+// w the row tile w, whose A operand (g1 (1 - t1^2), all N columns) stays in registers;
+// the 16 rows of W1 of each a are staged once for the four waves (double-buffered,
+// loaded two columns ahead).
+template <int PARTS>
+__global__ __launch_bounds__(256) void k_fit1_bwd_bf(Fit1Args P) {
+  extern __shared__ __align__(16) char sm[];
+  const int M = P.M, N = P.N, NP = (N + 31) & ~31, C = NP / 32;
+  float* Tl = (float*)sm;                                          // [F1R][16][4]: T<
+  __bf16* Bs = (__bf16*)(sm + F1R * 16 * 16);                      // [2][PARTS][16][NP + 8]
+  const int LDB = NP + 8;
+  const int r0 = blockIdx.x * F1R;
+  int sp = -1;
+  for (int t = 0; t < P.ntypes; t++)
+    if (r0 >= P.type_row0[t] && r0 < P.type_row0[t + 1]) sp = t;
+  if (sp < 0) return;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, rb = lane & 15, g = lane >> 4;
+  for (int q = tid; q < F1R * 16; q += 256) {
+    const int r = q >> 4, b = q & 15;
+    f4v v = {0.f, 0.f, 0.f, 0.f};
+    if (P.row_atom[r0 + r] >= 0) v = *(const f4v*)(P.T + ((size_t)(r0 + r) * M + b) * 4);
+    *(f4v*)(Tl + q * 4) = v;
+  }
+  // A operand of this wave's rows: lane (g, rb) holds row 16 wv + rb, k = 32 c + 8 g + i
+  bf8 ah[8], al[8];
+  {
+    const size_t ro = (size_t)(r0 + 16 * wv + rb) * N;
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+      float d[8];
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const int k = 32 * c + 8 * g + i;
+        float v = 0.f;
+        if (c < C && k < N) {
+          const float t = P.act[ro + k];
+          v = P.g[ro + k] * (1.f - t * t);
+        }
+        d[i] = v;
+      }
+      split8<PARTS>(d, ah[c], al[c]);
+    }
+  }
+  const int wi = (sp * P.nfit + 0) * 4 + 2;   // W1 [K1][N]: column a 16 + b of dD is row a 16 + b
+  const __bf16* __restrict__ Wh = (const __bf16*)P.Wb[wi];
+  const __bf16* __restrict__ Wl = (const __bf16*)P.Wb[wi + 1];
+  // staging of W1 rows 16 a .. 16 a + 15: e = tid + 256 j < 16 NP / 8 pieces of 8
+  const int nPiece = 2 * NP;   // 16 rows x NP / 8
+  u32x4 bq0[2], bq1[2];
+#define FIT1B_FETCH(A_, J)                                                                      \
+  do {                                                                                          \
+    const int e = tid + 256 * (J);                                                              \
+    if (e < nPiece) {                                                                           \
+      const int br = e / (NP / 8), kk = 8 * (e % (NP / 8));                                     \
+      u32x4 h = {0u, 0u, 0u, 0u}, l = {0u, 0u, 0u, 0u};                                         \
+      if ((A_) < M && kk < N) {                                                                 \
+        const size_t o = (size_t)(16 * (A_) + br) * N + kk;                                     \
+        h = *(const u32x4*)(Wh + o);                                                            \
+        if (PARTS == 2) l = *(const u32x4*)(Wl + o);                                            \
+      }                                                                                         \
+      bq0[J] = h;                                                                               \
+      bq1[J] = l;                                                                               \
+    }                                                                                           \
+  } while (0)
+#define FIT1B_STORE(BUF, J)                                                                     \
+  do {                                                                                          \
+    const int e = tid + 256 * (J);                                                              \
+    if (e < nPiece) {                                                                           \
+      const int br = e / (NP / 8), kk = 8 * (e % (NP / 8));                                     \
+      *(u32x4*)(Bs + ((size_t)((BUF) * PARTS + 0) * 16 + br) * LDB + kk) = bq0[J];              \
+      if (PARTS == 2) *(u32x4*)(Bs + ((size_t)((BUF) * PARTS + 1) * 16 + br) * LDB + kk) = bq1[J]; \
+    }                                                                                           \
+  } while (0)
+  // T[row][a] of this lane's 4 rows (16 wv + 4 g + q), one column ahead
+  const float* trow[4];
+  bool treal[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int r = r0 + 16 * wv + 4 * g + q;
+    trow[q] = P.T + (size_t)r * M * 4;
+    treal[q] = P.row_atom[r] >= 0;
+  }
+  f4v ta[4], tn[4];
+#define FIT1B_FETCH_T(A_, DST)                                                                  \
+  do {                                                                                          \
+    _Pragma("unroll") for (int q = 0; q < 4; q++) DST[q] =                                      \
+        ((A_) < M && treal[q]) ? *(const f4v*)(trow[q] + 4 * (A_)) : f4v{0.f, 0.f, 0.f, 0.f};  \
+  } while (0)
+  float lt[4][4];   // dE/dT[row 4 g + q][b = rb][c] from the second term
+#pragma unroll
+  for (int q = 0; q < 4; q++)
+#pragma unroll
+    for (int c = 0; c < 4; c++) lt[q][c] = 0.f;
+  FIT1B_FETCH(0, 0);
+  FIT1B_FETCH(0, 1);
+  FIT1B_STORE(0, 0);
+  FIT1B_STORE(0, 1);
+  FIT1B_FETCH(1, 0);
+  FIT1B_FETCH(1, 1);
+  FIT1B_FETCH_T(0, ta);
+  __syncthreads();
+  for (int a = 0; a < M; a++) {
+    const int buf = a & 1;
+    if (a + 1 < M) {
+      FIT1B_STORE(buf ^ 1, 0);   // W1 rows of a + 1 (fetched last step) into the other buffer
+      FIT1B_STORE(buf ^ 1, 1);
+    }
+    FIT1B_FETCH(a + 2, 0);
+    FIT1B_FETCH(a + 2, 1);
+    FIT1B_FETCH_T(a + 1, tn);
+    f4v acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+      if (c >= C) break;
+      const bf8 bh = *(const bf8*)(Bs + ((size_t)(buf * PARTS + 0) * 16 + rb) * LDB + 32 * c + 8 * g);
+      const bf8 bl = PARTS == 2 ? *(const bf8*)(Bs + ((size_t)(buf * PARTS + 1) * 16 + rb) * LDB + 32 * c + 8 * g)
+                                : bh;
+      acc = mfma_split<PARTS>(ah[c], al[c], bh, bl, acc);
+    }
+    // acc[q] = dD[row 16 wv + 4 g + q][a][b = rb]
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const f4v tb = *(const f4v*)(Tl + ((16 * wv + 4 * g + q) * 16 + rb) * 4);
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        v[4 * q + c] = acc[q] * tb[c];
+        lt[q][c] += acc[q] * ta[q][c];
+      }
+    }
+    // sum over b (the 16 lanes of the row group): lane rb ends with entry rb = (q, c)
+    {
+      const bool b3 = rb & 8, b2 = rb & 4, b1 = rb & 2, b0 = rb & 1;
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const float send = b3 ? v[i] : v[i + 8];
+        const float keep = b3 ? v[i + 8] : v[i];
+        v[i] = keep + dpp_mov<DPP_ROR8>(send);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const float send = b2 ? v[i] : v[i + 4];
+        const float keep = b2 ? v[i + 4] : v[i];
+        v[i] = keep + dpp_mov<DPP_HALF_MIRROR>(send);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; i++) {
+        const float send = b1 ? v[i] : v[i + 2];
+        const float keep = b1 ? v[i + 2] : v[i];
+        v[i] = keep + dpp_mov<DPP_XOR2>(send);
+      }
+      {
+        const float send = b0 ? v[0] : v[1];
+        const float keep = b0 ? v[1] : v[0];
+        v[0] = keep + dpp_mov<DPP_XOR1>(send);
+      }
+    }
+    {
+      const int q = rb >> 2, c = rb & 3;
+      P.gT[((size_t)(r0 + 16 * wv + 4 * g + q) * M + a) * 4 + c] = v[0];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) ta[q] = tn[q];
+    __syncthreads();
+  }
+#undef FIT1B_FETCH
+#undef FIT1B_STORE
+#undef FIT1B_FETCH_T
+  // second term (b < 16): this wave wrote dE/dT[row][b] above; add its partials
+  __threadfence_block();
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    float* o = P.gT + ((size_t)(r0 + 16 * wv + 4 * g + q) * M + rb) * 4;
+#pragma unroll
+    for (int c = 0; c < 4; c++) o[c] += lt[q][c];
+  }
+}
+
+size_t fit1_bwd_lds(int N, int parts) {
+  const int NP = (N + 31) & ~31;
+  return (size_t)F1R * 16 * 16 + (size_t)2 * parts * 16 * (NP + 8) * 2;
+}
+
+size_t fit1_fwd_lds(int N, int parts) {
+  return (size_t)F1R * 16 * 16 + (size_t)parts * (F1R + N) * F1LD * 2;
+}
 
 // D[row][a m2 + b] = sum_c T[row][a][c] T[row][b][c]; pad rows get zeros
 template <class T>
@@ -618,7 +821,7 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
     if (k == 0 && fuse_desc) {
       P1.out = (float*)(xs + k * L);
       P1.out2 = (float*)(act + k * L);
-      const size_t sh = fit1_fwd_lds(M, parts);
+      const size_t sh = fit1_fwd_lds(fw, parts);
       if (parts == 2) {
         (void)hipFuncSetAttribute((const void*)k_fit1_fwd_bf<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         hipLaunchKernelGGL(k_fit1_fwd_bf<2>, dim3(rows / F1R), dim3(256), sh, st, P1);
@@ -649,6 +852,20 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
     T* tmp = gcur;
     gcur = gnext;
     gnext = tmp;
+  }
+  if (fuse_desc) {
+    P1.g = (const float*)gcur;
+    P1.act = (const float*)act;
+    P1.gT = (float*)F.gT;
+    const size_t sh = fit1_bwd_lds(fw, parts);
+    if (parts == 2) {
+      (void)hipFuncSetAttribute((const void*)k_fit1_bwd_bf<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+      hipLaunchKernelGGL(k_fit1_bwd_bf<2>, dim3(rows / F1R), dim3(256), sh, st, P1);
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_fit1_bwd_bf<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+      hipLaunchKernelGGL(k_fit1_bwd_bf<1>, dim3(rows / F1R), dim3(256), sh, st, P1);
+    }
+    return;
   }
   G.K = fw;
   G.N = K1;
