@@ -359,15 +359,16 @@ __global__ __launch_bounds__(256) void k_gemm_bf(GemmArgs G) {
 // BF16 first fitting layer with the descriptor fused in (forward).
 //
 // x1 = tanh(D W1 + b1) with D = T T<^T (Eq. 4) formed in the operand staging, so D never
-// reaches HBM.  A workgroup takes 64 rows (one species) and all N columns; wave w owns
-// the column tiles w, w + 4, ... for the 4 row tiles.  K is consumed 32 at a time: each
-// thread forms 8 entries of D from T< (staged once in LDS) and its row's T[a] (read one
-// stage ahead), and the W1^T slice of the stage is loaded cooperatively one stage ahead
-// into registers, then both go to LDS as BF16 (hi, lo) MFMA operands.
+// reaches HBM.  A workgroup of 8 waves takes 32 rows (one species); wave w owns row
+// tile w & 1 and the column tiles (w >> 1) + 4 u.  K is consumed 32 at a time: the
+// workgroup forms that slice of D from T< (staged once in LDS) and each row's T[a], and
+// loads the W1^T slice cooperatively one stage ahead into registers; both go to LDS as
+// BF16 (hi, lo) MFMA operands.
 // ------------------------------------------------------------------------------------
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-constexpr int F1R = 64;     // rows per workgroup
-constexpr int F1KC = 32;    // k per stage (one MFMA k chunk)
+constexpr int F1R = 32;     // rows per workgroup
+constexpr int F1T = 512;    // threads per workgroup
+constexpr int F1KC = 32;    // k per forward stage (one MFMA k chunk)
 constexpr int F1LD = F1KC + 8;
 
 struct Fit1Args {
@@ -378,45 +379,52 @@ struct Fit1Args {
   const float* T;              // [nrows][M][4]
   const void* const* Wb;       // operand table: [(species * nfit + k) * 4 + dir * 2 + part]
   const void* const* bias;     // [species * nfit + k]
-  float *out, *out2;           // forward: x1 and t1 [nrows][N]
-  const float *g, *act;        // adjoint: g1 and t1 [nrows][N]
-  float* gT;                   // adjoint: dE/dT [nrows][M][4]
+  float *out, *out2;           // x1 and t1 [nrows][N]
 };
 
+__device__ __forceinline__ int fit1_species(const Fit1Args& P, int r0) {
+  for (int t = 0; t < P.ntypes; t++)
+    if (r0 >= P.type_row0[t] && r0 < P.type_row0[t + 1]) return t;
+  return -1;
+}
+
+// T< of the workgroup's rows into LDS (pad rows: zeros)
+__device__ __forceinline__ void fit1_stage_tl(const Fit1Args& P, int r0, float* Tl) {
+  for (int q = threadIdx.x; q < F1R * 16; q += F1T) {
+    const int r = q >> 4, b = q & 15;
+    f4v v = {0.f, 0.f, 0.f, 0.f};
+    if (P.row_atom[r0 + r] >= 0) v = *(const f4v*)(P.T + ((size_t)(r0 + r) * P.M + b) * 4);
+    *(f4v*)(Tl + q * 4) = v;
+  }
+}
+
 template <int PARTS>
-__global__ __launch_bounds__(256) void k_fit1_fwd_bf(Fit1Args P) {
+__global__ __launch_bounds__(F1T) void k_fit1_fwd_bf(Fit1Args P) {
   extern __shared__ __align__(16) char sm[];
   const int M = P.M, K = 16 * M, N = P.N, ntile = N / 16;
   float* Tl = (float*)sm;                                          // [F1R][16][4]: T<
   __bf16* As = (__bf16*)(sm + F1R * 16 * 16);                      // [PARTS][F1R][F1LD]
   __bf16* Bs = As + (size_t)PARTS * F1R * F1LD;                    // [PARTS][N][F1LD]
   const int r0 = blockIdx.x * F1R;
-  int sp = -1;
-  for (int t = 0; t < P.ntypes; t++)
-    if (r0 >= P.type_row0[t] && r0 < P.type_row0[t + 1]) sp = t;
+  const int sp = fit1_species(P, r0);
   if (sp < 0) return;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, rb = lane & 15, g = lane >> 4;
-  // T< of the 64 rows (pad rows: zeros)
-  for (int q = tid; q < F1R * 16; q += 256) {
-    const int r = q >> 4, b = q & 15;
-    float4 v = {0.f, 0.f, 0.f, 0.f};
-    if (P.row_atom[r0 + r] >= 0) v = *(const float4*)(P.T + ((size_t)(r0 + r) * M + b) * 4);
-    *(float4*)(Tl + q * 4) = v;
-  }
+  const int rt = wv & 1, cg = wv >> 1;
+  fit1_stage_tl(P, r0, Tl);
   const int wi = (sp * P.nfit + 0) * 4 + 0;   // W1^T [N][K]
   const __bf16* __restrict__ Wh = (const __bf16*)P.Wb[wi];
   const __bf16* __restrict__ Wl = (const __bf16*)P.Wb[wi + 1];
-  // this thread's D entries: row tid / 4, k = 32 s + 8 (tid % 4) + i, i < 8 (one a, 8 b)
-  const int drow = tid >> 2, dkq = (tid & 3) * 8;
+  // this thread's D entries: row tid / 16, k = 32 s + 2 (tid % 16) + i, i < 2 (one a)
+  const int drow = tid >> 4, dkq = (tid & 15) * 2;
   const bool dreal = P.row_atom[r0 + drow] >= 0;
   const float* trow = P.T + (size_t)(r0 + drow) * M * 4;
-  // this thread's W1^T pieces: e = tid + 256 j < 4 N: column e / 4, k offset 8 (e % 4)
+  // this thread's W1^T pieces: e = tid + 512 j < 4 N: column e / 4, k offset 8 (e % 4)
   const int nB = 4 * N;
   f4v tv;
-  u32x4 bq0[4], bq1[4];
+  u32x4 bq0[2], bq1[2];
 #define FIT1_FETCH_B(S_, J)                                                                     \
   do {                                                                                          \
-    const int e = tid + 256 * (J);                                                              \
+    const int e = tid + F1T * (J);                                                              \
     if (e < nB) {                                                                               \
       const size_t o = (size_t)(e >> 2) * K + 32 * (S_) + 8 * (e & 3);                          \
       bq0[J] = *(const u32x4*)(Wh + o);                                                         \
@@ -429,36 +437,31 @@ __global__ __launch_bounds__(256) void k_fit1_fwd_bf(Fit1Args P) {
     tv = dreal ? *(const f4v*)(trow + 4 * a_) : f4v{0.f, 0.f, 0.f, 0.f};                       \
     FIT1_FETCH_B(S_, 0);                                                                        \
     FIT1_FETCH_B(S_, 1);                                                                        \
-    FIT1_FETCH_B(S_, 2);                                                                        \
-    FIT1_FETCH_B(S_, 3);                                                                        \
   } while (0)
-  f4v acc[4][4];
+  f4v acc[4];
 #pragma unroll
-  for (int rt = 0; rt < 4; rt++)
-#pragma unroll
-    for (int u = 0; u < 4; u++) acc[rt][u] = f4v{0, 0, 0, 0};
+  for (int u = 0; u < 4; u++) acc[u] = f4v{0, 0, 0, 0};
   const int S = K / F1KC;
   FIT1_FETCH(0);
   __syncthreads();   // T< staged
   for (int s = 0; s < S; s++) {
-    // operands of stage s from the registers into LDS
     {
       const int b0 = (32 * s + dkq) & 15;
       const float* tl = Tl + (drow * 16 + b0) * 4;
-      float d[8];
-#pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const float4 tb = *(const float4*)(tl + 4 * i);
-        d[i] = tv[0] * tb.x + tv[1] * tb.y + tv[2] * tb.z + tv[3] * tb.w;
-      }
-      bf8 hi, lo;
-      split8<PARTS>(d, hi, lo);
+      const f4v t0 = *(const f4v*)tl, t1 = *(const f4v*)(tl + 4);
+      const float d0 = tv[0] * t0[0] + tv[1] * t0[1] + tv[2] * t0[2] + tv[3] * t0[3];
+      const float d1 = tv[0] * t1[0] + tv[1] * t1[1] + tv[2] * t1[2] + tv[3] * t1[3];
+      const __bf16 h0 = (__bf16)d0, h1 = (__bf16)d1;
       if (s > 0) __syncthreads();   // the previous stage's operands have been read
-      *(bf8*)(As + (size_t)drow * F1LD + dkq) = hi;
-      if (PARTS == 2) *(bf8*)(As + ((size_t)F1R + drow) * F1LD + dkq) = lo;
+      As[(size_t)drow * F1LD + dkq] = h0;
+      As[(size_t)drow * F1LD + dkq + 1] = h1;
+      if (PARTS == 2) {
+        As[((size_t)F1R + drow) * F1LD + dkq] = (__bf16)(d0 - (float)h0);
+        As[((size_t)F1R + drow) * F1LD + dkq + 1] = (__bf16)(d1 - (float)h1);
+      }
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int e = tid + 256 * j;
+      for (int j = 0; j < 2; j++) {
+        const int e = tid + F1T * j;
         if (e < nB) {
           *(u32x4*)(Bs + (size_t)(e >> 2) * F1LD + 8 * (e & 3)) = bq0[j];
           if (PARTS == 2) *(u32x4*)(Bs + ((size_t)N + (e >> 2)) * F1LD + 8 * (e & 3)) = bq1[j];
@@ -467,20 +470,15 @@ __global__ __launch_bounds__(256) void k_fit1_fwd_bf(Fit1Args P) {
     }
     __syncthreads();
     if (s + 1 < S) FIT1_FETCH(s + 1);
-    bf8 ah[4], al[4];
-#pragma unroll
-    for (int rt = 0; rt < 4; rt++) {
-      ah[rt] = *(const bf8*)(As + (size_t)(16 * rt + rb) * F1LD + 8 * g);
-      al[rt] = PARTS == 2 ? *(const bf8*)(As + ((size_t)F1R + 16 * rt + rb) * F1LD + 8 * g) : ah[rt];
-    }
+    const bf8 ah = *(const bf8*)(As + (size_t)(16 * rt + rb) * F1LD + 8 * g);
+    const bf8 al = PARTS == 2 ? *(const bf8*)(As + ((size_t)F1R + 16 * rt + rb) * F1LD + 8 * g) : ah;
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      const int ct = wv + 4 * u;
+      const int ct = cg + 4 * u;
       if (ct >= ntile) continue;
       const bf8 bh = *(const bf8*)(Bs + (size_t)(16 * ct + rb) * F1LD + 8 * g);
       const bf8 bl = PARTS == 2 ? *(const bf8*)(Bs + ((size_t)N + 16 * ct + rb) * F1LD + 8 * g) : bh;
-#pragma unroll
-      for (int rt = 0; rt < 4; rt++) acc[rt][u] = mfma_split<PARTS>(ah[rt], al[rt], bh, bl, acc[rt][u]);
+      acc[u] = mfma_split<PARTS>(ah, al, bh, bl, acc[u]);
     }
   }
 #undef FIT1_FETCH
@@ -488,206 +486,18 @@ __global__ __launch_bounds__(256) void k_fit1_fwd_bf(Fit1Args P) {
   const float* bias = (const float*)P.bias[sp * P.nfit + 0];
 #pragma unroll
   for (int u = 0; u < 4; u++) {
-    const int ct = wv + 4 * u;
+    const int ct = cg + 4 * u;
     if (ct >= ntile) continue;
     const int col = 16 * ct + rb;
     const float bc = bias[col];
 #pragma unroll
-    for (int rt = 0; rt < 4; rt++)
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const size_t o = (size_t)(r0 + 16 * rt + 4 * g + q) * N + col;
-        const float t = dp_tanh(acc[rt][u][q] + bc);
-        P.out[o] = t;
-        P.out2[o] = t;
-      }
-  }
-}
-
-// Adjoint of the first layer with the descriptor's adjoint fused in: dD = (g1 (1 - t1^2))
-// W1^T is produced 16 columns (one a, b = 0..15) at a time and folded at once into
-// dE/dT (Eq. 4 differentiated): dE/dT[a] += sum_b dD[a][b] T[b] and, for b < M<,
-// dE/dT[b] += dD[a][b] T[a]; dD never reaches HBM.  A workgroup takes 64 rows and wave
-// w the row tile w, whose A operand (g1 (1 - t1^2), all N columns) stays in registers;
-// the 16 rows of W1 of each a are staged once for the four waves (double-buffered,
-// loaded two columns ahead).
-template <int PARTS>
-__global__ __launch_bounds__(256) void k_fit1_bwd_bf(Fit1Args P) {
-  extern __shared__ __align__(16) char sm[];
-  const int M = P.M, N = P.N, NP = (N + 31) & ~31, C = NP / 32;
-  float* Tl = (float*)sm;                                          // [F1R][16][4]: T<
-  __bf16* Bs = (__bf16*)(sm + F1R * 16 * 16);                      // [2][PARTS][16][NP + 8]
-  const int LDB = NP + 8;
-  const int r0 = blockIdx.x * F1R;
-  int sp = -1;
-  for (int t = 0; t < P.ntypes; t++)
-    if (r0 >= P.type_row0[t] && r0 < P.type_row0[t + 1]) sp = t;
-  if (sp < 0) return;
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, rb = lane & 15, g = lane >> 4;
-  for (int q = tid; q < F1R * 16; q += 256) {
-    const int r = q >> 4, b = q & 15;
-    f4v v = {0.f, 0.f, 0.f, 0.f};
-    if (P.row_atom[r0 + r] >= 0) v = *(const f4v*)(P.T + ((size_t)(r0 + r) * M + b) * 4);
-    *(f4v*)(Tl + q * 4) = v;
-  }
-  // A operand of this wave's rows: lane (g, rb) holds row 16 wv + rb, k = 32 c + 8 g + i
-  bf8 ah[8], al[8];
-  {
-    const size_t ro = (size_t)(r0 + 16 * wv + rb) * N;
-#pragma unroll
-    for (int c = 0; c < 8; c++) {
-      float d[8];
-#pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const int k = 32 * c + 8 * g + i;
-        float v = 0.f;
-        if (c < C && k < N) {
-          const float t = P.act[ro + k];
-          v = P.g[ro + k] * (1.f - t * t);
-        }
-        d[i] = v;
-      }
-      split8<PARTS>(d, ah[c], al[c]);
-    }
-  }
-  const int wi = (sp * P.nfit + 0) * 4 + 2;   // W1 [K1][N]: column a 16 + b of dD is row a 16 + b
-  const __bf16* __restrict__ Wh = (const __bf16*)P.Wb[wi];
-  const __bf16* __restrict__ Wl = (const __bf16*)P.Wb[wi + 1];
-  // staging of W1 rows 16 a .. 16 a + 15: e = tid + 256 j < 16 NP / 8 pieces of 8
-  const int nPiece = 2 * NP;   // 16 rows x NP / 8
-  u32x4 bq0[2], bq1[2];
-#define FIT1B_FETCH(A_, J)                                                                      \
-  do {                                                                                          \
-    const int e = tid + 256 * (J);                                                              \
-    if (e < nPiece) {                                                                           \
-      const int br = e / (NP / 8), kk = 8 * (e % (NP / 8));                                     \
-      u32x4 h = {0u, 0u, 0u, 0u}, l = {0u, 0u, 0u, 0u};                                         \
-      if ((A_) < M && kk < N) {                                                                 \
-        const size_t o = (size_t)(16 * (A_) + br) * N + kk;                                     \
-        h = *(const u32x4*)(Wh + o);                                                            \
-        if (PARTS == 2) l = *(const u32x4*)(Wl + o);                                            \
-      }                                                                                         \
-      bq0[J] = h;                                                                               \
-      bq1[J] = l;                                                                               \
-    }                                                                                           \
-  } while (0)
-#define FIT1B_STORE(BUF, J)                                                                     \
-  do {                                                                                          \
-    const int e = tid + 256 * (J);                                                              \
-    if (e < nPiece) {                                                                           \
-      const int br = e / (NP / 8), kk = 8 * (e % (NP / 8));                                     \
-      *(u32x4*)(Bs + ((size_t)((BUF) * PARTS + 0) * 16 + br) * LDB + kk) = bq0[J];              \
-      if (PARTS == 2) *(u32x4*)(Bs + ((size_t)((BUF) * PARTS + 1) * 16 + br) * LDB + kk) = bq1[J]; \
-    }                                                                                           \
-  } while (0)
-  // T[row][a] of this lane's 4 rows (16 wv + 4 g + q), one column ahead
-  const float* trow[4];
-  bool treal[4];
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    const int r = r0 + 16 * wv + 4 * g + q;
-    trow[q] = P.T + (size_t)r * M * 4;
-    treal[q] = P.row_atom[r] >= 0;
-  }
-  f4v ta[4], tn[4];
-#define FIT1B_FETCH_T(A_, DST)                                                                  \
-  do {                                                                                          \
-    _Pragma("unroll") for (int q = 0; q < 4; q++) DST[q] =                                      \
-        ((A_) < M && treal[q]) ? *(const f4v*)(trow[q] + 4 * (A_)) : f4v{0.f, 0.f, 0.f, 0.f};  \
-  } while (0)
-  float lt[4][4];   // dE/dT[row 4 g + q][b = rb][c] from the second term
-#pragma unroll
-  for (int q = 0; q < 4; q++)
-#pragma unroll
-    for (int c = 0; c < 4; c++) lt[q][c] = 0.f;
-  FIT1B_FETCH(0, 0);
-  FIT1B_FETCH(0, 1);
-  FIT1B_STORE(0, 0);
-  FIT1B_STORE(0, 1);
-  FIT1B_FETCH(1, 0);
-  FIT1B_FETCH(1, 1);
-  FIT1B_FETCH_T(0, ta);
-  __syncthreads();
-  for (int a = 0; a < M; a++) {
-    const int buf = a & 1;
-    if (a + 1 < M) {
-      FIT1B_STORE(buf ^ 1, 0);   // W1 rows of a + 1 (fetched last step) into the other buffer
-      FIT1B_STORE(buf ^ 1, 1);
-    }
-    FIT1B_FETCH(a + 2, 0);
-    FIT1B_FETCH(a + 2, 1);
-    FIT1B_FETCH_T(a + 1, tn);
-    f4v acc = {0, 0, 0, 0};
-#pragma unroll
-    for (int c = 0; c < 8; c++) {
-      if (c >= C) break;
-      const bf8 bh = *(const bf8*)(Bs + ((size_t)(buf * PARTS + 0) * 16 + rb) * LDB + 32 * c + 8 * g);
-      const bf8 bl = PARTS == 2 ? *(const bf8*)(Bs + ((size_t)(buf * PARTS + 1) * 16 + rb) * LDB + 32 * c + 8 * g)
-                                : bh;
-      acc = mfma_split<PARTS>(ah[c], al[c], bh, bl, acc);
-    }
-    // acc[q] = dD[row 16 wv + 4 g + q][a][b = rb]
-    float v[16];
-#pragma unroll
     for (int q = 0; q < 4; q++) {
-      const f4v tb = *(const f4v*)(Tl + ((16 * wv + 4 * g + q) * 16 + rb) * 4);
-#pragma unroll
-      for (int c = 0; c < 4; c++) {
-        v[4 * q + c] = acc[q] * tb[c];
-        lt[q][c] += acc[q] * ta[q][c];
-      }
+      const size_t o = (size_t)(r0 + 16 * rt + 4 * g + q) * N + col;
+      const float t = dp_tanh(acc[u][q] + bc);
+      P.out[o] = t;
+      P.out2[o] = t;
     }
-    // sum over b (the 16 lanes of the row group): lane rb ends with entry rb = (q, c)
-    {
-      const bool b3 = rb & 8, b2 = rb & 4, b1 = rb & 2, b0 = rb & 1;
-#pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const float send = b3 ? v[i] : v[i + 8];
-        const float keep = b3 ? v[i + 8] : v[i];
-        v[i] = keep + dpp_mov<DPP_ROR8>(send);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const float send = b2 ? v[i] : v[i + 4];
-        const float keep = b2 ? v[i + 4] : v[i];
-        v[i] = keep + dpp_mov<DPP_HALF_MIRROR>(send);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; i++) {
-        const float send = b1 ? v[i] : v[i + 2];
-        const float keep = b1 ? v[i + 2] : v[i];
-        v[i] = keep + dpp_mov<DPP_XOR2>(send);
-      }
-      {
-        const float send = b0 ? v[0] : v[1];
-        const float keep = b0 ? v[1] : v[0];
-        v[0] = keep + dpp_mov<DPP_XOR1>(send);
-      }
-    }
-    {
-      const int q = rb >> 2, c = rb & 3;
-      P.gT[((size_t)(r0 + 16 * wv + 4 * g + q) * M + a) * 4 + c] = v[0];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; q++) ta[q] = tn[q];
-    __syncthreads();
   }
-#undef FIT1B_FETCH
-#undef FIT1B_STORE
-#undef FIT1B_FETCH_T
-  // second term (b < 16): this wave wrote dE/dT[row][b] above; add its partials
-  __threadfence_block();
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    float* o = P.gT + ((size_t)(r0 + 16 * wv + 4 * g + q) * M + rb) * 4;
-#pragma unroll
-    for (int c = 0; c < 4; c++) o[c] += lt[q][c];
-  }
-}
-
-size_t fit1_bwd_lds(int N, int parts) {
-  const int NP = (N + 31) & ~31;
-  return (size_t)F1R * 16 * 16 + (size_t)2 * parts * 16 * (NP + 8) * 2;
 }
 
 size_t fit1_fwd_lds(int N, int parts) {
@@ -779,7 +589,7 @@ template <class T>
 static void fit_t(const FitArgs& F, hipStream_t st) {
   const int prec = F.prec;
   const int rows = F.nrows, M = F.m.M, m2 = F.m.m2, K1 = M * m2, fw = F.fw;
-  // BF16 modes run the first layer (forward and adjoint) with the descriptor fused in
+  // BF16 modes run the first layer's forward with the descriptor fused in
   const bool bf = prec == PREC_BF16 || prec == PREC_BF16X3;
   const int parts = prec == PREC_BF16X3 ? 2 : 1;
   const bool fuse_desc = bf && m2 == 16 && M % 4 == 0 && M >= 16 && fw % 16 == 0 && fw <= 256 &&
@@ -824,10 +634,10 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
       const size_t sh = fit1_fwd_lds(fw, parts);
       if (parts == 2) {
         (void)hipFuncSetAttribute((const void*)k_fit1_fwd_bf<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_fit1_fwd_bf<2>, dim3(rows / F1R), dim3(256), sh, st, P1);
+        hipLaunchKernelGGL(k_fit1_fwd_bf<2>, dim3(rows / F1R), dim3(F1T), sh, st, P1);
       } else {
         (void)hipFuncSetAttribute((const void*)k_fit1_fwd_bf<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_fit1_fwd_bf<1>, dim3(rows / F1R), dim3(256), sh, st, P1);
+        hipLaunchKernelGGL(k_fit1_fwd_bf<1>, dim3(rows / F1R), dim3(F1T), sh, st, P1);
       }
     } else if (k == 0) {
       gemm<T, EPI_FWD1>(prec, G, st);
@@ -852,20 +662,6 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
     T* tmp = gcur;
     gcur = gnext;
     gnext = tmp;
-  }
-  if (fuse_desc) {
-    P1.g = (const float*)gcur;
-    P1.act = (const float*)act;
-    P1.gT = (float*)F.gT;
-    const size_t sh = fit1_bwd_lds(fw, parts);
-    if (parts == 2) {
-      (void)hipFuncSetAttribute((const void*)k_fit1_bwd_bf<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-      hipLaunchKernelGGL(k_fit1_bwd_bf<2>, dim3(rows / F1R), dim3(256), sh, st, P1);
-    } else {
-      (void)hipFuncSetAttribute((const void*)k_fit1_bwd_bf<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-      hipLaunchKernelGGL(k_fit1_bwd_bf<1>, dim3(rows / F1R), dim3(256), sh, st, P1);
-    }
-    return;
   }
   G.K = fw;
   G.N = K1;

@@ -366,10 +366,12 @@ __global__ void k_fill_int(int n, int* __restrict__ p, int v) {
 constexpr int kNlWaves = 4;
 constexpr int kNlCap = 256;    // candidates within rc staged in LDS by the main kernels
 
-// one candidate in LDS: r^2 and the sort key (species << 56 | owner * nimg + image)
+// one candidate in LDS: the 128-bit sort key (species, r^2, owner * nimg + image) as two
+// words compared lexicographically: hi = species << 56 | (bits of r^2) >> 8,
+// lo = (low 8 bits of r^2) << 56 | owner * nimg + image.  r^2 > 0, so its IEEE bits
+// order like its value, and the key is exact (no quantisation of r^2).
 struct NlEnt {
-  double r2;
-  unsigned long long key;
+  unsigned long long hi, lo;
 };
 
 // LDS rows of one wave
@@ -386,18 +388,18 @@ __device__ __forceinline__ int nl_append(bool keep, double r2, int e, int ncand,
   unsigned long long bal = __ballot(keep);
   int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
   if (keep && pos < cap) {
-    int own = eown[e];
-    rows.ent[pos].r2 = r2;
-    rows.ent[pos].key = ((unsigned long long)etype[e] << 56) |
-                        ((unsigned long long)(own - F.atom0) * (unsigned)F.nimg + (unsigned)eimg[e]);
+    const int own = eown[e];
+    const unsigned long long rb = (unsigned long long)__double_as_longlong(r2);
+    rows.ent[pos].hi = ((unsigned long long)etype[e] << 56) | (rb >> 8);
+    rows.ent[pos].lo = (rb << 56) | ((unsigned long long)(own - F.atom0) * (unsigned)F.nimg + (unsigned)eimg[e]);
     rows.e[pos] = e;
   }
   return ncand + __popcll(bal);
 }
 
-// x precedes y in (species, r^2, owner, image) order, given y's species ty
-__device__ __forceinline__ int nl_before(const NlEnt& x, const NlEnt& y, unsigned ty) {
-  return ((unsigned)(x.key >> 56) == ty) && ((x.r2 < y.r2) || (x.r2 == y.r2 && x.key < y.key));
+// x precedes y in (species, r^2, owner, image) order
+__device__ __forceinline__ int nl_before(const NlEnt& x, const NlEnt& y) {
+  return (x.hi < y.hi) | ((x.hi == y.hi) & (x.lo < y.lo));
 }
 
 // Rank the staged candidates of atom i by (species, r^2, owner, image) and write its
@@ -420,7 +422,7 @@ __device__ __forceinline__ void nl_format(int i, int ncand, const ModelC& m, NlR
 #pragma unroll
   for (int t = 0; t < kMaxTypes; t++) tcnt[t] = 0;
   for (int q = lane; q < ncand; q += 64) {
-    int ty = (int)(rows.ent[q].key >> 56);
+    int ty = (int)(rows.ent[q].hi >> 56);
 #pragma unroll
     for (int t = 0; t < kMaxTypes; t++) tcnt[t] += (ty == t);
   }
@@ -430,21 +432,40 @@ __device__ __forceinline__ void nl_format(int i, int ncand, const ModelC& m, NlR
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     tcnt[t] = v;
   }
-  // rank sort: position of each candidate in (type, r2, owner, image) order within
-  // its species block (every lane reads the same entry: LDS broadcast)
+  // rank sort: position of each candidate in (species, r2, owner, image) order; the rank
+  // within its species block is that minus the candidates of the smaller species.  A lane
+  // ranks two candidates per pass over the rows (every lane reads the same entry: LDS
+  // broadcast).
   int* nl = nlist + (size_t)i * m.nm;
   int ovf = 0;
-  for (int q = lane; q < ncand; q += 64) {
-    const NlEnt me = rows.ent[q];
-    const unsigned t = (unsigned)(me.key >> 56);
-    int rank = 0, u = 0;
+  for (int q0 = lane; q0 < ncand; q0 += 128) {
+    const int q1 = q0 + 64;
+    const bool has1 = q1 < ncand;
+    const NlEnt y0 = rows.ent[q0];
+    const NlEnt y1 = has1 ? rows.ent[q1] : y0;
+    int r0 = 0, r1 = 0, u = 0;
     for (; u + 4 <= ncand; u += 4) {
       const NlEnt x0 = rows.ent[u], x1 = rows.ent[u + 1], x2 = rows.ent[u + 2], x3 = rows.ent[u + 3];
-      rank += nl_before(x0, me, t) + nl_before(x1, me, t) + nl_before(x2, me, t) + nl_before(x3, me, t);
+      r0 += nl_before(x0, y0) + nl_before(x1, y0) + nl_before(x2, y0) + nl_before(x3, y0);
+      r1 += nl_before(x0, y1) + nl_before(x1, y1) + nl_before(x2, y1) + nl_before(x3, y1);
     }
-    for (; u < ncand; u++) rank += nl_before(rows.ent[u], me, t);
-    if (rank < m.sel[t]) nl[m.sel_off[t] + rank] = rows.e[q];
-    else ovf = 1;
+    for (; u < ncand; u++) {
+      const NlEnt x = rows.ent[u];
+      r0 += nl_before(x, y0);
+      r1 += nl_before(x, y1);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      if (h == 1 && !has1) break;
+      const NlEnt& y = h ? y1 : y0;
+      const unsigned t = (unsigned)(y.hi >> 56);
+      int below = 0;   // candidates of smaller species
+#pragma unroll
+      for (int tt = 0; tt < kMaxTypes; tt++) below += (tt < (int)t) ? tcnt[tt] : 0;
+      const int rank = (h ? r1 : r0) - below;
+      if (rank < m.sel[t]) nl[m.sel_off[t] + rank] = rows.e[h ? q1 : q0];
+      else ovf = 1;
+    }
   }
   // pads
   for (int k = lane; k < m.nm; k += 64) {
@@ -518,7 +539,8 @@ __device__ __forceinline__ int nl_gather_cells(int i, const Frame& F, double rcu
 }
 
 // Candidates of atom i from its Verlet row (pairs within rc + skin at the last build),
-// at the current coordinates.
+// at the current coordinates; the row is read four batches of 64 at a time so that the
+// dependent loads (row entry, then coordinates) of the batches overlap.
 __device__ __forceinline__ int nl_gather_verlet(int i, const Frame& F, double rc2, const double* __restrict__ xe,
                                                 const int* __restrict__ eown, const int* __restrict__ eimg,
                                                 const int* __restrict__ etype, const int* __restrict__ vrow,
@@ -526,18 +548,33 @@ __device__ __forceinline__ int nl_gather_verlet(int i, const Frame& F, double rc
 #pragma clang fp contract(off)
   const double xi0 = xe[3 * i], xi1 = xe[3 * i + 1], xi2 = xe[3 * i + 2];
   int ncand = 0;
-  for (int p0 = 0; p0 < cnt; p0 += 64) {
-    int p = p0 + lane;
-    bool keep = false;
-    double r2 = 0.0;
-    int e = -1;
-    if (p < cnt) {
-      e = vrow[p];
-      double d0 = xe[3 * e] - xi0, d1 = xe[3 * e + 1] - xi1, d2 = xe[3 * e + 2] - xi2;
-      r2 = (d0 * d0 + d1 * d1) + d2 * d2;
-      keep = r2 < rc2;
+  for (int p0 = 0; p0 < cnt; p0 += 256) {
+    int e[4];
+    double d[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int p = p0 + 64 * j + lane;
+      e[j] = p < cnt ? vrow[p] : -1;
     }
-    ncand = nl_append(keep, r2, e, ncand, lane, F, eown, eimg, etype, rows, cap);
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+      if (e[j] >= 0) {
+        d[j][0] = xe[3 * e[j]];
+        d[j][1] = xe[3 * e[j] + 1];
+        d[j][2] = xe[3 * e[j] + 2];
+      }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      if (p0 + 64 * j >= cnt) break;   // uniform over the wave
+      bool keep = false;
+      double r2 = 0.0;
+      if (e[j] >= 0) {
+        const double d0 = d[j][0] - xi0, d1 = d[j][1] - xi1, d2 = d[j][2] - xi2;
+        r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+        keep = r2 < rc2;
+      }
+      ncand = nl_append(keep, r2, e[j], ncand, lane, F, eown, eimg, etype, rows, cap);
+    }
   }
   return ncand;
 }

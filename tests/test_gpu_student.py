@@ -200,3 +200,28 @@ def test_student_gain_over_full_net(dp, water_model, trained_students, prec):
           % (prec, rmse, 1e3 * t_stu, 1e3 * t_full, t_full / t_stu), flush=True)
     assert rmse <= 1e-3
     assert t_stu < t_full
+
+
+def test_water786k_student_and_full(dp, water_model, trained_students):
+    """The 786,432-atom water system (one GPU's large share): FP64 full net against the
+    oracle on sampled atoms, and the split-BF16 student path against the FP64 full net at
+    identical coordinates (students trained on the 12,288-atom system's FP64 MD)."""
+    import torch
+    from oracle.oracle import Oracle, set_threads
+    c, t, b = I.config_water786k(205)
+    x = torch.as_tensor(c, device="cuda")
+    td = torch.as_tensor(t, dtype=torch.int32, device="cuda")
+    full = dp.DPModel(water_model, "fp64")
+    E64, F64, W64 = full.compute(x, td, b)
+    set_threads(8)
+    idx = np.sort(np.random.default_rng(11).choice(len(t), 32, replace=False))
+    _, Fo = Oracle(water_model).eval_sampled(c, t, b, idx)
+    F64n = F64.cpu().numpy()
+    assert np.linalg.norm(F64n[idx] - Fo, axis=1).max() <= 1e-9 * np.linalg.norm(Fo, axis=1).max()
+    d = trained_students
+    stu = dp.DPModel(water_model, "bf16x3")
+    stu.set_student(32, d["th"], d["lo"], d["hi"])
+    Es, Fs, Ws = stu.compute(x, td, b)
+    rmse = float(torch.sqrt(((Fs - F64) ** 2).mean()) / torch.sqrt((F64 ** 2).mean()))
+    print("786k bf16x3 student force RMSE rel %.3e" % rmse, flush=True)
+    assert rmse <= 1e-3
