@@ -56,6 +56,7 @@ __global__ __launch_bounds__(64) void k_fb_fwd(EmbedArgs A) {
     __syncthreads();
     if (lane < s1) {
       double z = nt.b1[lane];
+#pragma unroll 8
       for (int a = 0; a < s0; a++) z += h0[a] * nt.W1[a * s1 + lane];
       h1[lane] = h0[lane % s0] + dp_tanh(z);
     }
@@ -63,6 +64,7 @@ __global__ __launch_bounds__(64) void k_fb_fwd(EmbedArgs A) {
     T* Tr = (T*)A.T + (size_t)row * M * 4;
     for (int o = lane; o < M; o += 64) {
       double z = nt.b2[o];
+#pragma unroll 8
       for (int a = 0; a < s1; a++) z += h1[a] * nt.W2[a * M + o];
       double G = h1[o % s1] + dp_tanh(z);
       for (int c = 0; c < 4; c++) unsafeAtomicAdd(&Tr[o * 4 + c], (T)(G * env[1 + c] * m.inv_norm));
@@ -97,6 +99,7 @@ __global__ __launch_bounds__(64) void k_fb_bwd(EmbedArgs A) {
     __syncthreads();
     if (lane < s1) {
       double z = nt.b1[lane];
+#pragma unroll 8
       for (int a = 0; a < s0; a++) z += t0[a] * nt.W1[a * s1 + lane];
       t1[lane] = dp_tanh(z);
       h1[lane] = t0[lane % s0] + t1[lane];
@@ -106,6 +109,7 @@ __global__ __launch_bounds__(64) void k_fb_bwd(EmbedArgs A) {
     double gR[4] = {0, 0, 0, 0};
     for (int o = lane; o < M; o += 64) {
       double z = nt.b2[o];
+#pragma unroll 8
       for (int a = 0; a < s1; a++) z += h1[a] * nt.W2[a * M + o];
       double t2 = dp_tanh(z);
       double G = h1[o % s1] + t2;
@@ -122,6 +126,7 @@ __global__ __launch_bounds__(64) void k_fb_bwd(EmbedArgs A) {
     __syncthreads();
     if (lane < s1) {
       double v = gg[lane] + gg[lane + s1];   // concat skip of the last layer
+#pragma unroll 8
       for (int o = 0; o < M; o++) v += d2[o] * nt.W2[lane * M + o];
       gh1[lane] = v;
       d1[lane] = v * (1.0 - t1[lane] * t1[lane]);
@@ -130,6 +135,7 @@ __global__ __launch_bounds__(64) void k_fb_bwd(EmbedArgs A) {
     double ds = 0.0;
     if (lane < s0) {
       double v = gh1[lane] + gh1[lane + s0];   // concat skip of the middle layer
+#pragma unroll 8
       for (int o = 0; o < s1; o++) v += d1[o] * nt.W1[lane * s1 + o];
       ds = v * (1.0 - t0[lane] * t0[lane]) * nt.W0[lane];
     }
@@ -156,9 +162,6 @@ __global__ __launch_bounds__(64) void k_fb_bwd(EmbedArgs A) {
     __syncthreads();
   }
 }
-
-constexpr int kStuWaves = 8;
-
 
 void launch_fallback_fwd(const EmbedArgs& a, hipStream_t st) {
   if (a.prec == PREC_FP64) hipLaunchKernelGGL(k_fb_fwd<double>, dim3(1024), dim3(64), 0, st, a);
