@@ -11,13 +11,15 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdp.so")
-SOURCES = ["dp_api.cpp", "nlist.hip", "embed.hip", "fit.hip", "md.hip", "pgrad.hip", "student.hip", "student_infer.hip", "scatter.hip"]
+SOURCES = ["dp_api.cpp", "nlist.hip", "embed.hip", "fit.hip", "fit_bf.hip", "md.hip", "pgrad.hip", "student.hip", "student_infer.hip", "scatter.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions: plain FP32 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # MFMA accumulators in ordinary VGPRs (no AGPR copies in the GEMM loops)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 

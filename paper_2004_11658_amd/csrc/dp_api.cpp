@@ -348,6 +348,43 @@ static int upload_weights(dp_handle h) {
         nin = nout;
       }
     }
+  // the same weights as MFMA operand fragments for the 64-row-tile kernels: per species,
+  // layer and direction (0 forward B[k][n] = W[k][n], 1 adjoint B[k][n] = W[n][k]) blocks
+  // (ct, ks, part) of 64 lanes x 8, lane l holding B[32 ks + 8 (l / 16) + j][16 ct + l % 16],
+  // zero outside B.  Operands whose columns are fitting-layer outputs or inputs of width
+  // <= 256 get 16 column tiles (the kernels' waves take four each, unconditionally); the
+  // first layer's adjoint (columns = descriptor entries) gets exactly M tiles.
+  std::vector<size_t> offWf;
+  if (bf && fit_bf_supported(h->M, h->m2, h->fit_w[0]))
+    for (int a = 0; a < h->ntypes; a++) {
+      int nin = h->M * h->m2;
+      for (int k = 0; k < h->n_fit; k++) {
+        const int nout = h->fit_w[k];
+        const int64_t w0 = P.fW[a * (h->n_fit + 1) + k];
+        for (int dir = 0; dir < 2; dir++) {
+          offWf.push_back(bmap.size());
+          const int K = dir == 0 ? nin : nout, N = dir == 0 ? nout : nin;
+          // k steps: the first layer's forward takes all of K = 16 M; every other operand's k
+          // dimension is a fitting width, padded to 8 steps (256)
+          const int KS = (k == 0 && dir == 0) ? (K + 31) / 32 : 8;
+          const int NT = (k == 0 && dir == 1) ? (N + 15) / 16 : 16;
+          for (int ct = 0; ct < NT; ct++)
+            for (int ks = 0; ks < KS; ks++)
+              for (int part = 0; part < parts; part++)
+                for (int l = 0; l < 64; l++)
+                  for (int j = 0; j < 8; j++) {
+                    const int kk = 32 * ks + 8 * (l >> 4) + j, n = 16 * ct + (l & 15);
+                    if (kk >= K || n >= N) {
+                      bmap.push_back(-1);
+                      continue;
+                    }
+                    const int64_t idx = dir == 0 ? w0 + (int64_t)kk * nout + n : w0 + (int64_t)n * nout + kk;
+                    bmap.push_back((int)(4 * idx + part));
+                  }
+        }
+        nin = nout;
+      }
+    }
   // fitting weights, per species: W_k, b_k for k < nfit, then wo (rows padded to 64)
   std::vector<int> fmap;
   std::vector<size_t> offW, offB, offO;
@@ -394,6 +431,8 @@ static int upload_weights(dp_handle h) {
   for (size_t q = 0; q < offO.size(); q++) ptrs.push_back(base + offO[q] * sb);
   // BF16 operand table [(species * nfit + k) * 4 + dir * 2 + part]
   for (size_t q = 0; q < offWb.size(); q++) ptrs.push_back(h->d_fitb + offWb[q]);
+  // BF16 operand fragments [(species * nfit + k) * 2 + dir]
+  for (size_t q = 0; q < offWf.size(); q++) ptrs.push_back(h->d_fitb + offWf[q]);
   HIPCHECK(h, hipMalloc(&h->d_ptrs, ptrs.size() * sizeof(void*)));
   HIPCHECK(h, hipMemcpy(h->d_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice));
   std::vector<int64_t> noff((size_t)nnet * 6);
@@ -805,6 +844,7 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
   F.b = (const void* const*)h->d_ptrs + h->ntypes * h->n_fit;
   F.wo = (const void* const*)h->d_ptrs + 2 * h->ntypes * h->n_fit;
   F.Wb = (const void* const*)h->d_ptrs + 2 * h->ntypes * h->n_fit + h->ntypes;
+  F.Wf = F.Wb + 4 * h->ntypes * h->n_fit;
   F.bo = h->d_bo;
   F.D = W.at<void>(P.o_D);
   F.Dg = W.at<void>(P.o_Dg);

@@ -355,155 +355,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf(GemmArgs G) {
     }
 }
 
-// ------------------------------------------------------------------------------------
-// BF16 first fitting layer with the descriptor fused in (forward).
-//
-// x1 = tanh(D W1 + b1) with D = T T<^T (Eq. 4) formed in the operand staging, so D never
-// reaches HBM.  A workgroup of 8 waves takes 32 rows (one species); wave w owns row
-// tile w & 1 and the column tiles (w >> 1) + 4 u.  K is consumed 32 at a time: the
-// workgroup forms that slice of D from T< (staged once in LDS) and each row's T[a], and
-// loads the W1^T slice cooperatively one stage ahead into registers; both go to LDS as
-// BF16 (hi, lo) MFMA operands.
-// ------------------------------------------------------------------------------------
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-constexpr int F1R = 32;     // rows per workgroup
-constexpr int F1T = 512;    // threads per workgroup
-constexpr int F1KC = 32;    // k per forward stage (one MFMA k chunk)
-constexpr int F1LD = F1KC + 8;
-
-struct Fit1Args {
-  int M, N, nfit;              // embedding width, hidden width (multiple of 16, <= 256), layers
-  const int* type_row0;
-  int ntypes;
-  const int* row_atom;
-  const float* T;              // [nrows][M][4]
-  const void* const* Wb;       // operand table: [(species * nfit + k) * 4 + dir * 2 + part]
-  const void* const* bias;     // [species * nfit + k]
-  float *out, *out2;           // x1 and t1 [nrows][N]
-};
-
-__device__ __forceinline__ int fit1_species(const Fit1Args& P, int r0) {
-  for (int t = 0; t < P.ntypes; t++)
-    if (r0 >= P.type_row0[t] && r0 < P.type_row0[t + 1]) return t;
-  return -1;
-}
-
-// T< of the workgroup's rows into LDS (pad rows: zeros)
-__device__ __forceinline__ void fit1_stage_tl(const Fit1Args& P, int r0, float* Tl) {
-  for (int q = threadIdx.x; q < F1R * 16; q += F1T) {
-    const int r = q >> 4, b = q & 15;
-    f4v v = {0.f, 0.f, 0.f, 0.f};
-    if (P.row_atom[r0 + r] >= 0) v = *(const f4v*)(P.T + ((size_t)(r0 + r) * P.M + b) * 4);
-    *(f4v*)(Tl + q * 4) = v;
-  }
-}
-
-template <int PARTS>
-__global__ __launch_bounds__(F1T) void k_fit1_fwd_bf(Fit1Args P) {
-  extern __shared__ __align__(16) char sm[];
-  const int M = P.M, K = 16 * M, N = P.N, ntile = N / 16;
-  float* Tl = (float*)sm;                                          // [F1R][16][4]: T<
-  __bf16* As = (__bf16*)(sm + F1R * 16 * 16);                      // [PARTS][F1R][F1LD]
-  __bf16* Bs = As + (size_t)PARTS * F1R * F1LD;                    // [PARTS][N][F1LD]
-  const int r0 = blockIdx.x * F1R;
-  const int sp = fit1_species(P, r0);
-  if (sp < 0) return;
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, rb = lane & 15, g = lane >> 4;
-  const int rt = wv & 1, cg = wv >> 1;
-  fit1_stage_tl(P, r0, Tl);
-  const int wi = (sp * P.nfit + 0) * 4 + 0;   // W1^T [N][K]
-  const __bf16* __restrict__ Wh = (const __bf16*)P.Wb[wi];
-  const __bf16* __restrict__ Wl = (const __bf16*)P.Wb[wi + 1];
-  // this thread's D entries: row tid / 16, k = 32 s + 2 (tid % 16) + i, i < 2 (one a)
-  const int drow = tid >> 4, dkq = (tid & 15) * 2;
-  const bool dreal = P.row_atom[r0 + drow] >= 0;
-  const float* trow = P.T + (size_t)(r0 + drow) * M * 4;
-  // this thread's W1^T pieces: e = tid + 512 j < 4 N: column e / 4, k offset 8 (e % 4)
-  const int nB = 4 * N;
-  f4v tv;
-  u32x4 bq0[2], bq1[2];
-#define FIT1_FETCH_B(S_, J)                                                                     \
-  do {                                                                                          \
-    const int e = tid + F1T * (J);                                                              \
-    if (e < nB) {                                                                               \
-      const size_t o = (size_t)(e >> 2) * K + 32 * (S_) + 8 * (e & 3);                          \
-      bq0[J] = *(const u32x4*)(Wh + o);                                                         \
-      if (PARTS == 2) bq1[J] = *(const u32x4*)(Wl + o);                                         \
-    }                                                                                           \
-  } while (0)
-#define FIT1_FETCH(S_)                                                                          \
-  do {                                                                                          \
-    const int a_ = (32 * (S_) + dkq) >> 4;                                                      \
-    tv = dreal ? *(const f4v*)(trow + 4 * a_) : f4v{0.f, 0.f, 0.f, 0.f};                       \
-    FIT1_FETCH_B(S_, 0);                                                                        \
-    FIT1_FETCH_B(S_, 1);                                                                        \
-  } while (0)
-  f4v acc[4];
-#pragma unroll
-  for (int u = 0; u < 4; u++) acc[u] = f4v{0, 0, 0, 0};
-  const int S = K / F1KC;
-  FIT1_FETCH(0);
-  __syncthreads();   // T< staged
-  for (int s = 0; s < S; s++) {
-    {
-      const int b0 = (32 * s + dkq) & 15;
-      const float* tl = Tl + (drow * 16 + b0) * 4;
-      const f4v t0 = *(const f4v*)tl, t1 = *(const f4v*)(tl + 4);
-      const float d0 = tv[0] * t0[0] + tv[1] * t0[1] + tv[2] * t0[2] + tv[3] * t0[3];
-      const float d1 = tv[0] * t1[0] + tv[1] * t1[1] + tv[2] * t1[2] + tv[3] * t1[3];
-      const __bf16 h0 = (__bf16)d0, h1 = (__bf16)d1;
-      if (s > 0) __syncthreads();   // the previous stage's operands have been read
-      As[(size_t)drow * F1LD + dkq] = h0;
-      As[(size_t)drow * F1LD + dkq + 1] = h1;
-      if (PARTS == 2) {
-        As[((size_t)F1R + drow) * F1LD + dkq] = (__bf16)(d0 - (float)h0);
-        As[((size_t)F1R + drow) * F1LD + dkq + 1] = (__bf16)(d1 - (float)h1);
-      }
-#pragma unroll
-      for (int j = 0; j < 2; j++) {
-        const int e = tid + F1T * j;
-        if (e < nB) {
-          *(u32x4*)(Bs + (size_t)(e >> 2) * F1LD + 8 * (e & 3)) = bq0[j];
-          if (PARTS == 2) *(u32x4*)(Bs + ((size_t)N + (e >> 2)) * F1LD + 8 * (e & 3)) = bq1[j];
-        }
-      }
-    }
-    __syncthreads();
-    if (s + 1 < S) FIT1_FETCH(s + 1);
-    const bf8 ah = *(const bf8*)(As + (size_t)(16 * rt + rb) * F1LD + 8 * g);
-    const bf8 al = PARTS == 2 ? *(const bf8*)(As + ((size_t)F1R + 16 * rt + rb) * F1LD + 8 * g) : ah;
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int ct = cg + 4 * u;
-      if (ct >= ntile) continue;
-      const bf8 bh = *(const bf8*)(Bs + (size_t)(16 * ct + rb) * F1LD + 8 * g);
-      const bf8 bl = PARTS == 2 ? *(const bf8*)(Bs + ((size_t)N + 16 * ct + rb) * F1LD + 8 * g) : bh;
-      acc[u] = mfma_split<PARTS>(ah, al, bh, bl, acc[u]);
-    }
-  }
-#undef FIT1_FETCH
-#undef FIT1_FETCH_B
-  const float* bias = (const float*)P.bias[sp * P.nfit + 0];
-#pragma unroll
-  for (int u = 0; u < 4; u++) {
-    const int ct = cg + 4 * u;
-    if (ct >= ntile) continue;
-    const int col = 16 * ct + rb;
-    const float bc = bias[col];
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const size_t o = (size_t)(r0 + 16 * rt + 4 * g + q) * N + col;
-      const float t = dp_tanh(acc[u][q] + bc);
-      P.out[o] = t;
-      P.out2[o] = t;
-    }
-  }
-}
-
-size_t fit1_fwd_lds(int N, int parts) {
-  return (size_t)F1R * 16 * 16 + (size_t)parts * (F1R + N) * F1LD * 2;
-}
-
 // D[row][a m2 + b] = sum_c T[row][a][c] T[row][b][c]; pad rows get zeros
 template <class T>
 __global__ void k_desc(int nrows, int M, int m2, const int* __restrict__ row_atom,
@@ -589,26 +440,16 @@ template <class T>
 static void fit_t(const FitArgs& F, hipStream_t st) {
   const int prec = F.prec;
   const int rows = F.nrows, M = F.m.M, m2 = F.m.m2, K1 = M * m2, fw = F.fw;
-  // BF16 modes run the first layer's forward with the descriptor fused in
+  // BF16 modes: the 64-row-tile kernels (descriptor fused into the first layer, no D or dD
+  // in HBM) whenever the shapes allow
   const bool bf = prec == PREC_BF16 || prec == PREC_BF16X3;
-  const int parts = prec == PREC_BF16X3 ? 2 : 1;
-  const bool fuse_desc = bf && m2 == 16 && M % 4 == 0 && M >= 16 && fw % 16 == 0 && fw <= 256 &&
-                         rows % F1R == 0;
-  Fit1Args P1{};
-  P1.M = M;
-  P1.N = fw;
-  P1.nfit = F.nfit;
-  P1.type_row0 = F.type_row0;
-  P1.ntypes = F.m.ntypes;
-  P1.row_atom = F.row_atom;
-  P1.T = (const float*)F.T;
-  P1.Wb = F.Wb;
-  P1.bias = F.b;
-  if (!fuse_desc) {
-    size_t tot = (size_t)rows * K1;
-    hipLaunchKernelGGL(k_desc<T>, dim3((tot + 255) / 256), dim3(256), 0, st, rows, M, m2, F.row_atom,
-                       (const T*)F.T, (T*)F.D);
+  if (bf && fit_bf_supported(M, m2, fw)) {
+    launch_fit_bf(F, st);
+    return;
   }
+  size_t tot = (size_t)rows * K1;
+  hipLaunchKernelGGL(k_desc<T>, dim3((tot + 255) / 256), dim3(256), 0, st, rows, M, m2, F.row_atom,
+                     (const T*)F.T, (T*)F.D);
   T* act = (T*)F.act;
   T* xs = (T*)F.xs;
   size_t L = (size_t)rows * fw;
@@ -628,18 +469,7 @@ static void fit_t(const FitArgs& F, hipStream_t st) {
     G.Xprev = k == 0 ? nullptr : (const void*)(xs + (k - 1) * L);
     G.out = xs + k * L;
     G.out2 = act + k * L;
-    if (k == 0 && fuse_desc) {
-      P1.out = (float*)(xs + k * L);
-      P1.out2 = (float*)(act + k * L);
-      const size_t sh = fit1_fwd_lds(fw, parts);
-      if (parts == 2) {
-        (void)hipFuncSetAttribute((const void*)k_fit1_fwd_bf<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_fit1_fwd_bf<2>, dim3(rows / F1R), dim3(F1T), sh, st, P1);
-      } else {
-        (void)hipFuncSetAttribute((const void*)k_fit1_fwd_bf<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_fit1_fwd_bf<1>, dim3(rows / F1R), dim3(F1T), sh, st, P1);
-      }
-    } else if (k == 0) {
+    if (k == 0) {
       gemm<T, EPI_FWD1>(prec, G, st);
     } else {
       gemm<T, EPI_FWDRES>(prec, G, st);

@@ -1,0 +1,559 @@
+// BF16 fitting net (Section 2, Eq. 1-4) and its adjoint in three kernels per 64-row tile.
+//
+// Rows are centres grouped by species (groups padded to 64 rows), so one workgroup takes
+// one 64-row tile and one species' fitting net.  The MFMA runs with the weights as the
+// A operand (16 outputs x 32 k) and the activations as the B operand (32 k x 16 rows): a
+// lane of the result holds 4 consecutive outputs n = 16 ct + 4 g + q of one row 16 rt + rb
+// (rb = lane % 16, g = lane / 16).  Wave w of the 4 owns the output tiles ct = w + 4 u
+// for all four row tiles rt.
+//
+// Weights are pre-packed as MFMA fragments (block (ct, ks, part) of 64 lanes x 8 bf16,
+// lane l holding B[32 ks + 8 (l / 16) + j][16 ct + l % 16], B = W for the forward and
+// B = W^T for the adjoint, hi and lo parts), so a wave fetches a fragment with one
+// coalesced 1 KB load straight from L2, and every fragment is fetched by one wave only.
+// Activations are staged in LDS in the same fragment order.
+//
+//   k_fit_l1_fwd   t1 = tanh(D W1 + b1) with D = T T<^T (Eq. 4) formed while staging
+//   k_fit_tail     x_k = x_{k-1} + tanh(x_{k-1} W_k + b_k) for the square layers,
+//                  E_i = x_L . w_o + b_o, then back to d1 = dE/dz1 = g1 (1 - t1^2), stored as
+//                  MFMA operand fragments
+//   k_fit_l1_bwd   dD = d1 W1^T and dE/dT = dD T< + [a < m2] dD^T T (Eq. 4's adjoint);
+//                  dD never leaves the registers
+#include <hip/hip_runtime.h>
+
+#include "bf16ops.h"
+#include "common.h"
+#include "devmath.h"
+#include "kernels.h"
+
+namespace dp {
+
+constexpr int FR = 64;    // rows per workgroup
+constexpr int FT = 256;   // threads per workgroup (4 waves)
+
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+
+struct FitBfArgs {
+  int M, N, nfit, ntypes, nrows;
+  const int* type_row0;
+  const int* row_atom;
+  const float* T;                // [nrows][M][4]
+  const void* const* Wf;         // [(species * nfit + k) * 2 + dir] fragment-packed weights
+  const void* const* bias;       // [species * nfit + k] -> float [N]
+  const void* const* wo;         // [species] -> float [N]
+  const double* bo;              // [species]
+  float* t1;                     // [nrows][N] first-layer tanh
+  float* act;                    // [nfit][nrows][N] tanh of the square layers (per-tile lane order)
+  __bf16* d1f;                   // per tile [kKS][4][PARTS][512] dE/dz1 fragments
+  double* Ei;                    // [nrows]
+  float* gT;                     // [nrows][M][4]
+};
+
+__device__ __forceinline__ int fitbf_species(const FitBfArgs& P, int r0) {
+  for (int t = 0; t < P.ntypes; t++)
+    if (r0 >= P.type_row0[t] && r0 < P.type_row0[t + 1]) return t;
+  return -1;
+}
+
+// Loads through pointers read from the operand tables are generic (flat) unless told
+// otherwise; flat loads also count against the LDS wait counter, so name them global.
+#define GAS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T gld(const void* p) {
+  return *(const GAS T*)p;
+}
+
+// weight fragment (ct, ks) of a packed operand with KS k steps
+template <int PARTS>
+__device__ __forceinline__ void wfrag(const __bf16* __restrict__ W, int KS, int ct, int ks, int lane, bf8& h,
+                                      bf8& l) {
+  const __bf16* p = W + ((size_t)(ct * KS + ks) * PARTS) * 512 + lane * 8;
+  h = gld<bf8>(p);
+  l = PARTS == 2 ? gld<bf8>(p + 512) : h;
+}
+
+// Activation fragments: the value of row 16 rt + rb at n = 16 ct + 4 g + q sits in
+// fragment (ks = ct / 2, rt), lane rb + 16 (2 (ct % 2) + g / 2), element 4 (g % 2) + q.
+__device__ __forceinline__ int xfrag_off(int ct, int rt, int part, int parts, int rb, int g) {
+  const int ks = ct >> 1, lp = rb + 16 * (2 * (ct & 1) + (g >> 1));
+  return (((ks * 4 + rt) * parts + part) * 64 + lp) * 8 + 4 * (g & 1);
+}
+
+template <int PARTS>
+__device__ __forceinline__ void put4(__bf16* X, int ct, int rt, int rb, int g, f4v v) {
+  bf4 h, l;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const __bf16 hv = (__bf16)v[q];
+    h[q] = hv;
+    if (PARTS == 2) l[q] = (__bf16)(v[q] - (float)hv);
+  }
+  *(bf4*)(X + xfrag_off(ct, rt, 0, PARTS, rb, g)) = h;
+  if (PARTS == 2) *(bf4*)(X + xfrag_off(ct, rt, 1, PARTS, rb, g)) = l;
+}
+
+// stage a [u][rt] register tile (C layout of the wave's column tiles) into LDS fragments
+template <int PARTS>
+__device__ __forceinline__ void stage_tile(__bf16* Xs, const f4v (&v)[4][4], int w, int NT, int rb, int g) {
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int ct = w + 4 * u;
+    if (ct >= NT) continue;
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) put4<PARTS>(Xs, ct, rt, rb, g, v[u][rt]);
+  }
+}
+
+// acc[u][rt] += sum_ks W(ct_u, ks) X(ks, rt); W from global (one fragment step ahead),
+// X from LDS
+template <int PARTS>
+__device__ __forceinline__ void mma_step(const bf8 (&wh)[4], const bf8 (&wl)[4], const __bf16* Xs, int ks, int lane,
+                                         f4v (&acc)[4][4]) {
+  bf8 xh[4], xl[4];
+#pragma unroll
+  for (int rt = 0; rt < 4; rt++) {
+    const __bf16* p = Xs + ((size_t)(ks * 4 + rt) * PARTS) * 512 + lane * 8;
+    xh[rt] = *(const bf8*)p;
+    xl[rt] = PARTS == 2 ? *(const bf8*)(p + 512) : xh[rt];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; u++)
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) acc[u][rt] = mfma_split<PARTS>(wh[u], wl[u], xh[rt], xl[rt], acc[u][rt]);
+}
+
+// the wave's four column tiles w + 4 u of k step ks (operands padded to 16 column tiles)
+template <int PARTS>
+__device__ __forceinline__ void load_w4(const __bf16* __restrict__ W, int KS, int ks, int w, int lane,
+                                        bf8 (&wh)[4], bf8 (&wl)[4]) {
+#pragma unroll
+  for (int u = 0; u < 4; u++) wfrag<PARTS>(W, KS, w + 4 * u, ks, lane, wh[u], wl[u]);
+}
+
+// k steps of the operands whose k dimension is a fitting-layer width (<= 256, padded)
+constexpr int kKS = 8;
+
+template <int PARTS>
+__device__ __forceinline__ void tile_mm(const __bf16* __restrict__ W, int w, int lane, const __bf16* Xs,
+                                        f4v (&acc)[4][4]) {
+  bf8 wh[2][4], wl[2][4];
+  load_w4<PARTS>(W, kKS, 0, w, lane, wh[0], wl[0]);
+#pragma unroll
+  for (int ks = 0; ks < kKS; ks++) {
+    if (ks + 1 < kKS) load_w4<PARTS>(W, kKS, ks + 1, w, lane, wh[(ks + 1) & 1], wl[(ks + 1) & 1]);
+    __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's products
+    mma_step<PARTS>(wh[ks & 1], wl[ks & 1], Xs, ks, lane, acc);
+  }
+}
+
+__device__ __forceinline__ void zero_tile(f4v (&a)[4][4]) {
+#pragma unroll
+  for (int u = 0; u < 4; u++)
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) a[u][rt] = f4v{0.f, 0.f, 0.f, 0.f};
+}
+
+// ------------------------------------------------------------------------------------
+// first layer forward: t1 = tanh(D W1 + b1), K = 16 M consumed 32 at a time.  Thread
+// (w, lane) forms the D fragment slot of row 16 w + rb for the k step: 8 values
+// D[row][a][b], a = 2 s + g / 2, b = 8 (g % 2) + j, from T[row][a] and T<[row][b] (held
+// in registers for the whole loop); D slices are double-buffered in LDS, one barrier per
+// step, and the wave's weight fragments are fetched one step ahead.
+// ------------------------------------------------------------------------------------
+template <int PARTS>
+__global__ __launch_bounds__(FT) void k_fit_l1_fwd(FitBfArgs P) {
+  __shared__ __align__(16) __bf16 Ds[2][4 * PARTS * 512];
+  const int r0 = blockIdx.x * FR;
+  const int sp = fitbf_species(P, r0);
+  if (sp < 0) return;
+  const int M = P.M, KS = M / 2, N = P.N, NT = N / 16;
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, rb = lane & 15,
+            g = lane >> 4;
+  const int row = r0 + 16 * w + rb;
+  const bool real = P.row_atom[row] >= 0;
+  const float* Tr = P.T + (size_t)row * M * 4;
+  const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+  f4v tl[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    tl[j] = *(const f4v*)(Tr + 4 * (8 * (g & 1) + j));   // pad rows: loaded, then zeroed
+    if (!real) tl[j] = z4;
+  }
+  const __bf16* W = (const __bf16*)P.Wf[(sp * P.nfit) * 2];
+  f4v acc[4][4];
+  zero_tile(acc);
+  bf8 ah[4], al[4], bh[4], bl[4];
+  f4v ta;
+#define L1_LOAD_T(S_) ta = *(const f4v*)(Tr + 4 * (2 * (S_) + (g >> 1)))
+#define L1_FORM_D(BUF_)                                                                           \
+  do {                                                                                            \
+    float d_[8];                                                                                  \
+    const f4v tv_ = real ? ta : z4;                                                               \
+    _Pragma("unroll") for (int j = 0; j < 8; j++) d_[j] =                                         \
+        tv_[0] * tl[j][0] + tv_[1] * tl[j][1] + tv_[2] * tl[j][2] + tv_[3] * tl[j][3];            \
+    bf8 h_, l_;                                                                                   \
+    split8<PARTS>(d_, h_, l_);                                                                    \
+    *(bf8*)(&Ds[BUF_][(w * PARTS) * 512 + lane * 8]) = h_;                                        \
+    if (PARTS == 2) *(bf8*)(&Ds[BUF_][(w * PARTS + 1) * 512 + lane * 8]) = l_;                    \
+  } while (0)
+  // KS is even; fetches past the last step are clamped to it (harmless repeats), so
+  // no load sits behind a branch and the wait counts stay exact
+  // issue order as in the loop (T of the next step, then the b fragments), so that the
+  // wait counts at the loop head agree on both incoming paths
+  L1_LOAD_T(0);
+  load_w4<PARTS>(W, KS, 0, w, lane, ah, al);
+  L1_FORM_D(0);
+  L1_LOAD_T(1);
+  __builtin_amdgcn_sched_barrier(0);
+  load_w4<PARTS>(W, KS, 1, w, lane, bh, bl);
+  __syncthreads();
+  for (int s = 0; s < KS; s += 2) {
+    const int s2 = min(s + 2, KS - 1), s3 = min(s + 3, KS - 1);
+    mma_step<PARTS>(ah, al, Ds[0], 0, lane, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    load_w4<PARTS>(W, KS, s2, w, lane, ah, al);
+    __builtin_amdgcn_sched_barrier(0);   // the fetch two steps ahead stays here
+    L1_FORM_D(1);   // step s + 1
+    L1_LOAD_T(s2);
+    __syncthreads();
+    mma_step<PARTS>(bh, bl, Ds[1], 0, lane, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    load_w4<PARTS>(W, KS, s3, w, lane, bh, bl);
+    __builtin_amdgcn_sched_barrier(0);
+    L1_FORM_D(0);   // step s + 2 (unused after the last step)
+    L1_LOAD_T(s3);
+    __syncthreads();
+  }
+#undef L1_LOAD_T
+#undef L1_FORM_D
+  const float* bias = (const float*)P.bias[sp * P.nfit];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int ct = w + 4 * u;
+    if (ct >= NT) continue;
+    const f4v bv = gld<f4v>(bias + 16 * ct + 4 * g);
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) {
+      f4v t;
+#pragma unroll
+      for (int q = 0; q < 4; q++) t[q] = dp_tanh(acc[u][rt][q] + bv[q]);
+      *(f4v*)(P.t1 + (size_t)(r0 + 16 * rt + rb) * N + 16 * ct + 4 * g) = t;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// square layers, output and the adjoint back to the first layer
+// ------------------------------------------------------------------------------------
+size_t fit_tail_lds(int parts) { return (size_t)kKS * 4 * parts * 1024 + 4 * 64 * 8; }
+
+template <int PARTS>
+__global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
+  extern __shared__ __align__(16) char smem[];
+  const int N = P.N, NT = N / 16;
+  __bf16* Xs = (__bf16*)smem;
+  double* red = (double*)(smem + (size_t)kKS * 4 * PARTS * 1024);
+  const int r0 = blockIdx.x * FR;
+  const int sp = fitbf_species(P, r0);
+  if (sp < 0) return;
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, rb = lane & 15,
+            g = lane >> 4;
+  // the k >= N tail of the last fragment step stays zero
+  for (int q = tid; q < kKS * 4 * PARTS * 64; q += FT) ((u32x4v*)Xs)[q] = u32x4v{0u, 0u, 0u, 0u};
+  const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+  f4v x[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int ct = w + 4 * u;
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++)
+      x[u][rt] = ct < NT ? *(const f4v*)(P.t1 + (size_t)(r0 + 16 * rt + rb) * N + 16 * ct + 4 * g) : z4;
+  }
+  const size_t lstride = (size_t)P.nrows * N;
+  f4v acc[4][4];
+  for (int k = 1; k < P.nfit; k++) {
+    __syncthreads();
+    stage_tile<PARTS>(Xs, x, w, NT, rb, g);
+    __syncthreads();
+    zero_tile(acc);
+    tile_mm<PARTS>((const __bf16*)P.Wf[(sp * P.nfit + k) * 2], w, lane, Xs, acc);
+    const float* bias = (const float*)P.bias[sp * P.nfit + k];
+    float* ak = P.act + k * lstride + (size_t)r0 * N;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int ct = w + 4 * u;
+      if (ct >= NT) continue;
+      const f4v bv = gld<f4v>(bias + 16 * ct + 4 * g);
+#pragma unroll
+      for (int rt = 0; rt < 4; rt++) {
+        f4v t;
+#pragma unroll
+        for (int q = 0; q < 4; q++) t[q] = dp_tanh(acc[u][rt][q] + bv[q]);
+        x[u][rt] += t;
+        *(f4v*)(ak + ((size_t)(ct * 4 + rt) * 64 + lane) * 4) = t;
+      }
+    }
+  }
+  // E_i = x . w_o + b_o, FP64 sums
+  const float* wo = (const float*)P.wo[sp];
+  f4v wv[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) wv[u] = w + 4 * u < NT ? gld<f4v>(wo + 16 * (w + 4 * u) + 4 * g) : z4;
+  double e[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < 4; u++)
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) e[rt] += (double)x[u][rt][q] * (double)wv[u][q];
+#pragma unroll
+  for (int rt = 0; rt < 4; rt++) {
+    e[rt] += __shfl_xor(e[rt], 16);
+    e[rt] += __shfl_xor(e[rt], 32);
+  }
+  if (g == 0)
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) red[w * 64 + 16 * rt + rb] = e[rt];
+  __syncthreads();
+  if (tid < 64) {
+    const int row = r0 + tid;
+    P.Ei[row] = P.row_atom[row] >= 0 ? red[tid] + red[64 + tid] + red[128 + tid] + red[192 + tid] + P.bo[sp] : 0.0;
+  }
+  // adjoint: g_L = w_o; g_{k-1} = g_k + (g_k (1 - t_k^2)) W_k^T
+  f4v gr[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; u++)
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) gr[u][rt] = wv[u];
+  for (int k = P.nfit - 1; k >= 1; k--) {
+    const float* ak = P.act + k * lstride + (size_t)r0 * N;
+    f4v d[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int ct = w + 4 * u;
+#pragma unroll
+      for (int rt = 0; rt < 4; rt++) {
+        f4v t = ct < NT ? *(const f4v*)(ak + ((size_t)(ct * 4 + rt) * 64 + lane) * 4) : z4;
+        d[u][rt] = gr[u][rt] * (1.f - t * t);
+      }
+    }
+    __syncthreads();
+    stage_tile<PARTS>(Xs, d, w, NT, rb, g);
+    __syncthreads();
+    zero_tile(acc);
+    tile_mm<PARTS>((const __bf16*)P.Wf[(sp * P.nfit + k) * 2 + 1], w, lane, Xs, acc);
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int rt = 0; rt < 4; rt++) gr[u][rt] += acc[u][rt];
+  }
+  // d1 = g1 (1 - t1^2) as fragments for the first layer's adjoint; pad rows and the
+  // k >= N tail are zero
+  __bf16* out = P.d1f + (size_t)blockIdx.x * kKS * 4 * PARTS * 512;
+  bool real[4];
+#pragma unroll
+  for (int rt = 0; rt < 4; rt++) real[rt] = P.row_atom[r0 + 16 * rt + rb] >= 0;
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int ct = w + 4 * u;
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) {
+      f4v v = z4;
+      if (ct < NT && real[rt]) {
+        const f4v t = *(const f4v*)(P.t1 + (size_t)(r0 + 16 * rt + rb) * N + 16 * ct + 4 * g);
+        v = gr[u][rt] * (1.f - t * t);
+      }
+      put4<PARTS>(out, ct, rt, rb, g, v);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// first layer adjoint and the descriptor adjoint.  Output tile a of dD = d1 W1^T holds
+// dD[row][a][b] for b < 16 in lane (rb = row, g) as b = 4 g + q, so
+//   dE/dT[row][a][c]  = sum_b dD[row][a][b] T[row][b][c]     (sum over q in the lane, then
+//                                                               a reduce-scatter over g)
+//   dE/dT[row][b][c] += sum_a dD[row][a][b] T[row][a][c]     (b < 16; accumulated per lane
+//                                                               over the wave's a, the four
+//                                                               waves' parts added in order)
+// Wave w takes the a range [w ceil(M/4), (w+1) ceil(M/4)), two a per pass; d1 fragments
+// sit in LDS, the wave's weight fragments are fetched one step ahead.
+// ------------------------------------------------------------------------------------
+constexpr int kTlStride = 68;   // floats per row of the staged T< (bank spread)
+
+size_t fit_l1_bwd_lds(int parts) {
+  const size_t xs = (size_t)kKS * 4 * parts * 1024, p2 = (size_t)4 * 64 * 64 * 4;
+  return (xs > p2 ? xs : p2) + 64 * 64 * 4 + 64 * kTlStride * 4;
+}
+
+// the weight fragments of the output tiles (a, a + 1) at k step ks
+template <int PARTS>
+__device__ __forceinline__ void load_w2(const __bf16* __restrict__ W, int a, int ks, int lane, bf8 (&wh)[2],
+                                        bf8 (&wl)[2]) {
+  wfrag<PARTS>(W, kKS, a, ks, lane, wh[0], wl[0]);
+  wfrag<PARTS>(W, kKS, a + 1, ks, lane, wh[1], wl[1]);
+}
+
+template <int PARTS>
+__global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_fit_l1_bwd(FitBfArgs P) {
+  extern __shared__ __align__(16) char smem[];
+  const int M = P.M;
+  const size_t xs_bytes = (size_t)kKS * 4 * PARTS * 1024, p2_bytes = (size_t)4 * 64 * 64 * 4;
+  __bf16* Xs = (__bf16*)smem;
+  float* P2 = (float*)smem;                                                     // after the GEMMs
+  float* T1s = (float*)(smem + (xs_bytes > p2_bytes ? xs_bytes : p2_bytes));   // [64][16][4]
+  float* Tls = T1s + 64 * 64;                                                   // [64][kTlStride]: T<
+  const int r0 = blockIdx.x * FR;
+  const int sp = fitbf_species(P, r0);
+  if (sp < 0) return;
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, rb = lane & 15,
+            g = lane >> 4;
+  {
+    const u32x4v* src = (const u32x4v*)(P.d1f + (size_t)blockIdx.x * kKS * 4 * PARTS * 512);
+    for (int q = tid; q < kKS * 4 * PARTS * 64; q += FT) ((u32x4v*)Xs)[q] = src[q];
+  }
+  const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+  // T< of the tile's rows (pad rows zero)
+  for (int q = tid; q < 64 * 16; q += FT) {
+    const int rl = q >> 4, b = q & 15;
+    f4v v = *(const f4v*)(P.T + ((size_t)(r0 + rl) * M + b) * 4);
+    if (P.row_atom[r0 + rl] < 0) v = z4;
+    *(f4v*)(Tls + rl * kTlStride + 4 * b) = v;
+  }
+  bool real[4];
+  const float* Trow[4];
+#pragma unroll
+  for (int rt = 0; rt < 4; rt++) {
+    const int row = r0 + 16 * rt + rb;
+    real[rt] = P.row_atom[row] >= 0;
+    Trow[rt] = P.T + (size_t)row * M * 4;
+  }
+  f4v p2[4][4];
+#pragma unroll
+  for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) p2[rt][q] = z4;
+  const __bf16* W = (const __bf16*)P.Wf[(sp * P.nfit) * 2 + 1];
+  // a range of this wave: an even count (M is even), two tiles per pass
+  const int per0 = (M + 3) / 4, per = per0 + (per0 & 1);
+  const int a0 = min(M, w * per), a1 = min(M, a0 + per);
+  __syncthreads();
+  // weight fragments, fetched two k steps ahead into a ring of four (kKS is a multiple
+  // of four, so every pass starts at buffer 0)
+  bf8 wh[4][2], wl[4][2];
+  if (a0 < a1) {
+    load_w2<PARTS>(W, a0, 0, lane, wh[0], wl[0]);
+    load_w2<PARTS>(W, a0, 1, lane, wh[1], wl[1]);
+  }
+  for (int a = a0; a < a1; a += 2) {
+    const int an = min(a + 2, a1 - 2);   // next pass (the last pass repeats itself)
+    f4v acc[2][4], tav[2][4];
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+      for (int rt = 0; rt < 4; rt++) {
+        acc[c][rt] = z4;
+        tav[c][rt] = *(const f4v*)(Trow[rt] + (a + c) * 4);
+      }
+#pragma unroll
+    for (int ks = 0; ks < kKS; ks++) {
+      const int nb = (ks + 2) & 3;
+      if (ks + 2 < kKS) load_w2<PARTS>(W, a, ks + 2, lane, wh[nb], wl[nb]);
+      else load_w2<PARTS>(W, an, ks + 2 - kKS, lane, wh[nb], wl[nb]);
+      __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's products
+      bf8 xh[4], xl[4];
+#pragma unroll
+      for (int rt = 0; rt < 4; rt++) {
+        const __bf16* p = Xs + ((size_t)(ks * 4 + rt) * PARTS) * 512 + lane * 8;
+        xh[rt] = *(const bf8*)p;
+        xl[rt] = PARTS == 2 ? *(const bf8*)(p + 512) : xh[rt];
+      }
+#pragma unroll
+      for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++)
+          acc[c][rt] = mfma_split<PARTS>(wh[ks & 3][c], wl[ks & 3][c], xh[rt], xl[rt], acc[c][rt]);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) {
+      f4v tl[4];   // T[row_rt][4 g + q]
+#pragma unroll
+      for (int q = 0; q < 4; q++) tl[q] = *(const f4v*)(Tls + (16 * rt + rb) * kTlStride + 4 * (4 * g + q));
+#pragma unroll
+      for (int c = 0; c < 2; c++) {
+        const f4v cv = acc[c][rt];
+        // first term: sum over b = 4 g + q (in the lane, then over g by a reduce-scatter
+        // that leaves component c = g in lane group g)
+        const f4v pv = cv[0] * tl[0] + cv[1] * tl[1] + cv[2] * tl[2] + cv[3] * tl[3];
+        const bool lo2 = g < 2, ev = (g & 1) == 0;
+        float k0 = lo2 ? pv[0] : pv[2], k1 = lo2 ? pv[1] : pv[3];
+        const float s0 = lo2 ? pv[2] : pv[0], s1 = lo2 ? pv[3] : pv[1];
+        k0 += __shfl_xor(s0, 32);
+        k1 += __shfl_xor(s1, 32);
+        float kk = ev ? k0 : k1;
+        kk += __shfl_xor(ev ? k1 : k0, 16);
+        if (a + c >= 16) P.gT[((size_t)(r0 + 16 * rt + rb) * M + a + c) * 4 + g] = kk;
+        else T1s[((16 * rt + rb) * 16 + a + c) * 4 + g] = kk;
+        // second term, accumulated over the wave's a
+        const f4v tv = real[rt] ? tav[c][rt] : z4;
+#pragma unroll
+        for (int q = 0; q < 4; q++) p2[rt][q] += cv[q] * tv;
+      }
+    }
+  }
+  __syncthreads();   // every read of the d1 fragments is done; P2 reuses that space
+#pragma unroll
+  for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) *(f4v*)(P2 + ((w * 64 + 16 * rt + rb) * 16 + 4 * g + q) * 4) = p2[rt][q];
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += FT) {
+    const int rl = e >> 6, b = (e >> 2) & 15, c = e & 3;
+    const float v = T1s[e] + (((P2[e] + P2[4096 + e]) + P2[8192 + e]) + P2[12288 + e]);
+    P.gT[((size_t)(r0 + rl) * M + b) * 4 + c] = v;
+  }
+}
+
+bool fit_bf_supported(int M, int m2, int N) {
+  return m2 == 16 && M >= 16 && M % 4 == 0 && N >= 16 && N % 16 == 0 && N <= 256;
+}
+
+void launch_fit_bf(const FitArgs& F, hipStream_t st) {
+  const int parts = F.prec == PREC_BF16X3 ? 2 : 1;
+  FitBfArgs P{};
+  P.M = F.m.M;
+  P.N = F.fw;
+  P.nfit = F.nfit;
+  P.ntypes = F.m.ntypes;
+  P.nrows = F.nrows;
+  P.type_row0 = F.type_row0;
+  P.row_atom = F.row_atom;
+  P.T = (const float*)F.T;
+  P.Wf = F.Wf;
+  P.bias = F.b;
+  P.wo = F.wo;
+  P.bo = F.bo;
+  P.t1 = (float*)F.xs;
+  P.act = (float*)F.act;
+  P.d1f = (__bf16*)F.Dg;
+  P.Ei = F.Ei;
+  P.gT = (float*)F.gT;
+  const dim3 grid((F.nrows + FR - 1) / FR), block(FT);
+  const size_t sh_tail = fit_tail_lds(parts), sh_bwd = fit_l1_bwd_lds(parts);
+  if (parts == 2) {
+    (void)hipFuncSetAttribute((const void*)k_fit_tail<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_tail);
+    (void)hipFuncSetAttribute((const void*)k_fit_l1_bwd<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_bwd);
+    hipLaunchKernelGGL(k_fit_l1_fwd<2>, grid, block, 0, st, P);
+    hipLaunchKernelGGL(k_fit_tail<2>, grid, block, sh_tail, st, P);
+    hipLaunchKernelGGL(k_fit_l1_bwd<2>, grid, block, sh_bwd, st, P);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_fit_tail<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_tail);
+    (void)hipFuncSetAttribute((const void*)k_fit_l1_bwd<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_bwd);
+    hipLaunchKernelGGL(k_fit_l1_fwd<1>, grid, block, 0, st, P);
+    hipLaunchKernelGGL(k_fit_tail<1>, grid, block, sh_tail, st, P);
+    hipLaunchKernelGGL(k_fit_l1_bwd<1>, grid, block, sh_bwd, st, P);
+  }
+}
+
+}  // namespace dp

@@ -147,6 +147,9 @@ struct FitArgs {
   // BF16 modes: GEMM operands per species and layer, [(species * nfit + k) * 4 + dir * 2 + part]
   // with dir 0 = W^T [out][in] (forward), dir 1 = W [in][out] (adjoint), part 0 hi, 1 lo
   const void* const* Wb;
+  // BF16 modes: the same weights as MFMA operand fragments, [(species * nfit + k) * 2 + dir]
+  // (dir 0 forward, 1 adjoint), used by the 64-row-tile kernels when fit_bf_supported()
+  const void* const* Wf;
   const double* bo;      // [ntypes] device
   void *D, *Dg;        // [nrows][M*m2]
   void* act;           // [nfit][nrows][fw]  tanh outputs
@@ -155,6 +158,8 @@ struct FitArgs {
   double* Ei;          // [nrows]
 };
 void launch_fit(const FitArgs& a, hipStream_t st);
+bool fit_bf_supported(int M, int m2, int N);
+void launch_fit_bf(const FitArgs& a, hipStream_t st);
 
 // ---------------------------------------------------------------- reductions, MD
 void launch_zero(double* p, size_t n, hipStream_t st);
