@@ -4,8 +4,9 @@
 // one 64-row tile and one species' fitting net.  The MFMA runs with the weights as the
 // A operand (16 outputs x 32 k) and the activations as the B operand (32 k x 16 rows): a
 // lane of the result holds 4 consecutive outputs n = 16 ct + 4 g + q of one row 16 rt + rb
-// (rb = lane % 16, g = lane / 16).  Wave w of the 4 owns the output tiles ct = w + 4 u
-// for all four row tiles rt.
+// (rb = lane % 16, g = lane / 16).  Wave w of the 8 owns the output tiles ct = w and
+// w + 8 for all four row tiles rt; two waves share each SIMD, so one's epilogue and
+// waits overlap the other's products.
 //
 // Weights are pre-packed as MFMA fragments (block (ct, ks, part) of 64 lanes x 8 bf16,
 // lane l holding B[32 ks + 8 (l / 16) + j][16 ct + l % 16], B = W for the forward and
@@ -29,7 +30,9 @@
 namespace dp {
 
 constexpr int FR = 64;    // rows per workgroup
-constexpr int FT = 256;   // threads per workgroup (4 waves)
+constexpr int FW = 8;     // waves per workgroup
+constexpr int FT = 64 * FW;
+constexpr int kKS = 8;    // k steps of operands whose k dimension is a fitting width (<= 256, padded)
 
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
@@ -73,6 +76,14 @@ __device__ __forceinline__ void wfrag(const __bf16* __restrict__ W, int KS, int 
   l = PARTS == 2 ? gld<bf8>(p + 512) : h;
 }
 
+// the wave's two column tiles w and w + 8 at k step ks (operands padded to 16 tiles)
+template <int PARTS>
+__device__ __forceinline__ void load_wc(const __bf16* __restrict__ W, int KS, int ks, int w, int lane, bf8 (&wh)[2],
+                                        bf8 (&wl)[2]) {
+  wfrag<PARTS>(W, KS, w, ks, lane, wh[0], wl[0]);
+  wfrag<PARTS>(W, KS, w + 8, ks, lane, wh[1], wl[1]);
+}
+
 // Activation fragments: the value of row 16 rt + rb at n = 16 ct + 4 g + q sits in
 // fragment (ks = ct / 2, rt), lane rb + 16 (2 (ct % 2) + g / 2), element 4 (g % 2) + q.
 __device__ __forceinline__ int xfrag_off(int ct, int rt, int part, int parts, int rb, int g) {
@@ -81,35 +92,39 @@ __device__ __forceinline__ int xfrag_off(int ct, int rt, int part, int parts, in
 }
 
 template <int PARTS>
-__device__ __forceinline__ void put4(__bf16* X, int ct, int rt, int rb, int g, f4v v) {
-  bf4 h, l;
+__device__ __forceinline__ void split4(f4v v, bf4& h, bf4& l) {
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     const __bf16 hv = (__bf16)v[q];
     h[q] = hv;
     if (PARTS == 2) l[q] = (__bf16)(v[q] - (float)hv);
   }
+}
+
+template <int PARTS>
+__device__ __forceinline__ void put4(__bf16* X, int ct, int rt, int rb, int g, f4v v) {
+  bf4 h, l;
+  split4<PARTS>(v, h, l);
   *(bf4*)(X + xfrag_off(ct, rt, 0, PARTS, rb, g)) = h;
   if (PARTS == 2) *(bf4*)(X + xfrag_off(ct, rt, 1, PARTS, rb, g)) = l;
 }
 
 // stage a [u][rt] register tile (C layout of the wave's column tiles) into LDS fragments
 template <int PARTS>
-__device__ __forceinline__ void stage_tile(__bf16* Xs, const f4v (&v)[4][4], int w, int NT, int rb, int g) {
+__device__ __forceinline__ void stage_tile(__bf16* Xs, const f4v (&v)[2][4], int w, int NT, int rb, int g) {
 #pragma unroll
-  for (int u = 0; u < 4; u++) {
-    const int ct = w + 4 * u;
+  for (int u = 0; u < 2; u++) {
+    const int ct = w + 8 * u;
     if (ct >= NT) continue;
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) put4<PARTS>(Xs, ct, rt, rb, g, v[u][rt]);
   }
 }
 
-// acc[u][rt] += sum_ks W(ct_u, ks) X(ks, rt); W from global (one fragment step ahead),
-// X from LDS
+// acc[u][rt] += W(ct_u) X(rt) for one k step; X fragments of the step from LDS
 template <int PARTS>
-__device__ __forceinline__ void mma_step(const bf8 (&wh)[4], const bf8 (&wl)[4], const __bf16* Xs, int ks, int lane,
-                                         f4v (&acc)[4][4]) {
+__device__ __forceinline__ void mma_step(const bf8 (&wh)[2], const bf8 (&wl)[2], const __bf16* Xs, int ks, int lane,
+                                         f4v (&acc)[2][4]) {
   bf8 xh[4], xl[4];
 #pragma unroll
   for (int rt = 0; rt < 4; rt++) {
@@ -118,48 +133,40 @@ __device__ __forceinline__ void mma_step(const bf8 (&wh)[4], const bf8 (&wl)[4],
     xl[rt] = PARTS == 2 ? *(const bf8*)(p + 512) : xh[rt];
   }
 #pragma unroll
-  for (int u = 0; u < 4; u++)
+  for (int u = 0; u < 2; u++)
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) acc[u][rt] = mfma_split<PARTS>(wh[u], wl[u], xh[rt], xl[rt], acc[u][rt]);
 }
 
-// the wave's four column tiles w + 4 u of k step ks (operands padded to 16 column tiles)
-template <int PARTS>
-__device__ __forceinline__ void load_w4(const __bf16* __restrict__ W, int KS, int ks, int w, int lane,
-                                        bf8 (&wh)[4], bf8 (&wl)[4]) {
-#pragma unroll
-  for (int u = 0; u < 4; u++) wfrag<PARTS>(W, KS, w + 4 * u, ks, lane, wh[u], wl[u]);
-}
-
-// k steps of the operands whose k dimension is a fitting-layer width (<= 256, padded)
-constexpr int kKS = 8;
-
+// acc += W X over the kKS steps of a square layer; weights fetched one step ahead
 template <int PARTS>
 __device__ __forceinline__ void tile_mm(const __bf16* __restrict__ W, int w, int lane, const __bf16* Xs,
-                                        f4v (&acc)[4][4]) {
-  bf8 wh[2][4], wl[2][4];
-  load_w4<PARTS>(W, kKS, 0, w, lane, wh[0], wl[0]);
+                                        f4v (&acc)[2][4]) {
+  bf8 wh[2][2], wl[2][2];
+  load_wc<PARTS>(W, kKS, 0, w, lane, wh[0], wl[0]);
 #pragma unroll
   for (int ks = 0; ks < kKS; ks++) {
-    if (ks + 1 < kKS) load_w4<PARTS>(W, kKS, ks + 1, w, lane, wh[(ks + 1) & 1], wl[(ks + 1) & 1]);
+    if (ks + 1 < kKS) load_wc<PARTS>(W, kKS, ks + 1, w, lane, wh[(ks + 1) & 1], wl[(ks + 1) & 1]);
     __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's products
     mma_step<PARTS>(wh[ks & 1], wl[ks & 1], Xs, ks, lane, acc);
   }
 }
 
-__device__ __forceinline__ void zero_tile(f4v (&a)[4][4]) {
+template <int U>
+__device__ __forceinline__ void zero_tile(f4v (&a)[U][4]) {
 #pragma unroll
-  for (int u = 0; u < 4; u++)
+  for (int u = 0; u < U; u++)
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) a[u][rt] = f4v{0.f, 0.f, 0.f, 0.f};
 }
 
 // ------------------------------------------------------------------------------------
-// first layer forward: t1 = tanh(D W1 + b1), K = 16 M consumed 32 at a time.  Thread
-// (w, lane) forms the D fragment slot of row 16 w + rb for the k step: 8 values
-// D[row][a][b], a = 2 s + g / 2, b = 8 (g % 2) + j, from T[row][a] and T<[row][b] (held
-// in registers for the whole loop); D slices are double-buffered in LDS, one barrier per
-// step, and the wave's weight fragments are fetched one step ahead.
+// first layer forward: t1 = tanh(D W1 + b1), K = 16 M consumed 32 at a time.  The D
+// fragment slot of row 16 dr + rb (dr = w % 4) for a k step holds D[row][a][b] with
+// a = 2 s + g / 2, b = 8 (g % 2) + j; wave w forms its half j = 4 (w / 4) .. + 3 from
+// T[row][a] and T<[row][b] (in registers for the whole loop).  D slices are
+// double-buffered in LDS with one barrier per step; the wave's weight fragments are
+// fetched one step ahead.
 // ------------------------------------------------------------------------------------
 template <int PARTS>
 __global__ __launch_bounds__(FT) void k_fit_l1_fwd(FitBfArgs P) {
@@ -170,56 +177,58 @@ __global__ __launch_bounds__(FT) void k_fit_l1_fwd(FitBfArgs P) {
   const int M = P.M, KS = M / 2, N = P.N, NT = N / 16;
   const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, rb = lane & 15,
             g = lane >> 4;
-  const int row = r0 + 16 * w + rb;
+  const int dr = w & 3, dh = w >> 2;
+  const int row = r0 + 16 * dr + rb;
   const bool real = P.row_atom[row] >= 0;
   const float* Tr = P.T + (size_t)row * M * 4;
   const f4v z4 = {0.f, 0.f, 0.f, 0.f};
-  f4v tl[8];
+  f4v tl[4];
 #pragma unroll
-  for (int j = 0; j < 8; j++) {
-    tl[j] = *(const f4v*)(Tr + 4 * (8 * (g & 1) + j));   // pad rows: loaded, then zeroed
+  for (int j = 0; j < 4; j++) {
+    tl[j] = *(const f4v*)(Tr + 4 * (8 * (g & 1) + 4 * dh + j));   // pad rows: loaded, then zeroed
     if (!real) tl[j] = z4;
   }
   const __bf16* W = (const __bf16*)P.Wf[(sp * P.nfit) * 2];
-  f4v acc[4][4];
+  f4v acc[2][4];
   zero_tile(acc);
-  bf8 ah[4], al[4], bh[4], bl[4];
+  bf8 ah[2], al[2], bh[2], bl[2];
   f4v ta;
+  __bf16* dslot = &Ds[0][0] + (dr * PARTS) * 512 + lane * 8 + 4 * dh;
 #define L1_LOAD_T(S_) ta = *(const f4v*)(Tr + 4 * (2 * (S_) + (g >> 1)))
 #define L1_FORM_D(BUF_)                                                                           \
   do {                                                                                            \
-    float d_[8];                                                                                  \
     const f4v tv_ = real ? ta : z4;                                                               \
-    _Pragma("unroll") for (int j = 0; j < 8; j++) d_[j] =                                         \
+    f4v d_;                                                                                       \
+    _Pragma("unroll") for (int j = 0; j < 4; j++) d_[j] =                                         \
         tv_[0] * tl[j][0] + tv_[1] * tl[j][1] + tv_[2] * tl[j][2] + tv_[3] * tl[j][3];            \
-    bf8 h_, l_;                                                                                   \
-    split8<PARTS>(d_, h_, l_);                                                                    \
-    *(bf8*)(&Ds[BUF_][(w * PARTS) * 512 + lane * 8]) = h_;                                        \
-    if (PARTS == 2) *(bf8*)(&Ds[BUF_][(w * PARTS + 1) * 512 + lane * 8]) = l_;                    \
+    bf4 h_, l_;                                                                                   \
+    split4<PARTS>(d_, h_, l_);                                                                    \
+    *(bf4*)(dslot + (BUF_) * 4 * PARTS * 512) = h_;                                               \
+    if (PARTS == 2) *(bf4*)(dslot + (BUF_) * 4 * PARTS * 512 + 512) = l_;                         \
   } while (0)
-  // KS is even; fetches past the last step are clamped to it (harmless repeats), so
-  // no load sits behind a branch and the wait counts stay exact
-  // issue order as in the loop (T of the next step, then the b fragments), so that the
-  // wait counts at the loop head agree on both incoming paths
+  // KS is even; fetches past the last step are clamped to it (harmless repeats), so no
+  // load sits behind a branch and the wait counts stay exact.  The prologue issues in
+  // the loop's order (T of the next step, then the b fragments), so that the wait
+  // counts at the loop head agree on both incoming paths.
   L1_LOAD_T(0);
-  load_w4<PARTS>(W, KS, 0, w, lane, ah, al);
+  load_wc<PARTS>(W, KS, 0, w, lane, ah, al);
   L1_FORM_D(0);
   L1_LOAD_T(1);
   __builtin_amdgcn_sched_barrier(0);
-  load_w4<PARTS>(W, KS, 1, w, lane, bh, bl);
+  load_wc<PARTS>(W, KS, 1, w, lane, bh, bl);
   __syncthreads();
   for (int s = 0; s < KS; s += 2) {
     const int s2 = min(s + 2, KS - 1), s3 = min(s + 3, KS - 1);
     mma_step<PARTS>(ah, al, Ds[0], 0, lane, acc);
     __builtin_amdgcn_sched_barrier(0);
-    load_w4<PARTS>(W, KS, s2, w, lane, ah, al);
+    load_wc<PARTS>(W, KS, s2, w, lane, ah, al);
     __builtin_amdgcn_sched_barrier(0);   // the fetch two steps ahead stays here
     L1_FORM_D(1);   // step s + 1
     L1_LOAD_T(s2);
     __syncthreads();
     mma_step<PARTS>(bh, bl, Ds[1], 0, lane, acc);
     __builtin_amdgcn_sched_barrier(0);
-    load_w4<PARTS>(W, KS, s3, w, lane, bh, bl);
+    load_wc<PARTS>(W, KS, s3, w, lane, bh, bl);
     __builtin_amdgcn_sched_barrier(0);
     L1_FORM_D(0);   // step s + 2 (unused after the last step)
     L1_LOAD_T(s3);
@@ -229,8 +238,8 @@ __global__ __launch_bounds__(FT) void k_fit_l1_fwd(FitBfArgs P) {
 #undef L1_FORM_D
   const float* bias = (const float*)P.bias[sp * P.nfit];
 #pragma unroll
-  for (int u = 0; u < 4; u++) {
-    const int ct = w + 4 * u;
+  for (int u = 0; u < 2; u++) {
+    const int ct = w + 8 * u;
     if (ct >= NT) continue;
     const f4v bv = gld<f4v>(bias + 16 * ct + 4 * g);
 #pragma unroll
@@ -246,7 +255,7 @@ __global__ __launch_bounds__(FT) void k_fit_l1_fwd(FitBfArgs P) {
 // ------------------------------------------------------------------------------------
 // square layers, output and the adjoint back to the first layer
 // ------------------------------------------------------------------------------------
-size_t fit_tail_lds(int parts) { return (size_t)kKS * 4 * parts * 1024 + 4 * 64 * 8; }
+size_t fit_tail_lds(int parts) { return (size_t)kKS * 4 * parts * 1024 + FW * 64 * 8; }
 
 template <int PARTS>
 __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
@@ -262,16 +271,16 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
   // the k >= N tail of the last fragment step stays zero
   for (int q = tid; q < kKS * 4 * PARTS * 64; q += FT) ((u32x4v*)Xs)[q] = u32x4v{0u, 0u, 0u, 0u};
   const f4v z4 = {0.f, 0.f, 0.f, 0.f};
-  f4v x[4][4];
+  f4v x[2][4];
 #pragma unroll
-  for (int u = 0; u < 4; u++) {
-    const int ct = w + 4 * u;
+  for (int u = 0; u < 2; u++) {
+    const int ct = w + 8 * u;
 #pragma unroll
     for (int rt = 0; rt < 4; rt++)
       x[u][rt] = ct < NT ? *(const f4v*)(P.t1 + (size_t)(r0 + 16 * rt + rb) * N + 16 * ct + 4 * g) : z4;
   }
   const size_t lstride = (size_t)P.nrows * N;
-  f4v acc[4][4];
+  f4v acc[2][4];
   for (int k = 1; k < P.nfit; k++) {
     __syncthreads();
     stage_tile<PARTS>(Xs, x, w, NT, rb, g);
@@ -281,8 +290,8 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
     const float* bias = (const float*)P.bias[sp * P.nfit + k];
     float* ak = P.act + k * lstride + (size_t)r0 * N;
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int ct = w + 4 * u;
+    for (int u = 0; u < 2; u++) {
+      const int ct = w + 8 * u;
       if (ct >= NT) continue;
       const f4v bv = gld<f4v>(bias + 16 * ct + 4 * g);
 #pragma unroll
@@ -297,12 +306,12 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
   }
   // E_i = x . w_o + b_o, FP64 sums
   const float* wo = (const float*)P.wo[sp];
-  f4v wv[4];
+  f4v wv[2];
 #pragma unroll
-  for (int u = 0; u < 4; u++) wv[u] = w + 4 * u < NT ? gld<f4v>(wo + 16 * (w + 4 * u) + 4 * g) : z4;
+  for (int u = 0; u < 2; u++) wv[u] = w + 8 * u < NT ? gld<f4v>(wo + 16 * (w + 8 * u) + 4 * g) : z4;
   double e[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int u = 0; u < 4; u++)
+  for (int u = 0; u < 2; u++)
 #pragma unroll
     for (int rt = 0; rt < 4; rt++)
 #pragma unroll
@@ -318,23 +327,25 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
   __syncthreads();
   if (tid < 64) {
     const int row = r0 + tid;
-    P.Ei[row] = P.row_atom[row] >= 0 ? red[tid] + red[64 + tid] + red[128 + tid] + red[192 + tid] + P.bo[sp] : 0.0;
+    double s = 0.0;
+    for (int v = 0; v < FW; v++) s += red[v * 64 + tid];
+    P.Ei[row] = P.row_atom[row] >= 0 ? s + P.bo[sp] : 0.0;
   }
   // adjoint: g_L = w_o; g_{k-1} = g_k + (g_k (1 - t_k^2)) W_k^T
-  f4v gr[4][4];
+  f4v gr[2][4];
 #pragma unroll
-  for (int u = 0; u < 4; u++)
+  for (int u = 0; u < 2; u++)
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) gr[u][rt] = wv[u];
   for (int k = P.nfit - 1; k >= 1; k--) {
     const float* ak = P.act + k * lstride + (size_t)r0 * N;
-    f4v d[4][4];
+    f4v d[2][4];
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int ct = w + 4 * u;
+    for (int u = 0; u < 2; u++) {
+      const int ct = w + 8 * u;
 #pragma unroll
       for (int rt = 0; rt < 4; rt++) {
-        f4v t = ct < NT ? *(const f4v*)(ak + ((size_t)(ct * 4 + rt) * 64 + lane) * 4) : z4;
+        const f4v t = ct < NT ? *(const f4v*)(ak + ((size_t)(ct * 4 + rt) * 64 + lane) * 4) : z4;
         d[u][rt] = gr[u][rt] * (1.f - t * t);
       }
     }
@@ -344,19 +355,19 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
     zero_tile(acc);
     tile_mm<PARTS>((const __bf16*)P.Wf[(sp * P.nfit + k) * 2 + 1], w, lane, Xs, acc);
 #pragma unroll
-    for (int u = 0; u < 4; u++)
+    for (int u = 0; u < 2; u++)
 #pragma unroll
       for (int rt = 0; rt < 4; rt++) gr[u][rt] += acc[u][rt];
   }
   // d1 = g1 (1 - t1^2) as fragments for the first layer's adjoint; pad rows and the
-  // k >= N tail are zero
+  // k >= N tail are zero (ct runs over all 2 kKS = 16 tiles)
   __bf16* out = P.d1f + (size_t)blockIdx.x * kKS * 4 * PARTS * 512;
   bool real[4];
 #pragma unroll
   for (int rt = 0; rt < 4; rt++) real[rt] = P.row_atom[r0 + 16 * rt + rb] >= 0;
 #pragma unroll
-  for (int u = 0; u < 4; u++) {
-    const int ct = w + 4 * u;
+  for (int u = 0; u < 2; u++) {
+    const int ct = w + 8 * u;
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) {
       f4v v = z4;
@@ -375,10 +386,10 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
 //   dE/dT[row][a][c]  = sum_b dD[row][a][b] T[row][b][c]     (sum over q in the lane, then
 //                                                               a reduce-scatter over g)
 //   dE/dT[row][b][c] += sum_a dD[row][a][b] T[row][a][c]     (b < 16; accumulated per lane
-//                                                               over the wave's a, the four
+//                                                               over the wave's a, the
 //                                                               waves' parts added in order)
-// Wave w takes the a range [w ceil(M/4), (w+1) ceil(M/4)), two a per pass; d1 fragments
-// sit in LDS, the wave's weight fragments are fetched one step ahead.
+// Wave w takes an even-sized a range, two a per pass; d1 fragments and T< sit in LDS, the
+// wave's weight fragments are fetched one step ahead.
 // ------------------------------------------------------------------------------------
 constexpr int kTlStride = 68;   // floats per row of the staged T< (bank spread)
 
@@ -396,7 +407,7 @@ __device__ __forceinline__ void load_w2(const __bf16* __restrict__ W, int a, int
 }
 
 template <int PARTS>
-__global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_fit_l1_bwd(FitBfArgs P) {
+__global__ __launch_bounds__(FT) void k_fit_l1_bwd(FitBfArgs P) {
   extern __shared__ __align__(16) char smem[];
   const int M = P.M;
   const size_t xs_bytes = (size_t)kKS * 4 * PARTS * 1024, p2_bytes = (size_t)4 * 64 * 64 * 4;
@@ -436,16 +447,11 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     for (int q = 0; q < 4; q++) p2[rt][q] = z4;
   const __bf16* W = (const __bf16*)P.Wf[(sp * P.nfit) * 2 + 1];
   // a range of this wave: an even count (M is even), two tiles per pass
-  const int per0 = (M + 3) / 4, per = per0 + (per0 & 1);
+  const int per0 = (M + FW - 1) / FW, per = per0 + (per0 & 1);
   const int a0 = min(M, w * per), a1 = min(M, a0 + per);
   __syncthreads();
-  // weight fragments, fetched two k steps ahead into a ring of four (kKS is a multiple
-  // of four, so every pass starts at buffer 0)
-  bf8 wh[4][2], wl[4][2];
-  if (a0 < a1) {
-    load_w2<PARTS>(W, a0, 0, lane, wh[0], wl[0]);
-    load_w2<PARTS>(W, a0, 1, lane, wh[1], wl[1]);
-  }
+  bf8 wh[2][2], wl[2][2];   // [buffer][tile of the pair]
+  if (a0 < a1) load_w2<PARTS>(W, a0, 0, lane, wh[0], wl[0]);
   for (int a = a0; a < a1; a += 2) {
     const int an = min(a + 2, a1 - 2);   // next pass (the last pass repeats itself)
     f4v acc[2][4], tav[2][4];
@@ -458,9 +464,9 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
       }
 #pragma unroll
     for (int ks = 0; ks < kKS; ks++) {
-      const int nb = (ks + 2) & 3;
-      if (ks + 2 < kKS) load_w2<PARTS>(W, a, ks + 2, lane, wh[nb], wl[nb]);
-      else load_w2<PARTS>(W, an, ks + 2 - kKS, lane, wh[nb], wl[nb]);
+      const int nb = (ks + 1) & 1;   // kKS is even: every pass starts at buffer 0
+      if (ks + 1 < kKS) load_w2<PARTS>(W, a, ks + 1, lane, wh[nb], wl[nb]);
+      else load_w2<PARTS>(W, an, 0, lane, wh[nb], wl[nb]);
       __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's products
       bf8 xh[4], xl[4];
 #pragma unroll
@@ -473,7 +479,7 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
       for (int c = 0; c < 2; c++)
 #pragma unroll
         for (int rt = 0; rt < 4; rt++)
-          acc[c][rt] = mfma_split<PARTS>(wh[ks & 3][c], wl[ks & 3][c], xh[rt], xl[rt], acc[c][rt]);
+          acc[c][rt] = mfma_split<PARTS>(wh[ks & 1][c], wl[ks & 1][c], xh[rt], xl[rt], acc[c][rt]);
     }
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) {
@@ -502,11 +508,24 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
       }
     }
   }
+  // second-term parts of the 8 waves, added in a fixed order: waves 4..7 hand theirs to
+  // waves 0..3, which then hand the pair sums to the final pass
+  float* mine = P2 + (size_t)(w & 3) * 4096;
   __syncthreads();   // every read of the d1 fragments is done; P2 reuses that space
+  if (w >= 4)
 #pragma unroll
-  for (int rt = 0; rt < 4; rt++)
+    for (int rt = 0; rt < 4; rt++)
 #pragma unroll
-    for (int q = 0; q < 4; q++) *(f4v*)(P2 + ((w * 64 + 16 * rt + rb) * 16 + 4 * g + q) * 4) = p2[rt][q];
+      for (int q = 0; q < 4; q++) *(f4v*)(mine + ((16 * rt + rb) * 16 + 4 * g + q) * 4) = p2[rt][q];
+  __syncthreads();
+  if (w < 4)
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        f4v* p = (f4v*)(mine + ((16 * rt + rb) * 16 + 4 * g + q) * 4);
+        *p = p2[rt][q] + *p;
+      }
   __syncthreads();
   for (int e = tid; e < 64 * 64; e += FT) {
     const int rl = e >> 6, b = (e >> 2) & 15, c = e & 3;

@@ -76,6 +76,20 @@ def test_nlist_dense_second_pass_bit_exact(dp, copper_model):
     assert _frel(F.cpu().numpy(), r["F"]) < 1e-9
 
 
+def test_nlist_perfect_lattice_ties_bit_exact(dp, copper_model):
+    """Unjittered FCC copper: whole neighbour shells share one r^2, so the formatting's
+    fast ranking by quantised r^2 sees ties and must fall back to the exact key
+    (species, r^2, owner, image); the list is still bit-exact against the oracle."""
+    c, t, b = I.copper_fcc(4, 3.634, 1, sigma=0.0)
+    m = dp.DPModel(copper_model)
+    nl, img, nn, rc = m.nlist(c, t, b)
+    onl, oimg, onn, _ = Oracle(copper_model).nlist(c, t, b)
+    assert onn.max() <= 256
+    assert np.array_equal(nl.cpu().numpy(), onl)
+    assert np.array_equal(img.cpu().numpy(), oimg)
+    assert np.array_equal(nn.cpu().numpy(), onn)
+
+
 def test_nlist_water192_bit_exact(dp, water_model, water192):
     c, t, b = water192
     m = dp.DPModel(water_model)
