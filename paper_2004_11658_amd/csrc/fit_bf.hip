@@ -121,34 +121,63 @@ __device__ __forceinline__ void stage_tile(__bf16* Xs, const f4v (&v)[2][4], int
   }
 }
 
-// acc[u][rt] += W(ct_u) X(rt) for one k step; X fragments of the step from LDS
+// X fragments (all four row tiles) of k step ks from LDS
 template <int PARTS>
-__device__ __forceinline__ void mma_step(const bf8 (&wh)[2], const bf8 (&wl)[2], const __bf16* Xs, int ks, int lane,
-                                         f4v (&acc)[2][4]) {
-  bf8 xh[4], xl[4];
+__device__ __forceinline__ void load_x(const __bf16* Xs, int ks, int lane, bf8 (&xh)[4], bf8 (&xl)[4]) {
 #pragma unroll
   for (int rt = 0; rt < 4; rt++) {
     const __bf16* p = Xs + ((size_t)(ks * 4 + rt) * PARTS) * 512 + lane * 8;
     xh[rt] = *(const bf8*)p;
     xl[rt] = PARTS == 2 ? *(const bf8*)(p + 512) : xh[rt];
   }
-#pragma unroll
-  for (int u = 0; u < 2; u++)
-#pragma unroll
-    for (int rt = 0; rt < 4; rt++) acc[u][rt] = mfma_split<PARTS>(wh[u], wl[u], xh[rt], xl[rt], acc[u][rt]);
 }
 
-// acc += W X over the kKS steps of a square layer; weights fetched one step ahead
+// acc[u][rt] += W(ct_u) X(rt) for one k step.  The split products go in three sweeps
+// over the accumulators (lo hi, hi lo, then hi hi: the same order per accumulator as
+// mfma_split), so that dependent products on one accumulator are never adjacent.
+template <int PARTS, int U>
+__device__ __forceinline__ void mma_sweeps(const bf8 (&wh)[U], const bf8 (&wl)[U], const bf8 (&xh)[4],
+                                           const bf8 (&xl)[4], f4v (&acc)[U][4]) {
+  if (PARTS == 2) {
+#pragma unroll
+    for (int u = 0; u < U; u++)
+#pragma unroll
+      for (int rt = 0; rt < 4; rt++) acc[u][rt] = mfma_bf(wl[u], xh[rt], acc[u][rt]);
+#pragma unroll
+    for (int u = 0; u < U; u++)
+#pragma unroll
+      for (int rt = 0; rt < 4; rt++) acc[u][rt] = mfma_bf(wh[u], xl[rt], acc[u][rt]);
+  }
+#pragma unroll
+  for (int u = 0; u < U; u++)
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) acc[u][rt] = mfma_bf(wh[u], xh[rt], acc[u][rt]);
+}
+
+template <int PARTS>
+__device__ __forceinline__ void mma_step(const bf8 (&wh)[2], const bf8 (&wl)[2], const __bf16* Xs, int ks, int lane,
+                                         f4v (&acc)[2][4]) {
+  bf8 xh[4], xl[4];
+  load_x<PARTS>(Xs, ks, lane, xh, xl);
+  mma_sweeps<PARTS, 2>(wh, wl, xh, xl, acc);
+}
+
+// acc += W X over the kKS steps of a square layer; weights and X fragments fetched one
+// step ahead
 template <int PARTS>
 __device__ __forceinline__ void tile_mm(const __bf16* __restrict__ W, int w, int lane, const __bf16* Xs,
                                         f4v (&acc)[2][4]) {
-  bf8 wh[2][2], wl[2][2];
+  bf8 wh[2][2], wl[2][2], xh[2][4], xl[2][4];
   load_wc<PARTS>(W, kKS, 0, w, lane, wh[0], wl[0]);
+  load_x<PARTS>(Xs, 0, lane, xh[0], xl[0]);
 #pragma unroll
   for (int ks = 0; ks < kKS; ks++) {
-    if (ks + 1 < kKS) load_wc<PARTS>(W, kKS, ks + 1, w, lane, wh[(ks + 1) & 1], wl[(ks + 1) & 1]);
+    if (ks + 1 < kKS) {
+      load_wc<PARTS>(W, kKS, ks + 1, w, lane, wh[(ks + 1) & 1], wl[(ks + 1) & 1]);
+      load_x<PARTS>(Xs, ks + 1, lane, xh[(ks + 1) & 1], xl[(ks + 1) & 1]);
+    }
     __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's products
-    mma_step<PARTS>(wh[ks & 1], wl[ks & 1], Xs, ks, lane, acc);
+    mma_sweeps<PARTS, 2>(wh[ks & 1], wl[ks & 1], xh[ks & 1], xl[ks & 1], acc);
   }
 }
 
@@ -391,6 +420,21 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
 // Wave w takes an even-sized a range, two a per pass; d1 fragments and T< sit in LDS, the
 // wave's weight fragments are fetched one step ahead.
 // ------------------------------------------------------------------------------------
+// Reduce-scatter of four values over the four lane groups g (lanes rb + 16 g): returns
+// in lane group g the sum over g' of v[g] held by group g'.  v_permlane32_swap trades
+// the upper half of its first operand with the lower half of its second, so summing
+// the swapped (v0, v2) pair leaves component 0 summed over g, g + 2 in lanes < 32 and
+// component 2 in lanes >= 32 (likewise (v1, v3)); v_permlane16_swap then trades the odd
+// rows of the first operand with the even rows of the second, finishing the sum.
+__device__ __forceinline__ float rs4(f4v v) {
+  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[0]), __float_as_uint(v[2]), false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[1]), __float_as_uint(v[3]), false, false);
+  const float k0 = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  const float k1 = __uint_as_float(b[0]) + __uint_as_float(b[1]);
+  const auto c = __builtin_amdgcn_permlane16_swap(__float_as_uint(k0), __float_as_uint(k1), false, false);
+  return __uint_as_float(c[0]) + __uint_as_float(c[1]);
+}
+
 constexpr int kTlStride = 68;   // floats per row of the staged T< (bank spread)
 
 size_t fit_l1_bwd_lds(int parts) {
@@ -451,7 +495,9 @@ __global__ __launch_bounds__(FT) void k_fit_l1_bwd(FitBfArgs P) {
   const int a0 = min(M, w * per), a1 = min(M, a0 + per);
   __syncthreads();
   bf8 wh[2][2], wl[2][2];   // [buffer][tile of the pair]
+  bf8 xh[2][4], xl[2][4];   // [buffer][row tile]
   if (a0 < a1) load_w2<PARTS>(W, a0, 0, lane, wh[0], wl[0]);
+  load_x<PARTS>(Xs, 0, lane, xh[0], xl[0]);
   for (int a = a0; a < a1; a += 2) {
     const int an = min(a + 2, a1 - 2);   // next pass (the last pass repeats itself)
     f4v acc[2][4], tav[2][4];
@@ -467,19 +513,9 @@ __global__ __launch_bounds__(FT) void k_fit_l1_bwd(FitBfArgs P) {
       const int nb = (ks + 1) & 1;   // kKS is even: every pass starts at buffer 0
       if (ks + 1 < kKS) load_w2<PARTS>(W, a, ks + 1, lane, wh[nb], wl[nb]);
       else load_w2<PARTS>(W, an, 0, lane, wh[nb], wl[nb]);
+      load_x<PARTS>(Xs, (ks + 1) % kKS, lane, xh[nb], xl[nb]);
       __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's products
-      bf8 xh[4], xl[4];
-#pragma unroll
-      for (int rt = 0; rt < 4; rt++) {
-        const __bf16* p = Xs + ((size_t)(ks * 4 + rt) * PARTS) * 512 + lane * 8;
-        xh[rt] = *(const bf8*)p;
-        xl[rt] = PARTS == 2 ? *(const bf8*)(p + 512) : xh[rt];
-      }
-#pragma unroll
-      for (int c = 0; c < 2; c++)
-#pragma unroll
-        for (int rt = 0; rt < 4; rt++)
-          acc[c][rt] = mfma_split<PARTS>(wh[ks & 1][c], wl[ks & 1][c], xh[rt], xl[rt], acc[c][rt]);
+      mma_sweeps<PARTS, 2>(wh[ks & 1], wl[ks & 1], xh[ks & 1], xl[ks & 1], acc);
     }
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) {
@@ -492,13 +528,7 @@ __global__ __launch_bounds__(FT) void k_fit_l1_bwd(FitBfArgs P) {
         // first term: sum over b = 4 g + q (in the lane, then over g by a reduce-scatter
         // that leaves component c = g in lane group g)
         const f4v pv = cv[0] * tl[0] + cv[1] * tl[1] + cv[2] * tl[2] + cv[3] * tl[3];
-        const bool lo2 = g < 2, ev = (g & 1) == 0;
-        float k0 = lo2 ? pv[0] : pv[2], k1 = lo2 ? pv[1] : pv[3];
-        const float s0 = lo2 ? pv[2] : pv[0], s1 = lo2 ? pv[3] : pv[1];
-        k0 += __shfl_xor(s0, 32);
-        k1 += __shfl_xor(s1, 32);
-        float kk = ev ? k0 : k1;
-        kk += __shfl_xor(ev ? k1 : k0, 16);
+        const float kk = rs4(pv);
         if (a + c >= 16) P.gT[((size_t)(r0 + 16 * rt + rb) * M + a + c) * 4 + g] = kk;
         else T1s[((16 * rt + rb) * 16 + a + c) * 4 + g] = kk;
         // second term, accumulated over the wave's a

@@ -374,10 +374,14 @@ struct NlEnt {
   unsigned long long hi, lo;
 };
 
-// LDS rows of one wave
+// LDS rows of one wave.  k holds a 32-bit key per candidate, species << 28 | r^2
+// quantised to 28 bits (floor(r^2 2^28 / rc^2), non-decreasing in r^2): distinct keys
+// order the candidates exactly as the full key does.
 struct NlRows {
   NlEnt* ent;
   int* e;
+  unsigned* k;
+  double qs;   // 2^28 / rc^2
 };
 
 // Append the candidates of one 64-wide batch that lie within the cutoff to the wave's
@@ -393,6 +397,7 @@ __device__ __forceinline__ int nl_append(bool keep, double r2, int e, int ncand,
     rows.ent[pos].hi = ((unsigned long long)etype[e] << 56) | (rb >> 8);
     rows.ent[pos].lo = (rb << 56) | ((unsigned long long)(own - F.atom0) * (unsigned)F.nimg + (unsigned)eimg[e]);
     rows.e[pos] = e;
+    if (rows.k) rows.k[pos] = ((unsigned)etype[e] << 28) | (unsigned)fmin(r2 * rows.qs, 268435455.0);
   }
   return ncand + __popcll(bal);
 }
@@ -400,6 +405,35 @@ __device__ __forceinline__ int nl_append(bool keep, double r2, int e, int ncand,
 // x precedes y in (species, r^2, owner, image) order
 __device__ __forceinline__ int nl_before(const NlEnt& x, const NlEnt& y) {
   return (x.hi < y.hi) | ((x.hi == y.hi) & (x.lo < y.lo));
+}
+
+// rk[h] = number of 32-bit keys below that of candidate lane + 64 h (h < NH); every lane
+// reads the same four keys per LDS access (broadcast)
+typedef unsigned u32x4n __attribute__((ext_vector_type(4)));
+template <int NH>
+__device__ __forceinline__ void nl_rank32(const unsigned* K, int ncand, int lane, int (&rk)[4]) {
+  unsigned y[NH];
+#pragma unroll
+  for (int h = 0; h < NH; h++) {
+    const int q = lane + 64 * h;
+    y[h] = q < ncand ? K[q] : 0u;
+  }
+  int r[NH];
+#pragma unroll
+  for (int h = 0; h < NH; h++) r[h] = 0;
+  int u = 0;
+  for (; u + 4 <= ncand; u += 4) {
+    const u32x4n x = *(const u32x4n*)(K + u);
+#pragma unroll
+    for (int h = 0; h < NH; h++) r[h] += (int)(x[0] < y[h]) + (int)(x[1] < y[h]) + (int)(x[2] < y[h]) + (int)(x[3] < y[h]);
+  }
+  for (; u < ncand; u++) {
+    const unsigned x = K[u];
+#pragma unroll
+    for (int h = 0; h < NH; h++) r[h] += (int)(x < y[h]);
+  }
+#pragma unroll
+  for (int h = 0; h < 4; h++) rk[h] = h < NH ? r[h] : 0;
 }
 
 // Rank the staged candidates of atom i by (species, r^2, owner, image) and write its
@@ -438,6 +472,36 @@ __device__ __forceinline__ void nl_format(int i, int ncand, const ModelC& m, NlR
   // broadcast).
   int* nl = nlist + (size_t)i * m.nm;
   int ovf = 0;
+  // Fast path (up to 256 candidates): rank by the 32-bit keys, four candidates per lane.
+  // With distinct keys the ranks are a permutation and sum to n (n - 1) / 2; a tie lowers
+  // the sum, and then the exact 128-bit ranking below runs instead.
+  if (rows.k && ncand <= 256) {
+    const int nh = (ncand + 63) >> 6;
+    int rk[4];
+    if (nh <= 1) nl_rank32<1>(rows.k, ncand, lane, rk);
+    else if (nh == 2) nl_rank32<2>(rows.k, ncand, lane, rk);
+    else if (nh == 3) nl_rank32<3>(rows.k, ncand, lane, rk);
+    else nl_rank32<4>(rows.k, ncand, lane, rk);
+    int sum = 0;
+#pragma unroll
+    for (int h = 0; h < 4; h++) sum += (lane + 64 * h < ncand) ? rk[h] : 0;
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    if (sum == ncand * (ncand - 1) / 2) {
+#pragma unroll
+      for (int h = 0; h < 4; h++) {
+        const int q = lane + 64 * h;
+        if (q >= ncand) break;
+        const unsigned t = rows.k[q] >> 28;
+        int below = 0;
+#pragma unroll
+        for (int tt = 0; tt < kMaxTypes; tt++) below += (tt < (int)t) ? tcnt[tt] : 0;
+        const int rank = rk[h] - below;
+        if (rank < m.sel[t]) nl[m.sel_off[t] + rank] = rows.e[q];
+        else ovf = 1;
+      }
+      ncand = 0;   // formatted: skip the exact ranking
+    }
+  }
   for (int q0 = lane; q0 < ncand; q0 += 128) {
     const int q1 = q0 + 64;
     const bool has1 = q1 < ncand;
@@ -599,9 +663,10 @@ template <int CAP>
 __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(NlKArgs A) {
   __shared__ NlEnt s_ent[kNlWaves][CAP];
   __shared__ int s_e[kNlWaves][CAP];
+  __shared__ __align__(16) unsigned s_k[kNlWaves][CAP <= kNlCap ? CAP : 4];
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const NlRows rows{s_ent[wv], s_e[wv]};
+  const NlRows rows{s_ent[wv], s_e[wv], CAP <= kNlCap ? s_k[wv] : nullptr, 268435456.0 / A.m.rc2};
   const bool second = CAP > kNlCap;
   const int nwork = second ? *A.nbig : A.n;
   const int stride = second ? gridDim.x * kNlWaves : nwork;
@@ -638,7 +703,7 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_vbuild(
   const Frame& F = frames[frame_of[i]];
   int too_close = 0;
   int cnt = nl_gather_cells<true>(i, F, rl2, xe, nullptr, nullptr, nullptr, ecell, cell_start, cell_atoms, lane,
-                                  NlRows{nullptr, nullptr}, 0, vlist + (size_t)i * vcap, vcap, too_close);
+                                  NlRows{nullptr, nullptr, nullptr, 0.0}, 0, vlist + (size_t)i * vcap, vcap, too_close);
   if (too_close) atomicOr(&status[STW_FLAGS], ST_OVERLAP);
   if (lane == 0) {
     vcnt[i] = cnt < vcap ? cnt : vcap;
