@@ -37,6 +37,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/s on 1 GPU: FP64 vs mixed/student at force RMSE ≤1e-3 rel"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+# vector ALU without packed FP32 instructions (the build disables them): one FMA per lane
+# per cycle, 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz
+ALU_PEAK_TFLOPS = 78.6
 DTYPE = {"fp64": "f64", "fp32": "f32 operands, f32 accumulate", "bf16": "bf16 operands, f32 accumulate",
          "bf16x3": "bf16x3 operands, f32 accumulate"}
 
@@ -52,15 +55,21 @@ def algorithmic_flops(spec, rows, natoms, student=False):
     and backward (Eq. 1-4)."""
     s0, s1, M = spec.emb_width
     if student:
+        # the student net is affine in its hidden layer h, so the contraction and its
+        # adjoint factor through per-centre products (S = sum h R^T, V = W2 dE/dT):
+        # per row h (2 H + 5 H for the tanh), S += h R (8 H), and in the adjoint h again,
+        # h . V (8 H), V R (8 H), dE/ds (3 H); per centre and neighbour species
+        # T = W2^T S + b2 rbar^T and V, u: 8 (H + 1) M each
         H = STUDENT_HIDDEN
-        chain = 2 * H + 2 * H * M
-        chain_bwd = 2 * H * M + 2 * H
+        emb_fwd_row = 7 * H + 8 * H + 4
+        emb_bwd_row = 7 * H + 8 * H + 8 * H + 3 * H + 30
+        per_centre = spec.ntypes * 8 * (H + 1) * M   # per direction, over the neighbour species
     else:
         chain = 2 * s0 + 2 * s0 * s1 + 2 * s1 * M
         chain_bwd = 2 * s1 * M + 2 * s0 * s1 + 2 * s0
-    contract_row = 2 * M * 4
-    emb_fwd_row = chain + contract_row
-    emb_bwd_row = chain + 2 * contract_row + chain_bwd
+        contract_row = 2 * M * 4
+        emb_fwd_row = chain + contract_row
+        emb_bwd_row = chain + 2 * contract_row + chain_bwd
     K1, fw, nf = spec.M * spec.m2, spec.fit_width[0], len(spec.fit_width)
     fit_atom = 2 * (2 * K1 * fw + 2 * fw * fw * (nf - 1) + 2 * fw) + 2 * spec.M * spec.m2 * 4 * 3
     # the part of the adjoint's work that is not a layer product (vector ALU): layer-0
@@ -68,8 +77,12 @@ def algorithmic_flops(spec, rows, natoms, student=False):
     # and skip adds, the recompute's 1 - tanh^2 factors, dE/dR = G . dE/dT (8 M), dE/ds
     # and the FP64 force / virial assembly (~30)
     if student:
-        H = STUDENT_HIDDEN
-        alu_bwd_row = 2 * H + 5 * H + M + 8 * M + 4 * H + 30
+        alu_bwd_row = emb_bwd_row   # all of it is vector-ALU work
+        return dict(embed_fwd=rows * emb_fwd_row + natoms * per_centre,
+                    embed_bwd=rows * emb_bwd_row + natoms * per_centre, fit=natoms * fit_atom,
+                    emb_bwd_row=emb_bwd_row, emb_fwd_row=emb_fwd_row, fit_atom=fit_atom,
+                    alu_bwd_row=alu_bwd_row, alu_bwd=rows * emb_bwd_row + natoms * per_centre,
+                    per_centre=per_centre)
     else:
         ntanh = s0 + s1 + M
         alu_bwd_row = 2 * s0 + 5 * ntanh + 2 * (s1 + M) + 8 * M + 3 * ntanh + (s1 + M) + 3 * s0 + 30
@@ -103,8 +116,8 @@ def traffic_for(kernel: str):
 
 
 POLICY = {"fp64": "NetNative<double>", "fp32": "NetNative<float>", "bf16": "NetBF16<1>", "bf16x3": "NetBF16<2>"}
-STUDENT_POLICY = {"fp64": "StuNative<double>", "fp32": "StuNative<float>", "bf16": "StuBF16<1>",
-                  "bf16x3": "StuBF16<2>"}
+STUDENT_KERNEL = {"fp64": "k_stu_bwd<double>", "fp32": "k_stu_bwd<float>", "bf16": "k_stu_bwd<float>",
+                  "bf16x3": "k_stu_bwd<float>"}
 
 
 def main():
@@ -247,19 +260,30 @@ def main():
                                        for s_ in ("embed_fwd", "fit", "embed_bwd")}
     bwd_ms = R["stages_ms"]["embed_bwd"]
     achieved = fl["embed_bwd"] / (bwd_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[hprec]
-    kname = "k_embed_bwd<%s, 8>" % (STUDENT_POLICY if R["student"] else POLICY)[hprec]
-    roofline = dict(bound="mfma", kernel=kname,
-                    achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                    frac=round(achieved / peak, 4), traffic=traffic_for(kname),
-                    flops_per_launch=fl["embed_bwd"], rows_per_launch=rows,
-                    flops_per_row=fl["emb_bwd_row"], avg_launch_ms=bwd_ms,
-                    stage_tflops=stage_rates,
-                    # the same kernel against the vector-ALU ceiling (its non-product work)
-                    alu=dict(flops_per_row=fl["alu_bwd_row"],
-                             achieved=round(fl["alu_bwd"] / (bwd_ms * 1e-3) / 1e12, 3),
-                             peak=PEAK_TFLOPS["fp32"], unit="TFLOP/s",
-                             frac=round(fl["alu_bwd"] / (bwd_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4)))
+    if R["student"]:
+        # no matrix product per neighbour: vector-ALU bound, against the non-packed
+        # FP32 / FP64 FMA rate (256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz)
+        kname = STUDENT_KERNEL[hprec]
+        peak = ALU_PEAK_TFLOPS
+        roofline = dict(bound="alu", kernel=kname, achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                        frac=round(achieved / peak, 4), traffic=traffic_for(kname),
+                        flops_per_launch=fl["embed_bwd"], rows_per_launch=rows,
+                        flops_per_row=fl["emb_bwd_row"], flops_per_centre=fl["per_centre"],
+                        avg_launch_ms=bwd_ms, stage_tflops=stage_rates)
+    else:
+        peak = PEAK_TFLOPS[hprec]
+        kname = "k_embed_bwd<%s, 8>" % POLICY[hprec]
+        roofline = dict(bound="mfma", kernel=kname,
+                        achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                        frac=round(achieved / peak, 4), traffic=traffic_for(kname),
+                        flops_per_launch=fl["embed_bwd"], rows_per_launch=rows,
+                        flops_per_row=fl["emb_bwd_row"], avg_launch_ms=bwd_ms,
+                        stage_tflops=stage_rates,
+                        # the same kernel against the vector-ALU ceiling (its non-product work)
+                        alu=dict(flops_per_row=fl["alu_bwd_row"],
+                                 achieved=round(fl["alu_bwd"] / (bwd_ms * 1e-3) / 1e12, 3),
+                                 peak=ALU_PEAK_TFLOPS, unit="TFLOP/s",
+                                 frac=round(fl["alu_bwd"] / (bwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, 4)))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -1267,15 +1267,13 @@ int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const dou
     h->d_student = nullptr;
     h->d_student_map = nullptr;
   }
-  const bool bf = bf16_mode(h->opt.precision);
-  const int parts = prec_parts(h->opt.precision);
-  const size_t blk = bf ? (size_t)snet_u16(parts) : (size_t)kStuElems;
+  // student blocks: FP64 in the FP64 mode, FP32 otherwise (the student kernels have no
+  // per-neighbour matrix product, so the BF16 operand modes do not apply to them)
+  const size_t blk = (size_t)kStuElems;
   if (!h->d_student) {
     std::vector<int> map((size_t)nnet * blk, -1);
-    std::vector<int> nat(kStuElems);
     for (int net = 0; net < nnet; net++) {
-      int* b = bf ? nat.data() : map.data() + (size_t)net * blk;
-      for (int q = 0; q < kStuElems; q++) b[q] = -1;
+      int* b = map.data() + (size_t)net * blk;
       size_t o = net * size;
       for (int j = 0; j < hidden; j++) {
         b[kSW1 + j] = (int)(o + j);
@@ -1287,45 +1285,14 @@ int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const dou
         b[kSB2 + p] = (int)(o + 2 * hidden + (size_t)hidden * M + f);
         for (int j = 0; j < hidden; j++) b[kSW2 + j * kSW2Stride + p] = (int)(o + 2 * hidden + (size_t)j * M + f);
       }
-      if (!bf) continue;
-      // BF16 block (layout in kernels.h): float part, then W2 packed like the full
-      // net's layers (k slot (g, j) = position 16 (2 kc + j / 4) + 4 g + j % 4)
-      int* u = map.data() + (size_t)net * blk;
-      for (int q = 0; q < kSBFloat; q++) {
-        u[2 * q] = nat[q] >= 0 ? 4 * nat[q] + 2 : -1;
-        u[2 * q + 1] = nat[q] >= 0 ? -2 : -1;
-      }
-      auto w2 = [&](int hid, int gpos) -> int {
-        int f = pos_feature(gpos, h->s0);
-        if (hid >= hidden || f < 0) return -1;
-        return (int)(o + 2 * hidden + (size_t)hid * M + f);
-      };
-      const int f0 = 2 * kSBFloat, b0 = f0 + parts * kSW2F;
-      for (int part = 0; part < parts; part++)
-        for (int lane = 0; lane < 64; lane++)
-          for (int j = 0; j < 8; j++) {
-            const int g = lane >> 4, rb = lane & 15;
-            for (int mt = 0; mt < 8; mt++) {
-              int idx = w2(16 * (j / 4) + 4 * g + j % 4, 16 * mt + rb);
-              u[f0 + part * kSW2F + (mt * 64 + lane) * 8 + j] = idx >= 0 ? 4 * idx + part : -1;
-            }
-            for (int nt = 0; nt < 2; nt++)
-              for (int kc = 0; kc < 4; kc++) {
-                int idx = w2(16 * nt + rb, 16 * (2 * kc + j / 4) + 4 * g + j % 4);
-                u[b0 + part * kSW2B + ((nt * 4 + kc) * 64 + lane) * 8 + j] = idx >= 0 ? 4 * idx + part : -1;
-              }
-          }
     }
     HIPCHECK(h, hipMalloc(&h->d_student_map, sizeof(int) * map.size()));
     HIPCHECK(h, hipMemcpy(h->d_student_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
-    HIPCHECK(h, hipMalloc(&h->d_student, map.size() * (bf ? 2 : storage_bytes(h->opt.precision))));
+    HIPCHECK(h, hipMalloc(&h->d_student, map.size() * storage_bytes(h->opt.precision)));
     h->student_hidden = hidden;
   }
-  if (bf)
-    launch_pack_bf16((size_t)nnet * blk, h->d_student_map, theta_s, (uint16_t*)h->d_student, (hipStream_t)stream);
-  else
-    launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, (size_t)nnet * kStuElems, h->d_student_map,
-                          theta_s, h->d_student, (hipStream_t)stream);
+  launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, (size_t)nnet * kStuElems, h->d_student_map, theta_s,
+                        h->d_student, (hipStream_t)stream);
   HIPCHECK(h, hipGetLastError());
   for (int q = 0; q < nnet; q++) {
     h->st_lo[q] = s_lo[q];

@@ -25,15 +25,13 @@
 // operand preparation; g_ij = dR^T dE/dR, F_i += g, F_j -= g (FP64 atomics), and the
 // per-centre virial -d (x) g.
 //
-// The per-neighbour net is a policy of the kernels: the full embedding net or the
-// student net G_s(s) = tanh(s W1 + b1) W2 + b2 (1 -> H <= 32 -> M; its rows outside the
-// student's trained s range go to a fallback list handled by the FP64 full net, see
-// student_infer.hip), each with native operands (NetNative / StuNative: 16x16x4 MFMA in
-// T, FP64 or FP32) or BF16 operands (NetBF16 / StuBF16: layer inputs rounded to BF16 on
+// The operand precision is a policy of the kernels: native operands (NetNative: 16x16x4
+// MFMA in T, FP64 or FP32) or BF16 operands (NetBF16: layer inputs rounded to BF16 on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation, one k chunk of 32 positions per
 // instruction, against weights pre-packed per lane; PARTS = 2 splits both operands into
 // hi + lo BF16 and sums hi hi + hi lo + lo hi).  Everything outside the layer products
-// (s, layer 0, biases, tanh, the skips, the contraction) stays in FP32 or FP64.
+// (s, layer 0, biases, tanh, the skips, the contraction) stays in FP32 or FP64.  Student
+// nets have kernels of their own (student_embed.hip).
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -116,7 +114,6 @@ __device__ __forceinline__ void chain_take_dG(T (&t2)[8][4], T (&res1)[4][4], in
 template <class T>
 struct NetNative {
   typedef T Tv;
-  static constexpr bool kStudent = false;
   struct State {
     T t0[2][4], t1[4][4], t2[8][4];
   };
@@ -232,7 +229,6 @@ __device__ __forceinline__ void bf_pack(const float (&v)[NT][4], int kc, bf8& hi
 template <int PARTS>
 struct NetBF16 {
   typedef float Tv;
-  static constexpr bool kStudent = false;
   typedef typename NetNative<float>::State State;
   typedef typename NetNative<float>::Aux Aux;
   static constexpr int kFloatBytes = 4 * kBFloat;
@@ -335,135 +331,6 @@ struct NetBF16 {
   }
 };
 
-// Student net, native operands: block of kStuElems T (W1, b1 at hidden positions 0..31,
-// b2 at G positions, W2 [32][kSW2Stride]).
-template <class T>
-struct StuNative {
-  typedef T Tv;
-  static constexpr bool kStudent = true;
-  struct State {
-    T h[2][4], G[8][4];   // G is overwritten by dE/dG in the adjoint
-  };
-  struct Aux {};
-  static constexpr int kFwdBytes = sizeof(T) * kStuElems;
-  static constexpr int kBwdBytes = sizeof(T) * kStuElems;
-  static constexpr int kBlockBytes = sizeof(T) * kStuElems;
-  __device__ static const char* block(const EmbedArgs& A, int pair) {
-    return (const char*)A.snets + (size_t)pair * kBlockBytes;
-  }
-  __device__ static void fwd(const char* sm, T s, int g, int rb, int lane, State& st) {
-    typedef typename Acc4<T>::type A4;
-    const T* sn = (const T*)sm;
-#pragma unroll
-    for (int n = 0; n < 2; n++)
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        int p = 16 * n + LP(g, q);
-        st.h[n][q] = tanh_t(s * sn[kSW1 + p] + sn[kSB1 + p]);
-      }
-#pragma unroll
-    for (int mt = 0; mt < 8; mt++) {
-      A4 c = {0, 0, 0, 0};
-#pragma unroll
-      for (int n = 0; n < 2; n++)
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-          c = mfma4(sn[kSW2 + (16 * n + LP(g, q)) * kSW2Stride + 16 * mt + rb], st.h[n][q], c);
-#pragma unroll
-      for (int q = 0; q < 4; q++) st.G[mt][q] = c[q] + sn[kSB2 + 16 * mt + LP(g, q)];
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  __device__ static T G(const State& st, int mt, int q) { return st.G[mt][q]; }
-  __device__ static void take_dG(State& st, Aux&, int mt, int q, T gG) { st.G[mt][q] = gG; }
-  __device__ static T back(const char* sm, State& st, Aux&, int g, int rb, int lane) {
-    typedef typename Acc4<T>::type A4;
-    const T (&dG)[8][4] = st.G;
-    const T* sn = (const T*)sm;
-    T dsl = (T)0;
-#pragma unroll
-    for (int nt = 0; nt < 2; nt++) {
-      A4 c = {0, 0, 0, 0};
-#pragma unroll
-      for (int mt = 0; mt < 8; mt++)
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-          c = mfma4(sn[kSW2 + (16 * nt + rb) * kSW2Stride + 16 * mt + LP(g, q)], dG[mt][q], c);
-#pragma unroll
-      for (int q = 0; q < 4; q++)
-        dsl += c[q] * ((T)1 - st.h[nt][q] * st.h[nt][q]) * sn[kSW1 + 16 * nt + LP(g, q)];
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    return dsl;
-  }
-};
-
-// Student net, BF16 operands: float part (W1, b1, b2 at the kStuElems offsets), then W2
-// packed per lane for the forward (8 output tiles x 1 k chunk) and the adjoint (2 x 4).
-template <int PARTS>
-struct StuBF16 {
-  typedef float Tv;
-  static constexpr bool kStudent = true;
-  typedef typename StuNative<float>::State State;
-  typedef typename StuNative<float>::Aux Aux;
-  static constexpr int kFloatBytes = 4 * kSBFloat;
-  static constexpr int kFwdBytes = kFloatBytes + PARTS * 2 * kSW2F;
-  static constexpr int kBwdBytes = kFwdBytes + PARTS * 2 * kSW2B;
-  static constexpr int kBlockBytes = 2 * snet_u16(PARTS);
-  __device__ static const char* block(const EmbedArgs& A, int pair) {
-    return (const char*)A.snets + (size_t)pair * kBlockBytes;
-  }
-  __device__ static void fwd(const char* sm, float s, int g, int rb, int lane, State& st) {
-    const float* fn = (const float*)sm;
-#pragma unroll
-    for (int n = 0; n < 2; n++)
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        int p = 16 * n + 4 * g + q;
-        st.h[n][q] = tanh_t(s * fn[kSW1 + p] + fn[kSB1 + p]);
-      }
-    bf8 xh, xl;
-    bf_pack<PARTS, 2>(st.h, 0, xh, xl);
-#pragma unroll
-    for (int mt = 0; mt < 8; mt++) {
-      f4v c = {0, 0, 0, 0};
-      bf8 wh = bf_tile<PARTS>(sm, kFloatBytes, 0, kSW2F, mt, lane);
-      bf8 wl = PARTS == 2 ? bf_tile<PARTS>(sm, kFloatBytes, 1, kSW2F, mt, lane) : wh;
-      c = mfma_split<PARTS>(wh, wl, xh, xl, c);
-#pragma unroll
-      for (int q = 0; q < 4; q++) st.G[mt][q] = c[q] + fn[kSB2 + 16 * mt + 4 * g + q];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  __device__ static float G(const State& st, int mt, int q) { return st.G[mt][q]; }
-  __device__ static void take_dG(State& st, Aux&, int mt, int q, float gG) { st.G[mt][q] = gG; }
-  __device__ static float back(const char* sm, State& st, Aux&, int g, int rb, int lane) {
-    const float* fn = (const float*)sm;
-    const float (&dG)[8][4] = st.G;
-    bf8 xh[4], xl[4];
-#pragma unroll
-    for (int kc = 0; kc < 4; kc++) bf_pack<PARTS, 8>(dG, kc, xh[kc], xl[kc]);
-    float dsl = 0.f;
-#pragma unroll
-    for (int nt = 0; nt < 2; nt++) {
-      f4v c = {0, 0, 0, 0};
-#pragma unroll
-      for (int kc = 0; kc < 4; kc++) {
-        bf8 wh = bf_tile<PARTS>(sm, kFwdBytes, 0, kSW2B, 4 * nt + kc, lane);
-        bf8 wl = PARTS == 2 ? bf_tile<PARTS>(sm, kFwdBytes, 1, kSW2B, 4 * nt + kc, lane) : wh;
-        c = mfma_split<PARTS>(wh, wl, xh[kc], xl[kc], c);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; q++) dsl += c[q] * (1.f - st.h[nt][q] * st.h[nt][q]) * fn[kSW1 + 16 * nt + 4 * g + q];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    return dsl;
-  }
-};
-
-__device__ __forceinline__ bool out_of_range(const EmbedArgs& A, int pair, double s) {
-  return s < A.st_lo[pair] || s > A.st_hi[pair];
-}
 
 // ------------------------------------------------------------------------------------
 // forward: T_i = (1/N_m) sum_j G_j^T R_j
@@ -510,17 +377,9 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd(EmbedArgs A) {
       if (k < nn) {
         const int e = nl[k];
         env_row(m, A.xe, e, xi, v);
-        if (NP::kStudent && out_of_range(A, pair, v.s)) {
-          // left to the full net (fallback list); contributes nothing here
-          if (g == 0) {
-            int p = atomicAdd(A.fb_count, 1);
-            if (p < A.fb_cap) A.fb_list[p] = make_int2(row, e);
-          }
-        } else {
-          s = (T)v.s;
+        s = (T)v.s;
 #pragma unroll
-          for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
-        }
+        for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
       }
       typename NP::State st;
       NP::fwd(smem_raw, s, g, rb, lane, st);
@@ -628,13 +487,9 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd(EmbedArgs A) {
       if (valid) {
         e = nl[k];
         env_row(m, A.xe, e, xi, v);
-        if (NP::kStudent && out_of_range(A, pair, v.s)) {
-          valid = false;  // handled by the fallback kernel
-        } else {
-          s = (T)v.s;
+        s = (T)v.s;
 #pragma unroll
-          for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
-        }
+        for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
       }
       typename NP::State st;
       NP::fwd(smem_raw, s, g, rb, lane, st);
@@ -743,24 +598,6 @@ void launch_embed_bwd(const EmbedArgs& a, hipStream_t st) {
     case PREC_FP32: embed_bwd_t<NetNative<float>>(a, st); break;
     case PREC_BF16: embed_bwd_t<NetBF16<1>>(a, st); break;
     default: embed_bwd_t<NetBF16<2>>(a, st); break;
-  }
-}
-
-void launch_student_fwd(const EmbedArgs& a, hipStream_t st) {
-  switch (a.prec) {
-    case PREC_FP64: embed_fwd_t<StuNative<double>>(a, st); break;
-    case PREC_FP32: embed_fwd_t<StuNative<float>>(a, st); break;
-    case PREC_BF16: embed_fwd_t<StuBF16<1>>(a, st); break;
-    default: embed_fwd_t<StuBF16<2>>(a, st); break;
-  }
-}
-
-void launch_student_bwd(const EmbedArgs& a, hipStream_t st) {
-  switch (a.prec) {
-    case PREC_FP64: embed_bwd_t<StuNative<double>>(a, st); break;
-    case PREC_FP32: embed_bwd_t<StuNative<float>>(a, st); break;
-    case PREC_BF16: embed_bwd_t<StuBF16<1>>(a, st); break;
-    default: embed_bwd_t<StuBF16<2>>(a, st); break;
   }
 }
 

@@ -76,12 +76,6 @@ inline constexpr int bnet_u16(int parts) { return 2 * kBFloat + parts * (kBFwd +
 constexpr int kSW1 = 0, kSB1 = kP0, kSB2 = 2 * kP0, kSW2 = 2 * kP0 + kP2;
 constexpr int kSW2Stride = kP2 + 1;
 constexpr int kStuElems = kSW2 + kP0 * kSW2Stride;
-// BF16 student block, in 16-bit units: the float part (W1, b1, b2 at the offsets above,
-// 192 floats), then W2 packed per lane for the forward (8 output tiles x 1 k chunk) and
-// for the adjoint (2 x 4), each once per part.
-constexpr int kSBFloat = kSW2;
-constexpr int kSW2F = 8 * 1 * 512, kSW2B = 2 * 4 * 512;
-inline constexpr int snet_u16(int parts) { return 2 * kSBFloat + parts * (kSW2F + kSW2B); }
 
 struct EmbedArgs {
   int prec;

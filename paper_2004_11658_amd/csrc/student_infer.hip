@@ -1,7 +1,7 @@
 // Fallback rows of the student embedding nets at inference.
 //
-// The student kernels (the StuNative / StuBF16 policies of the embedding kernels)
-// leave out every neighbour whose s lies outside the student's trained range
+// The student kernels (student_embed.hip) leave out every neighbour whose s lies
+// outside the student's trained range
 // [s_lo, s_hi] of its species pair and append it to a fallback list; these kernels
 // evaluate the full net for those rows afterwards in FP64 (one wave per row) and add
 // their contribution to T, and in the adjoint to the forces and the virial.

@@ -12,6 +12,10 @@ visits along its own MD trajectory:
      loss gradient kernel (dp_student_loss_grad, dp_adam), kept only if it helps.
 The trained range [s_lo, s_hi] is the [1e-4, 1 - 1e-4] quantile range of the samples
 (rarer, more extreme s values go to the full net); dp_set_student installs the result.
+The installed lower end is 0 when the trained one is tiny (below 1e-6 s_hi, the
+neighbours just inside the cutoff): extrapolating the smooth student from s_lo down to
+0 changes G by at most s_lo max|dG/ds|, and those neighbours enter T through
+R~ = s (1, x/r, y/r, z/r) anyway, so they need no fallback.
 Random numbers (neighbour subsampling) are drawn here with numpy PCG64 and passed to
 the kernels.
 """
@@ -100,7 +104,7 @@ def train_students(model: D.DPModel, frames, hidden: int = 32, n_samples: int = 
             s = samples[(a, b)]
             th, loss, rms, lo, hi = train_pair(model, a, b, s, hidden, refine_steps)
             thetas.append(th)
-            los.append(lo)
+            los.append(0.0 if lo < 1e-6 * hi else lo)
             his.append(hi)
             report["%d-%d" % (a, b)] = dict(samples=int(s.numel()), s_lo=lo, s_hi=hi,
                                             rmse_rel=math.sqrt(loss) / rms)
