@@ -223,6 +223,10 @@ enum { DP_STAGE_NLIST = 0, DP_STAGE_EMBED_FWD = 1, DP_STAGE_FIT = 2, DP_STAGE_EM
        DP_STAGE_REDUCE = 4, DP_STAGE_MD = 5, DP_STAGE_FALLBACK = 6, DP_NSTAGES = 7 };
 int dp_profile(dp_handle h, int32_t enable);
 int dp_profile_read(dp_handle h, int32_t stage, double* total_ms, int64_t* launches);
+/* As dp_profile(h, 1), but timing only the stages whose bit (1 << DP_STAGE_*) is set in
+ * stage_mask (0: stop recording).  Each timed stage adds two event records per call to
+ * the stream, so timing one stage perturbs a run less than timing all of them. */
+int dp_profile_stages(dp_handle h, uint32_t stage_mask);
 
 /* Synchronise stream and read the status word of the last call that used workspace.
  * flags (may be NULL) receives the raw flag bits; detail (may be NULL) the count
@@ -230,6 +234,12 @@ int dp_profile_read(dp_handle h, int32_t stage, double* total_ms, int64_t* launc
  * negative DP_ERR_* for device-detected conditions. */
 int dp_status(dp_handle h, const void* workspace, void* stream, int32_t* flags,
               int64_t* detail);
+
+/* Synchronise stream and read how many neighbour rows the last force evaluation that
+ * used workspace handed from the student nets to the full net (their s lay outside the
+ * students' trained ranges; the fallback of the student embedding).  0 without
+ * students.  Returns DP_OK or DP_ERR_ARG (NULL argument). */
+int dp_fallback_rows(dp_handle h, const void* workspace, void* stream, int64_t* rows);
 
 const char* dp_strerror(int code);
 const char* dp_last_error(dp_handle h);

@@ -18,7 +18,7 @@ enum : int32_t {
   ST_NONFINITE = 16,
   ST_OVERLAP = 32,
 };
-enum { STW_FLAGS = 0, STW_SEL_ROWS = 1, STW_MAX_CAND = 2, STW_GHOSTS = 3, STW_N = 16 };
+enum { STW_FLAGS = 0, STW_SEL_ROWS = 1, STW_MAX_CAND = 2, STW_GHOSTS = 3, STW_FALLBACK = 4, STW_N = 16 };
 
 // Per-frame constants, built on the host.
 struct Frame {

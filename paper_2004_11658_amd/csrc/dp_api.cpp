@@ -57,6 +57,7 @@ struct dp_handle_s {
   int slot = 0;
   // stage timing
   bool prof_on = false;
+  uint32_t prof_mask = 0;          // stages timed while prof_on (bit DP_STAGE_*)
   std::vector<hipEvent_t> prof_pool;
   size_t prof_used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_rec;
@@ -79,7 +80,7 @@ struct StageTimer {
   hipStream_t st;
   hipEvent_t e0 = nullptr;
   StageTimer(dp_handle h_, int stage_, hipStream_t st_) : h(h_), stage(stage_), st(st_) {
-    if (h->prof_on && (e0 = prof_event(h))) (void)hipEventRecord(e0, st);
+    if (h->prof_on && ((h->prof_mask >> stage) & 1u) && (e0 = prof_event(h))) (void)hipEventRecord(e0, st);
   }
   ~StageTimer() {
     if (h->prof_on && e0) {
@@ -527,7 +528,7 @@ struct Plan {
   bool verlet = false;
   size_t o_wk, o_xref, o_eabc, o_vlist, o_vcnt, o_vflag;
   int n, nframes, ncell, ghost_cap, nrows, vcap, max_frame_atoms;
-  size_t o_redpart;
+  size_t o_redpart, o_reddone;
   size_t o_gbuf = 0, o_rev = 0;   // deterministic force gather
   size_t o_big = 0;
 };
@@ -621,6 +622,7 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
   P.o_tmpj = take(sizeof(double) * nframes * 10);
   P.max_frame_atoms = (int)maxna;
   P.o_redpart = take(sizeof(double) * 10 * (size_t)nframes * frame_reduce_chunks((int)maxna));
+  P.o_reddone = take(sizeof(int) * (size_t)nframes);
   P.o_tmpi = take(sizeof(int) * 16);
   P.o_mdF = take(sizeof(double) * 3 * n);
   P.o_mdE = take(sizeof(double) * nframes);
@@ -766,6 +768,7 @@ static int stage_frames(dp_handle h, int nframes, const int64_t* off, const doub
   }
   // the status word covers the whole call
   launch_zero_int(A.status, STW_N, st);
+  launch_zero_int(W.at<int>(P.o_reddone), P.nframes, st);   // frame-reduction counters
   return DP_OK;
 }
 
@@ -786,7 +789,7 @@ static int stage_frames_and_nlist(dp_handle h, int nframes, const int64_t* off, 
 
 static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, hipStream_t st,
                      double* energies, double* forces, double* virials, double* atom_energy,
-                     bool want_forces, double* T_out, double* gT_out) {
+                     bool want_forces, double* T_out, double* gT_out, bool forces_zeroed = false) {
   Ws W{(char*)ws, &P};
   EmbedArgs E{};
   E.prec = h->opt.precision;
@@ -814,6 +817,7 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
     E.fb_list = W.at<int2>(P.o_fb);
     E.fb_count = W.at<int>(P.o_fbcnt);
     E.fb_cap = P.n * h->nm;
+    E.fb_note = A.status + STW_FALLBACK;   // reported by dp_fallback_rows
     E.theta = h->d_theta;
     E.net_off = h->d_net_off;
     E.etype = A.etype;
@@ -863,7 +867,7 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
     HIPCHECK(h, hipGetLastError());
   }
   if (want_forces) {
-    launch_zero(forces, (size_t)P.n * 3, st);
+    if (!forces_zeroed) launch_zero(forces, (size_t)P.n * 3, st);
     {
       StageTimer tm(h, DP_STAGE_EMBED_BWD, st);
       if (h->student_on) launch_student_bwd(E, st);
@@ -884,7 +888,7 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
   {
     StageTimer tm(h, DP_STAGE_REDUCE, st);
     launch_frame_reduce(P.nframes, P.max_frame_atoms, A.frames, A.row_of, F.Ei, want_forces ? E.vir_part : nullptr,
-                        energies, virials, atom_energy, W.at<double>(P.o_redpart), st);
+                        energies, virials, atom_energy, W.at<double>(P.o_redpart), W.at<int>(P.o_reddone), st);
   }
   HIPCHECK(h, hipGetLastError());
   return DP_OK;
@@ -1085,7 +1089,7 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
   double vol = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
                B[2] * (B[3] * B[7] - B[4] * B[6]);
   const int n = (int)natoms;
-  auto force = [&]() -> int {
+  auto force = [&](bool f_zeroed) -> int {
     if (verlet) {
       StageTimer tm(h, DP_STAGE_NLIST, st);
       launch_nlist_verlet(A, 0.5 * h->opt.skin, st);
@@ -1095,24 +1099,32 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
       int r = stage_nlist(h, A, st);
       if (r != DP_OK) return r;
     }
-    return run_model(h, P, A, workspace, st, E, F, Wv, nullptr, true, nullptr, nullptr);
+    return run_model(h, P, A, workspace, st, E, F, Wv, nullptr, true, nullptr, nullptr, f_zeroed);
   };
-  rc = force();
+  rc = force(false);
   if (rc != DP_OK) return rc;
   int row = 0;
   if (thermo) launch_thermo(n, types, mm, vol, 0, v, E, Wv, thermo + 6 * row++, st);
+  // Velocity Verlet: half kick + drift, forces, half kick.  Between two steps without a
+  // thermo row the closing half kick and the next opening half kick + drift run as one
+  // kernel, which also clears F for the next force evaluation.
+  bool opened = false;   // the current step's opening half kick + drift is done
   for (int s = 1; s <= nsteps; s++) {
-    {
+    if (!opened) {
       StageTimer tm(h, DP_STAGE_MD, st);
       launch_vv(n, types, mm, dt_fs, F, v, x, true, st);
     }
-    rc = force();
+    rc = force(opened);
     if (rc != DP_OK) return rc;
-    {
-      StageTimer tm(h, DP_STAGE_MD, st);
+    const bool thermo_row = thermo && thermo_every > 0 && s % thermo_every == 0;
+    StageTimer tm(h, DP_STAGE_MD, st);
+    if (thermo_row || s == nsteps) {
       launch_vv(n, types, mm, dt_fs, F, v, x, false, st);
-      if (thermo && thermo_every > 0 && s % thermo_every == 0)
-        launch_thermo(n, types, mm, vol, s, v, E, Wv, thermo + 6 * row++, st);
+      if (thermo_row) launch_thermo(n, types, mm, vol, s, v, E, Wv, thermo + 6 * row++, st);
+      opened = false;
+    } else {
+      launch_vv_merged(n, types, mm, dt_fs, F, v, x, st);
+      opened = true;
     }
   }
   HIPCHECK(h, hipGetLastError());
@@ -1400,16 +1412,21 @@ int dp_adam(int64_t n, double* theta, double* m, double* v, const double* g, int
   return hipGetLastError() == hipSuccess ? DP_OK : DP_ERR_HIP;
 }
 
-int dp_profile(dp_handle h, int32_t enable) {
+int dp_profile_stages(dp_handle h, uint32_t stage_mask) {
   if (!h) return DP_ERR_ARG;
-  if (enable) {
+  if (stage_mask) {
     // the pooled events are reused: wait for the ones still in flight
     for (auto& r : h->prof_rec) (void)hipEventSynchronize(r.second.second);
     h->prof_rec.clear();
     h->prof_used = 0;
   }
-  h->prof_on = enable != 0;
+  h->prof_on = stage_mask != 0;
+  h->prof_mask = stage_mask;
   return DP_OK;
+}
+
+int dp_profile(dp_handle h, int32_t enable) {
+  return dp_profile_stages(h, enable ? (1u << DP_NSTAGES) - 1u : 0u);
 }
 
 int dp_profile_read(dp_handle h, int32_t stage, double* total_ms, int64_t* launches) {
@@ -1426,6 +1443,16 @@ int dp_profile_read(dp_handle h, int32_t stage, double* total_ms, int64_t* launc
   }
   if (total_ms) *total_ms = tot;
   if (launches) *launches = cnt;
+  return DP_OK;
+}
+
+int dp_fallback_rows(dp_handle h, const void* workspace, void* stream, int64_t* rows) {
+  if (!h || !workspace || !rows) return DP_ERR_ARG;
+  int st_host[STW_N];
+  HIPCHECK(h, hipMemcpyAsync(st_host, workspace, sizeof(st_host), hipMemcpyDeviceToHost,
+                             (hipStream_t)stream));
+  HIPCHECK(h, hipStreamSynchronize((hipStream_t)stream));
+  *rows = st_host[STW_FALLBACK];
   return DP_OK;
 }
 

@@ -521,19 +521,23 @@ void launch_zero(double* p, size_t n, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, st, n, p);
 }
 
-// Per frame, fixed-order sums of E_i and the per-centre virials in two passes: block
-// (c, f) sums the atoms [c * kRedChunk, (c + 1) * kRedChunk) of frame f into partial
-// row (f, c); then one block per frame adds its partial rows in order.
+// Per frame, fixed-order sums of E_i and the per-centre virials: block (c, f) sums the
+// atoms [c * kRedChunk, (c + 1) * kRedChunk) of frame f into partial row (f, c); the block
+// that finishes last for frame f (a per-frame counter) adds the partial rows in chunk
+// order and resets the counter, so the result does not depend on block scheduling.
 constexpr int kRedChunk = 1024;
 
-__global__ __launch_bounds__(256) void k_frame_partial(const Frame* __restrict__ frames,
-                                                       const int* __restrict__ row_of,
-                                                       const double* __restrict__ Ei,
-                                                       const double* __restrict__ vir,
-                                                       double* __restrict__ atom_energy,
-                                                       double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_frame_reduce(const Frame* __restrict__ frames,
+                                                      const int* __restrict__ row_of,
+                                                      const double* __restrict__ Ei,
+                                                      const double* __restrict__ vir,
+                                                      double* __restrict__ atom_energy,
+                                                      double* __restrict__ part, int* __restrict__ done,
+                                                      double* __restrict__ energies, double* __restrict__ virials) {
   __shared__ double sh[256][10];
-  const Frame& F = frames[blockIdx.y];
+  __shared__ int last;
+  const int f = blockIdx.y, nchunk = gridDim.x;
+  const Frame& F = frames[f];
   const int beg = F.atom0 + blockIdx.x * kRedChunk;
   const int end = min(F.atom0 + F.natoms, beg + kRedChunk);
   double acc[10];
@@ -557,29 +561,31 @@ __global__ __launch_bounds__(256) void k_frame_partial(const Frame* __restrict__
       for (int q = 0; q < 10; q++) sh[threadIdx.x][q] += sh[threadIdx.x + s][q];
     __syncthreads();
   }
-  if (threadIdx.x < 10) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 10 + threadIdx.x] = sh[0][threadIdx.x];
-}
-
-__global__ __launch_bounds__(64) void k_frame_final(int nchunk, const double* __restrict__ part,
-                                                    const double* __restrict__ vir, double* __restrict__ energies,
-                                                    double* __restrict__ virials) {
-  const int f = blockIdx.x, q = threadIdx.x;
-  if (q >= 10) return;
-  double acc = 0.0;
-  for (int c = 0; c < nchunk; c++) acc += part[((size_t)f * nchunk + c) * 10 + q];
-  if (q == 0) energies[f] = acc;
-  else if (virials && vir) virials[f * 9 + q - 1] = acc;
+  if (threadIdx.x < 10) part[((size_t)f * nchunk + blockIdx.x) * 10 + threadIdx.x] = sh[0][threadIdx.x];
+  __threadfence();   // the partial row is visible device-wide before the count
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&done[f], 1) == nchunk - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();   // every other block's partial row is visible
+  const int q = threadIdx.x;
+  if (q < 10) {
+    double a = 0.0;
+    for (int c = 0; c < nchunk; c++) a += part[((size_t)f * nchunk + c) * 10 + q];
+    if (q == 0) energies[f] = a;
+    else if (virials && vir) virials[f * 9 + q - 1] = a;
+  }
+  if (q == 0) done[f] = 0;   // ready for the next evaluation
 }
 
 int frame_reduce_chunks(int max_frame_atoms) { return (max_frame_atoms + kRedChunk - 1) / kRedChunk; }
 
 void launch_frame_reduce(int nframes, int max_frame_atoms, const Frame* frames, const int* row_of,
                          const double* Ei, const double* vir_rows, double* energies, double* virials,
-                         double* atom_energy, double* part, hipStream_t st) {
+                         double* atom_energy, double* part, int* done, hipStream_t st) {
   const int nchunk = frame_reduce_chunks(max_frame_atoms);
-  hipLaunchKernelGGL(k_frame_partial, dim3(nchunk, nframes), dim3(256), 0, st, frames, row_of, Ei, vir_rows,
-                     atom_energy, part);
-  hipLaunchKernelGGL(k_frame_final, dim3(nframes), dim3(64), 0, st, nchunk, part, vir_rows, energies, virials);
+  hipLaunchKernelGGL(k_frame_reduce, dim3(nchunk, nframes), dim3(256), 0, st, frames, row_of, Ei, vir_rows,
+                     atom_energy, part, done, energies, virials);
 }
 
 template <class T>

@@ -103,6 +103,7 @@ struct EmbedArgs {
   int2* fb_list;             // fallback rows (species row, extended neighbour index)
   int* fb_count;
   int fb_cap;
+  int* fb_note;              // if set, the forward fallback kernel stores the row count here
   const double* theta;       // flat FP64 parameters (fallback rows use the full net)
   const int64_t* net_off;    // [ntypes*ntypes][6] offsets of W0, b0, W1, b1, W2, b2
   const int* etype;
@@ -159,9 +160,10 @@ void launch_fit_bf(const FitArgs& a, hipStream_t st);
 void launch_zero(double* p, size_t n, hipStream_t st);
 // part: frame_reduce_chunks(max atoms of a frame) * nframes * 10 doubles of scratch
 int frame_reduce_chunks(int max_frame_atoms);
+// done: nframes ints, zero before the first use of a call (each use leaves them zero)
 void launch_frame_reduce(int nframes, int max_frame_atoms, const Frame* frames, const int* row_of,
                          const double* Ei, const double* vir_rows, double* energies, double* virials,
-                         double* atom_energy, double* part, hipStream_t st);
+                         double* atom_energy, double* part, int* done, hipStream_t st);
 void launch_export_T(int prec, int n, int M, const int* row_of, const void* Tm, const void* gT,
                      double* To, double* gTo, hipStream_t st);
 
@@ -220,6 +222,9 @@ struct MDMass {
   double m[kMaxTypes];
   double inv[kMaxTypes];
 };
+// closing half kick of a step + opening half kick and drift of the next; clears F
+void launch_vv_merged(int n, const int* types, const MDMass& mass, double dt, double* F, double* v, double* x,
+                      hipStream_t st);
 void launch_vv(int n, const int* types, const MDMass& mass, double dt, const double* F, double* v,
                double* x, bool drift, hipStream_t st);
 void launch_thermo(int n, const int* types, const MDMass& mass, double volume, int step,

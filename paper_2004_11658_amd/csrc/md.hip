@@ -27,6 +27,24 @@ __global__ void k_vv(int n, const int* __restrict__ types, MDMass mass, double h
   if (drift) x[q] += dt * vv;
 }
 
+// the closing half kick of one step and the opening half kick and drift of the next in
+// one pass (the two half kicks are added one after the other, exactly as two launches
+// would); F is consumed and cleared for the next force evaluation
+__global__ void k_vv2(int n, const int* __restrict__ types, MDMass mass, double half_dt_acc, double dt,
+                      double* __restrict__ F, double* __restrict__ v, double* __restrict__ x) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 3 * n) return;
+  int i = q / 3;
+  int t = types[i];
+  double im = (t >= 0 && t < kMaxTypes) ? mass.inv[t] : 0.0;
+  const double f = F[q];
+  double vv = v[q] + half_dt_acc * f * im;
+  vv = vv + half_dt_acc * f * im;
+  v[q] = vv;
+  x[q] += dt * vv;
+  F[q] = 0.0;
+}
+
 // thermo row [step, PE, KE, T, Etot, P(bar)]: one block, fixed-order reduction
 __global__ __launch_bounds__(1024) void k_thermo(int n, const int* __restrict__ types, MDMass mass,
                                                  double volume, int step,
@@ -64,6 +82,12 @@ void launch_vv(int n, const int* types, const MDMass& mass, double dt, const dou
                double* x, bool drift, hipStream_t st) {
   hipLaunchKernelGGL(k_vv, dim3((3 * n + 255) / 256), dim3(256), 0, st, n, types, mass, 0.5 * dt * kAcc,
                      dt, F, v, x, drift ? 1 : 0);
+}
+
+void launch_vv_merged(int n, const int* types, const MDMass& mass, double dt, double* F, double* v, double* x,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_vv2, dim3((3 * n + 255) / 256), dim3(256), 0, st, n, types, mass, 0.5 * dt * kAcc, dt, F,
+                     v, x);
 }
 
 void launch_thermo(int n, const int* types, const MDMass& mass, double volume, int step,

@@ -386,18 +386,37 @@ struct NlRows {
 
 // Append the candidates of one 64-wide batch that lie within the cutoff to the wave's
 // LDS rows (up to cap); returns the new candidate count (which may exceed cap).
+// full 128-bit key of candidate e at distance^2 r2
+__device__ __forceinline__ NlEnt nl_key(double r2, int e, const Frame& F, const int* __restrict__ eown,
+                                        const int* __restrict__ eimg, const int* __restrict__ etype) {
+  const unsigned long long rb = (unsigned long long)__double_as_longlong(r2);
+  NlEnt k;
+  k.hi = ((unsigned long long)etype[e] << 56) | (rb >> 8);
+  k.lo = (rb << 56) | ((unsigned long long)(eown[e] - F.atom0) * (unsigned)F.nimg + (unsigned)eimg[e]);
+  return k;
+}
+
+// r^2 of the pair (xi, e), in the one evaluation order every list decision uses
+// (contraction off, as in the candidate gathers)
+__device__ __forceinline__ double nl_r2(const double* __restrict__ xe, int e, const double (&xi)[3]) {
+#pragma clang fp contract(off)
+  const double d0 = xe[3 * e] - xi[0], d1 = xe[3 * e + 1] - xi[1], d2 = xe[3 * e + 2] - xi[2];
+  return (d0 * d0 + d1 * d1) + d2 * d2;
+}
+
+// Append the candidates of one 64-wide batch that lie within the cutoff to the wave's
+// LDS rows (up to cap); returns the new candidate count (which may exceed cap).  With
+// 32-bit keys (the main pass) only the key and the index are stored; the full key is
+// built later, and only if two 32-bit keys tie.
 __device__ __forceinline__ int nl_append(bool keep, double r2, int e, int ncand, int lane, const Frame& F,
                                          const int* __restrict__ eown, const int* __restrict__ eimg,
                                          const int* __restrict__ etype, NlRows rows, int cap) {
   unsigned long long bal = __ballot(keep);
   int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
   if (keep && pos < cap) {
-    const int own = eown[e];
-    const unsigned long long rb = (unsigned long long)__double_as_longlong(r2);
-    rows.ent[pos].hi = ((unsigned long long)etype[e] << 56) | (rb >> 8);
-    rows.ent[pos].lo = (rb << 56) | ((unsigned long long)(own - F.atom0) * (unsigned)F.nimg + (unsigned)eimg[e]);
     rows.e[pos] = e;
     if (rows.k) rows.k[pos] = ((unsigned)etype[e] << 28) | (unsigned)fmin(r2 * rows.qs, 268435455.0);
+    else rows.ent[pos] = nl_key(r2, e, F, eown, eimg, etype);
   }
   return ncand + __popcll(bal);
 }
@@ -440,7 +459,9 @@ __device__ __forceinline__ void nl_rank32(const unsigned* K, int ncand, int lane
 // formatted row: per-species blocks of width sel, nearest first, -1 pads (Alg. 1).
 __device__ __forceinline__ void nl_format(int i, int ncand, const ModelC& m, NlRows rows, int lane,
                                           int* __restrict__ nlist, int* __restrict__ nnei,
-                                          int* __restrict__ status) {
+                                          int* __restrict__ status, const Frame& F,
+                                          const double* __restrict__ xe, const int* __restrict__ eown,
+                                          const int* __restrict__ eimg, const int* __restrict__ etype) {
   if (ncand > kMaxCand) {
     if (lane == 0) {
       atomicOr(&status[STW_FLAGS], ST_CAPACITY);
@@ -456,7 +477,7 @@ __device__ __forceinline__ void nl_format(int i, int ncand, const ModelC& m, NlR
 #pragma unroll
   for (int t = 0; t < kMaxTypes; t++) tcnt[t] = 0;
   for (int q = lane; q < ncand; q += 64) {
-    int ty = (int)(rows.ent[q].hi >> 56);
+    int ty = rows.k ? (int)(rows.k[q] >> 28) : (int)(rows.ent[q].hi >> 56);
 #pragma unroll
     for (int t = 0; t < kMaxTypes; t++) tcnt[t] += (ty == t);
   }
@@ -500,6 +521,16 @@ __device__ __forceinline__ void nl_format(int i, int ncand, const ModelC& m, NlR
         else ovf = 1;
       }
       ncand = 0;   // formatted: skip the exact ranking
+    } else {
+      // tied keys: build the full keys for the exact ranking
+      const double xi[3] = {xe[3 * i], xe[3 * i + 1], xe[3 * i + 2]};
+      for (int q = lane; q < ncand; q += 64) {
+        const int e = rows.e[q];
+        rows.ent[q] = nl_key(nl_r2(xe, e, xi), e, F, eown, eimg, etype);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
   for (int q0 = lane; q0 < ncand; q0 += 128) {
@@ -685,7 +716,7 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(NlKArgs A) {
       if (lane == 0) A.big[atomicAdd(A.nbig, 1)] = i;
       continue;
     }
-    nl_format(i, ncand, A.m, rows, lane, A.nlist, A.nnei, A.status);
+    nl_format(i, ncand, A.m, rows, lane, A.nlist, A.nnei, A.status, F, A.xe, A.eown, A.eimg, A.etype);
   }
 }
 
@@ -728,9 +759,10 @@ __global__ __launch_bounds__(256) void k_update_ext(int n, int ne_cap, const int
                                                     const int* __restrict__ frame_of,
                                                     const double* __restrict__ x, const int* __restrict__ wk,
                                                     const int* __restrict__ eown, const int* __restrict__ eabc,
-                                                    double* __restrict__ xe) {
+                                                    double* __restrict__ xe, int* __restrict__ gate) {
 #pragma clang fp contract(off)
   int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) *gate = 0;   // the rebuild (if any) is done; the next step's check sets it again
   if (e >= ne_cap || e >= n_ext[0]) return;
   int i = eown[e];
   const Frame& F = frames[frame_of[i]];
@@ -900,10 +932,9 @@ void launch_nlist_verlet(const NlistArgs& A, double half_skin, hipStream_t st) {
   hipLaunchKernelGGL(k_disp, dim3((n + 255) / 256), dim3(256), 0, st, n, A.x, A.xref, half_skin * half_skin,
                      (int*)A.gate);
   launch_nlist(A, st);
-  fill_int(1, (int*)A.gate, 0, nullptr, st);
   int ne_cap = n + A.ghost_cap;
   hipLaunchKernelGGL(k_update_ext, dim3((ne_cap + 255) / 256), dim3(256), 0, st, n, ne_cap, A.n_ext, A.frames,
-                     A.frame_of, A.x, A.wk, A.eown, A.eabc, A.xe);
+                     A.frame_of, A.x, A.wk, A.eown, A.eabc, A.xe, (int*)A.gate);
   launch_format(format_args(A), st);
 }
 

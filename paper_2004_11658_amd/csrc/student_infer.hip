@@ -38,6 +38,7 @@ __global__ __launch_bounds__(64) void k_fb_fwd(EmbedArgs A) {
   const int lane = threadIdx.x;
   const int cnt = min(*A.fb_count, A.fb_cap);
   const int s0 = m.s0, s1 = 2 * s0, M = m.M;
+  if (blockIdx.x == 0 && lane == 0 && A.fb_note) *A.fb_note = cnt;
   for (int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
     const int2 it = A.fb_list[idx];
     const int row = it.x, e = it.y;

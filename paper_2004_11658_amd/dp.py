@@ -48,8 +48,10 @@ def _load():
         "dp_nlist": ([P, I64, P, P, P, P, P, P, P, SZ, P], C.c_int),
         "dp_descriptor": ([P, I64, P, P, P, P, P, P, SZ, P], C.c_int),
         "dp_status": ([P, P, P, P, P], C.c_int),
+        "dp_fallback_rows": ([P, P, P, P], C.c_int),
         "dp_md_run": ([P, I64, P, P, P, P, P, D, I32, I32, P, P, P, SZ, P], C.c_int),
         "dp_profile": ([P, I32], C.c_int),
+        "dp_profile_stages": ([P, C.c_uint32], C.c_int),
         "dp_set_params": ([P, P, P], C.c_int),
         "dp_get_params": ([P, P, P], C.c_int),
         "dp_param_grad_workspace_size": ([P, I32, P, P, P], C.c_int),
@@ -117,7 +119,7 @@ class DPModel:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:   # _lib is gone at interpreter exit
             _lib.dp_free(h)
             self.h = None
 
@@ -136,6 +138,13 @@ class DPModel:
         if self._ws is None or self._ws.numel() < nb.value:
             self._ws = torch.empty(int(nb.value * 1.1) + 4096, dtype=torch.uint8, device=self.device)
         return self._ws
+
+    def fallback_rows(self) -> int:
+        """Neighbour rows the last force evaluation handed from the student nets to the
+        full net (dp_fallback_rows)."""
+        rows = C.c_int64()
+        self._check(_lib.dp_fallback_rows(self.h, _ptr(self._ws), _stream(), C.byref(rows)))
+        return int(rows.value)
 
     def status(self) -> int:
         flags, det = C.c_int32(), C.c_int64()
@@ -239,8 +248,15 @@ class DPModel:
             self.status()
         return th
 
-    def profile(self, enable: bool):
-        self._check(_lib.dp_profile(self.h, 1 if enable else 0))
+    def profile(self, enable: bool, stages=None):
+        """Stage timing on (all stages, or only the named ones) or off."""
+        if enable and stages is not None:
+            mask = 0
+            for s in stages:
+                mask |= 1 << STAGES[s]
+            self._check(_lib.dp_profile_stages(self.h, mask))
+        else:
+            self._check(_lib.dp_profile(self.h, 1 if enable else 0))
 
     def profile_read(self, stage: str):
         """(total milliseconds, launches) of one stage since profile(True)."""
