@@ -38,6 +38,7 @@ struct NlistArgs {
   int vcap;
   double rl2;
   bool skip_rows;   // leave the species-grouped row order as it is (MD after its first step)
+  bool cells_zeroed;   // cell counters already cleared by the caller (MD displacement check)
   int *big, *nbig;  // atoms with more candidates within rc than the first formatting pass holds
 };
 size_t scan_sums_ints(int n, int W);
@@ -71,8 +72,8 @@ constexpr int kBW1B = 2 * 2 * 512, kBW2B = 4 * 4 * 512;
 constexpr int kBFwd = kBW1F + kBW2F, kBBwd = kBW1B + kBW2B;
 inline constexpr int bnet_u16(int parts) { return 2 * kBFloat + parts * (kBFwd + kBBwd); }
 
-// Position-padded student block (1 -> H <= 32 tanh -> M affine): W1, b1 at hidden
-// positions 0..31, b2 at the output positions of G, W2 [32][kP2 + 1].
+// Student block (1 -> H <= 32 tanh -> M <= 128 affine), zero-padded: W1, b1 at hidden
+// units 0..31, b2 [128] and W2 [32][kP2 + 1] by output feature.
 constexpr int kSW1 = 0, kSB1 = kP0, kSB2 = 2 * kP0, kSW2 = 2 * kP0 + kP2;
 constexpr int kSW2Stride = kP2 + 1;
 constexpr int kStuElems = kSW2 + kP0 * kSW2Stride;

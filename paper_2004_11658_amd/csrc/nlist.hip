@@ -168,10 +168,64 @@ struct LoadTypeOneHot {
   }
 };
 
+// Single-launch exclusive scan of up to kOneTile ints by one 1024-thread block: 16
+// consecutive items per thread, wave scans by shuffles, then the 16 wave totals.
+constexpr int kOneBlock = 1024;
+constexpr int kOneItems = 16;
+constexpr int kOneTile = kOneBlock * kOneItems;
+
+template <class Load>
+__global__ __launch_bounds__(kOneBlock) void k_scan_one(int n, Load load, int* __restrict__ out,
+                                                       int* __restrict__ total, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int wsum[kOneBlock / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int base = t * kOneItems;
+  int it[kOneItems];
+  int tot = 0;
+#pragma unroll
+  for (int k = 0; k < kOneItems; k++) {
+    const int i = base + k;
+    const int x = i < n ? load(i).v[0] : 0;
+    it[k] = tot;
+    tot += x;
+  }
+  int incl = tot;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const int v = lane < kOneBlock / 64 ? wsum[lane] : 0;
+    int sc = v;
+#pragma unroll
+    for (int off = 1; off < kOneBlock / 64; off <<= 1) {
+      const int y = __shfl_up(sc, off, 64);
+      if (lane >= off) sc += y;
+    }
+    if (lane < kOneBlock / 64) wsum[lane] = sc - v;
+    if (lane == kOneBlock / 64 - 1) total[0] = sc;
+  }
+  __syncthreads();
+  const int excl = wsum[w] + incl - tot;
+#pragma unroll
+  for (int k = 0; k < kOneItems; k++) {
+    const int i = base + k;
+    if (i < n) out[i] = excl + it[k];
+  }
+}
+
 // scan scratch: sums[nblocks * W]; gate (may be NULL): skip the scan when *gate == 0
 template <int W, class Load>
 static void scan_launch(int n, Load load, int* out, int* sums, int* total, hipStream_t st,
                         const int* gate = nullptr) {
+  if (W == 1 && n <= kOneTile) {
+    hipLaunchKernelGGL((k_scan_one<Load>), dim3(1), dim3(kOneBlock), 0, st, n, load, out, total, gate);
+    return;
+  }
   int nb = (n + kScanTile - 1) / kScanTile;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL((k_scan_up<W, Load>), dim3(nb), dim3(kScanBlock), 0, st, n, load, out, sums, gate);
@@ -335,24 +389,24 @@ __global__ __launch_bounds__(256) void k_ghost_emit(
       }
 }
 
-__global__ __launch_bounds__(256) void k_cell_place(int ne_cap, const int* __restrict__ n_ext,
+// n_ext = n + min(ghost total, ghost_cap) (ghosts beyond the capacity were not
+// emitted), written by thread 0; then every extended atom is placed in its cell.
+__global__ __launch_bounds__(256) void k_cell_place(int n, int ghost_cap, const int* __restrict__ gtotal,
+                                                    int* __restrict__ n_ext,
                                                     const int* __restrict__ ecell,
                                                     const int* __restrict__ cell_start,
                                                     int* __restrict__ cell_fill,
                                                     int* __restrict__ cell_atoms,
                                                     const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int g = gtotal[0];
+  const int ne = n + (g < ghost_cap ? g : ghost_cap);
   int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne_cap || (gate && *gate == 0) || e >= n_ext[0]) return;
+  if (e == 0) n_ext[0] = ne;
+  if (e >= ne) return;
   int c = ecell[e];
   int p = atomicAdd(&cell_fill[c], 1);
   cell_atoms[cell_start[c] + p] = e;
-}
-
-__global__ void k_ext_count(int n, int ghost_cap, const int* __restrict__ gtotal,
-                            int* __restrict__ n_ext, const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  int g = gtotal[0];
-  n_ext[0] = n + (g < ghost_cap ? g : ghost_cap);
 }
 
 // ------------------------------------------------------------------------------------
@@ -779,10 +833,16 @@ __global__ __launch_bounds__(256) void k_update_ext(int n, int ne_cap, const int
 }
 
 // *flag |= 1 when some atom moved more than half the skin since the last rebuild
-// (or has a non-finite coordinate)
+// (or has a non-finite coordinate).  Also clears the cell counters (nc1 and nc2 ints)
+// for the rebuild that may follow; nothing else reads them between rebuilds.
 __global__ __launch_bounds__(256) void k_disp(int n, const double* __restrict__ x, const double* __restrict__ xref,
-                                              double lim2, int* __restrict__ flag) {
+                                              double lim2, int* __restrict__ flag, int nc1, int* __restrict__ c1,
+                                              int nc2, int* __restrict__ c2) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int q = i; q < nc1 || q < nc2; q += gridDim.x * blockDim.x) {
+    if (q < nc1) c1[q] = 0;
+    if (q < nc2) c2[q] = 0;
+  }
   bool moved = false;
   if (i < n) {
     double d0 = x[3 * i] - xref[3 * i], d1 = x[3 * i + 1] - xref[3 * i + 1], d2 = x[3 * i + 2] - xref[3 * i + 2];
@@ -887,19 +947,19 @@ void launch_nlist(const NlistArgs& A, hipStream_t st) {
   const int n = A.n;
   const int nb = (n + 255) / 256;
   const int* G = A.gate;
-  hipLaunchKernelGGL(k_zero2_gated, dim3((A.ncell + 1 + 255) / 256), dim3(256), 0, st, A.ncell + 1, A.cell_count,
-                     A.ncell, A.cell_fill, G);
+  if (!A.cells_zeroed)
+    hipLaunchKernelGGL(k_zero2_gated, dim3((A.ncell + 1 + 255) / 256), dim3(256), 0, st, A.ncell + 1,
+                       A.cell_count, A.ncell, A.cell_fill, G);
   hipLaunchKernelGGL(k_wrap, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes, A.x,
                      A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status, G, A.wk, A.xref);
   scan_launch<1>(n, LoadInt{A.gcount}, A.goff, A.scan_sums, A.gtotal, st, G);
   hipLaunchKernelGGL(k_ghost_emit, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, A.ghost_cap, A.frames, A.frame_of,
                      A.types, A.xw, A.fw, A.goff, A.gtotal, A.xe, A.eown, A.eimg, A.etype, A.ecell,
                      A.cell_count, A.status, G, A.eabc);
-  hipLaunchKernelGGL(k_ext_count, dim3(1), dim3(1), 0, st, n, A.ghost_cap, A.gtotal, A.n_ext, G);
   scan_launch<1>(A.ncell + 1, LoadInt{A.cell_count}, A.cell_start, A.scan_sums, A.ctotal, st, G);
   int ne_cap = n + A.ghost_cap;
-  hipLaunchKernelGGL(k_cell_place, dim3((ne_cap + 255) / 256), dim3(256), 0, st, ne_cap, A.n_ext,
-                     A.ecell, A.cell_start, A.cell_fill, A.cell_atoms, G);
+  hipLaunchKernelGGL(k_cell_place, dim3((ne_cap + 255) / 256), dim3(256), 0, st, n, A.ghost_cap, A.gtotal,
+                     A.n_ext, A.ecell, A.cell_start, A.cell_fill, A.cell_atoms, G);
   if (A.vlist)
     hipLaunchKernelGGL(k_vbuild, dim3((n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, n, A.rl2,
                        A.frames, A.frame_of, A.xe, A.ecell, A.cell_start, A.cell_atoms, A.vlist, A.vcnt,
@@ -930,8 +990,10 @@ void launch_nlist(const NlistArgs& A, hipStream_t st) {
 void launch_nlist_verlet(const NlistArgs& A, double half_skin, hipStream_t st) {
   const int n = A.n;
   hipLaunchKernelGGL(k_disp, dim3((n + 255) / 256), dim3(256), 0, st, n, A.x, A.xref, half_skin * half_skin,
-                     (int*)A.gate);
-  launch_nlist(A, st);
+                     (int*)A.gate, A.ncell + 1, A.cell_count, A.ncell, A.cell_fill);
+  NlistArgs B = A;
+  B.cells_zeroed = true;
+  launch_nlist(B, st);
   int ne_cap = n + A.ghost_cap;
   hipLaunchKernelGGL(k_update_ext, dim3((ne_cap + 255) / 256), dim3(256), 0, st, n, ne_cap, A.n_ext, A.frames,
                      A.frame_of, A.x, A.wk, A.eown, A.eabc, A.xe, (int*)A.gate);

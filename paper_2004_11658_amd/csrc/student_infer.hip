@@ -81,6 +81,7 @@ __global__ __launch_bounds__(64) void k_fb_bwd(EmbedArgs A) {
   const int lane = threadIdx.x;
   const int cnt = min(*A.fb_count, A.fb_cap);
   const int s0 = m.s0, s1 = 2 * s0, M = m.M;
+  if (blockIdx.x == 0 && lane == 0 && A.fb_note) *A.fb_note = cnt;
   for (int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
     const int2 it = A.fb_list[idx];
     const int row = it.x, e = it.y;
@@ -164,14 +165,19 @@ __global__ __launch_bounds__(64) void k_fb_bwd(EmbedArgs A) {
   }
 }
 
+// The row count lives on the device, so the grid is fixed: 16 one-wave blocks per CU, so
+// that a few thousand rows run about one per wave (each row is a chain of dependent
+// loads and products, latency-bound); surplus blocks exit at once.
+constexpr int kFbBlocks = 4096;
+
 void launch_fallback_fwd(const EmbedArgs& a, hipStream_t st) {
-  if (a.prec == PREC_FP64) hipLaunchKernelGGL(k_fb_fwd<double>, dim3(1024), dim3(64), 0, st, a);
-  else hipLaunchKernelGGL(k_fb_fwd<float>, dim3(1024), dim3(64), 0, st, a);
+  if (a.prec == PREC_FP64) hipLaunchKernelGGL(k_fb_fwd<double>, dim3(kFbBlocks), dim3(64), 0, st, a);
+  else hipLaunchKernelGGL(k_fb_fwd<float>, dim3(kFbBlocks), dim3(64), 0, st, a);
 }
 
 void launch_fallback_bwd(const EmbedArgs& a, hipStream_t st) {
-  if (a.prec == PREC_FP64) hipLaunchKernelGGL(k_fb_bwd<double>, dim3(1024), dim3(64), 0, st, a);
-  else hipLaunchKernelGGL(k_fb_bwd<float>, dim3(1024), dim3(64), 0, st, a);
+  if (a.prec == PREC_FP64) hipLaunchKernelGGL(k_fb_bwd<double>, dim3(kFbBlocks), dim3(64), 0, st, a);
+  else hipLaunchKernelGGL(k_fb_bwd<float>, dim3(kFbBlocks), dim3(64), 0, st, a);
 }
 
 
