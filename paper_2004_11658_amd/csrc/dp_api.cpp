@@ -751,7 +751,7 @@ static int stage_frames(dp_handle h, int nframes, const int64_t* off, const doub
   A.row_of = W.at<int>(P.o_rowof);
   A.row_atom = W.at<int>(P.o_rowatom);
   A.big = W.at<int>(P.o_big);
-  A.nbig = small + 32;
+  A.nbig = small + 32;         // and its second-pass counter at small + 33
   A.skip_rows = false;
   A.gate = nullptr;
   if (P.verlet) {
@@ -769,6 +769,7 @@ static int stage_frames(dp_handle h, int nframes, const int64_t* off, const doub
   // the status word covers the whole call
   launch_zero_int(A.status, STW_N, st);
   launch_zero_int(W.at<int>(P.o_reddone), P.nframes, st);   // frame-reduction counters
+  launch_zero_int(A.nbig, 2, st);   // deferred-atom count and its pass counter
   return DP_OK;
 }
 
@@ -1089,10 +1090,21 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
   double vol = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
                B[2] * (B[3] * B[7] - B[4] * B[6]);
   const int n = (int)natoms;
-  auto force = [&](bool f_zeroed) -> int {
+  // the skin check runs inside every drift of the loop (none before the first force)
+  VvCheck chk{};
+  if (verlet) {
+    chk.xref = A.xref;
+    chk.lim2 = 0.25 * h->opt.skin * h->opt.skin;
+    chk.gate = (int*)A.gate;
+    chk.nc1 = A.ncell + 1;
+    chk.c1 = A.cell_count;
+    chk.nc2 = A.ncell;
+    chk.c2 = A.cell_fill;
+  }
+  auto force = [&](bool f_zeroed, bool disp_done) -> int {
     if (verlet) {
       StageTimer tm(h, DP_STAGE_NLIST, st);
-      launch_nlist_verlet(A, 0.5 * h->opt.skin, st);
+      launch_nlist_verlet(A, 0.5 * h->opt.skin, disp_done, st);
       A.skip_rows = true;   // the species row order is fixed after the first build
       HIPCHECK(h, hipGetLastError());
     } else {
@@ -1101,7 +1113,7 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
     }
     return run_model(h, P, A, workspace, st, E, F, Wv, nullptr, true, nullptr, nullptr, f_zeroed);
   };
-  rc = force(false);
+  rc = force(false, false);
   if (rc != DP_OK) return rc;
   int row = 0;
   if (thermo) launch_thermo(n, types, mm, vol, 0, v, E, Wv, thermo + 6 * row++, st);
@@ -1112,18 +1124,18 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
   for (int s = 1; s <= nsteps; s++) {
     if (!opened) {
       StageTimer tm(h, DP_STAGE_MD, st);
-      launch_vv(n, types, mm, dt_fs, F, v, x, true, st);
+      launch_vv(n, types, mm, dt_fs, F, v, x, true, chk, st);
     }
-    rc = force(opened);
+    rc = force(opened, true);
     if (rc != DP_OK) return rc;
     const bool thermo_row = thermo && thermo_every > 0 && s % thermo_every == 0;
     StageTimer tm(h, DP_STAGE_MD, st);
     if (thermo_row || s == nsteps) {
-      launch_vv(n, types, mm, dt_fs, F, v, x, false, st);
+      launch_vv(n, types, mm, dt_fs, F, v, x, false, chk, st);
       if (thermo_row) launch_thermo(n, types, mm, vol, s, v, E, Wv, thermo + 6 * row++, st);
       opened = false;
     } else {
-      launch_vv_merged(n, types, mm, dt_fs, F, v, x, st);
+      launch_vv_merged(n, types, mm, dt_fs, F, v, x, chk, st);
       opened = true;
     }
   }
@@ -1291,11 +1303,12 @@ int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const dou
         b[kSW1 + j] = (int)(o + j);
         b[kSB1 + j] = (int)(o + hidden + j);
       }
-      for (int p = 0; p < kP2; p++) {
-        int f = pos_feature(p, h->s0);
-        if (f < 0) continue;
-        b[kSB2 + p] = (int)(o + 2 * hidden + (size_t)hidden * M + f);
-        for (int j = 0; j < hidden; j++) b[kSW2 + j * kSW2Stride + p] = (int)(o + 2 * hidden + (size_t)j * M + f);
+      for (int f = 0; f < M; f++) {
+        b[kSB2 + f] = (int)(o + 2 * hidden + (size_t)hidden * M + f);
+        for (int j = 0; j < hidden; j++) {
+          b[kSW2 + j * kP2 + f] = (int)(o + 2 * hidden + (size_t)j * M + f);
+          b[kSW2T + f * kP0 + j] = (int)(o + 2 * hidden + (size_t)j * M + f);
+        }
       }
     }
     HIPCHECK(h, hipMalloc(&h->d_student_map, sizeof(int) * map.size()));

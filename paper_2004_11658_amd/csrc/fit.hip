@@ -522,56 +522,79 @@ void launch_zero(double* p, size_t n, hipStream_t st) {
 }
 
 // Per frame, fixed-order sums of E_i and the per-centre virials: block (c, f) sums the
-// atoms [c * kRedChunk, (c + 1) * kRedChunk) of frame f into partial row (f, c); the block
+// atoms [c * kRedChunk, (c + 1) * kRedChunk) of frame f (one per thread; wave sums by
+// butterfly shuffles, then the four waves in order) into partial row (f, c); the block
 // that finishes last for frame f (a per-frame counter) adds the partial rows in chunk
 // order and resets the counter, so the result does not depend on block scheduling.
-constexpr int kRedChunk = 1024;
+constexpr int kRedChunk = 256;
 
-__global__ __launch_bounds__(256) void k_frame_reduce(const Frame* __restrict__ frames,
-                                                      const int* __restrict__ row_of,
-                                                      const double* __restrict__ Ei,
-                                                      const double* __restrict__ vir,
-                                                      double* __restrict__ atom_energy,
-                                                      double* __restrict__ part, int* __restrict__ done,
-                                                      double* __restrict__ energies, double* __restrict__ virials) {
-  __shared__ double sh[256][10];
+__global__ __launch_bounds__(kRedChunk) void k_frame_reduce(const Frame* __restrict__ frames,
+                                                            const int* __restrict__ row_of,
+                                                            const double* __restrict__ Ei,
+                                                            const double* __restrict__ vir,
+                                                            double* __restrict__ atom_energy,
+                                                            double* __restrict__ part, int* __restrict__ done,
+                                                            double* __restrict__ energies,
+                                                            double* __restrict__ virials) {
+  __shared__ double sh[kRedChunk / 64][10];
   __shared__ int last;
   const int f = blockIdx.y, nchunk = gridDim.x;
   const Frame& F = frames[f];
-  const int beg = F.atom0 + blockIdx.x * kRedChunk;
-  const int end = min(F.atom0 + F.natoms, beg + kRedChunk);
+  const int i = F.atom0 + blockIdx.x * kRedChunk + threadIdx.x;
   double acc[10];
 #pragma unroll
   for (int q = 0; q < 10; q++) acc[q] = 0.0;
-  for (int i = beg + threadIdx.x; i < end; i += 256) {
-    int r = row_of[i];
-    double e = Ei[r];
-    acc[0] += e;
+  if (i < F.atom0 + F.natoms) {
+    const int r = row_of[i];
+    const double e = Ei[r];
+    acc[0] = e;
     if (atom_energy) atom_energy[i] = e;
     if (vir)
 #pragma unroll
-      for (int q = 0; q < 9; q++) acc[1 + q] += vir[(size_t)r * 9 + q];
+      for (int q = 0; q < 9; q++) acc[1 + q] = vir[(size_t)r * 9 + q];
   }
 #pragma unroll
-  for (int q = 0; q < 10; q++) sh[threadIdx.x][q] = acc[q];
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int q = 0; q < 10; q++) acc[q] += __shfl_xor(acc[q], o);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 10; q++) sh[wv][q] = acc[q];
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
+  if (threadIdx.x < 10) {
+    double a = 0.0;
 #pragma unroll
-      for (int q = 0; q < 10; q++) sh[threadIdx.x][q] += sh[threadIdx.x + s][q];
-    __syncthreads();
+    for (int w = 0; w < kRedChunk / 64; w++) a += sh[w][threadIdx.x];
+    part[((size_t)f * nchunk + blockIdx.x) * 10 + threadIdx.x] = a;
   }
-  if (threadIdx.x < 10) part[((size_t)f * nchunk + blockIdx.x) * 10 + threadIdx.x] = sh[0][threadIdx.x];
   __threadfence();   // the partial row is visible device-wide before the count
   __syncthreads();
   if (threadIdx.x == 0) last = atomicAdd(&done[f], 1) == nchunk - 1;
   __syncthreads();
   if (!last) return;
   __threadfence();   // every other block's partial row is visible
+  // the partial rows in a fixed order: thread t adds rows t, t + kRedChunk, ..., then the
+  // same shuffle and wave order as above
+#pragma unroll
+  for (int q = 0; q < 10; q++) acc[q] = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += kRedChunk)
+#pragma unroll
+    for (int q = 0; q < 10; q++) acc[q] += part[((size_t)f * nchunk + c) * 10 + q];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int q = 0; q < 10; q++) acc[q] += __shfl_xor(acc[q], o);
+  __syncthreads();   // sh is reused
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 10; q++) sh[wv][q] = acc[q];
+  __syncthreads();
   const int q = threadIdx.x;
   if (q < 10) {
     double a = 0.0;
-    for (int c = 0; c < nchunk; c++) a += part[((size_t)f * nchunk + c) * 10 + q];
+#pragma unroll
+    for (int w = 0; w < kRedChunk / 64; w++) a += sh[w][q];
     if (q == 0) energies[f] = a;
     else if (virials && vir) virials[f * 9 + q - 1] = a;
   }
@@ -584,7 +607,7 @@ void launch_frame_reduce(int nframes, int max_frame_atoms, const Frame* frames, 
                          const double* Ei, const double* vir_rows, double* energies, double* virials,
                          double* atom_energy, double* part, int* done, hipStream_t st) {
   const int nchunk = frame_reduce_chunks(max_frame_atoms);
-  hipLaunchKernelGGL(k_frame_reduce, dim3(nchunk, nframes), dim3(256), 0, st, frames, row_of, Ei, vir_rows,
+  hipLaunchKernelGGL(k_frame_reduce, dim3(nchunk, nframes), dim3(kRedChunk), 0, st, frames, row_of, Ei, vir_rows,
                      atom_energy, part, done, energies, virials);
 }
 

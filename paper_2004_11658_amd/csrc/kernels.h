@@ -39,11 +39,13 @@ struct NlistArgs {
   double rl2;
   bool skip_rows;   // leave the species-grouped row order as it is (MD after its first step)
   bool cells_zeroed;   // cell counters already cleared by the caller (MD displacement check)
-  int *big, *nbig;  // atoms with more candidates within rc than the first formatting pass holds
+  int *big, *nbig;  // atoms deferred to the second formatting pass (too many candidates or tied
+                    // short keys); nbig[0] is zero on entry and left zero, nbig[1] its pass counter
 };
 size_t scan_sums_ints(int n, int W);
 void launch_nlist(const NlistArgs& a, hipStream_t st);
-void launch_nlist_verlet(const NlistArgs& a, double half_skin, hipStream_t st);
+// disp_done: the skin check (and the clearing of the cell counters) ran with the drift
+void launch_nlist_verlet(const NlistArgs& a, double half_skin, bool disp_done, hipStream_t st);
 void launch_nlist_export(int n, int nm, const int* nlist, const int* eown, const int* eimg,
                          const int* frame_of, const Frame* frames, int* out_j, int* out_img,
                          hipStream_t st);
@@ -73,10 +75,10 @@ constexpr int kBFwd = kBW1F + kBW2F, kBBwd = kBW1B + kBW2B;
 inline constexpr int bnet_u16(int parts) { return 2 * kBFloat + parts * (kBFwd + kBBwd); }
 
 // Student block (1 -> H <= 32 tanh -> M <= 128 affine), zero-padded: W1, b1 at hidden
-// units 0..31, b2 [128] and W2 [32][kP2 + 1] by output feature.
-constexpr int kSW1 = 0, kSB1 = kP0, kSB2 = 2 * kP0, kSW2 = 2 * kP0 + kP2;
-constexpr int kSW2Stride = kP2 + 1;
-constexpr int kStuElems = kSW2 + kP0 * kSW2Stride;
+// units 0..31, b2 [128], W2 [32][128] by (hidden unit, output feature) and its
+// transpose W2T [128][32].
+constexpr int kSW1 = 0, kSB1 = kP0, kSB2 = 2 * kP0, kSW2 = 2 * kP0 + kP2, kSW2T = kSW2 + kP0 * kP2;
+constexpr int kStuElems = kSW2T + kP2 * kP0;
 
 struct EmbedArgs {
   int prec;
@@ -223,11 +225,22 @@ struct MDMass {
   double m[kMaxTypes];
   double inv[kMaxTypes];
 };
+// neighbour-skin check fused into a drift (gate == NULL: none): *gate |= 1 when some
+// atom moved more than sqrt(lim2) from xref; the cell counters c1[nc1], c2[nc2] are cleared
+struct VvCheck {
+  const double* xref;
+  double lim2;
+  int* gate;
+  int nc1;
+  int* c1;
+  int nc2;
+  int* c2;
+};
 // closing half kick of a step + opening half kick and drift of the next; clears F
 void launch_vv_merged(int n, const int* types, const MDMass& mass, double dt, double* F, double* v, double* x,
-                      hipStream_t st);
+                      const VvCheck& chk, hipStream_t st);
 void launch_vv(int n, const int* types, const MDMass& mass, double dt, const double* F, double* v,
-               double* x, bool drift, hipStream_t st);
+               double* x, bool drift, const VvCheck& chk, hipStream_t st);
 void launch_thermo(int n, const int* types, const MDMass& mass, double volume, int step,
                    const double* v, const double* E, const double* W, double* row, hipStream_t st);
 

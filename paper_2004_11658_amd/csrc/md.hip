@@ -13,36 +13,66 @@ constexpr double kAcc = 9.64853321e-3;    // eV / (A amu) in A / fs^2
 constexpr double kKb = 8.617333262e-5;    // eV / K
 constexpr double kEvA3Bar = 1.602176634e6;
 
-// v += (dt/2) F / m; optionally x += dt v
-__global__ void k_vv(int n, const int* __restrict__ types, MDMass mass, double half_dt_acc,
-                     double dt, const double* __restrict__ F, double* __restrict__ v,
-                     double* __restrict__ x, int drift) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= 3 * n) return;
-  int i = q / 3;
-  int t = types[i];
-  double im = (t >= 0 && t < kMaxTypes) ? mass.inv[t] : 0.0;
-  double vv = v[q] + half_dt_acc * F[q] * im;
-  v[q] = vv;
-  if (drift) x[q] += dt * vv;
+// After a drift: flag (*gate |= 1) when some atom moved more than half the neighbour
+// skin since the last list build (or has a non-finite coordinate), and clear the cell
+// counters for the rebuild that may follow.  gate == NULL: no check.
+__device__ __forceinline__ void vv_check(const VvCheck& c, int i, int n, const double* __restrict__ x) {
+  if (!c.gate) return;
+  for (int q = i; q < c.nc1 || q < c.nc2; q += gridDim.x * blockDim.x) {
+    if (q < c.nc1) c.c1[q] = 0;
+    if (q < c.nc2) c.c2[q] = 0;
+  }
+  bool moved = false;
+  if (i < n) {
+    const double d0 = x[3 * i] - c.xref[3 * i], d1 = x[3 * i + 1] - c.xref[3 * i + 1],
+                 d2 = x[3 * i + 2] - c.xref[3 * i + 2];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    moved = !(r2 <= c.lim2);
+  }
+  if (__ballot(moved) && (threadIdx.x & 63) == 0) atomicOr(c.gate, 1);
+}
+
+// v += (dt/2) F / m; optionally x += dt v (one thread per atom)
+__global__ __launch_bounds__(256) void k_vv(int n, const int* __restrict__ types, MDMass mass, double half_dt_acc,
+                                            double dt, const double* __restrict__ F, double* __restrict__ v,
+                                            double* __restrict__ x, int drift, VvCheck chk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int t = types[i];
+    const double im = (t >= 0 && t < kMaxTypes) ? mass.inv[t] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const int q = 3 * i + c;
+      const double vv = v[q] + half_dt_acc * F[q] * im;
+      v[q] = vv;
+      if (drift) x[q] += dt * vv;
+    }
+  }
+  if (drift) vv_check(chk, i, n, x);
 }
 
 // the closing half kick of one step and the opening half kick and drift of the next in
 // one pass (the two half kicks are added one after the other, exactly as two launches
 // would); F is consumed and cleared for the next force evaluation
-__global__ void k_vv2(int n, const int* __restrict__ types, MDMass mass, double half_dt_acc, double dt,
-                      double* __restrict__ F, double* __restrict__ v, double* __restrict__ x) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= 3 * n) return;
-  int i = q / 3;
-  int t = types[i];
-  double im = (t >= 0 && t < kMaxTypes) ? mass.inv[t] : 0.0;
-  const double f = F[q];
-  double vv = v[q] + half_dt_acc * f * im;
-  vv = vv + half_dt_acc * f * im;
-  v[q] = vv;
-  x[q] += dt * vv;
-  F[q] = 0.0;
+__global__ __launch_bounds__(256) void k_vv2(int n, const int* __restrict__ types, MDMass mass, double half_dt_acc,
+                                             double dt, double* __restrict__ F, double* __restrict__ v,
+                                             double* __restrict__ x, VvCheck chk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int t = types[i];
+    const double im = (t >= 0 && t < kMaxTypes) ? mass.inv[t] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const int q = 3 * i + c;
+      const double f = F[q];
+      double vv = v[q] + half_dt_acc * f * im;
+      vv = vv + half_dt_acc * f * im;
+      v[q] = vv;
+      x[q] += dt * vv;
+      F[q] = 0.0;
+    }
+  }
+  vv_check(chk, i, n, x);
 }
 
 // thermo row [step, PE, KE, T, Etot, P(bar)]: one block, fixed-order reduction
@@ -79,15 +109,15 @@ __global__ __launch_bounds__(1024) void k_thermo(int n, const int* __restrict__ 
 }
 
 void launch_vv(int n, const int* types, const MDMass& mass, double dt, const double* F, double* v,
-               double* x, bool drift, hipStream_t st) {
-  hipLaunchKernelGGL(k_vv, dim3((3 * n + 255) / 256), dim3(256), 0, st, n, types, mass, 0.5 * dt * kAcc,
-                     dt, F, v, x, drift ? 1 : 0);
+               double* x, bool drift, const VvCheck& chk, hipStream_t st) {
+  hipLaunchKernelGGL(k_vv, dim3((n + 255) / 256), dim3(256), 0, st, n, types, mass, 0.5 * dt * kAcc,
+                     dt, F, v, x, drift ? 1 : 0, chk);
 }
 
 void launch_vv_merged(int n, const int* types, const MDMass& mass, double dt, double* F, double* v, double* x,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_vv2, dim3((3 * n + 255) / 256), dim3(256), 0, st, n, types, mass, 0.5 * dt * kAcc, dt, F,
-                     v, x);
+                      const VvCheck& chk, hipStream_t st) {
+  hipLaunchKernelGGL(k_vv2, dim3((n + 255) / 256), dim3(256), 0, st, n, types, mass, 0.5 * dt * kAcc, dt, F,
+                     v, x, chk);
 }
 
 void launch_thermo(int n, const int* types, const MDMass& mass, double volume, int step,

@@ -511,7 +511,9 @@ __device__ __forceinline__ void nl_rank32(const unsigned* K, int ncand, int lane
 
 // Rank the staged candidates of atom i by (species, r^2, owner, image) and write its
 // formatted row: per-species blocks of width sel, nearest first, -1 pads (Alg. 1).
-__device__ __forceinline__ void nl_format(int i, int ncand, const ModelC& m, NlRows rows, int lane,
+// Returns false, having written nothing, when 32-bit keys tie and the rows have no room
+// for the full keys (the caller defers the atom to the pass that has).
+__device__ __forceinline__ bool nl_format(int i, int ncand, const ModelC& m, NlRows rows, int lane,
                                           int* __restrict__ nlist, int* __restrict__ nnei,
                                           int* __restrict__ status, const Frame& F,
                                           const double* __restrict__ xe, const int* __restrict__ eown,
@@ -577,6 +579,7 @@ __device__ __forceinline__ void nl_format(int i, int ncand, const ModelC& m, NlR
       ncand = 0;   // formatted: skip the exact ranking
     } else {
       // tied keys: build the full keys for the exact ranking
+      if (!rows.ent) return false;
       const double xi[3] = {xe[3 * i], xe[3 * i + 1], xe[3 * i + 2]};
       for (int q = lane; q < ncand; q += 64) {
         const int e = rows.e[q];
@@ -636,6 +639,7 @@ __device__ __forceinline__ void nl_format(int i, int ncand, const ModelC& m, NlR
     atomicOr(&status[STW_FLAGS], ST_SEL_OVERFLOW);
     atomicAdd(&status[STW_SEL_ROWS], 1);
   }
+  return true;
 }
 
 // Candidates of atom i in the 27 cells around its own: those with r^2 < rcut2 are
@@ -738,20 +742,24 @@ struct NlKArgs {
   const int *vlist, *vcnt;   // Verlet rows (NULL: search the cells)
   int vcap;
   int *nlist, *nnei, *status;
-  int *big, *nbig;           // atoms with more than kNlCap candidates, for the second pass
+  int *big, *nbig;           // atoms deferred to the second pass (more than kNlCap candidates,
+                             // or tied 32-bit keys); *nbig is zero on entry and left zero
+  int* big_done;             // second-pass blocks finished (zero on entry, left zero)
 };
 
-// Formatted list, one wave per atom.  CAP = kNlCap: the main pass (atoms with more
-// candidates are deferred to the list big); CAP = kMaxCand: the second pass over that
-// list (a fixed grid striding over *nbig entries).
+// Formatted list, one wave per atom.  CAP = kNlCap: the main pass with 32-bit keys only
+// (atoms with more candidates, or with tied keys, are deferred to the list big);
+// CAP = kMaxCand: the second pass over that list with the full keys (a fixed grid
+// striding over *nbig entries; its last block to finish clears *nbig).
 template <int CAP>
 __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(NlKArgs A) {
-  __shared__ NlEnt s_ent[kNlWaves][CAP];
+  constexpr bool kMain = CAP <= kNlCap;
+  __shared__ NlEnt s_ent[kNlWaves][kMain ? 1 : CAP];
   __shared__ int s_e[kNlWaves][CAP];
-  __shared__ __align__(16) unsigned s_k[kNlWaves][CAP <= kNlCap ? CAP : 4];
+  __shared__ __align__(16) unsigned s_k[kNlWaves][kMain ? CAP : 4];
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const NlRows rows{s_ent[wv], s_e[wv], CAP <= kNlCap ? s_k[wv] : nullptr, 268435456.0 / A.m.rc2};
+  const NlRows rows{kMain ? nullptr : s_ent[wv], s_e[wv], kMain ? s_k[wv] : nullptr, 268435456.0 / A.m.rc2};
   const bool second = CAP > kNlCap;
   const int nwork = second ? *A.nbig : A.n;
   const int stride = second ? gridDim.x * kNlWaves : nwork;
@@ -770,7 +778,20 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(NlKArgs A) {
       if (lane == 0) A.big[atomicAdd(A.nbig, 1)] = i;
       continue;
     }
-    nl_format(i, ncand, A.m, rows, lane, A.nlist, A.nnei, A.status, F, A.xe, A.eown, A.eimg, A.etype);
+    if (!nl_format(i, ncand, A.m, rows, lane, A.nlist, A.nnei, A.status, F, A.xe, A.eown, A.eimg, A.etype) &&
+        lane == 0)
+      A.big[atomicAdd(A.nbig, 1)] = i;
+  }
+  if (second) {
+    // every block has read *nbig; the last one to finish leaves both counters zero
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      if (atomicAdd(A.big_done, 1) == (int)gridDim.x - 1) {
+        *A.nbig = 0;
+        *A.big_done = 0;
+      }
+    }
   }
 }
 
@@ -801,7 +822,6 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_vbuild(
 
 // both passes of the formatted list
 static void launch_format(const NlKArgs& K, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, K.nbig, 0);
   hipLaunchKernelGGL((k_nlist<kNlCap>), dim3((K.n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, K);
   hipLaunchKernelGGL((k_nlist<kMaxCand>), dim3(64), dim3(64 * kNlWaves), 0, st, K);
 }
@@ -931,6 +951,7 @@ static NlKArgs format_args(const NlistArgs& A) {
   K.status = A.status;
   K.big = A.big;
   K.nbig = A.nbig;
+  K.big_done = A.nbig + 1;
   return K;
 }
 
@@ -987,10 +1008,11 @@ void launch_nlist(const NlistArgs& A, hipStream_t st) {
 // One MD step's list with Verlet reuse: flag a rebuild when some atom moved more
 // than half the skin (A.gate is the flag), rebuild if flagged, then refresh the
 // extended coordinates and format the list within rc from the Verlet rows.
-void launch_nlist_verlet(const NlistArgs& A, double half_skin, hipStream_t st) {
+void launch_nlist_verlet(const NlistArgs& A, double half_skin, bool disp_done, hipStream_t st) {
   const int n = A.n;
-  hipLaunchKernelGGL(k_disp, dim3((n + 255) / 256), dim3(256), 0, st, n, A.x, A.xref, half_skin * half_skin,
-                     (int*)A.gate, A.ncell + 1, A.cell_count, A.ncell, A.cell_fill);
+  if (!disp_done)
+    hipLaunchKernelGGL(k_disp, dim3((n + 255) / 256), dim3(256), 0, st, n, A.x, A.xref, half_skin * half_skin,
+                       (int*)A.gate, A.ncell + 1, A.cell_count, A.ncell, A.cell_fill);
   NlistArgs B = A;
   B.cells_zeroed = true;
   launch_nlist(B, st);

@@ -14,16 +14,21 @@
 // per-neighbour matrix product remains.  Neighbours outside the trained range are
 // left to the full net (the fallback rows of student_infer.hip).
 //
-// One wave per centre; lane (rb, g) (rb = lane % 16, g = lane / 16) takes neighbour rb of
-// each chunk of 16 and the hidden units k = 16 n + 4 g + q (n < 2, q < 4).
+// One wave per centre, four per block and no block-level sharing; lane (rb, g)
+// (rb = lane % 16, g = lane / 16) takes neighbour rb of each chunk of 16 and the hidden
+// units k = 16 n + 4 g + q (n < 2, q < 4).  The student blocks (a few KB per pair) are
+// read from global memory, where they stay cache-resident: W2 [k][f] for the forward
+// product (a wave reads 64 consecutive f) and its transpose W2T [f][k] for the adjoint's
+// (a lane pair per k).  The LDS holds only each wave's per-centre products.
 #include <hip/hip_runtime.h>
 
 #include "embed_common.h"
 
 namespace dp {
 
-constexpr int kStuWaves = 8;
-constexpr int kStuS = 33 * 4;   // per wave: S (or V) rows k < 32, then rbar (or u)
+constexpr int kStuWaves = 4;
+#define GAS_T(T) __attribute__((address_space(1))) T
+constexpr int kStuS = 33 * 8;   // per wave: S rows k < 32 then rbar (stride 4), or V rows with W1, b1 then u (stride 8)
 
 // sum over the 16 lanes of a row (all lanes get the sum): DPP row rotations by 8, 4, 2, 1
 template <int CTRL>
@@ -146,11 +151,10 @@ __device__ __forceinline__ int stu_fetch(const double* __restrict__ xe, const in
   return e;
 }
 
-// feature of output position p (positions (f / s0) * 32 + f % s0), or -1
-__device__ __forceinline__ int pos_feat(int p, int s0) { return (p % kP0) < s0 ? (p / kP0) * s0 + (p % kP0) : -1; }
-
-size_t stu_lds_bytes(int elem, bool bwd) {
-  return (size_t)elem * (kStuElems + kStuWaves * kStuS + (bwd ? kStuWaves * kP2 * 4 : 0));
+// student block of a pair, read through global (not generic) pointers
+template <class T>
+__device__ __forceinline__ const GAS_T(T)* stu_block(const EmbedArgs& A, int pair) {
+  return (const GAS_T(T)*)((const T*)A.snets + (size_t)pair * kStuElems);
 }
 
 // ------------------------------------------------------------------------------------
@@ -158,33 +162,24 @@ size_t stu_lds_bytes(int elem, bool bwd) {
 // ------------------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
-  extern __shared__ __align__(16) char smem[];
-  T* sn = (T*)smem;                                    // the pair's student block
+  __shared__ __align__(16) T s_w[kStuWaves][kStuS];
   const ModelC& m = A.m;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, rb = lane & 15, g = lane >> 4;
-  T* Sw = sn + kStuElems + wv * kStuS;                 // this wave's S and rbar
-  const int r0 = blockIdx.x * kStuWaves;
-  const int alpha = species_of(r0, m.ntypes, A.type_row0);
-  if (alpha < 0) return;   // uniform over the block
-  const int row = r0 + wv;
+  T* Sw = s_w[wv];                                     // this wave's S and rbar
+  const int row = blockIdx.x * kStuWaves + wv;
+  if (row >= A.nrows) return;
+  const int alpha = species_of(row, m.ntypes, A.type_row0);
   const int atom = A.row_atom[row];
-  double xi[3] = {0, 0, 0};
-  if (atom >= 0) {
-    xi[0] = A.xe[3 * atom];
-    xi[1] = A.xe[3 * atom + 1];
-    xi[2] = A.xe[3 * atom + 2];
-  }
-  T tacc[2][4];   // T at positions lane and lane + 64 (unscaled)
+  if (alpha < 0 || atom < 0) return;   // padding row (uniform over the wave)
+  const double xi[3] = {A.xe[3 * atom], A.xe[3 * atom + 1], A.xe[3 * atom + 2]};
+  T tacc[2][4];   // T at features lane and lane + 64 (unscaled)
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
     for (int c = 0; c < 4; c++) tacc[i][c] = (T)0;
   for (int beta = 0; beta < m.ntypes; beta++) {
     const int pair = alpha * m.ntypes + beta;
-    __syncthreads();
-    stage_bytes(sn, (const T*)A.snets + (size_t)pair * kStuElems, (int)sizeof(T) * kStuElems);
-    __syncthreads();
-    if (atom < 0) continue;
+    const auto sn = stu_block<T>(A, pair);
     T w1[8], b1[8];
 #pragma unroll
     for (int j = 0; j < 8; j++) {
@@ -249,32 +244,34 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
         for (int c = 0; c < 4; c++) Sw[32 * 4 + c] = rs[c];
     }
     wave_sync_lds();
-    // T += W2^T S + b2 rbar^T at this lane's two positions
+    // T += W2^T S + b2 rbar^T at this lane's two features (W2 rows read 64 wide)
+    const bool two = lane + 64 < kP2;
+#pragma unroll 8
     for (int kk = 0; kk < 32; kk++) {
       T s4[4];
 #pragma unroll
       for (int c = 0; c < 4; c++) s4[c] = Sw[kk * 4 + c];
-      const T wa = sn[kSW2 + kk * kSW2Stride + lane], wb = sn[kSW2 + kk * kSW2Stride + lane + 64];
+      const T wa = sn[kSW2 + kk * kP2 + lane], wb = two ? sn[kSW2 + kk * kP2 + lane + 64] : (T)0;
 #pragma unroll
       for (int c = 0; c < 4; c++) {
         tacc[0][c] += wa * s4[c];
         tacc[1][c] += wb * s4[c];
       }
     }
+    const T ba = sn[kSB2 + lane], bb = two ? sn[kSB2 + lane + 64] : (T)0;
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-      tacc[0][c] += sn[kSB2 + lane] * Sw[32 * 4 + c];
-      tacc[1][c] += sn[kSB2 + lane + 64] * Sw[32 * 4 + c];
+      tacc[0][c] += ba * Sw[32 * 4 + c];
+      tacc[1][c] += bb * Sw[32 * 4 + c];
     }
     wave_sync_lds();   // Sw is rewritten by the next pair
   }
-  if (atom < 0) return;
   T* Tout = (T*)A.T + (size_t)row * m.M * 4;
   const T scale = (T)m.inv_norm;
 #pragma unroll
   for (int i = 0; i < 2; i++) {
-    const int f = pos_feat(lane + 64 * i, m.s0);
-    if (f >= 0 && f < m.M)
+    const int f = lane + 64 * i;
+    if (f < m.M)
 #pragma unroll
       for (int c = 0; c < 4; c++) Tout[f * 4 + c] = tacc[i][c] * scale;
   }
@@ -283,79 +280,89 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
 // ------------------------------------------------------------------------------------
 // adjoint: forces (scattered with atomics to the neighbours' owners) and per-centre virial
 // ------------------------------------------------------------------------------------
+constexpr int kStuBwdWaves = 8;
+
+// LDS of the adjoint: W2T of two pairs, then per wave V rows (with W1, b1) and u of two
+size_t stu_bwd_lds_bytes(int elem) { return (size_t)elem * (2 * kP2 * kP0 + kStuBwdWaves * 2 * kStuS); }
+
 template <class T>
-__global__ __launch_bounds__(64 * kStuWaves) void k_stu_bwd(EmbedArgs A) {
+__global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
   extern __shared__ __align__(16) char smem[];
-  T* sn = (T*)smem;
+  T* w2s = (T*)smem;                                   // W2T of the pass's two pairs [2][kP2][kP0]
   const ModelC& m = A.m;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, rb = lane & 15, g = lane >> 4;
-  T* Vw = sn + kStuElems + wv * kStuS;                                   // V rows, then u
-  T* gt = sn + kStuElems + kStuWaves * kStuS + wv * kP2 * 4;            // dE/dT at positions
-  const int r0 = blockIdx.x * kStuWaves;
+  T* Vall = w2s + 2 * kP2 * kP0 + wv * 2 * kStuS;     // per pair of the pass: V rows with W1, b1, then u
+  const int r0 = blockIdx.x * kStuBwdWaves;
   const int alpha = species_of(r0, m.ntypes, A.type_row0);
-  if (alpha < 0) return;
-  const int row = r0 + wv;
-  const int atom = A.row_atom[row];
+  if (alpha < 0) return;   // uniform over the block (rows of one species: groups are padded to 64)
+  const int row = __builtin_amdgcn_readfirstlane(r0 + wv);
+  const int atom = row < A.nrows ? A.row_atom[row] : -1;
+  const bool live = atom >= 0;   // padding rows still take part in the block's barriers
+  const int M = m.M;
   double xi[3] = {0, 0, 0};
-  if (atom >= 0) {
+  if (live) {
     xi[0] = A.xe[3 * atom];
     xi[1] = A.xe[3 * atom + 1];
     xi[2] = A.xe[3 * atom + 2];
-    const T* src = (const T*)A.gT + (size_t)row * m.M * 4;
-    for (int q = lane; q < kP2 * 4; q += 64) {
-      const int f = pos_feat(q >> 2, m.s0);
-      gt[q] = (f >= 0 && f < m.M) ? src[f * 4 + (q & 3)] : (T)0;
-    }
   }
+  // dE/dT of this centre [f][4]: wave-uniform and not written by this kernel, so read
+  // through the constant address space (scalar loads into scalar registers)
+  const __attribute__((address_space(4))) T* gt =
+      (const __attribute__((address_space(4))) T*)((const T*)A.gT + (size_t)(live ? row : 0) * M * 4);
   T fi = (T)0;                    // force component g on the centre (lane groups 0..2)
   T vir[3] = {(T)0, (T)0, (T)0};  // virial column g: W[a][g]
   const T inorm = (T)m.inv_norm;
-  for (int beta = 0; beta < m.ntypes; beta++) {
-    const int pair = alpha * m.ntypes + beta;
+  for (int b0 = 0; b0 < m.ntypes; b0 += 2) {
+    const int nb = min(2, m.ntypes - b0);
+    __syncthreads();   // the previous pass's W2T is no longer read
+    for (int q = 0; q < nb; q++)
+      stage_bytes(w2s + q * kP2 * kP0, (const T*)A.snets + (size_t)(alpha * m.ntypes + b0 + q) * kStuElems + kSW2T,
+                  (int)sizeof(T) * kP2 * kP0);
     __syncthreads();
-    stage_bytes(sn, (const T*)A.snets + (size_t)pair * kStuElems, (int)sizeof(T) * kStuElems);
-    __syncthreads();
-    if (atom < 0) continue;
-    // V[k][c] = sum_p W2[k][p] gt[p][c]: the lane pair (2 k, 2 k + 1) takes hidden unit k,
-    // each lane every other position, and the pair adds its halves (DPP quad_perm 1,0,3,2)
+    if (!live) continue;
+    // V_beta[k][c] = sum_f W2[k][f] gt[f][c] with one lane per (beta, k): lanes 0..31 the
+    // pass's first pair, 32..63 its second; dE/dT is the same for both (scalar operands)
     {
-      const int kk = lane >> 1, ph = lane & 1;
+      const int hb = lane >> 5, kk = lane & 31;
+      const T* w = w2s + hb * kP2 * kP0 + kk;
       T v4[4] = {(T)0, (T)0, (T)0, (T)0};
-      const T* w = sn + kSW2 + kk * kSW2Stride;
-      for (int p = ph; p < kP2; p += 2) {
-        const T wp = w[p];
+#pragma unroll 8
+      for (int f = 0; f < M; f++) {
+        const T wf = w[f * kP0];
 #pragma unroll
-        for (int c = 0; c < 4; c++) v4[c] += wp * gt[p * 4 + c];
+        for (int c = 0; c < 4; c++) v4[c] += wf * gt[f * 4 + c];
       }
+      if (hb < nb) {
+        const auto sn = stu_block<T>(A, alpha * m.ntypes + b0 + hb);
+        T* Vb = Vall + hb * kStuS;
 #pragma unroll
-      for (int c = 0; c < 4; c++) v4[c] += dpp_mov<DPP_XOR1>(v4[c]);
-      if (ph == 0)
-#pragma unroll
-        for (int c = 0; c < 4; c++) Vw[kk * 4 + c] = v4[c];
-      // u[c] = sum_p b2[p] gt[p][c]
-      T u[4];
-#pragma unroll
-      for (int c = 0; c < 4; c++) {
-        u[c] = sn[kSB2 + lane] * gt[lane * 4 + c] + sn[kSB2 + lane + 64] * gt[(lane + 64) * 4 + c];
-        u[c] = sum_g(row_sum16(u[c]));
+        for (int c = 0; c < 4; c++) Vb[kk * 8 + c] = v4[c];
+        Vb[kk * 8 + 4] = sn[kSW1 + kk];
+        Vb[kk * 8 + 5] = sn[kSB1 + kk];
       }
-      if (lane == 0)
+      // u_beta[c] = sum_f b2_beta[f] gt[f][c]
+      for (int q = 0; q < nb; q++) {
+        const auto sn = stu_block<T>(A, alpha * m.ntypes + b0 + q);
+        const int f1 = lane + 64;
 #pragma unroll
-        for (int c = 0; c < 4; c++) Vw[32 * 4 + c] = u[c];
+        for (int c = 0; c < 4; c++) {
+          T u = (lane < M ? sn[kSB2 + lane] * gt[lane * 4 + c] : (T)0) +
+                (f1 < M ? sn[kSB2 + f1] * gt[f1 * 4 + c] : (T)0);
+          u = sum_g(row_sum16(u));
+          if (lane == 0) Vall[q * kStuS + 32 * 8 + c] = u;
+        }
+      }
     }
     wave_sync_lds();
-    T w1[8], b1[8], vk[8][4], uu[4];
+    for (int q = 0; q < nb; q++) {
+    const int beta = b0 + q;
+    const int pair = alpha * m.ntypes + beta;
+    const T* Vw = Vall + q * kStuS;
+    // V, W1 and b1 of the lane's hidden units are read from LDS inside the neighbour loop
+    // (held in registers they would cost 48 VGPRs and lower the waves per SIMD)
+    T uu[4];
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int kk = 16 * (j >> 2) + 4 * g + (j & 3);
-      w1[j] = sn[kSW1 + kk];
-      b1[j] = sn[kSB1 + kk];
-#pragma unroll
-      for (int c = 0; c < 4; c++) vk[j][c] = Vw[kk * 4 + c];
-    }
-#pragma unroll
-    for (int c = 0; c < 4; c++) uu[c] = Vw[32 * 4 + c];
-    wave_sync_lds();   // Vw is rewritten by the next pair
+    for (int c = 0; c < 4; c++) uu[c] = Vw[32 * 8 + c];
     const int nn = A.nnei[atom * m.ntypes + beta];
     const int* nl = A.nlist + (size_t)atom * m.nm + m.sel_off[beta];
     double xn[3] = {0, 0, 0};
@@ -379,16 +386,20 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_bwd(EmbedArgs A) {
       }
       // gR[c] = sum_p G[p] gt[p][c] = h . V[:, c] + u[c];  dsl = dE/ds through G
       T gR[4] = {(T)0, (T)0, (T)0, (T)0}, dsp = (T)0;
+      int zo = 0;
+      asm volatile("" : "+s"(zo));   // keeps the V loads inside the loop (not hoisted into registers)
 #pragma unroll
       for (int j = 0; j < 8; j++) {
-        const T h = tanh_t(s * w1[j] + b1[j]);
+        const T* P = Vw + zo + (16 * (j >> 2) + 4 * g + (j & 3)) * 8;
+        const T vk[4] = {P[0], P[1], P[2], P[3]}, w1 = P[4], b1 = P[5];
+        const T h = tanh_t(s * w1 + b1);
         T dh = (T)0;
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-          gR[c] += h * vk[j][c];
-          dh += vk[j][c] * R[c];
+          gR[c] += h * vk[c];
+          dh += vk[c] * R[c];
         }
-        dsp += dh * ((T)1 - h * h) * w1[j];
+        dsp += dh * ((T)1 - h * h) * w1;
       }
 #pragma unroll
       for (int c = 0; c < 4; c++) gR[c] = sum_g(gR[c]) + uu[c];
@@ -409,8 +420,10 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_bwd(EmbedArgs A) {
         for (int a = 0; a < 3; a++) vir[a] -= v.d[a] * gv;   // W[a][g]
       }
     }
+    }
+    wave_sync_lds();   // the V rows are rewritten in the next pass
   }
-  if (atom < 0) return;
+  if (!live) return;
 #pragma unroll
   for (int o = 1; o < 16; o <<= 1) {
     fi += __shfl_xor(fi, o);
@@ -426,16 +439,16 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_bwd(EmbedArgs A) {
 
 template <class T>
 static void stu_fwd_t(const EmbedArgs& a, hipStream_t st) {
-  const size_t sh = stu_lds_bytes(sizeof(T), false);
-  (void)hipFuncSetAttribute((const void*)k_stu_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL(k_stu_fwd<T>, dim3((a.nrows + kStuWaves - 1) / kStuWaves), dim3(64 * kStuWaves), sh, st, a);
+  const int grid = (a.nrows + kStuWaves - 1) / kStuWaves;
+  if (grid > 0) hipLaunchKernelGGL(k_stu_fwd<T>, dim3(grid), dim3(64 * kStuWaves), 0, st, a);
 }
 
 template <class T>
 static void stu_bwd_t(const EmbedArgs& a, hipStream_t st) {
-  const size_t sh = stu_lds_bytes(sizeof(T), true);
+  const int grid = (a.nrows + kStuBwdWaves - 1) / kStuBwdWaves;
+  const size_t sh = stu_bwd_lds_bytes(sizeof(T));
   (void)hipFuncSetAttribute((const void*)k_stu_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL(k_stu_bwd<T>, dim3((a.nrows + kStuWaves - 1) / kStuWaves), dim3(64 * kStuWaves), sh, st, a);
+  if (grid > 0) hipLaunchKernelGGL(k_stu_bwd<T>, dim3(grid), dim3(64 * kStuBwdWaves), sh, st, a);
 }
 
 // The student blocks are FP64 in the FP64 mode and FP32 otherwise: with no per-neighbour
