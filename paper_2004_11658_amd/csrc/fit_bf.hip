@@ -436,10 +436,11 @@ __device__ __forceinline__ float rs4(f4v v) {
 }
 
 constexpr int kTlStride = 68;   // floats per row of the staged T< (bank spread)
+constexpr int kRowF = 68;        // floats per row of the [64][16][4] second-term and T1 tiles (bank spread)
 
 size_t fit_l1_bwd_lds(int parts) {
-  const size_t xs = (size_t)kKS * 4 * parts * 1024, p2 = (size_t)4 * 64 * 64 * 4;
-  return (xs > p2 ? xs : p2) + 64 * 64 * 4 + 64 * kTlStride * 4;
+  const size_t xs = (size_t)kKS * 4 * parts * 1024, p2 = (size_t)4 * 64 * kRowF * 4;
+  return (xs > p2 ? xs : p2) + 64 * kRowF * 4 + 64 * kTlStride * 4;
 }
 
 // the weight fragments of the output tiles (a, a + 1) at k step ks
@@ -454,11 +455,11 @@ template <int PARTS>
 __global__ __launch_bounds__(FT) void k_fit_l1_bwd(FitBfArgs P) {
   extern __shared__ __align__(16) char smem[];
   const int M = P.M;
-  const size_t xs_bytes = (size_t)kKS * 4 * PARTS * 1024, p2_bytes = (size_t)4 * 64 * 64 * 4;
+  const size_t xs_bytes = (size_t)kKS * 4 * PARTS * 1024, p2_bytes = (size_t)4 * 64 * kRowF * 4;
   __bf16* Xs = (__bf16*)smem;
-  float* P2 = (float*)smem;                                                     // after the GEMMs
-  float* T1s = (float*)(smem + (xs_bytes > p2_bytes ? xs_bytes : p2_bytes));   // [64][16][4]
-  float* Tls = T1s + 64 * 64;                                                   // [64][kTlStride]: T<
+  float* P2 = (float*)smem;                                                     // after the GEMMs: [4][64][kRowF]
+  float* T1s = (float*)(smem + (xs_bytes > p2_bytes ? xs_bytes : p2_bytes));   // [64][kRowF]: [16][4] used
+  float* Tls = T1s + 64 * kRowF;                                                // [64][kTlStride]: T<
   const int r0 = blockIdx.x * FR;
   const int sp = fitbf_species(P, r0);
   if (sp < 0) return;
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(FT) void k_fit_l1_bwd(FitBfArgs P) {
         const f4v pv = cv[0] * tl[0] + cv[1] * tl[1] + cv[2] * tl[2] + cv[3] * tl[3];
         const float kk = rs4(pv);
         if (a + c >= 16) P.gT[((size_t)(r0 + 16 * rt + rb) * M + a + c) * 4 + g] = kk;
-        else T1s[((16 * rt + rb) * 16 + a + c) * 4 + g] = kk;
+        else T1s[(16 * rt + rb) * kRowF + (a + c) * 4 + g] = kk;
         // second term, accumulated over the wave's a
         const f4v tv = real[rt] ? tav[c][rt] : z4;
 #pragma unroll
@@ -540,26 +541,27 @@ __global__ __launch_bounds__(FT) void k_fit_l1_bwd(FitBfArgs P) {
   }
   // second-term parts of the 8 waves, added in a fixed order: waves 4..7 hand theirs to
   // waves 0..3, which then hand the pair sums to the final pass
-  float* mine = P2 + (size_t)(w & 3) * 4096;
+  float* mine = P2 + (size_t)(w & 3) * 64 * kRowF;
   __syncthreads();   // every read of the d1 fragments is done; P2 reuses that space
   if (w >= 4)
 #pragma unroll
     for (int rt = 0; rt < 4; rt++)
 #pragma unroll
-      for (int q = 0; q < 4; q++) *(f4v*)(mine + ((16 * rt + rb) * 16 + 4 * g + q) * 4) = p2[rt][q];
+      for (int q = 0; q < 4; q++) *(f4v*)(mine + (16 * rt + rb) * kRowF + (4 * g + q) * 4) = p2[rt][q];
   __syncthreads();
   if (w < 4)
 #pragma unroll
     for (int rt = 0; rt < 4; rt++)
 #pragma unroll
       for (int q = 0; q < 4; q++) {
-        f4v* p = (f4v*)(mine + ((16 * rt + rb) * 16 + 4 * g + q) * 4);
+        f4v* p = (f4v*)(mine + (16 * rt + rb) * kRowF + (4 * g + q) * 4);
         *p = p2[rt][q] + *p;
       }
   __syncthreads();
   for (int e = tid; e < 64 * 64; e += FT) {
-    const int rl = e >> 6, b = (e >> 2) & 15, c = e & 3;
-    const float v = T1s[e] + (((P2[e] + P2[4096 + e]) + P2[8192 + e]) + P2[12288 + e]);
+    const int rl = e >> 6, b = (e >> 2) & 15, c = e & 3, x = rl * kRowF + 4 * b + c;
+    constexpr int S = 64 * kRowF;
+    const float v = T1s[x] + (((P2[x] + P2[S + x]) + P2[2 * S + x]) + P2[3 * S + x]);
     P.gT[((size_t)(r0 + rl) * M + b) * 4 + c] = v;
   }
 }

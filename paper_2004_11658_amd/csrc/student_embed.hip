@@ -28,7 +28,14 @@ namespace dp {
 
 constexpr int kStuWaves = 4;
 #define GAS_T(T) __attribute__((address_space(1))) T
-constexpr int kStuS = 33 * 8;   // per wave: S rows k < 32 then rbar (stride 4), or V rows with W1, b1 then u (stride 8)
+constexpr int kStuS = 37 * 8;   // per wave: S rows k < 32 then rbar (stride 4), or V rows with W1, b1 then u
+// V row k of the adjoint (6 words used) at vrow(k): stride 8, skewed by 4 per group of four
+// rows so that the four lane groups (rows 4 g + r) read different LDS banks, and by 16
+// more for k >= 16 so that the skewed rows never overlap (row 15 ends at 138, row 16
+// starts at 144; row 31 ends at 282)
+__device__ __forceinline__ int vrow(int k) { return 8 * k + 4 * ((k >> 2) & 3) + 16 * (k >> 4); }
+constexpr int kStuU = 284;   // u after the 32 skewed V rows
+constexpr int kW2Pad = 32;           // the second staged W2T starts 32 words later (other banks)
 
 // sum over the 16 lanes of a row (all lanes get the sum): DPP row rotations by 8, 4, 2, 1
 template <int CTRL>
@@ -42,6 +49,19 @@ __device__ __forceinline__ T row_sum16(T v) {
   v += row_rot<0x122>(v);
   v += row_rot<0x121>(v);
   return v;
+}
+
+// one reduce-scatter step over an array of N values: the lane whose "up" bit is set keeps
+// the upper half, its DPP partner (bit clear) the lower half, each adding the partner's copy
+template <class T, int N, int CTRL>
+__device__ __forceinline__ void stu_rs_step(T (&v)[32], bool up) {
+#pragma unroll
+  for (int k = 0; k < N / 2; k++) {
+    const T a = v[k], b = v[k + N / 2];
+    const T send = up ? a : b;
+    const T keep = up ? b : a;
+    v[k] = keep + row_rot<CTRL>(send);
+  }
 }
 
 // sum over the four rows (lane groups g) of the wave, every lane gets the sum:
@@ -225,24 +245,34 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
 #pragma unroll
       for (int c = 0; c < 4; c++) rs[c] += R[c];
     }
-    // sums over the 16 neighbour lanes (each lane group holds all rows for its k)
+    // sums over the 16 neighbour lanes of a lane group: a reduce-scatter of the 32 values
+    // S[j][c] (flat index 4 j + c) leaves lane rb with the full sums of flat indices
+    // 2 rb' and 2 rb' + 1, rb' = the bit-reversed step order below (ror 8, half mirror,
+    // xor 2, xor 1 pair lanes differing in bit 3, 2, 1, 0 of rb)
+    {
+      T v[32];
 #pragma unroll
-    for (int j = 0; j < 8; j++)
+      for (int j = 0; j < 8; j++)
 #pragma unroll
-      for (int c = 0; c < 4; c++) S[j][c] = row_sum16(S[j][c]);
+        for (int c = 0; c < 4; c++) v[4 * j + c] = S[j][c];
+      stu_rs_step<T, 32, DPP_ROR8>(v, (rb & 8) != 0);
+      stu_rs_step<T, 16, DPP_HALF_MIRROR>(v, (rb & 4) != 0);
+      stu_rs_step<T, 8, DPP_XOR2>(v, (rb & 2) != 0);
+      stu_rs_step<T, 4, DPP_XOR1>(v, (rb & 1) != 0);
+      // lane rb holds flat indices 16 b3 + 8 b2 + 4 b1 + 2 b0 + {0, 1} (b = bits of rb)
+      const int base = 16 * ((rb >> 3) & 1) + 8 * ((rb >> 2) & 1) + 4 * ((rb >> 1) & 1) + 2 * (rb & 1);
+#pragma unroll
+      for (int t = 0; t < 2; t++) {
+        const int fl = base + t, j = fl >> 2, c = fl & 3;
+        const int kk = 16 * (j >> 2) + 4 * g + (j & 3);
+        Sw[kk * 4 + c] = v[t];
+      }
+    }
 #pragma unroll
     for (int c = 0; c < 4; c++) rs[c] = row_sum16(rs[c]);
-    if (rb == 0) {
+    if (lane == 0)
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const int kk = 16 * (j >> 2) + 4 * g + (j & 3);
-#pragma unroll
-        for (int c = 0; c < 4; c++) Sw[kk * 4 + c] = S[j][c];
-      }
-      if (g == 0)
-#pragma unroll
-        for (int c = 0; c < 4; c++) Sw[32 * 4 + c] = rs[c];
-    }
+      for (int c = 0; c < 4; c++) Sw[32 * 4 + c] = rs[c];
     wave_sync_lds();
     // T += W2^T S + b2 rbar^T at this lane's two features (W2 rows read 64 wide)
     const bool two = lane + 64 < kP2;
@@ -283,7 +313,7 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
 constexpr int kStuBwdWaves = 8;
 
 // LDS of the adjoint: W2T of two pairs, then per wave V rows (with W1, b1) and u of two
-size_t stu_bwd_lds_bytes(int elem) { return (size_t)elem * (2 * kP2 * kP0 + kStuBwdWaves * 2 * kStuS); }
+size_t stu_bwd_lds_bytes(int elem) { return (size_t)elem * (2 * kP2 * kP0 + kW2Pad + kStuBwdWaves * 2 * kStuS); }
 
 template <class T>
 __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
@@ -291,7 +321,7 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
   T* w2s = (T*)smem;                                   // W2T of the pass's two pairs [2][kP2][kP0]
   const ModelC& m = A.m;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, rb = lane & 15, g = lane >> 4;
-  T* Vall = w2s + 2 * kP2 * kP0 + wv * 2 * kStuS;     // per pair of the pass: V rows with W1, b1, then u
+  T* Vall = w2s + 2 * kP2 * kP0 + kW2Pad + wv * 2 * kStuS;   // per pair of the pass: V rows with W1, b1, then u
   const int r0 = blockIdx.x * kStuBwdWaves;
   const int alpha = species_of(r0, m.ntypes, A.type_row0);
   if (alpha < 0) return;   // uniform over the block (rows of one species: groups are padded to 64)
@@ -316,7 +346,7 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
     const int nb = min(2, m.ntypes - b0);
     __syncthreads();   // the previous pass's W2T is no longer read
     for (int q = 0; q < nb; q++)
-      stage_bytes(w2s + q * kP2 * kP0, (const T*)A.snets + (size_t)(alpha * m.ntypes + b0 + q) * kStuElems + kSW2T,
+      stage_bytes(w2s + q * (kP2 * kP0 + kW2Pad), (const T*)A.snets + (size_t)(alpha * m.ntypes + b0 + q) * kStuElems + kSW2T,
                   (int)sizeof(T) * kP2 * kP0);
     __syncthreads();
     if (!live) continue;
@@ -324,7 +354,7 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
     // pass's first pair, 32..63 its second; dE/dT is the same for both (scalar operands)
     {
       const int hb = lane >> 5, kk = lane & 31;
-      const T* w = w2s + hb * kP2 * kP0 + kk;
+      const T* w = w2s + hb * (kP2 * kP0 + kW2Pad) + kk;
       T v4[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll 8
       for (int f = 0; f < M; f++) {
@@ -336,9 +366,9 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
         const auto sn = stu_block<T>(A, alpha * m.ntypes + b0 + hb);
         T* Vb = Vall + hb * kStuS;
 #pragma unroll
-        for (int c = 0; c < 4; c++) Vb[kk * 8 + c] = v4[c];
-        Vb[kk * 8 + 4] = sn[kSW1 + kk];
-        Vb[kk * 8 + 5] = sn[kSB1 + kk];
+        for (int c = 0; c < 4; c++) Vb[vrow(kk) + c] = v4[c];
+        Vb[vrow(kk) + 4] = sn[kSW1 + kk];
+        Vb[vrow(kk) + 5] = sn[kSB1 + kk];
       }
       // u_beta[c] = sum_f b2_beta[f] gt[f][c]
       for (int q = 0; q < nb; q++) {
@@ -349,7 +379,7 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
           T u = (lane < M ? sn[kSB2 + lane] * gt[lane * 4 + c] : (T)0) +
                 (f1 < M ? sn[kSB2 + f1] * gt[f1 * 4 + c] : (T)0);
           u = sum_g(row_sum16(u));
-          if (lane == 0) Vall[q * kStuS + 32 * 8 + c] = u;
+          if (lane == 0) Vall[q * kStuS + kStuU + c] = u;
         }
       }
     }
@@ -362,7 +392,7 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
     // (held in registers they would cost 48 VGPRs and lower the waves per SIMD)
     T uu[4];
 #pragma unroll
-    for (int c = 0; c < 4; c++) uu[c] = Vw[32 * 8 + c];
+    for (int c = 0; c < 4; c++) uu[c] = Vw[kStuU + c];
     const int nn = A.nnei[atom * m.ntypes + beta];
     const int* nl = A.nlist + (size_t)atom * m.nm + m.sel_off[beta];
     double xn[3] = {0, 0, 0};
@@ -390,7 +420,7 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
       asm volatile("" : "+s"(zo));   // keeps the V loads inside the loop (not hoisted into registers)
 #pragma unroll
       for (int j = 0; j < 8; j++) {
-        const T* P = Vw + zo + (16 * (j >> 2) + 4 * g + (j & 3)) * 8;
+        const T* P = Vw + zo + vrow(16 * (j >> 2) + 4 * g + (j & 3));
         const T vk[4] = {P[0], P[1], P[2], P[3]}, w1 = P[4], b1 = P[5];
         const T h = tanh_t(s * w1 + b1);
         T dh = (T)0;
