@@ -67,7 +67,8 @@ struct dp_handle_s {
 static hipEvent_t prof_event(dp_handle h) {
   if (h->prof_used == h->prof_pool.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    // timing only: no system-scope fence (cache writeback) at each record
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     h->prof_pool.push_back(e);
   }
   return h->prof_pool[h->prof_used++];
@@ -790,7 +791,8 @@ static int stage_frames_and_nlist(dp_handle h, int nframes, const int64_t* off, 
 
 static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, hipStream_t st,
                      double* energies, double* forces, double* virials, double* atom_energy,
-                     bool want_forces, double* T_out, double* gT_out, bool forces_zeroed = false) {
+                     bool want_forces, double* T_out, double* gT_out, bool forces_zeroed = false,
+                     bool want_energy = true, bool fb_zeroed = false) {
   Ws W{(char*)ws, &P};
   EmbedArgs E{};
   E.prec = h->opt.precision;
@@ -822,7 +824,7 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
     E.theta = h->d_theta;
     E.net_off = h->d_net_off;
     E.etype = A.etype;
-    launch_zero_int(E.fb_count, 1, st);
+    if (!fb_zeroed) launch_zero_int(E.fb_count, 1, st);
   }
   {
     StageTimer tm(h, DP_STAGE_EMBED_FWD, st);
@@ -886,7 +888,7 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
     }
   }
   HIPCHECK(h, hipGetLastError());
-  {
+  if (want_energy) {
     StageTimer tm(h, DP_STAGE_REDUCE, st);
     launch_frame_reduce(P.nframes, P.max_frame_atoms, A.frames, A.row_of, F.Ei, want_forces ? E.vir_part : nullptr,
                         energies, virials, atom_energy, W.at<double>(P.o_redpart), W.at<int>(P.o_reddone), st);
@@ -1101,19 +1103,23 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
     chk.nc2 = A.ncell;
     chk.c2 = A.cell_fill;
   }
-  auto force = [&](bool f_zeroed, bool disp_done) -> int {
+  // with the Verlet list, k_update_ext also clears the fallback-row counter of the students
+  int* fb_clear = (verlet && h->student_on) ? W.at<int>(P.o_fbcnt) : nullptr;
+  // energies and virials are summed only when a thermo row needs them
+  auto force = [&](bool f_zeroed, bool disp_done, bool want_energy) -> int {
     if (verlet) {
       StageTimer tm(h, DP_STAGE_NLIST, st);
-      launch_nlist_verlet(A, 0.5 * h->opt.skin, disp_done, st);
+      launch_nlist_verlet(A, 0.5 * h->opt.skin, disp_done, fb_clear, st);
       A.skip_rows = true;   // the species row order is fixed after the first build
       HIPCHECK(h, hipGetLastError());
     } else {
       int r = stage_nlist(h, A, st);
       if (r != DP_OK) return r;
     }
-    return run_model(h, P, A, workspace, st, E, F, Wv, nullptr, true, nullptr, nullptr, f_zeroed);
+    return run_model(h, P, A, workspace, st, E, F, Wv, nullptr, true, nullptr, nullptr, f_zeroed, want_energy,
+                     fb_clear != nullptr);
   };
-  rc = force(false, false);
+  rc = force(false, false, thermo != nullptr);
   if (rc != DP_OK) return rc;
   int row = 0;
   if (thermo) launch_thermo(n, types, mm, vol, 0, v, E, Wv, thermo + 6 * row++, st);
@@ -1126,9 +1132,9 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
       StageTimer tm(h, DP_STAGE_MD, st);
       launch_vv(n, types, mm, dt_fs, F, v, x, true, chk, st);
     }
-    rc = force(opened, true);
-    if (rc != DP_OK) return rc;
     const bool thermo_row = thermo && thermo_every > 0 && s % thermo_every == 0;
+    rc = force(opened, true, thermo_row);
+    if (rc != DP_OK) return rc;
     StageTimer tm(h, DP_STAGE_MD, st);
     if (thermo_row || s == nsteps) {
       launch_vv(n, types, mm, dt_fs, F, v, x, false, chk, st);

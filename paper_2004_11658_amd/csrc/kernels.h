@@ -44,8 +44,9 @@ struct NlistArgs {
 };
 size_t scan_sums_ints(int n, int W);
 void launch_nlist(const NlistArgs& a, hipStream_t st);
-// disp_done: the skin check (and the clearing of the cell counters) ran with the drift
-void launch_nlist_verlet(const NlistArgs& a, double half_skin, bool disp_done, hipStream_t st);
+// disp_done: the skin check (and the clearing of the cell counters) ran with the drift;
+// clear (may be NULL): one int zeroed for the coming evaluation
+void launch_nlist_verlet(const NlistArgs& a, double half_skin, bool disp_done, int* clear, hipStream_t st);
 void launch_nlist_export(int n, int nm, const int* nlist, const int* eown, const int* eimg,
                          const int* frame_of, const Frame* frames, int* out_j, int* out_img,
                          hipStream_t st);

@@ -281,17 +281,12 @@ __device__ __forceinline__ int find_frame(const Frame* __restrict__ fr, int nfra
 // ------------------------------------------------------------------------------------
 // 1. wrap local atoms, validate, count their ghost images
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_wrap(int n, int nframes, const Frame* __restrict__ frames,
-                                              int ntypes, const double* __restrict__ x,
-                                              const int* __restrict__ types,
-                                              int* __restrict__ frame_of,
-                                              double* __restrict__ xw, double* __restrict__ fw,
-                                              int* __restrict__ gcount, int* __restrict__ status,
-                                              const int* __restrict__ gate, int* __restrict__ wk,
-                                              double* __restrict__ xref) {
+__device__ __forceinline__ void wrap_one(int i, int nframes, const Frame* __restrict__ frames, int ntypes,
+                                         const double* __restrict__ x, const int* __restrict__ types,
+                                         int* __restrict__ frame_of, double* __restrict__ xw,
+                                         double* __restrict__ fw, int* __restrict__ gcount,
+                                         int* __restrict__ status, int* __restrict__ wk, double* __restrict__ xref) {
 #pragma clang fp contract(off)
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || (gate && *gate == 0)) return;
   int fi = find_frame(frames, nframes, i);
   frame_of[i] = fi;
   const Frame& F = frames[fi];
@@ -328,19 +323,29 @@ __global__ __launch_bounds__(256) void k_wrap(int n, int nframes, const Frame* _
   gcount[i] = cnt;
 }
 
+__global__ __launch_bounds__(256) void k_wrap(int n, int nframes, const Frame* __restrict__ frames,
+                                              int ntypes, const double* __restrict__ x,
+                                              const int* __restrict__ types,
+                                              int* __restrict__ frame_of,
+                                              double* __restrict__ xw, double* __restrict__ fw,
+                                              int* __restrict__ gcount, int* __restrict__ status,
+                                              const int* __restrict__ gate, int* __restrict__ wk,
+                                              double* __restrict__ xref) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || (gate && *gate == 0)) return;
+  wrap_one(i, nframes, frames, ntypes, x, types, frame_of, xw, fw, gcount, status, wk, xref);
+}
+
 // ------------------------------------------------------------------------------------
 // 2. write the extended arrays (locals then ghosts) and count cell occupancy
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ghost_emit(
-    int n, int ntypes, int ghost_cap, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
+__device__ __forceinline__ void ghost_emit_one(
+    int i, int n, int ntypes, int ghost_cap, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
     const int* __restrict__ types, const double* __restrict__ xw, const double* __restrict__ fw,
     const int* __restrict__ goff, const int* __restrict__ gtotal, double* __restrict__ xe,
     int* __restrict__ eown, int* __restrict__ eimg, int* __restrict__ etype,
-    int* __restrict__ ecell, int* __restrict__ cell_count, int* __restrict__ status,
-    const int* __restrict__ gate, int* __restrict__ eabc) {
+    int* __restrict__ ecell, int* __restrict__ cell_count, int* __restrict__ status, int* __restrict__ eabc) {
 #pragma clang fp contract(off)
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || (gate && *gate == 0)) return;
   if (i == 0 && gtotal[0] > ghost_cap) {
     atomicOr(&status[STW_FLAGS], ST_GHOST_CAP);
     atomicMax(&status[STW_GHOSTS], gtotal[0]);
@@ -387,6 +392,19 @@ __global__ __launch_bounds__(256) void k_ghost_emit(
         }
         q++;
       }
+}
+
+__global__ __launch_bounds__(256) void k_ghost_emit(
+    int n, int ntypes, int ghost_cap, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
+    const int* __restrict__ types, const double* __restrict__ xw, const double* __restrict__ fw,
+    const int* __restrict__ goff, const int* __restrict__ gtotal, double* __restrict__ xe,
+    int* __restrict__ eown, int* __restrict__ eimg, int* __restrict__ etype,
+    int* __restrict__ ecell, int* __restrict__ cell_count, int* __restrict__ status,
+    const int* __restrict__ gate, int* __restrict__ eabc) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || (gate && *gate == 0)) return;
+  ghost_emit_one(i, n, ntypes, ghost_cap, frames, frame_of, types, xw, fw, goff, gtotal, xe, eown, eimg, etype,
+                 ecell, cell_count, status, eabc);
 }
 
 // n_ext = n + min(ghost total, ghost_cap) (ghosts beyond the capacity were not
@@ -504,6 +522,28 @@ __device__ __forceinline__ void nl_rank32(const unsigned* K, int ncand, int lane
     const unsigned x = K[u];
 #pragma unroll
     for (int h = 0; h < NH; h++) r[h] += (int)(x < y[h]);
+  }
+#pragma unroll
+  for (int h = 0; h < 4; h++) rk[h] = h < NH ? r[h] : 0;
+}
+
+// rk[h] = position of candidate lane + 64 h (h < NH) in (32-bit key, staging index)
+// order: a permutation of 0..ncand-1 even where keys tie
+template <int NH>
+__device__ __forceinline__ void nl_rank32_stable(const unsigned* K, int ncand, int lane, int (&rk)[4]) {
+  unsigned y[NH];
+#pragma unroll
+  for (int h = 0; h < NH; h++) {
+    const int q = lane + 64 * h;
+    y[h] = q < ncand ? K[q] : 0u;
+  }
+  int r[NH];
+#pragma unroll
+  for (int h = 0; h < NH; h++) r[h] = 0;
+  for (int u = 0; u < ncand; u++) {
+    const unsigned x = K[u];
+#pragma unroll
+    for (int h = 0; h < NH; h++) r[h] += (int)(x < y[h]) + (int)((x == y[h]) & (u < lane + 64 * h));
   }
 #pragma unroll
   for (int h = 0; h < 4; h++) rk[h] = h < NH ? r[h] : 0;
@@ -796,20 +836,41 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(NlKArgs A) {
 }
 
 // Verlet candidate rows: every extended atom within rl of atom i (rl = rc + skin),
-// in cell order; rebuilt only when *gate != 0.
-__global__ __launch_bounds__(64 * kNlWaves) void k_vbuild(
-    int n, double rl2, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
-    const double* __restrict__ xe, const int* __restrict__ ecell, const int* __restrict__ cell_start,
-    const int* __restrict__ cell_atoms, int* __restrict__ vlist, int* __restrict__ vcnt, int vcap,
-    int* __restrict__ status, const int* __restrict__ gate) {
-  const int wv = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * kNlWaves + wv;
-  if (i >= n || (gate && *gate == 0)) return;
+// rebuilt only when *gate != 0.  Rows of up to kNlCap candidates are stored sorted by
+// (species, r^2 at the build) through 32-bit keys, ties in gather order; larger rows are
+// stored in cell order (the per-step pass then defers their atoms to the exact ranking).
+__device__ __forceinline__ void vbuild_wave(
+    int i, int lane, int* s_e, unsigned* s_k, double rl2, const Frame* __restrict__ frames,
+    const int* __restrict__ frame_of, const double* __restrict__ xe, const int* __restrict__ etype,
+    const int* __restrict__ ecell, const int* __restrict__ cell_start, const int* __restrict__ cell_atoms,
+    int* __restrict__ vlist, int* __restrict__ vcnt, int vcap, int* __restrict__ status) {
   const Frame& F = frames[frame_of[i]];
+  int* vrow = vlist + (size_t)i * vcap;
   int too_close = 0;
-  int cnt = nl_gather_cells<true>(i, F, rl2, xe, nullptr, nullptr, nullptr, ecell, cell_start, cell_atoms, lane,
-                                  NlRows{nullptr, nullptr, nullptr, 0.0}, 0, vlist + (size_t)i * vcap, vcap, too_close);
+  const NlRows rows{nullptr, s_e, s_k, 268435456.0 / rl2};
+  int cnt = nl_gather_cells<false>(i, F, rl2, xe, nullptr, nullptr, etype, ecell, cell_start, cell_atoms, lane, rows,
+                                   kNlCap, nullptr, 0, too_close);
+  if (cnt <= kNlCap) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nh = (cnt + 63) >> 6;
+    int rk[4];
+    if (nh <= 1) nl_rank32_stable<1>(s_k, cnt, lane, rk);
+    else if (nh == 2) nl_rank32_stable<2>(s_k, cnt, lane, rk);
+    else if (nh == 3) nl_rank32_stable<3>(s_k, cnt, lane, rk);
+    else nl_rank32_stable<4>(s_k, cnt, lane, rk);
+    const int lim = cnt < vcap ? cnt : vcap;
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+      const int q = lane + 64 * h;
+      if (q < cnt && rk[h] < lim) vrow[rk[h]] = s_e[q];
+    }
+  } else {
+    too_close = 0;
+    cnt = nl_gather_cells<true>(i, F, rl2, xe, nullptr, nullptr, nullptr, ecell, cell_start, cell_atoms, lane,
+                                NlRows{nullptr, nullptr, nullptr, 0.0}, 0, vrow, vcap, too_close);
+  }
   if (too_close) atomicOr(&status[STW_FLAGS], ST_OVERLAP);
   if (lane == 0) {
     vcnt[i] = cnt < vcap ? cnt : vcap;
@@ -820,6 +881,94 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_vbuild(
   }
 }
 
+__global__ __launch_bounds__(64 * kNlWaves) void k_vbuild(
+    int n, double rl2, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
+    const double* __restrict__ xe, const int* __restrict__ etype, const int* __restrict__ ecell,
+    const int* __restrict__ cell_start, const int* __restrict__ cell_atoms, int* __restrict__ vlist,
+    int* __restrict__ vcnt, int vcap, int* __restrict__ status, const int* __restrict__ gate) {
+  __shared__ int s_e[kNlWaves][kNlCap];
+  __shared__ __align__(16) unsigned s_k[kNlWaves][kNlCap];
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kNlWaves + wv;
+  if (i >= n || (gate && *gate == 0)) return;
+  vbuild_wave(i, lane, s_e[wv], s_k[wv], rl2, frames, frame_of, xe, etype, ecell, cell_start, cell_atoms, vlist,
+              vcnt, vcap, status);
+}
+
+// Per-step list from sorted Verlet rows (MD): the row's candidates still within rc,
+// in the row's order (species, then r^2 at the last build), compacted into the species
+// blocks; -1 pads.  At a build step this is the order of Alg. 1 (up to ties within the
+// 28-bit key); between builds the order is the build's, which changes the descriptor
+// only by summation order (Eq. 4 sums over neighbours).  An atom whose row is unsorted
+// (more than kNlCap candidates) or where a species has more than sel neighbours within
+// rc (the nearest sel must then be chosen at the current distances) is deferred to the
+// exact second pass.
+__global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kNlWaves + wv;
+  if (i >= A.n) return;
+  const ModelC& m = A.m;
+  const int cnt = A.vcnt[i];
+  if (cnt > kNlCap) {
+    if (lane == 0) A.big[atomicAdd(A.nbig, 1)] = i;
+    return;
+  }
+  const int* vrow = A.vlist + (size_t)i * A.vcap;
+  const double xi[3] = {A.xe[3 * i], A.xe[3 * i + 1], A.xe[3 * i + 2]};
+  int* nl = A.nlist + (size_t)i * m.nm;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int tc[kMaxTypes];
+#pragma unroll
+  for (int t = 0; t < kMaxTypes; t++) tc[t] = 0;
+  for (int p0 = 0; p0 < cnt; p0 += 256) {
+    int e[4];
+    double r2[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int p = p0 + 64 * j + lane;
+      e[j] = p < cnt ? vrow[p] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) r2[j] = e[j] >= 0 ? nl_r2(A.xe, e[j], xi) : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      if (p0 + 64 * j >= cnt) break;   // uniform over the wave
+      const bool keep = e[j] >= 0 && r2[j] < m.rc2;
+      const int t = keep ? A.etype[e[j]] : -1;
+#pragma unroll
+      for (int T = 0; T < kMaxTypes; T++) {
+        if (T >= m.ntypes) break;
+        const unsigned long long mk = __ballot(t == T);
+        if (t == T) {
+          const int pos = tc[T] + __popcll(mk & below);
+          if (pos < m.sel[T]) nl[m.sel_off[T] + pos] = e[j];
+        }
+        tc[T] += __popcll(mk);
+      }
+    }
+  }
+  bool ovf = false;
+#pragma unroll
+  for (int T = 0; T < kMaxTypes; T++) ovf |= T < m.ntypes && tc[T] > m.sel[T];
+  if (ovf) {
+    if (lane == 0) A.big[atomicAdd(A.nbig, 1)] = i;
+    return;
+  }
+  for (int k = lane; k < m.nm; k += 64) {
+    int t = 0;
+    while (t + 1 < m.ntypes && k >= m.sel_off[t + 1]) t++;
+    int c = 0;
+#pragma unroll
+    for (int u = 0; u < kMaxTypes; u++) c = (u == t) ? tc[u] : c;
+    if (k - m.sel_off[t] >= c) nl[k] = -1;
+  }
+#pragma unroll
+  for (int t = 0; t < kMaxTypes; t++)
+    if (lane == t && t < m.ntypes) A.nnei[(size_t)i * m.ntypes + t] = tc[t];
+}
+
 // both passes of the formatted list
 static void launch_format(const NlKArgs& K, hipStream_t st) {
   hipLaunchKernelGGL((k_nlist<kNlCap>), dim3((K.n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, K);
@@ -828,16 +977,11 @@ static void launch_format(const NlKArgs& K, hipStream_t st) {
 
 // Extended coordinates at the current positions with the wrap and image integers of
 // the last rebuild (the same arithmetic as k_wrap / k_ghost_emit).
-__global__ __launch_bounds__(256) void k_update_ext(int n, int ne_cap, const int* __restrict__ n_ext,
-                                                    const Frame* __restrict__ frames,
-                                                    const int* __restrict__ frame_of,
-                                                    const double* __restrict__ x, const int* __restrict__ wk,
-                                                    const int* __restrict__ eown, const int* __restrict__ eabc,
-                                                    double* __restrict__ xe, int* __restrict__ gate) {
+__device__ __forceinline__ void update_ext_one(int e, int n, const Frame* __restrict__ frames,
+                                               const int* __restrict__ frame_of, const double* __restrict__ x,
+                                               const int* __restrict__ wk, const int* __restrict__ eown,
+                                               const int* __restrict__ eabc, double* __restrict__ xe) {
 #pragma clang fp contract(off)
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e == 0) *gate = 0;   // the rebuild (if any) is done; the next step's check sets it again
-  if (e >= ne_cap || e >= n_ext[0]) return;
   int i = eown[e];
   const Frame& F = frames[frame_of[i]];
   double s[3], w[3];
@@ -850,6 +994,22 @@ __global__ __launch_bounds__(256) void k_update_ext(int n, int ne_cap, const int
   double g[3];
   shift_of(F, eabc[3 * e], eabc[3 * e + 1], eabc[3 * e + 2], g);
   for (int c = 0; c < 3; c++) xe[3 * e + c] = w[c] + g[c];
+}
+
+__global__ __launch_bounds__(256) void k_update_ext(int n, int ne_cap, const int* __restrict__ n_ext,
+                                                    const Frame* __restrict__ frames,
+                                                    const int* __restrict__ frame_of,
+                                                    const double* __restrict__ x, const int* __restrict__ wk,
+                                                    const int* __restrict__ eown, const int* __restrict__ eabc,
+                                                    double* __restrict__ xe, int* __restrict__ gate,
+                                                    int* __restrict__ clear) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) {
+    *gate = 0;   // the rebuild (if any) is done; the next step's check sets it again
+    if (clear) *clear = 0;
+  }
+  if (e >= ne_cap || e >= n_ext[0]) return;
+  update_ext_one(e, n, frames, frame_of, x, wk, eown, eabc, xe);
 }
 
 // *flag |= 1 when some atom moved more than half the skin since the last rebuild
@@ -983,7 +1143,7 @@ void launch_nlist(const NlistArgs& A, hipStream_t st) {
                      A.n_ext, A.ecell, A.cell_start, A.cell_fill, A.cell_atoms, G);
   if (A.vlist)
     hipLaunchKernelGGL(k_vbuild, dim3((n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, n, A.rl2,
-                       A.frames, A.frame_of, A.xe, A.ecell, A.cell_start, A.cell_atoms, A.vlist, A.vcnt,
+                       A.frames, A.frame_of, A.xe, A.etype, A.ecell, A.cell_start, A.cell_atoms, A.vlist, A.vcnt,
                        A.vcap, A.status, G);
   else
     launch_format(format_args(A), st);
@@ -1008,7 +1168,7 @@ void launch_nlist(const NlistArgs& A, hipStream_t st) {
 // One MD step's list with Verlet reuse: flag a rebuild when some atom moved more
 // than half the skin (A.gate is the flag), rebuild if flagged, then refresh the
 // extended coordinates and format the list within rc from the Verlet rows.
-void launch_nlist_verlet(const NlistArgs& A, double half_skin, bool disp_done, hipStream_t st) {
+void launch_nlist_verlet(const NlistArgs& A, double half_skin, bool disp_done, int* clear, hipStream_t st) {
   const int n = A.n;
   if (!disp_done)
     hipLaunchKernelGGL(k_disp, dim3((n + 255) / 256), dim3(256), 0, st, n, A.x, A.xref, half_skin * half_skin,
@@ -1018,8 +1178,10 @@ void launch_nlist_verlet(const NlistArgs& A, double half_skin, bool disp_done, h
   launch_nlist(B, st);
   int ne_cap = n + A.ghost_cap;
   hipLaunchKernelGGL(k_update_ext, dim3((ne_cap + 255) / 256), dim3(256), 0, st, n, ne_cap, A.n_ext, A.frames,
-                     A.frame_of, A.x, A.wk, A.eown, A.eabc, A.xe, (int*)A.gate);
-  launch_format(format_args(A), st);
+                     A.frame_of, A.x, A.wk, A.eown, A.eabc, A.xe, (int*)A.gate, clear);
+  const NlKArgs K = format_args(A);
+  hipLaunchKernelGGL(k_nlist_vstep, dim3((K.n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, K);
+  hipLaunchKernelGGL((k_nlist<kMaxCand>), dim3(64), dim3(64 * kNlWaves), 0, st, K);
 }
 
 // exclusive scan of n ints (out [n], total [1])

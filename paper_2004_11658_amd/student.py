@@ -11,7 +11,9 @@ visits along its own MD trajectory:
      Cholesky on the device), then a short Adam refinement of every parameter with the
      loss gradient kernel (dp_student_loss_grad, dp_adam), kept only if it helps.
 The trained range [s_lo, s_hi] is the [1e-4, 1 - 1e-4] quantile range of the samples
-(rarer, more extreme s values go to the full net); dp_set_student installs the result.
+(rarer, more extreme s values go to the full net), extended upward by half its top value
+with extra uniform points (closer approaches than the sampled frames hold); dp_set_student
+installs the result.
 The installed lower end is 0 when the trained one is tiny (below 1e-6 s_hi, the
 neighbours just inside the cutoff): extrapolating the smooth student from s_lo down to
 0 changes G by at most s_lo max|dG/ds|, and those neighbours enter T through
@@ -93,15 +95,30 @@ def train_pair(model: D.DPModel, alpha: int, beta: int, s: torch.Tensor, hidden:
     return best, best_loss, float(torch.sqrt((G * G).mean()).item()), lo, hi
 
 
+def extend_upward(s: torch.Tensor, margin: float, frac: float, seed: int) -> torch.Tensor:
+    """The samples plus frac * len(s) points spread uniformly over (s_max, s_max (1 + margin)]:
+    s grows as neighbours approach, and MD runs longer than the sampled frames reach closer
+    approaches; the full net is evaluated there like anywhere else."""
+    if margin <= 0 or frac <= 0 or s.numel() == 0:
+        return s
+    hi = float(s.max())
+    rng = np.random.Generator(np.random.PCG64(seed))
+    extra = hi * (1.0 + margin * (1.0 - rng.random(max(1, int(frac * s.numel())))))
+    return torch.cat([s, torch.as_tensor(extra, dtype=s.dtype, device=s.device)])
+
+
 def train_students(model: D.DPModel, frames, hidden: int = 32, n_samples: int = 1_000_000,
-                   seed_sample: int = 405, refine_steps: int = 100):
-    """Train one student per species pair; returns (theta_all, s_lo, s_hi, report)."""
+                   seed_sample: int = 405, refine_steps: int = 100, margin: float = 0.5,
+                   margin_frac: float = 0.05):
+    """Train one student per species pair; returns (theta_all, s_lo, s_hi, report).  The
+    trained range reaches margin * s_max above the largest sampled s (margin_frac more
+    samples there)."""
     samples = gather_samples(model, frames, n_samples, seed_sample)
     nt = model.ntypes
     thetas, los, his, report = [], [], [], {}
     for a in range(nt):
         for b in range(nt):
-            s = samples[(a, b)]
+            s = extend_upward(samples[(a, b)], margin, margin_frac, seed_sample + 1 + a * nt + b)
             th, loss, rms, lo, hi = train_pair(model, a, b, s, hidden, refine_steps)
             thetas.append(th)
             los.append(0.0 if lo < 1e-6 * hi else lo)
