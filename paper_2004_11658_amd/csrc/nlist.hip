@@ -437,6 +437,8 @@ __global__ void k_fill_int(int n, int* __restrict__ p, int v) {
 
 constexpr int kNlWaves = 4;
 constexpr int kNlCap = 256;    // candidates within rc staged in LDS by the main kernels
+constexpr int kVCap = 512;     // candidates within rc + skin sorted in LDS when Verlet rows are built
+constexpr int kSecondPassBlocks = 256;   // grid of the exact second formatting pass (strides over *nbig)
 
 // one candidate in LDS: the 128-bit sort key (species, r^2, owner * nimg + image) as two
 // words compared lexicographically: hi = species << 56 | (bits of r^2) >> 8,
@@ -530,7 +532,7 @@ __device__ __forceinline__ void nl_rank32(const unsigned* K, int ncand, int lane
 // rk[h] = position of candidate lane + 64 h (h < NH) in (32-bit key, staging index)
 // order: a permutation of 0..ncand-1 even where keys tie
 template <int NH>
-__device__ __forceinline__ void nl_rank32_stable(const unsigned* K, int ncand, int lane, int (&rk)[4]) {
+__device__ __forceinline__ void nl_rank32_stable(const unsigned* K, int ncand, int lane, int (&rk)[8]) {
   unsigned y[NH];
 #pragma unroll
   for (int h = 0; h < NH; h++) {
@@ -546,7 +548,7 @@ __device__ __forceinline__ void nl_rank32_stable(const unsigned* K, int ncand, i
     for (int h = 0; h < NH; h++) r[h] += (int)(x < y[h]) + (int)((x == y[h]) & (u < lane + 64 * h));
   }
 #pragma unroll
-  for (int h = 0; h < 4; h++) rk[h] = h < NH ? r[h] : 0;
+  for (int h = 0; h < 8; h++) rk[h] = h < NH ? r[h] : 0;
 }
 
 // Rank the staged candidates of atom i by (species, r^2, owner, image) and write its
@@ -684,6 +686,9 @@ __device__ __forceinline__ bool nl_format(int i, int ncand, const ModelC& m, NlR
 
 // Candidates of atom i in the 27 cells around its own: those with r^2 < rcut2 are
 // appended to the LDS rows (LIST = false) or written to the Verlet row vrow (LIST = true).
+// The cells' members are taken as one index space (cells in (a, b, c) order, members in
+// cell order), 64 lanes per batch and four batches in flight, so the short cells do not
+// each cost a batch and a round of dependent loads.
 template <bool LIST>
 __device__ __forceinline__ int nl_gather_cells(int i, const Frame& F, double rcut2, const double* __restrict__ xe,
                                                const int* __restrict__ eown, const int* __restrict__ eimg,
@@ -693,38 +698,72 @@ __device__ __forceinline__ int nl_gather_cells(int i, const Frame& F, double rcu
                                                int* vrow, int vcap, int& too_close) {
 #pragma clang fp contract(off)
   const double xi0 = xe[3 * i], xi1 = xe[3 * i + 1], xi2 = xe[3 * i + 2];
-  int ci = ecell[i] - F.cell0;
-  int c2 = ci % F.nc[2], c1 = (ci / F.nc[2]) % F.nc[1], c0 = ci / (F.nc[2] * F.nc[1]);
+  const int ci = ecell[i] - F.cell0;
+  const int c2 = ci % F.nc[2], c1 = (ci / F.nc[2]) % F.nc[1], c0 = ci / (F.nc[2] * F.nc[1]);
+  // lane q < 27: member range of cell q = (c0 - 1 + q / 9, c1 - 1 + q / 3 % 3, c2 - 1 + q % 3)
+  int cb = 0, cn = 0;
+  if (lane < 27) {
+    const int a = c0 - 1 + lane / 9, b = c1 - 1 + (lane / 3) % 3, c = c2 - 1 + lane % 3;
+    if (a >= 0 && a < F.nc[0] && b >= 0 && b < F.nc[1] && c >= 0 && c < F.nc[2]) {
+      const int cell = F.cell0 + (a * F.nc[1] + b) * F.nc[2] + c;
+      cb = cell_start[cell];
+      cn = cell_start[cell + 1] - cb;
+    }
+  }
+  int incl = cn;
+#pragma unroll
+  for (int off = 1; off < 32; off <<= 1) {
+    const int y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  const int total = __shfl(incl, 26, 64);
+  const int excl = incl - cn;   // first flattened index of cell q (non-decreasing in q)
   int ncand = 0;
-  for (int a = c0 - 1; a <= c0 + 1; a++) {
-    if (a < 0 || a >= F.nc[0]) continue;
-    for (int b = c1 - 1; b <= c1 + 1; b++) {
-      if (b < 0 || b >= F.nc[1]) continue;
-      for (int c = c2 - 1; c <= c2 + 1; c++) {
-        if (c < 0 || c >= F.nc[2]) continue;
-        int cell = F.cell0 + (a * F.nc[1] + b) * F.nc[2] + c;
-        int beg = cell_start[cell], end = cell_start[cell + 1];
-        for (int p0 = beg; p0 < end; p0 += 64) {
-          int p = p0 + lane;
-          bool keep = false;
-          double r2 = 0.0;
-          int e = -1;
-          if (p < end) {
-            e = cell_atoms[p];
-            double d0 = xe[3 * e] - xi0, d1 = xe[3 * e + 1] - xi1, d2 = xe[3 * e + 2] - xi2;
-            r2 = (d0 * d0 + d1 * d1) + d2 * d2;
-            keep = (r2 < rcut2) && (e != i);
-            if (keep && r2 < 1e-12) too_close = 1;
-          }
-          if constexpr (LIST) {
-            unsigned long long bal = __ballot(keep);
-            int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
-            if (keep && pos < vcap) vrow[pos] = e;
-            ncand += __popcll(bal);
-          } else {
-            ncand = nl_append(keep, r2, e, ncand, lane, F, eown, eimg, etype, rows, cap);
-          }
+  for (int p0 = 0; p0 < total; p0 += 256) {
+    int e[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int p = p0 + 64 * j + lane;
+      // the cell holding p: the last q < 27 with excl[q] <= p (all lanes take part)
+      int q = 0, exq = 0;
+#pragma unroll
+      for (int step = 16; step > 0; step >>= 1) {
+        const int t = q + step;
+        const int ex = __shfl(excl, t < 27 ? t : 26, 64);
+        if (t < 27 && ex <= p) {
+          q = t;
+          exq = ex;
         }
+      }
+      const int cbq = __shfl(cb, q, 64);
+      e[j] = p < total ? cell_atoms[cbq + (p - exq)] : -1;
+    }
+    double d[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+      if (e[j] >= 0) {
+        d[j][0] = xe[3 * e[j]];
+        d[j][1] = xe[3 * e[j] + 1];
+        d[j][2] = xe[3 * e[j] + 2];
+      }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      if (p0 + 64 * j >= total) break;   // uniform over the wave
+      bool keep = false;
+      double r2 = 0.0;
+      if (e[j] >= 0) {
+        const double d0 = d[j][0] - xi0, d1 = d[j][1] - xi1, d2 = d[j][2] - xi2;
+        r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+        keep = (r2 < rcut2) && (e[j] != i);
+        if (keep && r2 < 1e-12) too_close = 1;
+      }
+      if constexpr (LIST) {
+        unsigned long long bal = __ballot(keep);
+        int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
+        if (keep && pos < vcap) vrow[pos] = e[j];
+        ncand += __popcll(bal);
+      } else {
+        ncand = nl_append(keep, r2, e[j], ncand, lane, F, eown, eimg, etype, rows, cap);
       }
     }
   }
@@ -836,7 +875,7 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(NlKArgs A) {
 }
 
 // Verlet candidate rows: every extended atom within rl of atom i (rl = rc + skin),
-// rebuilt only when *gate != 0.  Rows of up to kNlCap candidates are stored sorted by
+// rebuilt only when *gate != 0.  Rows of up to kVCap candidates are stored sorted by
 // (species, r^2 at the build) through 32-bit keys, ties in gather order; larger rows are
 // stored in cell order (the per-step pass then defers their atoms to the exact ranking).
 __device__ __forceinline__ void vbuild_wave(
@@ -849,20 +888,22 @@ __device__ __forceinline__ void vbuild_wave(
   int too_close = 0;
   const NlRows rows{nullptr, s_e, s_k, 268435456.0 / rl2};
   int cnt = nl_gather_cells<false>(i, F, rl2, xe, nullptr, nullptr, etype, ecell, cell_start, cell_atoms, lane, rows,
-                                   kNlCap, nullptr, 0, too_close);
-  if (cnt <= kNlCap) {
+                                   kVCap, nullptr, 0, too_close);
+  if (cnt <= kVCap) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int nh = (cnt + 63) >> 6;
-    int rk[4];
+    int rk[8];
     if (nh <= 1) nl_rank32_stable<1>(s_k, cnt, lane, rk);
     else if (nh == 2) nl_rank32_stable<2>(s_k, cnt, lane, rk);
     else if (nh == 3) nl_rank32_stable<3>(s_k, cnt, lane, rk);
-    else nl_rank32_stable<4>(s_k, cnt, lane, rk);
+    else if (nh == 4) nl_rank32_stable<4>(s_k, cnt, lane, rk);
+    else if (nh <= 6) nl_rank32_stable<6>(s_k, cnt, lane, rk);
+    else nl_rank32_stable<8>(s_k, cnt, lane, rk);
     const int lim = cnt < vcap ? cnt : vcap;
 #pragma unroll
-    for (int h = 0; h < 4; h++) {
+    for (int h = 0; h < 8; h++) {
       const int q = lane + 64 * h;
       if (q < cnt && rk[h] < lim) vrow[rk[h]] = s_e[q];
     }
@@ -886,8 +927,8 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_vbuild(
     const double* __restrict__ xe, const int* __restrict__ etype, const int* __restrict__ ecell,
     const int* __restrict__ cell_start, const int* __restrict__ cell_atoms, int* __restrict__ vlist,
     int* __restrict__ vcnt, int vcap, int* __restrict__ status, const int* __restrict__ gate) {
-  __shared__ int s_e[kNlWaves][kNlCap];
-  __shared__ __align__(16) unsigned s_k[kNlWaves][kNlCap];
+  __shared__ int s_e[kNlWaves][kVCap];
+  __shared__ __align__(16) unsigned s_k[kNlWaves][kVCap];
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * kNlWaves + wv;
@@ -901,7 +942,7 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_vbuild(
 // blocks; -1 pads.  At a build step this is the order of Alg. 1 (up to ties within the
 // 28-bit key); between builds the order is the build's, which changes the descriptor
 // only by summation order (Eq. 4 sums over neighbours).  An atom whose row is unsorted
-// (more than kNlCap candidates) or where a species has more than sel neighbours within
+// (more than kVCap candidates) or where a species has more than sel neighbours within
 // rc (the nearest sel must then be chosen at the current distances) is deferred to the
 // exact second pass.
 __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
@@ -911,7 +952,7 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
   if (i >= A.n) return;
   const ModelC& m = A.m;
   const int cnt = A.vcnt[i];
-  if (cnt > kNlCap) {
+  if (cnt > kVCap) {
     if (lane == 0) A.big[atomicAdd(A.nbig, 1)] = i;
     return;
   }
@@ -972,7 +1013,7 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
 // both passes of the formatted list
 static void launch_format(const NlKArgs& K, hipStream_t st) {
   hipLaunchKernelGGL((k_nlist<kNlCap>), dim3((K.n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, K);
-  hipLaunchKernelGGL((k_nlist<kMaxCand>), dim3(64), dim3(64 * kNlWaves), 0, st, K);
+  hipLaunchKernelGGL((k_nlist<kMaxCand>), dim3(kSecondPassBlocks), dim3(64 * kNlWaves), 0, st, K);
 }
 
 // Extended coordinates at the current positions with the wrap and image integers of
@@ -1181,7 +1222,7 @@ void launch_nlist_verlet(const NlistArgs& A, double half_skin, bool disp_done, i
                      A.frame_of, A.x, A.wk, A.eown, A.eabc, A.xe, (int*)A.gate, clear);
   const NlKArgs K = format_args(A);
   hipLaunchKernelGGL(k_nlist_vstep, dim3((K.n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, K);
-  hipLaunchKernelGGL((k_nlist<kMaxCand>), dim3(64), dim3(64 * kNlWaves), 0, st, K);
+  hipLaunchKernelGGL((k_nlist<kMaxCand>), dim3(kSecondPassBlocks), dim3(64 * kNlWaves), 0, st, K);
 }
 
 // exclusive scan of n ints (out [n], total [1])
