@@ -529,26 +529,68 @@ __device__ __forceinline__ void nl_rank32(const unsigned* K, int ncand, int lane
   for (int h = 0; h < 4; h++) rk[h] = h < NH ? r[h] : 0;
 }
 
-// rk[h] = position of candidate lane + 64 h (h < NH) in (32-bit key, staging index)
-// order: a permutation of 0..ncand-1 even where keys tie
-template <int NH>
-__device__ __forceinline__ void nl_rank32_stable(const unsigned* K, int ncand, int lane, int (&rk)[8]) {
-  unsigned y[NH];
+// Ascending bitonic sort of the wave's 64 K (key, value) pairs, element i = 64 k + lane
+// (pads carry key 0xffffffff and sort to the end).  The network is fixed, so equal keys
+// end in a deterministic order; a pair exchanges only on a strict inequality, so the
+// values stay a permutation.
+template <int K>
+__device__ __forceinline__ void wave_bitonic(unsigned (&key)[K], int (&val)[K], int lane) {
+  constexpr int N = 64 * K;
 #pragma unroll
-  for (int h = 0; h < NH; h++) {
-    const int q = lane + 64 * h;
-    y[h] = q < ncand ? K[q] : 0u;
+  for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
+        const int jr = j >> 6;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+          const int kp = k ^ jr;
+          if (kp > k) {
+            const bool up = ((64 * k + lane) & size) == 0;
+            const bool sw = up ? key[kp] < key[k] : key[kp] > key[k];
+            const unsigned a = key[k], b = key[kp];
+            const int va = val[k], vb = val[kp];
+            key[k] = sw ? b : a;
+            key[kp] = sw ? a : b;
+            val[k] = sw ? vb : va;
+            val[kp] = sw ? va : vb;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+          const unsigned pk = __shfl_xor(key[k], j, 64);
+          const int pv = __shfl_xor(val[k], j, 64);
+          const bool up = ((64 * k + lane) & size) == 0;
+          const bool lower = (lane & j) == 0;
+          const bool take = (lower == up) ? pk < key[k] : pk > key[k];
+          key[k] = take ? pk : key[k];
+          val[k] = take ? pv : val[k];
+        }
+      }
+    }
   }
-  int r[NH];
+}
+
+// Sort the staged (32-bit key, index) rows of one wave (cnt <= 64 K) and write the
+// indices in key order to out[0, min(cnt, lim))
+template <int K>
+__device__ __forceinline__ void wave_sort_rows(const unsigned* sk, const int* se, int cnt, int lane, int* out,
+                                               int lim) {
+  unsigned key[K];
+  int val[K];
 #pragma unroll
-  for (int h = 0; h < NH; h++) r[h] = 0;
-  for (int u = 0; u < ncand; u++) {
-    const unsigned x = K[u];
-#pragma unroll
-    for (int h = 0; h < NH; h++) r[h] += (int)(x < y[h]) + (int)((x == y[h]) & (u < lane + 64 * h));
+  for (int k = 0; k < K; k++) {
+    const int q = 64 * k + lane;
+    key[k] = q < cnt ? sk[q] : 0xffffffffu;
+    val[k] = q < cnt ? se[q] : -1;
   }
+  wave_bitonic<K>(key, val, lane);
 #pragma unroll
-  for (int h = 0; h < 8; h++) rk[h] = h < NH ? r[h] : 0;
+  for (int k = 0; k < K; k++) {
+    const int q = 64 * k + lane;
+    if (q < cnt && q < lim) out[q] = val[k];
+  }
 }
 
 // Rank the staged candidates of atom i by (species, r^2, owner, image) and write its
@@ -876,7 +918,7 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(NlKArgs A) {
 
 // Verlet candidate rows: every extended atom within rl of atom i (rl = rc + skin),
 // rebuilt only when *gate != 0.  Rows of up to kVCap candidates are stored sorted by
-// (species, r^2 at the build) through 32-bit keys, ties in gather order; larger rows are
+// (species, r^2 at the build) through 32-bit keys (a bitonic network); larger rows are
 // stored in cell order (the per-step pass then defers their atoms to the exact ranking).
 __device__ __forceinline__ void vbuild_wave(
     int i, int lane, int* s_e, unsigned* s_k, double rl2, const Frame* __restrict__ frames,
@@ -893,20 +935,11 @@ __device__ __forceinline__ void vbuild_wave(
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int nh = (cnt + 63) >> 6;
-    int rk[8];
-    if (nh <= 1) nl_rank32_stable<1>(s_k, cnt, lane, rk);
-    else if (nh == 2) nl_rank32_stable<2>(s_k, cnt, lane, rk);
-    else if (nh == 3) nl_rank32_stable<3>(s_k, cnt, lane, rk);
-    else if (nh == 4) nl_rank32_stable<4>(s_k, cnt, lane, rk);
-    else if (nh <= 6) nl_rank32_stable<6>(s_k, cnt, lane, rk);
-    else nl_rank32_stable<8>(s_k, cnt, lane, rk);
     const int lim = cnt < vcap ? cnt : vcap;
-#pragma unroll
-    for (int h = 0; h < 8; h++) {
-      const int q = lane + 64 * h;
-      if (q < cnt && rk[h] < lim) vrow[rk[h]] = s_e[q];
-    }
+    if (cnt <= 64) wave_sort_rows<1>(s_k, s_e, cnt, lane, vrow, lim);
+    else if (cnt <= 128) wave_sort_rows<2>(s_k, s_e, cnt, lane, vrow, lim);
+    else if (cnt <= 256) wave_sort_rows<4>(s_k, s_e, cnt, lane, vrow, lim);
+    else wave_sort_rows<8>(s_k, s_e, cnt, lane, vrow, lim);
   } else {
     too_close = 0;
     cnt = nl_gather_cells<true>(i, F, rl2, xe, nullptr, nullptr, nullptr, ecell, cell_start, cell_atoms, lane,
