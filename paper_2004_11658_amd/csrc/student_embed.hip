@@ -64,6 +64,10 @@ __device__ __forceinline__ void stu_rs_step(T (&v)[32], bool up) {
   }
 }
 
+// value of lane src (any lane of the wave)
+__device__ __forceinline__ float wave_shfl(float v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ double wave_shfl(double v, int src) { return __shfl(v, src, 64); }
+
 // sum over the four rows (lane groups g) of the wave, every lane gets the sum:
 // v_permlane32_swap(v, v) pairs each lane with lane +- 32, v_permlane16_swap(v, v)
 // each row with its neighbour row
@@ -214,36 +218,46 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
       for (int c = 0; c < 4; c++) S[j][c] = (T)0;
     const int nn = A.nnei[atom * m.ntypes + beta];
     const int* nl = A.nlist + (size_t)atom * m.nm + m.sel_off[beta];
+    // Environment rows 64 at a time, one neighbour per lane (c0 + lane), then in chunks of
+    // 16 the lane group g of the hidden units takes neighbour rb of the chunk from lane
+    // 16 q + rb: each row is formed once, not once per lane group
     double xn[3] = {0, 0, 0};
-    int en = stu_fetch(A.xe, nl, rb, nn, xn);   // the next chunk's neighbour, fetched a chunk ahead
-    for (int c0 = 0; c0 < nn; c0 += 16) {
+    int en = stu_fetch(A.xe, nl, lane, nn, xn);   // the next 64 neighbours, fetched a pass ahead
+    for (int c0 = 0; c0 < nn; c0 += 64) {
       const int e = en;
       const double xj[3] = {xn[0], xn[1], xn[2]};
-      en = stu_fetch(A.xe, nl, c0 + 16 + rb, nn, xn);
-      T s = (T)0, R[4] = {(T)0, (T)0, (T)0, (T)0};
+      en = stu_fetch(A.xe, nl, c0 + 64 + lane, nn, xn);
+      T sL = (T)0, RL[4] = {(T)0, (T)0, (T)0, (T)0};
       if (e >= 0) {
         StuEnv<T> v;
         stu_env(m, xj, xi, v);
         if (stu_out_of_range(A, pair, (double)v.s)) {
           // left to the full net (fallback list); contributes nothing here
-          if (g == 0) {
-            const int p = atomicAdd(A.fb_count, 1);
-            if (p < A.fb_cap) A.fb_list[p] = make_int2(row, e);
-          }
+          const int p = atomicAdd(A.fb_count, 1);
+          if (p < A.fb_cap) A.fb_list[p] = make_int2(row, e);
         } else {
-          s = v.s;
+          sL = v.s;
 #pragma unroll
-          for (int c = 0; c < 4; c++) R[c] = v.R[c];
+          for (int c = 0; c < 4; c++) RL[c] = v.R[c];
         }
       }
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const T h = tanh_t(s * w1[j] + b1[j]);
+      for (int c = 0; c < 4; c++) rs[c] += RL[c];
 #pragma unroll
-        for (int c = 0; c < 4; c++) S[j][c] += h * R[c];
+      for (int q = 0; q < 4; q++) {
+        if (c0 + 16 * q >= nn) break;   // uniform over the wave
+        const int src = 16 * q + rb;
+        const T s = wave_shfl(sL, src);
+        T R[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) R[c] = wave_shfl(RL[c], src);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const T h = tanh_t(s * w1[j] + b1[j]);
+#pragma unroll
+          for (int c = 0; c < 4; c++) S[j][c] += h * R[c];
+        }
       }
-#pragma unroll
-      for (int c = 0; c < 4; c++) rs[c] += R[c];
     }
     // sums over the 16 neighbour lanes of a lane group: a reduce-scatter of the 32 values
     // S[j][c] (flat index 4 j + c) leaves lane rb with the full sums of flat indices
@@ -269,7 +283,7 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
       }
     }
 #pragma unroll
-    for (int c = 0; c < 4; c++) rs[c] = row_sum16(rs[c]);
+    for (int c = 0; c < 4; c++) rs[c] = sum_g(row_sum16(rs[c]));   // one neighbour per lane: all 64
     if (lane == 0)
 #pragma unroll
       for (int c = 0; c < 4; c++) Sw[32 * 4 + c] = rs[c];
