@@ -903,8 +903,9 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist(NlKArgs A) {
         lane == 0)
       A.big[atomicAdd(A.nbig, 1)] = i;
   }
-  if (second) {
-    // every block has read *nbig; the last one to finish leaves both counters zero
+  if (second && nwork > 0) {
+    // every block has read *nbig; the last one to finish leaves both counters zero (with no
+    // deferred atom there is nothing to reset, and no block pays for the fence)
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();

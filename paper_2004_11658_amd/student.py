@@ -11,7 +11,7 @@ visits along its own MD trajectory:
      Cholesky on the device), then a short Adam refinement of every parameter with the
      loss gradient kernel (dp_student_loss_grad, dp_adam), kept only if it helps.
 The trained range [s_lo, s_hi] is the [1e-4, 1 - 1e-4] quantile range of the samples
-(rarer, more extreme s values go to the full net), extended upward by half its top value
+(rarer, more extreme s values go to the full net), extended upward to twice its top value
 with extra uniform points (closer approaches than the sampled frames hold); dp_set_student
 installs the result.
 The installed lower end is 0 when the trained one is tiny (below 1e-6 s_hi, the
@@ -108,7 +108,7 @@ def extend_upward(s: torch.Tensor, margin: float, frac: float, seed: int) -> tor
 
 
 def train_students(model: D.DPModel, frames, hidden: int = 32, n_samples: int = 1_000_000,
-                   seed_sample: int = 405, refine_steps: int = 100, margin: float = 0.5,
+                   seed_sample: int = 405, refine_steps: int = 100, margin: float = 1.0,
                    margin_frac: float = 0.05):
     """Train one student per species pair; returns (theta_all, s_lo, s_hi, report).  The
     trained range reaches margin * s_max above the largest sampled s (margin_frac more
