@@ -5,8 +5,8 @@ One step = one MD step of the whole hot path: displacement check against the nei
 skin (wrap + ghost images + cell list + candidate rows rebuilt when some atom moved
 more than skin/2), neighbour formatting within rc, embedding forward, descriptor +
 fitting net forward and backward, embedding adjoint with force / virial scatter,
-reductions, and the two velocity-Verlet half kicks and drift.  Inputs are resident in
-HBM before timing.
+energy and virial sums (on the steps that write a thermo row, every 20), and the two
+velocity-Verlet half kicks and drift.  Inputs are resident in HBM before timing.
 
 Each precision mode is timed over the same K steps from the same initial state; the
 headline value is the fastest mode whose force RMSE (relative to FP64 at identical
