@@ -281,7 +281,32 @@ __device__ __forceinline__ int find_frame(const Frame* __restrict__ fr, int nfra
 // ------------------------------------------------------------------------------------
 // 1. wrap local atoms, validate, count their ghost images
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ void wrap_one(int i, int nframes, const Frame* __restrict__ frames, int ntypes,
+// image m = floor(f) of an atom, its wrapped position w and fractional coordinates ff
+__device__ __forceinline__ void wrap_pos(const Frame& F, const double xi[3], int m[3], double w[3], double ff[3]) {
+#pragma clang fp contract(off)
+  double f[3], s[3];
+  frac_of(F, xi, f);
+  for (int k = 0; k < 3; k++) m[k] = (int)floor(f[k]);
+  shift_of(F, m[0], m[1], m[2], s);
+  for (int c = 0; c < 3; c++) w[c] = xi[c] - s[c];
+  frac_of(F, w, ff);
+}
+
+// Ghost images of a wrapped atom: the shell test is a product of one test per
+// dimension, so the images are the products of the shifts n in [-Kg, Kg] that keep
+// ff + n inside [-g, 1 + g) in each dimension, less the atom itself.
+__device__ __forceinline__ int ghost_count(const Frame& F, const double ff[3]) {
+  int c[3];
+  for (int k = 0; k < 3; k++) {
+    c[k] = 0;
+    for (int a = -F.Kg[k]; a <= F.Kg[k]; a++) {
+      const double v = ff[k] + a;
+      c[k] += (v >= -F.g[k] && v < 1.0 + F.g[k]) ? 1 : 0;
+    }
+  }
+  return c[0] * c[1] * c[2] - (in_shell(F, ff, 0, 0, 0) ? 1 : 0);
+}
+__device__ __forceinline__ int wrap_one(int i, int nframes, const Frame* __restrict__ frames, int ntypes,
                                          const double* __restrict__ x, const int* __restrict__ types,
                                          int* __restrict__ frame_of, double* __restrict__ xw,
                                          double* __restrict__ fw, int* __restrict__ gcount,
@@ -299,28 +324,34 @@ __device__ __forceinline__ void wrap_one(int i, int nframes, const Frame* __rest
     atomicOr(&status[STW_FLAGS], bad);
     xi[0] = xi[1] = xi[2] = 0.0;
   }
-  double f[3], s[3], w[3], ff[3];
-  frac_of(F, xi, f);
-  const int m0 = (int)floor(f[0]), m1 = (int)floor(f[1]), m2 = (int)floor(f[2]);
-  shift_of(F, m0, m1, m2, s);
+  int m[3];
+  double w[3], ff[3];
+  wrap_pos(F, xi, m, w, ff);
   if (wk) {
-    wk[3 * i] = m0;
-    wk[3 * i + 1] = m1;
-    wk[3 * i + 2] = m2;
+    for (int c = 0; c < 3; c++) wk[3 * i + c] = m[c];
     for (int c = 0; c < 3; c++) xref[3 * i + c] = xi[c];
   }
-  for (int c = 0; c < 3; c++) w[c] = xi[c] - s[c];
-  frac_of(F, w, ff);
   for (int c = 0; c < 3; c++) {
     xw[3 * i + c] = w[c];
     fw[3 * i + c] = ff[c];
   }
-  int cnt = 0;
-  for (int a = -F.Kg[0]; a <= F.Kg[0]; a++)
-    for (int b = -F.Kg[1]; b <= F.Kg[1]; b++)
-      for (int c = -F.Kg[2]; c <= F.Kg[2]; c++)
-        if ((a | b | c) != 0 && in_shell(F, ff, a, b, c)) cnt++;
+  const int cnt = ghost_count(F, ff);
   gcount[i] = cnt;
+  return cnt;
+}
+
+// the ghost count of atom j as wrap_one finds it, without its stores
+__device__ __forceinline__ int ghost_count_of(int j, int nframes, const Frame* __restrict__ frames, int ntypes,
+                                              const double* __restrict__ x, const int* __restrict__ types) {
+  const Frame& F = frames[find_frame(frames, nframes, j)];
+  double xi[3] = {x[3 * j], x[3 * j + 1], x[3 * j + 2]};
+  const int t = types[j];
+  if (t < 0 || t >= ntypes || !isfinite(xi[0]) || !isfinite(xi[1]) || !isfinite(xi[2]))
+    xi[0] = xi[1] = xi[2] = 0.0;
+  int m[3];
+  double w[3], ff[3];
+  wrap_pos(F, xi, m, w, ff);
+  return ghost_count(F, ff);
 }
 
 __global__ __launch_bounds__(256) void k_wrap(int n, int nframes, const Frame* __restrict__ frames,
@@ -342,14 +373,10 @@ __global__ __launch_bounds__(256) void k_wrap(int n, int nframes, const Frame* _
 __device__ __forceinline__ void ghost_emit_one(
     int i, int n, int ntypes, int ghost_cap, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
     const int* __restrict__ types, const double* __restrict__ xw, const double* __restrict__ fw,
-    const int* __restrict__ goff, const int* __restrict__ gtotal, double* __restrict__ xe,
+    int q, double* __restrict__ xe,
     int* __restrict__ eown, int* __restrict__ eimg, int* __restrict__ etype,
-    int* __restrict__ ecell, int* __restrict__ cell_count, int* __restrict__ status, int* __restrict__ eabc) {
+    int* __restrict__ ecell, int* __restrict__ cell_count, int* __restrict__ eabc) {
 #pragma clang fp contract(off)
-  if (i == 0 && gtotal[0] > ghost_cap) {
-    atomicOr(&status[STW_FLAGS], ST_GHOST_CAP);
-    atomicMax(&status[STW_GHOSTS], gtotal[0]);
-  }
   const Frame& F = frames[frame_of[i]];
   double w[3] = {xw[3 * i], xw[3 * i + 1], xw[3 * i + 2]};
   double f[3] = {fw[3 * i], fw[3 * i + 1], fw[3 * i + 2]};
@@ -363,7 +390,6 @@ __device__ __forceinline__ void ghost_emit_one(
   ecell[i] = cl;
   atomicAdd(&cell_count[cl], 1);
   if (eabc) eabc[3 * i] = eabc[3 * i + 1] = eabc[3 * i + 2] = 0;
-  int q = goff[i];
   for (int a = -F.Kg[0]; a <= F.Kg[0]; a++)
     for (int b = -F.Kg[1]; b <= F.Kg[1]; b++)
       for (int c = -F.Kg[2]; c <= F.Kg[2]; c++) {
@@ -403,8 +429,71 @@ __global__ __launch_bounds__(256) void k_ghost_emit(
     const int* __restrict__ gate, int* __restrict__ eabc) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || (gate && *gate == 0)) return;
-  ghost_emit_one(i, n, ntypes, ghost_cap, frames, frame_of, types, xw, fw, goff, gtotal, xe, eown, eimg, etype,
-                 ecell, cell_count, status, eabc);
+  if (i == 0 && gtotal[0] > ghost_cap) {
+    atomicOr(&status[STW_FLAGS], ST_GHOST_CAP);
+    atomicMax(&status[STW_GHOSTS], gtotal[0]);
+  }
+  ghost_emit_one(i, n, ntypes, ghost_cap, frames, frame_of, types, xw, fw, goff[i], xe, eown, eimg, etype, ecell,
+                 cell_count, eabc);
+}
+
+// Systems of at most kOneTile atoms and kCellScanCap cells skip the two scan launches
+// and the wrap launch: every block of the ghost pass recounts the ghost images of the
+// atoms before its own and scans its 256 in registers, and every block of the cell pass scans all cell counts in
+// LDS (block 0 also stores them for the list kernels).  The redundant sums cost a few
+// KB of L2 reads and a few thousand FP64 operations per thread on a rebuild; a step
+// without one saves three launches.
+constexpr int kCellScanCap = 8192;
+
+// exclusive scan of one value per thread over a 256-thread block; *total gets the sum
+__device__ __forceinline__ int block_scan256(int v, int* wsum, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int pre = 0;
+  for (int k = 0; k < w; k++) pre += wsum[k];
+  *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  __syncthreads();
+  return pre + incl - v;
+}
+
+// k_wrap and the ghost pass in one launch: every block wraps its own atoms and recounts
+// the ghost images of the atoms before its own (the same arithmetic, no stores) for its
+// prefix; the ghost pass then runs on the block's own atoms.
+__global__ __launch_bounds__(256) void k_wrap_ghost_scan(
+    int n, int nframes, const Frame* __restrict__ frames, int ntypes, int ghost_cap, const double* __restrict__ x,
+    const int* __restrict__ types, int* __restrict__ frame_of, double* __restrict__ xw, double* __restrict__ fw,
+    int* __restrict__ gcount, int* __restrict__ gtotal, double* __restrict__ xe, int* __restrict__ eown,
+    int* __restrict__ eimg, int* __restrict__ etype, int* __restrict__ ecell, int* __restrict__ cell_count,
+    int* __restrict__ status, const int* __restrict__ gate, int* __restrict__ wk, double* __restrict__ xref,
+    int* __restrict__ eabc) {
+  if (gate && *gate == 0) return;
+  __shared__ int wsum[4];
+  const int t = threadIdx.x, b0 = blockIdx.x * 256, i = b0 + t;
+  int part = 0;
+  for (int j = t; j < b0; j += 256) part += ghost_count_of(j, nframes, frames, ntypes, x, types);
+  int base;
+  (void)block_scan256(part, wsum, &base);
+  const int c = i < n ? wrap_one(i, nframes, frames, ntypes, x, types, frame_of, xw, fw, gcount, status, wk, xref) : 0;
+  int btot;
+  const int q = base + block_scan256(c, wsum, &btot);
+  if (blockIdx.x == gridDim.x - 1 && t == 0) {
+    const int g = base + btot;
+    gtotal[0] = g;
+    if (g > ghost_cap) {
+      atomicOr(&status[STW_FLAGS], ST_GHOST_CAP);
+      atomicMax(&status[STW_GHOSTS], g);
+    }
+  }
+  if (i >= n) return;
+  ghost_emit_one(i, n, ntypes, ghost_cap, frames, frame_of, types, xw, fw, q, xe, eown, eimg, etype, ecell,
+                 cell_count, eabc);
 }
 
 // n_ext = n + min(ghost total, ghost_cap) (ghosts beyond the capacity were not
@@ -425,6 +514,49 @@ __global__ __launch_bounds__(256) void k_cell_place(int n, int ghost_cap, const 
   int c = ecell[e];
   int p = atomicAdd(&cell_fill[c], 1);
   cell_atoms[cell_start[c] + p] = e;
+}
+
+// k_cell_place with the scan of the ncs = ncell + 1 cell counts done by every block in LDS
+__global__ __launch_bounds__(256) void k_cell_place_scan(int n, int ghost_cap, const int* __restrict__ gtotal,
+                                                         int* __restrict__ n_ext, int ncs,
+                                                         const int* __restrict__ cell_count,
+                                                         int* __restrict__ cell_start, int* __restrict__ ctotal,
+                                                         const int* __restrict__ ecell,
+                                                         int* __restrict__ cell_fill,
+                                                         int* __restrict__ cell_atoms,
+                                                         const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int cs[kCellScanCap];
+  __shared__ int wsum[4];
+  const int t = threadIdx.x;
+  const int per = (ncs + 255) / 256, lo = t * per;
+  int tot = 0;
+  for (int k = 0; k < per; k++) {
+    const int qc = lo + k;
+    if (qc < ncs) {
+      cs[qc] = tot;
+      tot += cell_count[qc];
+    }
+  }
+  int all;
+  const int ex = block_scan256(tot, wsum, &all);
+  for (int k = 0; k < per; k++) {
+    const int qc = lo + k;
+    if (qc < ncs) cs[qc] += ex;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int qc = t; qc < ncs; qc += 256) cell_start[qc] = cs[qc];
+    if (t == 0) ctotal[0] = all;
+  }
+  const int g = gtotal[0];
+  const int ne = n + (g < ghost_cap ? g : ghost_cap);
+  const int e = blockIdx.x * 256 + t;
+  if (e == 0) n_ext[0] = ne;
+  if (e >= ne) return;
+  const int c = ecell[e];
+  const int p = atomicAdd(&cell_fill[c], 1);
+  cell_atoms[cs[c] + p] = e;
 }
 
 // ------------------------------------------------------------------------------------
@@ -866,6 +998,7 @@ struct NlKArgs {
   int *big, *nbig;           // atoms deferred to the second pass (more than kNlCap candidates,
                              // or tied 32-bit keys); *nbig is zero on entry and left zero
   int* big_done;             // second-pass blocks finished (zero on entry, left zero)
+  int *gate, *clear;         // per-step filter: re-armed (zeroed) by its first thread, or NULL
 };
 
 // Formatted list, one wave per atom.  CAP = kNlCap: the main pass with 32-bit keys only
@@ -983,6 +1116,11 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * kNlWaves + wv;
+  if (i == 0 && lane == 0) {
+    // the rebuild (if any) and the refresh are done: the next step's check sets the flag
+    if (A.gate) *A.gate = 0;
+    if (A.clear) *A.clear = 0;
+  }
   if (i >= A.n) return;
   const ModelC& m = A.m;
   const int cnt = A.vcnt[i];
@@ -1071,20 +1209,32 @@ __device__ __forceinline__ void update_ext_one(int e, int n, const Frame* __rest
   for (int c = 0; c < 3; c++) xe[3 * e + c] = w[c] + g[c];
 }
 
-__global__ __launch_bounds__(256) void k_update_ext(int n, int ne_cap, const int* __restrict__ n_ext,
-                                                    const Frame* __restrict__ frames,
-                                                    const int* __restrict__ frame_of,
-                                                    const double* __restrict__ x, const int* __restrict__ wk,
-                                                    const int* __restrict__ eown, const int* __restrict__ eabc,
-                                                    double* __restrict__ xe, int* __restrict__ gate,
-                                                    int* __restrict__ clear) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e == 0) {
-    *gate = 0;   // the rebuild (if any) is done; the next step's check sets it again
-    if (clear) *clear = 0;
+// The launch that follows the (gated) rebuild chain of a Verlet step: with the rebuild
+// flag set it builds the Verlet rows, one wave per atom (the ghost pass has just written
+// the extended coordinates from the current positions); otherwise it refreshes the
+// extended coordinates from the moved atoms, one thread per extended atom.  The flag is
+// only read here; the per-step filter that runs next re-arms it.
+__global__ __launch_bounds__(64 * kNlWaves) void k_vbuild_refresh(
+    int n, double rl2, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
+    double* __restrict__ xe, const int* __restrict__ etype, const int* __restrict__ ecell,
+    const int* __restrict__ cell_start, const int* __restrict__ cell_atoms, int* __restrict__ vlist,
+    int* __restrict__ vcnt, int vcap, int* __restrict__ status, const int* __restrict__ gate, int ne_cap,
+    const int* __restrict__ n_ext, const double* __restrict__ x, const int* __restrict__ wk,
+    const int* __restrict__ eown, const int* __restrict__ eabc) {
+  __shared__ int s_e[kNlWaves][kVCap];
+  __shared__ __align__(16) unsigned s_k[kNlWaves][kVCap];
+  if (*gate != 0) {
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * kNlWaves + wv;
+    if (i >= n) return;
+    vbuild_wave(i, lane, s_e[wv], s_k[wv], rl2, frames, frame_of, xe, etype, ecell, cell_start, cell_atoms, vlist,
+                vcnt, vcap, status);
+    return;
   }
-  if (e >= ne_cap || e >= n_ext[0]) return;
-  update_ext_one(e, n, frames, frame_of, x, wk, eown, eabc, xe);
+  const int ne = min(ne_cap, n_ext[0]);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x)
+    update_ext_one(e, n, frames, frame_of, x, wk, eown, eabc, xe);
 }
 
 // *flag |= 1 when some atom moved more than half the skin since the last rebuild
@@ -1199,29 +1349,40 @@ __global__ void k_zero2_gated(int n1, int* __restrict__ p1, int n2, int* __restr
   if (i < n2) p2[i] = 0;
 }
 
-void launch_nlist(const NlistArgs& A, hipStream_t st) {
+// the (gated) rebuild chain; rows_later: the Verlet rows are built by the launch that
+// follows (k_vbuild_refresh)
+static void launch_rebuild(const NlistArgs& A, bool rows_later, hipStream_t st) {
   const int n = A.n;
   const int nb = (n + 255) / 256;
   const int* G = A.gate;
   if (!A.cells_zeroed)
     hipLaunchKernelGGL(k_zero2_gated, dim3((A.ncell + 1 + 255) / 256), dim3(256), 0, st, A.ncell + 1,
                        A.cell_count, A.ncell, A.cell_fill, G);
-  hipLaunchKernelGGL(k_wrap, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes, A.x,
-                     A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status, G, A.wk, A.xref);
-  scan_launch<1>(n, LoadInt{A.gcount}, A.goff, A.scan_sums, A.gtotal, st, G);
-  hipLaunchKernelGGL(k_ghost_emit, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, A.ghost_cap, A.frames, A.frame_of,
-                     A.types, A.xw, A.fw, A.goff, A.gtotal, A.xe, A.eown, A.eimg, A.etype, A.ecell,
-                     A.cell_count, A.status, G, A.eabc);
-  scan_launch<1>(A.ncell + 1, LoadInt{A.cell_count}, A.cell_start, A.scan_sums, A.ctotal, st, G);
-  int ne_cap = n + A.ghost_cap;
-  hipLaunchKernelGGL(k_cell_place, dim3((ne_cap + 255) / 256), dim3(256), 0, st, n, A.ghost_cap, A.gtotal,
-                     A.n_ext, A.ecell, A.cell_start, A.cell_fill, A.cell_atoms, G);
-  if (A.vlist)
+  const int ne_cap = n + A.ghost_cap;
+  if (n <= kOneTile && A.ncell + 1 <= kCellScanCap) {
+    hipLaunchKernelGGL(k_wrap_ghost_scan, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes,
+                       A.ghost_cap, A.x, A.types, A.frame_of, A.xw, A.fw, A.gcount, A.gtotal, A.xe, A.eown, A.eimg,
+                       A.etype, A.ecell, A.cell_count, A.status, G, A.wk, A.xref, A.eabc);
+    hipLaunchKernelGGL(k_cell_place_scan, dim3((ne_cap + 255) / 256), dim3(256), 0, st, n, A.ghost_cap, A.gtotal,
+                       A.n_ext, A.ncell + 1, A.cell_count, A.cell_start, A.ctotal, A.ecell, A.cell_fill,
+                       A.cell_atoms, G);
+  } else {
+    hipLaunchKernelGGL(k_wrap, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes, A.x,
+                       A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status, G, A.wk, A.xref);
+    scan_launch<1>(n, LoadInt{A.gcount}, A.goff, A.scan_sums, A.gtotal, st, G);
+    hipLaunchKernelGGL(k_ghost_emit, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, A.ghost_cap, A.frames,
+                       A.frame_of, A.types, A.xw, A.fw, A.goff, A.gtotal, A.xe, A.eown, A.eimg, A.etype, A.ecell,
+                       A.cell_count, A.status, G, A.eabc);
+    scan_launch<1>(A.ncell + 1, LoadInt{A.cell_count}, A.cell_start, A.scan_sums, A.ctotal, st, G);
+    hipLaunchKernelGGL(k_cell_place, dim3((ne_cap + 255) / 256), dim3(256), 0, st, n, A.ghost_cap, A.gtotal,
+                       A.n_ext, A.ecell, A.cell_start, A.cell_fill, A.cell_atoms, G);
+  }
+  if (!A.vlist)
+    launch_format(format_args(A), st);
+  else if (!rows_later)
     hipLaunchKernelGGL(k_vbuild, dim3((n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, n, A.rl2,
                        A.frames, A.frame_of, A.xe, A.etype, A.ecell, A.cell_start, A.cell_atoms, A.vlist, A.vcnt,
                        A.vcap, A.status, G);
-  else
-    launch_format(format_args(A), st);
   // species-grouped rows (species do not change during MD: built once there)
   if (A.skip_rows) return;
   if (A.m.ntypes == 1) {
@@ -1240,6 +1401,8 @@ void launch_nlist(const NlistArgs& A, hipStream_t st) {
   hipLaunchKernelGGL(k_row_atoms, dim3(nb), dim3(256), 0, st, n, A.row_of, A.row_atom, G);
 }
 
+void launch_nlist(const NlistArgs& A, hipStream_t st) { launch_rebuild(A, false, st); }
+
 // One MD step's list with Verlet reuse: flag a rebuild when some atom moved more
 // than half the skin (A.gate is the flag), rebuild if flagged, then refresh the
 // extended coordinates and format the list within rc from the Verlet rows.
@@ -1250,11 +1413,14 @@ void launch_nlist_verlet(const NlistArgs& A, double half_skin, bool disp_done, i
                        (int*)A.gate, A.ncell + 1, A.cell_count, A.ncell, A.cell_fill);
   NlistArgs B = A;
   B.cells_zeroed = true;
-  launch_nlist(B, st);
-  int ne_cap = n + A.ghost_cap;
-  hipLaunchKernelGGL(k_update_ext, dim3((ne_cap + 255) / 256), dim3(256), 0, st, n, ne_cap, A.n_ext, A.frames,
-                     A.frame_of, A.x, A.wk, A.eown, A.eabc, A.xe, (int*)A.gate, clear);
-  const NlKArgs K = format_args(A);
+  launch_rebuild(B, true, st);
+  const int ne_cap = n + A.ghost_cap;
+  hipLaunchKernelGGL(k_vbuild_refresh, dim3((n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, n, A.rl2,
+                     A.frames, A.frame_of, A.xe, A.etype, A.ecell, A.cell_start, A.cell_atoms, A.vlist, A.vcnt,
+                     A.vcap, A.status, A.gate, ne_cap, A.n_ext, A.x, A.wk, A.eown, A.eabc);
+  NlKArgs K = format_args(A);
+  K.gate = (int*)A.gate;
+  K.clear = clear;
   hipLaunchKernelGGL(k_nlist_vstep, dim3((K.n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, K);
   hipLaunchKernelGGL((k_nlist<kMaxCand>), dim3(kSecondPassBlocks), dim3(64 * kNlWaves), 0, st, K);
 }
