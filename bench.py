@@ -122,6 +122,51 @@ STUDENT_KERNEL = {"fp64": "k_stu_bwd<double>", "fp32": "k_stu_bwd<float>", "bf16
                   "bf16x3": "k_stu_bwd<float>"}
 
 
+def train_bench(args, path, log):
+    """Training steps on a 64-frame ragged water batch (32-1024 molecules per frame):
+    labels are the model's own FP64 energies and forces plus seeded noise; the timed
+    region is whole steps of the training loop and, separately, the parameter gradient."""
+    import numpy as np
+    import torch
+    from paper_2004_11658_amd import inputs as I
+    from paper_2004_11658_amd import dp as D
+    from paper_2004_11658_amd import train as T
+    frames = I.ragged_water_batch(64, 204)
+    coords = np.concatenate([f[0] for f in frames])
+    types = np.concatenate([f[1] for f in frames]).astype(np.int32)
+    boxes = np.stack([f[2] for f in frames])
+    off = np.concatenate([[0], np.cumsum([len(f[1]) for f in frames])]).astype(np.int64)
+    model = D.DPModel(path, "fp64")
+    E, F, _ = model.compute_batch(coords, types, off, boxes)
+    rng = np.random.default_rng(206)
+    Et = E.cpu().numpy() + rng.normal(0.0, 0.5, len(frames))
+    Ft = F.cpu().numpy() + rng.normal(0.0, 0.05, F.shape)
+    log("training batch: %d frames, %d atoms" % (len(frames), len(types)))
+    T.train(model, coords, types, off, boxes, Et, Ft, args.warmup, lr=1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T.train(model, coords, types, off, boxes, Et, Ft, args.train_steps, lr=1e-4)
+    torch.cuda.synchronize()
+    dt_step = (time.perf_counter() - t0) / args.train_steps
+    x = torch.as_tensor(coords, device="cuda")
+    t = torch.as_tensor(types, device="cuda")
+    gE = torch.ones(len(frames), dtype=torch.float64, device="cuda")
+    gF = torch.full((len(types), 3), 0.1, dtype=torch.float64, device="cuda")
+    model.param_grad(x, t, off, boxes, gE, gF)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.train_steps):
+        model.param_grad(x, t, off, boxes, gE, gF)
+    torch.cuda.synchronize()
+    dt_grad = (time.perf_counter() - t0) / args.train_steps
+    n = len(types)
+    print(json.dumps({"metric": "training step (E + F loss, Adam)", "frames": len(frames), "atoms": n,
+                      "steps": args.train_steps, "warmup": args.warmup, "ms_per_step": dt_step * 1e3,
+                      "atoms_per_s": n / dt_step, "param_grad_ms": dt_grad * 1e3,
+                      "param_grad_atoms_per_s": n / dt_grad, "dtype": "f64",
+                      "data": "synthetic"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +180,9 @@ def main():
                     help="neighbour skin (A): the list is rebuilt when some atom moved more than skin/2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=0,
+                    help="instead of MD: time this many training steps (energies and forces, parameter "
+                         "gradient of the E + F loss, Adam) on 64 ragged water frames")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -164,6 +212,9 @@ def main():
     spec = I.WATER
     tmp = tempfile.mkdtemp()
     path = I.write_model(os.path.join(tmp, "water.bin"), spec, I.random_params(spec, 101))
+    if args.train_steps:
+        train_bench(args, path, log)
+        return
     masses = [I.MASS["O"], I.MASS["H"]]
     if args.workload == "water786k":
         coords, types, box = I.config_water786k(205)
