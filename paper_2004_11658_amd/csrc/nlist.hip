@@ -281,32 +281,7 @@ __device__ __forceinline__ int find_frame(const Frame* __restrict__ fr, int nfra
 // ------------------------------------------------------------------------------------
 // 1. wrap local atoms, validate, count their ghost images
 // ------------------------------------------------------------------------------------
-// image m = floor(f) of an atom, its wrapped position w and fractional coordinates ff
-__device__ __forceinline__ void wrap_pos(const Frame& F, const double xi[3], int m[3], double w[3], double ff[3]) {
-#pragma clang fp contract(off)
-  double f[3], s[3];
-  frac_of(F, xi, f);
-  for (int k = 0; k < 3; k++) m[k] = (int)floor(f[k]);
-  shift_of(F, m[0], m[1], m[2], s);
-  for (int c = 0; c < 3; c++) w[c] = xi[c] - s[c];
-  frac_of(F, w, ff);
-}
-
-// Ghost images of a wrapped atom: the shell test is a product of one test per
-// dimension, so the images are the products of the shifts n in [-Kg, Kg] that keep
-// ff + n inside [-g, 1 + g) in each dimension, less the atom itself.
-__device__ __forceinline__ int ghost_count(const Frame& F, const double ff[3]) {
-  int c[3];
-  for (int k = 0; k < 3; k++) {
-    c[k] = 0;
-    for (int a = -F.Kg[k]; a <= F.Kg[k]; a++) {
-      const double v = ff[k] + a;
-      c[k] += (v >= -F.g[k] && v < 1.0 + F.g[k]) ? 1 : 0;
-    }
-  }
-  return c[0] * c[1] * c[2] - (in_shell(F, ff, 0, 0, 0) ? 1 : 0);
-}
-__device__ __forceinline__ int wrap_one(int i, int nframes, const Frame* __restrict__ frames, int ntypes,
+__device__ __forceinline__ void wrap_one(int i, int nframes, const Frame* __restrict__ frames, int ntypes,
                                          const double* __restrict__ x, const int* __restrict__ types,
                                          int* __restrict__ frame_of, double* __restrict__ xw,
                                          double* __restrict__ fw, int* __restrict__ gcount,
@@ -324,34 +299,28 @@ __device__ __forceinline__ int wrap_one(int i, int nframes, const Frame* __restr
     atomicOr(&status[STW_FLAGS], bad);
     xi[0] = xi[1] = xi[2] = 0.0;
   }
-  int m[3];
-  double w[3], ff[3];
-  wrap_pos(F, xi, m, w, ff);
+  double f[3], s[3], w[3], ff[3];
+  frac_of(F, xi, f);
+  const int m0 = (int)floor(f[0]), m1 = (int)floor(f[1]), m2 = (int)floor(f[2]);
+  shift_of(F, m0, m1, m2, s);
   if (wk) {
-    for (int c = 0; c < 3; c++) wk[3 * i + c] = m[c];
+    wk[3 * i] = m0;
+    wk[3 * i + 1] = m1;
+    wk[3 * i + 2] = m2;
     for (int c = 0; c < 3; c++) xref[3 * i + c] = xi[c];
   }
+  for (int c = 0; c < 3; c++) w[c] = xi[c] - s[c];
+  frac_of(F, w, ff);
   for (int c = 0; c < 3; c++) {
     xw[3 * i + c] = w[c];
     fw[3 * i + c] = ff[c];
   }
-  const int cnt = ghost_count(F, ff);
+  int cnt = 0;
+  for (int a = -F.Kg[0]; a <= F.Kg[0]; a++)
+    for (int b = -F.Kg[1]; b <= F.Kg[1]; b++)
+      for (int c = -F.Kg[2]; c <= F.Kg[2]; c++)
+        if ((a | b | c) != 0 && in_shell(F, ff, a, b, c)) cnt++;
   gcount[i] = cnt;
-  return cnt;
-}
-
-// the ghost count of atom j as wrap_one finds it, without its stores
-__device__ __forceinline__ int ghost_count_of(int j, int nframes, const Frame* __restrict__ frames, int ntypes,
-                                              const double* __restrict__ x, const int* __restrict__ types) {
-  const Frame& F = frames[find_frame(frames, nframes, j)];
-  double xi[3] = {x[3 * j], x[3 * j + 1], x[3 * j + 2]};
-  const int t = types[j];
-  if (t < 0 || t >= ntypes || !isfinite(xi[0]) || !isfinite(xi[1]) || !isfinite(xi[2]))
-    xi[0] = xi[1] = xi[2] = 0.0;
-  int m[3];
-  double w[3], ff[3];
-  wrap_pos(F, xi, m, w, ff);
-  return ghost_count(F, ff);
 }
 
 __global__ __launch_bounds__(256) void k_wrap(int n, int nframes, const Frame* __restrict__ frames,
@@ -437,12 +406,11 @@ __global__ __launch_bounds__(256) void k_ghost_emit(
                  cell_count, eabc);
 }
 
-// Systems of at most kOneTile atoms and kCellScanCap cells skip the two scan launches
-// and the wrap launch: every block of the ghost pass recounts the ghost images of the
-// atoms before its own and scans its 256 in registers, and every block of the cell pass scans all cell counts in
+// Systems of at most kOneTile atoms and kCellScanCap cells skip the two scan launches:
+// every block of the ghost pass sums the ghost counts of the atoms before its own and
+// scans its 256 in registers, and every block of the cell pass scans all cell counts in
 // LDS (block 0 also stores them for the list kernels).  The redundant sums cost a few
-// KB of L2 reads and a few thousand FP64 operations per thread on a rebuild; a step
-// without one saves three launches.
+// KB of L2 reads per block on a rebuild; a step without one saves two launches.
 constexpr int kCellScanCap = 8192;
 
 // exclusive scan of one value per thread over a 256-thread block; *total gets the sum
@@ -463,24 +431,21 @@ __device__ __forceinline__ int block_scan256(int v, int* wsum, int* total) {
   return pre + incl - v;
 }
 
-// k_wrap and the ghost pass in one launch: every block wraps its own atoms and recounts
-// the ghost images of the atoms before its own (the same arithmetic, no stores) for its
-// prefix; the ghost pass then runs on the block's own atoms.
-__global__ __launch_bounds__(256) void k_wrap_ghost_scan(
-    int n, int nframes, const Frame* __restrict__ frames, int ntypes, int ghost_cap, const double* __restrict__ x,
-    const int* __restrict__ types, int* __restrict__ frame_of, double* __restrict__ xw, double* __restrict__ fw,
-    int* __restrict__ gcount, int* __restrict__ gtotal, double* __restrict__ xe, int* __restrict__ eown,
-    int* __restrict__ eimg, int* __restrict__ etype, int* __restrict__ ecell, int* __restrict__ cell_count,
-    int* __restrict__ status, const int* __restrict__ gate, int* __restrict__ wk, double* __restrict__ xref,
-    int* __restrict__ eabc) {
+__global__ __launch_bounds__(256) void k_ghost_emit_scan(
+    int n, int ntypes, int ghost_cap, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
+    const int* __restrict__ types, const double* __restrict__ xw, const double* __restrict__ fw,
+    const int* __restrict__ gcount, int* __restrict__ gtotal, double* __restrict__ xe,
+    int* __restrict__ eown, int* __restrict__ eimg, int* __restrict__ etype,
+    int* __restrict__ ecell, int* __restrict__ cell_count, int* __restrict__ status,
+    const int* __restrict__ gate, int* __restrict__ eabc) {
   if (gate && *gate == 0) return;
   __shared__ int wsum[4];
   const int t = threadIdx.x, b0 = blockIdx.x * 256, i = b0 + t;
   int part = 0;
-  for (int j = t; j < b0; j += 256) part += ghost_count_of(j, nframes, frames, ntypes, x, types);
+  for (int j = t; j < b0; j += 256) part += gcount[j];
   int base;
   (void)block_scan256(part, wsum, &base);
-  const int c = i < n ? wrap_one(i, nframes, frames, ntypes, x, types, frame_of, xw, fw, gcount, status, wk, xref) : 0;
+  const int c = i < n ? gcount[i] : 0;
   int btot;
   const int q = base + block_scan256(c, wsum, &btot);
   if (blockIdx.x == gridDim.x - 1 && t == 0) {
@@ -1358,17 +1323,17 @@ static void launch_rebuild(const NlistArgs& A, bool rows_later, hipStream_t st) 
   if (!A.cells_zeroed)
     hipLaunchKernelGGL(k_zero2_gated, dim3((A.ncell + 1 + 255) / 256), dim3(256), 0, st, A.ncell + 1,
                        A.cell_count, A.ncell, A.cell_fill, G);
+  hipLaunchKernelGGL(k_wrap, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes, A.x,
+                     A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status, G, A.wk, A.xref);
   const int ne_cap = n + A.ghost_cap;
   if (n <= kOneTile && A.ncell + 1 <= kCellScanCap) {
-    hipLaunchKernelGGL(k_wrap_ghost_scan, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes,
-                       A.ghost_cap, A.x, A.types, A.frame_of, A.xw, A.fw, A.gcount, A.gtotal, A.xe, A.eown, A.eimg,
-                       A.etype, A.ecell, A.cell_count, A.status, G, A.wk, A.xref, A.eabc);
+    hipLaunchKernelGGL(k_ghost_emit_scan, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, A.ghost_cap, A.frames,
+                       A.frame_of, A.types, A.xw, A.fw, A.gcount, A.gtotal, A.xe, A.eown, A.eimg, A.etype,
+                       A.ecell, A.cell_count, A.status, G, A.eabc);
     hipLaunchKernelGGL(k_cell_place_scan, dim3((ne_cap + 255) / 256), dim3(256), 0, st, n, A.ghost_cap, A.gtotal,
                        A.n_ext, A.ncell + 1, A.cell_count, A.cell_start, A.ctotal, A.ecell, A.cell_fill,
                        A.cell_atoms, G);
   } else {
-    hipLaunchKernelGGL(k_wrap, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes, A.x,
-                       A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status, G, A.wk, A.xref);
     scan_launch<1>(n, LoadInt{A.gcount}, A.goff, A.scan_sums, A.gtotal, st, G);
     hipLaunchKernelGGL(k_ghost_emit, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, A.ghost_cap, A.frames,
                        A.frame_of, A.types, A.xw, A.fw, A.goff, A.gtotal, A.xe, A.eown, A.eimg, A.etype, A.ecell,
