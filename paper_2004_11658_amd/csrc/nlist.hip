@@ -442,7 +442,17 @@ __global__ __launch_bounds__(256) void k_ghost_emit_scan(
   __shared__ int wsum[4];
   const int t = threadIdx.x, b0 = blockIdx.x * 256, i = b0 + t;
   int part = 0;
-  for (int j = t; j < b0; j += 256) part += gcount[j];
+  {
+    // b0 is a multiple of 256 and gcount is 16-byte aligned (checked at launch):
+    // 16-byte loads, four in flight per thread
+    const int4* g4 = (const int4*)gcount;
+    const int nq = b0 >> 2;
+#pragma unroll 4
+    for (int j = t; j < nq; j += 256) {
+      const int4 v = g4[j];
+      part += (v.x + v.y) + (v.z + v.w);
+    }
+  }
   int base;
   (void)block_scan256(part, wsum, &base);
   const int c = i < n ? gcount[i] : 0;
@@ -1326,7 +1336,7 @@ static void launch_rebuild(const NlistArgs& A, bool rows_later, hipStream_t st) 
   hipLaunchKernelGGL(k_wrap, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes, A.x,
                      A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status, G, A.wk, A.xref);
   const int ne_cap = n + A.ghost_cap;
-  if (n <= kOneTile && A.ncell + 1 <= kCellScanCap) {
+  if (n <= kOneTile && A.ncell + 1 <= kCellScanCap && ((uintptr_t)A.gcount & 15) == 0) {
     hipLaunchKernelGGL(k_ghost_emit_scan, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, A.ghost_cap, A.frames,
                        A.frame_of, A.types, A.xw, A.fw, A.gcount, A.gtotal, A.xe, A.eown, A.eimg, A.etype,
                        A.ecell, A.cell_count, A.status, G, A.eabc);
