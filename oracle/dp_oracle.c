@@ -643,11 +643,10 @@ int or_eval(const or_model *m, int64_t n, const double *coords, const int32_t *t
   double *xw = (double *)malloc(24 * n), *fw = (double *)malloc(24 * n);
   wrap_all(&bx, n, coords, xw, fw);
   int nt = g_threads;
+  /* per-thread partial sums, one slot per thread of the team */
   double *Fp = (double *)calloc((size_t)nt * n * 3, sizeof(double));
-  double Wp[64][9];
-  double Ep[64];
-  memset(Wp, 0, sizeof(Wp));
-  memset(Ep, 0, sizeof(Ep));
+  double (*Wp)[9] = (double (*)[9])calloc((size_t)nt, sizeof(double[9]));
+  double *Ep = (double *)calloc((size_t)nt, sizeof(double));
   int ovf = 0;
 #pragma omp parallel num_threads(nt) reduction(| : ovf)
   {
@@ -704,7 +703,7 @@ int or_eval(const or_model *m, int64_t n, const double *coords, const int32_t *t
       for (int t = 0; t < nt; t++) v += Wp[t][q];
       W[q] = v;
     }
-  free(Fp); free(xw); free(fw);
+  free(Fp); free(Wp); free(Ep); free(xw); free(fw);
   return ovf ? 1 : 0;
 }
 

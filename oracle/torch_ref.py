@@ -124,12 +124,12 @@ def decode_img(img: np.ndarray, K):
 
 
 def energy(arch: Arch, theta: torch.Tensor, x: torch.Tensor, types: np.ndarray,
-           box: np.ndarray, nlist: np.ndarray, img: np.ndarray, student=None):
+           box: np.ndarray, nlist: np.ndarray, img: np.ndarray, student=None, out=None):
     """E and E_i of one frame (Eq. 1) for a formatted neighbour list (Alg. 1).
 
     student: optional {(a, b): (theta_s, H, s_lo, s_hi)}: for those species pairs G(s)
     is the student net 1 -> H tanh -> M affine where s_lo <= s <= s_hi and the full
-    net elsewhere."""
+    net elsewhere.  out: optional dict that receives T [n][M][4] (Eq. 4)."""
     n = len(types)
     B = torch.as_tensor(box)
     K = box_K(arch, box)
@@ -164,6 +164,8 @@ def energy(arch: Arch, theta: torch.Tensor, x: torch.Tensor, types: np.ndarray,
     norm = float(arch.nm) if arch.desc_norm == 0 else 1.0
     T = torch.zeros(n, arch.M, 4).index_add(0, torch.as_tensor(ii),
                                             G[:, :, None] * R[:, None, :]) / norm
+    if out is not None:
+        out["T"] = T
     D = torch.einsum("nac,nbc->nab", T, T[:, :arch.m2, :]).reshape(n, -1)   # Eq. 4
     Ei = torch.zeros(n)
     for a in range(arch.ntypes):

@@ -58,9 +58,15 @@ def test_student_loss_grad_and_adam(dp):
 def test_student_learns_a_student_shaped_teacher(dp):
     """Learnability: targets from a net of the student's own shape.  With the teacher's
     hidden layer, the least-squares kernel recovers the output layer exactly; from a
-    perturbed output layer, Adam with the gradient kernel drives the loss to ~0."""
+    perturbed output layer, Adam with the gradient kernel follows the oracle's own Adam
+    loop (same samples, same cosine schedule) down the loss curve.
+
+    Bars: the GPU loop's final loss within 2 % of the oracle loop's, and below
+    1e-4 L0.  The oracle loop itself ends at 1.2e-5 L0 after these 3,000 steps (Adam is
+    first order and the 32 tanh features over s in [0, 1.2] are strongly correlated,
+    so the output-layer problem is ill conditioned); 1e-4 keeps an 8x margin."""
     import torch
-    H, M, n = 32, 100, 20000
+    H, M, n, steps = 32, 100, 4000, 3000
     rng = np.random.default_rng(2)
     teacher = rng.normal(0, 0.5, dp.student_size(H, M))
     teacher[:H] *= 3.0
@@ -76,16 +82,26 @@ def test_student_learns_a_student_shaped_teacher(dp):
     assert float(loss.item()) < 1e-12 * rms2
     pert = teacher.copy()
     pert[2 * H:] += rng.normal(0, 0.05, pert.size - 2 * H)
+    lrs = [3e-3 * (0.001 + 0.999 * 0.5 * (1 + math.cos(math.pi * (k - 1) / steps))) for k in range(1, steps + 1)]
+    # oracle loop
+    tr, mr, vr = pert.copy(), np.zeros_like(pert), np.zeros_like(pert)
+    L0_ref, gr = TR.student_loss_grad(tr, H, M, s, G)
+    for step in range(1, steps + 1):
+        tr, mr, vr = TR.adam_step(tr, mr, vr, gr, step, lrs[step - 1])
+        L_ref, gr = TR.student_loss_grad(tr, H, M, s, G)
+    # GPU loop
     th = d(pert)
     m, v = torch.zeros_like(th), torch.zeros_like(th)
     loss, g, sc = dp.student_loss_grad(H, M, sd, Gd, th)
     L0 = float(loss.item())
-    for step in range(1, 3001):
-        lr = 3e-3 * (0.001 + 0.999 * 0.5 * (1 + math.cos(math.pi * (step - 1) / 3000)))
-        dp.adam_step(th, m, v, g, step, lr)
+    for step in range(1, steps + 1):
+        dp.adam_step(th, m, v, g, step, lrs[step - 1])
         loss, g, sc = dp.student_loss_grad(H, M, sd, Gd, th, sc)
-    print("student loss", L0, "->", float(loss.item()), flush=True)
-    assert float(loss.item()) < 1e-4 * L0
+    L = float(loss.item())
+    print("student loss", L0, "->", L, "oracle loop", L0_ref, "->", L_ref, flush=True)
+    assert abs(L0 - L0_ref) <= 1e-12 * L0_ref
+    assert abs(L - L_ref) <= 0.02 * L_ref
+    assert L < 1e-4 * L0
 
 
 def test_full_net_eval_and_sample_gather(dp, water_model, water192):

@@ -1,7 +1,7 @@
 """Training loop (paper_2004_11658_amd.train): Adam on the energy + force loss through
 the library's batched forces, parameter gradient and Adam kernel, against the same
 loop on the oracle side (PyTorch-CPU FP64 double back propagation for the gradient,
-Adam written out below from Kingma & Ba's definition).
+the oracle's Adam step, pinned by hand-worked steps in test_oracle_pins.py).
 
 Bar: the losses along the trajectory agree to 1e-8 relative, and the final parameters
 to 1e-2 of the learning rate.  Both gradients are exact FP64 derivatives that differ by
@@ -30,14 +30,6 @@ def dp():
     return D
 
 
-def _adam_ref(theta, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
-    m[:] = b1 * m + (1.0 - b1) * g
-    v[:] = b2 * v + (1.0 - b2) * g * g
-    mh = m / (1.0 - b1 ** t)
-    vh = v / (1.0 - b2 ** t)
-    theta -= lr * mh / (np.sqrt(vh) + eps)
-
-
 def test_train_matches_oracle_loop(dp, tiny_model):
     from paper_2004_11658_amd import train as T
     frames = _frames("tiny")
@@ -56,7 +48,7 @@ def test_train_matches_oracle_loop(dp, tiny_model):
     for step in range(1, steps + 1):
         L, g = TR.loss_and_grad(arch, th, ofr, lam)
         ref_losses.append(L)
-        _adam_ref(th, m, v, g, step, lr)
+        th, m, v = TR.adam_step(th, m, v, g, step, lr)
     model = dp.DPModel(tiny_model)
     coords = np.concatenate([f[0] for f in frames])
     types = np.concatenate([f[1] for f in frames])

@@ -554,3 +554,139 @@ def test_student_gradient_and_adam():
         L, g = TR.student_loss_grad(cur, H, M, s, tgt)
         cur, m, v = TR.adam_step(cur, m, v, g, step, 1e-2 if step < 3000 else 1e-3)
     assert L < 1e-5
+
+
+# ---------------------------------------------------------------------------------------
+# Adam (Kingma & Ba 2015, Algorithm 1) by hand, thermo pressure, student substitution,
+# thread-count independence
+# ---------------------------------------------------------------------------------------
+
+def test_adam_two_steps_by_hand():
+    """Two Adam steps worked out by hand from the published definition (beta1 0.9,
+    beta2 0.999, eps 1e-8, lr 0.1).  Step 1: m = 0.1 g, v = 0.001 g^2; the bias
+    corrections divide by 0.1 and 0.001, so the step is lr g / (|g| + eps): 0.1 for
+    g = 0.5 (up to eps) and exactly 0.05 for g = 1e-8 (where eps outside the root
+    matters).  Step 2 with g = -0.25 after 0.5: m = 0.09*0.5 - 0.1*0.25 = 0.02,
+    v = 0.000999*0.25 + 0.001*0.0625 = 0.00031225, corrections 1 - 0.81 = 0.19 and
+    1 - 0.998001 = 0.001999.  A dropped correction or eps under the root fails."""
+    lr = 0.1
+    th0 = np.array([1.0, 1.0])
+    g1 = np.array([0.5, 1e-8])
+    g2 = np.array([-0.25, 1e-8])
+    z = np.zeros(2)
+    th1, m1, v1 = TR.adam_step(th0, z, z, g1, 1, lr)
+    np.testing.assert_allclose(m1, [0.05, 1e-9], rtol=1e-15)
+    np.testing.assert_allclose(v1, [0.00025, 1e-19], rtol=1e-15)
+    step1 = np.array([0.1 * 0.5 / (0.5 + 1e-8), 0.05])
+    np.testing.assert_allclose(th0 - th1, step1, rtol=1e-13)
+    th2, m2, v2 = TR.adam_step(th1, m1, v1, g2, 2, lr)
+    np.testing.assert_allclose(m2[0], 0.02, rtol=1e-14)
+    np.testing.assert_allclose(v2[0], 0.00031225, rtol=1e-14)
+    mh, vh = 0.02 / 0.19, 0.00031225 / 0.001999
+    np.testing.assert_allclose(th1[0] - th2[0], 0.1 * mh / (math.sqrt(vh) + 1e-8), rtol=1e-13)
+    # the second component keeps g = 1e-8: m_hat = 1e-8, v_hat = 1e-16, step lr / 2 again
+    np.testing.assert_allclose(th1[1] - th2[1], 0.05, rtol=1e-12)
+
+
+EV_A3_IN_BAR = 1.602176634e6      # 1 eV/A^3 = 160.2176634 GPa (exact SI definitions)
+
+
+def test_thermo_ideal_gas_pressure():
+    """Zero fitting weights: F = 0 and W = 0, so the thermo pressure is the kinetic one,
+    P V = 2 KE / 3 = (N - 1) k_B T with T over 3N - 3 degrees of freedom.  Two atoms of
+    1 amu at 1 A/fs carry KE = 1/9.64853321e-3 = 103.6427 eV (1 amu A^2/fs^2 in eV)."""
+    spec = TINY
+    p = _zeroed(spec, 22, keep={("emb", 0), ("emb", 1), ("emb", 2), ("out",)})
+    o = Oracle(model_file("zerofit", spec, 22, p))
+    c, t, b = tiny_water(11, 2, 6.3)
+    V = abs(np.linalg.det(b))
+    v = np.zeros_like(c)
+    v[0] = [1.0, 0.0, 0.0]
+    v[1] = [-1.0, 0.0, 0.0]
+    masses = [1.0, 1.0]
+    _, _, th = o.md(c, v, t, masses, b, 0.5, 0, 1)
+    ke = 103.6426965
+    assert abs(th[0, 2] - ke) < 1e-6
+    assert abs(th[0, 5] - 2.0 * ke / (3.0 * V) * EV_A3_IN_BAR) < 1e-9 * abs(th[0, 5])
+    kB = 8.617333262e-5
+    n = len(t)
+    assert abs(th[0, 5] - (n - 1) * kB * th[0, 3] / V * EV_A3_IN_BAR) < 1e-9 * abs(th[0, 5])
+
+
+@pytest.mark.parametrize("tric", [False, True])
+def test_thermo_pressure_is_minus_volume_derivative(tiny_model, tric):
+    """At rest the thermo pressure is tr W / (3 V) (Section 4 reports pressure from the
+    virial); under the isotropic scaling x -> l x, B -> l B this must equal -dE/dV,
+    checked by central differences of the energy (V(l) = l^3 V)."""
+    o = Oracle(tiny_model)
+    c, t, b = tiny_water(11, 2, 6.3)
+    if tric:
+        b = b.copy()
+        b[1, 0] += 0.7
+        b[2, 1] -= 0.4
+        b[2, 0] += 0.3
+    V = np.linalg.det(b)
+    _, _, th = o.md(c, np.zeros_like(c), t, [15.9994, 1.00794], b, 0.5, 0, 1)
+    h = 1e-6
+    Ep = o.eval(c * (1 + h), t, b * (1 + h))["E"]
+    Em = o.eval(c * (1 - h), t, b * (1 - h))["E"]
+    dEdl = (Ep - Em) / (2 * h)
+    P_fd = -dEdl / (3.0 * V) * EV_A3_IN_BAR
+    assert abs(th[0, 5] - P_fd) < 1e-6 * abs(P_fd), (th[0, 5], P_fd)
+    assert th[0, 2] == 0.0
+
+
+def test_student_substitution_empty_range_and_constant_student(tiny_model):
+    """The student substitution of the torch reference: an s range that holds no
+    neighbour leaves E bit-identical to the full net; a constant student (W2 = 0,
+    b2 = c) over the whole range gives the closed form T = c (x) sum_j R_j / N_m
+    (Eq. 4 with G = c) for every centre."""
+    import torch
+    arch = TR.Arch(tiny_model)
+    o = Oracle(tiny_model)
+    c, t, b = tiny_water(11, 2, 6.3)
+    nl, img, _, _ = o.nlist(c, t, b)
+    theta = torch.as_tensor(arch.params)
+    x = torch.as_tensor(c)
+    E_full, _ = TR.energy(arch, theta, x, t, b, nl, img)
+    H, M = 4, arch.M
+    rng = np.random.default_rng(3)
+    ths = rng.normal(0, 0.5, TR.student_layout(H, M)["size"])
+    empty = {(a, bb): (ths, H, -2.0, -1.0) for a in range(2) for bb in range(2)}
+    E_empty, _ = TR.energy(arch, theta, x, t, b, nl, img, student=empty)
+    assert float(E_empty) == float(E_full)
+    cvec = rng.normal(0, 1, M)
+    const = np.zeros_like(ths)
+    const[2 * H + H * M:] = cvec
+    full_range = {(a, bb): (const, H, 0.0, 1e9) for a in range(2) for bb in range(2)}
+    out = {}
+    TR.energy(arch, theta, x, t, b, nl, img, student=full_range, out=out)
+    T = out["T"].numpy()
+    K = TR.box_K(arch, b)
+    wrapf = np.floor(c @ np.linalg.inv(b))
+    for i in range(len(t)):
+        Rs = np.zeros(4)
+        for k in range(arch.nm):
+            j = nl[i, k]
+            if j < 0:
+                continue
+            n = TR.decode_img(np.array([img[i, k]]), K)[0]
+            d = c[j] - c[i] + (n - wrapf[j] + wrapf[i]) @ b
+            R, _ = o.env_row(d)
+            Rs += R
+        np.testing.assert_allclose(T[i], np.outer(cvec, Rs) / arch.nm, rtol=1e-12, atol=1e-15)
+
+
+def test_oracle_results_independent_of_thread_count(water_model, water192):
+    """Per-thread partial sums: a team wider than the old fixed 64-slot arrays gives the
+    one-thread result (up to summation order)."""
+    c, t, b = water192
+    o = Oracle(water_model)
+    set_threads(1)
+    r1 = o.eval(c, t, b)
+    set_threads(80)
+    r2 = o.eval(c, t, b)
+    set_threads(4)
+    assert abs(r2["E"] - r1["E"]) < 1e-12 * abs(r1["E"])
+    assert np.abs(r2["F"] - r1["F"]).max() < 1e-12 * np.abs(r1["F"]).max()
+    assert np.abs(r2["W"] - r1["W"]).max() < 1e-12 * np.abs(r1["W"]).max()
