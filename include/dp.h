@@ -12,8 +12,10 @@
  *   - Boxes: 3x3 row-major double, rows are the cell vectors a, b, c (right handed);
  *     fractional coordinates f satisfy x = f . B (row vectors).
  *   - Device pointers are HIP device memory owned by the caller (e.g. torch tensors);
- *     host pointers are ordinary host memory.  The library owns only its handle and the
- *     model weights it uploads at dp_init.
+ *     host pointers are ordinary host memory.  The caller owns every device buffer:
+ *     inputs, outputs, workspaces, the weight region (dp_device_bytes / dp_upload) and
+ *     the student region (dp_student_bytes / dp_set_student).  The library never
+ *     allocates device or pinned host memory; it owns only its handle (host metadata).
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Compute calls
  *     only enqueue work on it and return after host-side validation; they never
  *     synchronise.  Conditions found on the device are written to a status word in
@@ -72,13 +74,30 @@ typedef struct {
 } dp_options;
 
 /* Read a model file ("DPSEMDL1" format: architecture + FP64 parameters in the
- * documented flat order) and upload its weights to the current HIP device.
+ * documented flat order) and plan its weight layouts for the current HIP device (host
+ * work only; nothing is allocated on the device).  Before any compute call the caller
+ * provides the weight region with dp_device_bytes + dp_upload.
  * Supported architecture: 1..8 species, embedding nets of three layers
  * 1 -> s0 -> 2 s0 -> 4 s0 = M with s0 <= 32 (Section 2, Eq. 7-9), square hidden
  * fitting layers after the first (Eq. 3), M< <= M, N_m = sum(sel) <= 1024.
  * opt may be NULL (FP64, atomics, skin 0).  On error *out is NULL. */
 int dp_init(const char* model_path, const dp_options* opt, dp_handle* out);
+/* Releases the handle (host memory only; caller buffers are untouched). */
 void dp_free(dp_handle h);
+
+/* Bytes of the weight region (Section 2's network parameters in the kernels' layouts:
+ * the flat FP64 parameter vector, its index maps, the precision's embedding net
+ * blocks (Eq. 7-9) and fitting weights (Eq. 1-3), pointer tables).  Depends only on the
+ * model and the precision option. */
+int dp_device_bytes(dp_handle h, size_t* weight_bytes);
+/* Binds the weight region to weights (device, >= dp_device_bytes bytes, 256-byte
+ * aligned, owned by the caller and kept alive and unmodified while the handle uses it),
+ * copies the model file's parameters in and builds the kernel layouts on stream.
+ * Synchronises the stream.  May be called again to move the region (the model file's
+ * parameters are reinstalled).  Errors: DP_ERR_ARG (NULL, misaligned),
+ * DP_ERR_WORKSPACE (too small), DP_ERR_HIP. Every other device call on the handle
+ * returns DP_ERR_ARG until this has succeeded. */
+int dp_upload(dp_handle h, void* weights, size_t bytes, void* stream);
 
 /* Architecture summary. Any output pointer may be NULL. */
 int dp_model_info(dp_handle h, int32_t* ntypes, int32_t* nm, int32_t* M, int32_t* m2,
@@ -201,16 +220,24 @@ int dp_student_lsq(int32_t hidden, int32_t M, int64_t n, const double* s, const 
 int dp_adam(int64_t n, double* theta, double* m, double* v, const double* g, int32_t step, double lr,
             double beta1, double beta2, double eps, void* stream);
 
+/* Bytes of the student region for dp_set_student (index map + ntypes^2 padded student
+ * blocks in the precision's storage type). */
+int dp_student_bytes(dp_handle h, size_t* bytes);
+
 /* Install (enable = 1) or remove (enable = 0) student embedding nets for inference.
  * theta_s (device, FP64): ntypes^2 consecutive student parameter blocks, species pair
  * (alpha, beta) at index alpha * ntypes + beta, each laid out as for
- * dp_student_loss_grad with hidden width 1..32.  s_lo, s_hi (host [ntypes^2]): the s
- * range each student was trained on.  While enabled, every compute, MD and descriptor
+ * dp_student_loss_grad with hidden width 1..32.  s_lo, s_hi (host [ntypes^2], finite,
+ * s_lo <= s_hi): the s range each student was trained on.  student_mem (device,
+ * >= dp_student_bytes bytes, 256-byte aligned, caller-owned, kept alive while enabled)
+ * receives the student layouts.  While enabled, every compute, MD and descriptor
  * call uses the student for neighbours with s in [s_lo, s_hi] and the full net (FP64)
- * for the others.  Workspaces must be sized after this call.  DP_ERR_ARG on a handle
- * made with deterministic = 1. */
+ * for the others.  Workspaces must be sized after this call.  Synchronises the stream.
+ * DP_ERR_ARG on a handle made with deterministic = 1 or bad ranges; DP_ERR_WORKSPACE if
+ * student_bytes is too small.  With enable = 0 the other arguments are ignored. */
 int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const double* s_lo,
-                   const double* s_hi, int32_t enable, void* stream);
+                   const double* s_hi, int32_t enable, void* student_mem, size_t student_bytes,
+                   void* stream);
 
 /* Stage timing with HIP events recorded on the call's stream around each stage
  * (neighbour list, embedding forward, fitting net, embedding adjoint, reductions,

@@ -26,7 +26,13 @@ struct dp_handle_s {
   int64_t nparams = 0;
   dp_options opt{};
   int device = 0;
-  // device weights
+  // weight region: one caller-owned device buffer (dp_device_bytes / dp_upload) holding
+  // the flat parameters, their index maps and every kernel layout built from them
+  bool uploaded = false;
+  char* d_wbase = nullptr;
+  size_t w_total = 0;
+  size_t o_theta = 0, o_net_map = 0, o_fit_map = 0, o_bo_map = 0, o_fitb_map = 0, o_nets = 0, o_fit = 0,
+         o_bo = 0, o_fitb = 0, o_ptrs = 0, o_net_off = 0;
   void* d_nets = nullptr;          // ntypes^2 embedding net blocks
   void* d_fit = nullptr;           // fitting weights (storage type)
   double* d_bo = nullptr;          // output biases [ntypes]
@@ -40,21 +46,18 @@ struct dp_handle_s {
   uint16_t* d_fitb = nullptr;
   int* d_fitb_map = nullptr;
   size_t fitb_elems = 0;
-  // student embedding nets
+  // host copies of the index maps and layout offsets (built at dp_init, copied by dp_upload)
+  std::vector<int> h_nmap, h_fmap, h_bmap, h_bomap;
+  std::vector<int64_t> h_noff;
+  std::vector<size_t> h_offW, h_offB, h_offO, h_offWb, h_offWf;
+  // student embedding nets (blocks and index map in a caller-owned buffer)
   bool student_on = false;
   int student_hidden = 0;
   void* d_student = nullptr;       // [nnet][kStuElems] storage type
   int* d_student_map = nullptr;
+  std::vector<int> h_student_map;
   double st_lo[kMaxTypes * kMaxTypes] = {}, st_hi[kMaxTypes * kMaxTypes] = {};
   int64_t* d_net_off = nullptr;    // [nnet][6] parameter offsets of the full nets
-  // pinned staging for per-call frame tables: a ring of slots, each reused only
-  // after the copy that last read it has completed
-  static constexpr int kSlots = 8;
-  Frame* h_frames[kSlots] = {};
-  int h_frames_cap[kSlots] = {};
-  hipEvent_t frames_done[kSlots] = {};
-  bool frames_pending[kSlots] = {};
-  int slot = 0;
   // stage timing
   bool prof_on = false;
   uint32_t prof_mask = 0;          // stages timed while prof_on (bit DP_STAGE_*)
@@ -314,7 +317,8 @@ static int refresh_weights(dp_handle h, hipStream_t st) {
   return DP_OK;
 }
 
-static int upload_weights(dp_handle h) {
+// index maps and layout offsets of the weight region, on the host (dp_init)
+static void plan_weights(dp_handle h) {
   ParamIndex P = index_params(h);
   const int sb = storage_bytes(h->opt.precision);
   int nnet = h->ntypes * h->ntypes;
@@ -409,72 +413,91 @@ static int upload_weights(dp_handle h) {
   h->net_elems = nmap.size();
   h->fit_elems = fmap.size();
   h->fitb_elems = bmap.size();
-  if (bf) {
-    HIPCHECK(h, hipMalloc(&h->d_fitb_map, sizeof(int) * bmap.size()));
-    HIPCHECK(h, hipMemcpy(h->d_fitb_map, bmap.data(), sizeof(int) * bmap.size(), hipMemcpyHostToDevice));
-    HIPCHECK(h, hipMalloc(&h->d_fitb, sizeof(uint16_t) * bmap.size()));
-  }
-  HIPCHECK(h, hipMalloc(&h->d_theta, sizeof(double) * h->nparams));
-  HIPCHECK(h, hipMemcpy(h->d_theta, h->params.data(), sizeof(double) * h->nparams, hipMemcpyHostToDevice));
-  HIPCHECK(h, hipMalloc(&h->d_net_map, sizeof(int) * nmap.size()));
-  HIPCHECK(h, hipMemcpy(h->d_net_map, nmap.data(), sizeof(int) * nmap.size(), hipMemcpyHostToDevice));
-  HIPCHECK(h, hipMalloc(&h->d_fit_map, sizeof(int) * fmap.size()));
-  HIPCHECK(h, hipMemcpy(h->d_fit_map, fmap.data(), sizeof(int) * fmap.size(), hipMemcpyHostToDevice));
-  HIPCHECK(h, hipMalloc(&h->d_bo_map, sizeof(int) * bomap.size()));
-  HIPCHECK(h, hipMemcpy(h->d_bo_map, bomap.data(), sizeof(int) * bomap.size(), hipMemcpyHostToDevice));
-  HIPCHECK(h, hipMalloc(&h->d_nets, bf ? nmap.size() * 2 : nmap.size() * sb));
-  HIPCHECK(h, hipMalloc(&h->d_fit, fmap.size() * sb));
-  HIPCHECK(h, hipMalloc(&h->d_bo, h->ntypes * sizeof(double)));
-  // pointer tables: W [ntypes*nfit], b [ntypes*nfit], wo [ntypes]
-  std::vector<void*> ptrs;
-  char* base = (char*)h->d_fit;
-  for (size_t q = 0; q < offW.size(); q++) ptrs.push_back(base + offW[q] * sb);
-  for (size_t q = 0; q < offB.size(); q++) ptrs.push_back(base + offB[q] * sb);
-  for (size_t q = 0; q < offO.size(); q++) ptrs.push_back(base + offO[q] * sb);
-  // BF16 operand table [(species * nfit + k) * 4 + dir * 2 + part]
-  for (size_t q = 0; q < offWb.size(); q++) ptrs.push_back(h->d_fitb + offWb[q]);
-  // BF16 operand fragments [(species * nfit + k) * 2 + dir]
-  for (size_t q = 0; q < offWf.size(); q++) ptrs.push_back(h->d_fitb + offWf[q]);
-  HIPCHECK(h, hipMalloc(&h->d_ptrs, ptrs.size() * sizeof(void*)));
-  HIPCHECK(h, hipMemcpy(h->d_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice));
   std::vector<int64_t> noff((size_t)nnet * 6);
   for (int net = 0; net < nnet; net++)
     for (int k = 0; k < 3; k++) {
       noff[net * 6 + 2 * k] = P.eW[net * 3 + k];
       noff[net * 6 + 2 * k + 1] = P.eB[net * 3 + k];
     }
-  HIPCHECK(h, hipMalloc(&h->d_net_off, sizeof(int64_t) * noff.size()));
-  HIPCHECK(h, hipMemcpy(h->d_net_off, noff.data(), sizeof(int64_t) * noff.size(), hipMemcpyHostToDevice));
-  int rc = refresh_weights(h, nullptr);
-  if (rc != DP_OK) return rc;
-  HIPCHECK(h, hipDeviceSynchronize());
+  // pointer tables: W [ntypes*nfit], b [ntypes*nfit], wo [ntypes], BF16 operand table
+  // [(species * nfit + k) * 4 + dir * 2 + part], BF16 operand fragments
+  // [(species * nfit + k) * 2 + dir]
+  const size_t nptrs = offW.size() + offB.size() + offO.size() + offWb.size() + offWf.size();
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = (o + bytes + 255) & ~(size_t)255; return r; };
+  h->o_theta = take(sizeof(double) * h->nparams);
+  h->o_net_map = take(sizeof(int) * nmap.size());
+  h->o_fit_map = take(sizeof(int) * fmap.size());
+  h->o_bo_map = take(sizeof(int) * bomap.size());
+  h->o_fitb_map = take(sizeof(int) * bmap.size());
+  h->o_nets = take(bf ? nmap.size() * 2 : nmap.size() * sb);
+  h->o_fit = take(fmap.size() * sb);
+  h->o_bo = take(h->ntypes * sizeof(double));
+  h->o_fitb = take(sizeof(uint16_t) * bmap.size());
+  h->o_ptrs = take(nptrs * sizeof(void*));
+  h->o_net_off = take(sizeof(int64_t) * noff.size());
+  h->w_total = o;
+  h->h_nmap = std::move(nmap);
+  h->h_fmap = std::move(fmap);
+  h->h_bmap = std::move(bmap);
+  h->h_bomap = std::move(bomap);
+  h->h_noff = std::move(noff);
+  h->h_offW = std::move(offW);
+  h->h_offB = std::move(offB);
+  h->h_offO = std::move(offO);
+  h->h_offWb = std::move(offWb);
+  h->h_offWf = std::move(offWf);
+}
+
+// binds the weight region to a caller buffer: copies the parameters, maps and pointer
+// tables in and builds the kernel layouts (synchronises the stream)
+static int bind_weights(dp_handle h, void* base, hipStream_t st) {
+  char* w = (char*)base;
+  h->d_wbase = w;
+  h->d_theta = (double*)(w + h->o_theta);
+  h->d_net_map = (int*)(w + h->o_net_map);
+  h->d_fit_map = (int*)(w + h->o_fit_map);
+  h->d_bo_map = (int*)(w + h->o_bo_map);
+  h->d_fitb_map = h->h_bmap.empty() ? nullptr : (int*)(w + h->o_fitb_map);
+  h->d_nets = w + h->o_nets;
+  h->d_fit = w + h->o_fit;
+  h->d_bo = (double*)(w + h->o_bo);
+  h->d_fitb = h->h_bmap.empty() ? nullptr : (uint16_t*)(w + h->o_fitb);
+  h->d_ptrs = (void**)(w + h->o_ptrs);
+  h->d_net_off = (int64_t*)(w + h->o_net_off);
+  const int sb = storage_bytes(h->opt.precision);
+  std::vector<void*> ptrs;
+  char* fb = (char*)h->d_fit;
+  for (size_t q : h->h_offW) ptrs.push_back(fb + q * sb);
+  for (size_t q : h->h_offB) ptrs.push_back(fb + q * sb);
+  for (size_t q : h->h_offO) ptrs.push_back(fb + q * sb);
+  for (size_t q : h->h_offWb) ptrs.push_back(h->d_fitb + q);
+  for (size_t q : h->h_offWf) ptrs.push_back(h->d_fitb + q);
+  HIPCHECK(h, hipSetDevice(h->device));
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  HIPCHECK(h, up(h->d_theta, h->params.data(), sizeof(double) * h->nparams));
+  HIPCHECK(h, up(h->d_net_map, h->h_nmap.data(), sizeof(int) * h->h_nmap.size()));
+  HIPCHECK(h, up(h->d_fit_map, h->h_fmap.data(), sizeof(int) * h->h_fmap.size()));
+  HIPCHECK(h, up(h->d_bo_map, h->h_bomap.data(), sizeof(int) * h->h_bomap.size()));
+  if (h->d_fitb_map) HIPCHECK(h, up(h->d_fitb_map, h->h_bmap.data(), sizeof(int) * h->h_bmap.size()));
+  HIPCHECK(h, up(h->d_ptrs, ptrs.data(), sizeof(void*) * ptrs.size()));
+  HIPCHECK(h, up(h->d_net_off, h->h_noff.data(), sizeof(int64_t) * h->h_noff.size()));
+  h->uploaded = true;
+  int rc = refresh_weights(h, st);
+  if (rc != DP_OK) {
+    h->uploaded = false;
+    return rc;
+  }
+  // the host arrays above are read by the copies: wait for them
+  HIPCHECK(h, hipStreamSynchronize(st));
   return DP_OK;
 }
 
-static void release_weights(dp_handle h) {
-  if (h->d_student) (void)hipFree(h->d_student);
-  if (h->d_student_map) (void)hipFree(h->d_student_map);
-  if (h->d_net_off) (void)hipFree(h->d_net_off);
-  h->d_student = nullptr;
-  h->d_student_map = nullptr;
-  h->d_net_off = nullptr;
-  if (h->d_theta) (void)hipFree(h->d_theta);
-  if (h->d_net_map) (void)hipFree(h->d_net_map);
-  if (h->d_fit_map) (void)hipFree(h->d_fit_map);
-  if (h->d_bo_map) (void)hipFree(h->d_bo_map);
-  h->d_theta = nullptr;
-  h->d_net_map = h->d_fit_map = h->d_bo_map = nullptr;
-  if (h->d_nets) (void)hipFree(h->d_nets);
-  if (h->d_fit) (void)hipFree(h->d_fit);
-  if (h->d_bo) (void)hipFree(h->d_bo);
-  if (h->d_ptrs) (void)hipFree(h->d_ptrs);
-  if (h->d_fitb) (void)hipFree(h->d_fitb);
-  if (h->d_fitb_map) (void)hipFree(h->d_fitb_map);
-  h->d_fitb = nullptr;
-  h->d_fitb_map = nullptr;
-  h->d_nets = h->d_fit = nullptr;
-  h->d_bo = nullptr;
-  h->d_ptrs = nullptr;
+static int need_weights(dp_handle h) {
+  if (!h->uploaded) return fail(h, DP_ERR_ARG, "weights not uploaded: call dp_upload first");
+  return DP_OK;
 }
 
 // ------------------------------------------------------------------------------------
@@ -651,6 +674,19 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
   return DP_OK;
 }
 
+namespace dp {
+int handle_device(dp_handle h) { return h->device; }
+int set_error(dp_handle h, int code, const std::string& msg) { return fail(h, code, msg); }
+int compute_ws_bytes(dp_handle h, int64_t natoms, const double* box, size_t* bytes) {
+  int64_t off[2] = {0, natoms};
+  Plan P;
+  int rc = make_plan(h, 1, off, box, nullptr, P);
+  if (rc != DP_OK) return rc;
+  *bytes = P.total;
+  return DP_OK;
+}
+}  // namespace dp
+
 // ------------------------------------------------------------------------------------
 // public API
 // ------------------------------------------------------------------------------------
@@ -689,6 +725,7 @@ struct Ws {
 static int stage_frames(dp_handle h, int nframes, const int64_t* off, const double* boxes,
                         const double* coords, const int32_t* types, void* ws, size_t ws_bytes,
                         hipStream_t st, Plan& P, NlistArgs& A, bool verlet = false) {
+  if (need_weights(h) != DP_OK) return DP_ERR_ARG;
   std::vector<Frame> frames;
   int rc = make_plan(h, nframes, off, boxes, &frames, P, verlet);
   if (rc != DP_OK) return rc;
@@ -696,25 +733,9 @@ static int stage_frames(dp_handle h, int nframes, const int64_t* off, const doub
     return fail(h, DP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(P.total) + " bytes");
   if (!coords || !types) return fail(h, DP_ERR_ARG, "null coordinates or types");
   HIPCHECK(h, hipSetDevice(h->device));
-  int s = h->slot;
-  h->slot = (h->slot + 1) % dp_handle_s::kSlots;
-  if (h->frames_pending[s]) {
-    HIPCHECK(h, hipEventSynchronize(h->frames_done[s]));
-    h->frames_pending[s] = false;
-  }
-  if (!h->frames_done[s]) HIPCHECK(h, hipEventCreateWithFlags(&h->frames_done[s], hipEventDisableTiming));
-  if (h->h_frames_cap[s] < nframes) {
-    if (h->h_frames[s]) (void)hipHostFree(h->h_frames[s]);
-    h->h_frames[s] = nullptr;
-    HIPCHECK(h, hipHostMalloc((void**)&h->h_frames[s], sizeof(Frame) * nframes, 0));
-    h->h_frames_cap[s] = nframes;
-  }
-  memcpy(h->h_frames[s], frames.data(), sizeof(Frame) * nframes);
   Ws W{(char*)ws, &P};
-  HIPCHECK(h, hipMemcpyAsync(W.at<Frame>(P.o_frames), h->h_frames[s], sizeof(Frame) * nframes,
-                             hipMemcpyHostToDevice, st));
-  HIPCHECK(h, hipEventRecord(h->frames_done[s], st));
-  h->frames_pending[s] = true;
+  // the frame table travels in kernel arguments (no staging memory, no host wait)
+  launch_put_frames(frames.data(), nframes, W.at<Frame>(P.o_frames), st);
   A.n = P.n;
   A.nframes = nframes;
   A.ncell = P.ncell;
@@ -949,29 +970,17 @@ int dp_init(const char* model_path, const dp_options* opt, dp_handle* out) {
     delete h;
     return fail(nullptr, DP_ERR_HIP, "no HIP device");
   }
-  rc = upload_weights(h);
-  if (rc != DP_OK) {
-    g_init_err = h->err;
-    release_weights(h);
-    delete h;
-    return rc;
-  }
+  plan_weights(h);
   *out = h;
   return DP_OK;
 }
 
 void dp_free(dp_handle h) {
   if (!h) return;
-  for (int s = 0; s < dp_handle_s::kSlots; s++) {
-    if (h->frames_pending[s]) (void)hipEventSynchronize(h->frames_done[s]);
-    if (h->h_frames[s]) (void)hipHostFree(h->h_frames[s]);
-    if (h->frames_done[s]) (void)hipEventDestroy(h->frames_done[s]);
-  }
   for (hipEvent_t e : h->prof_pool) {
     (void)hipEventSynchronize(e);
     (void)hipEventDestroy(e);
   }
-  release_weights(h);
   delete h;
 }
 
@@ -985,6 +994,20 @@ int dp_model_info(dp_handle h, int32_t* ntypes, int32_t* nm, int32_t* M, int32_t
   if (rc) *rc = h->rc;
   if (nparams) *nparams = h->nparams;
   return DP_OK;
+}
+
+int dp_device_bytes(dp_handle h, size_t* weight_bytes) {
+  if (!h || !weight_bytes) return fail(h, DP_ERR_ARG, "null argument");
+  *weight_bytes = h->w_total;
+  return DP_OK;
+}
+
+int dp_upload(dp_handle h, void* weights, size_t bytes, void* stream) {
+  if (!h || !weights) return fail(h, DP_ERR_ARG, "null argument");
+  if (bytes < h->w_total)
+    return fail(h, DP_ERR_WORKSPACE, "weight buffer too small: need " + std::to_string(h->w_total) + " bytes");
+  if (((uintptr_t)weights & 255) != 0) return fail(h, DP_ERR_ARG, "weight buffer must be 256-byte aligned");
+  return bind_weights(h, weights, (hipStream_t)stream);
 }
 
 int dp_workspace_size(dp_handle h, int32_t nframes, const int64_t* atom_offsets, const double* boxes,
@@ -1151,6 +1174,7 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
 
 int dp_set_params(dp_handle h, const double* theta, void* stream) {
   if (!h || !theta) return fail(h, DP_ERR_ARG, "null argument");
+  if (need_weights(h) != DP_OK) return DP_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   HIPCHECK(h, hipMemcpyAsync(h->d_theta, theta, sizeof(double) * h->nparams, hipMemcpyDeviceToDevice, st));
   return refresh_weights(h, st);
@@ -1158,6 +1182,7 @@ int dp_set_params(dp_handle h, const double* theta, void* stream) {
 
 int dp_get_params(dp_handle h, double* theta, void* stream) {
   if (!h || !theta) return fail(h, DP_ERR_ARG, "null argument");
+  if (need_weights(h) != DP_OK) return DP_ERR_ARG;
   HIPCHECK(h, hipMemcpyAsync(theta, h->d_theta, sizeof(double) * h->nparams, hipMemcpyDeviceToDevice,
                              (hipStream_t)stream));
   return DP_OK;
@@ -1279,8 +1304,23 @@ int dp_param_grad(dp_handle h, int32_t nframes, const int64_t* atom_offsets, con
   return DP_OK;
 }
 
+// bytes of the student region: the index map, then the blocks in the storage type
+static size_t student_map_bytes(dp_handle h) {
+  return (sizeof(int) * (size_t)h->ntypes * h->ntypes * kStuElems + 255) & ~(size_t)255;
+}
+static size_t student_region_bytes(dp_handle h) {
+  return student_map_bytes(h) + (size_t)h->ntypes * h->ntypes * kStuElems * storage_bytes(h->opt.precision);
+}
+
+int dp_student_bytes(dp_handle h, size_t* bytes) {
+  if (!h || !bytes) return fail(h, DP_ERR_ARG, "null argument");
+  *bytes = student_region_bytes(h);
+  return DP_OK;
+}
+
 int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const double* s_lo,
-                   const double* s_hi, int32_t enable, void* stream) {
+                   const double* s_hi, int32_t enable, void* student_mem, size_t student_bytes,
+                   void* stream) {
   if (!h) return DP_ERR_ARG;
   if (!enable) {
     h->student_on = false;
@@ -1289,42 +1329,47 @@ int dp_set_student(dp_handle h, int32_t hidden, const double* theta_s, const dou
   if (!theta_s || !s_lo || !s_hi || hidden < 1 || hidden > kP0)
     return fail(h, DP_ERR_ARG, "student: bad arguments (hidden must be 1..32)");
   if (h->opt.deterministic) return fail(h, DP_ERR_ARG, "student nets are not available in deterministic mode");
+  if (!student_mem || ((uintptr_t)student_mem & 255) != 0)
+    return fail(h, DP_ERR_ARG, "student buffer must be non-NULL and 256-byte aligned");
+  if (student_bytes < student_region_bytes(h))
+    return fail(h, DP_ERR_WORKSPACE,
+                "student buffer too small: need " + std::to_string(student_region_bytes(h)) + " bytes");
+  for (int q = 0; q < h->ntypes * h->ntypes; q++)
+    if (!(s_lo[q] <= s_hi[q]) || !std::isfinite(s_lo[q]) || !std::isfinite(s_hi[q]))
+      return fail(h, DP_ERR_ARG, "student: every range needs finite s_lo <= s_hi");
   const int nnet = h->ntypes * h->ntypes, M = h->M;
   const size_t size = 2 * (size_t)hidden + (size_t)hidden * M + M;
-  if (h->d_student && h->student_hidden != hidden) {
-    (void)hipFree(h->d_student);
-    (void)hipFree(h->d_student_map);
-    h->d_student = nullptr;
-    h->d_student_map = nullptr;
-  }
   // student blocks: FP64 in the FP64 mode, FP32 otherwise (the student kernels have no
   // per-neighbour matrix product, so the BF16 operand modes do not apply to them)
   const size_t blk = (size_t)kStuElems;
-  if (!h->d_student) {
-    std::vector<int> map((size_t)nnet * blk, -1);
-    for (int net = 0; net < nnet; net++) {
-      int* b = map.data() + (size_t)net * blk;
-      size_t o = net * size;
+  std::vector<int>& map = h->h_student_map;
+  map.assign((size_t)nnet * blk, -1);
+  for (int net = 0; net < nnet; net++) {
+    int* b = map.data() + (size_t)net * blk;
+    size_t o = net * size;
+    for (int j = 0; j < hidden; j++) {
+      b[kSW1 + j] = (int)(o + j);
+      b[kSB1 + j] = (int)(o + hidden + j);
+    }
+    for (int f = 0; f < M; f++) {
+      b[kSB2 + f] = (int)(o + 2 * hidden + (size_t)hidden * M + f);
       for (int j = 0; j < hidden; j++) {
-        b[kSW1 + j] = (int)(o + j);
-        b[kSB1 + j] = (int)(o + hidden + j);
-      }
-      for (int f = 0; f < M; f++) {
-        b[kSB2 + f] = (int)(o + 2 * hidden + (size_t)hidden * M + f);
-        for (int j = 0; j < hidden; j++) {
-          b[kSW2 + j * kP2 + f] = (int)(o + 2 * hidden + (size_t)j * M + f);
-          b[kSW2T + f * kP0 + j] = (int)(o + 2 * hidden + (size_t)j * M + f);
-        }
+        b[kSW2 + j * kP2 + f] = (int)(o + 2 * hidden + (size_t)j * M + f);
+        b[kSW2T + f * kP0 + j] = (int)(o + 2 * hidden + (size_t)j * M + f);
       }
     }
-    HIPCHECK(h, hipMalloc(&h->d_student_map, sizeof(int) * map.size()));
-    HIPCHECK(h, hipMemcpy(h->d_student_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
-    HIPCHECK(h, hipMalloc(&h->d_student, map.size() * storage_bytes(h->opt.precision)));
-    h->student_hidden = hidden;
   }
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHECK(h, hipSetDevice(h->device));
+  h->d_student_map = (int*)student_mem;
+  h->d_student = (char*)student_mem + student_map_bytes(h);
+  h->student_hidden = hidden;
+  HIPCHECK(h, hipMemcpyAsync(h->d_student_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice, st));
   launch_scatter_params(h->opt.precision == PREC_FP64 ? 0 : 1, (size_t)nnet * kStuElems, h->d_student_map, theta_s,
-                        h->d_student, (hipStream_t)stream);
+                        h->d_student, st);
   HIPCHECK(h, hipGetLastError());
+  // the host map above is read by the copy: wait for it
+  HIPCHECK(h, hipStreamSynchronize(st));
   for (int q = 0; q < nnet; q++) {
     h->st_lo[q] = s_lo[q];
     h->st_hi[q] = s_hi[q];
@@ -1382,6 +1427,7 @@ int dp_student_samples_workspace_size(dp_handle h, int64_t natoms, const double*
 int dp_embed_eval(dp_handle h, int32_t alpha, int32_t beta, int64_t n, const double* s, double* G, void* stream) {
   if (!h || !s || !G || n < 0) return fail(h, DP_ERR_ARG, "bad argument");
   if (alpha < 0 || alpha >= h->ntypes || beta < 0 || beta >= h->ntypes) return fail(h, DP_ERR_ARG, "bad species");
+  if (need_weights(h) != DP_OK) return DP_ERR_ARG;
   ParamIndex PI = index_params(h);
   int net = alpha * h->ntypes + beta;
   const double* th[6];

@@ -4,7 +4,11 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "common.h"
+
+struct dp_handle_s;
 
 namespace dp {
 
@@ -43,6 +47,8 @@ struct NlistArgs {
                     // short keys); nbig[0] is zero on entry and left zero, nbig[1] its pass counter
 };
 size_t scan_sums_ints(int n, int W);
+// copies nframes frames from host memory to dst on the stream through kernel arguments
+void launch_put_frames(const Frame* frames, int nframes, Frame* dst, hipStream_t st);
 void launch_nlist(const NlistArgs& a, hipStream_t st);
 // disp_done: the skin check (and the clearing of the cell counters) ran with the drift;
 // clear (may be NULL): one int zeroed for the coming evaluation
@@ -221,6 +227,12 @@ void launch_student_lsq(long n, int H, int M, const double* s, const double* G, 
 void launch_adam(size_t n, double* th, double* m, double* v, const double* g, double lr, double b1, double b2,
                  double eps, int t, hipStream_t st);
 size_t scan_sums_ints(int n, int W);
+
+// C ABI helpers shared by the entry-point files
+int handle_device(dp_handle_s* h);
+int set_error(dp_handle_s* h, int code, const std::string& msg);
+// workspace bytes of a one-frame force evaluation (dp_compute)
+int compute_ws_bytes(dp_handle_s* h, int64_t natoms, const double* box, size_t* bytes);
 
 struct MDMass {
   double m[kMaxTypes];

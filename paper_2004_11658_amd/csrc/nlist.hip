@@ -12,6 +12,8 @@
 // floating-point contraction off, in a fixed operation order:
 //   x_w = x - (m0 B0 + m1 B1) + m2 B2   (m = floor(x . B^-1)),
 //   ghost = x_w + (n0 B0 + n1 B1) + n2 B2,  d = ghost - x_w,i,  r^2 = (dx dx + dy dy) + dz dz.
+#include <cstring>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -237,6 +239,34 @@ size_t scan_sums_ints(int n, int W) {
   int nb = (n + kScanTile - 1) / kScanTile;
   if (nb < 1) nb = 1;
   return (size_t)nb * W;
+}
+
+// ------------------------------------------------------------------------------------
+// frame table upload through kernel arguments: a call's frames (box, inverse, cell
+// grid) are copied by value into the launch, so no host staging buffer has to outlive
+// the call and no host wait is needed
+// ------------------------------------------------------------------------------------
+constexpr int kFramesPerLaunch = 12;
+struct FramePack {
+  Frame f[kFramesPerLaunch];
+};
+static_assert(sizeof(FramePack) + 16 <= 4096, "frame pack exceeds the kernel argument budget");
+static_assert(sizeof(Frame) % sizeof(uint32_t) == 0, "Frame is copied in 32-bit words");
+
+__global__ void k_put_frames(FramePack pack, int count, Frame* dst) {
+  constexpr int kWords = (int)(sizeof(Frame) / sizeof(uint32_t));
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(pack.f);
+  uint32_t* out = reinterpret_cast<uint32_t*>(dst);
+  for (int w = threadIdx.x; w < count * kWords; w += blockDim.x) out[w] = src[w];
+}
+
+void launch_put_frames(const Frame* frames, int nframes, Frame* dst, hipStream_t st) {
+  for (int f0 = 0; f0 < nframes; f0 += kFramesPerLaunch) {
+    const int c = nframes - f0 < kFramesPerLaunch ? nframes - f0 : kFramesPerLaunch;
+    FramePack pack;
+    memcpy(pack.f, frames + f0, sizeof(Frame) * c);
+    hipLaunchKernelGGL(k_put_frames, dim3(1), dim3(256), 0, st, pack, c, dst + f0);
+  }
 }
 
 // ------------------------------------------------------------------------------------

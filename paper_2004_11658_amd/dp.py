@@ -42,6 +42,9 @@ def _load():
         "dp_init": ([C.c_char_p, P, P], C.c_int),
         "dp_free": ([P], None),
         "dp_model_info": ([P, P, P, P, P, P, P], C.c_int),
+        "dp_device_bytes": ([P, P], C.c_int),
+        "dp_upload": ([P, P, SZ, P], C.c_int),
+        "dp_student_bytes": ([P, P], C.c_int),
         "dp_workspace_size": ([P, I32, P, P, P], C.c_int),
         "dp_compute": ([P, I64, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
         "dp_compute_batch": ([P, I32, P, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
@@ -64,7 +67,7 @@ def _load():
         "dp_adam": ([I64, P, P, P, P, I32, D, D, D, D, P], C.c_int),
         "dp_student_lsq_scratch_size": ([I32, I32, I64, P], C.c_int),
         "dp_student_lsq": ([I32, I32, I64, P, P, P, D, P, SZ, P], C.c_int),
-        "dp_set_student": ([P, I32, P, P, P, I32, P], C.c_int),
+        "dp_set_student": ([P, I32, P, P, P, I32, P, SZ, P], C.c_int),
         "dp_profile_read": ([P, I32, P, P], C.c_int),
         "dp_strerror": ([C.c_int], C.c_char_p),
         "dp_last_error": ([P], C.c_char_p),
@@ -116,6 +119,12 @@ class DPModel:
         self.rc, self.nparams = rcut.value, npar.value
         self._ws = None
         self.device = torch.device("cuda", torch.cuda.current_device())
+        # the weight region is caller memory: a torch buffer the library lays its layouts in
+        nb = C.c_size_t()
+        self._check(_lib.dp_device_bytes(h, C.byref(nb)))
+        self._weights = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=self.device)
+        self._check(_lib.dp_upload(h, _ptr(self._weights), self._weights.numel(), _stream()))
+        self._student_mem = None
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -293,15 +302,20 @@ class DPModel:
 
     def set_student(self, hidden: int, theta_s: Optional[torch.Tensor], s_lo=None, s_hi=None, enable: bool = True):
         if not enable:
-            self._check(_lib.dp_set_student(self.h, hidden, None, None, None, 0, _stream()))
+            self._check(_lib.dp_set_student(self.h, hidden, None, None, None, 0, None, 0, _stream()))
             self._ws = None
             return
         th = self._dev(theta_s, torch.float64)
         assert th.numel() == self.ntypes ** 2 * student_size(hidden, self.M)
         lo = np.ascontiguousarray(s_lo, dtype=np.float64)
         hi = np.ascontiguousarray(s_hi, dtype=np.float64)
+        nb = C.c_size_t()
+        self._check(_lib.dp_student_bytes(self.h, C.byref(nb)))
+        if self._student_mem is None or self._student_mem.numel() < nb.value:
+            self._student_mem = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
         self._check(_lib.dp_set_student(self.h, hidden, _ptr(th), lo.ctypes.data_as(C.c_void_p),
-                                        hi.ctypes.data_as(C.c_void_p), 1, _stream()))
+                                        hi.ctypes.data_as(C.c_void_p), 1, _ptr(self._student_mem),
+                                        self._student_mem.numel(), _stream()))
         self._ws = None       # workspace layout changes with the student's fallback list
 
     # ------------------------------------------------------------------ parameters
