@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Benchmark: velocity-Verlet MD of 12,288 water atoms with the DP-SE model on one GPU.
+"""Benchmark: velocity-Verlet MD of 786,432 water atoms with the DP-SE model on one GPU.
 
 One step = one MD step of the whole hot path: displacement check against the neighbour
 skin (wrap + ghost images + cell list + candidate rows rebuilt when some atom moved
@@ -8,19 +8,30 @@ fitting net forward and backward, embedding adjoint with force / virial scatter,
 energy and virial sums (on the steps that write a thermo row, every 20), and the two
 velocity-Verlet half kicks and drift.  Inputs are resident in HBM before timing.
 
-Each precision mode is timed over the same K steps from the same initial state; the
-headline value is the fastest mode whose force RMSE (relative to FP64 at identical
-coordinates) is at most 1e-3, as the metric asks.  In the timed pass only the embedding
-adjoint (the roofline kernel) is bracketed by HIP events; the per-stage breakdown comes
-from a second pass over the same steps with every stage timed.  The FP64 CPU oracle is timed on a
-bounded sample (one force evaluation of the same frame) as the CPU baseline.
+Workload of the benchmark line: 262,144 H2O (786,432 atoms) in a 197.9 A cube, 20 steps
+of 0.5 fs from 300 K (--steps), the largest configuration that fits one GPU.  Each
+precision mode is timed over the same steps from the same initial state.  Its force
+error is measured on the timed path itself: the forces the mode's MD returns at the
+end of the timed run (Verlet list with skin, student nets with fallback) against a fresh
+FP64 full-net evaluation at the same coordinates.  The students are trained on frames of
+a different system (the 12,288-atom water's FP64 MD), so every frame of the timed run is
+held out.  The headline value is the fastest mode whose force RMSE is at most 1e-3, as
+the metric asks.  In the timed pass only the embedding adjoint (the roofline kernel) is
+bracketed by HIP events; the per-stage breakdown comes from a second pass over the same
+steps with every stage timed.  The FP64 CPU oracle is timed on a bounded sample (exact
+forces of sampled atoms of the same frame) with all threads of the job's CPU share and
+with one thread, as the CPU baseline.
 
-    python bench.py [--gpus 1] [--steps 100] [--warmup 3] [--modes fp64,fp32,bf16x3,bf16,fp32+student,bf16x3+student]
+Extra lines in the same JSON object ("extra"): the 12,288-atom water (100 steps of
+0.5 fs, started 50 steps past the last student training frame) and FCC copper of
+131,072 atoms (50 steps of 1 fs), each timed per mode the same way.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--modes ...] [--no-extras]
 
 Modes: fp64, fp32, bf16, bf16x3 (operand precision of the embedding and fitting GEMMs),
 and "<precision>+student": the student embedding nets, trained before timing on frames
-of the FP64 full model's own MD of the same system (sampling, targets and fit all run in
-the library's kernels), with the full net as fallback outside their s range.
+of the FP64 full model's own MD (sampling, targets and fit all run in the library's
+kernels), with the full net as fallback outside their s range.
 """
 from __future__ import annotations
 
@@ -167,17 +178,150 @@ def train_bench(args, path, log):
                       "data": "synthetic"}), flush=True)
 
 
+def sig(v, d=6):
+    """v to d significant digits (small values such as drifts keep their magnitude)."""
+    return float("%.*g" % (d, v)) if isinstance(v, float) else v
+
+
+def cpu_threads():
+    """Threads of the job's CPU share: the affinity mask, capped by OMP_NUM_THREADS."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(n, 1)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def train_student_set(D, I, S, path, masses, dt, log):
+    """Students trained on frames of the FP64 full model's own MD of the 12,288-atom water
+    (frames at steps 0, 10, 20, 30); also returns that trajectory's state at step 80, 50
+    steps past the last training frame, where the held-out 12,288-atom run starts."""
+    import torch
+    full = D.DPModel(path, "fp64")
+    c12, t12, b12 = I.config_water12k(202)
+    v12 = I.maxwell_velocities(t12, masses, 300.0, 302)
+    xs = torch.as_tensor(c12, device="cuda")
+    vs = torch.as_tensor(v12, device="cuda")
+    t12d = torch.as_tensor(t12, dtype=torch.int32, device="cuda")
+    frames = []
+    for _ in range(4):
+        frames.append((xs.clone(), t12d, b12))
+        full.md_run(xs, vs, t12d, masses, b12, dt, 10, 0)
+    full.md_run(xs, vs, t12d, masses, b12, dt, 40, 0)
+    tt = time.perf_counter()
+    th, lo, hi, rep = S.train_students(full, frames, hidden=STUDENT_HIDDEN, n_samples=1_000_000)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - tt
+    log("student training %.1f s" % secs, json.dumps(rep))
+    return dict(theta=th, lo=lo, hi=hi, report=rep, seconds=secs, x12=xs, v12=vs, t12=t12d, b12=b12)
+
+
+def run_modes(D, path, x0, v0, t_dev, box, masses, dt, steps, warmup, modes, skin, student, log,
+              stage_pass=True):
+    """Times each mode's MD from (x0, v0); its force error is that of the forces the timed
+    run returns at its final coordinates against a fresh FP64 full-net evaluation there."""
+    import torch
+    n = x0.shape[0]
+    ref = D.DPModel(path, "fp64")
+    _, _, nn, _ = ref.nlist(x0, t_dev, box)
+    rows = int(nn.sum().item())
+    results = {}
+    for mode in modes:
+        prec, _, extra = mode.partition("+")
+        model = D.DPModel(path, prec, skin=skin)
+        if extra == "student":
+            model.set_student(STUDENT_HIDDEN, student["theta"], student["lo"], student["hi"])
+        x = x0.clone()
+        v = v0.clone()
+        model.md_run(x, v, t_dev, masses, box, dt, warmup, 0)
+        x.copy_(x0)
+        v.copy_(v0)
+        F_end = torch.empty_like(x0)
+        torch.cuda.synchronize()
+        # timed pass: only the embedding adjoint (the roofline kernel) carries HIP events
+        model.profile(True, stages=["embed_bwd"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th = model.md_run(x, v, t_dev, masses, box, dt, steps, 20, forces=F_end, check=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        model.status()
+        fb1 = model.fallback_rows() if extra == "student" else 0
+        model.profile(False)
+        bwd_timed = model.profile_read("embed_bwd")
+        stages = None
+        if stage_pass:
+            # second pass over the same steps with every stage timed (the stage breakdown;
+            # its event records slow the step, so it is not the timed pass)
+            x2 = x0.clone()
+            v2 = v0.clone()
+            torch.cuda.synchronize()
+            model.profile(True)
+            model.md_run(x2, v2, t_dev, masses, box, dt, steps, 0, check=False)
+            torch.cuda.synchronize()
+            model.profile(False)
+            stages = {s: model.profile_read(s) for s in D.STAGES}
+            del x2, v2
+        else:
+            stages = {"embed_bwd": bwd_timed}
+        stages["embed_bwd"] = bwd_timed
+        del model
+        # force error on the timed path: final forces vs fresh FP64 at the same coordinates
+        _, Fr, _ = ref.compute(x, t_dev, box)
+        dF = F_end - Fr
+        rmse = float(torch.sqrt((dF * dF).mean()) / torch.sqrt((Fr * Fr).mean()))
+        wall = t1 - t0
+        thermo = th.cpu().numpy()
+        drift = float(np.abs(thermo[:, 4] - thermo[0, 4]).max() / n)
+        results[mode] = dict(value=n * steps / wall, ms_per_step=1e3 * wall / steps,
+                             force_rmse_rel=rmse, energy_drift_ev_per_atom=drift, student=extra == "student",
+                             fallback_rows_last_step=fb1,
+                             stages_ms={s: v_[0] / max(v_[1], 1) for s, v_ in stages.items()},
+                             stage_launches={s: v_[1] for s, v_ in stages.items()})
+        log(mode, json.dumps({k: sig(v_) for k, v_ in results[mode].items() if k != "stage_launches"}))
+        del x, v, F_end, Fr, dF
+    del ref
+    return results, rows
+
+
+def stage_rates(spec, rows, n, res):
+    """Achieved TFLOP/s of the compute stages that were timed (HIP-event average per launch)."""
+    fl = algorithmic_flops(spec, rows, n, student=res["student"])
+    out = {}
+    for st_, key in [("embed_fwd", "embed_fwd"), ("fit", "fit"), ("embed_bwd", "embed_bwd")]:
+        ms = res["stages_ms"].get(st_, 0.0)
+        out[st_] = sig(fl[key] / (ms * 1e-3) / 1e12) if ms > 0 else None
+    return out
+
+
+def summarise(results):
+    return {m: {k: (sig(v_) if isinstance(v_, float) else v_) for k, v_ in r.items()} for m, r in results.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--modes", default="fp64,fp32,bf16x3,bf16,fp32+student,bf16x3+student")
-    ap.add_argument("--workload", default="water12k", choices=["water12k", "water786k"],
-                    help="water12k: 12,288 atoms (the benchmark line); water786k: 786,432 atoms, "
-                         "students trained on frames of the 12,288-atom system's FP64 MD")
+    ap.add_argument("--workload", default="water786k", choices=["water786k", "water12k"],
+                    help="water786k: 786,432 atoms (the benchmark line); water12k: 12,288 atoms, started "
+                         "50 steps past the last student training frame")
     ap.add_argument("--skin", type=float, default=2.0,
                     help="neighbour skin (A): the list is rebuilt when some atom moved more than skin/2")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the extra lines (12,288-atom water, 131,072-atom copper)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--train-steps", type=int, default=0,
@@ -203,6 +347,7 @@ def main():
         return
     from paper_2004_11658_amd import inputs as I
     from paper_2004_11658_amd import dp as D
+    from paper_2004_11658_amd import student as S
 
     def log(*a):
         if not args.quiet:
@@ -216,116 +361,39 @@ def main():
         train_bench(args, path, log)
         return
     masses = [I.MASS["O"], I.MASS["H"]]
-    if args.workload == "water786k":
-        coords, types, box = I.config_water786k(205)
-        vel = I.maxwell_velocities(types, masses, 300.0, 305)
-    else:
-        coords, types, box = I.config_water12k(202)
-        vel = I.maxwell_velocities(types, masses, 300.0, 302)
-    n = len(types)
     dt = 0.5
-    x0 = torch.as_tensor(coords, device="cuda")
-    v0 = torch.as_tensor(vel, device="cuda")
-    t_dev = torch.as_tensor(types, dtype=torch.int32, device="cuda")
-    # student training data: the 12,288-atom system's own FP64 MD
-    c12, t12, b12 = I.config_water12k(202)
-    v12 = I.maxwell_velocities(t12, masses, 300.0, 302)
-    log("workload: water %d atoms, %d steps, dt %.2f fs" % (n, args.steps, dt))
-
-    results = {}
-    F_ref = None
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     if "fp64" not in modes:
         modes = ["fp64"] + modes
-    rows = None
     student = None
-    for mode in modes:
-        prec, _, extra = mode.partition("+")
-        model = D.DPModel(path, prec, skin=args.skin)
-        if extra == "student":
-            if student is None:
-                # training data: frames of the FP64 full model's own trajectory
-                from paper_2004_11658_amd import student as S
-                full = D.DPModel(path, "fp64")
-                xs = torch.as_tensor(c12, device="cuda")
-                vs = torch.as_tensor(v12, device="cuda")
-                t12d = torch.as_tensor(t12, dtype=torch.int32, device="cuda")
-                frames = []
-                for k in range(4):
-                    frames.append((xs.clone(), t12d, b12))
-                    full.md_run(xs, vs, t12d, masses, b12, dt, 10, 0)
-                tt = time.perf_counter()
-                th, lo, hi, rep = S.train_students(full, frames, hidden=STUDENT_HIDDEN,
-                                                   n_samples=1_000_000)
-                torch.cuda.synchronize()
-                student = (th, lo, hi, rep, time.perf_counter() - tt)
-                log("student training %.1f s" % student[4], json.dumps(rep))
-                del full
-            model.set_student(STUDENT_HIDDEN, student[0], student[1], student[2])
-        if rows is None:
-            _, _, nn, _ = model.nlist(x0, t_dev, box)
-            rows = int(nn.sum().item())
-        E0, F0, W0 = model.compute(x0, t_dev, box)
-        fb0 = model.fallback_rows() if extra == "student" else 0
-        if mode == "fp64":
-            F_ref = F0.clone()
-        dF = F0 - F_ref
-        rmse = float(torch.sqrt((dF * dF).mean()) / torch.sqrt((F_ref * F_ref).mean()))
-        # warm-up steps (untimed), from a copy of the initial state
-        x = x0.clone()
-        v = v0.clone()
-        model.md_run(x, v, t_dev, masses, box, dt, args.warmup, 0)
-        x.copy_(x0)
-        v.copy_(v0)
-        torch.cuda.synchronize()
-        # timed pass: only the embedding adjoint (the roofline kernel) carries HIP events
-        model.profile(True, stages=["embed_bwd"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        th = model.md_run(x, v, t_dev, masses, box, dt, args.steps, 20, check=False)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        model.status()
-        fb1 = model.fallback_rows() if extra == "student" else 0
-        model.profile(False)
-        bwd_timed = model.profile_read("embed_bwd")
-        # second pass over the same steps with every stage timed (the stage breakdown;
-        # its event records slow the step, so it is not the timed pass)
-        x2 = x0.clone()
-        v2 = v0.clone()
-        torch.cuda.synchronize()
-        model.profile(True)
-        model.md_run(x2, v2, t_dev, masses, box, dt, args.steps, 0, check=False)
-        torch.cuda.synchronize()
-        model.profile(False)
-        stages = {s: model.profile_read(s) for s in D.STAGES}
-        stages["embed_bwd"] = bwd_timed
-        wall = t1 - t0
-        thermo = th.cpu().numpy()
-        drift = float(np.abs(thermo[:, 4] - thermo[0, 4]).max() / n)
-        results[mode] = dict(value=n * args.steps / wall, ms_per_step=1e3 * wall / args.steps,
-                             force_rmse_rel=rmse, energy_drift_ev_per_atom=drift, student=extra == "student",
-                             fallback_rows=dict(first_step=fb0, last_step=fb1),
-                             stages_ms={s: round(v_[0] / max(v_[1], 1), 5) for s, v_ in stages.items()},
-                             stage_launches={s: v_[1] for s, v_ in stages.items()})
-        log(mode, json.dumps(results[mode]))
-        del model
+    if any(m.endswith("+student") for m in modes):
+        student = train_student_set(D, I, S, path, masses, dt, log)
+
+    if args.workload == "water786k":
+        coords, types, box = I.config_water786k(205)
+        vel = I.maxwell_velocities(types, masses, 300.0, 305)
+        x0 = torch.as_tensor(coords, device="cuda")
+        v0 = torch.as_tensor(vel, device="cuda")
+        t_dev = torch.as_tensor(types, dtype=torch.int32, device="cuda")
+        wl = "water 786,432 atoms (262,144 H2O, 197.9 A cube)"
+    else:
+        assert student is not None, "the held-out 12,288-atom start comes from the student training run"
+        x0, v0, t_dev, box = student["x12"].clone(), student["v12"].clone(), student["t12"], student["b12"]
+        coords, types = x0.cpu().numpy(), t_dev.cpu().numpy()
+        wl = "water 12,288 atoms (4,096 H2O, 49.7 A cube), 50 steps past the last student training frame"
+    n = len(types)
+    log("workload: %s, %d steps, dt %.2f fs" % (wl, args.steps, dt))
+    results, rows = run_modes(D, path, x0, v0, t_dev, box, masses, dt, args.steps, args.warmup, modes,
+                              args.skin, student, log)
 
     ok = [m for m in modes if results[m]["force_rmse_rel"] <= 1e-3]
     head = max(ok, key=lambda m: results[m]["value"])
     R = results[head]
     hprec = head.partition("+")[0]
     fl = algorithmic_flops(spec, rows, n, student=R["student"])
-    # achieved rate of each compute stage (HIP-event average per launch)
-    stage_rates = {}
-    for st_, key in [("embed_fwd", "embed_fwd"), ("fit", "fit"), ("embed_bwd", "embed_bwd")]:
-        ms = R["stages_ms"][st_]
-        stage_rates[st_] = round(fl[key] / (ms * 1e-3) / 1e12, 3) if ms > 0 else None
+    rates = stage_rates(spec, rows, n, R)
     for m_ in modes:
-        flm = algorithmic_flops(spec, rows, n, student=results[m_]["student"])
-        results[m_]["stage_tflops"] = {s_: (round(flm[s_] / (results[m_]["stages_ms"][s_] * 1e-3) / 1e12, 3)
-                                            if results[m_]["stages_ms"][s_] > 0 else None)
-                                       for s_ in ("embed_fwd", "fit", "embed_bwd")}
+        results[m_]["stage_tflops"] = stage_rates(spec, rows, n, results[m_])
     bwd_ms = R["stages_ms"]["embed_bwd"]
     achieved = fl["embed_bwd"] / (bwd_ms * 1e-3) / 1e12
     if R["student"]:
@@ -333,67 +401,90 @@ def main():
         # FP32 / FP64 FMA rate (256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz)
         kname = STUDENT_KERNEL[hprec]
         peak = ALU_PEAK_TFLOPS
-        roofline = dict(bound="alu", kernel=kname, achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                        frac=round(achieved / peak, 4), traffic=traffic_for(kname),
+        roofline = dict(bound="alu", kernel=kname, achieved=sig(achieved), peak=peak, unit="TFLOP/s",
+                        frac=sig(achieved / peak, 4), traffic=traffic_for(kname),
                         flops_per_launch=fl["embed_bwd"], rows_per_launch=rows,
                         flops_per_row=fl["emb_bwd_row"], flops_per_centre=fl["per_centre"],
-                        avg_launch_ms=bwd_ms, stage_tflops=stage_rates)
+                        avg_launch_ms=sig(bwd_ms), stage_tflops=rates)
     else:
         peak = PEAK_TFLOPS[hprec]
         kname = "k_embed_bwd<%s, 8>" % POLICY[hprec]
         roofline = dict(bound="mfma", kernel=kname,
-                        achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                        frac=round(achieved / peak, 4), traffic=traffic_for(kname),
+                        achieved=sig(achieved), peak=peak, unit="TFLOP/s",
+                        frac=sig(achieved / peak, 4), traffic=traffic_for(kname),
                         flops_per_launch=fl["embed_bwd"], rows_per_launch=rows,
-                        flops_per_row=fl["emb_bwd_row"], avg_launch_ms=bwd_ms,
-                        stage_tflops=stage_rates,
-                        # the same kernel against the vector-ALU ceiling (its non-product work)
+                        flops_per_row=fl["emb_bwd_row"], avg_launch_ms=sig(bwd_ms),
+                        stage_tflops=rates,
                         alu=dict(flops_per_row=fl["alu_bwd_row"],
-                                 achieved=round(fl["alu_bwd"] / (bwd_ms * 1e-3) / 1e12, 3),
+                                 achieved=sig(fl["alu_bwd"] / (bwd_ms * 1e-3) / 1e12),
                                  peak=ALU_PEAK_TFLOPS, unit="TFLOP/s",
-                                 frac=round(fl["alu_bwd"] / (bwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, 4)))
+                                 frac=sig(fl["alu_bwd"] / (bwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, 4)))
+
+    extra = {}
+    if not args.no_extras:
+        if args.workload == "water786k" and student is not None:
+            log("extra: water 12,288 atoms, 100 steps")
+            r12, rows12 = run_modes(D, path, student["x12"].clone(), student["v12"].clone(), student["t12"],
+                                    student["b12"], masses, dt, 100, args.warmup, modes, args.skin, student, log,
+                                    stage_pass=False)
+            for m_ in modes:
+                r12[m_]["embed_bwd_tflops"] = stage_rates(spec, rows12, 12288, r12[m_])["embed_bwd"]
+            extra["water12k"] = dict(workload="water 12,288 atoms (4,096 H2O, 49.7 A cube), 100 steps of 0.5 fs, "
+                                              "started 50 steps past the last student training frame",
+                                     atoms=12288, steps=100, real_neighbour_rows=rows12, modes=summarise(r12))
+        log("extra: copper 131,072 atoms, 50 steps of 1 fs")
+        cspec = I.COPPER
+        cpath = I.write_model(os.path.join(tmp, "copper.bin"), cspec, I.random_params(cspec, 103))
+        cc, ct, cb = I.config_copper131k(203)
+        cm = [I.MASS["Cu"]]
+        cv = I.maxwell_velocities(ct, cm, 300.0, 303)
+        cmodes = [m for m in modes if not m.endswith("+student")]
+        rcu, rowscu = run_modes(D, cpath, torch.as_tensor(cc, device="cuda"), torch.as_tensor(cv, device="cuda"),
+                                torch.as_tensor(ct, dtype=torch.int32, device="cuda"), cb, cm, 1.0, 50,
+                                args.warmup, cmodes, args.skin, None, log, stage_pass=False)
+        for m_ in cmodes:
+            rcu[m_]["embed_bwd_tflops"] = stage_rates(cspec, rowscu, len(ct), rcu[m_])["embed_bwd"]
+        extra["copper131k"] = dict(workload="Cu FCC 32^3 cells (131,072 atoms, a 3.634 A, 0.1 A jitter), "
+                                            "rc 8 A sel 512, emb 32x64x128, fit 240^3, 50 steps of 1 fs from 300 K",
+                                   atoms=len(ct), steps=50, real_neighbour_rows=rowscu, modes=summarise(rcu))
 
     cpu = None
     if not args.no_cpu_baseline:
         from oracle.oracle import Oracle, set_threads
-        nthr = min(16, os.cpu_count() or 1)
-        set_threads(nthr)
+        nthr = cpu_threads()
         o = Oracle(path)
-        if args.workload == "water786k":
-            # bounded sample: the oracle's per-atom evaluation of 1,024 atoms of the frame
-            idx = np.sort(np.random.default_rng(7).choice(n, 1024, replace=False))
+        rng = np.random.default_rng(7)
+        runs = {}
+        for thr, ns in ((nthr, 1024), (1, 64)):
+            set_threads(thr)
+            idx = np.sort(rng.choice(n, ns, replace=False))
             tc = time.perf_counter()
             o.eval_sampled(coords, types, box, idx)
             tc = time.perf_counter() - tc
-            cpu = dict(value=round(len(idx) / tc, 2), unit="atom-steps/s", cores=nthr, kind="oracle",
-                       sample="FP64 energy and forces of 1,024 sampled atoms of the 786,432-atom frame "
-                              "(per-atom evaluation incl. their neighbours' terms); %.1f s on %d threads"
-                              % (tc, nthr))
-        else:
-            tc = time.perf_counter()
-            o.eval(coords, types, box)
-            tc = time.perf_counter() - tc
-            cpu = dict(value=round(n / tc, 2), unit="atom-steps/s", cores=nthr, kind="oracle",
-                       sample="one FP64 force evaluation (E, F, virial) of the 12,288-atom frame = "
-                              "one MD step's force work; %.1f s on %d threads" % (tc, nthr))
+            runs[thr] = (ns / tc, ns, tc)
+        cpu = dict(value=sig(runs[nthr][0]), unit="atom-steps/s", cores=nthr, kind="oracle",
+                   sample="FP64 energy and exact forces of %d sampled atoms of the first frame (the oracle's "
+                          "local evaluation: every centre within rc of a sampled atom), one MD step's force "
+                          "work per atom; %.1f s on %d threads" % (runs[nthr][1], runs[nthr][2], nthr),
+                   single_thread=dict(value=sig(runs[1][0]), sample="%d sampled atoms, %.1f s on 1 thread"
+                                      % (runs[1][1], runs[1][2])),
+                   cpu_model=cpu_model(), os_cpu_count=os.cpu_count())
         log("cpu baseline", json.dumps(cpu))
 
     line = {
-        "metric": METRIC, "value": round(R["value"], 2), "unit": "atom-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(R["ms_per_step"], 4),
+        "metric": METRIC, "value": sig(R["value"], 8), "unit": "atom-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sig(R["ms_per_step"]),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[hprec] + (", student embedding" if R["student"] else ""), "data": "synthetic",
-        "config": {"workload": ("water 12,288 atoms (4,096 H2O, 49.7 A cube)" if args.workload == "water12k"
-                                else "water 786,432 atoms (262,144 H2O, 197.9 A cube)") +
-                               ", velocity-Verlet MD dt 0.5 fs from 300 K, DP-SE rc 6 A sel 46/92 emb "
+        "config": {"workload": wl + ", velocity-Verlet MD dt 0.5 fs from 300 K, DP-SE rc 6 A sel 46/92 emb "
                                "25x50x100 fit 240^3, random weights, neighbour skin %.1f A" % args.skin,
-                   "atoms": n, "mode": head, "skin_A": args.skin,
-                   "real_neighbour_rows": rows},
+                   "atoms": n, "mode": head, "skin_A": args.skin, "real_neighbour_rows": rows},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "modes": {m: {k: (round(v_, 6) if isinstance(v_, float) else v_) for k, v_ in r.items()}
-                  for m, r in results.items()},
-        "student_training": None if student is None else dict(seconds=round(student[4], 2), pairs=student[3]),
+        "modes": summarise(results),
+        "student_training": None if student is None else dict(seconds=sig(student["seconds"]),
+                                                              pairs=student["report"]),
+        "extra": extra,
     }
     print(json.dumps(line), flush=True)
 
