@@ -120,6 +120,21 @@ int dp_compute(dp_handle h, int64_t natoms, const double* coords, const int32_t*
                const double* box, double* energy, double* forces, double* virial,
                double* atom_energy, void* workspace, size_t ws_bytes, void* stream);
 
+/* dp_compute for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the workspace is the
+ * library's built-in scratch array of 64 MiB per device (a file-scope device array held
+ * until the process ends; enough for about 1,000 water atoms in FP64).  Arguments as
+ * dp_compute without workspace and ws_bytes; the weight region must be uploaded.
+ * Returns DP_ERR_WORKSPACE, launching nothing, when the frame needs more workspace than
+ * the array holds.  Every call on one device shares that device's array: calls that
+ * overlap in time on one device (other streams or threads) race and give undefined
+ * results.  The status word lives in the array, so device-detected conditions
+ * (DP_ERR_TYPE, DP_ERR_NONFINITE, DP_ERR_OVERLAP, DP_ERR_CAPACITY, the sel warning) are
+ * not reported: validate unfamiliar inputs with dp_compute first. */
+int dp_compute_noalloc(dp_handle h, int64_t natoms, const double* coords, const int32_t* types,
+                       const double* box, double* energy, double* forces, double* virial,
+                       double* atom_energy, void* stream);
+
 /* The same for a batch of independent frames of uneven size, in one launch per kernel.
  *   atom_offsets [nframes+1] host, coords/types/forces/atom_energy concatenated over
  *   frames, boxes [nframes][9] host, energies [nframes] and virials [nframes][9] device

@@ -970,6 +970,10 @@ int dp_init(const char* model_path, const dp_options* opt, dp_handle* out) {
     delete h;
     return fail(nullptr, DP_ERR_HIP, "no HIP device");
   }
+  if (noalloc_setup(h->device) != DP_OK) {
+    delete h;
+    return fail(nullptr, DP_ERR_HIP, "cannot resolve the scratch array of dp_compute_noalloc");
+  }
   plan_weights(h);
   *out = h;
   return DP_OK;

@@ -228,11 +228,13 @@ void launch_adam(size_t n, double* th, double* m, double* v, const double* g, do
                  double eps, int t, hipStream_t st);
 size_t scan_sums_ints(int n, int W);
 
-// C ABI helpers shared by the entry-point files
+// C ABI helpers shared by the entry-point files (dp_api.cpp, noalloc.hip)
 int handle_device(dp_handle_s* h);
 int set_error(dp_handle_s* h, int code, const std::string& msg);
 // workspace bytes of a one-frame force evaluation (dp_compute)
 int compute_ws_bytes(dp_handle_s* h, int64_t natoms, const double* box, size_t* bytes);
+// records the device address of the no-allocation scratch array of the current device
+int noalloc_setup(int device);
 
 struct MDMass {
   double m[kMaxTypes];
