@@ -853,3 +853,138 @@ int or_md(const or_model *m, int64_t n, double *x, double *v, const int32_t *typ
   free(F);
   return 0;
 }
+
+/* ---------------------------------------------------------------------------------
+ * Isobaric MD (isotropic box scaling), an extension of Section 4's velocity Verlet in
+ * which the pressure from the virial (the thermo quantity of Section 4) drives the box.
+ * Equations of motion of Martyna, Tobias and Klein (1994) with a Nose-Hoover thermostat
+ * on the particles (none when tau_t <= 0, i.e. isoenthalpic), N_f = 3N - 3 degrees of
+ * freedom, alpha = 1 + 3 / N_f, v_eps = p_eps / W, v_xi = p_xi / Q:
+ *   dx/dt = v + v_eps x
+ *   dv/dt = F / m - alpha v_eps v - v_xi v
+ *   dV/dt = 3 V v_eps,   dp_eps/dt = alpha 2 KE + tr(virial) - 3 V P_ext
+ *   dxi/dt = v_xi,       dp_xi/dt = 2 KE - N_f kT
+ * with W = (N_f + 3) kT tau_p^2 and Q = N_f kT tau_t^2.  Integrated by the symmetric
+ * splitting T(dt/2) E(dt/2) P(dt/2) R(dt) [forces] P(dt/2) E(dt/2) T(dt/2), each part
+ * solved exactly:
+ *   E(h): p_eps += h G_eps
+ *   P(h): v <- v exp(-alpha v_eps h) + h a exp(-alpha v_eps h / 2) sinhc(alpha v_eps h / 2)
+ *   R(h): x <- x exp(v_eps h) + h v exp(v_eps h / 2) sinhc(v_eps h / 2),  B <- B exp(v_eps h)
+ *   T(h): p_xi += h/2 G_xi;  v <- v exp(-h v_xi);  xi += h v_xi;  p_xi += h/2 G_xi
+ * It conserves H = E_pot + KE + p_eps^2 / (2 W) + P_ext V + p_xi^2 / (2 Q) + N_f kT xi up
+ * to O(dt^2).  box [9] is updated in place; thermo rows of 8:
+ * [step, PE, KE, T, Etot, P(bar), V, H]; state [3] (may be NULL) receives p_eps, xi, p_xi.
+ * --------------------------------------------------------------------------------- */
+static double npt_sinhc(double y) {
+  return fabs(y) < 1e-4 ? 1.0 + y * y / 6.0 * (1.0 + y * y / 20.0) : sinh(y) / y;
+}
+
+static double npt_ke(int64_t n, const double *v, const int32_t *types, const double *mass) {
+  double ke = 0.0;
+  for (int64_t i = 0; i < n; i++)
+    for (int c = 0; c < 3; c++) ke += 0.5 * mass[types[i]] * v[3 * i + c] * v[3 * i + c];
+  return ke / OR_ACC;
+}
+
+static double npt_volume(const double *B) {
+  return B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
+         B[2] * (B[3] * B[7] - B[4] * B[6]);
+}
+
+int or_md_npt(const or_model *m, int64_t n, double *x, double *v, const int32_t *types,
+              const double *mass, double *box, double pext_bar, double tau_p, double temp,
+              double tau_t, double dt, int nsteps, int thermo_every, double *thermo,
+              double *state) {
+  if (n < 2 || !(tau_p > 0) || !(temp > 0)) return -1;
+  const double nf = 3.0 * (double)n - 3.0, alpha = 1.0 + 3.0 / nf, kT = OR_KB * temp;
+  const double Wb = (nf + 3.0) * kT * tau_p * tau_p;
+  const int thermostat = tau_t > 0;
+  const double Q = thermostat ? nf * kT * tau_t * tau_t : 1.0;
+  const double pext = pext_bar / OR_EVA3_BAR;
+  double *F = (double *)malloc(24 * n);
+  double E, W[9];
+  int rc = or_eval(m, n, x, types, box, &E, F, W, NULL, NULL, NULL, NULL);
+  if (rc < 0) { free(F); return rc; }
+  double peps = 0.0, xi = 0.0, pxi = 0.0;
+  const double h = 0.5 * dt;
+  int row = 0;
+  for (int s = 0; s <= nsteps; s++) {
+    if (s > 0) {
+      /* T(dt/2) */
+      if (thermostat) {
+        double ke = npt_ke(n, v, types, mass);
+        pxi += 0.5 * h * (2.0 * ke - nf * kT);
+        const double c = exp(-h * pxi / Q);
+        for (int64_t q = 0; q < 3 * n; q++) v[q] *= c;
+        xi += h * pxi / Q;
+        ke = npt_ke(n, v, types, mass);
+        pxi += 0.5 * h * (2.0 * ke - nf * kT);
+      }
+      /* E(dt/2) */
+      {
+        const double ke = npt_ke(n, v, types, mass);
+        peps += h * (alpha * 2.0 * ke + (W[0] + W[4] + W[8]) - 3.0 * npt_volume(box) * pext);
+      }
+      /* P(dt/2) */
+      {
+        const double ve = peps / Wb, y = alpha * ve * h;
+        const double a1 = exp(-y), b1 = h * exp(-0.5 * y) * npt_sinhc(0.5 * y);
+        for (int64_t i = 0; i < n; i++)
+          for (int c = 0; c < 3; c++)
+            v[3 * i + c] = v[3 * i + c] * a1 + b1 * F[3 * i + c] / mass[types[i]] * OR_ACC;
+      }
+      /* R(dt) */
+      {
+        const double ve = peps / Wb, y = ve * dt;
+        const double sx = exp(y), b2 = dt * exp(0.5 * y) * npt_sinhc(0.5 * y);
+        for (int64_t q = 0; q < 3 * n; q++) x[q] = x[q] * sx + b2 * v[q];
+        for (int q = 0; q < 9; q++) box[q] *= sx;
+      }
+      rc = or_eval(m, n, x, types, box, &E, F, W, NULL, NULL, NULL, NULL);
+      if (rc < 0) { free(F); return rc; }
+      /* P(dt/2) */
+      {
+        const double ve = peps / Wb, y = alpha * ve * h;
+        const double a1 = exp(-y), b1 = h * exp(-0.5 * y) * npt_sinhc(0.5 * y);
+        for (int64_t i = 0; i < n; i++)
+          for (int c = 0; c < 3; c++)
+            v[3 * i + c] = v[3 * i + c] * a1 + b1 * F[3 * i + c] / mass[types[i]] * OR_ACC;
+      }
+      /* E(dt/2) */
+      {
+        const double ke = npt_ke(n, v, types, mass);
+        peps += h * (alpha * 2.0 * ke + (W[0] + W[4] + W[8]) - 3.0 * npt_volume(box) * pext);
+      }
+      /* T(dt/2) */
+      if (thermostat) {
+        double ke = npt_ke(n, v, types, mass);
+        pxi += 0.5 * h * (2.0 * ke - nf * kT);
+        const double c = exp(-h * pxi / Q);
+        for (int64_t q = 0; q < 3 * n; q++) v[q] *= c;
+        xi += h * pxi / Q;
+        ke = npt_ke(n, v, types, mass);
+        pxi += 0.5 * h * (2.0 * ke - nf * kT);
+      }
+    }
+    if (thermo && (s == 0 || (thermo_every > 0 && s % thermo_every == 0))) {
+      const double ke = npt_ke(n, v, types, mass), V = npt_volume(box);
+      double *r = thermo + 8 * row++;
+      r[0] = s;
+      r[1] = E;
+      r[2] = ke;
+      r[3] = 2.0 * ke / (nf * OR_KB);
+      r[4] = E + ke;
+      r[5] = (2.0 * ke + (W[0] + W[4] + W[8])) / (3.0 * V) * OR_EVA3_BAR;
+      r[6] = V;
+      r[7] = E + ke + 0.5 * peps * peps / Wb + pext * V +
+             (thermostat ? 0.5 * pxi * pxi / Q + nf * kT * xi : 0.0);
+    }
+  }
+  if (state) {
+    state[0] = peps;
+    state[1] = xi;
+    state[2] = pxi;
+  }
+  free(F);
+  return 0;
+}

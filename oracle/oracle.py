@@ -48,6 +48,7 @@ def lib():
         L.or_eval.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
         L.or_eval_sampled.argtypes = [P, I64, P, P, P, I64, P, P, P]
         L.or_md.argtypes = [P, I64, P, P, P, P, P, D, C.c_int, C.c_int, P]
+        L.or_md_npt.argtypes = [P, I64, P, P, P, P, P, D, D, D, D, D, C.c_int, C.c_int, P, P]
         L.or_set_threads.argtypes = [C.c_int]
         L.or_get_threads.restype = C.c_int
         _lib = L
@@ -171,3 +172,20 @@ class Oracle:
         if rc < 0:
             raise ValueError("oracle md error %d" % rc)
         return x, v, th
+
+    def md_npt(self, x, v, types, masses, box, pext_bar, tau_p, temp, tau_t, dt, nsteps, thermo_every):
+        """Isotropic isobaric MD (Martyna-Tobias-Klein barostat, optional Nose-Hoover
+        thermostat: tau_t <= 0 gives the isoenthalpic form).  Returns x, v, box, thermo
+        rows [step, PE, KE, T, Etot, P(bar), V, H] and (p_eps, xi, p_xi)."""
+        x, v = _f64(x).copy(), _f64(v).copy()
+        types, masses = _i32(types), _f64(masses)
+        box = _f64(box).reshape(9).copy()
+        nrow = 1 + (nsteps // thermo_every if thermo_every > 0 else 0)
+        th = np.zeros((nrow, 8))
+        st = np.zeros(3)
+        rc = lib().or_md_npt(self.h, len(types), _p(x), _p(v), _p(types), _p(masses), _p(box),
+                             float(pext_bar), float(tau_p), float(temp), float(tau_t), float(dt), int(nsteps),
+                             int(thermo_every), _p(th), _p(st))
+        if rc < 0:
+            raise ValueError("oracle md_npt error %d" % rc)
+        return x, v, box.reshape(3, 3), th, st

@@ -690,3 +690,93 @@ def test_oracle_results_independent_of_thread_count(water_model, water192):
     assert abs(r2["E"] - r1["E"]) < 1e-12 * abs(r1["E"])
     assert np.abs(r2["F"] - r1["F"]).max() < 1e-12 * np.abs(r1["F"]).max()
     assert np.abs(r2["W"] - r1["W"]).max() < 1e-12 * np.abs(r1["W"]).max()
+
+
+# ---------------------------------------------------------------------------------------
+# isobaric MD (Martyna-Tobias-Klein barostat driven by the virial pressure, optional
+# Nose-Hoover thermostat), the oracle's or_md_npt
+# ---------------------------------------------------------------------------------------
+
+KB_EV = 8.617333262e-5
+
+
+def _ideal_gas_oracle():
+    spec = TINY
+    p = _zeroed(spec, 22, keep={("emb", 0), ("emb", 1), ("emb", 2), ("out",)})
+    return Oracle(model_file("zerofit", spec, 22, p))
+
+
+def test_npt_ideal_gas_adiabatic_invariant():
+    """With F = 0 and W = 0 the isoenthalpic equations reduce to dv/dt = -alpha v_eps v,
+    dV/dt = 3 V v_eps, so KE V^(2 alpha / 3) is invariant (alpha = 1 + 3 / N_f); the
+    splitting solves both exactly at constant v_eps, so the invariant holds to rounding at
+    any step size while the gas is compressed far from its start (here it oscillates
+    between 250 and 10 A^3 with a period of 60 fs)."""
+    o = _ideal_gas_oracle()
+    c, t, b = tiny_water(11, 2, 6.3)
+    masses = [15.9994, 1.00794]
+    v = I.maxwell_velocities(t, masses, 300.0, 3)
+    n = len(t)
+    alpha = 1.0 + 3.0 / (3.0 * n - 3.0)
+    x, v2, box, th, st = o.md_npt(c, v, t, masses, b, 5.0e4, 40.0, 300.0, 0.0, 2.0, 60, 5)
+    inv = th[:, 2] * th[:, 6] ** (2.0 * alpha / 3.0)
+    assert th[:, 6].min() < 0.1 * th[0, 6]        # the box really moved
+    np.testing.assert_allclose(inv, inv[0], rtol=1e-12)
+    # the wrong exponent (alpha = 1, the non-MTK form) would not be invariant
+    inv1 = th[:, 2] * th[:, 6] ** (2.0 / 3.0)
+    assert np.abs(inv1 / inv1[0] - 1.0).max() > 1e-4
+    assert abs(np.linalg.det(box) - th[-1, 6]) < 1e-9 * th[-1, 6]
+
+
+def test_npt_ideal_gas_barostat_at_equilibrium():
+    """P_ext equal to the ideal gas's alpha-weighted kinetic pressure alpha 2 KE / (3 V):
+    the barostat force vanishes, so the box stays put and the atoms fly freely."""
+    o = _ideal_gas_oracle()
+    c, t, b = tiny_water(11, 2, 6.3)
+    masses = [15.9994, 1.00794]
+    v = I.maxwell_velocities(t, masses, 300.0, 3)
+    n = len(t)
+    alpha = 1.0 + 3.0 / (3.0 * n - 3.0)
+    m = np.array(masses)[t]
+    ke = 0.5 * (m[:, None] * v * v).sum() * I.AMU_A2_FS2_IN_EV
+    V = np.linalg.det(b)
+    pext = alpha * 2.0 * ke / (3.0 * V) * EV_A3_IN_BAR
+    x, v2, box, th, st = o.md_npt(c, v, t, masses, b, pext, 40.0, 300.0, 0.0, 1.0, 10, 5)
+    np.testing.assert_allclose(box, b, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(v2, v, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(x, c + 10 * 1.0 * v, rtol=0, atol=1e-10)
+    assert abs(st[0]) < 1e-9
+
+
+def test_npt_infinite_barostat_mass_is_velocity_verlet(tiny_model):
+    """A barostat of huge mass (tau_p = 1e9 fs) and no thermostat leave the box fixed and
+    reduce every part of the splitting to velocity Verlet: the trajectory equals or_md's."""
+    o = Oracle(tiny_model)
+    c, t, b = tiny_water(11, 2, 6.3)
+    masses = [15.9994, 1.00794]
+    v = I.maxwell_velocities(t, masses, 300.0, 4)
+    x1, v1, box, th, _ = o.md_npt(c, v, t, masses, b, 1.0, 1e9, 300.0, 0.0, 0.5, 20, 5)
+    x0, v0, th0 = o.md(c, v, t, masses, b, 0.5, 20, 5)
+    np.testing.assert_allclose(x1, x0, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(v1, v0, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(th[:, :6], th0, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(box, b, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("tau_t", [0.0, 25.0])
+def test_npt_conserved_quantity_error_scales_as_dt_squared(tau_t):
+    """The splitting is second order: the drift of H = E_pot + KE + p_eps^2 / 2W + P_ext V
+    (+ p_xi^2 / 2Q + N_f kT xi with the thermostat) falls about 4x when dt halves."""
+    spec = I.ModelSpec(ntypes=2, emb_width=(4, 8, 16), fit_width=(12, 12, 12), m2=4,
+                       sel=(30, 60), rc=4.0, rcs=0.5)
+    o = Oracle(model_file("tinywide", spec, 7))
+    c, t, b = tiny_water(11, 2, 6.3)
+    masses = [15.9994, 1.00794]
+    v = I.maxwell_velocities(t, masses, 300.0, 4)
+    errs = []
+    for dt, n in [(1.0, 40), (0.5, 80)]:
+        _, _, box, th, _ = o.md_npt(c, v, t, masses, b, 2000.0, 30.0, 300.0, tau_t, dt, n, 1)
+        errs.append(np.abs(th[:, 7] - th[0, 7]).max())
+        assert abs(th[-1, 6] / th[0, 6] - 1.0) > 1e-3     # the box moved
+    ratio = errs[0] / errs[1]
+    assert 3.5 < ratio < 4.5, (errs, ratio)
