@@ -174,6 +174,45 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
               int32_t thermo_every, double* thermo, double* forces, void* workspace,
               size_t ws_bytes, void* stream);
 
+/* Isobaric molecular dynamics (an extension of Section 4's velocity Verlet: the
+ * pressure from the virial, the thermo quantity of Section 4, drives an isotropic box
+ * scaling).  Equations of motion of Martyna, Tobias and Klein with an optional
+ * Nose-Hoover thermostat on the particles, N_f = 3N - 3, alpha = 1 + 3 / N_f:
+ *   dx/dt = v + v_eps x,  dv/dt = F/m - alpha v_eps v - v_xi v,  dV/dt = 3 V v_eps,
+ *   dp_eps/dt = alpha 2 KE + tr W - 3 V P_ext,  dp_xi/dt = 2 KE - N_f k_B T
+ * with v_eps = p_eps / W_b, W_b = (N_f + 3) k_B T tau_p^2, v_xi = p_xi / Q,
+ * Q = N_f k_B T tau_t^2, integrated by the symmetric splitting
+ * T(dt/2) E(dt/2) P(dt/2) R(dt) [forces] P(dt/2) E(dt/2) T(dt/2) (each part exact),
+ * which conserves H = E_pot + KE + p_eps^2/(2 W_b) + P_ext V (+ p_xi^2/(2Q) + N_f k_B T xi)
+ * to O(dt^2).  Any right-handed box (triclinic included) keeps its shape. */
+typedef struct {
+  double pressure_bar;   /* P_ext (bar) */
+  double tau_p_fs;       /* barostat time scale (> 0) */
+  double temperature_K;  /* T of the thermostat and of the barostat mass (> 0) */
+  double tau_t_fs;       /* thermostat time scale; 0: no thermostat (isoenthalpic) */
+  double min_scale;      /* smallest linear box scale, relative to the initial box, that
+                            the workspace plan covers, in (0.5, 1]; a run that compresses
+                            further reports DP_ERR_CAPACITY through dp_status */
+} dp_npt_options;
+
+/* Workspace bytes of dp_md_run_npt for one frame of natoms atoms in box (host [9]). */
+int dp_md_npt_workspace_size(dp_handle h, int64_t natoms, const double* box, double min_scale, size_t* bytes);
+
+/* nsteps isobaric MD steps of dt_fs on one frame; needs a handle with skin > 0 (the list
+ * of pairs within rc + skin is rebuilt when some atom's displacement beyond the affine
+ * box scaling exceeds (mu (rc + skin) - rc) / 2, mu = box scale relative to the last
+ * build).  x, v device [natoms][3] updated in place (x not wrapped); box host [9] is the
+ * initial box and is not modified; thermo (device, may be NULL) receives rows of 8
+ * [step, E_pot, E_kin, T(K), E_pot + E_kin, P(bar), V(A^3), H(eV)] at step 0 and every
+ * thermo_every steps; box_out (device [9], may be NULL) the final box; state_out (device
+ * [3], may be NULL) p_eps (eV fs), xi, p_xi (eV fs) at the end; forces (device
+ * [natoms][3], may be NULL) the final forces.  The run starts with p_eps = xi = p_xi = 0.
+ * Errors as dp_md_run; DP_ERR_ARG for bad options or a handle without a skin. */
+int dp_md_run_npt(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* types, const double* masses,
+                  const double* box, const dp_npt_options* npt, double dt_fs, int32_t nsteps,
+                  int32_t thermo_every, double* thermo, double* box_out, double* state_out, double* forces,
+                  void* workspace, size_t ws_bytes, void* stream);
+
 /* Replace the model parameters by theta (device, FP64, nparams values in the model
  * file's flat order) and rebuild the kernels' weight layouts on stream.  Later calls
  * on the handle use the new parameters.  dp_get_params copies the current ones out. */

@@ -550,7 +550,7 @@ struct Plan {
       o_g1, o_Ei, o_vir, o_tmpj, o_tmpi, o_mdF, o_mdE, o_mdW, o_fb, o_fbcnt;
   // Verlet reuse (MD with a skin)
   bool verlet = false;
-  size_t o_wk, o_xref, o_eabc, o_vlist, o_vcnt, o_vflag;
+  size_t o_wk, o_xref, o_eabc, o_vlist, o_vcnt, o_vflag, o_npt = 0;
   int n, nframes, ncell, ghost_cap, nrows, vcap, max_frame_atoms;
   size_t o_redpart, o_reddone;
   size_t o_gbuf = 0, o_rev = 0;   // deterministic force gather
@@ -561,8 +561,10 @@ static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // verlet: lay out the MD Verlet reuse as well (ghost shell and cells for rc + skin,
 // image codes over the whole ghost range)
+// min_scale < 1 (isobaric MD): the Verlet plan's ghost shell, cells and candidate rows
+// also cover the box compressed to min_scale times its linear size
 static int make_plan(dp_handle h, int nframes, const int64_t* off, const double* boxes,
-                     std::vector<Frame>* frames, Plan& P, bool verlet = false) {
+                     std::vector<Frame>* frames, Plan& P, bool verlet = false, double min_scale = 1.0) {
   if (nframes < 1) return fail(h, DP_ERR_ARG, "nframes must be >= 1");
   if (off[0] != 0) return fail(h, DP_ERR_ARG, "atom_offsets[0] must be 0");
   int64_t n = off[nframes];
@@ -574,7 +576,7 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
     if (na < 1) return fail(h, DP_ERR_ARG, "every frame needs at least one atom");
     maxna = std::max(maxna, na);
     Frame F{};
-    if (box_setup(boxes + 9 * f, verlet ? h->rc + h->opt.skin : h->rc, F))
+    if (box_setup(boxes + 9 * f, verlet ? (h->rc + h->opt.skin) / min_scale : h->rc, F))
       return fail(h, DP_ERR_BOX, "singular or left-handed box");
     if (verlet) {
       F.nimg = 1;
@@ -661,7 +663,7 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
   P.vcap = 0;
   if (verlet) {
     // candidates within rc + skin: the rc capacity scaled by the volume ratio
-    double q = (h->rc + h->opt.skin) / h->rc;
+    double q = (h->rc + h->opt.skin) / (h->rc * min_scale);
     P.vcap = (int)std::min<double>(4.0 * kMaxCand, std::ceil(kMaxCand * q * q * q / 64.0) * 64.0);
     P.o_wk = take(sizeof(int) * 3 * n);
     P.o_xref = take(sizeof(double) * 3 * n);
@@ -669,6 +671,7 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
     P.o_vlist = take(sizeof(int) * (size_t)n * P.vcap);
     P.o_vcnt = take(sizeof(int) * n);
     P.o_vflag = take(sizeof(int) * 64);
+    P.o_npt = take(sizeof(double) * NS_COUNT);
   }
   P.total = o;
   return DP_OK;
@@ -724,10 +727,10 @@ struct Ws {
 // plans the call, validates the workspace and copies the frame table to the device
 static int stage_frames(dp_handle h, int nframes, const int64_t* off, const double* boxes,
                         const double* coords, const int32_t* types, void* ws, size_t ws_bytes,
-                        hipStream_t st, Plan& P, NlistArgs& A, bool verlet = false) {
+                        hipStream_t st, Plan& P, NlistArgs& A, bool verlet = false, double min_scale = 1.0) {
   if (need_weights(h) != DP_OK) return DP_ERR_ARG;
   std::vector<Frame> frames;
-  int rc = make_plan(h, nframes, off, boxes, &frames, P, verlet);
+  int rc = make_plan(h, nframes, off, boxes, &frames, P, verlet, min_scale);
   if (rc != DP_OK) return rc;
   if (!ws || ws_bytes < P.total)
     return fail(h, DP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(P.total) + " bytes");
@@ -1172,6 +1175,118 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
       opened = true;
     }
   }
+  HIPCHECK(h, hipGetLastError());
+  return DP_OK;
+}
+
+int dp_md_npt_workspace_size(dp_handle h, int64_t natoms, const double* box, double min_scale, size_t* bytes) {
+  if (!h || !box || !bytes) return fail(h, DP_ERR_ARG, "null argument");
+  if (!(h->opt.skin > 0)) return fail(h, DP_ERR_ARG, "isobaric MD needs a handle with a neighbour skin > 0");
+  if (!(min_scale > 0.5 && min_scale <= 1.0)) return fail(h, DP_ERR_ARG, "min_scale must be in (0.5, 1]");
+  int64_t off[2] = {0, natoms};
+  Plan P;
+  int rc = make_plan(h, 1, off, box, nullptr, P, true, min_scale);
+  if (rc != DP_OK) return rc;
+  *bytes = P.total;
+  return DP_OK;
+}
+
+int dp_md_run_npt(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* types, const double* masses,
+                  const double* box, const dp_npt_options* npt, double dt_fs, int32_t nsteps,
+                  int32_t thermo_every, double* thermo, double* box_out, double* state_out, double* forces,
+                  void* workspace, size_t ws_bytes, void* stream) {
+  if (!h) return DP_ERR_ARG;
+  if (!x || !v || !types || !masses || !box || !npt) return fail(h, DP_ERR_ARG, "null argument");
+  if (!(h->opt.skin > 0)) return fail(h, DP_ERR_ARG, "isobaric MD needs a handle with a neighbour skin > 0");
+  if (nsteps < 0 || thermo_every < 0 || !(dt_fs > 0) || !std::isfinite(dt_fs))
+    return fail(h, DP_ERR_ARG, "bad step count or time step");
+  if (!(npt->tau_p_fs > 0) || !(npt->temperature_K > 0) || !std::isfinite(npt->pressure_bar) ||
+      !(npt->tau_t_fs >= 0) || !(npt->min_scale > 0.5 && npt->min_scale <= 1.0))
+    return fail(h, DP_ERR_ARG, "bad isobaric options (tau_p > 0, T > 0, tau_t >= 0, min_scale in (0.5, 1])");
+  if (natoms < 2) return fail(h, DP_ERR_ARG, "isobaric MD needs at least two atoms");
+  MDMass mm{};
+  for (int t = 0; t < h->ntypes; t++) {
+    if (!(masses[t] > 0) || !std::isfinite(masses[t])) return fail(h, DP_ERR_ARG, "masses must be > 0");
+    mm.m[t] = masses[t];
+    mm.inv[t] = 1.0 / masses[t];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int64_t off[2] = {0, natoms};
+  Plan P;
+  NlistArgs A{};
+  int rc = stage_frames(h, 1, off, box, x, types, workspace, ws_bytes, st, P, A, true, npt->min_scale);
+  if (rc != DP_OK) return rc;
+  Ws W{(char*)workspace, &P};
+  double* S = W.at<double>(P.o_npt);
+  A.npt = S;
+  launch_fill_int((int*)A.gate, 1, 1, st);   // build at the first step
+  // constants of the run; the plan's frame (box_setup at the enlarged radius) carries the
+  // initial box and its inverse
+  NptConst c{};
+  {
+    Frame F0{};
+    if (box_setup(box, h->rc, F0)) return fail(h, DP_ERR_BOX, "singular or left-handed box");
+    for (int k = 0; k < 9; k++) {
+      c.B0[k] = F0.B[k];
+      c.Bi0[k] = F0.Bi[k];
+    }
+  }
+  const double* B = box;
+  c.V0 = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) + B[2] * (B[3] * B[7] - B[4] * B[6]);
+  c.nf = 3.0 * (double)natoms - 3.0;
+  c.alpha = 1.0 + 3.0 / c.nf;
+  c.kT = 8.617333262e-5 * npt->temperature_K;
+  c.W = (c.nf + 3.0) * c.kT * npt->tau_p_fs * npt->tau_p_fs;
+  c.thermostat = npt->tau_t_fs > 0 ? 1 : 0;
+  c.Q = c.thermostat ? c.nf * c.kT * npt->tau_t_fs * npt->tau_t_fs : 1.0;
+  c.pext = npt->pressure_bar / 1.602176634e6;
+  c.h = 0.5 * dt_fs;
+  c.dt = dt_fs;
+  c.rl = h->rc + h->opt.skin;
+  c.rc = h->rc;
+  c.min_scale = npt->min_scale;
+  const int n = (int)natoms;
+  double* F = forces ? forces : W.at<double>(P.o_mdF);
+  double* E = W.at<double>(P.o_mdE);
+  double* Wv = W.at<double>(P.o_mdW);
+  VvCheck chk{};
+  chk.xref = A.xref;
+  chk.gate = (int*)A.gate;
+  chk.nc1 = A.ncell + 1;
+  chk.c1 = A.cell_count;
+  chk.nc2 = A.ncell;
+  chk.c2 = A.cell_fill;
+  int* fb_clear = h->student_on ? W.at<int>(P.o_fbcnt) : nullptr;
+  // every step sums energy and virial: the barostat needs tr W
+  auto force = [&](bool f_zeroed, bool disp_done) -> int {
+    {
+      StageTimer tm(h, DP_STAGE_NLIST, st);
+      launch_nlist_verlet(A, 0.5 * h->opt.skin, disp_done, fb_clear, st);
+      A.skip_rows = true;
+      HIPCHECK(h, hipGetLastError());
+    }
+    return run_model(h, P, A, workspace, st, E, F, Wv, nullptr, true, nullptr, nullptr, f_zeroed, true,
+                     fb_clear != nullptr);
+  };
+  launch_npt_init(n, types, mm, v, S, c, st);
+  rc = force(false, false);
+  if (rc != DP_OK) return rc;
+  int row = 0;
+  if (thermo) launch_npt_close(n, types, mm, v, S, c, E, Wv, 0, thermo + 8 * row++, false, st);
+  for (int s = 1; s <= nsteps; s++) {
+    {
+      StageTimer tm(h, DP_STAGE_MD, st);
+      launch_npt_open(S, c, Wv, W.at<Frame>(P.o_frames), A.status, st);
+      launch_vv_npt_open(n, types, mm, F, v, x, S, chk, st);
+    }
+    rc = force(true, true);
+    if (rc != DP_OK) return rc;
+    StageTimer tm(h, DP_STAGE_MD, st);
+    launch_vv_npt_close(n, types, mm, F, v, S, st);
+    const bool thermo_row = thermo && thermo_every > 0 && s % thermo_every == 0;
+    launch_npt_close(n, types, mm, v, S, c, E, Wv, s, thermo_row ? thermo + 8 * row++ : nullptr, true, st);
+  }
+  launch_npt_finish(n, v, S, W.at<Frame>(P.o_frames), box_out, state_out, st);
   HIPCHECK(h, hipGetLastError());
   return DP_OK;
 }

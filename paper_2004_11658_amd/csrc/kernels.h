@@ -45,6 +45,8 @@ struct NlistArgs {
   bool cells_zeroed;   // cell counters already cleared by the caller (MD displacement check)
   int *big, *nbig;  // atoms deferred to the second formatting pass (too many candidates or tied
                     // short keys); nbig[0] is zero on entry and left zero, nbig[1] its pass counter
+  double* npt;      // isobaric MD state (NULL otherwise): a rebuild records the box scale
+                    // at which the rows were built (npt[NS_LAMB] = npt[NS_LAM])
 };
 size_t scan_sums_ints(int n, int W);
 // copies nframes frames from host memory to dst on the stream through kernel arguments
@@ -251,6 +253,48 @@ struct VvCheck {
   int nc2;
   int* c2;
 };
+// Isobaric MD (isotropic Martyna-Tobias-Klein barostat, optional Nose-Hoover thermostat
+// on the particles): constants of a run and the device state (doubles, in the workspace)
+struct NptConst {
+  double alpha;         // 1 + 3 / N_f
+  double nf, kT;        // N_f = 3N - 3, k_B T (eV)
+  double W, Q;          // barostat and thermostat masses (eV fs^2)
+  double pext;          // P_ext (eV / A^3)
+  double h, dt;         // dt / 2, dt (fs)
+  double rl, rc;        // list radius rc + skin at a build, cutoff
+  double min_scale;     // smallest linear box scale the workspace plan covers
+  int thermostat;       // 0: isoenthalpic
+  double B0[9], Bi0[9], V0;   // initial box, its inverse and volume
+};
+enum {
+  NS_PEPS = 0, NS_XI, NS_PXI,   // barostat momentum (eV fs), thermostat position and momentum
+  NS_LAM, NS_LAMB,              // box scale vs the initial box; scale at the last list build
+  NS_KE,                        // kinetic energy of v times NS_CPEND^2 (eV)
+  NS_CPEND,                     // thermostat scale not yet applied to v
+  NS_A1O, NS_A1, NS_B1,         // velocity factors: opening (with the pending scale), plain, force term
+  NS_SX, NS_B2,                 // position factors of the drift
+  NS_MU, NS_LIM2,               // scale since the last build, squared displacement limit of the skin check
+  NS_V,                         // volume (A^3)
+  NS_COUNT = 16
+};
+void launch_npt_init(int n, const int* types, const MDMass& mass, const double* v, double* state, const NptConst& c,
+                     hipStream_t st);
+// one thread: T(dt/2), E(dt/2), the step's factors, the box update of frame 0, skin limit
+void launch_npt_open(double* state, const NptConst& c, const double* W, Frame* frames, int* status, hipStream_t st);
+// P(dt/2) + R(dt) with the skin check (scaled reference positions); clears F
+void launch_vv_npt_open(int n, const int* types, const MDMass& mass, double* F, double* v, double* x,
+                        const double* state, const VvCheck& chk, hipStream_t st);
+// P(dt/2) after the force evaluation
+void launch_vv_npt_close(int n, const int* types, const MDMass& mass, const double* F, double* v,
+                         const double* state, hipStream_t st);
+// kinetic energy, E(dt/2), T(dt/2); a thermo row [step, PE, KE, T, Etot, P(bar), V, H] if row != NULL
+void launch_npt_close(int n, const int* types, const MDMass& mass, const double* v, double* state,
+                      const NptConst& c, const double* E, const double* W, int step, double* row, bool kick,
+                      hipStream_t st);
+// applies the pending thermostat scale to v; box_out [9] and state_out [3] (p_eps, xi, p_xi) may be NULL
+void launch_npt_finish(int n, double* v, const double* state, const Frame* frames, double* box_out,
+                       double* state_out, hipStream_t st);
+
 // closing half kick of a step + opening half kick and drift of the next; clears F
 void launch_vv_merged(int n, const int* types, const MDMass& mass, double dt, double* F, double* v, double* x,
                       const VvCheck& chk, hipStream_t st);

@@ -360,9 +360,11 @@ __global__ __launch_bounds__(256) void k_wrap(int n, int nframes, const Frame* _
                                               double* __restrict__ xw, double* __restrict__ fw,
                                               int* __restrict__ gcount, int* __restrict__ status,
                                               const int* __restrict__ gate, int* __restrict__ wk,
-                                              double* __restrict__ xref) {
+                                              double* __restrict__ xref, double* __restrict__ npt) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || (gate && *gate == 0)) return;
+  // isobaric MD: the reference positions written here belong to the current box scale
+  if (npt && i == 0) npt[NS_LAMB] = npt[NS_LAM];
   wrap_one(i, nframes, frames, ntypes, x, types, frame_of, xw, fw, gcount, status, wk, xref);
 }
 
@@ -1364,7 +1366,7 @@ static void launch_rebuild(const NlistArgs& A, bool rows_later, hipStream_t st) 
     hipLaunchKernelGGL(k_zero2_gated, dim3((A.ncell + 1 + 255) / 256), dim3(256), 0, st, A.ncell + 1,
                        A.cell_count, A.ncell, A.cell_fill, G);
   hipLaunchKernelGGL(k_wrap, dim3(nb), dim3(256), 0, st, n, A.nframes, A.frames, A.m.ntypes, A.x,
-                     A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status, G, A.wk, A.xref);
+                     A.types, A.frame_of, A.xw, A.fw, A.gcount, A.status, G, A.wk, A.xref, A.npt);
   const int ne_cap = n + A.ghost_cap;
   if (n <= kOneTile && A.ncell + 1 <= kCellScanCap && ((uintptr_t)A.gcount & 15) == 0) {
     hipLaunchKernelGGL(k_ghost_emit_scan, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, A.ghost_cap, A.frames,

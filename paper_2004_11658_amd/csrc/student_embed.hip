@@ -101,62 +101,43 @@ __device__ __forceinline__ bool stu_out_of_range(const EmbedArgs& A, int pair, d
   return s < A.st_lo[pair] || s > A.st_hi[pair];
 }
 
-// Environment row of one neighbour (Eq. 5) in the student's storage type: FP64 as
-// everywhere else, or FP32 (displacement from the FP64 coordinates, then r, 1/r, the
-// switch and R~ in FP32 with the hardware square root and reciprocal, about 1e-7
-// relative) for the FP32 student.
-template <class T>
+// Environment row of one neighbour (Eq. 5) in FP64 whatever the student's storage type:
+// displacement, r, 1/r, the switch s(r) and its derivative, R~ and the force geometry
+// stay FP64 (the precision contract of every mode); only s and R~ are rounded to the
+// student's type for the tanh layer and the per-centre products.
+// The switch is written through om = (rc - r) / (rc - rcs) = 1 - u: the same quintic as
+// the full net's, w = om^3 (6 u^2 + 3 u + 1), dw/dr = -30 u^2 om^2 / (rc - rcs), which keeps
+// its relative precision (and its sign) as w -> 0 at the cutoff, where the expanded form
+// 1 + u^3 (-6 u^2 + 15 u - 10) cancels to a few ulps of 1, possibly below zero; s then
+// never leaves a trained range that starts at 0.
 struct StuEnv {
-  T d[3], ir, s, ds, R[4];
+  double d[3], ir, s, ds, R[4];
 };
-__device__ __forceinline__ void stu_env(const ModelC& m, const double xj[3], const double xi[3], StuEnv<double>& v) {
-  Env e;
-  e.d[0] = xj[0] - xi[0];
-  e.d[1] = xj[1] - xi[1];
-  e.d[2] = xj[2] - xi[2];
-  const double r2 = e.d[0] * e.d[0] + e.d[1] * e.d[1] + e.d[2] * e.d[2];
-  e.r = sqrt(r2);
-  e.ir = 1.0 / e.r;
-  smooth_fn_ir(m, e.r, e.ir, e.s, e.ds);
-  const double sr = e.s * e.ir;
-  for (int c = 0; c < 3; c++) v.d[c] = e.d[c];
-  v.ir = e.ir;
-  v.s = e.s;
-  v.ds = e.ds;
-  v.R[0] = e.s;
-  v.R[1] = sr * e.d[0];
-  v.R[2] = sr * e.d[1];
-  v.R[3] = sr * e.d[2];
-}
-__device__ __forceinline__ void stu_env(const ModelC& m, const double xj[3], const double xi[3], StuEnv<float>& v) {
-  v.d[0] = (float)(xj[0] - xi[0]);
-  v.d[1] = (float)(xj[1] - xi[1]);
-  v.d[2] = (float)(xj[2] - xi[2]);
-  const float r2 = v.d[0] * v.d[0] + v.d[1] * v.d[1] + v.d[2] * v.d[2];
-  const float r = __builtin_amdgcn_sqrtf(r2);
-  v.ir = __builtin_amdgcn_rcpf(r);
-  float w = 0.f, dw = 0.f;
-  const float rcs = (float)m.rcs, rc = (float)m.rc, ih = (float)m.inv_h;
-  if (r < rcs) {
-    w = 1.f;
-  } else if (r < rc) {
-    // 1 - u = (rc - r) / (rc - rcs) without cancellation, and the quintic in the
-    // factored form w = (1 - u)^3 (6 u^2 + 3 u + 1), which keeps its relative precision
-    // as w -> 0 at the cutoff (1 + u^3 (-6 u^2 + 15 u - 10) would cancel there in FP32)
-    const float om = (rc - r) * ih, u = 1.f - om;
+__device__ __forceinline__ void stu_env(const ModelC& m, const double xj[3], const double xi[3], StuEnv& v) {
+  v.d[0] = xj[0] - xi[0];
+  v.d[1] = xj[1] - xi[1];
+  v.d[2] = xj[2] - xi[2];
+  const double r2 = v.d[0] * v.d[0] + v.d[1] * v.d[1] + v.d[2] * v.d[2];
+  const double r = sqrt(r2);
+  v.ir = 1.0 / r;
+  double w = 0.0, dw = 0.0;
+  if (r < m.rcs) {
+    w = 1.0;
+  } else if (r < m.rc) {
+    const double om = (m.rc - r) * m.inv_h, u = 1.0 - om;
     if (m.switch_kind == 1) {
-      float sp, cp;
-      __sincosf(3.14159265358979f * om, &sp, &cp);   // cos(pi u) = -cos(pi (1 - u))
-      w = 0.5f - 0.5f * cp;
-      dw = -0.5f * 3.14159265358979f * sp * ih;      // sin(pi u) = sin(pi (1 - u))
+      double sp, cp;
+      sincos(M_PI * om, &sp, &cp);   // cos(pi u) = -cos(pi (1 - u)), sin(pi u) = sin(pi (1 - u))
+      w = 0.5 - 0.5 * cp;
+      dw = -0.5 * M_PI * sp * m.inv_h;
     } else {
-      w = om * om * om * (6.f * u * u + 3.f * u + 1.f);
-      dw = -30.f * u * u * om * om * ih;
+      w = om * om * om * (6.0 * u * u + 3.0 * u + 1.0);
+      dw = -30.0 * u * u * om * om * m.inv_h;
     }
   }
   v.s = w * v.ir;
   v.ds = (dw - w * v.ir) * v.ir;
-  const float sr = v.s * v.ir;
+  const double sr = v.s * v.ir;
   v.R[0] = v.s;
   v.R[1] = sr * v.d[0];
   v.R[2] = sr * v.d[1];
@@ -229,16 +210,16 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
       en = stu_fetch(A.xe, nl, c0 + 64 + lane, nn, xn);
       T sL = (T)0, RL[4] = {(T)0, (T)0, (T)0, (T)0};
       if (e >= 0) {
-        StuEnv<T> v;
+        StuEnv v;
         stu_env(m, xj, xi, v);
-        if (stu_out_of_range(A, pair, (double)v.s)) {
+        if (stu_out_of_range(A, pair, v.s)) {
           // left to the full net (fallback list); contributes nothing here
           const int p = atomicAdd(A.fb_count, 1);
           if (p < A.fb_cap) A.fb_list[p] = make_int2(row, e);
         } else {
-          sL = v.s;
+          sL = (T)v.s;
 #pragma unroll
-          for (int c = 0; c < 4; c++) RL[c] = v.R[c];
+          for (int c = 0; c < 4; c++) RL[c] = (T)v.R[c];
         }
       }
 #pragma unroll
@@ -353,8 +334,8 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
   // through the constant address space (scalar loads into scalar registers)
   const __attribute__((address_space(4))) T* gt =
       (const __attribute__((address_space(4))) T*)((const T*)A.gT + (size_t)(live ? row : 0) * M * 4);
-  T fi = (T)0;                    // force component g on the centre (lane groups 0..2)
-  T vir[3] = {(T)0, (T)0, (T)0};  // virial column g: W[a][g]
+  double fi = 0.0;                    // force component g on the centre (lane groups 0..2)
+  double vir[3] = {0.0, 0.0, 0.0};    // virial column g: W[a][g]
   const T inorm = (T)m.inv_norm;
   for (int b0 = 0; b0 < m.ntypes; b0 += 2) {
     const int nb = min(2, m.ntypes - b0);
@@ -416,16 +397,16 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
       const double xj[3] = {xn[0], xn[1], xn[2]};
       en = stu_fetch(A.xe, nl, c0 + 16 + rb, nn, xn);
       bool valid = e >= 0;
-      StuEnv<T> v;
+      StuEnv v;
       T s = (T)0, R[4] = {(T)0, (T)0, (T)0, (T)0};
       if (valid) {
         stu_env(m, xj, xi, v);
-        if (stu_out_of_range(A, pair, (double)v.s)) {
+        if (stu_out_of_range(A, pair, v.s)) {
           valid = false;   // handled by the fallback kernel
         } else {
-          s = v.s;
+          s = (T)v.s;
 #pragma unroll
-          for (int c = 0; c < 4; c++) R[c] = v.R[c];
+          for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
         }
       }
       // gR[c] = sum_p G[p] gt[p][c] = h . V[:, c] + u[c];  dsl = dE/ds through G
@@ -447,19 +428,22 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
       }
 #pragma unroll
       for (int c = 0; c < 4; c++) gR[c] = sum_g(gR[c]) + uu[c];
-      const T dsl = sum_g(dsp) * inorm;
-      // g_ij = dR^T dE/dR (Eq. 5 differentiated): lane group g < 3 computes component g
+      const T dsl = sum_g(dsp) * inorm;   // dE/ds through G, in the student's type
+      // g_ij = dR^T dE/dR (Eq. 5 differentiated) in FP64: lane group g < 3 computes
+      // component g from the FP64 environment row and dE/dR~ (the student's sums)
       if (valid && g < 3) {
-        const T gRd[4] = {gR[0] * inorm + dsl, gR[1] * inorm, gR[2] * inorm, gR[3] * inorm};
-        const T ir = v.ir;
-        const T sr = v.s * ir;
-        const T qf = (v.ds * ir - v.s * ir * ir) * ir;
-        const T dot = gRd[1] * v.d[0] + gRd[2] * v.d[1] + gRd[3] * v.d[2];
-        const T db = g == 0 ? v.d[0] : g == 1 ? v.d[1] : v.d[2];
-        const T gRb = g == 0 ? gRd[1] : g == 1 ? gRd[2] : gRd[3];
-        const T gv = gRd[0] * v.ds * db * ir + qf * dot * db + sr * gRb;
+        const double in = m.inv_norm;
+        const double gRd[4] = {(double)gR[0] * in + (double)dsl, (double)gR[1] * in, (double)gR[2] * in,
+                               (double)gR[3] * in};
+        const double ir = v.ir;
+        const double sr = v.s * ir;
+        const double qf = (v.ds * ir - v.s * ir * ir) * ir;
+        const double dot = gRd[1] * v.d[0] + gRd[2] * v.d[1] + gRd[3] * v.d[2];
+        const double db = g == 0 ? v.d[0] : g == 1 ? v.d[1] : v.d[2];
+        const double gRb = g == 0 ? gRd[1] : g == 1 ? gRd[2] : gRd[3];
+        const double gv = gRd[0] * v.ds * db * ir + qf * dot * db + sr * gRb;
         fi += gv;
-        unsafeAtomicAdd(&A.forces[3 * A.eown[e] + g], -(double)gv);
+        unsafeAtomicAdd(&A.forces[3 * A.eown[e] + g], -gv);
 #pragma unroll
         for (int a = 0; a < 3; a++) vir[a] -= v.d[a] * gv;   // W[a][g]
       }
@@ -475,9 +459,9 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
     for (int a = 0; a < 3; a++) vir[a] += __shfl_xor(vir[a], o);
   }
   if (rb == 0 && g < 3) {
-    unsafeAtomicAdd(&A.forces[3 * atom + g], (double)fi);
+    unsafeAtomicAdd(&A.forces[3 * atom + g], fi);
 #pragma unroll
-    for (int a = 0; a < 3; a++) A.vir_part[(size_t)row * 9 + 3 * a + g] = (double)vir[a];
+    for (int a = 0; a < 3; a++) A.vir_part[(size_t)row * 9 + 3 * a + g] = vir[a];
   }
 }
 

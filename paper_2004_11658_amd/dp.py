@@ -32,6 +32,11 @@ class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("deterministic", C.c_int32), ("skin", C.c_double)]
 
 
+class _NptOptions(C.Structure):
+    _fields_ = [("pressure_bar", C.c_double), ("tau_p_fs", C.c_double), ("temperature_K", C.c_double),
+                ("tau_t_fs", C.c_double), ("min_scale", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libdp.so is not built (run __graft_entry__.build() or "
@@ -53,6 +58,8 @@ def _load():
         "dp_status": ([P, P, P, P, P], C.c_int),
         "dp_fallback_rows": ([P, P, P, P], C.c_int),
         "dp_md_run": ([P, I64, P, P, P, P, P, D, I32, I32, P, P, P, SZ, P], C.c_int),
+        "dp_md_npt_workspace_size": ([P, I64, P, D, P], C.c_int),
+        "dp_md_run_npt": ([P, I64, P, P, P, P, P, P, D, I32, I32, P, P, P, P, P, SZ, P], C.c_int),
         "dp_profile": ([P, I32], C.c_int),
         "dp_profile_stages": ([P, C.c_uint32], C.c_int),
         "dp_set_params": ([P, P, P], C.c_int),
@@ -256,6 +263,38 @@ class DPModel:
         if check:
             self.status()
         return th
+
+    def md_run_npt(self, x: torch.Tensor, v: torch.Tensor, types, masses, box, pressure_bar: float,
+                   tau_p: float, temperature: float, tau_t: float, dt: float, nsteps: int,
+                   thermo_every: int = 0, min_scale: float = 0.9, forces: Optional[torch.Tensor] = None,
+                   check: bool = True):
+        """Isobaric MD in place on device tensors x, v (dp_md_run_npt); returns the thermo
+        rows [step, PE, KE, T, Etot, P(bar), V, H], the final box (3 x 3) and
+        (p_eps, xi, p_xi), device tensors."""
+        assert x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()
+        assert v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+        t = self._dev(types, torch.int32)
+        n = x.shape[0]
+        b = _box9(box)
+        ms = np.ascontiguousarray(masses, dtype=np.float64)
+        nb = C.c_size_t()
+        self._check(_lib.dp_md_npt_workspace_size(self.h, n, b.ctypes.data_as(C.c_void_p), float(min_scale),
+                                                  C.byref(nb)))
+        if self._ws is None or self._ws.numel() < nb.value:
+            self._ws = torch.empty(int(nb.value * 1.1) + 4096, dtype=torch.uint8, device=self.device)
+        ws = self._ws
+        opt = _NptOptions(float(pressure_bar), float(tau_p), float(temperature), float(tau_t), float(min_scale))
+        nrow = 1 + (nsteps // thermo_every if thermo_every > 0 else 0)
+        th = torch.zeros(nrow, 8, dtype=torch.float64, device=x.device)
+        box_out = torch.zeros(9, dtype=torch.float64, device=x.device)
+        state = torch.zeros(3, dtype=torch.float64, device=x.device)
+        self._check(_lib.dp_md_run_npt(self.h, n, _ptr(x), _ptr(v), _ptr(t), ms.ctypes.data_as(C.c_void_p),
+                                       b.ctypes.data_as(C.c_void_p), C.byref(opt), float(dt), int(nsteps),
+                                       int(thermo_every), _ptr(th), _ptr(box_out), _ptr(state), _ptr(forces),
+                                       _ptr(ws), ws.numel(), _stream()))
+        if check:
+            self.status()
+        return th, box_out.view(3, 3), state
 
     def profile(self, enable: bool, stages=None):
         """Stage timing on (all stages, or only the named ones) or off."""

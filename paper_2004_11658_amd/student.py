@@ -6,10 +6,11 @@ visits along its own MD trajectory:
   1. run FP64 velocity-Verlet MD with the full model and keep frames,
   2. gather s of the real (alpha, beta) neighbours of those frames (dp_student_samples),
   3. evaluate the full net at those s (dp_embed_eval, FP64),
-  4. fit: hidden units tanh(s W1 + b1) spread evenly over the sample range, the output
+  4. fit: hidden units tanh(s W1 + b1) spread evenly over the sample range and the output
      layer by least squares (dp_student_lsq: design matrix, normal equations by GEMM,
-     Cholesky on the device), then a short Adam refinement of every parameter with the
-     loss gradient kernel (dp_student_loss_grad, dp_adam), kept only if it helps.
+     Cholesky on the device); then the hidden layer is trained by Adam with the loss
+     gradient kernel (dp_student_loss_grad, dp_adam), the output layer re-solved by least
+     squares after every step (variable projection).
 The trained range [s_lo, s_hi] is the [1e-4, 1 - 1e-4] quantile range of the samples
 (rarer, more extreme s values go to the full net), extended upward to twice its top value
 with extra uniform points (closer approaches than the sampled frames hold); dp_set_student
@@ -74,9 +75,15 @@ def gather_samples(model: D.DPModel, frames, n_samples: int, seed: int, q: float
 
 
 def train_pair(model: D.DPModel, alpha: int, beta: int, s: torch.Tensor, hidden: int,
-               refine_steps: int = 100, refine_lr: float = 1e-7, kappa: float = 0.25):
-    """Fit one species pair: spread hidden layer, least-squares output layer (GPU), then a
-    short Adam refinement of all parameters kept only if it lowers the loss."""
+               steps: int = 300, lr_rel: float = 2e-3, kappa: float = 0.25):
+    """Fit one species pair.  Start: hidden units spread over the sample range and the
+    output layer by least squares (GPU).  Then train the hidden layer by Adam on the loss
+    gradient (dp_student_loss_grad), re-solving the output layer by least squares after
+    every step, so the loss minimised is the variable-projection one, L(W1, b1) =
+    min over (W2, b2) of the MSE; its gradient in (W1, b1) is the partial gradient at the
+    least-squares output layer.  The step size is lr_rel times the initial slope |W1|
+    (Adam moves every parameter by about lr per step).  Returns the best parameters, their
+    loss, the loss of the least-squares start, the RMS of G and the sample range."""
     M = model.M
     G = model.embed_eval(alpha, beta, s)
     lo, hi = float(s.min()), float(s.max())
@@ -84,15 +91,21 @@ def train_pair(model: D.DPModel, alpha: int, beta: int, s: torch.Tensor, hidden:
     th = torch.as_tensor(np.concatenate([W1, b1, np.zeros(hidden * M + M)]), device=s.device)
     D.student_lsq(hidden, M, s, G, th)
     loss, g, scratch = D.student_loss_grad(hidden, M, s, G, th)
-    best, best_loss = th.clone(), float(loss.item())
+    loss_lsq = float(loss.item())
+    best, best_loss = th.clone(), loss_lsq
+    mask = torch.zeros_like(th)
+    mask[:2 * hidden] = 1.0
     m = torch.zeros_like(th)
     v = torch.zeros_like(th)
-    for step in range(1, refine_steps + 1):
-        D.adam_step(th, m, v, g, step, refine_lr)
+    lr = lr_rel * float(np.abs(W1).mean())
+    for step in range(1, steps + 1):
+        D.adam_step(th, m, v, g * mask, step, lr)
+        D.student_lsq(hidden, M, s, G, th)
         loss, g, scratch = D.student_loss_grad(hidden, M, s, G, th, scratch)
-        if float(loss.item()) < best_loss:
-            best, best_loss = th.clone(), float(loss.item())
-    return best, best_loss, float(torch.sqrt((G * G).mean()).item()), lo, hi
+        lv = float(loss.item())
+        if lv < best_loss:
+            best, best_loss = th.clone(), lv
+    return best, best_loss, loss_lsq, float(torch.sqrt((G * G).mean()).item()), lo, hi
 
 
 def extend_upward(s: torch.Tensor, margin: float, frac: float, seed: int) -> torch.Tensor:
@@ -108,7 +121,7 @@ def extend_upward(s: torch.Tensor, margin: float, frac: float, seed: int) -> tor
 
 
 def train_students(model: D.DPModel, frames, hidden: int = 32, n_samples: int = 1_000_000,
-                   seed_sample: int = 405, refine_steps: int = 100, margin: float = 1.0,
+                   seed_sample: int = 405, steps: int = 300, margin: float = 1.0,
                    margin_frac: float = 0.05):
     """Train one student per species pair; returns (theta_all, s_lo, s_hi, report).  The
     trained range reaches margin * s_max above the largest sampled s (margin_frac more
@@ -119,10 +132,11 @@ def train_students(model: D.DPModel, frames, hidden: int = 32, n_samples: int = 
     for a in range(nt):
         for b in range(nt):
             s = extend_upward(samples[(a, b)], margin, margin_frac, seed_sample + 1 + a * nt + b)
-            th, loss, rms, lo, hi = train_pair(model, a, b, s, hidden, refine_steps)
+            th, loss, loss_lsq, rms, lo, hi = train_pair(model, a, b, s, hidden, steps)
             thetas.append(th)
             los.append(0.0 if lo < 1e-6 * hi else lo)
             his.append(hi)
             report["%d-%d" % (a, b)] = dict(samples=int(s.numel()), s_lo=lo, s_hi=hi,
-                                            rmse_rel=math.sqrt(loss) / rms)
+                                            rmse_rel=math.sqrt(loss) / rms,
+                                            rmse_rel_lsq_start=math.sqrt(loss_lsq) / rms)
     return torch.cat(thetas), np.array(los), np.array(his), report

@@ -183,8 +183,47 @@ def trained_students(dp, water_model):
         full64.md_run(x, vd, t, masses, b, 0.5, 10, 0)
     th, lo, hi, rep = S.train_students(full64, frames, hidden=32, n_samples=400000)
     print("student training", rep, flush=True)
-    full64.md_run(x, vd, t, masses, b, 0.5, 10, 0)
-    return dict(th=th, lo=lo, hi=hi, x=x, v=vd, t=t, b=b, masses=masses, full64=full64)
+    # 60 steps past the last training frame (step 30): held-out coordinates
+    full64.md_run(x, vd, t, masses, b, 0.5, 50, 0)
+    return dict(th=th, lo=lo, hi=hi, rep=rep, x=x, v=vd, t=t, b=b, masses=masses, full64=full64)
+
+
+def test_student_hidden_layer_training_lowers_the_loss(dp, trained_students):
+    """Adam on the hidden layer (output layer re-solved by least squares each step) ends
+    below the least-squares start for every species pair."""
+    for pair, r in trained_students["rep"].items():
+        print(pair, "rmse rel: least-squares start %.3e, trained %.3e" % (r["rmse_rel_lsq_start"], r["rmse_rel"]),
+              flush=True)
+        assert r["rmse_rel"] < r["rmse_rel_lsq_start"]
+        assert r["rmse_rel"] < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_student_md_with_skin_equals_fresh_list(dp, water_model, trained_students, prec):
+    """The timed path of the benchmark (Verlet list with a 2 A skin, students with
+    fallback): after 40 MD steps from the held-out frame, the forces of the last step
+    equal a fresh-list student evaluation at the same coordinates (summation order only:
+    the two lists order the ~90 neighbours of a centre differently, and FP32 sums of n
+    terms in two orders differ by at most 2 n u = 1.1e-5 of the sum of magnitudes,
+    u = 2^-24, n = 90; FP64 by 2 n u = 2e-14)."""
+    import torch
+    d = trained_students
+    x, vd, t, b, masses = d["x"].clone(), d["v"].clone(), d["t"], d["b"], d["masses"]
+    md = dp.DPModel(water_model, prec, skin=2.0)
+    md.set_student(32, d["th"], d["lo"], d["hi"])
+    F_md = torch.empty_like(x)
+    md.md_run(x, vd, t, masses, b, 0.5, 40, 0, forces=F_md)
+    fb_md = md.fallback_rows()
+    fresh = dp.DPModel(water_model, prec)
+    fresh.set_student(32, d["th"], d["lo"], d["hi"])
+    _, F, _ = fresh.compute(x, t, b)
+    fb = fresh.fallback_rows()
+    F_md, F = F_md.cpu().numpy(), F.cpu().numpy()
+    err = np.abs(F_md - F).max() / np.abs(F).max()
+    print(prec, "skin vs fresh list, student: max |dF| / max |F| %.3e, fallback rows %d / %d" % (err, fb_md, fb),
+          flush=True)
+    assert fb_md == fb
+    assert err <= (1e-12 if prec == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
