@@ -309,6 +309,126 @@ def summarise(results):
     return {m: {k: (sig(v_) if isinstance(v_, float) else v_) for k, v_ in r.items()} for m, r in results.items()}
 
 
+def _counter_rows(directory):
+    """Rows of every rocprofv3 counter-collection CSV under a directory."""
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit("no counter_collection.csv under %s" % directory)
+    return rows
+
+
+def _per_kernel(rows, counters):
+    """{kernel: {counter: mean value per dispatch, "launches": n}} over the rows."""
+    acc = {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        c = r["Counter_Name"]
+        if c not in counters:
+            continue
+        k = acc.setdefault(name, {"dispatches": {}, "sum": {}})
+        k["dispatches"].setdefault(c, set()).add(r["Dispatch_Id"])
+        k["sum"][c] = k["sum"].get(c, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for name, k in acc.items():
+        d = {c: k["sum"][c] / len(k["dispatches"][c]) for c in k["sum"]}
+        d["launches"] = max(len(v) for v in k["dispatches"].values())
+        out[name] = d
+    return out
+
+
+def _short(name):
+    """Kernel name without the namespace, argument list and launch suffix."""
+    n = name.split("(")[0]
+    n = n.replace("dp::", "").replace("void ", "").strip()
+    return n
+
+
+KERNEL_SOURCES = {"k_stu_": ["student_embed.hip", "embed_common.h", "common.h", "kernels.h"],
+                  "k_fit_": ["fit_bf.hip", "common.h", "bf16ops.h", "devmath.h", "kernels.h"],
+                  "k_embed_": ["embed.hip", "embed_common.h", "common.h", "bf16ops.h", "devmath.h", "kernels.h"],
+                  "k_gemm": ["fit.hip", "common.h", "devmath.h", "kernels.h"],
+                  "k_fb_": ["student_infer.hip", "embed_common.h", "common.h", "kernels.h"],
+                  "k_nlist": ["nlist.hip", "common.h", "kernels.h"], "k_vbuild": ["nlist.hip", "common.h", "kernels.h"]}
+
+
+def write_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload):
+    """profiles/traffic.json from four rocprofv3 runs (FETCH_SIZE and WRITE_SIZE of the
+    benchmark and of a device copy of known size)."""
+    cf = _per_kernel(_counter_rows(copy_fetch_dir), {"FETCH_SIZE"})
+    cw = _per_kernel(_counter_rows(copy_write_dir), {"WRITE_SIZE"})
+    copy_f = max(cf.items(), key=lambda kv: kv[1]["FETCH_SIZE"])[1]["FETCH_SIZE"]
+    copy_w = max(cw.items(), key=lambda kv: kv[1]["WRITE_SIZE"])[1]["WRITE_SIZE"]
+    copy_bytes = 256 * (1 << 20)
+    fscale = copy_bytes / (copy_f * 1024.0)
+    wscale = copy_bytes / (copy_w * 1024.0)
+    fe = _per_kernel(_counter_rows(fetch_dir), {"FETCH_SIZE"})
+    wr = _per_kernel(_counter_rows(write_dir), {"WRITE_SIZE"})
+    kernels = {}
+    for name in sorted(set(fe) & set(wr)):
+        short = _short(name)
+        srcs = next((v for k, v in KERNEL_SOURCES.items() if short.startswith(k)), None)
+        if srcs is None:
+            continue
+        rb = fe[name]["FETCH_SIZE"] * 1024.0 * fscale
+        wb = wr[name]["WRITE_SIZE"] * 1024.0 * wscale
+        kernels[short] = dict(read_bytes=int(rb), written_bytes=int(wb), bytes_per_launch=int(rb + wb),
+                              launches=fe[name]["launches"], sources=srcs, source_hash=source_hash(srcs))
+    out = dict(note="HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (one counter per run) on %s, "
+                    "scaled by a 256 MiB device copy (read x fetch_scale, write x write_scale); an entry applies "
+                    "while the hash of its source files is unchanged" % workload,
+               copy_fetch_kib=copy_f, copy_write_kib=copy_w, fetch_scale=fscale, write_scale=wscale,
+               kernels=kernels)
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({k: v["bytes_per_launch"] for k, v in kernels.items()}))
+
+
+def mfma_table(pmc_dir):
+    """Markdown table of MFMA utilisation per kernel from a rocprofv3 run that collected
+    SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE and the MFMA op counters."""
+    cnt = {"SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_BF16",
+           "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_F64"}
+    import csv
+    import glob
+    rows = _counter_rows(pmc_dir)
+    dur = {}
+    traces = glob.glob(os.path.join(pmc_dir, "**", "*kernel_trace.csv"), recursive=True)
+    src = []
+    for f in traces:
+        with open(f) as fh:
+            src.extend(csv.DictReader(fh))
+    if not src:
+        src = rows
+    for r in src:
+        if r.get("Start_Timestamp") and r.get("End_Timestamp"):
+            dur.setdefault(r["Kernel_Name"], {})[r["Dispatch_Id"]] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+    pk = _per_kernel(rows, cnt)
+    simd = 256 * 4
+    lines = ["| Kernel | Launches | MFMA busy (% of SIMD cycles) | MFMA FLOP per launch (issued) | "
+             "MFMA TFLOP/s while running |", "|---|---:|---:|---:|---:|"]
+    for name, d in sorted(pk.items(), key=lambda kv: -kv[1].get("SQ_VALU_MFMA_BUSY_CYCLES", 0)):
+        mops = sum(d.get(c, 0.0) for c in ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+                                           "SQ_INSTS_VALU_MFMA_MOPS_F64"))
+        if mops == 0:
+            continue
+        # the CSV sums GRBM_GUI_ACTIVE over the 8 XCDs (each counts the kernel's cycles)
+        # and SQ_VALU_MFMA_BUSY_CYCLES over all SIMDs
+        util = 100.0 * d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (d.get("GRBM_GUI_ACTIVE", 1.0) / 8.0 * simd)
+        ds = dur.get(name, {})
+        t = sum(ds.values()) / len(ds) * 1e-9 if ds else 0.0
+        rate = mops * 512 / t / 1e12 if t > 0 else float("nan")
+        short = _short(name)
+        if short.startswith("Cijk_"):
+            short = short[:40] + "..."
+        lines.append("| `%s` | %d | %.1f | %.4g | %.1f |" % (short, d["launches"], util, mops * 512, rate))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,13 +449,36 @@ def main():
                          "gradient of the E + F loss, Adam) on 64 ragged water frames")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--calibrate-gemm", type=int, default=0,
+                    help="only run torch matrix products of this size in bf16, fp32 and fp64 (MFMA counter "
+                         "calibration: 2 n^3 FLOP each)")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="only write profiles/traffic.json from rocprofv3 counter runs")
+    ap.add_argument("--traffic-workload", default="the 786,432-atom water bench (bf16x3+student and fp64 modes)")
+    ap.add_argument("--mfma-table", metavar="PMC_DIR", help="only print the MFMA utilisation table of a counter run")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic, workload=args.traffic_workload)
+        return
+    if args.mfma_table:
+        mfma_table(args.mfma_table)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU spatial decomposition is "
               "designed but not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    if args.calibrate_gemm:
+        n = args.calibrate_gemm
+        for dt_ in (torch.bfloat16, torch.float32, torch.float64):
+            a = torch.randn(n, n, device="cuda", dtype=dt_)
+            b = torch.randn(n, n, device="cuda", dtype=dt_)
+            c = a @ b
+            torch.cuda.synchronize()
+            del a, b, c
+        print(json.dumps({"gemm_n": n, "flop_each": 2 * n ** 3}))
+        return
     if args.calibrate_copy_mb:
         n = args.calibrate_copy_mb * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -101,19 +101,30 @@ __global__ void k_st_hidden(long n, int H, const double* __restrict__ s, const d
   Hm[q] = dp_tanh(s[i] * W1[j] + b1[j]);
 }
 
-// Y = H W2 (from the GEMM) + b2; dY = 2 (Y - G) / (n M); loss partial sums
-__global__ void k_st_resid(long n, int M, const double* __restrict__ b2, const double* __restrict__ G,
-                           double* __restrict__ Y, double* __restrict__ loss) {
-  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Y = H W2 (from the GEMM) + b2; dY = 2 (Y - G) / (n M); the loss summed per block (a
+// grid-stride loop over a bounded grid, so the loss takes one atomic per block rather
+// than one per wave)
+constexpr int kResidBlocks = 2048;
+__global__ __launch_bounds__(256) void k_st_resid(long n, int M, const double* __restrict__ b2,
+                                                  const double* __restrict__ G, double* __restrict__ Y,
+                                                  double* __restrict__ loss) {
+  __shared__ double part[4];
+  const size_t tot = (size_t)n * M;
+  const double inv = 1.0 / ((double)n * M);
   double l = 0.0;
-  if (q < (size_t)n * M) {
-    int j = (int)(q % M);
-    double r = Y[q] + b2[j] - G[q];
-    Y[q] = 2.0 * r / ((double)n * M);
-    l = r * r / ((double)n * M);
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(q % M);
+    const double r = Y[q] + b2[j] - G[q];
+    Y[q] = 2.0 * r * inv;
+    l += r * r * inv;
   }
   for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o);
-  if ((threadIdx.x & 63) == 0 && l != 0.0) unsafeAtomicAdd(loss, l);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double b = (part[0] + part[1]) + (part[2] + part[3]);
+    if (b != 0.0) unsafeAtomicAdd(loss, b);
+  }
 }
 
 // dP = dH (1 - H^2) in place
@@ -254,7 +265,9 @@ void launch_student_loss_grad(long n, int H, int M, const double* s, const doubl
   hipLaunchKernelGGL(k_st_zero, dim3(((size_t)n * H + 255) / 256), dim3(256), 0, st, (size_t)n * H, dH);
   hipLaunchKernelGGL(k_st_hidden, dim3(((size_t)n * H + 255) / 256), dim3(256), 0, st, n, H, s, W1, b1, Hm);
   pg_gemm(0, 0, (int)n, M, H, Hm, H, W2, M, Y, M, st);
-  hipLaunchKernelGGL(k_st_resid, dim3(((size_t)n * M + 255) / 256), dim3(256), 0, st, n, M, b2, G, Y, loss);
+  const size_t rb = ((size_t)n * M + 255) / 256;
+  hipLaunchKernelGGL(k_st_resid, dim3(rb < (size_t)kResidBlocks ? (rb ? rb : 1) : kResidBlocks), dim3(256), 0, st, n,
+                     M, b2, G, Y, loss);
   // Y now holds dL/dY
   pg_gemm(1, 0, H, M, (int)n, Hm, H, Y, M, gW2, M, st);
   colsum(n, M, Y, nullptr, gb2, st);
