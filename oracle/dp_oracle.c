@@ -633,9 +633,11 @@ static double center_eval(const or_model *m, int ti, const int64_t *slot_j,
 /* E, F [n][3], W [9] (row major, W_ab = -sum d_a g_b), optional Ei [n], T [n][M][4],
  * D [n][M][m2], gT [n][M][4].  Returns 0; -1 bad box; -2 bad type; 1 sel overflow
  * (results valid, nearest neighbours kept). */
-int or_eval(const or_model *m, int64_t n, const double *coords, const int32_t *types,
-            const double *box, double *E, double *F, double *W, double *Ei, double *T,
-            double *D, double *gT) {
+/* Wi (may be NULL): per-centre virial [n][9], W_i = -sum_j d_ij (x) dE_i/dd_ij over the
+ * neighbours j of centre i (each pair term of W assigned to its centre; sum_i W_i = W) */
+static int eval_core(const or_model *m, int64_t n, const double *coords, const int32_t *types,
+                     const double *box, double *E, double *F, double *W, double *Ei, double *T,
+                     double *D, double *gT, double *Wi) {
   box_t bx;
   if (box_setup(box, m->rc, &bx)) return -1;
   for (int64_t i = 0; i < n; i++)
@@ -685,6 +687,14 @@ int or_eval(const or_model *m, int64_t n, const double *coords, const int32_t *t
         for (int a = 0; a < 3; a++)
           for (int b = 0; b < 3; b++) Wp[tid][3 * a + b] -= sd[k][a] * g[k][b];
       }
+      if (Wi) {
+        for (int q = 0; q < 9; q++) Wi[9 * i + q] = 0.0;
+        for (int k = 0; k < m->nm; k++) {
+          if (sj[k] < 0) continue;
+          for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Wi[9 * i + 3 * a + b] -= sd[k][a] * g[k][b];
+        }
+      }
     }
     ws_free(&w);
     free(sj); free(si); free(st); free(sd); free(g);
@@ -705,6 +715,18 @@ int or_eval(const or_model *m, int64_t n, const double *coords, const int32_t *t
     }
   free(Fp); free(Wp); free(Ep); free(xw); free(fw);
   return ovf ? 1 : 0;
+}
+
+int or_eval(const or_model *m, int64_t n, const double *coords, const int32_t *types,
+            const double *box, double *E, double *F, double *W, double *Ei, double *T,
+            double *D, double *gT) {
+  return eval_core(m, n, coords, types, box, E, F, W, Ei, T, D, gT, NULL);
+}
+
+/* or_eval with the per-atom energy Ei [n] and per-centre virial Wi [n][9] */
+int or_eval_atomic(const or_model *m, int64_t n, const double *coords, const int32_t *types,
+                   const double *box, double *E, double *F, double *W, double *Ei, double *Wi) {
+  return eval_core(m, n, coords, types, box, E, F, W, Ei, NULL, NULL, NULL, Wi);
 }
 
 /* ------------------------------------------------------------------------------------ */

@@ -47,6 +47,7 @@ def lib():
         L.or_nlist.argtypes = [P, I64, P, P, P, I64, P, P, P, P, P]
         L.or_eval.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
         L.or_eval_sampled.argtypes = [P, I64, P, P, P, I64, P, P, P]
+        L.or_eval_atomic.argtypes = [P, I64, P, P, P, P, P, P, P, P]
         L.or_md.argtypes = [P, I64, P, P, P, P, P, D, C.c_int, C.c_int, P]
         L.or_md_npt.argtypes = [P, I64, P, P, P, P, P, D, D, D, D, D, C.c_int, C.c_int, P, P]
         L.or_set_threads.argtypes = [C.c_int]
@@ -150,6 +151,21 @@ class Oracle:
         if dumps:
             out.update(T=T, D=D, gT=gT)
         return out
+
+    def eval_atomic(self, coords, types, box):
+        """E, F, W with the per-atom energies Ei [n] and per-centre virials Wi [n][3][3]
+        (W_i = -sum_j d_ij (x) dE_i/dd_ij; sum_i W_i = W)."""
+        coords, types, box = _f64(coords), _i32(types), _f64(box)
+        n = len(types)
+        E = np.zeros(1)
+        F = np.zeros((n, 3))
+        W = np.zeros(9)
+        Ei = np.zeros(n)
+        Wi = np.zeros((n, 9))
+        rc = lib().or_eval_atomic(self.h, n, _p(coords), _p(types), _p(box), _p(E), _p(F), _p(W), _p(Ei), _p(Wi))
+        if rc < 0:
+            raise ValueError("oracle eval error %d" % rc)
+        return dict(E=float(E[0]), F=F, W=W.reshape(3, 3), Ei=Ei, Wi=Wi.reshape(n, 3, 3), overflow=bool(rc == 1))
 
     def eval_sampled(self, coords, types, box, samples):
         coords, types, box = _f64(coords), _i32(types), _f64(box)

@@ -780,3 +780,37 @@ def test_npt_conserved_quantity_error_scales_as_dt_squared(tau_t):
         assert abs(th[-1, 6] / th[0, 6] - 1.0) > 1e-3     # the box moved
     ratio = errs[0] / errs[1]
     assert 3.5 < ratio < 4.5, (errs, ratio)
+
+
+# ---------------------------------------------------------------------------------------
+# per-atom outputs (the engine-facing interface): E_i and the per-centre virial W_i
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tric", [False, True])
+def test_per_centre_virial_is_minus_strain_derivative_of_atomic_energy(tiny_model, tric):
+    """E_i depends only on the relative vectors d_ij of centre i's environment (Eq. 1-5),
+    so W_i = -sum_j d_ij (x) dE_i/dd_ij equals -dE_i/d(eps) under x -> x (I + eps), checked
+    per atom and component by central differences; sum_i W_i = W, sum_i E_i = E.  A pair
+    term assigned to the neighbour instead of the centre fails the per-atom check while
+    the sums still agree; a sign error fails the sum.  (W_i is symmetric, by the
+    rotational invariance of E_i, so a transposed outer product gives the same matrix.)"""
+    o = Oracle(tiny_model)
+    c, t, b = tiny_water(12, 2, 6.6)
+    if tric:
+        B2 = np.array([[6.6, 0.0, 0.0], [1.3, 6.4, 0.0], [-0.9, 0.7, 6.5]])
+        c = c @ np.linalg.inv(b) @ B2
+        b = B2
+    r = o.eval_atomic(c, t, b)
+    Wi = r["Wi"]
+    np.testing.assert_allclose(Wi.sum(axis=0), r["W"], rtol=0, atol=1e-12 * np.abs(r["W"]).max())
+    assert abs(r["Ei"].sum() - r["E"]) <= 1e-12 * abs(r["E"])
+    h = 1e-6
+    scale = np.abs(Wi).max()
+    for a in range(3):
+        for bb in range(3):
+            eps = np.zeros((3, 3))
+            eps[a, bb] = h
+            Ep = o.eval_atomic(c @ (np.eye(3) + eps), t, b @ (np.eye(3) + eps))["Ei"]
+            Em = o.eval_atomic(c @ (np.eye(3) - eps), t, b @ (np.eye(3) - eps))["Ei"]
+            fd = -(Ep - Em) / (2 * h)
+            assert np.abs(fd - Wi[:, a, bb]).max() <= 1e-6 * scale, (a, bb)
