@@ -135,6 +135,33 @@ int dp_compute_noalloc(dp_handle h, int64_t natoms, const double* coords, const 
                        const double* box, double* energy, double* forces, double* virial,
                        double* atom_energy, void* stream);
 
+/* dp_compute with the per-atom virial: atom_virial [natoms][9] device (row-major 3x3, or
+ * NULL), W_i = -sum_j d_ij (x) dE_i/dd_ij over the neighbours j of centre i (each pair
+ * term of the virial assigned to its centre; sum_i W_i = virial).  Since E_i depends only
+ * on the vectors d_ij of its environment (Eq. 1-5), W_i = -dE_i/d(eps) under the strain
+ * x -> x (I + eps), and W_i is symmetric.  Workspace as dp_compute. */
+int dp_compute_atomic(dp_handle h, int64_t natoms, const double* coords, const int32_t* types,
+                      const double* box, double* energy, double* forces, double* virial, double* atom_energy,
+                      double* atom_virial, void* workspace, size_t ws_bytes, void* stream);
+
+/* Engine-facing evaluation (an MD engine's pair interface, Section 3.1's domain
+ * decomposition): the caller supplies its nlocal local atoms followed by nghost ghost
+ * atoms (copies of other domains' or periodic images' atoms that lie within rc of a
+ * local atom), with no periodic box: coords [nlocal + nghost][3] and types device;
+ * bounds (host [6]: xlo, ylo, zlo, xhi, yhi, zhi) enclose every local and ghost atom.
+ * Only local atoms are centres: energy [1] = sum of E_i over local atoms, atom_energy
+ * [nlocal] and atom_virial [nlocal][9] (may be NULL) per local atom, virial [9] (may be
+ * NULL) the sum of the local atoms' W_i.  forces [nlocal + nghost][3] receives the forces
+ * on local AND ghost atoms: the force of each pair goes to the atom the caller supplied
+ * (Remark 4), so the caller adds each ghost's force to the atom it copies (reverse
+ * communication) to obtain the forces of its local energy.  Not available with
+ * deterministic = 1 (DP_ERR_ARG).  Workspace: dp_compute_local_workspace_size. */
+int dp_compute_local_workspace_size(dp_handle h, int64_t nlocal, int64_t nghost, const double* bounds,
+                                    size_t* bytes);
+int dp_compute_local(dp_handle h, int64_t nlocal, int64_t nghost, const double* coords, const int32_t* types,
+                     const double* bounds, double* energy, double* forces, double* virial, double* atom_energy,
+                     double* atom_virial, void* workspace, size_t ws_bytes, void* stream);
+
 /* The same for a batch of independent frames of uneven size, in one launch per kernel.
  *   atom_offsets [nframes+1] host, coords/types/forces/atom_energy concatenated over
  *   frames, boxes [nframes][9] host, energies [nframes] and virials [nframes][9] device

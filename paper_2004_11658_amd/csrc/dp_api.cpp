@@ -544,6 +544,7 @@ static int box_setup(const double* b9, double rc, Frame& F) {
 
 struct Plan {
   size_t total = 0;
+  size_t o_frames_red = 0;   // caller-supplied ghosts: frame 0 restricted to the centres (reductions)
   size_t o_status, o_frames, o_frame_of, o_xw, o_fw, o_gcount, o_goff, o_small, o_scan;
   size_t o_xe, o_eown, o_eimg, o_etype, o_ecell, o_ccount, o_cstart, o_cfill, o_catoms;
   size_t o_nlist, o_nnei, o_tpos, o_rowof, o_rowatom, o_T, o_gT, o_D, o_Dg, o_act, o_xs, o_g0,
@@ -609,6 +610,7 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
   auto take = [&](size_t bytes) { size_t r = o; o = al(o + bytes); return r; };
   P.o_status = take(sizeof(int) * STW_N);
   P.o_frames = take(sizeof(Frame) * nframes);
+  P.o_frames_red = take(sizeof(Frame));
   P.o_frame_of = take(sizeof(int) * n);
   P.o_xw = take(sizeof(double) * 3 * n);
   P.o_fw = take(sizeof(double) * 3 * n);
@@ -816,7 +818,8 @@ static int stage_frames_and_nlist(dp_handle h, int nframes, const int64_t* off, 
 static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, hipStream_t st,
                      double* energies, double* forces, double* virials, double* atom_energy,
                      bool want_forces, double* T_out, double* gT_out, bool forces_zeroed = false,
-                     bool want_energy = true, bool fb_zeroed = false) {
+                     bool want_energy = true, bool fb_zeroed = false, double* atom_virial = nullptr,
+                     const Frame* reduce_frames = nullptr, int ncentre = 0) {
   Ws W{(char*)ws, &P};
   EmbedArgs E{};
   E.prec = h->opt.precision;
@@ -912,10 +915,15 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
     }
   }
   HIPCHECK(h, hipGetLastError());
+  if (atom_virial && want_forces) {
+    launch_export_atom_virial(ncentre > 0 ? ncentre : P.n, A.row_of, E.vir_part, atom_virial, st);
+    HIPCHECK(h, hipGetLastError());
+  }
   if (want_energy) {
     StageTimer tm(h, DP_STAGE_REDUCE, st);
-    launch_frame_reduce(P.nframes, P.max_frame_atoms, A.frames, A.row_of, F.Ei, want_forces ? E.vir_part : nullptr,
-                        energies, virials, atom_energy, W.at<double>(P.o_redpart), W.at<int>(P.o_reddone), st);
+    launch_frame_reduce(P.nframes, P.max_frame_atoms, reduce_frames ? reduce_frames : A.frames, A.row_of, F.Ei,
+                        want_forces ? E.vir_part : nullptr, energies, virials, atom_energy,
+                        W.at<double>(P.o_redpart), W.at<int>(P.o_reddone), st);
   }
   HIPCHECK(h, hipGetLastError());
   return DP_OK;
@@ -1056,6 +1064,81 @@ int dp_compute(dp_handle h, int64_t natoms, const double* coords, const int32_t*
   int64_t off[2] = {0, natoms};
   return dp_compute_batch(h, 1, off, coords, types, box, energy, forces, virial, atom_energy,
                           workspace, ws_bytes, stream);
+}
+
+int dp_compute_atomic(dp_handle h, int64_t natoms, const double* coords, const int32_t* types,
+                      const double* box, double* energy, double* forces, double* virial, double* atom_energy,
+                      double* atom_virial, void* workspace, size_t ws_bytes, void* stream) {
+  if (!h) return DP_ERR_ARG;
+  if (!box || !energy || !forces) return fail(h, DP_ERR_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  int64_t off[2] = {0, natoms};
+  Plan P;
+  NlistArgs A{};
+  int rc = stage_frames_and_nlist(h, 1, off, box, coords, types, workspace, ws_bytes, st, P, A);
+  if (rc != DP_OK) return rc;
+  return run_model(h, P, A, workspace, st, energy, forces, virial, atom_energy, true, nullptr, nullptr, false,
+                   true, false, atom_virial);
+}
+
+// The frame of an evaluation with caller-supplied ghost atoms: an orthogonal box whose
+// edges exceed the atoms' extent by rc + 1 A, so that no periodic image of any atom comes
+// within rc of another atom and the periodic machinery sees the open cluster.
+static int local_box(dp_handle h, const double* bounds, double box[9]) {
+  for (int k = 0; k < 3; k++)
+    if (!std::isfinite(bounds[k]) || !std::isfinite(bounds[3 + k]) || !(bounds[3 + k] >= bounds[k]))
+      return fail(h, DP_ERR_ARG, "bounds must be finite with hi >= lo");
+  for (int q = 0; q < 9; q++) box[q] = 0.0;
+  for (int k = 0; k < 3; k++) box[4 * k] = (bounds[3 + k] - bounds[k]) + h->rc + 1.0;
+  return DP_OK;
+}
+
+int dp_compute_local_workspace_size(dp_handle h, int64_t nlocal, int64_t nghost, const double* bounds,
+                                    size_t* bytes) {
+  if (!h || !bounds || !bytes) return fail(h, DP_ERR_ARG, "null argument");
+  if (nlocal < 1 || nghost < 0) return fail(h, DP_ERR_ARG, "nlocal must be >= 1 and nghost >= 0");
+  double box[9];
+  int rc = local_box(h, bounds, box);
+  if (rc != DP_OK) return rc;
+  int64_t off[2] = {0, nlocal + nghost};
+  Plan P;
+  rc = make_plan(h, 1, off, box, nullptr, P);
+  if (rc != DP_OK) return rc;
+  *bytes = P.total;
+  return DP_OK;
+}
+
+int dp_compute_local(dp_handle h, int64_t nlocal, int64_t nghost, const double* coords, const int32_t* types,
+                     const double* bounds, double* energy, double* forces, double* virial, double* atom_energy,
+                     double* atom_virial, void* workspace, size_t ws_bytes, void* stream) {
+  if (!h) return DP_ERR_ARG;
+  if (!bounds || !energy || !forces) return fail(h, DP_ERR_ARG, "null argument");
+  if (nlocal < 1 || nghost < 0) return fail(h, DP_ERR_ARG, "nlocal must be >= 1 and nghost >= 0");
+  if (h->opt.deterministic)
+    return fail(h, DP_ERR_ARG, "caller-supplied ghost atoms are not available in deterministic mode");
+  double box[9];
+  int rc = local_box(h, bounds, box);
+  if (rc != DP_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  int64_t off[2] = {0, nlocal + nghost};
+  Plan P;
+  NlistArgs A{};
+  rc = stage_frames(h, 1, off, box, coords, types, workspace, ws_bytes, st, P, A);
+  if (rc != DP_OK) return rc;
+  A.ncentre = (int)nlocal;
+  // the reductions (energy, virial, E_i) run over the centres only
+  Ws W{(char*)workspace, &P};
+  {
+    Frame Fr{};
+    if (box_setup(box, h->rc, Fr)) return fail(h, DP_ERR_BOX, "degenerate bounds");
+    Fr.atom0 = 0;
+    Fr.natoms = (int)nlocal;
+    launch_put_frames(&Fr, 1, W.at<Frame>(P.o_frames_red), st);
+  }
+  rc = stage_nlist(h, A, st);
+  if (rc != DP_OK) return rc;
+  return run_model(h, P, A, workspace, st, energy, forces, virial, atom_energy, true, nullptr, nullptr, false,
+                   true, false, atom_virial, W.at<Frame>(P.o_frames_red), (int)nlocal);
 }
 
 int dp_nlist(dp_handle h, int64_t natoms, const double* coords, const int32_t* types,

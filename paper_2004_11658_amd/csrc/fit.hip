@@ -633,4 +633,17 @@ void launch_export_T(int prec, int n, int M, const int* row_of, const void* Tm, 
                        (const float*)Tm, (const float*)gT, To, gTo);
 }
 
+__global__ void k_export_atom_virial(int n, const int* __restrict__ row_of, const double* __restrict__ vir_rows,
+                                     double* __restrict__ out) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (size_t)n * 9) return;
+  const int i = (int)(q / 9);
+  out[q] = vir_rows[(size_t)row_of[i] * 9 + q % 9];
+}
+
+void launch_export_atom_virial(int n, const int* row_of, const double* vir_rows, double* out, hipStream_t st) {
+  const size_t tot = (size_t)n * 9;
+  if (tot) hipLaunchKernelGGL(k_export_atom_virial, dim3((tot + 255) / 256), dim3(256), 0, st, n, row_of, vir_rows, out);
+}
+
 }  // namespace dp

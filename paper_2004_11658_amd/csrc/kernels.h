@@ -47,6 +47,8 @@ struct NlistArgs {
                     // short keys); nbig[0] is zero on entry and left zero, nbig[1] its pass counter
   double* npt;      // isobaric MD state (NULL otherwise): a rebuild records the box scale
                     // at which the rows were built (npt[NS_LAMB] = npt[NS_LAM])
+  int ncentre;      // > 0: only atoms [0, ncentre) are centres (formatted lists, species rows);
+                    // the others (caller-supplied ghost atoms) are neighbours only
 };
 size_t scan_sums_ints(int n, int W);
 // copies nframes frames from host memory to dst on the stream through kernel arguments
@@ -178,6 +180,8 @@ void launch_frame_reduce(int nframes, int max_frame_atoms, const Frame* frames, 
                          double* atom_energy, double* part, int* done, hipStream_t st);
 void launch_export_T(int prec, int n, int M, const int* row_of, const void* Tm, const void* gT,
                      double* To, double* gTo, hipStream_t st);
+// per-atom virial [n][9] of the centres from the per-centre rows
+void launch_export_atom_virial(int n, const int* row_of, const double* vir_rows, double* out, hipStream_t st);
 
 // ---------------------------------------------------------------- parameter gradient
 struct PGradArgs {

@@ -1324,7 +1324,7 @@ static void fill_int(int n, int* p, int v, const int* gate, hipStream_t st) {
 // within rc + skin (k_vbuild), and the species-grouped row order.
 static NlKArgs format_args(const NlistArgs& A) {
   NlKArgs K{};
-  K.n = A.n;
+  K.n = A.ncentre > 0 ? A.ncentre : A.n;
   K.m = A.m;
   K.frames = A.frames;
   K.frame_of = A.frame_of;
@@ -1392,20 +1392,23 @@ static void launch_rebuild(const NlistArgs& A, bool rows_later, hipStream_t st) 
                        A.vcap, A.status, G);
   // species-grouped rows (species do not change during MD: built once there)
   if (A.skip_rows) return;
+  // rows of the centres only (all atoms unless the caller supplied ghost atoms)
+  const int nc = A.ncentre > 0 ? A.ncentre : n;
+  const int nbc = (nc + 255) / 256;
   if (A.m.ntypes == 1) {
-    scan_launch<1>(n, LoadTypeOneHot<1>{A.types, 1}, A.tpos, A.scan_sums, A.tcount, st, G);
+    scan_launch<1>(nc, LoadTypeOneHot<1>{A.types, 1}, A.tpos, A.scan_sums, A.tcount, st, G);
   } else if (A.m.ntypes == 2) {
-    scan_launch<2>(n, LoadTypeOneHot<2>{A.types, 2}, A.tpos, A.scan_sums, A.tcount, st, G);
+    scan_launch<2>(nc, LoadTypeOneHot<2>{A.types, 2}, A.tpos, A.scan_sums, A.tcount, st, G);
   } else if (A.m.ntypes <= 4) {
-    scan_launch<4>(n, LoadTypeOneHot<4>{A.types, 4}, A.tpos, A.scan_sums, A.tcount, st, G);
+    scan_launch<4>(nc, LoadTypeOneHot<4>{A.types, 4}, A.tpos, A.scan_sums, A.tcount, st, G);
   } else {
-    scan_launch<8>(n, LoadTypeOneHot<8>{A.types, 8}, A.tpos, A.scan_sums, A.tcount, st, G);
+    scan_launch<8>(nc, LoadTypeOneHot<8>{A.types, 8}, A.tpos, A.scan_sums, A.tcount, st, G);
   }
   int W = A.m.ntypes == 1 ? 1 : A.m.ntypes == 2 ? 2 : A.m.ntypes <= 4 ? 4 : 8;
   fill_int(A.nrows, A.row_atom, -1, G, st);
-  hipLaunchKernelGGL(k_type_rows, dim3(nb), dim3(256), 0, st, n, A.m.ntypes, W, A.types, A.tpos,
+  hipLaunchKernelGGL(k_type_rows, dim3(nbc), dim3(256), 0, st, nc, A.m.ntypes, W, A.types, A.tpos,
                      A.tcount, A.row_of, A.type_row0, G);
-  hipLaunchKernelGGL(k_row_atoms, dim3(nb), dim3(256), 0, st, n, A.row_of, A.row_atom, G);
+  hipLaunchKernelGGL(k_row_atoms, dim3(nbc), dim3(256), 0, st, nc, A.row_of, A.row_atom, G);
 }
 
 void launch_nlist(const NlistArgs& A, hipStream_t st) { launch_rebuild(A, false, st); }

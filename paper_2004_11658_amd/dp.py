@@ -53,6 +53,9 @@ def _load():
         "dp_workspace_size": ([P, I32, P, P, P], C.c_int),
         "dp_compute": ([P, I64, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
         "dp_compute_batch": ([P, I32, P, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
+        "dp_compute_atomic": ([P, I64, P, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
+        "dp_compute_local_workspace_size": ([P, I64, I64, P, P], C.c_int),
+        "dp_compute_local": ([P, I64, I64, P, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
         "dp_nlist": ([P, I64, P, P, P, P, P, P, P, SZ, P], C.c_int),
         "dp_descriptor": ([P, I64, P, P, P, P, P, P, SZ, P], C.c_int),
         "dp_status": ([P, P, P, P, P], C.c_int),
@@ -192,6 +195,53 @@ class DPModel:
         if check:
             self.status()
         return (E, F, W.view(3, 3), Ei) if atom_energy else (E, F, W.view(3, 3))
+
+    def compute_atomic(self, coords, types, box, check: bool = True):
+        """E [1], F [N][3], W [3][3], E_i [N], W_i [N][3][3] of one periodic frame."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        n = x.shape[0]
+        b = _box9(box)
+        ws = self.workspace(np.array([0, n]), b)
+        E = torch.empty(1, dtype=torch.float64, device=x.device)
+        F = torch.empty(n, 3, dtype=torch.float64, device=x.device)
+        W = torch.empty(9, dtype=torch.float64, device=x.device)
+        Ei = torch.empty(n, dtype=torch.float64, device=x.device)
+        Wi = torch.empty(n, 9, dtype=torch.float64, device=x.device)
+        self._check(_lib.dp_compute_atomic(self.h, n, _ptr(x), _ptr(t), b.ctypes.data_as(C.c_void_p), _ptr(E),
+                                           _ptr(F), _ptr(W), _ptr(Ei), _ptr(Wi), _ptr(ws), ws.numel(), _stream()))
+        if check:
+            self.status()
+        return E, F, W.view(3, 3), Ei, Wi.view(n, 3, 3)
+
+    def compute_local(self, coords, types, nlocal: int, bounds=None, check: bool = True):
+        """Engine-facing evaluation: atoms [0, nlocal) are local, the rest caller-supplied
+        ghosts (no periodic box).  Returns E [1] (local atoms), F [nlocal + nghost][3]
+        (forces on locals and ghosts), W [3][3], E_i [nlocal], W_i [nlocal][3][3]."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        n = x.shape[0]
+        if bounds is None:
+            xc = x.detach().cpu().numpy()
+            bounds = np.concatenate([xc.min(axis=0), xc.max(axis=0)])
+        bd = np.ascontiguousarray(bounds, dtype=np.float64).reshape(6)
+        nb = C.c_size_t()
+        self._check(_lib.dp_compute_local_workspace_size(self.h, int(nlocal), int(n - nlocal),
+                                                         bd.ctypes.data_as(C.c_void_p), C.byref(nb)))
+        if self._ws is None or self._ws.numel() < nb.value:
+            self._ws = torch.empty(int(nb.value * 1.1) + 4096, dtype=torch.uint8, device=self.device)
+        ws = self._ws
+        E = torch.empty(1, dtype=torch.float64, device=x.device)
+        F = torch.empty(n, 3, dtype=torch.float64, device=x.device)
+        W = torch.empty(9, dtype=torch.float64, device=x.device)
+        Ei = torch.empty(nlocal, dtype=torch.float64, device=x.device)
+        Wi = torch.empty(nlocal, 9, dtype=torch.float64, device=x.device)
+        self._check(_lib.dp_compute_local(self.h, int(nlocal), int(n - nlocal), _ptr(x), _ptr(t),
+                                          bd.ctypes.data_as(C.c_void_p), _ptr(E), _ptr(F), _ptr(W), _ptr(Ei),
+                                          _ptr(Wi), _ptr(ws), ws.numel(), _stream()))
+        if check:
+            self.status()
+        return E, F, W.view(3, 3), Ei, Wi.view(nlocal, 3, 3)
 
     def compute_batch(self, coords, types, offsets: Sequence[int], boxes, atom_energy: bool = False,
                       check: bool = True):
