@@ -117,3 +117,86 @@ def test_param_grad_finite_differences(dp, tiny_model):
         tm[q] -= h
         fd = (float(loss(tp)) - float(loss(tm))) / (2 * h)
         assert abs(fd - g[q]) <= 1e-5 * max(abs(g[q]), 1e-3 * np.abs(g).max()), (q, fd, g[q])
+
+
+def test_param_grad_chunked_calls_match_oracle(dp, water_model):
+    """The ragged batch split across several dp_param_grad calls (max_atoms below the
+    batch size: every frame its own call here) gives the oracle's gradient."""
+    import torch
+    frames = _frames("water")
+    o = Oracle(water_model)
+    tg = _targets(o, frames, 7)
+    lam = 1.0
+    arch = TR.Arch(water_model)
+    ofr = []
+    for (c, t, b), (Et, Ft) in zip(frames, tg):
+        nl, img, _, _ = o.nlist(c, t, b)
+        ofr.append((c, t, b, nl, img, Et, Ft))
+    L_ref, g_ref = TR.loss_and_grad(arch, arch.params, ofr, lam)
+    m = dp.DPModel(water_model)
+    coords = np.concatenate([f[0] for f in frames])
+    types = np.concatenate([f[1] for f in frames])
+    boxes = np.stack([f[2] for f in frames])
+    off = np.concatenate([[0], np.cumsum([len(f[1]) for f in frames])])
+    E, F, _ = m.compute_batch(coords, types, off, boxes)
+    Et = torch.as_tensor([x[0] for x in tg], device="cuda")
+    Ft = torch.as_tensor(np.concatenate([x[1] for x in tg]), device="cuda")
+    nat = torch.as_tensor(np.diff(off), device="cuda", dtype=torch.float64)
+    gE = 2.0 * (E - Et) / nat
+    gF = 2.0 * lam * (F - Ft)
+    biggest = int(np.diff(off).max())
+    print("frames", np.diff(off), "max_atoms", biggest, flush=True)
+    g = m.param_grad(coords, types, off, boxes, gE, gF, max_atoms=biggest).cpu().numpy()
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print("chunked grad rel err", err, flush=True)
+    assert err < 1e-9
+
+
+def test_param_grad_whole_batch_finite_differences(dp, water_model, water_model_b):
+    """The 64-frame ragged water batch (96-3,072 atoms per frame, 102k atoms): the
+    gradient of L = sum_f dE_f^2 / N_f + sum |dF|^2 (targets from a second random model)
+    through the library's chunked calls, against central differences (h = 1e-6) of the
+    GPU loss on 16 sampled parameters (weights of every layer, output biases).  Deterministic handles make the
+    loss bit-reproducible, so the differences see truncation only."""
+    import torch
+    frames = I.ragged_water_batch(64, 204)
+    coords = np.concatenate([f[0] for f in frames])
+    types = np.concatenate([f[1] for f in frames]).astype(np.int32)
+    boxes = np.stack([f[2] for f in frames])
+    off = np.concatenate([[0], np.cumsum([len(f[1]) for f in frames])]).astype(np.int64)
+    print("batch atoms", int(off[-1]), flush=True)
+    Et, Ft, _ = dp.DPModel(water_model_b, deterministic=True).compute_batch(coords, types, off, boxes)
+    m = dp.DPModel(water_model, deterministic=True)
+    nat = torch.as_tensor(np.diff(off), device="cuda", dtype=torch.float64)
+    x = torch.as_tensor(coords, device="cuda")
+    t = torch.as_tensor(types, device="cuda")
+
+    def loss_and_seeds():
+        E, F, _ = m.compute_batch(x, t, off, boxes)
+        L = float((((E - Et) ** 2) / nat).sum() + ((F - Ft) ** 2).sum())
+        return L, 2.0 * (E - Et) / nat, 2.0 * (F - Ft)
+
+    L0, gE, gF = loss_and_seeds()
+    g = m.param_grad(x, t, off, boxes, gE, gF).cpu().numpy()
+    arch = TR.Arch(water_model)
+    theta0 = torch.as_tensor(arch.params, device="cuda")
+    rng = np.random.default_rng(8)
+    picks = []
+    for lay in list(arch.emb.values())[:2] + list(arch.fit.values()):
+        for (woff, (ni, no), boff) in lay:
+            picks.append(woff + int(rng.integers(0, ni * no)))
+    picks = picks[:16] + [lay[-1][2] for lay in arch.fit.values()][:4]   # + output-layer biases
+    h = 1e-6
+    gmax = np.abs(g).max()
+    for q in picks:
+        tp, tm = theta0.clone(), theta0.clone()
+        tp[q] += h
+        tm[q] -= h
+        m.set_params(tp)
+        Lp = loss_and_seeds()[0]
+        m.set_params(tm)
+        Lm = loss_and_seeds()[0]
+        fd = (Lp - Lm) / (2 * h)
+        print("param", q, "fd", fd, "grad", g[q], flush=True)
+        assert abs(fd - g[q]) <= 1e-5 * max(abs(g[q]), 1e-3 * gmax), (q, fd, g[q])
+    m.set_params(theta0)
