@@ -97,9 +97,7 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ bool stu_out_of_range(const EmbedArgs& A, int pair, double s) {
-  return s < A.st_lo[pair] || s > A.st_hi[pair];
-}
+__device__ __forceinline__ bool stu_out_of_range(double lo, double hi, double s) { return s < lo || s > hi; }
 
 // Environment row of one neighbour (Eq. 5) in FP64 whatever the student's storage type:
 // displacement, r, 1/r, the switch s(r) and its derivative, R~ and the force geometry
@@ -144,16 +142,30 @@ __device__ __forceinline__ void stu_env(const ModelC& m, const double xj[3], con
   v.R[3] = sr * v.d[2];
 }
 
-// neighbour k of the chunk (its extended index and coordinates), -1 past the end
-__device__ __forceinline__ int stu_fetch(const double* __restrict__ xe, const int* __restrict__ nl, int k, int nn,
-                                         double (&x)[3]) {
-  const int e = k < nn ? nl[k] : -1;
-  if (e >= 0) {
-    x[0] = xe[3 * e];
-    x[1] = xe[3 * e + 1];
-    x[2] = xe[3 * e + 2];
-  }
-  return e;
+// Software pipeline of the neighbour gathers: the list entry of a chunk is loaded two
+// chunks before its use and the coordinates one chunk before, so that no gather waits
+// on the list load issued just before it.
+// Both loads are unconditional (the slot index clamped into the species block of width
+// sel, a -1 entry read as atom 0) so that every lane and path issues the same loads and
+// the waits can count down to the older gather only.
+__device__ __forceinline__ int stu_index(const int* __restrict__ nl, int k, int nn, int sel) {
+  const int v = nl[k < sel ? k : (sel > 0 ? sel - 1 : 0)];
+  return k < nn ? v : -1;
+}
+__device__ __forceinline__ void stu_coords(const double* __restrict__ xe, int e, double (&x)[3]) {
+  const int q = e > 0 ? e : 0;
+  x[0] = xe[3 * q];
+  x[1] = xe[3 * q + 1];
+  x[2] = xe[3 * q + 2];
+}
+// the coordinates and the owner (the atom that receives the neighbour's force)
+__device__ __forceinline__ void stu_coords_owner(const double* __restrict__ xe, const int* __restrict__ eown, int e,
+                                                 double (&x)[3], int& own) {
+  const int q = e > 0 ? e : 0;
+  x[0] = xe[3 * q];
+  x[1] = xe[3 * q + 1];
+  x[2] = xe[3 * q + 2];
+  own = eown[q];
 }
 
 // student block of a pair, read through global (not generic) pointers
@@ -185,6 +197,7 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
   for (int beta = 0; beta < m.ntypes; beta++) {
     const int pair = alpha * m.ntypes + beta;
     const auto sn = stu_block<T>(A, pair);
+    const double slo = A.st_lo[pair], shi = A.st_hi[pair];
     T w1[8], b1[8];
 #pragma unroll
     for (int j = 0; j < 8; j++) {
@@ -202,17 +215,20 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
     // Environment rows 64 at a time, one neighbour per lane (c0 + lane), then in chunks of
     // 16 the lane group g of the hidden units takes neighbour rb of the chunk from lane
     // 16 q + rb: each row is formed once, not once per lane group
+    const int sel = m.sel[beta];
     double xn[3] = {0, 0, 0};
-    int en = stu_fetch(A.xe, nl, lane, nn, xn);   // the next 64 neighbours, fetched a pass ahead
+    int en = stu_index(nl, lane, nn, sel);   // the next 64 neighbours, fetched a pass ahead
+    stu_coords(A.xe, en, xn);
     for (int c0 = 0; c0 < nn; c0 += 64) {
       const int e = en;
       const double xj[3] = {xn[0], xn[1], xn[2]};
-      en = stu_fetch(A.xe, nl, c0 + 64 + lane, nn, xn);
+      en = stu_index(nl, c0 + 64 + lane, nn, sel);
+      stu_coords(A.xe, en, xn);
       T sL = (T)0, RL[4] = {(T)0, (T)0, (T)0, (T)0};
       if (e >= 0) {
         StuEnv v;
         stu_env(m, xj, xi, v);
-        if (stu_out_of_range(A, pair, v.s)) {
+        if (stu_out_of_range(slo, shi, v.s)) {
           // left to the full net (fallback list); contributes nothing here
           const int p = atomicAdd(A.fb_count, 1);
           if (p < A.fb_cap) A.fb_list[p] = make_int2(row, e);
@@ -307,8 +323,11 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
 // ------------------------------------------------------------------------------------
 constexpr int kStuBwdWaves = 8;
 
-// LDS of the adjoint: W2T of two pairs, then per wave V rows (with W1, b1) and u of two
-size_t stu_bwd_lds_bytes(int elem) { return (size_t)elem * (2 * kP2 * kP0 + kW2Pad + kStuBwdWaves * 2 * kStuS); }
+// LDS of the adjoint: W2T of two pairs, then per wave V rows (with W1, b1) and u of two,
+// then per wave the centre's dE/dT [kP2][4]
+size_t stu_bwd_lds_bytes(int elem) {
+  return (size_t)elem * (2 * kP2 * kP0 + kW2Pad + kStuBwdWaves * 2 * kStuS + kStuBwdWaves * kP2 * 4);
+}
 
 template <class T>
 __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
@@ -330,10 +349,20 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
     xi[1] = A.xe[3 * atom + 1];
     xi[2] = A.xe[3 * atom + 2];
   }
-  // dE/dT of this centre [f][4]: wave-uniform and not written by this kernel, so read
-  // through the constant address space (scalar loads into scalar registers)
-  const __attribute__((address_space(4))) T* gt =
-      (const __attribute__((address_space(4))) T*)((const T*)A.gT + (size_t)(live ? row : 0) * M * 4);
+  // dE/dT of this centre [f][4]: one coalesced load into registers (feature lane and
+  // lane + 64), copied to the wave's LDS rows for the broadcast reads of the V product
+  T* gts = w2s + 2 * kP2 * kP0 + kW2Pad + kStuBwdWaves * 2 * kStuS + wv * kP2 * 4;
+  typedef T t4v __attribute__((ext_vector_type(4)));
+  t4v gtv[2];
+  {
+    const t4v* src = (const t4v*)((const T*)A.gT + (size_t)(live ? row : 0) * M * 4);
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      const int f = lane + 64 * i;
+      gtv[i] = (live && f < M) ? src[f] : t4v{(T)0, (T)0, (T)0, (T)0};
+      if (f < kP2) *(t4v*)(gts + 4 * f) = gtv[i];
+    }
+  }
   double fi = 0.0;                    // force component g on the centre (lane groups 0..2)
   double vir[3] = {0.0, 0.0, 0.0};    // virial column g: W[a][g]
   const T inorm = (T)m.inv_norm;
@@ -346,7 +375,7 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
     __syncthreads();
     if (!live) continue;
     // V_beta[k][c] = sum_f W2[k][f] gt[f][c] with one lane per (beta, k): lanes 0..31 the
-    // pass's first pair, 32..63 its second; dE/dT is the same for both (scalar operands)
+    // pass's first pair, 32..63 its second; dE/dT is the same for both (LDS broadcast)
     {
       const int hb = lane >> 5, kk = lane & 31;
       const T* w = w2s + hb * (kP2 * kP0 + kW2Pad) + kk;
@@ -354,8 +383,9 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
 #pragma unroll 8
       for (int f = 0; f < M; f++) {
         const T wf = w[f * kP0];
+        const t4v g4 = *(const t4v*)(gts + 4 * f);
 #pragma unroll
-        for (int c = 0; c < 4; c++) v4[c] += wf * gt[f * 4 + c];
+        for (int c = 0; c < 4; c++) v4[c] += wf * g4[c];
       }
       if (hb < nb) {
         const auto sn = stu_block<T>(A, alpha * m.ntypes + b0 + hb);
@@ -369,10 +399,10 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
       for (int q = 0; q < nb; q++) {
         const auto sn = stu_block<T>(A, alpha * m.ntypes + b0 + q);
         const int f1 = lane + 64;
+        const T bl = lane < M ? sn[kSB2 + lane] : (T)0, bh = f1 < M ? sn[kSB2 + f1] : (T)0;
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-          T u = (lane < M ? sn[kSB2 + lane] * gt[lane * 4 + c] : (T)0) +
-                (f1 < M ? sn[kSB2 + f1] * gt[f1 * 4 + c] : (T)0);
+          T u = bl * gtv[0][c] + bh * gtv[1][c];
           u = sum_g(row_sum16(u));
           if (lane == 0) Vall[q * kStuS + kStuU + c] = u;
         }
@@ -383,6 +413,7 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
     const int beta = b0 + q;
     const int pair = alpha * m.ntypes + beta;
     const T* Vw = Vall + q * kStuS;
+    const double slo = A.st_lo[pair], shi = A.st_hi[pair];
     // V, W1 and b1 of the lane's hidden units are read from LDS inside the neighbour loop
     // (held in registers they would cost 48 VGPRs and lower the waves per SIMD)
     T uu[4];
@@ -390,18 +421,16 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
     for (int c = 0; c < 4; c++) uu[c] = Vw[kStuU + c];
     const int nn = A.nnei[atom * m.ntypes + beta];
     const int* nl = A.nlist + (size_t)atom * m.nm + m.sel_off[beta];
-    double xn[3] = {0, 0, 0};
-    int en = stu_fetch(A.xe, nl, rb, nn, xn);   // the next chunk's neighbour, fetched a chunk ahead
-    for (int c0 = 0; c0 < nn; c0 += 16) {
-      const int e = en;
-      const double xj[3] = {xn[0], xn[1], xn[2]};
-      en = stu_fetch(A.xe, nl, c0 + 16 + rb, nn, xn);
+    const int sel = m.sel[beta];
+    // one chunk of 16 neighbours: lane (rb, g) takes neighbour rb and the hidden units of
+    // lane group g; the caller supplies the neighbour's index, owner and coordinates
+    auto chunk = [&](int e, int own, const double (&xj)[3]) {
       bool valid = e >= 0;
       StuEnv v;
       T s = (T)0, R[4] = {(T)0, (T)0, (T)0, (T)0};
       if (valid) {
         stu_env(m, xj, xi, v);
-        if (stu_out_of_range(A, pair, v.s)) {
+        if (stu_out_of_range(slo, shi, v.s)) {
           valid = false;   // handled by the fallback kernel
         } else {
           s = (T)v.s;
@@ -431,6 +460,7 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
       const T dsl = sum_g(dsp) * inorm;   // dE/ds through G, in the student's type
       // g_ij = dR^T dE/dR (Eq. 5 differentiated) in FP64: lane group g < 3 computes
       // component g from the FP64 environment row and dE/dR~ (the student's sums)
+      double gv = 0.0;
       if (valid && g < 3) {
         const double in = m.inv_norm;
         const double gRd[4] = {(double)gR[0] * in + (double)dsl, (double)gR[1] * in, (double)gR[2] * in,
@@ -441,12 +471,24 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
         const double dot = gRd[1] * v.d[0] + gRd[2] * v.d[1] + gRd[3] * v.d[2];
         const double db = g == 0 ? v.d[0] : g == 1 ? v.d[1] : v.d[2];
         const double gRb = g == 0 ? gRd[1] : g == 1 ? gRd[2] : gRd[3];
-        const double gv = gRd[0] * v.ds * db * ir + qf * dot * db + sr * gRb;
+        gv = gRd[0] * v.ds * db * ir + qf * dot * db + sr * gRb;
         fi += gv;
-        unsafeAtomicAdd(&A.forces[3 * A.eown[e] + g], -gv);
 #pragma unroll
         for (int a = 0; a < 3; a++) vir[a] -= v.d[a] * gv;   // W[a][g]
       }
+      if (valid && g < 3) unsafeAtomicAdd(&A.forces[3 * own + g], -gv);
+    };
+    int en = stu_index(nl, rb, nn, sel), en2 = stu_index(nl, 16 + rb, nn, sel);
+    double xn[3];
+    int own_n;
+    stu_coords_owner(A.xe, A.eown, en, xn, own_n);
+    for (int c0 = 0; c0 < nn; c0 += 16) {
+      const int e = en, own = own_n;
+      const double xj[3] = {xn[0], xn[1], xn[2]};
+      en = en2;
+      en2 = stu_index(nl, c0 + 32 + rb, nn, sel);
+      stu_coords_owner(A.xe, A.eown, en, xn, own_n);
+      chunk(e, own, xj);
     }
     }
     wave_sync_lds();   // the V rows are rewritten in the next pass
