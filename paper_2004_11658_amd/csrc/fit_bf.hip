@@ -284,7 +284,12 @@ __global__ __launch_bounds__(FT) void k_fit_l1_fwd(FitBfArgs P) {
 // ------------------------------------------------------------------------------------
 // square layers, output and the adjoint back to the first layer
 // ------------------------------------------------------------------------------------
-size_t fit_tail_lds(int parts) { return (size_t)kKS * 4 * parts * 1024 + FW * 64 * 8; }
+// LDS of the tail: the staged X fragments, the row sums of E_i and the tanh of the first
+// square layer (the last one stays in registers; deeper nets keep the middle ones in the
+// workspace)
+size_t fit_tail_lds(int parts) {
+  return (size_t)kKS * 4 * parts * 1024 + FW * 64 * 8 + (size_t)16 * 4 * 64 * 16;
+}
 
 template <int PARTS>
 __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
@@ -292,6 +297,7 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
   const int N = P.N, NT = N / 16;
   __bf16* Xs = (__bf16*)smem;
   double* red = (double*)(smem + (size_t)kKS * 4 * PARTS * 1024);
+  float* act1 = (float*)(smem + (size_t)kKS * 4 * PARTS * 1024 + FW * 64 * 8);   // [NT][4][64][4]
   const int r0 = blockIdx.x * FR;
   const int sp = fitbf_species(P, r0);
   if (sp < 0) return;
@@ -309,7 +315,9 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
       x[u][rt] = ct < NT ? *(const f4v*)(P.t1 + (size_t)(r0 + 16 * rt + rb) * N + 16 * ct + 4 * g) : z4;
   }
   const size_t lstride = (size_t)P.nrows * N;
-  f4v acc[2][4];
+  // per-lane slot of a square layer's tanh: (ct, rt) tile, lane order
+#define TAIL_ACT(BASE_, U_, RT_) (*(f4v*)((BASE_) + ((size_t)((w + 8 * (U_)) * 4 + (RT_)) * 64 + lane) * 4))
+  f4v acc[2][4], tk[2][4];   // tk: tanh of the latest square layer
   for (int k = 1; k < P.nfit; k++) {
     __syncthreads();
     stage_tile<PARTS>(Xs, x, w, NT, rb, g);
@@ -317,20 +325,24 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
     zero_tile(acc);
     tile_mm<PARTS>((const __bf16*)P.Wf[(sp * P.nfit + k) * 2], w, lane, Xs, acc);
     const float* bias = (const float*)P.bias[sp * P.nfit + k];
-    float* ak = P.act + k * lstride + (size_t)r0 * N;
 #pragma unroll
     for (int u = 0; u < 2; u++) {
       const int ct = w + 8 * u;
-      if (ct >= NT) continue;
-      const f4v bv = gld<f4v>(bias + 16 * ct + 4 * g);
+      const f4v bv = ct < NT ? gld<f4v>(bias + 16 * ct + 4 * g) : z4;
 #pragma unroll
       for (int rt = 0; rt < 4; rt++) {
-        f4v t;
 #pragma unroll
-        for (int q = 0; q < 4; q++) t[q] = dp_tanh(acc[u][rt][q] + bv[q]);
-        x[u][rt] += t;
-        *(f4v*)(ak + ((size_t)(ct * 4 + rt) * 64 + lane) * 4) = t;
+        for (int q = 0; q < 4; q++) tk[u][rt][q] = ct < NT ? dp_tanh(acc[u][rt][q] + bv[q]) : 0.f;
+        x[u][rt] += tk[u][rt];
       }
+    }
+    if (k < P.nfit - 1) {   // kept for the adjoint: the first in LDS, deeper ones in the workspace
+      float* dst = k == 1 ? act1 : P.act + k * lstride + (size_t)r0 * N;
+#pragma unroll
+      for (int u = 0; u < 2; u++)
+        if (w + 8 * u < NT)
+#pragma unroll
+          for (int rt = 0; rt < 4; rt++) TAIL_ACT(dst, u, rt) = tk[u][rt];
     }
   }
   // E_i = x . w_o + b_o, FP64 sums
@@ -367,17 +379,18 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) gr[u][rt] = wv[u];
   for (int k = P.nfit - 1; k >= 1; k--) {
-    const float* ak = P.act + k * lstride + (size_t)r0 * N;
+    if (k < P.nfit - 1) {   // the last layer's tanh is still in tk
+      const float* src = k == 1 ? act1 : P.act + k * lstride + (size_t)r0 * N;
+#pragma unroll
+      for (int u = 0; u < 2; u++)
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++) tk[u][rt] = w + 8 * u < NT ? TAIL_ACT(src, u, rt) : z4;
+    }
     f4v d[2][4];
 #pragma unroll
-    for (int u = 0; u < 2; u++) {
-      const int ct = w + 8 * u;
+    for (int u = 0; u < 2; u++)
 #pragma unroll
-      for (int rt = 0; rt < 4; rt++) {
-        const f4v t = ct < NT ? *(const f4v*)(ak + ((size_t)(ct * 4 + rt) * 64 + lane) * 4) : z4;
-        d[u][rt] = gr[u][rt] * (1.f - t * t);
-      }
-    }
+      for (int rt = 0; rt < 4; rt++) d[u][rt] = gr[u][rt] * (1.f - tk[u][rt] * tk[u][rt]);
     __syncthreads();
     stage_tile<PARTS>(Xs, d, w, NT, rb, g);
     __syncthreads();
@@ -388,6 +401,7 @@ __global__ __launch_bounds__(FT) void k_fit_tail(FitBfArgs P) {
 #pragma unroll
       for (int rt = 0; rt < 4; rt++) gr[u][rt] += acc[u][rt];
   }
+#undef TAIL_ACT
   // d1 = g1 (1 - t1^2) as fragments for the first layer's adjoint; pad rows and the
   // k >= N tail are zero (ct runs over all 2 kKS = 16 tiles)
   __bf16* out = P.d1f + (size_t)blockIdx.x * kKS * 4 * PARTS * 512;
