@@ -14,12 +14,14 @@
 // per-neighbour matrix product remains.  Neighbours outside the trained range are
 // left to the full net (the fallback rows of student_infer.hip).
 //
-// One wave per centre, four per block and no block-level sharing; lane (rb, g)
-// (rb = lane % 16, g = lane / 16) takes neighbour rb of each chunk of 16 and the hidden
-// units k = 16 n + 4 g + q (n < 2, q < 4).  The student blocks (a few KB per pair) are
-// read from global memory, where they stay cache-resident: W2 [k][f] for the forward
-// product (a wave reads 64 consecutive f) and its transpose W2T [f][k] for the adjoint's
-// (a lane pair per k).  The LDS holds only each wave's per-centre products.
+// One wave per centre; lane (rb, g) (rb = lane % 16, g = lane / 16) takes neighbour rb of
+// each chunk of 16 and the hidden units k = 16 n + 4 g + q (n < 2, q < 4), each
+// neighbour's environment row being formed once, by one lane, and handed to the chunk
+// lanes.  The forward runs four independent waves per block, the W2 [k][f] product read
+// from global memory (where the student blocks, a few KB per pair, stay cache-resident).
+// The adjoint runs eight centres per block: their V products are one small matrix
+// product on the MFMA with W2T [f][k] staged in LDS, and each wave pipelines the gathers
+// of its neighbour blocks across both species of a pass.
 #include <hip/hip_runtime.h>
 
 #include "embed_common.h"
@@ -324,18 +326,23 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
 constexpr int kStuBwdWaves = 8;
 
 // LDS of the adjoint: W2T of two pairs, then per wave V rows (with W1, b1) and u of two,
-// then per wave the centre's dE/dT [kP2][4]
+// then per wave the centre's dE/dT [kP2][4], then per wave s and R~ of the 64 neighbours
+// in flight (the same rows then carry their three FP64 force components: at least 24
+// bytes per lane)
+constexpr int kEnvStride = 6;
+
 size_t stu_bwd_lds_bytes(int elem) {
-  return (size_t)elem * (2 * kP2 * kP0 + kW2Pad + kStuBwdWaves * 2 * kStuS + kStuBwdWaves * kP2 * 4);
+  return (size_t)elem * (2 * kP2 * kP0 + kW2Pad + kStuBwdWaves * (2 * kStuS + kP2 * 4 + 64 * kEnvStride));
 }
 
 template <class T>
-__global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
+__global__ __launch_bounds__(64 * kStuBwdWaves) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_stu_bwd(EmbedArgs A) {
   extern __shared__ __align__(16) char smem[];
   T* w2s = (T*)smem;                                   // W2T of the pass's two pairs [2][kP2][kP0]
   const ModelC& m = A.m;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, rb = lane & 15, g = lane >> 4;
-  T* Vall = w2s + 2 * kP2 * kP0 + kW2Pad + wv * 2 * kStuS;   // per pair of the pass: V rows with W1, b1, then u
+  T* Vall0 = w2s + 2 * kP2 * kP0 + kW2Pad;                     // per wave, per pair of the pass: V rows with W1, b1, then u
+  T* Vall = Vall0 + wv * 2 * kStuS;
   const int r0 = blockIdx.x * kStuBwdWaves;
   const int alpha = species_of(r0, m.ntypes, A.type_row0);
   if (alpha < 0) return;   // uniform over the block (rows of one species: groups are padded to 64)
@@ -351,7 +358,8 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
   }
   // dE/dT of this centre [f][4]: one coalesced load into registers (feature lane and
   // lane + 64), copied to the wave's LDS rows for the broadcast reads of the V product
-  T* gts = w2s + 2 * kP2 * kP0 + kW2Pad + kStuBwdWaves * 2 * kStuS + wv * kP2 * 4;
+  T* gts0 = w2s + 2 * kP2 * kP0 + kW2Pad + kStuBwdWaves * 2 * kStuS;
+  T* gts = gts0 + wv * kP2 * 4;
   typedef T t4v __attribute__((ext_vector_type(4)));
   t4v gtv[2];
   {
@@ -363,39 +371,75 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
       if (f < kP2) *(t4v*)(gts + 4 * f) = gtv[i];
     }
   }
-  double fi = 0.0;                    // force component g on the centre (lane groups 0..2)
-  double vir[3] = {0.0, 0.0, 0.0};    // virial column g: W[a][g]
+  double fi[3] = {0.0, 0.0, 0.0};     // this lane's part of the force on the centre
+  double vir[3][3] = {};              // and of the centre's virial W[a][b]
+  T* envw = w2s + 2 * kP2 * kP0 + kW2Pad + kStuBwdWaves * (2 * kStuS + kP2 * 4) + wv * 64 * kEnvStride;
   const T inorm = (T)m.inv_norm;
   for (int b0 = 0; b0 < m.ntypes; b0 += 2) {
     const int nb = min(2, m.ntypes - b0);
+    // The pass's neighbour blocks of 64, (pair q, start c0) flattened over both pairs, run
+    // as one software pipeline: list entries two blocks ahead, coordinates and owners one
+    // block ahead, so that the first blocks' gathers overlap the V product and the
+    // barriers.  Block (q, c0) exists for c0 < nn_q; "q = 2" is the end (a dummy list
+    // row with nn = 0, whose loads stay in bounds).
+    const int* nlrow = A.nlist + (size_t)(live ? atom : 0) * m.nm;
+    const int nnq0 = live ? A.nnei[atom * m.ntypes + b0] : 0;
+    const int nnq1 = live && nb > 1 ? A.nnei[atom * m.ntypes + b0 + 1] : 0;
+    auto nnq = [&](int q) { return q == 0 ? nnq0 : q == 1 ? nnq1 : 0; };
+    auto norm = [&](int& q, int& c) {
+      while (q < 2 && c >= nnq(q)) {
+        q++;
+        c = 0;
+      }
+    };
+    auto blk_index = [&](int q, int c) {
+      const int qq = q < 2 ? q : 0;
+      return stu_index(nlrow + m.sel_off[b0 + (qq < nb ? qq : 0)], c + lane, nnq(q), m.sel[b0 + (qq < nb ? qq : 0)]);
+    };
+    int q1 = 0, c1 = 0;
+    norm(q1, c1);
+    int q2 = q1, c2 = c1 + 64;
+    norm(q2, c2);
+    int en = blk_index(q1, c1), en2 = blk_index(q2, c2);
     __syncthreads();   // the previous pass's W2T is no longer read
     for (int q = 0; q < nb; q++)
       stage_bytes(w2s + q * (kP2 * kP0 + kW2Pad), (const T*)A.snets + (size_t)(alpha * m.ntypes + b0 + q) * kStuElems + kSW2T,
                   (int)sizeof(T) * kP2 * kP0);
     __syncthreads();
-    if (!live) continue;
-    // V_beta[k][c] = sum_f W2[k][f] gt[f][c] with one lane per (beta, k): lanes 0..31 the
-    // pass's first pair, 32..63 its second; dE/dT is the same for both (LDS broadcast)
+    double xn[3];
+    int own_n;
+    stu_coords_owner(A.xe, A.eown, en, xn, own_n);
+    // V_beta[k][(w, c)] = sum_f W2[k][f] gt_w[f][c] for the block's eight centres w on the
+    // MFMA (16x16x4): wave wv takes the output tile of pair q = wv / 4, hidden units
+    // 16 kt .. 16 kt + 15 (kt = (wv / 2) % 2) and centres 4 nt .. 4 nt + 3 (nt = wv % 2),
+    // four components each; A = W2T rows f (staged above), B = the centres' dE/dT rows
+    // (zero at f >= M, so the last k step may run past M)
+    {
+      const int q = wv >> 2, kt = (wv >> 1) & 1, nt = wv & 1;
+      if (q < nb) {
+        const int wsrc = 4 * nt + (rb >> 2), c = rb & 3;
+        const T* Aw = w2s + q * (kP2 * kP0 + kW2Pad) + 16 * kt + rb;
+        const T* Bw = gts0 + wsrc * kP2 * 4 + c;
+        typedef T acc4 __attribute__((ext_vector_type(4)));
+        acc4 acc = {(T)0, (T)0, (T)0, (T)0};
+        for (int f0 = 0; f0 < M; f0 += 4) {
+          const int f = f0 + g;
+          acc = mfma4(Aw[f * kP0], Bw[4 * f], acc);
+        }
+        T* Vb = Vall0 + wsrc * 2 * kStuS + q * kStuS;
+#pragma unroll
+        for (int r = 0; r < 4; r++) Vb[vrow(16 * kt + lpos(T(), g, r)) + c] = acc[r];
+      }
+    }
+    // W1 and b1 beside each V row of the wave's own centre, and u_beta[c] = sum_f b2_beta[f] gt[f][c]
     {
       const int hb = lane >> 5, kk = lane & 31;
-      const T* w = w2s + hb * (kP2 * kP0 + kW2Pad) + kk;
-      T v4[4] = {(T)0, (T)0, (T)0, (T)0};
-#pragma unroll 8
-      for (int f = 0; f < M; f++) {
-        const T wf = w[f * kP0];
-        const t4v g4 = *(const t4v*)(gts + 4 * f);
-#pragma unroll
-        for (int c = 0; c < 4; c++) v4[c] += wf * g4[c];
-      }
       if (hb < nb) {
         const auto sn = stu_block<T>(A, alpha * m.ntypes + b0 + hb);
         T* Vb = Vall + hb * kStuS;
-#pragma unroll
-        for (int c = 0; c < 4; c++) Vb[vrow(kk) + c] = v4[c];
         Vb[vrow(kk) + 4] = sn[kSW1 + kk];
         Vb[vrow(kk) + 5] = sn[kSB1 + kk];
       }
-      // u_beta[c] = sum_f b2_beta[f] gt[f][c]
       for (int q = 0; q < nb; q++) {
         const auto sn = stu_block<T>(A, alpha * m.ntypes + b0 + q);
         const int f1 = lane + 64;
@@ -408,103 +452,140 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) void k_stu_bwd(EmbedArgs A) {
         }
       }
     }
-    wave_sync_lds();
-    for (int q = 0; q < nb; q++) {
-    const int beta = b0 + q;
-    const int pair = alpha * m.ntypes + beta;
-    const T* Vw = Vall + q * kStuS;
-    const double slo = A.st_lo[pair], shi = A.st_hi[pair];
-    // V, W1 and b1 of the lane's hidden units are read from LDS inside the neighbour loop
-    // (held in registers they would cost 48 VGPRs and lower the waves per SIMD)
-    T uu[4];
+    __syncthreads();   // every centre's V rows are complete
+    if (!live) continue;
+    const double slo0 = A.st_lo[alpha * m.ntypes + b0], shi0 = A.st_hi[alpha * m.ntypes + b0];
+    const double slo1 = nb > 1 ? A.st_lo[alpha * m.ntypes + b0 + 1] : 0.0;
+    const double shi1 = nb > 1 ? A.st_hi[alpha * m.ntypes + b0 + 1] : 0.0;
+    // Each block: lane L forms the FP64 environment row of neighbour c0 + L once and
+    // publishes s and R~ (the student's type) in the wave's LDS rows; then in chunks of 16
+    // lane (rb, g) takes neighbour rb of the chunk and the hidden units of lane group g.
+    // The sums over the lane groups land in every group; lane group q keeps those of
+    // chunk q, which are its own neighbours', and assembles their forces.
+    while (q1 < 2) {
+      const int q = q1, c0 = c1, nn = nnq(q);
+      const int e = en, own = own_n;
+      const double xj[3] = {xn[0], xn[1], xn[2]};
+      int q3 = q2, c3 = c2 + 64;
+      norm(q3, c3);
+      en = en2;
+      en2 = blk_index(q3, c3);
+      stu_coords_owner(A.xe, A.eown, en, xn, own_n);
+      q1 = q2;
+      c1 = c2;
+      q2 = q3;
+      c2 = c3;
+      // V, W1 and b1 of the lane's hidden units are read from LDS inside the chunk loop
+      // (held in registers they would cost 48 VGPRs and lower the waves per SIMD)
+      const T* Vw = Vall + q * kStuS;
+      const double slo = q == 0 ? slo0 : slo1, shi = q == 0 ? shi0 : shi1;
+      T uu[4];
 #pragma unroll
-    for (int c = 0; c < 4; c++) uu[c] = Vw[kStuU + c];
-    const int nn = A.nnei[atom * m.ntypes + beta];
-    const int* nl = A.nlist + (size_t)atom * m.nm + m.sel_off[beta];
-    const int sel = m.sel[beta];
-    // one chunk of 16 neighbours: lane (rb, g) takes neighbour rb and the hidden units of
-    // lane group g; the caller supplies the neighbour's index, owner and coordinates
-    auto chunk = [&](int e, int own, const double (&xj)[3]) {
+      for (int c = 0; c < 4; c++) uu[c] = Vw[kStuU + c];
       bool valid = e >= 0;
       StuEnv v;
-      T s = (T)0, R[4] = {(T)0, (T)0, (T)0, (T)0};
+      T sL = (T)0, RL[4] = {(T)0, (T)0, (T)0, (T)0};
       if (valid) {
         stu_env(m, xj, xi, v);
         if (stu_out_of_range(slo, shi, v.s)) {
           valid = false;   // handled by the fallback kernel
         } else {
-          s = (T)v.s;
+          sL = (T)v.s;
 #pragma unroll
-          for (int c = 0; c < 4; c++) R[c] = (T)v.R[c];
+          for (int c = 0; c < 4; c++) RL[c] = (T)v.R[c];
         }
       }
-      // gR[c] = sum_p G[p] gt[p][c] = h . V[:, c] + u[c];  dsl = dE/ds through G
-      T gR[4] = {(T)0, (T)0, (T)0, (T)0}, dsp = (T)0;
-      int zo = 0;
-      asm volatile("" : "+s"(zo));   // keeps the V loads inside the loop (not hoisted into registers)
+      wave_sync_lds();   // the previous block's rows have been read
+      envw[kEnvStride * lane] = sL;
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const T* P = Vw + zo + vrow(16 * (j >> 2) + 4 * g + (j & 3));
-        const T vk[4] = {P[0], P[1], P[2], P[3]}, w1 = P[4], b1 = P[5];
-        const T h = tanh_t(s * w1 + b1);
-        T dh = (T)0;
+      for (int c = 0; c < 4; c++) envw[kEnvStride * lane + 1 + c] = RL[c];
+      wave_sync_lds();
+      // gR[c] = sum_p G[p] gt[p][c] = h . V[:, c] + u[c];  dsl = dE/ds through G
+      T gRo[4] = {(T)0, (T)0, (T)0, (T)0}, dslo = (T)0;
+#pragma unroll
+      for (int qc = 0; qc < 4; qc++) {
+        if (c0 + 16 * qc >= nn) break;   // uniform over the wave
+        const T* E = envw + kEnvStride * (16 * qc + rb);
+        const T s = E[0], R[4] = {E[1], E[2], E[3], E[4]};
+        T gR[4] = {(T)0, (T)0, (T)0, (T)0}, dsp = (T)0;
+        int zo = 0;
+        asm volatile("" : "+s"(zo));   // keeps the V loads inside the loop (not hoisted into registers)
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const T* P = Vw + zo + vrow(16 * (j >> 2) + 4 * g + (j & 3));
+          const T vk[4] = {P[0], P[1], P[2], P[3]}, w1 = P[4], b1 = P[5];
+          const T h = tanh_t(s * w1 + b1);
+          T dh = (T)0;
+#pragma unroll
+          for (int c = 0; c < 4; c++) {
+            gR[c] += h * vk[c];
+            dh += vk[c] * R[c];
+          }
+          dsp += dh * ((T)1 - h * h) * w1;
+        }
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-          gR[c] += h * vk[c];
-          dh += vk[c] * R[c];
+          gR[c] = sum_g(gR[c]) + uu[c];
+          gRo[c] = g == qc ? gR[c] : gRo[c];
         }
-        dsp += dh * ((T)1 - h * h) * w1;
+        const T dsl = sum_g(dsp) * inorm;   // dE/ds through G, in the student's type
+        dslo = g == qc ? dsl : dslo;
       }
-#pragma unroll
-      for (int c = 0; c < 4; c++) gR[c] = sum_g(gR[c]) + uu[c];
-      const T dsl = sum_g(dsp) * inorm;   // dE/ds through G, in the student's type
-      // g_ij = dR^T dE/dR (Eq. 5 differentiated) in FP64: lane group g < 3 computes
-      // component g from the FP64 environment row and dE/dR~ (the student's sums)
-      double gv = 0.0;
-      if (valid && g < 3) {
+      // g_ij = dR^T dE/dR (Eq. 5 differentiated) in FP64 from the lane's environment row
+      // and dE/dR~ (the student's sums): g_b = d_b (dE/dR0 ds/r + qf d.dE/dR) + (s/r) dE/dR_b
+      double gv[3] = {0.0, 0.0, 0.0};
+      if (valid) {
         const double in = m.inv_norm;
-        const double gRd[4] = {(double)gR[0] * in + (double)dsl, (double)gR[1] * in, (double)gR[2] * in,
-                               (double)gR[3] * in};
+        const double gRd[4] = {(double)gRo[0] * in + (double)dslo, (double)gRo[1] * in, (double)gRo[2] * in,
+                               (double)gRo[3] * in};
         const double ir = v.ir;
         const double sr = v.s * ir;
         const double qf = (v.ds * ir - v.s * ir * ir) * ir;
         const double dot = gRd[1] * v.d[0] + gRd[2] * v.d[1] + gRd[3] * v.d[2];
-        const double db = g == 0 ? v.d[0] : g == 1 ? v.d[1] : v.d[2];
-        const double gRb = g == 0 ? gRd[1] : g == 1 ? gRd[2] : gRd[3];
-        gv = gRd[0] * v.ds * db * ir + qf * dot * db + sr * gRb;
-        fi += gv;
+        const double cf = gRd[0] * v.ds * ir + qf * dot;
 #pragma unroll
-        for (int a = 0; a < 3; a++) vir[a] -= v.d[a] * gv;   // W[a][g]
+        for (int b = 0; b < 3; b++) {
+          gv[b] = cf * v.d[b] + sr * gRd[b + 1];
+          fi[b] += gv[b];
+#pragma unroll
+          for (int a = 0; a < 3; a++) vir[a][b] -= v.d[a] * gv[b];   // W[a][b]
+        }
       }
-      if (valid && g < 3) unsafeAtomicAdd(&A.forces[3 * own + g], -gv);
-    };
-    int en = stu_index(nl, rb, nn, sel), en2 = stu_index(nl, 16 + rb, nn, sel);
-    double xn[3];
-    int own_n;
-    stu_coords_owner(A.xe, A.eown, en, xn, own_n);
-    for (int c0 = 0; c0 < nn; c0 += 16) {
-      const int e = en, own = own_n;
-      const double xj[3] = {xn[0], xn[1], xn[2]};
-      en = en2;
-      en2 = stu_index(nl, c0 + 32 + rb, nn, sel);
-      stu_coords_owner(A.xe, A.eown, en, xn, own_n);
-      chunk(e, own, xj);
-    }
+      // the neighbours' forces go out through the LDS rows in the chunk layout, lane
+      // (rb, g < 3) adding component g of neighbour rb: one atomic instruction per chunk
+      // covers 16 neighbours with their three components side by side (one L2 line each)
+      wave_sync_lds();   // the chunks' reads of s and R~ are done
+      double* gvw = (double*)envw;
+#pragma unroll
+      for (int b = 0; b < 3; b++) gvw[3 * lane + b] = gv[b];
+      wave_sync_lds();
+      const int ownv = valid ? own : -1;
+#pragma unroll
+      for (int qc = 0; qc < 4; qc++) {
+        if (c0 + 16 * qc >= nn) break;   // uniform over the wave
+        const int o = __shfl(ownv, 16 * qc + rb, 64);
+        const double f = gvw[3 * (16 * qc + rb) + (g < 3 ? g : 0)];
+        if (g < 3 && o >= 0) unsafeAtomicAdd(&A.forces[3 * o + g], -f);
+      }
     }
     wave_sync_lds();   // the V rows are rewritten in the next pass
   }
   if (!live) return;
+  // sums over the wave: lane b < 3 adds force component b to the centre, lane k < 9
+  // writes virial entry k = 3 a + b
+  double fsum = 0.0, wsum = 0.0;
 #pragma unroll
-  for (int o = 1; o < 16; o <<= 1) {
-    fi += __shfl_xor(fi, o);
-#pragma unroll
-    for (int a = 0; a < 3; a++) vir[a] += __shfl_xor(vir[a], o);
+  for (int b = 0; b < 3; b++) {
+    const double t = sum_g(row_sum16(fi[b]));
+    fsum = lane == b ? t : fsum;
   }
-  if (rb == 0 && g < 3) {
-    unsafeAtomicAdd(&A.forces[3 * atom + g], fi);
 #pragma unroll
-    for (int a = 0; a < 3; a++) A.vir_part[(size_t)row * 9 + 3 * a + g] = vir[a];
+  for (int k = 0; k < 9; k++) {
+    const double t = sum_g(row_sum16(vir[k / 3][k % 3]));
+    wsum = lane == k ? t : wsum;
   }
+  if (lane < 3) unsafeAtomicAdd(&A.forces[3 * atom + lane], fsum);
+  if (lane < 9) A.vir_part[(size_t)row * 9 + lane] = wsum;
 }
 
 template <class T>
