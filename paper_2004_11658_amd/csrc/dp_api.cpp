@@ -553,7 +553,7 @@ struct Plan {
   bool verlet = false;
   size_t o_wk, o_xref, o_eabc, o_vlist, o_vcnt, o_vflag, o_npt = 0;
   int n, nframes, ncell, ghost_cap, nrows, vcap, max_frame_atoms;
-  size_t o_redpart, o_reddone;
+  size_t o_redpart;
   size_t o_gbuf = 0, o_rev = 0;   // deterministic force gather
   size_t o_big = 0;
 };
@@ -650,7 +650,6 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
   P.o_tmpj = take(sizeof(double) * nframes * 10);
   P.max_frame_atoms = (int)maxna;
   P.o_redpart = take(sizeof(double) * 10 * (size_t)nframes * frame_reduce_chunks((int)maxna));
-  P.o_reddone = take(sizeof(int) * (size_t)nframes);
   P.o_tmpi = take(sizeof(int) * 16);
   P.o_mdF = take(sizeof(double) * 3 * n);
   P.o_mdE = take(sizeof(double) * nframes);
@@ -795,7 +794,6 @@ static int stage_frames(dp_handle h, int nframes, const int64_t* off, const doub
   }
   // the status word covers the whole call
   launch_zero_int(A.status, STW_N, st);
-  launch_zero_int(W.at<int>(P.o_reddone), P.nframes, st);   // frame-reduction counters
   launch_zero_int(A.nbig, 2, st);   // deferred-atom count and its pass counter
   return DP_OK;
 }
@@ -923,7 +921,7 @@ static int run_model(dp_handle h, const Plan& P, const NlistArgs& A, void* ws, h
     StageTimer tm(h, DP_STAGE_REDUCE, st);
     launch_frame_reduce(P.nframes, P.max_frame_atoms, reduce_frames ? reduce_frames : A.frames, A.row_of, F.Ei,
                         want_forces ? E.vir_part : nullptr, energies, virials, atom_energy,
-                        W.at<double>(P.o_redpart), W.at<int>(P.o_reddone), st);
+                        W.at<double>(P.o_redpart), st);
   }
   HIPCHECK(h, hipGetLastError());
   return DP_OK;
@@ -1201,6 +1199,7 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
   double* F = forces ? forces : W.at<double>(P.o_mdF);
   double* E = W.at<double>(P.o_mdE);
   double* Wv = W.at<double>(P.o_mdW);
+  double* kepart = W.at<double>(P.o_redpart);   // free once the frame reduction is done
   const double* B = box;
   double vol = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
                B[2] * (B[3] * B[7] - B[4] * B[6]);
@@ -1235,7 +1234,7 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
   rc = force(false, false, thermo != nullptr);
   if (rc != DP_OK) return rc;
   int row = 0;
-  if (thermo) launch_thermo(n, types, mm, vol, 0, v, E, Wv, thermo + 6 * row++, st);
+  if (thermo) launch_thermo(n, types, mm, vol, 0, v, E, Wv, thermo + 6 * row++, kepart, st);
   // Velocity Verlet: half kick + drift, forces, half kick.  Between two steps without a
   // thermo row the closing half kick and the next opening half kick + drift run as one
   // kernel, which also clears F for the next force evaluation.
@@ -1251,7 +1250,7 @@ int dp_md_run(dp_handle h, int64_t natoms, double* x, double* v, const int32_t* 
     StageTimer tm(h, DP_STAGE_MD, st);
     if (thermo_row || s == nsteps) {
       launch_vv(n, types, mm, dt_fs, F, v, x, false, chk, st);
-      if (thermo_row) launch_thermo(n, types, mm, vol, s, v, E, Wv, thermo + 6 * row++, st);
+      if (thermo_row) launch_thermo(n, types, mm, vol, s, v, E, Wv, thermo + 6 * row++, kepart, st);
       opened = false;
     } else {
       launch_vv_merged(n, types, mm, dt_fs, F, v, x, chk, st);

@@ -521,23 +521,41 @@ void launch_zero(double* p, size_t n, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, st, n, p);
 }
 
-// Per frame, fixed-order sums of E_i and the per-centre virials: block (c, f) sums the
-// atoms [c * kRedChunk, (c + 1) * kRedChunk) of frame f (one per thread; wave sums by
-// butterfly shuffles, then the four waves in order) into partial row (f, c); the block
-// that finishes last for frame f (a per-frame counter) adds the partial rows in chunk
-// order and resets the counter, so the result does not depend on block scheduling.
+// Per frame, fixed-order sums of E_i and the per-centre virials in two launches: block
+// (c, f) sums the atoms [c * kRedChunk, (c + 1) * kRedChunk) of frame f (one per thread;
+// wave sums by butterfly shuffles, then the four waves in order) into partial row (f, c);
+// then one block per frame adds the partial rows in chunk order, so the result does not
+// depend on block scheduling.  (A last-block-finishes scheme would need a device-wide
+// fence per block, which writes back the L2 of every XCD.)
 constexpr int kRedChunk = 256;
+
+// sum of acc over the block (every thread of wave 0 gets it), the waves added in order
+__device__ __forceinline__ void block_sum10(double (&acc)[10], double (*sh)[10]) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int q = 0; q < 10; q++) acc[q] += __shfl_xor(acc[q], o);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 10; q++) sh[wv][q] = acc[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 10; q++) {
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < kRedChunk / 64; w++) a += sh[w][q];
+    acc[q] = a;
+  }
+}
 
 __global__ __launch_bounds__(kRedChunk) void k_frame_reduce(const Frame* __restrict__ frames,
                                                             const int* __restrict__ row_of,
                                                             const double* __restrict__ Ei,
                                                             const double* __restrict__ vir,
                                                             double* __restrict__ atom_energy,
-                                                            double* __restrict__ part, int* __restrict__ done,
-                                                            double* __restrict__ energies,
-                                                            double* __restrict__ virials) {
+                                                            double* __restrict__ part) {
   __shared__ double sh[kRedChunk / 64][10];
-  __shared__ int last;
   const int f = blockIdx.y, nchunk = gridDim.x;
   const Frame& F = frames[f];
   const int i = F.atom0 + blockIdx.x * kRedChunk + threadIdx.x;
@@ -553,62 +571,49 @@ __global__ __launch_bounds__(kRedChunk) void k_frame_reduce(const Frame* __restr
 #pragma unroll
       for (int q = 0; q < 9; q++) acc[1 + q] = vir[(size_t)r * 9 + q];
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-    for (int q = 0; q < 10; q++) acc[q] += __shfl_xor(acc[q], o);
-  const int wv = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0)
-#pragma unroll
-    for (int q = 0; q < 10; q++) sh[wv][q] = acc[q];
-  __syncthreads();
+  block_sum10(acc, sh);
   if (threadIdx.x < 10) {
     double a = 0.0;
 #pragma unroll
-    for (int w = 0; w < kRedChunk / 64; w++) a += sh[w][threadIdx.x];
+    for (int q = 0; q < 10; q++) a = q == (int)threadIdx.x ? acc[q] : a;
     part[((size_t)f * nchunk + blockIdx.x) * 10 + threadIdx.x] = a;
   }
-  __threadfence();   // the partial row is visible device-wide before the count
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&done[f], 1) == nchunk - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();   // every other block's partial row is visible
-  // the partial rows in a fixed order: thread t adds rows t, t + kRedChunk, ..., then the
-  // same shuffle and wave order as above
+}
+
+// the partial rows of frame blockIdx.x in a fixed order: thread t adds rows t,
+// t + kRedChunk, ..., then the block sum as above
+__global__ __launch_bounds__(kRedChunk) void k_frame_reduce_rows(int nchunk, const double* __restrict__ part,
+                                                                 double* __restrict__ energies,
+                                                                 double* __restrict__ virials, int with_vir) {
+  __shared__ double sh[kRedChunk / 64][10];
+  const int f = blockIdx.x;
+  double acc[10];
 #pragma unroll
   for (int q = 0; q < 10; q++) acc[q] = 0.0;
   for (int c = threadIdx.x; c < nchunk; c += kRedChunk)
 #pragma unroll
     for (int q = 0; q < 10; q++) acc[q] += part[((size_t)f * nchunk + c) * 10 + q];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-    for (int q = 0; q < 10; q++) acc[q] += __shfl_xor(acc[q], o);
-  __syncthreads();   // sh is reused
-  if ((threadIdx.x & 63) == 0)
-#pragma unroll
-    for (int q = 0; q < 10; q++) sh[wv][q] = acc[q];
-  __syncthreads();
+  block_sum10(acc, sh);
   const int q = threadIdx.x;
   if (q < 10) {
     double a = 0.0;
 #pragma unroll
-    for (int w = 0; w < kRedChunk / 64; w++) a += sh[w][q];
+    for (int k = 0; k < 10; k++) a = k == q ? acc[k] : a;
     if (q == 0) energies[f] = a;
-    else if (virials && vir) virials[f * 9 + q - 1] = a;
+    else if (virials && with_vir) virials[f * 9 + q - 1] = a;
   }
-  if (q == 0) done[f] = 0;   // ready for the next evaluation
 }
 
 int frame_reduce_chunks(int max_frame_atoms) { return (max_frame_atoms + kRedChunk - 1) / kRedChunk; }
 
 void launch_frame_reduce(int nframes, int max_frame_atoms, const Frame* frames, const int* row_of,
                          const double* Ei, const double* vir_rows, double* energies, double* virials,
-                         double* atom_energy, double* part, int* done, hipStream_t st) {
+                         double* atom_energy, double* part, hipStream_t st) {
   const int nchunk = frame_reduce_chunks(max_frame_atoms);
   hipLaunchKernelGGL(k_frame_reduce, dim3(nchunk, nframes), dim3(kRedChunk), 0, st, frames, row_of, Ei, vir_rows,
-                     atom_energy, part, done, energies, virials);
+                     atom_energy, part);
+  hipLaunchKernelGGL(k_frame_reduce_rows, dim3(nframes), dim3(kRedChunk), 0, st, nchunk, part, energies, virials,
+                     vir_rows ? 1 : 0);
 }
 
 template <class T>

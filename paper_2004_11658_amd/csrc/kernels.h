@@ -174,10 +174,9 @@ void launch_fit_bf(const FitArgs& a, hipStream_t st);
 void launch_zero(double* p, size_t n, hipStream_t st);
 // part: frame_reduce_chunks(max atoms of a frame) * nframes * 10 doubles of scratch
 int frame_reduce_chunks(int max_frame_atoms);
-// done: nframes ints, zero before the first use of a call (each use leaves them zero)
 void launch_frame_reduce(int nframes, int max_frame_atoms, const Frame* frames, const int* row_of,
                          const double* Ei, const double* vir_rows, double* energies, double* virials,
-                         double* atom_energy, double* part, int* done, hipStream_t st);
+                         double* atom_energy, double* part, hipStream_t st);
 void launch_export_T(int prec, int n, int M, const int* row_of, const void* Tm, const void* gT,
                      double* To, double* gTo, hipStream_t st);
 // per-atom virial [n][9] of the centres from the per-centre rows
@@ -304,7 +303,9 @@ void launch_vv_merged(int n, const int* types, const MDMass& mass, double dt, do
                       const VvCheck& chk, hipStream_t st);
 void launch_vv(int n, const int* types, const MDMass& mass, double dt, const double* F, double* v,
                double* x, bool drift, const VvCheck& chk, hipStream_t st);
+// part: scratch of at least thermo_parts(n) doubles (the frame reduction's, which is free by then)
+int thermo_parts(int n);
 void launch_thermo(int n, const int* types, const MDMass& mass, double volume, int step,
-                   const double* v, const double* E, const double* W, double* row, hipStream_t st);
+                   const double* v, const double* E, const double* W, double* row, double* part, hipStream_t st);
 
 }  // namespace dp

@@ -75,20 +75,39 @@ __global__ __launch_bounds__(256) void k_vv2(int n, const int* __restrict__ type
   vv_check(chk, i, n, x);
 }
 
-// thermo row [step, PE, KE, T, Etot, P(bar)]: one block, fixed-order reduction
-__global__ __launch_bounds__(1024) void k_thermo(int n, const int* __restrict__ types, MDMass mass,
+// thermo row [step, PE, KE, T, Etot, P(bar)] in two launches with fixed-order sums: block
+// b adds the kinetic energies of atoms [1024 b, 1024 b + 1024) (butterfly shuffles, then
+// its four waves in order) into part[b]; one block then adds the parts in order
+constexpr int kKePer = 1024;
+
+__global__ __launch_bounds__(256) void k_thermo_part(int n, const int* __restrict__ types, MDMass mass,
+                                                     const double* __restrict__ v, double* __restrict__ part) {
+  __shared__ double sh[4];
+  double ke = 0.0;
+#pragma unroll
+  for (int k = 0; k < kKePer / 256; k++) {
+    const int i = blockIdx.x * kKePer + 256 * k + threadIdx.x;
+    if (i < n) {
+      const int t = types[i];
+      const double m = (t >= 0 && t < kMaxTypes) ? mass.m[t] : 0.0;
+      ke += 0.5 * m * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2]);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ke += __shfl_xor(ke, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ke;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+__global__ __launch_bounds__(1024) void k_thermo(int n, int nparts, const double* __restrict__ part,
                                                  double volume, int step,
-                                                 const double* __restrict__ v,
                                                  const double* __restrict__ E,
                                                  const double* __restrict__ W,
                                                  double* __restrict__ row) {
   __shared__ double sh[1024];
   double ke = 0.0;
-  for (int i = threadIdx.x; i < n; i += 1024) {
-    int t = types[i];
-    double m = (t >= 0 && t < kMaxTypes) ? mass.m[t] : 0.0;
-    ke += 0.5 * m * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2]);
-  }
+  for (int b = threadIdx.x; b < nparts; b += 1024) ke += part[b];
   sh[threadIdx.x] = ke;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
@@ -108,6 +127,8 @@ __global__ __launch_bounds__(1024) void k_thermo(int n, const int* __restrict__ 
   }
 }
 
+int thermo_parts(int n) { return (n + kKePer - 1) / kKePer; }
+
 void launch_vv(int n, const int* types, const MDMass& mass, double dt, const double* F, double* v,
                double* x, bool drift, const VvCheck& chk, hipStream_t st) {
   hipLaunchKernelGGL(k_vv, dim3((n + 255) / 256), dim3(256), 0, st, n, types, mass, 0.5 * dt * kAcc,
@@ -121,8 +142,10 @@ void launch_vv_merged(int n, const int* types, const MDMass& mass, double dt, do
 }
 
 void launch_thermo(int n, const int* types, const MDMass& mass, double volume, int step,
-                   const double* v, const double* E, const double* W, double* row, hipStream_t st) {
-  hipLaunchKernelGGL(k_thermo, dim3(1), dim3(1024), 0, st, n, types, mass, volume, step, v, E, W, row);
+                   const double* v, const double* E, const double* W, double* row, double* part, hipStream_t st) {
+  const int np = thermo_parts(n);
+  hipLaunchKernelGGL(k_thermo_part, dim3(np), dim3(256), 0, st, n, types, mass, v, part);
+  hipLaunchKernelGGL(k_thermo, dim3(1), dim3(1024), 0, st, n, np, part, volume, step, E, W, row);
 }
 
 // ------------------------------------------------------------------------------------
