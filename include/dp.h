@@ -251,14 +251,16 @@ int dp_get_params(dp_handle h, double* theta, void* stream);
  * with gE [nframes] and gF [natoms][3] device doubles (the loss gradients with respect
  * to the energies and forces) and gtheta [nparams] device doubles (accumulated: zero
  * it first).  Computed exactly (forward-over-reverse, FP64, any precision option).
- * Batch arguments as dp_compute_batch.  The workspace must hold
- * dp_param_grad_workspace_size bytes (roughly 8 KB per neighbour pair: split large
- * batches into several calls).  Synchronises the stream once. */
+ * Batch arguments as dp_compute_batch.  The library runs the batch in chunks of whole
+ * frames of at most max_atoms atoms together (0: 8192; a larger frame is a chunk of its
+ * own), so the workspace, dp_param_grad_workspace_size bytes for the same max_atoms,
+ * is that of the largest chunk (roughly 8 KB per neighbour pair of it), whatever the
+ * batch size.  Synchronises the stream once per chunk. */
 int dp_param_grad_workspace_size(dp_handle h, int32_t nframes, const int64_t* atom_offsets,
-                                 const double* boxes, size_t* bytes);
+                                 const double* boxes, int64_t max_atoms, size_t* bytes);
 int dp_param_grad(dp_handle h, int32_t nframes, const int64_t* atom_offsets, const double* coords,
                   const int32_t* types, const double* boxes, const double* gE, const double* gF,
-                  double* gtheta, void* workspace, size_t ws_bytes, void* stream);
+                  double* gtheta, int64_t max_atoms, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---- student embedding net (a narrower G_s(s) = tanh(s W1 + b1) W2 + b2, 1 -> H -> M,
  * trained to reproduce the full embedding net on the s range the model visits) ---- */

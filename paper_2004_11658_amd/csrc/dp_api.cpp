@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -1409,22 +1410,72 @@ static PGLayout pg_layout(dp_handle h, const Plan& P) {
   return L;
 }
 
-int dp_param_grad_workspace_size(dp_handle h, int32_t nframes, const int64_t* atom_offsets,
-                                 const double* boxes, size_t* bytes) {
-  if (!h || !atom_offsets || !boxes || !bytes) return fail(h, DP_ERR_ARG, "null argument");
-  Plan P;
-  int rc = make_plan(h, nframes, atom_offsets, boxes, nullptr, P);
-  if (rc != DP_OK) return rc;
-  *bytes = pg_layout(h, P).total;
+// The batch runs in chunks of whole frames, greedily packed up to max_atoms atoms (a
+// larger frame is a chunk of its own): the workspace holds the largest chunk's plan, so it
+// is bounded by the chunk size, not by the batch.
+static constexpr int64_t kPgChunkAtoms = 8192;
+
+static int pg_chunks(int32_t nframes, const int64_t* off, int64_t max_atoms,
+                     const std::function<int(int32_t, int32_t)>& fn) {
+  if (max_atoms <= 0) max_atoms = kPgChunkAtoms;
+  int32_t f0 = 0;
+  while (f0 < nframes) {
+    int32_t f1 = f0 + 1;
+    while (f1 < nframes && off[f1 + 1] - off[f0] <= max_atoms) f1++;
+    int rc = fn(f0, f1);
+    if (rc != DP_OK) return rc;
+    f0 = f1;
+  }
   return DP_OK;
 }
 
+static std::vector<int64_t> pg_sub_offsets(const int64_t* off, int32_t f0, int32_t f1) {
+  std::vector<int64_t> sub((size_t)(f1 - f0) + 1);
+  for (int32_t f = f0; f <= f1; f++) sub[(size_t)(f - f0)] = off[f] - off[f0];
+  return sub;
+}
+
+int dp_param_grad_workspace_size(dp_handle h, int32_t nframes, const int64_t* atom_offsets,
+                                 const double* boxes, int64_t max_atoms, size_t* bytes) {
+  if (!h || !atom_offsets || !boxes || !bytes) return fail(h, DP_ERR_ARG, "null argument");
+  if (nframes < 1) return fail(h, DP_ERR_ARG, "nframes must be >= 1");
+  size_t need = 0;
+  int rc = pg_chunks(nframes, atom_offsets, max_atoms, [&](int32_t f0, int32_t f1) {
+    const std::vector<int64_t> sub = pg_sub_offsets(atom_offsets, f0, f1);
+    Plan P;
+    int r = make_plan(h, f1 - f0, sub.data(), boxes + 9 * (size_t)f0, nullptr, P);
+    if (r != DP_OK) return r;
+    need = std::max(need, pg_layout(h, P).total);
+    return (int)DP_OK;
+  });
+  if (rc != DP_OK) return rc;
+  *bytes = need;
+  return DP_OK;
+}
+
+static int param_grad_chunk(dp_handle h, int32_t nframes, const int64_t* atom_offsets, const double* coords,
+                            const int32_t* types, const double* boxes, const double* gE, const double* gF,
+                            double* gtheta, void* workspace, size_t ws_bytes, hipStream_t st);
+
 int dp_param_grad(dp_handle h, int32_t nframes, const int64_t* atom_offsets, const double* coords,
                   const int32_t* types, const double* boxes, const double* gE, const double* gF,
-                  double* gtheta, void* workspace, size_t ws_bytes, void* stream) {
+                  double* gtheta, int64_t max_atoms, void* workspace, size_t ws_bytes, void* stream) {
   if (!h) return DP_ERR_ARG;
-  if (!atom_offsets || !boxes || !gE || !gF || !gtheta) return fail(h, DP_ERR_ARG, "null argument");
-  hipStream_t st = (hipStream_t)stream;
+  if (!atom_offsets || !boxes || !gE || !gF || !gtheta || !coords || !types)
+    return fail(h, DP_ERR_ARG, "null argument");
+  if (nframes < 1) return fail(h, DP_ERR_ARG, "nframes must be >= 1");
+  return pg_chunks(nframes, atom_offsets, max_atoms, [&](int32_t f0, int32_t f1) {
+    const std::vector<int64_t> sub = pg_sub_offsets(atom_offsets, f0, f1);
+    const int64_t a0 = atom_offsets[f0];
+    return param_grad_chunk(h, f1 - f0, sub.data(), coords + 3 * a0, types + a0, boxes + 9 * (size_t)f0, gE + f0,
+                            gF + 3 * a0, gtheta, workspace, ws_bytes, (hipStream_t)stream);
+  });
+}
+
+// one chunk of frames (offsets rebased to its first atom)
+static int param_grad_chunk(dp_handle h, int32_t nframes, const int64_t* atom_offsets, const double* coords,
+                            const int32_t* types, const double* boxes, const double* gE, const double* gF,
+                            double* gtheta, void* workspace, size_t ws_bytes, hipStream_t st) {
   Plan P;
   NlistArgs A{};
   {
@@ -1453,7 +1504,7 @@ int dp_param_grad(dp_handle h, int32_t nframes, const int64_t* atom_offsets, con
   int32_t stw[STW_N];
   HIPCHECK(h, hipMemcpy(stw, A.status, sizeof(stw), hipMemcpyDeviceToHost));
   if (stw[STW_FLAGS] & (ST_BAD_TYPE | ST_NONFINITE | ST_OVERLAP | ST_GHOST_CAP | ST_CAPACITY))
-    return dp_status(h, workspace, stream, nullptr, nullptr);
+    return dp_status(h, workspace, st, nullptr, nullptr);
   PGradArgs G{};
   G.m = A.m;
   G.nrows = nrows;

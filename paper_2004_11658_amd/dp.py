@@ -67,8 +67,8 @@ def _load():
         "dp_profile_stages": ([P, C.c_uint32], C.c_int),
         "dp_set_params": ([P, P, P], C.c_int),
         "dp_get_params": ([P, P, P], C.c_int),
-        "dp_param_grad_workspace_size": ([P, I32, P, P, P], C.c_int),
-        "dp_param_grad": ([P, I32, P, P, P, P, P, P, P, P, SZ, P], C.c_int),
+        "dp_param_grad_workspace_size": ([P, I32, P, P, I64, P], C.c_int),
+        "dp_param_grad": ([P, I32, P, P, P, P, P, P, P, I64, P, SZ, P], C.c_int),
         "dp_student_samples_workspace_size": ([P, I64, P, P], C.c_int),
         "dp_student_samples": ([P, I32, I32, I64, P, P, P, P, D, P, I64, P, P, SZ, P], C.c_int),
         "dp_embed_eval": ([P, I32, I32, I64, P, P, P], C.c_int),
@@ -128,6 +128,7 @@ class DPModel:
         self.ntypes, self.nm, self.M, self.m2 = nt.value, nm.value, M.value, m2.value
         self.rc, self.nparams = rcut.value, npar.value
         self._ws = None
+        self._pg_ws = None    # parameter-gradient workspace (reused between calls)
         self.device = torch.device("cuda", torch.cuda.current_device())
         # the weight region is caller memory: a torch buffer the library lays its layouts in
         nb = C.c_size_t()
@@ -418,8 +419,10 @@ class DPModel:
         assert th.numel() == self.nparams
         self._check(_lib.dp_set_params(self.h, _ptr(th), _stream()))
 
-    def param_grad(self, coords, types, offsets, boxes, gE, gF, max_atoms: int = 8192) -> torch.Tensor:
-        """sum_f gE_f dE_f/dtheta + sum_i gF_i . dF_i/dtheta for a ragged batch (FP64)."""
+    def param_grad(self, coords, types, offsets, boxes, gE, gF, max_atoms: int = 0) -> torch.Tensor:
+        """sum_f gE_f dE_f/dtheta + sum_i gF_i . dF_i/dtheta for a ragged batch (FP64); the
+        library splits the batch into chunks of whole frames of at most max_atoms atoms
+        (0: its default)."""
         x = self._dev(coords, torch.float64)
         t = self._dev(types, torch.int32)
         off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -428,24 +431,15 @@ class DPModel:
         gE = self._dev(gE, torch.float64).reshape(nf)
         gF = self._dev(gF, torch.float64).reshape(-1, 3)
         gt = torch.zeros(self.nparams, dtype=torch.float64, device=x.device)
-        f0 = 0
-        while f0 < nf:                      # frames in chunks of at most max_atoms atoms
-            f1 = f0 + 1
-            while f1 < nf and off[f1 + 1] - off[f0] <= max_atoms:
-                f1 += 1
-            sub = np.ascontiguousarray(off[f0:f1 + 1] - off[f0])
-            a0, a1 = int(off[f0]), int(off[f1])
-            bb = np.ascontiguousarray(b[f0:f1])
-            nb = C.c_size_t()
-            self._check(_lib.dp_param_grad_workspace_size(self.h, f1 - f0, sub.ctypes.data_as(C.c_void_p),
-                                                          bb.ctypes.data_as(C.c_void_p), C.byref(nb)))
-            ws = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
-            xs, ts = x[a0:a1].contiguous(), t[a0:a1].contiguous()
-            gEs, gFs = gE[f0:f1].contiguous(), gF[a0:a1].contiguous()
-            self._check(_lib.dp_param_grad(self.h, f1 - f0, sub.ctypes.data_as(C.c_void_p), _ptr(xs), _ptr(ts),
-                                           bb.ctypes.data_as(C.c_void_p), _ptr(gEs), _ptr(gFs), _ptr(gt),
-                                           _ptr(ws), ws.numel(), _stream()))
-            f0 = f1
+        nb = C.c_size_t()
+        self._check(_lib.dp_param_grad_workspace_size(self.h, nf, off.ctypes.data_as(C.c_void_p),
+                                                      b.ctypes.data_as(C.c_void_p), int(max_atoms), C.byref(nb)))
+        if self._pg_ws is None or self._pg_ws.numel() < nb.value:
+            self._pg_ws = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
+        ws = self._pg_ws
+        self._check(_lib.dp_param_grad(self.h, nf, off.ctypes.data_as(C.c_void_p), _ptr(x), _ptr(t),
+                                       b.ctypes.data_as(C.c_void_p), _ptr(gE), _ptr(gF), _ptr(gt), int(max_atoms),
+                                       _ptr(ws), ws.numel(), _stream()))
         return gt
 
 

@@ -120,8 +120,8 @@ def test_param_grad_finite_differences(dp, tiny_model):
 
 
 def test_param_grad_chunked_calls_match_oracle(dp, water_model):
-    """The ragged batch split across several dp_param_grad calls (max_atoms below the
-    batch size: every frame its own call here) gives the oracle's gradient."""
+    """The ragged batch split by the library into several chunks (max_atoms the largest
+    frame: every frame a chunk of its own here) gives the oracle's gradient."""
     import torch
     frames = _frames("water")
     o = Oracle(water_model)
