@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdp.so")
-SOURCES = ["dp_api.cpp", "nlist.hip", "embed.hip", "fit.hip", "fit_bf.hip", "md.hip", "pgrad.hip", "student.hip", "student_infer.hip", "student_embed.hip", "scatter.hip", "noalloc.hip"]
+SOURCES = ["dp_api.cpp", "nlist.hip", "embed.hip", "fit.hip", "fit_bf.hip", "md.hip", "pgrad.hip", "pgrad_fused.hip", "student.hip", "student_infer.hip", "student_embed.hip", "scatter.hip", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

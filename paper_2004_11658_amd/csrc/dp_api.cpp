@@ -49,6 +49,7 @@ struct dp_handle_s {
   size_t fitb_elems = 0;
   // host copies of the index maps and layout offsets (built at dp_init, copied by dp_upload)
   std::vector<int> h_nmap, h_fmap, h_bmap, h_bomap;
+  std::vector<int> h_pgmap;   // FP64 position-packed nets <- theta (the parameter gradient's)
   std::vector<int64_t> h_noff;
   std::vector<size_t> h_offW, h_offB, h_offO, h_offWb, h_offWf;
   // student embedding nets (blocks and index map in a caller-owned buffer)
@@ -331,6 +332,8 @@ static void plan_weights(dp_handle h) {
     if (bf) bnet_block_map(h, P, net, parts, nmap.data() + (size_t)net * blk_units);
     else net_block_map(h, P, net, nmap.data() + (size_t)net * blk_units);
   }
+  h->h_pgmap.assign((size_t)nnet * kNetElems, -1);
+  for (int net = 0; net < nnet; net++) net_block_map(h, P, net, h->h_pgmap.data() + (size_t)net * kNetElems);
   // BF16 GEMM operands per species and layer: W^T [out][in] then W [in][out], each as
   // hi and lo parts, every group padded to a multiple of 8 units (16-byte rows)
   std::vector<int> bmap;
@@ -1391,7 +1394,7 @@ int dp_get_params(dp_handle h, double* theta, void* stream) {
 }
 
 struct PGLayout {
-  size_t o_base, o_sums, o_ptrs, o_gtan, o_scr, scr_bytes, total;
+  size_t o_base, o_sums, o_pgmap, o_pgnets, o_gtan, o_scr, scr_bytes, total;
   long np_max;
 };
 
@@ -1401,7 +1404,8 @@ static PGLayout pg_layout(dp_handle h, const Plan& P) {
   auto take = [&](size_t bytes) { size_t r = o; o = al(o + bytes); return r; };
   L.o_base = take(sizeof(int) * (size_t)h->ntypes * (P.nrows + 1));
   L.o_sums = take(sizeof(int) * (scan_sums_ints(P.nrows + 1, 1) + 16));
-  L.o_ptrs = take(sizeof(void*) * kMaxTypes + sizeof(int) * kMaxTypes);
+  L.o_pgmap = take(sizeof(int) * h->h_pgmap.size());        // FP64 position-packed nets <- theta
+  L.o_pgnets = take(sizeof(double) * h->h_pgmap.size());
   L.o_gtan = take(sizeof(double) * h->nparams);
   L.np_max = (long)P.n * h->nm;
   L.scr_bytes = param_grad_scratch_bytes(P.nrows, L.np_max, h->M, h->m2, h->s0, h->fit_w[0], h->n_fit);
@@ -1525,12 +1529,13 @@ static int param_grad_chunk(dp_handle h, int32_t nframes, const int64_t* atom_of
       G.group[(a * nt + b) * 2 + 1] = bb[tr0[a + 1]] - bb[tr0[a]];
     }
   for (int t = 0; t <= nt; t++) G.type_row0_h[t] = tr0[t];
-  // device copies of the base pointers and offsets
-  char* pt = W.at<char>(L.o_ptrs);
-  HIPCHECK(h, hipMemcpy(pt, G.base, sizeof(void*) * kMaxTypes, hipMemcpyHostToDevice));
-  HIPCHECK(h, hipMemcpy(pt + sizeof(void*) * kMaxTypes, G.boff, sizeof(int) * kMaxTypes, hipMemcpyHostToDevice));
-  G.base_dev = (const int* const*)pt;
-  G.boff_dev = (const int*)(pt + sizeof(void*) * kMaxTypes);
+  // the embedding nets in FP64 at the force path's positions, whatever the precision option
+  int* pgmap = W.at<int>(L.o_pgmap);
+  double* pgnets = W.at<double>(L.o_pgnets);
+  HIPCHECK(h, hipMemcpyAsync(pgmap, h->h_pgmap.data(), sizeof(int) * h->h_pgmap.size(), hipMemcpyHostToDevice, st));
+  launch_scatter_params(0, h->h_pgmap.size(), pgmap, h->d_theta, pgnets, st);
+  G.nets = pgnets;
+  G.type_row0 = A.type_row0;
   ParamIndex PI = index_params(h);
   G.eW = PI.eW.data();
   G.eB = PI.eB.data();

@@ -198,14 +198,35 @@ struct PGradArgs {
   const int* frame_of;
   const int* base[kMaxTypes];  // per neighbour species: exclusive scan over rows [nrows+1]
   int boff[kMaxTypes];         // first pair row of each neighbour-species block
-  const int* const* base_dev;  // device copies of base[] and boff[]
-  const int* boff_dev;
   int group[2 * kMaxTypes * kMaxTypes];  // (first pair row, count) per species pair
   int type_row0_h[kMaxTypes + 1];
   const int64_t *eW, *eB, *fW, *fB;      // parameter offsets (host)
+  const double* nets;                    // FP64 position-packed embedding nets (device)
+  const int* type_row0;                  // species row groups (device)
   void* scratch;
   size_t scratch_bytes;
 };
+// fused embedding passes of the parameter gradient (pgrad_fused.hip): one wave per centre
+struct PgfArgs {
+  ModelC m;
+  int nrows;
+  const int* type_row0;
+  const int* row_atom;
+  const int* nnei;
+  const int* nlist;
+  const int* eown;
+  const double* xe;
+  const double* vdir;          // tangent direction of the coordinates [n][3]
+  const double* nets;          // FP64 position-packed nets [ntypes^2][kNetElems]
+  double *Tm, *Tmd;            // pass 1 out: T and its tangent [nrows][M][4]
+  const double *gTm, *gTmd;    // pass 2 in: dE/dT and its tangent [nrows][M][4]
+  const int* base[kMaxTypes];  // per neighbour species: exclusive scan of the rows' counts
+  int boff[kMaxTypes];         // first pair index of each neighbour-species block
+  // pass 2 out, per pair (feature order): layer inputs and pre-activation adjoints with tangents
+  double *X0, *X0d, *X1, *X1d, *P0, *P0d, *P1, *P1d, *P2, *P2d, *S, *Sd;
+};
+void launch_pgf_fwd(const PgfArgs& a, hipStream_t st);
+void launch_pgf_bwd(const PgfArgs& a, hipStream_t st);
 size_t param_grad_scratch_bytes(int nrows, long np_max, int M, int m2, int s0, int fw, int nfit);
 int launch_param_grad(const PGradArgs& a, hipStream_t st);
 void launch_pair_scan(int nrows, int ntypes, int beta, const int* row_atom, const int* nnei, int* base,

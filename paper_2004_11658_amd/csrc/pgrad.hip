@@ -9,11 +9,13 @@
 // of the resulting parameter adjoint equals d_gF dE/dtheta - sum_f gE_f dE_f/dtheta,
 // so g_theta = -(tangent part).
 //
-// Unlike the force path, this path stores the per-neighbour activations of the
-// embedding nets (grouped by species pair) so that the weight gradients become GEMMs
-// over the neighbour rows (dW = X^T P).  All arithmetic is FP64.  GEMMs run on the
-// FP64 16x16x4 MFMA; long reductions over rows are split across workgroups and summed
-// with FP64 atomics.
+// The embedding nets run in two fused passes (pgrad_fused.hip): the forward with
+// tangents straight into T, and after the fitting net the reverse chain, which recomputes
+// the activations and writes per neighbour row only the operands of the weight gradients
+// (layer inputs and pre-activation adjoints with their tangents), so that those become
+// products over the rows (dW = X^T P).  The fitting net is per centre (row-major
+// activations, GEMMs).  All arithmetic is FP64.  GEMMs run on the FP64 16x16x4 MFMA;
+// long reductions over rows are split across workgroups and summed with FP64 atomics.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -144,65 +146,6 @@ static void pg_zero(double* p, size_t n, hipStream_t st) {
   if (n) hipLaunchKernelGGL(k_pg_zero, dim3((n + 255) / 256), dim3(256), 0, st, n, p);
 }
 
-// pair rows of each centre: for species block beta, rows [base[row], base[row] + nnei)
-__global__ void k_pg_pairs(int nrows, int ntypes, int nm, int beta, int sel_off,
-                           const int* __restrict__ row_atom, const int* __restrict__ nnei,
-                           const int* __restrict__ nlist, const int* __restrict__ base, int off,
-                           int* __restrict__ p_row, int* __restrict__ p_e) {
-  int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= nrows) return;
-  int atom = row_atom[row];
-  if (atom < 0) return;
-  int nn = nnei[atom * ntypes + beta];
-  int b = off + base[row];
-  for (int k = 0; k < nn; k++) {
-    p_row[b + k] = row;
-    p_e[b + k] = nlist[(size_t)atom * nm + sel_off + k];
-  }
-}
-
-// environment rows with tangents: R, dR = (dR/dd) (v_j - v_i); S = R[0]
-__global__ void k_pg_env(int np, ModelC m, const int* __restrict__ p_row, const int* __restrict__ p_e,
-                         const int* __restrict__ row_atom, const int* __restrict__ eown,
-                         const double* __restrict__ xe, const double* __restrict__ vdir,
-                         double* __restrict__ R, double* __restrict__ Rd) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np) return;
-  int i = row_atom[p_row[p]], e = p_e[p];
-  double d[3], dd[3];
-  int own = eown[e];
-  for (int c = 0; c < 3; c++) {
-    d[c] = xe[3 * e + c] - xe[3 * i + c];
-    dd[c] = vdir[3 * own + c] - vdir[3 * i + c];
-  }
-  double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-  double s, ds;
-  smooth_fn(m, r, s, ds);
-  double ir = 1.0 / r, sr = s * ir;
-  double dot = (d[0] * dd[0] + d[1] * dd[1] + d[2] * dd[2]) * ir;  // dr along the tangent
-  double qf = (ds * ir - s * ir * ir);                               // d(s/r)/dr
-  R[4 * p] = s;
-  Rd[4 * p] = ds * dot;
-  for (int c = 0; c < 3; c++) {
-    R[4 * p + 1 + c] = sr * d[c];
-    Rd[4 * p + 1 + c] = qf * dot * d[c] + sr * dd[c];
-  }
-}
-
-// first embedding layer: X0 = tanh(s W0 + b0), dX0 = (1 - X0^2) ds W0
-__global__ void k_pg_l0(int np, int s0, const double* __restrict__ R, const double* __restrict__ Rd,
-                        const double* __restrict__ W0, const double* __restrict__ b0,
-                        double* __restrict__ X0, double* __restrict__ X0d) {
-  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (size_t)np * s0) return;
-  size_t p = q / s0;
-  int j = (int)(q % s0);
-  double s = R[4 * p], sd = Rd[4 * p];
-  double t = dp_tanh(s * W0[j] + b0[j]);
-  X0[q] = t;
-  X0d[q] = (1.0 - t * t) * sd * W0[j];
-}
-
 // y = skip(x) + tanh(z + b) with tangents; z, zd hold x W and dx W on entry and
 // receive t and dt.  skip: 0 none, 1 identity, 2 concat (x, x).  xo/xod may be null.
 __global__ void k_pg_act(size_t rows, int nin, int nout, int skip, const double* __restrict__ bias,
@@ -223,42 +166,6 @@ __global__ void k_pg_act(size_t rows, int nin, int nout, int skip, const double*
     else if (skip == 2) { sv = x[r * nin + j % nin]; sd = xd[r * nin + j % nin]; }
     xo[q] = sv + t;
     xod[q] = sd + td;
-  }
-}
-
-// T = sum over a centre's pair rows of G R / N_m (and tangent), G = (X1, X1) + T2
-__global__ __launch_bounds__(256) void k_pg_contract(int nrows, int ntypes, int M, double inv_norm,
-                                                     const int* __restrict__ row_atom,
-                                                     const int* __restrict__ nnei,
-                                                     const int* const* __restrict__ base,
-                                                     const int* __restrict__ boff,
-                                                     const double* __restrict__ X1,
-                                                     const double* __restrict__ X1d,
-                                                     const double* __restrict__ T2,
-                                                     const double* __restrict__ T2d,
-                                                     const double* __restrict__ R,
-                                                     const double* __restrict__ Rd,
-                                                     double* __restrict__ T, double* __restrict__ Td) {
-  const int row = blockIdx.x;
-  const int atom = row_atom[row];
-  const int s1 = M / 2;
-  for (int q = threadIdx.x; q < M * 4; q += blockDim.x) {
-    int a = q >> 2, c = q & 3;
-    double v = 0.0, vd = 0.0;
-    if (atom >= 0)
-      for (int beta = 0; beta < ntypes; beta++) {
-        int nn = nnei[atom * ntypes + beta];
-        size_t p0 = (size_t)boff[beta] + base[beta][row];
-        for (int k = 0; k < nn; k++) {
-          size_t p = p0 + k;
-          double G = X1[p * s1 + a % s1] + T2[p * M + a];
-          double Gd = X1d[p * s1 + a % s1] + T2d[p * M + a];
-          v += G * R[4 * p + c];
-          vd += Gd * R[4 * p + c] + G * Rd[4 * p + c];
-        }
-      }
-    T[(size_t)row * M * 4 + q] = v * inv_norm;
-    Td[(size_t)row * M * 4 + q] = vd * inv_norm;
   }
 }
 
@@ -387,48 +294,6 @@ __global__ __launch_bounds__(256) void k_pg_desc_bwd(int M, int m2, const double
   }
 }
 
-// per pair row: dE/dG = dT R / N_m (with tangent); writes the concat-skip part of
-// dE/dX1 (G = (X1, X1) + T2) and P2 = dE/dG (1 - T2^2) with its tangent
-__global__ void k_pg_gbar(size_t np, int M, double inv_norm, const int* __restrict__ p_row,
-                          const double* __restrict__ gT, const double* __restrict__ gTd,
-                          const double* __restrict__ R, const double* __restrict__ Rd,
-                          const double* __restrict__ T2, const double* __restrict__ T2d,
-                          double* __restrict__ P2, double* __restrict__ P2d, double* __restrict__ X1b,
-                          double* __restrict__ X1bd) {
-  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int s1 = M / 2;
-  if (q >= np * s1) return;
-  size_t p = q / s1;
-  int a = (int)(q % s1);
-  size_t row = p_row[p];
-  const double* r = R + 4 * p;
-  const double* rd = Rd + 4 * p;
-  double sk = 0.0, skd = 0.0;
-  for (int h = 0; h < 2; h++) {
-    int f = a + h * s1;
-    const double* g = gT + row * M * 4 + f * 4;
-    const double* gd = gTd + row * M * 4 + f * 4;
-    double v = 0.0, vd = 0.0;
-    for (int c = 0; c < 4; c++) {
-      v += g[c] * r[c];
-      vd += gd[c] * r[c] + g[c] * rd[c];
-    }
-    v *= inv_norm;
-    vd *= inv_norm;
-    sk += v;
-    skd += vd;
-    double t = T2[p * M + f], td = T2d[p * M + f];
-    double u = 1.0 - t * t;
-    P2[p * M + f] = v * u;
-    P2d[p * M + f] = vd * u - 2.0 * v * t * td;
-  }
-  X1b[p * s1 + a] = sk;
-  X1bd[p * s1 + a] = skd;
-}
-
-// first-layer weight gradient (tangent): gW0[j] += sum_r (S dP0 + dS P0); S = R[0]
-// handled by k_pg_colsum with weights taken from R (stride 4)
-
 // ------------------------------------------------------------------------------------
 // orchestration
 // ------------------------------------------------------------------------------------
@@ -436,9 +301,10 @@ static size_t pgal(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t param_grad_scratch_bytes(int nrows, long np_max, int M, int m2, int s0, int fw, int nfit) {
   int s1 = 2 * s0;
-  size_t per_pair = 8 + 8 + 2 * s0 + 2 * s0 + 2 * s1 + 2 * s1 + 2 * M + 2 * M + 2 * s1 + 2 * s0;
-  size_t per_row = 8 * M + 4 * M * m2 + (size_t)nfit * 6 * fw + 4 * fw + 8 * M;
-  return pgal(sizeof(int) * 2 * np_max) + pgal(sizeof(double) * per_pair * np_max) +
+  // per pair: X0, X0d, P0, P0d (s0), X1, X1d, P1, P1d (s1), P2, P2d (M), S, Sd
+  size_t per_pair = 4 * (size_t)s0 + 4 * (size_t)s1 + 2 * (size_t)M + 2;
+  size_t per_row = 8 * M + 4 * M * m2 + (size_t)nfit * 6 * fw + 4 * fw;
+  return 12 * pgal(0) + pgal(sizeof(double) * per_pair * np_max) + 12 * 256 +
          pgal(sizeof(double) * per_row * nrows) + 65536;
 }
 
@@ -450,24 +316,33 @@ int launch_param_grad(const PGradArgs& G, hipStream_t st) {
   double* gt = G.gtheta_tan;
   char* w = (char*)G.scratch;
   auto take = [&](size_t bytes) { char* p = w; w += pgal(bytes); return p; };
-  int* p_row = (int*)take(sizeof(int) * np);
-  int* p_e = (int*)take(sizeof(int) * np);
-  double* R = (double*)take(sizeof(double) * 4 * np);
-  double* Rd = (double*)take(sizeof(double) * 4 * np);
-  double* X0 = (double*)take(sizeof(double) * s0 * np);
-  double* X0d = (double*)take(sizeof(double) * s0 * np);
-  double* T1 = (double*)take(sizeof(double) * s1 * np);
-  double* T1d = (double*)take(sizeof(double) * s1 * np);
-  double* X1 = (double*)take(sizeof(double) * s1 * np);
-  double* X1d = (double*)take(sizeof(double) * s1 * np);
-  double* T2 = (double*)take(sizeof(double) * M * np);
-  double* T2d = (double*)take(sizeof(double) * M * np);
-  double* P2 = (double*)take(sizeof(double) * M * np);
-  double* P2d = (double*)take(sizeof(double) * M * np);
-  double* X1b = (double*)take(sizeof(double) * s1 * np);
-  double* X1bd = (double*)take(sizeof(double) * s1 * np);
-  double* X0b = (double*)take(sizeof(double) * s0 * np);
-  double* X0bd = (double*)take(sizeof(double) * s0 * np);
+  PgfArgs F{};
+  F.m = m;
+  F.nrows = nrows;
+  F.type_row0 = G.type_row0;
+  F.row_atom = G.row_atom;
+  F.nnei = G.nnei;
+  F.nlist = G.nlist;
+  F.eown = G.eown;
+  F.xe = G.xe;
+  F.vdir = G.vdir;
+  F.nets = G.nets;
+  for (int b = 0; b < kMaxTypes; b++) {
+    F.base[b] = G.base[b];
+    F.boff[b] = G.boff[b];
+  }
+  F.X0 = (double*)take(sizeof(double) * s0 * (size_t)np);
+  F.X0d = (double*)take(sizeof(double) * s0 * (size_t)np);
+  F.P0 = (double*)take(sizeof(double) * s0 * (size_t)np);
+  F.P0d = (double*)take(sizeof(double) * s0 * (size_t)np);
+  F.X1 = (double*)take(sizeof(double) * s1 * (size_t)np);
+  F.X1d = (double*)take(sizeof(double) * s1 * (size_t)np);
+  F.P1 = (double*)take(sizeof(double) * s1 * (size_t)np);
+  F.P1d = (double*)take(sizeof(double) * s1 * (size_t)np);
+  F.P2 = (double*)take(sizeof(double) * M * (size_t)np);
+  F.P2d = (double*)take(sizeof(double) * M * (size_t)np);
+  F.S = (double*)take(sizeof(double) * (size_t)np);
+  F.Sd = (double*)take(sizeof(double) * (size_t)np);
   size_t rs = nrows;
   double* Tm = (double*)take(sizeof(double) * rs * M * 4);
   double* Tmd = (double*)take(sizeof(double) * rs * M * 4);
@@ -487,43 +362,10 @@ int launch_param_grad(const PGradArgs& G, hipStream_t st) {
   double* xb2d = (double*)take(sizeof(double) * rs * fw);
   if ((size_t)(w - (char*)G.scratch) > G.scratch_bytes) return -1;
 
-  // 1. pair rows, grouped by neighbour species beta, then by centre species (row order)
-  for (int beta = 0; beta < nt; beta++)
-    hipLaunchKernelGGL(k_pg_pairs, dim3((nrows + 255) / 256), dim3(256), 0, st, nrows, nt, m.nm, beta,
-                       m.sel_off[beta], G.row_atom, G.nnei, G.nlist, G.base[beta], G.boff[beta], p_row, p_e);
-  hipLaunchKernelGGL(k_pg_env, dim3((np + 255) / 256), dim3(256), 0, st, np, m, p_row, p_e, G.row_atom,
-                     G.eown, G.xe, G.vdir, R, Rd);
-  // 2. embedding forward with tangents, per species pair group
-  for (int a = 0; a < nt; a++)
-    for (int b = 0; b < nt; b++) {
-      int g0 = G.group[(a * nt + b) * 2], ng = G.group[(a * nt + b) * 2 + 1];
-      if (ng <= 0) continue;
-      const double* W0 = th + G.eW[(a * nt + b) * 3 + 0];
-      const double* B0 = th + G.eB[(a * nt + b) * 3 + 0];
-      const double* W1 = th + G.eW[(a * nt + b) * 3 + 1];
-      const double* B1 = th + G.eB[(a * nt + b) * 3 + 1];
-      const double* W2 = th + G.eW[(a * nt + b) * 3 + 2];
-      const double* B2 = th + G.eB[(a * nt + b) * 3 + 2];
-      size_t o0 = (size_t)g0 * s0, o1 = (size_t)g0 * s1, o2 = (size_t)g0 * M;
-      hipLaunchKernelGGL(k_pg_l0, dim3(((size_t)ng * s0 + 255) / 256), dim3(256), 0, st, ng, s0, R + 4 * (size_t)g0,
-                         Rd + 4 * (size_t)g0, W0, B0, X0 + o0, X0d + o0);
-      pg_zero(T1 + o1, (size_t)ng * s1, st);
-      pg_zero(T1d + o1, (size_t)ng * s1, st);
-      pg_gemm(0, 0, ng, s1, s0, X0 + o0, s0, W1, s1, T1 + o1, s1, st);
-      pg_gemm(0, 0, ng, s1, s0, X0d + o0, s0, W1, s1, T1d + o1, s1, st);
-      hipLaunchKernelGGL(k_pg_act, dim3(((size_t)ng * s1 + 255) / 256), dim3(256), 0, st, (size_t)ng, s0, s1, 2, B1,
-                         X0 + o0, X0d + o0, T1 + o1, T1d + o1, X1 + o1, X1d + o1);
-      pg_zero(T2 + o2, (size_t)ng * M, st);
-      pg_zero(T2d + o2, (size_t)ng * M, st);
-      pg_gemm(0, 0, ng, M, s1, X1 + o1, s1, W2, M, T2 + o2, M, st);
-      pg_gemm(0, 0, ng, M, s1, X1d + o1, s1, W2, M, T2d + o2, M, st);
-      hipLaunchKernelGGL(k_pg_act, dim3(((size_t)ng * M + 255) / 256), dim3(256), 0, st, (size_t)ng, s1, M, 2, B2,
-                         (const double*)nullptr, (const double*)nullptr, T2 + o2, T2d + o2, (double*)nullptr,
-                         (double*)nullptr);
-    }
-  // 3. contraction and descriptor (with tangents)
-  hipLaunchKernelGGL(k_pg_contract, dim3(nrows), dim3(256), 0, st, nrows, nt, M, m.inv_norm, G.row_atom, G.nnei,
-                     G.base_dev, G.boff_dev, X1, X1d, T2, T2d, R, Rd, Tm, Tmd);
+  // 1-3. T and its tangent per centre (fused embedding forward), then D = T T<^T
+  F.Tm = Tm;
+  F.Tmd = Tmd;
+  launch_pgf_fwd(F, st);
   hipLaunchKernelGGL(k_pg_desc, dim3(((size_t)nrows * K1 + 255) / 256), dim3(256), 0, st, nrows, M, m2, Tm, Tmd, D, Dd);
   // 4. fitting net per species: forward with tangents, reverse with dual seeds
   const int nf = G.nfit;
@@ -597,16 +439,16 @@ int launch_param_grad(const PGradArgs& G, hipStream_t st) {
   }
   // 5. dE/dT with tangents
   hipLaunchKernelGGL(k_pg_desc_bwd, dim3(nrows), dim3(256), 0, st, M, m2, Tm, Tmd, Dg, Dgd, gTm, gTmd);
-  // 6. embedding reverse per species pair group
-  hipLaunchKernelGGL(k_pg_gbar, dim3(((size_t)np * s1 + 255) / 256), dim3(256), 0, st, (size_t)np, M, m.inv_norm,
-                     p_row, gTm, gTmd, R, Rd, T2, T2d, P2, P2d, X1b, X1bd);
+  // 6. embedding reverse (fused: the per-pair operands of the weight gradients), then the
+  // weight gradients as products over the pair rows of each species pair
+  F.gTm = gTm;
+  F.gTmd = gTmd;
+  launch_pgf_bwd(F, st);
   for (int a = 0; a < nt; a++)
     for (int b = 0; b < nt; b++) {
       int g0 = G.group[(a * nt + b) * 2], ng = G.group[(a * nt + b) * 2 + 1];
       if (ng <= 0) continue;
       int net = a * nt + b;
-      const double* W1 = th + G.eW[net * 3 + 1];
-      const double* W2 = th + G.eW[net * 3 + 2];
       double* gW0 = gt + G.eW[net * 3 + 0];
       double* gB0 = gt + G.eB[net * 3 + 0];
       double* gW1 = gt + G.eW[net * 3 + 1];
@@ -614,27 +456,17 @@ int launch_param_grad(const PGradArgs& G, hipStream_t st) {
       double* gW2 = gt + G.eW[net * 3 + 2];
       double* gB2 = gt + G.eB[net * 3 + 2];
       size_t o0 = (size_t)g0 * s0, o1 = (size_t)g0 * s1, o2 = (size_t)g0 * M;
-      // layer 2: gW2 += X1^T dP2 + dX1^T P2; gB2 += sum dP2; X1b += P2 W2^T
-      pg_gemm(1, 0, s1, M, ng, X1 + o1, s1, P2d + o2, M, gW2, M, st);
-      pg_gemm(1, 0, s1, M, ng, X1d + o1, s1, P2 + o2, M, gW2, M, st);
-      pg_colsum((size_t)ng, M, P2d + o2, nullptr, nullptr, nullptr, 0, gB2, st);
-      pg_gemm(0, 1, ng, s1, M, P2 + o2, M, W2, M, X1b + o1, s1, st);
-      pg_gemm(0, 1, ng, s1, M, P2d + o2, M, W2, M, X1bd + o1, s1, st);
-      // layer 1: skip to X0b, damp, gradients, X0b += P1 W1^T
-      hipLaunchKernelGGL(k_pg_skip, dim3(((size_t)ng * s0 + 255) / 256), dim3(256), 0, st, (size_t)ng, s1, s0, 2,
-                         X1b + o1, X1bd + o1, X0b + o0, X0bd + o0);
-      hipLaunchKernelGGL(k_pg_damp, dim3(((size_t)ng * s1 + 255) / 256), dim3(256), 0, st, (size_t)ng * s1, X1b + o1,
-                         X1bd + o1, T1 + o1, T1d + o1);
-      pg_gemm(1, 0, s0, s1, ng, X0 + o0, s0, X1bd + o1, s1, gW1, s1, st);
-      pg_gemm(1, 0, s0, s1, ng, X0d + o0, s0, X1b + o1, s1, gW1, s1, st);
-      pg_colsum((size_t)ng, s1, X1bd + o1, nullptr, nullptr, nullptr, 0, gB1, st);
-      pg_gemm(0, 1, ng, s0, s1, X1b + o1, s1, W1, s1, X0b + o0, s0, st);
-      pg_gemm(0, 1, ng, s0, s1, X1bd + o1, s1, W1, s1, X0bd + o0, s0, st);
-      // layer 0: P0 = X0b (1 - X0^2); gW0 += sum (s dP0 + ds P0); gB0 += sum dP0
-      hipLaunchKernelGGL(k_pg_damp, dim3(((size_t)ng * s0 + 255) / 256), dim3(256), 0, st, (size_t)ng * s0, X0b + o0,
-                         X0bd + o0, X0 + o0, X0d + o0);
-      pg_colsum((size_t)ng, s0, X0bd + o0, R + 4 * (size_t)g0, X0b + o0, Rd + 4 * (size_t)g0, 4, gW0, st);
-      pg_colsum((size_t)ng, s0, X0bd + o0, nullptr, nullptr, nullptr, 0, gB0, st);
+      // layer 2: gW2 += X1^T dP2 + dX1^T P2; gB2 += sum dP2
+      pg_gemm(1, 0, s1, M, ng, F.X1 + o1, s1, F.P2d + o2, M, gW2, M, st);
+      pg_gemm(1, 0, s1, M, ng, F.X1d + o1, s1, F.P2 + o2, M, gW2, M, st);
+      pg_colsum((size_t)ng, M, F.P2d + o2, nullptr, nullptr, nullptr, 0, gB2, st);
+      // layer 1: gW1 += X0^T dP1 + dX0^T P1; gB1 += sum dP1
+      pg_gemm(1, 0, s0, s1, ng, F.X0 + o0, s0, F.P1d + o1, s1, gW1, s1, st);
+      pg_gemm(1, 0, s0, s1, ng, F.X0d + o0, s0, F.P1 + o1, s1, gW1, s1, st);
+      pg_colsum((size_t)ng, s1, F.P1d + o1, nullptr, nullptr, nullptr, 0, gB1, st);
+      // layer 0: gW0 += sum (s dP0 + ds P0); gB0 += sum dP0
+      pg_colsum((size_t)ng, s0, F.P0d + o0, F.S + g0, F.P0 + o0, F.Sd + g0, 1, gW0, st);
+      pg_colsum((size_t)ng, s0, F.P0d + o0, nullptr, nullptr, nullptr, 0, gB0, st);
     }
   return 0;
 }
