@@ -244,26 +244,48 @@ __global__ void k_pg_damp(size_t n, double* __restrict__ xb, double* __restrict_
 
 // column sums: out[j] += sum_r (a[r][j] * (wa ? wa[r*ws] : 1) + b[r][j] * (wb ? wb[r*ws] : 1))
 // (b may be null).  Used for bias gradients and the first embedding layer's weights.
-__global__ void k_pg_colsum(size_t rows, int N, const double* __restrict__ a, const double* __restrict__ wa,
-                            const double* __restrict__ b, const double* __restrict__ wb, int ws,
-                            double* __restrict__ out) {
-  int j = blockIdx.y * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  double acc = 0.0;
-  for (size_t r = blockIdx.x; r < rows; r += gridDim.x) {
-    double v = a[r * N + j] * (wa ? wa[r * ws] : 1.0);
-    if (b) v += b[r * N + j] * (wb ? wb[r * ws] : 1.0);
-    acc += v;
+// Block (x, y) takes columns 64 y .. 64 y + 63 and a contiguous range of per_block rows;
+// its four waves take every fourth row of the range with four independent partial sums
+// each, then add in wave order; one atomic per column and block.
+__global__ __launch_bounds__(256) void k_pg_colsum(size_t rows, size_t per_block, int N, const double* __restrict__ a,
+                                                   const double* __restrict__ wa, const double* __restrict__ b,
+                                                   const double* __restrict__ wb, int ws, double* __restrict__ out) {
+  __shared__ double sh[4][64];
+  const int c = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = blockIdx.y * 64 + c;
+  const size_t r0 = (size_t)blockIdx.x * per_block, r1 = r0 + per_block < rows ? r0 + per_block : rows;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (j < N) {
+    size_t r = r0 + wv;
+    for (; r + 12 < r1; r += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const size_t q = r + 4 * u;
+        double v = a[q * N + j] * (wa ? wa[q * ws] : 1.0);
+        if (b) v += b[q * N + j] * (wb ? wb[q * ws] : 1.0);
+        acc[u] += v;
+      }
+    }
+    for (; r < r1; r += 4) {
+      double v = a[r * N + j] * (wa ? wa[r * ws] : 1.0);
+      if (b) v += b[r * N + j] * (wb ? wb[r * ws] : 1.0);
+      acc[0] += v;
+    }
   }
-  unsafeAtomicAdd(&out[j], acc);
+  sh[wv][c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (wv == 0 && j < N) unsafeAtomicAdd(&out[j], ((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c]);
 }
 
 static void pg_colsum(size_t rows, int N, const double* a, const double* wa, const double* b,
                       const double* wb, int ws, double* out, hipStream_t st) {
   if (!rows || !N) return;
-  int by = (N + 63) / 64;
-  int bx = (int)std::min<size_t>(rows, 1024);
-  hipLaunchKernelGGL(k_pg_colsum, dim3(bx, by), dim3(64), 0, st, rows, N, a, wa, b, wb, ws, out);
+  const int by = (N + 63) / 64;
+  // about 1024 blocks in all (a few rows each for short sums), rows in multiples of 16
+  size_t per = (rows * by + 1023) / 1024;
+  per = per < 16 ? 16 : (per + 15) / 16 * 16;
+  const int bx = (int)((rows + per - 1) / per);
+  hipLaunchKernelGGL(k_pg_colsum, dim3(bx, by), dim3(256), 0, st, rows, per, N, a, wa, b, wb, ws, out);
 }
 
 // dT from dD (Eq. 4 adjoint) with tangents, one block per centre row
