@@ -252,7 +252,7 @@ int dp_get_params(dp_handle h, double* theta, void* stream);
  * to the energies and forces) and gtheta [nparams] device doubles (accumulated: zero
  * it first).  Computed exactly (forward-over-reverse, FP64, any precision option).
  * Batch arguments as dp_compute_batch.  The library runs the batch in chunks of whole
- * frames of at most max_atoms atoms together (0: 8192; a larger frame is a chunk of its
+ * frames of at most max_atoms atoms together (0: 32768; a larger frame is a chunk of its
  * own), so the workspace, dp_param_grad_workspace_size bytes for the same max_atoms,
  * is that of the largest chunk (roughly 8 KB per neighbour pair of it), whatever the
  * batch size.  Synchronises the stream once per chunk. */

@@ -1417,7 +1417,7 @@ static PGLayout pg_layout(dp_handle h, const Plan& P) {
 // The batch runs in chunks of whole frames, greedily packed up to max_atoms atoms (a
 // larger frame is a chunk of its own): the workspace holds the largest chunk's plan, so it
 // is bounded by the chunk size, not by the batch.
-static constexpr int64_t kPgChunkAtoms = 8192;
+static constexpr int64_t kPgChunkAtoms = 32768;
 
 static int pg_chunks(int32_t nframes, const int64_t* off, int64_t max_atoms,
                      const std::function<int(int32_t, int32_t)>& fn) {
@@ -1497,8 +1497,11 @@ static int param_grad_chunk(dp_handle h, int32_t nframes, const int64_t* atom_of
   const int nt = h->ntypes, nrows = P.nrows;
   int* base = W.at<int>(L.o_base);
   int* sums = W.at<int>(L.o_sums);
+  // the scans' totals go after their block sums (scan_sums_ints ints, one per block of a
+  // multi-block scan): totals inside that range would overwrite a block's prefix
+  int* totals = sums + scan_sums_ints(nrows + 1, 1) + 8;
   for (int b = 0; b < nt; b++)
-    launch_pair_scan(nrows, nt, b, A.row_atom, A.nnei, base + (size_t)b * (nrows + 1), sums, sums + 8 + b, st);
+    launch_pair_scan(nrows, nt, b, A.row_atom, A.nnei, base + (size_t)b * (nrows + 1), sums, totals + b, st);
   HIPCHECK(h, hipGetLastError());
   // the pair-row groups size the GEMMs: read them back (one synchronisation)
   std::vector<int> hb((size_t)nt * (nrows + 1)), tr0(nt + 1);

@@ -200,3 +200,27 @@ def test_param_grad_whole_batch_finite_differences(dp, water_model, water_model_
         print("param", q, "fd", fd, "grad", g[q], flush=True)
         assert abs(fd - g[q]) <= 1e-5 * max(abs(g[q]), 1e-3 * gmax), (q, fd, g[q])
     m.set_params(theta0)
+
+
+def test_param_grad_large_chunks_match_default(dp, water_model):
+    """The 102k-atom ragged batch in chunks of up to 40,000 and of 102,435 atoms (pair
+    scans over more than 16,384 rows, which take the multi-block scan) against the default
+    8,192-atom chunks: the same gradient up to summation order."""
+    import torch
+    frames = I.ragged_water_batch(64, 204)
+    coords = np.concatenate([f[0] for f in frames])
+    types = np.concatenate([f[1] for f in frames]).astype(np.int32)
+    boxes = np.stack([f[2] for f in frames])
+    off = np.concatenate([[0], np.cumsum([len(f[1]) for f in frames])]).astype(np.int64)
+    m = dp.DPModel(water_model)
+    x = torch.as_tensor(coords, device="cuda")
+    t = torch.as_tensor(types, device="cuda")
+    gE = torch.linspace(0.5, 1.5, len(frames), dtype=torch.float64, device="cuda")
+    gF = torch.sin(torch.arange(3 * len(types), dtype=torch.float64, device="cuda")).reshape(-1, 3) * 0.1
+    g0 = m.param_grad(x, t, off, boxes, gE, gF).cpu().numpy()
+    for ma in (40000, int(off[-1])):
+        print("max_atoms", ma, flush=True)
+        g1 = m.param_grad(x, t, off, boxes, gE, gF, max_atoms=ma).cpu().numpy()
+        err = np.abs(g1 - g0).max() / np.abs(g0).max()
+        print("rel diff", err, flush=True)
+        assert err < 1e-12
