@@ -204,8 +204,8 @@ def test_param_grad_whole_batch_finite_differences(dp, water_model, water_model_
 
 def test_param_grad_large_chunks_match_default(dp, water_model):
     """The 102k-atom ragged batch in chunks of up to 40,000 and of 102,435 atoms (pair
-    scans over more than 16,384 rows, which take the multi-block scan) against the default
-    8,192-atom chunks: the same gradient up to summation order."""
+    scans over more than 16,384 rows, which take the multi-block scan) against chunks of
+    8,192 atoms (single-block scans): the same gradient up to summation order."""
     import torch
     frames = I.ragged_water_batch(64, 204)
     coords = np.concatenate([f[0] for f in frames])
@@ -217,7 +217,7 @@ def test_param_grad_large_chunks_match_default(dp, water_model):
     t = torch.as_tensor(types, device="cuda")
     gE = torch.linspace(0.5, 1.5, len(frames), dtype=torch.float64, device="cuda")
     gF = torch.sin(torch.arange(3 * len(types), dtype=torch.float64, device="cuda")).reshape(-1, 3) * 0.1
-    g0 = m.param_grad(x, t, off, boxes, gE, gF).cpu().numpy()
+    g0 = m.param_grad(x, t, off, boxes, gE, gF, max_atoms=8192).cpu().numpy()
     for ma in (40000, int(off[-1])):
         print("max_atoms", ma, flush=True)
         g1 = m.param_grad(x, t, off, boxes, gE, gF, max_atoms=ma).cpu().numpy()
