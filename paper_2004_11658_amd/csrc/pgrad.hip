@@ -323,8 +323,9 @@ static size_t pgal(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t param_grad_scratch_bytes(int nrows, long np_max, int M, int m2, int s0, int fw, int nfit) {
   int s1 = 2 * s0;
-  // per pair: X0, X0d, P0, P0d (s0), X1, X1d, P1, P1d (s1), P2, P2d (M), S, Sd
-  size_t per_pair = 4 * (size_t)s0 + 4 * (size_t)s1 + 2 * (size_t)M + 2;
+  // per pair: X0, X0d (s0 + 1), P0, P0d (s0), X1, X1d (s1 + 1), P1, P1d (s1), P2, P2d (M),
+  // S, Sd (2)
+  size_t per_pair = 4 * (size_t)s0 + 4 * (size_t)s1 + 2 * (size_t)M + 8;
   size_t per_row = 8 * M + 4 * M * m2 + (size_t)nfit * 6 * fw + 4 * fw;
   return 12 * pgal(0) + pgal(sizeof(double) * per_pair * np_max) + 12 * 256 +
          pgal(sizeof(double) * per_row * nrows) + 65536;
@@ -353,18 +354,18 @@ int launch_param_grad(const PGradArgs& G, hipStream_t st) {
     F.base[b] = G.base[b];
     F.boff[b] = G.boff[b];
   }
-  F.X0 = (double*)take(sizeof(double) * s0 * (size_t)np);
-  F.X0d = (double*)take(sizeof(double) * s0 * (size_t)np);
+  F.X0 = (double*)take(sizeof(double) * (s0 + 1) * (size_t)np);
+  F.X0d = (double*)take(sizeof(double) * (s0 + 1) * (size_t)np);
   F.P0 = (double*)take(sizeof(double) * s0 * (size_t)np);
   F.P0d = (double*)take(sizeof(double) * s0 * (size_t)np);
-  F.X1 = (double*)take(sizeof(double) * s1 * (size_t)np);
-  F.X1d = (double*)take(sizeof(double) * s1 * (size_t)np);
+  F.X1 = (double*)take(sizeof(double) * (s1 + 1) * (size_t)np);
+  F.X1d = (double*)take(sizeof(double) * (s1 + 1) * (size_t)np);
   F.P1 = (double*)take(sizeof(double) * s1 * (size_t)np);
   F.P1d = (double*)take(sizeof(double) * s1 * (size_t)np);
   F.P2 = (double*)take(sizeof(double) * M * (size_t)np);
   F.P2d = (double*)take(sizeof(double) * M * (size_t)np);
-  F.S = (double*)take(sizeof(double) * (size_t)np);
-  F.Sd = (double*)take(sizeof(double) * (size_t)np);
+  F.S = (double*)take(sizeof(double) * 2 * (size_t)np);
+  F.Sd = (double*)take(sizeof(double) * 2 * (size_t)np);
   size_t rs = nrows;
   double* Tm = (double*)take(sizeof(double) * rs * M * 4);
   double* Tmd = (double*)take(sizeof(double) * rs * M * 4);
@@ -471,24 +472,22 @@ int launch_param_grad(const PGradArgs& G, hipStream_t st) {
       int g0 = G.group[(a * nt + b) * 2], ng = G.group[(a * nt + b) * 2 + 1];
       if (ng <= 0) continue;
       int net = a * nt + b;
+      // (theta keeps each embedding layer's bias right after its weights: eB = eW + n_in n_out)
       double* gW0 = gt + G.eW[net * 3 + 0];
-      double* gB0 = gt + G.eB[net * 3 + 0];
       double* gW1 = gt + G.eW[net * 3 + 1];
-      double* gB1 = gt + G.eB[net * 3 + 1];
       double* gW2 = gt + G.eW[net * 3 + 2];
-      double* gB2 = gt + G.eB[net * 3 + 2];
       size_t o0 = (size_t)g0 * s0, o1 = (size_t)g0 * s1, o2 = (size_t)g0 * M;
-      // layer 2: gW2 += X1^T dP2 + dX1^T P2; gB2 += sum dP2
-      pg_gemm(1, 0, s1, M, ng, F.X1 + o1, s1, F.P2d + o2, M, gW2, M, st);
-      pg_gemm(1, 0, s1, M, ng, F.X1d + o1, s1, F.P2 + o2, M, gW2, M, st);
-      pg_colsum((size_t)ng, M, F.P2d + o2, nullptr, nullptr, nullptr, 0, gB2, st);
-      // layer 1: gW1 += X0^T dP1 + dX0^T P1; gB1 += sum dP1
-      pg_gemm(1, 0, s0, s1, ng, F.X0 + o0, s0, F.P1d + o1, s1, gW1, s1, st);
-      pg_gemm(1, 0, s0, s1, ng, F.X0d + o0, s0, F.P1 + o1, s1, gW1, s1, st);
-      pg_colsum((size_t)ng, s1, F.P1d + o1, nullptr, nullptr, nullptr, 0, gB1, st);
-      // layer 0: gW0 += sum (s dP0 + ds P0); gB0 += sum dP0
-      pg_colsum((size_t)ng, s0, F.P0d + o0, F.S + g0, F.P0 + o0, F.Sd + g0, 1, gW0, st);
-      pg_colsum((size_t)ng, s0, F.P0d + o0, nullptr, nullptr, nullptr, 0, gB0, st);
+      // the biases follow the weights in theta: the trailing column of the inputs (ones in
+      // the value, zeros in the tangent) turns row n_in of each product into the bias sum
+      // layer 2: [gW2; gB2] += [X1 1]^T dP2 + [dX1 0]^T P2
+      pg_gemm(1, 0, s1 + 1, M, ng, F.X1 + (size_t)g0 * (s1 + 1), s1 + 1, F.P2d + o2, M, gW2, M, st);
+      pg_gemm(1, 0, s1 + 1, M, ng, F.X1d + (size_t)g0 * (s1 + 1), s1 + 1, F.P2 + o2, M, gW2, M, st);
+      // layer 1: [gW1; gB1] += [X0 1]^T dP1 + [dX0 0]^T P1
+      pg_gemm(1, 0, s0 + 1, s1, ng, F.X0 + (size_t)g0 * (s0 + 1), s0 + 1, F.P1d + o1, s1, gW1, s1, st);
+      pg_gemm(1, 0, s0 + 1, s1, ng, F.X0d + (size_t)g0 * (s0 + 1), s0 + 1, F.P1 + o1, s1, gW1, s1, st);
+      // layer 0: [gW0; gB0] += [s 1]^T dP0 + [ds 0]^T P0
+      pg_gemm(1, 0, 2, s0, ng, F.S + 2 * (size_t)g0, 2, F.P0d + o0, s0, gW0, s0, st);
+      pg_gemm(1, 0, 2, s0, ng, F.Sd + 2 * (size_t)g0, 2, F.P0 + o0, s0, gW0, s0, st);
     }
   return 0;
 }

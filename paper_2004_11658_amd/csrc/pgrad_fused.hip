@@ -19,6 +19,7 @@
 //               (layer 2's adjoint accumulated tile by tile, the concatenation skips, the
 //               1 - tanh^2 factors and their tangents -2 t dt), writing per neighbour row
 //               only what the weight gradients need: the layer inputs X0 = t0, X1 = h1, s
+//               (each with a trailing column of ones, zeros in the tangent, for the biases)
 //               and the pre-activation adjoints P0, P1, P2, each with its tangent, in
 //               feature order.  The weight gradients are then plain products over the
 //               rows (launch_param_grad).
@@ -286,10 +287,13 @@ __global__ __launch_bounds__(64 * kPgfWaves) void k_pgf_bwd(PgfArgs A) {
       double t0[2][4], dt0[2][4], t1[4][4], dt1[4][4];
       pgf_l01(net, R[0], Rd[0], g, rb, t0, dt0, t1, dt1);
       if (valid) {
-        pgf_put(A.X0 + p * s0, s0, s0, 0, g, t0[0]);
-        pgf_put(A.X0 + p * s0, s0, s0, 1, g, t0[1]);
-        pgf_put(A.X0d + p * s0, s0, s0, 0, g, dt0[0]);
-        pgf_put(A.X0d + p * s0, s0, s0, 1, g, dt0[1]);
+        // layer inputs with a trailing column (1 for the value, 0 for the tangent): the
+        // weight-gradient products then also yield the bias gradients, which follow the
+        // weights in theta
+        pgf_put(A.X0 + p * (s0 + 1), s0, s0, 0, g, t0[0]);
+        pgf_put(A.X0 + p * (s0 + 1), s0, s0, 1, g, t0[1]);
+        pgf_put(A.X0d + p * (s0 + 1), s0, s0, 0, g, dt0[0]);
+        pgf_put(A.X0d + p * (s0 + 1), s0, s0, 1, g, dt0[1]);
 #pragma unroll
         for (int n = 0; n < 4; n++) {
           double h[4], hd[4];
@@ -298,12 +302,18 @@ __global__ __launch_bounds__(64 * kPgfWaves) void k_pgf_bwd(PgfArgs A) {
             h[q] = t0[n & 1][q] + t1[n][q];
             hd[q] = dt0[n & 1][q] + dt1[n][q];
           }
-          pgf_put(A.X1 + p * s1, s1, s0, n, g, h);
-          pgf_put(A.X1d + p * s1, s1, s0, n, g, hd);
+          pgf_put(A.X1 + p * (s1 + 1), s1, s0, n, g, h);
+          pgf_put(A.X1d + p * (s1 + 1), s1, s0, n, g, hd);
         }
         if (g == 0) {
-          A.S[p] = R[0];
-          A.Sd[p] = Rd[0];
+          A.X0[p * (s0 + 1) + s0] = 1.0;
+          A.X0d[p * (s0 + 1) + s0] = 0.0;
+          A.X1[p * (s1 + 1) + s1] = 1.0;
+          A.X1d[p * (s1 + 1) + s1] = 0.0;
+          A.S[2 * p] = R[0];
+          A.S[2 * p + 1] = 1.0;
+          A.Sd[2 * p] = Rd[0];
+          A.Sd[2 * p + 1] = 0.0;
         }
       }
       // dE/dh1 (layer 1's output) accumulated over the layer-2 tiles: the concatenation
