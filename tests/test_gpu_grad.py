@@ -30,6 +30,9 @@ def dp():
 def _frames(which):
     if which == "tiny":
         fr = [I.water_lattice(1, 3.2, 31), tiny_water(32, 2, 6.3), tiny_water(33, 2, 6.6)]
+    elif which == "copper":
+        # one species, first embedding width 32 (no pad positions), cells narrower than 2 rc
+        fr = [I.copper_fcc(3, 3.634, 41), I.copper_fcc(3, 3.70, 42)]
     else:
         allf = I.ragged_water_batch(64, 204)
         sizes = np.argsort([len(f[1]) for f in allf])
@@ -46,10 +49,10 @@ def _targets(o, frames, seed):
     return out
 
 
-@pytest.mark.parametrize("which", ["tiny", "water"])
-def test_param_grad_matches_oracle(dp, which, tiny_model, water_model):
+@pytest.mark.parametrize("which", ["tiny", "water", "copper"])
+def test_param_grad_matches_oracle(dp, which, tiny_model, water_model, copper_model):
     import torch
-    path = tiny_model if which == "tiny" else water_model
+    path = {"tiny": tiny_model, "water": water_model, "copper": copper_model}[which]
     frames = _frames(which)
     print("case", which, [len(f[1]) for f in frames], flush=True)
     o = Oracle(path)
