@@ -1130,12 +1130,18 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
   }
   if (i >= A.n) return;
   const ModelC& m = A.m;
+  const int* vrow = A.vlist + (size_t)i * A.vcap;
+  // The first 256 slots of the row are loaded with the count (slots past it are read,
+  // clamped into the row, and dropped) and the coordinates and types of the candidates are
+  // gathered together, so that an atom costs two dependent memory round trips, not four.
+  int e[4];
+#pragma unroll
+  for (int j = 0; j < 4; j++) e[j] = vrow[min(64 * j + lane, A.vcap - 1)];
   const int cnt = A.vcnt[i];
   if (cnt > kVCap) {
     if (lane == 0) A.big[atomicAdd(A.nbig, 1)] = i;
     return;
   }
-  const int* vrow = A.vlist + (size_t)i * A.vcap;
   const double xi[3] = {A.xe[3 * i], A.xe[3 * i + 1], A.xe[3 * i + 2]};
   int* nl = A.nlist + (size_t)i * m.nm;
   const unsigned long long below = (1ull << lane) - 1ull;
@@ -1143,20 +1149,26 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
 #pragma unroll
   for (int t = 0; t < kMaxTypes; t++) tc[t] = 0;
   for (int p0 = 0; p0 < cnt; p0 += 256) {
-    int e[4];
     double r2[4];
+    int ty[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const int p = p0 + 64 * j + lane;
-      e[j] = p < cnt ? vrow[p] : -1;
+      if (p0 > 0) e[j] = vrow[min(p, A.vcap - 1)];   // a row longer than 256 (rare)
+      if (p >= cnt) e[j] = -1;
     }
 #pragma unroll
-    for (int j = 0; j < 4; j++) r2[j] = e[j] >= 0 ? nl_r2(A.xe, e[j], xi) : 0.0;
+    for (int j = 0; j < 4; j++) {
+      const int q = e[j] >= 0 ? e[j] : 0;   // in bounds whatever the slot holds
+      const double d2 = nl_r2(A.xe, q, xi);
+      ty[j] = A.etype[q];
+      r2[j] = e[j] >= 0 ? d2 : 0.0;
+    }
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       if (p0 + 64 * j >= cnt) break;   // uniform over the wave
       const bool keep = e[j] >= 0 && r2[j] < m.rc2;
-      const int t = keep ? A.etype[e[j]] : -1;
+      const int t = keep ? ty[j] : -1;
 #pragma unroll
       for (int T = 0; T < kMaxTypes; T++) {
         if (T >= m.ntypes) break;
