@@ -288,28 +288,41 @@ static void pg_colsum(size_t rows, int N, const double* a, const double* wa, con
   hipLaunchKernelGGL(k_pg_colsum, dim3(bx, by), dim3(256), 0, st, rows, per, N, a, wa, b, wb, ws, out);
 }
 
-// dT from dD (Eq. 4 adjoint) with tangents, one block per centre row
+// dT from dD (Eq. 4 adjoint) with tangents, one block per centre row; the row's dD, its
+// tangent, T and its tangent are staged in LDS first (coalesced), the strided reads of the
+// second term then come from there
 __global__ __launch_bounds__(256) void k_pg_desc_bwd(int M, int m2, const double* __restrict__ T,
                                                      const double* __restrict__ Td,
                                                      const double* __restrict__ Dg,
                                                      const double* __restrict__ Dgd,
                                                      double* __restrict__ gT, double* __restrict__ gTd) {
+  extern __shared__ double sm[];
+  const int K1 = M * m2;
+  double* sdg = sm;           // [M][m2]
+  double* sdgd = sdg + K1;
+  double* st = sdgd + K1;     // [M][4]
+  double* std4 = st + M * 4;
   const size_t row = blockIdx.x;
-  const double* t = T + row * M * 4;
-  const double* td = Td + row * M * 4;
-  const double* dg = Dg + row * M * m2;
-  const double* dgd = Dgd + row * M * m2;
+  for (int q = threadIdx.x; q < K1; q += blockDim.x) {
+    sdg[q] = Dg[row * K1 + q];
+    sdgd[q] = Dgd[row * K1 + q];
+  }
+  for (int q = threadIdx.x; q < M * 4; q += blockDim.x) {
+    st[q] = T[row * M * 4 + q];
+    std4[q] = Td[row * M * 4 + q];
+  }
+  __syncthreads();
   for (int q = threadIdx.x; q < M * 4; q += blockDim.x) {
     int p = q >> 2, c = q & 3;
     double v = 0.0, vd = 0.0;
     for (int b = 0; b < m2; b++) {
-      v += dg[p * m2 + b] * t[b * 4 + c];
-      vd += dgd[p * m2 + b] * t[b * 4 + c] + dg[p * m2 + b] * td[b * 4 + c];
+      v += sdg[p * m2 + b] * st[b * 4 + c];
+      vd += sdgd[p * m2 + b] * st[b * 4 + c] + sdg[p * m2 + b] * std4[b * 4 + c];
     }
     if (p < m2)
       for (int a = 0; a < M; a++) {
-        v += dg[a * m2 + p] * t[a * 4 + c];
-        vd += dgd[a * m2 + p] * t[a * 4 + c] + dg[a * m2 + p] * td[a * 4 + c];
+        v += sdg[a * m2 + p] * st[a * 4 + c];
+        vd += sdgd[a * m2 + p] * st[a * 4 + c] + sdg[a * m2 + p] * std4[a * 4 + c];
       }
     gT[row * M * 4 + q] = v;
     gTd[row * M * 4 + q] = vd;
@@ -461,7 +474,11 @@ int launch_param_grad(const PGradArgs& G, hipStream_t st) {
     }
   }
   // 5. dE/dT with tangents
-  hipLaunchKernelGGL(k_pg_desc_bwd, dim3(nrows), dim3(256), 0, st, M, m2, Tm, Tmd, Dg, Dgd, gTm, gTmd);
+  {
+    const size_t sh = sizeof(double) * (2 * (size_t)K1 + 8 * (size_t)M);
+    (void)hipFuncSetAttribute((const void*)k_pg_desc_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL(k_pg_desc_bwd, dim3(nrows), dim3(256), sh, st, M, m2, Tm, Tmd, Dg, Dgd, gTm, gTmd);
+  }
   // 6. embedding reverse (fused: the per-pair operands of the weight gradients), then the
   // weight gradients as products over the pair rows of each species pair
   F.gTm = gTm;
