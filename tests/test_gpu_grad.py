@@ -30,6 +30,15 @@ def dp():
 def _frames(which):
     if which == "tiny":
         fr = [I.water_lattice(1, 3.2, 31), tiny_water(32, 2, 6.3), tiny_water(33, 2, 6.6)]
+    elif which == "sparse":
+        # an open cluster with an isolated atom (no neighbours at all) in a vacuum box, and a
+        # frame of two far-apart atoms: centres with empty neighbour lists and species pairs
+        # with no pairs
+        c, t, b = I.water_lattice(1, 3.2, 34)
+        c = np.concatenate([c + 10.0, [[25.0, 25.0, 25.0]]])
+        t = np.concatenate([t, [1]]).astype(np.int32)
+        fr = [(c, t, np.eye(3) * 40.0),
+              (np.array([[1.0, 1.0, 1.0], [15.0, 15.0, 15.0]]), np.array([0, 1], np.int32), np.eye(3) * 30.0)]
     elif which == "copper":
         # one species, first embedding width 32 (no pad positions), cells narrower than 2 rc
         fr = [I.copper_fcc(3, 3.634, 41), I.copper_fcc(3, 3.70, 42)]
@@ -49,10 +58,10 @@ def _targets(o, frames, seed):
     return out
 
 
-@pytest.mark.parametrize("which", ["tiny", "water", "copper"])
+@pytest.mark.parametrize("which", ["tiny", "water", "copper", "sparse"])
 def test_param_grad_matches_oracle(dp, which, tiny_model, water_model, copper_model):
     import torch
-    path = {"tiny": tiny_model, "water": water_model, "copper": copper_model}[which]
+    path = {"tiny": tiny_model, "water": water_model, "copper": copper_model, "sparse": tiny_model}[which]
     frames = _frames(which)
     print("case", which, [len(f[1]) for f in frames], flush=True)
     o = Oracle(path)
