@@ -18,6 +18,8 @@ FLAGS = [
     # no packed-FP32 instructions: plain FP32 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # every symbol resolved at link time
+    "-Wl,--no-undefined",
     # MFMA accumulators in ordinary VGPRs (no AGPR copies in the GEMM loops)
     "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",

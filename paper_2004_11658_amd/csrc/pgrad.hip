@@ -31,13 +31,14 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 //   TA = 0: A stored [M][lda]; TA = 1: A stored [K][lda] (A^T)
 //   TB = 0: B stored [K][ldb]; TB = 1: B stored [N][ldb] (B^T)
 // gridDim.z splits K; with more than one split the partial tiles are added atomically.
+// With `mode` 2 the tile is stored (C = op(A) op(B): one split), with 1 added atomically.
 // ------------------------------------------------------------------------------------
-constexpr int PG_T = 64, PG_KT = 16;
+constexpr int PG_T = 64, PG_KT = 16, PG_LD = PG_T * PG_KT / 256;
 
 template <int TA, int TB>
 __global__ __launch_bounds__(256) void k_pg_gemm(int M, int N, int K, int kchunk, const double* __restrict__ A,
                                                  int lda, const double* __restrict__ B, int ldb,
-                                                 double* __restrict__ C, int ldc, int atomic) {
+                                                 double* __restrict__ C, int ldc, int mode) {
   __shared__ double As[PG_T][PG_KT + 1];
   __shared__ double Bs[PG_KT][PG_T + 1];
   const int m0 = blockIdx.x * PG_T, n0 = blockIdx.y * PG_T;
@@ -50,10 +51,10 @@ __global__ __launch_bounds__(256) void k_pg_gemm(int M, int N, int K, int kchunk
   for (int a = 0; a < 2; a++)
 #pragma unroll
     for (int b = 0; b < 2; b++) acc[a][b] = d4v{0, 0, 0, 0};
-  double ra[4], rbv[4];
+  double ra[PG_LD], rbv[PG_LD];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
+    for (int j = 0; j < PG_LD; j++) {
       int e = tid + 256 * j;
       int m, k;
       if (TA) { k = e / PG_T; m = e % PG_T; } else { m = e / PG_KT; k = e % PG_KT; }
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(256) void k_pg_gemm(int M, int N, int K, int kchunk
       ra[j] = v;
     }
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
+    for (int j = 0; j < PG_LD; j++) {
       int e = tid + 256 * j;
       int n, k;
       if (TB) { n = e / PG_KT; k = e % PG_KT; } else { k = e / PG_T; n = e % PG_T; }
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(256) void k_pg_gemm(int M, int N, int K, int kchunk
   };
   auto store = [&]() {
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
+    for (int j = 0; j < PG_LD; j++) {
       int e = tid + 256 * j;
       if (TA) As[e % PG_T][e / PG_T] = ra[j];
       else As[e / PG_KT][e % PG_KT] = ra[j];
@@ -112,40 +113,201 @@ __global__ __launch_bounds__(256) void k_pg_gemm(int M, int N, int K, int kchunk
         int row = m0 + wr + 16 * a + g + 4 * q;  // FP64 16x16x4: rows g + 4q
         if (row >= M) continue;
         double* c = C + (size_t)row * ldc + col;
-        if (atomic) unsafeAtomicAdd(c, acc[a][b][q]);
+        if (mode == 1) unsafeAtomicAdd(c, acc[a][b][q]);
+        else if (mode == 2) *c = acc[a][b][q];
         else *c += acc[a][b][q];
       }
     }
 }
 
+// C += op(A) op(B); with `store`, C = op(A) op(B) (C need not be cleared first).
 void pg_gemm(int ta, int tb, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
-             double* C, int ldc, hipStream_t st) {
+             double* C, int ldc, hipStream_t st, bool store = false) {
   if (M <= 0 || N <= 0 || K <= 0) return;
   int gm = (M + PG_T - 1) / PG_T, gn = (N + PG_T - 1) / PG_T;
   // split long K so that the grid has enough workgroups
   int splits = 1;
-  while ((long)gm * gn * splits < 1024 && K / (splits * 2) >= 256) splits *= 2;
+  while (!store && (long)gm * gn * splits < 1024 && K / (splits * 2) >= 256) splits *= 2;
   int kchunk = ((K + splits - 1) / splits + PG_KT - 1) / PG_KT * PG_KT;
   splits = (K + kchunk - 1) / kchunk;
   dim3 grid(gm, gn, splits);
-  int atomic = splits > 1;
-  if (!ta && !tb) hipLaunchKernelGGL((k_pg_gemm<0, 0>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, C, ldc, atomic);
-  else if (!ta && tb) hipLaunchKernelGGL((k_pg_gemm<0, 1>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, C, ldc, atomic);
-  else if (ta && !tb) hipLaunchKernelGGL((k_pg_gemm<1, 0>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, C, ldc, atomic);
-  else hipLaunchKernelGGL((k_pg_gemm<1, 1>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, C, ldc, atomic);
+  const int mode = store ? 2 : (splits > 1 ? 1 : 0);
+  if (!ta && !tb) hipLaunchKernelGGL((k_pg_gemm<0, 0>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, C, ldc, mode);
+  else if (!ta && tb) hipLaunchKernelGGL((k_pg_gemm<0, 1>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, C, ldc, mode);
+  else if (ta && !tb) hipLaunchKernelGGL((k_pg_gemm<1, 0>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, C, ldc, mode);
+  else hipLaunchKernelGGL((k_pg_gemm<1, 1>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, C, ldc, mode);
+}
+
+// ------------------------------------------------------------------------------------
+// weight gradient of one embedding layer over the pair rows of one species pair:
+//   C[m][n] += sum_r A[r][m] Bd[r][n] + Ad[r][m] B[r][n]
+// A, Ad: [K][mA] (layer inputs and their tangents), B, Bd: [K][nB] (pre-activation
+// adjoints and their tangents), C: [mA][nB], all row-major.  The FP64 16x16x4 MFMA takes
+// its A operand as lane (i + 16k) <- A^T[i][k] and its B operand as lane (j + 16k) <-
+// B[k][j]; with the pair rows as the contracted index both are loads of 16 consecutive
+// columns from 4 consecutive rows, so the operands go from memory straight into the
+// products with no staging.
+// One workgroup per slice of rows (about one per CU).  Its waves are G tile groups x R row
+// waves: wave (g, r) accumulates the MT x NT output tiles of group g (a layer wider than
+// one group reads its rows once from memory, the other groups hit the cache) over the r-th
+// part of the slice.  The R row waves of a group are then summed in LDS in a fixed order
+// and the workgroup adds each entry of C once, atomically: few atomics per address, since
+// FP64 atomics on one address serialise.  Two groups of U K-steps are kept in flight; the
+// loads of whole groups carry no masks, so that nothing makes the compiler wait on them.
+// ------------------------------------------------------------------------------------
+template <int MT, int NT, int U, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_pg_wgrad(int K, int rows_per_block, int rows_per_wave, int mA, int nB,
+                                                   int ngn, int G, const double* __restrict__ A,
+                                                   const double* __restrict__ Ad, const double* __restrict__ B,
+                                                   const double* __restrict__ Bd, double* __restrict__ C) {
+  extern __shared__ double red[];  // [G][MT][NT][4][64]
+  constexpr int kGroup = MT * NT * 4 * 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, i = lane & 15, k = lane >> 4;
+  const int g = w % G, rw = w / G, R = (blockDim.x >> 6) / G;
+  const int b0 = blockIdx.x * rows_per_block, b1 = min(K, b0 + rows_per_block);
+  const int r0 = b0 + rw * rows_per_wave, r1 = min(b1, r0 + rows_per_wave);
+  const int m0 = (g / ngn) * 16 * MT, n0 = (g % ngn) * 16 * NT;
+  // columns past a width read the last column: they only feed result entries past the
+  // widths, which are never written
+  int ca[MT], cb[NT];
+#pragma unroll
+  for (int t = 0; t < MT; t++) ca[t] = min(m0 + 16 * t + i, mA - 1);
+#pragma unroll
+  for (int t = 0; t < NT; t++) cb[t] = min(n0 + 16 * t + i, nB - 1);
+  d4v acc[MT][NT];
+#pragma unroll
+  for (int a = 0; a < MT; a++)
+#pragma unroll
+    for (int b = 0; b < NT; b++) acc[a][b] = d4v{0, 0, 0, 0};
+  struct Buf {
+    double a[U][MT], ad[U][MT], b[U][NT], bd[U][NT];
+  };
+  // rows r .. r + 4U - 1; with `tail`, rows past the wave's part read row r0 and their A
+  // side is zeroed (then they add nothing)
+  auto load = [&](Buf& f, int r, bool tail) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int row = r + 4 * u + k;
+      const bool vr = !tail || row < r1;
+      const size_t rr = vr ? row : r0;
+      const double* pa = A + rr * mA;
+      const double* pad = Ad + rr * mA;
+      const double* pb = B + rr * nB;
+      const double* pbd = Bd + rr * nB;
+#pragma unroll
+      for (int t = 0; t < MT; t++) {
+        f.a[u][t] = pa[ca[t]];
+        f.ad[u][t] = pad[ca[t]];
+        if (tail) {
+          f.a[u][t] = vr ? f.a[u][t] : 0.0;
+          f.ad[u][t] = vr ? f.ad[u][t] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; t++) {
+        f.b[u][t] = pb[cb[t]];
+        f.bd[u][t] = pbd[cb[t]];
+      }
+    }
+  };
+  auto mma = [&](const Buf& f) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+#pragma unroll
+      for (int a = 0; a < MT; a++)
+#pragma unroll
+        for (int b = 0; b < NT; b++)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[u][a], f.bd[u][b], acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < MT; a++)
+#pragma unroll
+        for (int b = 0; b < NT; b++)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.ad[u][a], f.b[u][b], acc[a][b], 0, 0, 0);
+    }
+  };
+  if (r0 < r1) {
+    // whole groups of 4U rows, two in flight; then the partial group, if any
+    const int nfull = (r1 - r0) / (4 * U);
+    Buf f0, f1;
+    if (nfull > 0) {
+      load(f0, r0, false);
+      int gi = 0;
+      for (; gi + 2 <= nfull; gi += 2) {
+        load(f1, r0 + (gi + 1) * 4 * U, false);
+        mma(f0);
+        if (gi + 2 < nfull) load(f0, r0 + (gi + 2) * 4 * U, false);
+        mma(f1);
+      }
+      if (gi < nfull) mma(f0);
+    }
+    const int rt = r0 + nfull * 4 * U;
+    if (rt < r1) {
+      load(f1, rt, true);
+      mma(f1);
+    }
+  }
+  // fixed-order sum of the row waves of each group: round j adds row wave j's tiles
+  double* mine = red + (size_t)g * kGroup;
+  for (int j = 0; j < R; j++) {
+    if (rw == j) {
+#pragma unroll
+      for (int a = 0; a < MT; a++)
+#pragma unroll
+        for (int b = 0; b < NT; b++)
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            double* p = mine + ((a * NT + b) * 4 + q) * 64 + lane;
+            *p = (j == 0 ? 0.0 : *p) + acc[a][b][q];
+          }
+    }
+    __syncthreads();
+  }
+  // one atomic per entry of C and workgroup; result lane (i + 16k) of a tile holds rows
+  // k + 4q, column i
+  for (int e = threadIdx.x; e < G * kGroup; e += blockDim.x) {
+    const int gg = e / kGroup, t = e % kGroup, l = t & 63, q = (t >> 6) & 3, ab = t >> 8;
+    const int row = (gg / ngn) * 16 * MT + 16 * (ab / NT) + (l >> 4) + 4 * q;
+    const int col = (gg % ngn) * 16 * NT + 16 * (ab % NT) + (l & 15);
+    if (row < mA && col < nB) unsafeAtomicAdd(C + (size_t)row * nB + col, red[e]);
+  }
+}
+
+// R row waves per tile group: the waves of one workgroup fill a CU at the kernel's
+// occupancy (WAVES per CU), so one workgroup per CU and kWgradSlices workgroups.
+constexpr int kWgradSlices = 256;
+
+template <int MT, int NT, int U, int WAVES>
+static void pg_wgrad_launch(int K, int mA, int nB, const double* A, const double* Ad, const double* B,
+                            const double* Bd, double* C, hipStream_t st) {
+  const int mt = (mA + 15) / 16, nt = (nB + 15) / 16;
+  const int ngm = (mt + MT - 1) / MT, ngn = (nt + NT - 1) / NT, G = ngm * ngn;
+  const int R = std::max(1, WAVES / G);
+  int rpw = (K + kWgradSlices * R - 1) / (kWgradSlices * R);
+  rpw = (rpw + 4 * U - 1) / (4 * U) * (4 * U);
+  const int rpb = rpw * R;
+  const size_t lds = sizeof(double) * (size_t)G * MT * NT * 4 * 64;
+  (void)hipFuncSetAttribute((const void*)k_pg_wgrad<MT, NT, U, WAVES>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL((k_pg_wgrad<MT, NT, U, WAVES>), dim3((K + rpb - 1) / rpb), dim3(64 * G * R), lds, st, K, rpb, rpw, mA,
+                     nB, ngn, G, A, Ad, B, Bd, C);
+}
+
+// C [mA][nB] += A^T Bd + Ad^T B over K pair rows (see k_pg_wgrad).  Narrow layers take one
+// tile group; wider ones groups of 64 x 64 tiles, at most 2 x 2 of them (128 KB of LDS) for
+// the widths the model loader admits (s0 <= 32: layer 2 is at most 65 x 128).
+void pg_wgrad(int K, int mA, int nB, const double* A, const double* Ad, const double* B, const double* Bd,
+              double* C, hipStream_t st) {
+  if (K <= 0 || mA <= 0 || nB <= 0) return;
+  const int mt = (mA + 15) / 16, nt = (nB + 15) / 16;
+  if (mt <= 1 && nt <= 2) pg_wgrad_launch<1, 2, 2, 16>(K, mA, nB, A, Ad, B, Bd, C, st);
+  else if (mt <= 2 && nt <= 4) pg_wgrad_launch<2, 4, 2, 8>(K, mA, nB, A, Ad, B, Bd, C, st);
+  else if (mt <= 4 && nt == 7) pg_wgrad_launch<2, 7, 1, 8>(K, mA, nB, A, Ad, B, Bd, C, st);
+  else pg_wgrad_launch<4, 4, 1, 8>(K, mA, nB, A, Ad, B, Bd, C, st);
 }
 
 // ------------------------------------------------------------------------------------
 // elementwise pieces
 // ------------------------------------------------------------------------------------
-__global__ void k_pg_zero(size_t n, double* __restrict__ p) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
-}
-static void pg_zero(double* p, size_t n, hipStream_t st) {
-  if (n) hipLaunchKernelGGL(k_pg_zero, dim3((n + 255) / 256), dim3(256), 0, st, n, p);
-}
-
 // y = skip(x) + tanh(z + b) with tangents; z, zd hold x W and dx W on entry and
 // receive t and dt.  skip: 0 none, 1 identity, 2 concat (x, x).  xo/xod may be null.
 __global__ void k_pg_act(size_t rows, int nin, int nout, int skip, const double* __restrict__ bias,
@@ -417,10 +579,8 @@ int launch_param_grad(const PGradArgs& G, hipStream_t st) {
       const double* xind = k == 0 ? Dd + (size_t)r0 * K1 : fxd + (k - 1) * L + (size_t)r0 * fw;
       double* tk = ft + k * L + (size_t)r0 * fw;
       double* tkd = ftd + k * L + (size_t)r0 * fw;
-      pg_zero(tk, (size_t)nr * fw, st);
-      pg_zero(tkd, (size_t)nr * fw, st);
-      pg_gemm(0, 0, nr, fw, kin, xin, kin, Wk, fw, tk, fw, st);
-      pg_gemm(0, 0, nr, fw, kin, xind, kin, Wk, fw, tkd, fw, st);
+      pg_gemm(0, 0, nr, fw, kin, xin, kin, Wk, fw, tk, fw, st, true);
+      pg_gemm(0, 0, nr, fw, kin, xind, kin, Wk, fw, tkd, fw, st, true);
       int skip = (kin == fw) ? 1 : 0;
       hipLaunchKernelGGL(k_pg_act, dim3(((size_t)nr * fw + 255) / 256), dim3(256), 0, st, (size_t)nr, kin, fw, skip, bk,
                          xin, xind, tk, tkd, fx + k * L + (size_t)r0 * fw, fxd + k * L + (size_t)r0 * fw);
@@ -457,18 +617,15 @@ int launch_param_grad(const PGradArgs& G, hipStream_t st) {
       if (skip) {
         hipLaunchKernelGGL(k_pg_skip, dim3(((size_t)nr * kin + 255) / 256), dim3(256), 0, st, (size_t)nr, fw, kin, 1,
                            c, cd, dst, dstd);
-      } else {
-        pg_zero(dst, (size_t)nr * kin, st);
-        pg_zero(dstd, (size_t)nr * kin, st);
       }
       hipLaunchKernelGGL(k_pg_damp, dim3(((size_t)nr * fw + 255) / 256), dim3(256), 0, st, (size_t)nr * fw, c, cd, tk, tkd);
       // weight gradient (tangent): x^T dP + dx^T P; bias: sum dP
       pg_gemm(1, 0, kin, fw, nr, xin, kin, cd, fw, gWk, fw, st);
       pg_gemm(1, 0, kin, fw, nr, xind, kin, c, fw, gWk, fw, st);
       pg_colsum((size_t)nr, fw, cd, nullptr, nullptr, nullptr, 0, gbk, st);
-      // input adjoint += P W^T (value and tangent)
-      pg_gemm(0, 1, nr, kin, fw, c, fw, Wk, fw, dst, kin, st);
-      pg_gemm(0, 1, nr, kin, fw, cd, fw, Wk, fw, dstd, kin, st);
+      // input adjoint += P W^T (value and tangent; stored where there is no skip term)
+      pg_gemm(0, 1, nr, kin, fw, c, fw, Wk, fw, dst, kin, st, !skip);
+      pg_gemm(0, 1, nr, kin, fw, cd, fw, Wk, fw, dstd, kin, st, !skip);
       double* t1 = cur; cur = nxt; nxt = t1;
       double* t2 = curd; curd = nxtd; nxtd = t2;
     }
@@ -497,14 +654,13 @@ int launch_param_grad(const PGradArgs& G, hipStream_t st) {
       // the biases follow the weights in theta: the trailing column of the inputs (ones in
       // the value, zeros in the tangent) turns row n_in of each product into the bias sum
       // layer 2: [gW2; gB2] += [X1 1]^T dP2 + [dX1 0]^T P2
-      pg_gemm(1, 0, s1 + 1, M, ng, F.X1 + (size_t)g0 * (s1 + 1), s1 + 1, F.P2d + o2, M, gW2, M, st);
-      pg_gemm(1, 0, s1 + 1, M, ng, F.X1d + (size_t)g0 * (s1 + 1), s1 + 1, F.P2 + o2, M, gW2, M, st);
+      pg_wgrad(ng, s1 + 1, M, F.X1 + (size_t)g0 * (s1 + 1), F.X1d + (size_t)g0 * (s1 + 1), F.P2 + o2, F.P2d + o2,
+               gW2, st);
       // layer 1: [gW1; gB1] += [X0 1]^T dP1 + [dX0 0]^T P1
-      pg_gemm(1, 0, s0 + 1, s1, ng, F.X0 + (size_t)g0 * (s0 + 1), s0 + 1, F.P1d + o1, s1, gW1, s1, st);
-      pg_gemm(1, 0, s0 + 1, s1, ng, F.X0d + (size_t)g0 * (s0 + 1), s0 + 1, F.P1 + o1, s1, gW1, s1, st);
+      pg_wgrad(ng, s0 + 1, s1, F.X0 + (size_t)g0 * (s0 + 1), F.X0d + (size_t)g0 * (s0 + 1), F.P1 + o1, F.P1d + o1,
+               gW1, st);
       // layer 0: [gW0; gB0] += [s 1]^T dP0 + [ds 0]^T P0
-      pg_gemm(1, 0, 2, s0, ng, F.S + 2 * (size_t)g0, 2, F.P0d + o0, s0, gW0, s0, st);
-      pg_gemm(1, 0, 2, s0, ng, F.Sd + 2 * (size_t)g0, 2, F.P0 + o0, s0, gW0, s0, st);
+      pg_wgrad(ng, 2, s0, F.S + 2 * (size_t)g0, F.Sd + 2 * (size_t)g0, F.P0 + o0, F.P0d + o0, gW0, st);
     }
   return 0;
 }

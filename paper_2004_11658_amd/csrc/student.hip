@@ -19,7 +19,7 @@
 namespace dp {
 
 void pg_gemm(int ta, int tb, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
-             double* C, int ldc, hipStream_t st);
+             double* C, int ldc, hipStream_t st, bool store);
 
 // keep flag of each (atom, slot) of the species pair (alpha, beta)
 __global__ void k_st_flag(int n, int nm, int ntypes, int alpha, int beta, int sel_off, int sel,
@@ -217,8 +217,8 @@ void launch_student_lsq(long n, int H, int M, const double* s, const double* G, 
   double* R = C + (size_t)K * K;
   hipLaunchKernelGGL(k_st_design, dim3(((size_t)n * K + 255) / 256), dim3(256), 0, st, n, H, s, th, th + H, A);
   hipLaunchKernelGGL(k_st_zero, dim3((K * K + K * M + 255) / 256), dim3(256), 0, st, (size_t)(K * K + K * M), C);
-  pg_gemm(1, 0, K, K, (int)n, A, K, A, K, C, K, st);
-  pg_gemm(1, 0, K, M, (int)n, A, K, G, M, R, M, st);
+  pg_gemm(1, 0, K, K, (int)n, A, K, A, K, C, K, st, false);
+  pg_gemm(1, 0, K, M, (int)n, A, K, G, M, R, M, st, false);
   hipLaunchKernelGGL(k_st_cholsolve, dim3(1), dim3(128), 0, st, K, M, ridge, C, R, th + 2 * H, th + 2 * H + H * M);
 }
 
@@ -264,14 +264,14 @@ void launch_student_loss_grad(long n, int H, int M, const double* s, const doubl
   hipLaunchKernelGGL(k_st_zero, dim3(((size_t)n * M + 255) / 256), dim3(256), 0, st, (size_t)n * M, Y);
   hipLaunchKernelGGL(k_st_zero, dim3(((size_t)n * H + 255) / 256), dim3(256), 0, st, (size_t)n * H, dH);
   hipLaunchKernelGGL(k_st_hidden, dim3(((size_t)n * H + 255) / 256), dim3(256), 0, st, n, H, s, W1, b1, Hm);
-  pg_gemm(0, 0, (int)n, M, H, Hm, H, W2, M, Y, M, st);
+  pg_gemm(0, 0, (int)n, M, H, Hm, H, W2, M, Y, M, st, false);
   const size_t rb = ((size_t)n * M + 255) / 256;
   hipLaunchKernelGGL(k_st_resid, dim3(rb < (size_t)kResidBlocks ? (rb ? rb : 1) : kResidBlocks), dim3(256), 0, st, n,
                      M, b2, G, Y, loss);
   // Y now holds dL/dY
-  pg_gemm(1, 0, H, M, (int)n, Hm, H, Y, M, gW2, M, st);
+  pg_gemm(1, 0, H, M, (int)n, Hm, H, Y, M, gW2, M, st, false);
   colsum(n, M, Y, nullptr, gb2, st);
-  pg_gemm(0, 1, (int)n, H, M, Y, M, W2, M, dH, H, st);
+  pg_gemm(0, 1, (int)n, H, M, Y, M, W2, M, dH, H, st, false);
   hipLaunchKernelGGL(k_st_damp, dim3(((size_t)n * H + 255) / 256), dim3(256), 0, st, (size_t)n * H, Hm, dH);
   colsum(n, H, dH, s, gW1, st);
   colsum(n, H, dH, nullptr, gb1, st);
