@@ -505,9 +505,12 @@ __global__ __launch_bounds__(FT) void k_fit_l1_bwd(FitBfArgs P) {
 #pragma unroll
     for (int q = 0; q < 4; q++) p2[rt][q] = z4;
   const __bf16* W = (const __bf16*)P.Wf[(sp * P.nfit) * 2 + 1];
-  // a range of this wave: an even count (M is even), two tiles per pass
-  const int per0 = (M + FW - 1) / FW, per = per0 + (per0 & 1);
-  const int a0 = min(M, w * per), a1 = min(M, a0 + per);
+  // a range of this wave: whole pairs (M is even), two tiles per pass, the M / 2 pairs
+  // dealt evenly over the waves (waves w and w + 4 share a SIMD's MFMA: with 100 a this
+  // gives each SIMD 24 or 26 of them)
+  const int np = M / 2, pw = np / FW, px = np % FW;
+  const int p0 = w * pw + min(w, px);
+  const int a0 = 2 * p0, a1 = 2 * (p0 + pw + (w < px ? 1 : 0));
   __syncthreads();
   bf8 wh[2][2], wl[2][2];   // [buffer][tile of the pair]
   bf8 xh[2][4], xl[2][4];   // [buffer][row tile]
