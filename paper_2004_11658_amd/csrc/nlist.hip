@@ -1119,10 +1119,15 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_vbuild(
 // (more than kVCap candidates) or where a species has more than sel neighbours within
 // rc (the nearest sel must then be chosen at the current distances) is deferred to the
 // exact second pass.
+// Workgroups are dealt to the 8 XCDs round robin (block b on XCD b % 8), each XCD with its
+// own L2: the grid is a multiple of 8 and block b takes the atoms of logical block
+// (b % 8) (grid / 8) + b / 8, so each XCD filters a contiguous range of atoms, whose
+// candidates' coordinates largely coincide and stay in its L2.
 __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * kNlWaves + wv;
+  const int lb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const int i = lb * kNlWaves + wv;
   if (i == 0 && lane == 0) {
     // the rebuild (if any) and the refresh are done: the next step's check sets the flag
     if (A.gate) *A.gate = 0;
@@ -1443,7 +1448,8 @@ void launch_nlist_verlet(const NlistArgs& A, double half_skin, bool disp_done, i
   NlKArgs K = format_args(A);
   K.gate = (int*)A.gate;
   K.clear = clear;
-  hipLaunchKernelGGL(k_nlist_vstep, dim3((K.n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, K);
+  hipLaunchKernelGGL(k_nlist_vstep, dim3(((K.n + kNlWaves - 1) / kNlWaves + 7) / 8 * 8), dim3(64 * kNlWaves), 0, st,
+                     K);
   hipLaunchKernelGGL((k_nlist<kMaxCand>), dim3(kSecondPassBlocks), dim3(64 * kNlWaves), 0, st, K);
 }
 
