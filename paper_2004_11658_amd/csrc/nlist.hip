@@ -1122,8 +1122,12 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_vbuild(
 // Workgroups are dealt to the 8 XCDs round robin (block b on XCD b % 8), each XCD with its
 // own L2: the grid is a multiple of 8 and block b takes the atoms of logical block
 // (b % 8) (grid / 8) + b / 8, so each XCD filters a contiguous range of atoms, whose
-// candidates' coordinates largely coincide and stay in its L2.
+// candidates' coordinates largely coincide and stay in its L2.  NTY > 0 fixes the number of
+// species at compile time (the per-species loops then carry no bounds checks); NTY = 0
+// takes it from the model, up to kMaxTypes.
+template <int NTY>
 __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
+  constexpr int TT = NTY > 0 ? NTY : kMaxTypes;
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int lb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
@@ -1150,9 +1154,10 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
   const double xi[3] = {A.xe[3 * i], A.xe[3 * i + 1], A.xe[3 * i + 2]};
   int* nl = A.nlist + (size_t)i * m.nm;
   const unsigned long long below = (1ull << lane) - 1ull;
-  int tc[kMaxTypes];
+  const int nty = NTY > 0 ? NTY : m.ntypes;
+  int tc[TT];
 #pragma unroll
-  for (int t = 0; t < kMaxTypes; t++) tc[t] = 0;
+  for (int t = 0; t < TT; t++) tc[t] = 0;
   for (int p0 = 0; p0 < cnt; p0 += 256) {
     double r2[4];
     int ty[4];
@@ -1175,8 +1180,8 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
       const bool keep = e[j] >= 0 && r2[j] < m.rc2;
       const int t = keep ? ty[j] : -1;
 #pragma unroll
-      for (int T = 0; T < kMaxTypes; T++) {
-        if (T >= m.ntypes) break;
+      for (int T = 0; T < TT; T++) {
+        if (NTY == 0 && T >= nty) break;
         const unsigned long long mk = __ballot(t == T);
         if (t == T) {
           const int pos = tc[T] + __popcll(mk & below);
@@ -1188,22 +1193,25 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
   }
   bool ovf = false;
 #pragma unroll
-  for (int T = 0; T < kMaxTypes; T++) ovf |= T < m.ntypes && tc[T] > m.sel[T];
+  for (int T = 0; T < TT; T++) ovf |= T < nty && tc[T] > m.sel[T];
   if (ovf) {
     if (lane == 0) A.big[atomicAdd(A.nbig, 1)] = i;
     return;
   }
   for (int k = lane; k < m.nm; k += 64) {
-    int t = 0;
-    while (t + 1 < m.ntypes && k >= m.sel_off[t + 1]) t++;
-    int c = 0;
+    // species block of slot k and its count
+    int c = tc[0], o = m.sel_off[0];
 #pragma unroll
-    for (int u = 0; u < kMaxTypes; u++) c = (u == t) ? tc[u] : c;
-    if (k - m.sel_off[t] >= c) nl[k] = -1;
+    for (int u = 1; u < TT; u++)
+      if (u < nty && k >= m.sel_off[u]) {
+        c = tc[u];
+        o = m.sel_off[u];
+      }
+    if (k - o >= c) nl[k] = -1;
   }
 #pragma unroll
-  for (int t = 0; t < kMaxTypes; t++)
-    if (lane == t && t < m.ntypes) A.nnei[(size_t)i * m.ntypes + t] = tc[t];
+  for (int t = 0; t < TT; t++)
+    if (lane == t && t < nty) A.nnei[(size_t)i * nty + t] = tc[t];
 }
 
 // both passes of the formatted list
@@ -1448,8 +1456,13 @@ void launch_nlist_verlet(const NlistArgs& A, double half_skin, bool disp_done, i
   NlKArgs K = format_args(A);
   K.gate = (int*)A.gate;
   K.clear = clear;
-  hipLaunchKernelGGL(k_nlist_vstep, dim3(((K.n + kNlWaves - 1) / kNlWaves + 7) / 8 * 8), dim3(64 * kNlWaves), 0, st,
-                     K);
+  const dim3 vgrid(((K.n + kNlWaves - 1) / kNlWaves + 7) / 8 * 8), vblock(64 * kNlWaves);
+  switch (K.m.ntypes) {
+    case 1: hipLaunchKernelGGL(k_nlist_vstep<1>, vgrid, vblock, 0, st, K); break;
+    case 2: hipLaunchKernelGGL(k_nlist_vstep<2>, vgrid, vblock, 0, st, K); break;
+    case 4: hipLaunchKernelGGL(k_nlist_vstep<4>, vgrid, vblock, 0, st, K); break;
+    default: hipLaunchKernelGGL(k_nlist_vstep<0>, vgrid, vblock, 0, st, K); break;
+  }
   hipLaunchKernelGGL((k_nlist<kMaxCand>), dim3(kSecondPassBlocks), dim3(64 * kNlWaves), 0, st, K);
 }
 
