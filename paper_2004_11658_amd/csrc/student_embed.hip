@@ -182,9 +182,12 @@ __device__ __forceinline__ const GAS_T(T)* stu_block(const EmbedArgs& A, int pai
 template <class T>
 __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
   __shared__ __align__(16) T s_w[kStuWaves][kStuS];
+  __shared__ __align__(16) T s_env[kStuWaves][64 * 8];   // per wave: 64 rows [R~ (4), s, pad]
+  typedef T t4v __attribute__((ext_vector_type(4)));
   const ModelC& m = A.m;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, rb = lane & 15, g = lane >> 4;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   T* Sw = s_w[wv];                                     // this wave's S and rbar
+  T* Ew = s_env[wv];
   const int row = blockIdx.x * kStuWaves + wv;
   if (row >= A.nrows) return;
   const int alpha = species_of(row, m.ntypes, A.type_row0);
@@ -200,23 +203,17 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
     const int pair = alpha * m.ntypes + beta;
     const auto sn = stu_block<T>(A, pair);
     const double slo = A.st_lo[pair], shi = A.st_hi[pair];
-    T w1[8], b1[8];
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int k = 16 * (j >> 2) + 4 * g + (j & 3);
-      w1[j] = sn[kSW1 + k];
-      b1[j] = sn[kSB1 + k];
-    }
-    T S[8][4], rs[4] = {(T)0, (T)0, (T)0, (T)0};
-#pragma unroll
-    for (int j = 0; j < 8; j++)
-#pragma unroll
-      for (int c = 0; c < 4; c++) S[j][c] = (T)0;
+    // lane (k, p): hidden unit k = lane % 32 over the rows of parity p = lane / 32, so
+    // that S[k][c] = sum over rows of h_k R~_c accumulates inside the lane (the two row
+    // parities are added at the end) and no reduction over lanes is needed
+    const int hk = lane & 31, hp = lane >> 5;
+    const T w1 = sn[kSW1 + hk], b1 = sn[kSB1 + hk];
+    T Sp[4] = {(T)0, (T)0, (T)0, (T)0}, rs[4] = {(T)0, (T)0, (T)0, (T)0};
     const int nn = A.nnei[atom * m.ntypes + beta];
     const int* nl = A.nlist + (size_t)atom * m.nm + m.sel_off[beta];
-    // Environment rows 64 at a time, one neighbour per lane (c0 + lane), then in chunks of
-    // 16 the lane group g of the hidden units takes neighbour rb of the chunk from lane
-    // 16 q + rb: each row is formed once, not once per lane group
+    // Environment rows 64 at a time, one neighbour per lane (c0 + lane), published in the
+    // wave's LDS rows [R~ (4), s]; then every lane reads the rows of its parity (the same
+    // row across a half wave: broadcast reads) and applies its hidden unit
     const int sel = m.sel[beta];
     double xn[3] = {0, 0, 0};
     int en = stu_index(nl, lane, nn, sel);   // the next 64 neighbours, fetched a pass ahead
@@ -242,47 +239,29 @@ __global__ __launch_bounds__(64 * kStuWaves) void k_stu_fwd(EmbedArgs A) {
       }
 #pragma unroll
       for (int c = 0; c < 4; c++) rs[c] += RL[c];
+      wave_sync_lds();   // the previous block's rows have been read
+      *(t4v*)(Ew + 8 * lane) = t4v{RL[0], RL[1], RL[2], RL[3]};
+      Ew[8 * lane + 4] = sL;
+      wave_sync_lds();
+      const int half = (min(64, nn - c0) + 1) >> 1;   // row pairs holding a neighbour
+#pragma unroll 4
+      for (int i = 0; i < half; i++) {
+        const T* E = Ew + 8 * (2 * i + hp);
+        const t4v R = *(const t4v*)E;
+        const T h = tanh_t(E[4] * w1 + b1);
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        if (c0 + 16 * q >= nn) break;   // uniform over the wave
-        const int src = 16 * q + rb;
-        const T s = wave_shfl(sL, src);
-        T R[4];
-#pragma unroll
-        for (int c = 0; c < 4; c++) R[c] = wave_shfl(RL[c], src);
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-          const T h = tanh_t(s * w1[j] + b1[j]);
-#pragma unroll
-          for (int c = 0; c < 4; c++) S[j][c] += h * R[c];
-        }
+        for (int c = 0; c < 4; c++) Sp[c] += h * R[c];
       }
     }
-    // sums over the 16 neighbour lanes of a lane group: a reduce-scatter of the 32 values
-    // S[j][c] (flat index 4 j + c) leaves lane rb with the full sums of flat indices
-    // 2 rb' and 2 rb' + 1, rb' = the bit-reversed step order below (ror 8, half mirror,
-    // xor 2, xor 1 pair lanes differing in bit 3, 2, 1, 0 of rb)
-    {
-      T v[32];
+    // S[k][c] = both parities' sums; rbar = sum of R~ over the 64 lanes
 #pragma unroll
-      for (int j = 0; j < 8; j++)
-#pragma unroll
-        for (int c = 0; c < 4; c++) v[4 * j + c] = S[j][c];
-      stu_rs_step<T, 32, DPP_ROR8>(v, (rb & 8) != 0);
-      stu_rs_step<T, 16, DPP_HALF_MIRROR>(v, (rb & 4) != 0);
-      stu_rs_step<T, 8, DPP_XOR2>(v, (rb & 2) != 0);
-      stu_rs_step<T, 4, DPP_XOR1>(v, (rb & 1) != 0);
-      // lane rb holds flat indices 16 b3 + 8 b2 + 4 b1 + 2 b0 + {0, 1} (b = bits of rb)
-      const int base = 16 * ((rb >> 3) & 1) + 8 * ((rb >> 2) & 1) + 4 * ((rb >> 1) & 1) + 2 * (rb & 1);
-#pragma unroll
-      for (int t = 0; t < 2; t++) {
-        const int fl = base + t, j = fl >> 2, c = fl & 3;
-        const int kk = 16 * (j >> 2) + 4 * g + (j & 3);
-        Sw[kk * 4 + c] = v[t];
-      }
+    for (int c = 0; c < 4; c++) {
+      Sp[c] += wave_shfl(Sp[c], lane ^ 32);
+      rs[c] = sum_g(row_sum16(rs[c]));
     }
+    if (hp == 0)
 #pragma unroll
-    for (int c = 0; c < 4; c++) rs[c] = sum_g(row_sum16(rs[c]));   // one neighbour per lane: all 64
+      for (int c = 0; c < 4; c++) Sw[hk * 4 + c] = Sp[c];
     if (lane == 0)
 #pragma unroll
       for (int c = 0; c < 4; c++) Sw[32 * 4 + c] = rs[c];
