@@ -550,21 +550,24 @@ __global__ __launch_bounds__(64 * kStuBwdWaves) __attribute__((amdgpu_waves_per_
     wave_sync_lds();   // the V rows are rewritten in the next pass
   }
   if (!live) return;
-  // sums over the wave: lane b < 3 adds force component b to the centre, lane k < 9
-  // writes virial entry k = 3 a + b
-  double fsum = 0.0, wsum = 0.0;
+  // sums over the wave of the 12 values f = b (force component b on the centre) and
+  // f = 3 + 3 a + b (virial W[a][b]): a reduce-scatter inside each 16-lane row (partners
+  // xor 8, 7, 2, 1 keep the half of the values their bit selects) leaves lane rb with the
+  // row's sum of value rb; the four rows are then added
+  double v[32];
 #pragma unroll
-  for (int b = 0; b < 3; b++) {
-    const double t = sum_g(row_sum16(fi[b]));
-    fsum = lane == b ? t : fsum;
-  }
+  for (int b = 0; b < 3; b++) v[b] = fi[b];
 #pragma unroll
-  for (int k = 0; k < 9; k++) {
-    const double t = sum_g(row_sum16(vir[k / 3][k % 3]));
-    wsum = lane == k ? t : wsum;
-  }
-  if (lane < 3) unsafeAtomicAdd(&A.forces[3 * atom + lane], fsum);
-  if (lane < 9) A.vir_part[(size_t)row * 9 + lane] = wsum;
+  for (int k = 0; k < 9; k++) v[3 + k] = vir[k / 3][k % 3];
+#pragma unroll
+  for (int k = 12; k < 16; k++) v[k] = 0.0;
+  stu_rs_step<double, 16, DPP_ROR8>(v, (rb & 8) != 0);
+  stu_rs_step<double, 8, DPP_HALF_MIRROR>(v, (rb & 4) != 0);
+  stu_rs_step<double, 4, DPP_XOR2>(v, (rb & 2) != 0);
+  stu_rs_step<double, 2, DPP_XOR1>(v, (rb & 1) != 0);
+  const double t = sum_g(v[0]);
+  if (lane < 3) unsafeAtomicAdd(&A.forces[3 * atom + lane], t);
+  else if (lane < 12) A.vir_part[(size_t)row * 9 + lane - 3] = t;
 }
 
 template <class T>
