@@ -14,12 +14,14 @@
 // per-neighbour matrix product remains.  Neighbours outside the trained range are
 // left to the full net (the fallback rows of student_infer.hip).
 //
-// One wave per centre; lane (rb, g) (rb = lane % 16, g = lane / 16) takes neighbour rb of
-// each chunk of 16 and the hidden units k = 16 n + 4 g + q (n < 2, q < 4), each
-// neighbour's environment row being formed once, by one lane, and handed to the chunk
-// lanes.  The forward runs four independent waves per block, the W2 [k][f] product read
-// from global memory (where the student blocks, a few KB per pair, stay cache-resident).
-// The adjoint runs eight centres per block: their V products are one small matrix
+// One wave per centre; each neighbour's environment row is formed once, by one lane, and
+// handed to the other lanes through LDS.  The forward runs four independent waves per
+// block; lane (k, p) applies hidden unit k = lane % 32 to the rows of parity p = lane / 32,
+// so S accumulates inside the lane, and the W2 [k][f] product reads the student blocks (a
+// few KB per pair, cache-resident) straight from global memory.  The adjoint runs eight
+// centres per block: lane (rb, g) (rb = lane % 16, g = lane / 16) takes neighbour rb of
+// each chunk of 16 and the hidden units k = 16 n + 4 g + q (n < 2, q < 4), its per-row sums
+// over k closing over the four lane groups; the centres' V products are one small matrix
 // product on the MFMA with W2T [f][k] staged in LDS, and each wave pipelines the gathers
 // of its neighbour blocks across both species of a pass.
 #include <hip/hip_runtime.h>
