@@ -192,7 +192,7 @@ def loss_and_grad(arch: Arch, theta_np: np.ndarray, frames, lam: float):
         nat = len(types)
         L = L + (E - float(Et)) ** 2 / nat + lam * ((F - torch.as_tensor(Ft)) ** 2).sum()
     (g,) = torch.autograd.grad(L, theta)
-    return float(L), g.numpy()
+    return float(L.detach()), g.numpy()
 
 
 # ---------------------------------------------------------------------------------------
@@ -222,7 +222,7 @@ def student_loss_grad(theta_np, H, M, s_np, target_np):
     out = student_forward(th, H, M, torch.as_tensor(s_np))
     L = ((out - torch.as_tensor(target_np)) ** 2).mean()
     (g,) = torch.autograd.grad(L, th)
-    return float(L), g.numpy()
+    return float(L.detach()), g.numpy()
 
 
 def adam_step(theta, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
