@@ -555,7 +555,7 @@ struct Plan {
       o_g1, o_Ei, o_vir, o_tmpj, o_tmpi, o_mdF, o_mdE, o_mdW, o_fb, o_fbcnt;
   // Verlet reuse (MD with a skin)
   bool verlet = false;
-  size_t o_wk, o_xref, o_eabc, o_vlist, o_vcnt, o_vflag, o_npt = 0;
+  size_t o_wk, o_xref, o_eabc, o_vlist, o_vcnt, o_vflag, o_npt = 0, o_xq = 0;
   int n, nframes, ncell, ghost_cap, nrows, vcap, max_frame_atoms;
   size_t o_redpart;
   size_t o_gbuf = 0, o_rev = 0;   // deterministic force gather
@@ -673,6 +673,7 @@ static int make_plan(dp_handle h, int nframes, const int64_t* off, const double*
     P.o_wk = take(sizeof(int) * 3 * n);
     P.o_xref = take(sizeof(double) * 3 * n);
     P.o_eabc = take(sizeof(int) * 3 * ne);
+    P.o_xq = take(sizeof(double) * 4 * ne);
     P.o_vlist = take(sizeof(int) * (size_t)n * P.vcap);
     P.o_vcnt = take(sizeof(int) * n);
     P.o_vflag = take(sizeof(int) * 64);
@@ -788,6 +789,7 @@ static int stage_frames(dp_handle h, int nframes, const int64_t* off, const doub
     A.wk = W.at<int>(P.o_wk);
     A.xref = W.at<double>(P.o_xref);
     A.eabc = W.at<int>(P.o_eabc);
+    A.xq = W.at<double>(P.o_xq);
     A.vlist = W.at<int>(P.o_vlist);
     A.vcnt = W.at<int>(P.o_vcnt);
     A.vcap = P.vcap;

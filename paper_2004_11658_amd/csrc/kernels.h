@@ -41,6 +41,9 @@ struct NlistArgs {
   int *vlist, *vcnt;
   int vcap;
   double rl2;
+  // [ne][4]: x, y, z and the species (as a double) of each extended atom, refreshed with
+  // xe at every Verlet step: one aligned 32-byte record per candidate of the per-step filter
+  double* xq;
   bool skip_rows;   // leave the species-grouped row order as it is (MD after its first step)
   bool cells_zeroed;   // cell counters already cleared by the caller (MD displacement check)
   int *big, *nbig;  // atoms deferred to the second formatting pass (too many candidates or tied

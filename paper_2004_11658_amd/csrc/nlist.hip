@@ -617,6 +617,13 @@ __device__ __forceinline__ double nl_r2(const double* __restrict__ xe, int e, co
   return (d0 * d0 + d1 * d1) + d2 * d2;
 }
 
+// the same r^2 from a packed record: p = (x, y), q = (z, species)
+__device__ __forceinline__ double nl_r2q(const double2 p, const double2 q, const double (&xi)[3]) {
+#pragma clang fp contract(off)
+  const double d0 = p.x - xi[0], d1 = p.y - xi[1], d2 = q.x - xi[2];
+  return (d0 * d0 + d1 * d1) + d2 * d2;
+}
+
 // Append the candidates of one 64-wide batch that lie within the cutoff to the wave's
 // LDS rows (up to cap); returns the new candidate count (which may exceed cap).  With
 // 32-bit keys (the main pass) only the key and the index are stored; the full key is
@@ -1000,6 +1007,7 @@ struct NlKArgs {
   const double* xe;
   const int *eown, *eimg, *etype, *ecell, *cell_start, *cell_atoms;
   const int *vlist, *vcnt;   // Verlet rows (NULL: search the cells)
+  const double* xq;          // packed [x, y, z, species] records (per-step filter)
   int vcap;
   int *nlist, *nnei, *status;
   int *big, *nbig;           // atoms deferred to the second pass (more than kNlCap candidates,
@@ -1141,8 +1149,11 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
   const ModelC& m = A.m;
   const int* vrow = A.vlist + (size_t)i * A.vcap;
   // The first 256 slots of the row are loaded with the count (slots past it are read,
-  // clamped into the row, and dropped) and the coordinates and types of the candidates are
-  // gathered together, so that an atom costs two dependent memory round trips, not four.
+  // clamped into the row, and dropped) and the coordinates and species of the candidates
+  // are gathered together, so that an atom costs two dependent memory round trips, not
+  // four.  Each candidate is one aligned 32-byte record (two 16-byte loads from one cache
+  // line): the gathers are scattered, and their cost is the number of cache lines each
+  // load instruction touches, which separate x, y, z and species loads would double.
   int e[4];
 #pragma unroll
   for (int j = 0; j < 4; j++) e[j] = vrow[min(64 * j + lane, A.vcap - 1)];
@@ -1170,8 +1181,10 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_nlist_vstep(NlKArgs A) {
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const int q = e[j] >= 0 ? e[j] : 0;   // in bounds whatever the slot holds
-      const double d2 = nl_r2(A.xe, q, xi);
-      ty[j] = A.etype[q];
+      const double2* rec = reinterpret_cast<const double2*>(A.xq) + 2 * (size_t)q;
+      const double2 p = rec[0], s = rec[1];
+      const double d2 = nl_r2q(p, s, xi);
+      ty[j] = (int)s.y;
       r2[j] = e[j] >= 0 ? d2 : 0.0;
     }
 #pragma unroll
@@ -1225,26 +1238,30 @@ static void launch_format(const NlKArgs& K, hipStream_t st) {
 __device__ __forceinline__ void update_ext_one(int e, int n, const Frame* __restrict__ frames,
                                                const int* __restrict__ frame_of, const double* __restrict__ x,
                                                const int* __restrict__ wk, const int* __restrict__ eown,
-                                               const int* __restrict__ eabc, double* __restrict__ xe) {
+                                               const int* __restrict__ eabc, const int* __restrict__ etype,
+                                               double* __restrict__ xe, double* __restrict__ xq) {
 #pragma clang fp contract(off)
   int i = eown[e];
   const Frame& F = frames[frame_of[i]];
   double s[3], w[3];
   shift_of(F, wk[3 * i], wk[3 * i + 1], wk[3 * i + 2], s);
   for (int c = 0; c < 3; c++) w[c] = x[3 * i + c] - s[c];
-  if (e < n) {
-    for (int c = 0; c < 3; c++) xe[3 * e + c] = w[c];
-    return;
+  if (e >= n) {
+    double g[3];
+    shift_of(F, eabc[3 * e], eabc[3 * e + 1], eabc[3 * e + 2], g);
+    for (int c = 0; c < 3; c++) w[c] = w[c] + g[c];
   }
-  double g[3];
-  shift_of(F, eabc[3 * e], eabc[3 * e + 1], eabc[3 * e + 2], g);
-  for (int c = 0; c < 3; c++) xe[3 * e + c] = w[c] + g[c];
+  for (int c = 0; c < 3; c++) xe[3 * e + c] = w[c];
+  double2* r = reinterpret_cast<double2*>(xq) + 2 * (size_t)e;
+  r[0] = make_double2(w[0], w[1]);
+  r[1] = make_double2(w[2], (double)etype[e]);
 }
 
 // The launch that follows the (gated) rebuild chain of a Verlet step: with the rebuild
 // flag set it builds the Verlet rows, one wave per atom (the ghost pass has just written
 // the extended coordinates from the current positions); otherwise it refreshes the
-// extended coordinates from the moved atoms, one thread per extended atom.  The flag is
+// extended coordinates from the moved atoms, one thread per extended atom.  Both ways it
+// writes the packed [x, y, z, species] records that the filter gathers.  The flag is
 // only read here; the per-step filter that runs next re-arms it.
 __global__ __launch_bounds__(64 * kNlWaves) void k_vbuild_refresh(
     int n, double rl2, const Frame* __restrict__ frames, const int* __restrict__ frame_of,
@@ -1252,10 +1269,17 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_vbuild_refresh(
     const int* __restrict__ cell_start, const int* __restrict__ cell_atoms, int* __restrict__ vlist,
     int* __restrict__ vcnt, int vcap, int* __restrict__ status, const int* __restrict__ gate, int ne_cap,
     const int* __restrict__ n_ext, const double* __restrict__ x, const int* __restrict__ wk,
-    const int* __restrict__ eown, const int* __restrict__ eabc) {
+    const int* __restrict__ eown, const int* __restrict__ eabc, double* __restrict__ xq) {
   __shared__ int s_e[kNlWaves][kVCap];
   __shared__ __align__(16) unsigned s_k[kNlWaves][kVCap];
+  const int ne = min(ne_cap, n_ext[0]);
   if (*gate != 0) {
+    // the ghost pass has written xe and etype: pack them (the grid has 64 threads per atom)
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+      double2* r = reinterpret_cast<double2*>(xq) + 2 * (size_t)e;
+      r[0] = make_double2(xe[3 * e], xe[3 * e + 1]);
+      r[1] = make_double2(xe[3 * e + 2], (double)etype[e]);
+    }
     const int wv = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * kNlWaves + wv;
@@ -1264,9 +1288,8 @@ __global__ __launch_bounds__(64 * kNlWaves) void k_vbuild_refresh(
                 vcnt, vcap, status);
     return;
   }
-  const int ne = min(ne_cap, n_ext[0]);
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x)
-    update_ext_one(e, n, frames, frame_of, x, wk, eown, eabc, xe);
+    update_ext_one(e, n, frames, frame_of, x, wk, eown, eabc, etype, xe, xq);
 }
 
 // *flag |= 1 when some atom moved more than half the skin since the last rebuild
@@ -1354,6 +1377,7 @@ static NlKArgs format_args(const NlistArgs& A) {
   K.frames = A.frames;
   K.frame_of = A.frame_of;
   K.xe = A.xe;
+  K.xq = A.xq;
   K.eown = A.eown;
   K.eimg = A.eimg;
   K.etype = A.etype;
@@ -1452,7 +1476,7 @@ void launch_nlist_verlet(const NlistArgs& A, double half_skin, bool disp_done, i
   const int ne_cap = n + A.ghost_cap;
   hipLaunchKernelGGL(k_vbuild_refresh, dim3((n + kNlWaves - 1) / kNlWaves), dim3(64 * kNlWaves), 0, st, n, A.rl2,
                      A.frames, A.frame_of, A.xe, A.etype, A.ecell, A.cell_start, A.cell_atoms, A.vlist, A.vcnt,
-                     A.vcap, A.status, A.gate, ne_cap, A.n_ext, A.x, A.wk, A.eown, A.eabc);
+                     A.vcap, A.status, A.gate, ne_cap, A.n_ext, A.x, A.wk, A.eown, A.eabc, A.xq);
   NlKArgs K = format_args(A);
   K.gate = (int*)A.gate;
   K.clear = clear;
