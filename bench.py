@@ -285,7 +285,9 @@ def run_modes(D, path, x0, v0, t_dev, box, masses, dt, steps, warmup, modes, ski
         thermo = th.cpu().numpy()
         drift = float(np.abs(thermo[:, 4] - thermo[0, 4]).max() / n)
         results[mode] = dict(value=n * steps / wall, ms_per_step=1e3 * wall / steps,
-                             force_rmse_rel=rmse, energy_drift_ev_per_atom=drift, student=extra == "student",
+                             force_rmse_rel=rmse, energy_drift_ev_per_atom=drift,
+                             temperature_K_start_end=[float(thermo[0, 3]), float(thermo[-1, 3])],
+                             closest_pair_A_end=closest_pair(x, box), student=extra == "student",
                              fallback_rows_last_step=fb1,
                              stages_ms={s: v_[0] / max(v_[1], 1) for s, v_ in stages.items()},
                              stage_launches={s: v_[1] for s, v_ in stages.items()})
@@ -293,6 +295,22 @@ def run_modes(D, path, x0, v0, t_dev, box, masses, dt, steps, warmup, modes, ski
         del x, v, F_end, Fr, dF
     del ref
     return results, rows
+
+
+def closest_pair(x, box):
+    """Smallest periodic distance between two atoms (A) of a cubic box, on the host.
+
+    The synthetic potential has random weights: its tanh layers saturate as two atoms
+    approach, so it holds no short-range repulsion and atoms can run into each other;
+    the closest pair tells whether a run's energy drift comes from such an encounter."""
+    from scipy.spatial import cKDTree
+    L = float(box[0][0])
+    if not np.allclose(np.asarray(box, dtype=np.float64), np.diag([L, L, L])):
+        return None
+    p = np.mod(x.cpu().numpy(), L)
+    p[p >= L] = 0.0
+    d, _ = cKDTree(p, boxsize=L).query(p, k=2)
+    return float(d[:, 1].min())
 
 
 def stage_rates(spec, rows, n, res):
@@ -306,7 +324,13 @@ def stage_rates(spec, rows, n, res):
 
 
 def summarise(results):
-    return {m: {k: (sig(v_) if isinstance(v_, float) else v_) for k, v_ in r.items()} for m, r in results.items()}
+    def one(v_):
+        if isinstance(v_, float):
+            return sig(v_)
+        if isinstance(v_, list):
+            return [sig(u) if isinstance(u, float) else u for u in v_]
+        return v_
+    return {m: {k: one(v_) for k, v_ in r.items()} for m, r in results.items()}
 
 
 def _counter_rows(directory):
