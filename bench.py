@@ -488,7 +488,7 @@ def main():
         mfma_table(args.mfma_table)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU spatial decomposition is "
+        print("bench.py: the benchmark runs on one GPU only (the multi-GPU spatial decomposition is "
               "designed but not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
