@@ -107,7 +107,10 @@ int dp_model_info(dp_handle h, int32_t* ntypes, int32_t* nm, int32_t* M, int32_t
  * arrays atom_offsets [nframes+1] (frame f owns atoms [atom_offsets[f], atom_offsets[f+1]))
  * and boxes [nframes][9].  The workspace carries the neighbour list, ghost images,
  * per-atom descriptors and status words; one workspace serves calls of at most that
- * size and equal or smaller ghost shells. */
+ * size and equal or smaller ghost shells.  Every frame must hold at least one atom and
+ * the batch at most 2^26 atoms: an empty frame, a decreasing atom_offsets or a larger
+ * batch returns DP_ERR_ARG here and from every evaluation entry point, before anything
+ * is launched (an empty frame's energy is zero by Eq. 1; the caller skips it). */
 int dp_workspace_size(dp_handle h, int32_t nframes, const int64_t* atom_offsets,
                       const double* boxes, size_t* bytes);
 

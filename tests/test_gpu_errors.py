@@ -178,6 +178,48 @@ def test_err_arg_before_upload_and_nulls(dp, tiny_model):
         L.dp_free(h)
 
 
+def test_err_arg_atom_counts(dp, tiny_model):
+    """An empty frame (alone or inside a ragged batch) and a batch above 2^26 atoms are
+    rejected on the host with DP_ERR_ARG, before anything is launched."""
+    import torch
+    L = dp.lib()
+    m = dp.DPModel(tiny_model, "fp64")
+    c, t, b = tiny_water(11, 2, 6.3)
+    n = len(t)
+    b9 = np.ascontiguousarray(np.tile(np.asarray(b, dtype=np.float64).reshape(9), 3))
+    nb = C.c_size_t()
+    for case, off in (("empty frame", [0, 0]), ("empty middle frame", [0, n, n, 2 * n]),
+                      ("decreasing offsets", [0, n, n - 1, 2 * n]), ("above 2^26 atoms", [0, (1 << 26) + 1])):
+        print("case", case, flush=True)
+        o = np.asarray(off, dtype=np.int64)
+        nf = len(off) - 1
+        assert L.dp_workspace_size(m.h, nf, o.ctypes.data_as(C.c_void_p), b9.ctypes.data_as(C.c_void_p),
+                                   C.byref(nb)) == DP_ERR_ARG
+        assert L.dp_last_error(m.h)
+    # the evaluations themselves: nothing launched, outputs untouched
+    x = torch.as_tensor(np.vstack([c, c]), device="cuda")
+    ty = torch.as_tensor(np.concatenate([t, t]), dtype=torch.int32, device="cuda")
+    E = torch.full((3,), 7.0, dtype=torch.float64, device="cuda")
+    F = torch.full((2 * n, 3), 7.0, dtype=torch.float64, device="cuda")
+    ws = torch.empty(1 << 24, dtype=torch.uint8, device="cuda")
+    print("case dp_compute natoms 0", flush=True)
+    assert L.dp_compute(m.h, 0, C.c_void_p(x.data_ptr()), C.c_void_p(ty.data_ptr()),
+                        b9.ctypes.data_as(C.c_void_p), C.c_void_p(E.data_ptr()), C.c_void_p(F.data_ptr()),
+                        None, None, C.c_void_p(ws.data_ptr()), ws.numel(), None) == DP_ERR_ARG
+    print("case dp_compute_batch empty middle frame", flush=True)
+    o = np.asarray([0, n, n, 2 * n], dtype=np.int64)
+    assert L.dp_compute_batch(m.h, 3, o.ctypes.data_as(C.c_void_p), C.c_void_p(x.data_ptr()),
+                              C.c_void_p(ty.data_ptr()), b9.ctypes.data_as(C.c_void_p), C.c_void_p(E.data_ptr()),
+                              C.c_void_p(F.data_ptr()), None, None, C.c_void_p(ws.data_ptr()), ws.numel(),
+                              None) == DP_ERR_ARG
+    torch.cuda.synchronize()
+    assert bool((E == 7.0).all()) and bool((F == 7.0).all())
+    # the handle still works after the rejected calls
+    En, Fn, _ = m.compute(torch.as_tensor(c, device="cuda"), torch.as_tensor(t, dtype=torch.int32, device="cuda"), b)
+    r = Oracle(tiny_model).eval(c, t, b)
+    assert abs(float(En.cpu()[0]) - r["E"]) <= 1e-10 * abs(r["E"])
+
+
 def test_two_handles_on_two_streams(dp, tiny_model, water_model, water192):
     """Two handles, each with its own workspace, launched on two streams back to back
     without a synchronisation between them: both results equal the serial ones."""
