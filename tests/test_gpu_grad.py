@@ -87,7 +87,7 @@ def test_param_grad_matches_oracle(dp, which, tiny_model, water_model, copper_mo
     L = (((E - Et) ** 2) / nat).sum() + lam * ((F - Ft) ** 2).sum()
     L.backward()
     g = theta.grad.cpu().numpy()
-    assert abs(float(L) - L_ref) <= 1e-10 * abs(L_ref)
+    assert abs(float(L.detach()) - L_ref) <= 1e-10 * abs(L_ref)
     err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
     print("grad rel err", err, flush=True)
     assert err < 1e-9
